@@ -1,0 +1,172 @@
+"""Pins of the oracle's matrix-P estimator (CPU only): per-sample identities,
+printed values of the paper, and statistical agreement with the exact laws."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator, exact, sampler
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_g0_m4_worked_value():
+    """Appendix A: for lossless total counts the matrix-P projector G_0(4)
+    lies in (0, 0.4) with its largest values near 0.39."""
+    g = json.load(open(os.path.join(GOLDEN, "g0_m4_density.json")))
+    n = np.linspace(-25, 25, 200_001)
+    n = n[n != 0]
+    G = estimator.pattern_probability(n, n[:, None].astype(complex), [np.array([g["m"]])])[:, 0]
+    assert np.all(np.abs(G.imag) <= 1e-14 * np.abs(G))
+    lo, hi = g["range"]
+    assert G.real.min() > lo and G.real.max() < hi
+    assert abs(G.real.max() - g["peak_value_approx"]) < g["peak_tolerance"]
+    # closed form given with the projector: g0(2m) = n^2m / ((2m)! cosh n)
+    np.testing.assert_allclose(G.real, n ** 4 / (24 * np.cosh(n)), rtol=1e-12)
+
+
+def test_lossless_odd_counts_vanish_per_sample():
+    """g0(2m+1) = 0 when every channel is counted (n_S = n)."""
+    rng = np.random.default_rng(0)
+    n = rng.normal(3, 4, size=500)
+    G = estimator.pattern_probability(n, n[:, None].astype(complex), [np.arange(40)])
+    assert np.abs(G[:, 1::2]).max() < 1e-300 or np.abs(G[:, 1::2]).max() == 0.0
+    assert np.abs(G[:, 0::2]).max() > 0
+
+
+def test_generating_function_identity_per_sample():
+    """sum_m G(m) z^m = cosh(n + n_S (z - 1)) / cosh(n) for each sample (the
+    per-sample characteristic function of eq. c-number-variable)."""
+    rng = np.random.default_rng(1)
+    E = 64
+    n = rng.normal(4, 3, size=E)
+    nS = (0.6 * n + rng.normal(0, 0.7, E)) + 1j * rng.normal(0, 0.7, E)
+    m = np.arange(160)
+    G = estimator.pattern_probability(n, nS[:, None], [m])
+    for z in (1.0, -1.0, np.exp(0.7j), 0.3 - 0.2j):
+        lhs = (G * z ** m[None, :]).sum(1)
+        rhs = np.cosh(n + nS * (z - 1)) / np.cosh(n)
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-13)
+
+
+def test_plus_p_generating_function():
+    rng = np.random.default_rng(2)
+    n = rng.normal(4, 1, 8)
+    nS = n * 0.7 + 0.2j
+    m = np.arange(120)
+    G = estimator.pattern_probability(n, nS[:, None], [m], plus_p=True)
+    z = np.exp(0.4j)
+    np.testing.assert_allclose((G * z ** m).sum(1), np.exp(nS * (z - 1)), rtol=1e-12)
+
+
+def test_joint_sums_to_marginal_and_total():
+    rng = np.random.default_rng(3)
+    E = 40
+    n = rng.normal(5, 2, E)
+    nb = np.stack([0.3 * n + 0.1j * rng.normal(size=E), 0.4 * n - 0.2j * rng.normal(size=E)], 1)
+    m = np.arange(60)
+    J = estimator.pattern_probability(n, nb, [m, m])
+    M1 = estimator.pattern_probability(n, nb[:, :1], [m])
+    np.testing.assert_allclose(J.sum(2), M1, rtol=1e-11, atol=1e-15)
+    tot = estimator.pattern_probability(n, nb.sum(1, keepdims=True), [m])
+    diag = np.stack([sum(J[:, a, k - a] for a in range(k + 1)) for k in range(60)], 1)
+    np.testing.assert_allclose(diag, tot, rtol=1e-11, atol=1e-15)
+
+
+def test_uniform_loss_invariant():
+    """For T = t U every sample has n_S = t^2 n (unitary invariance of
+    alpha . beta)."""
+    r = np.linspace(0.3, 1.2, 12)
+    T = 0.8 * synth.haar_unitary(12, 4)
+    a, b, n = sampler.sample(r, 0, 200, seed=6)
+    ap, bp = estimator.propagate(T, a, b)
+    nS = estimator.bin_occupations(ap, bp, np.zeros(12, int), 1)[:, 0]
+    np.testing.assert_allclose(nS, 0.64 * n, rtol=1e-12, atol=1e-12)
+
+
+def _z(res, ref, rel_floor=1e-3):
+    P, s = res["P"], res["sigma"]
+    bulk = ref > rel_floor * ref.max()
+    return np.abs((P - ref)[bulk] / s[bulk])
+
+
+def test_small_workload_vs_determinant_law():
+    """M = 16, Haar x 0.5, r = 1, E = 1e4: bulk bins within 5 sigma_T."""
+    w = synth.workload_small()
+    res = estimator.estimate(w.T, w.r, w.seed, w.E, w.n_sub, w.bins, 1, w.windows)
+    ref = exact.gaussian_total(w.T, w.r, np.ones(16), 128)
+    assert _z(res, ref).max() < 5
+    assert abs(res["P"].sum() - 1) < 1e-12
+
+
+def test_lossless_vs_negative_binomial():
+    U = synth.haar_unitary(8, 3)
+    res = estimator.estimate(U, np.full(8, 0.5), 99, 40_000, 20, np.zeros(8, int), 1, [(0, 64)])
+    ref = exact.lossless_uniform_total(8, 0.5, np.arange(64))
+    assert _z(res, ref).max() < 5
+    assert np.abs(res["P_complex"][1::2]).max() < 1e-14
+
+
+def _lossy_two_mode():
+    r = np.array([0.4, 0.6])
+    T = 0.8 * synth.haar_unitary(2, 7)
+    return T, r
+
+
+def test_global_n_reading_against_exact():
+    """Lossy two-mode network, many samples: the global-n estimator agrees
+    with the exact joint law; replacing the global n by the counted output
+    photon number (a planted mistake) is rejected."""
+    T, r = _lossy_two_mode()
+    E, nsub = 200_000, 40
+    res = estimator.estimate(T, r, 31, E, nsub, np.array([0, 1]), 2, [(0, 16), (0, 16)],
+                             chunk=20_000)
+    ref = exact.gaussian_joint2(T, r, np.array([0, 1]), 64, 64)[:16, :16]
+    assert _z(res, ref).max() < 5
+    # planted mistake: n := Re(n_S), the counted output number
+    a, b, n = sampler.sample(r, 0, E, 31)
+    ap, bp = estimator.propagate(T, a, b)
+    nb = estimator.bin_occupations(ap, bp, np.array([0, 1]), 2)
+    wrong = estimator.pattern_probability(nb.sum(1).real, nb, [np.arange(16)] * 2).real
+    Ps = wrong.reshape(nsub, E // nsub, 16, 16).mean(1)
+    z = np.abs(Ps.mean(0) - ref) / (Ps.std(0, ddof=1) / np.sqrt(nsub) + 1e-30)
+    assert z.max() > 20
+
+
+def test_two_bin_joint_vs_determinant_law():
+    r = np.array([0.5, 0.8, 0.6, 0.7])
+    T = 0.9 * synth.haar_unitary(4, 21)
+    bins = np.array([0, 0, 1, 1])
+    res = estimator.estimate(T, r, 5, 100_000, 25, bins, 2, [(0, 16), (0, 16)], chunk=20_000)
+    ref = exact.gaussian_joint2(T, r, bins, 64, 64)[:16, :16]
+    assert _z(res, ref).max() < 5
+
+
+def test_marginal_mode_matches_single_bin_runs():
+    r = np.array([0.5, 0.8, 0.6, 0.7, 1.0, 0.9])
+    T = 0.9 * synth.haar_unitary(6, 2)
+    bins = np.array([0, 0, 1, 1, 2, 2])
+    res = estimator.estimate(T, r, 5, 2000, 4, bins, 3, [(0, 24)] * 3, mode="marginals")
+    for b in range(3):
+        only = np.where(bins == b, 0, -1)
+        one = estimator.estimate(T, r, 5, 2000, 4, only, 1, [(0, 24)])
+        np.testing.assert_allclose(res["P_complex"][b], one["P_complex"], rtol=1e-12, atol=1e-15)
+
+
+def test_factorial_moments_vs_closed_form():
+    """eq. moment with T_0 = tanh n: E[n_S] and E[n_S (n_S - 1)] ... reduce
+    to the closed-form mean and variance."""
+    r = np.linspace(0.4, 1.1, 6)
+    T = 0.85 * synth.haar_unitary(6, 9)
+    counted = np.array([1, 1, 1, 0, 0, 1])
+    bins = np.where(counted == 1, 0, -1)
+    a, b, n = sampler.sample(r, 0, 400_000, 13)
+    ap, bp = estimator.propagate(T, a, b)
+    nS = estimator.bin_occupations(ap, bp, bins, 1)[:, 0]
+    f = estimator.factorial_moment_samples(n, nS, 2)
+    mean, var = exact.count_moments(T, r, counted)
+    f1, f2 = f[:, 0].real, f[:, 1].real
+    assert abs(f1.mean() - mean) < 5 * f1.std() / np.sqrt(len(f1))
+    assert abs((f2.mean() + mean - mean ** 2) - var) < 5 * f2.std() / np.sqrt(len(f2)) + 1e-9
