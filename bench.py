@@ -1,0 +1,207 @@
+"""Benchmark of the matrix-P hot path on one MI355X.
+
+Workload: M = 8000 modes, Haar network x t = 0.95, r = 1 on every mode,
+total-count distribution on the window [8083, 8083 + 3840) (mean 9972,
+sd 209), sub-ensembles of 8192 samples.  One step = one chunk of 65536
+samples through the whole path: mp_sample -> mp_propagate (split-BF16 MFMA
+GEMM) -> mp_binned_counts; the inverse DFT (mp_counts_finalize) runs once
+after the timed steps.  The FP32 path is timed on the same workload for the
+mixed-vs-FP32 comparison.
+
+Prints one JSON line (last line of stdout).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "samples·M²/s and seconds to binned P(m) at 1σ≤1e-3, M=8000, mixed vs FP32"
+PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_run(mp, torch, pipe, steps, warmup, g_start=0):
+    """Runs warmup + steps chunks; returns (seconds, per-launch GEMM ms, last g)."""
+    stream = torch.cuda.current_stream()
+    E = pipe.chunk
+    g = g_start
+    for _ in range(warmup):
+        pipe.run_chunk(g, E)
+        g += E
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        mp.mp_sample(pipe.M, g, E, pipe.r, pipe.seed, pipe.net, pipe.prec, pipe.ab, pipe.n)
+        ev[i][0].record(stream)
+        mp.mp_propagate(pipe.M, E, pipe.T, pipe.prec, pipe.ab, pipe.C, pipe.ws_prop)
+        ev[i][1].record(stream)
+        pipe.counts_chunk(g, E)
+        g += E
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    gemm_ms = [a.elapsed_time(b) for a, b in ev]
+    return secs, gemm_ms, g
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    from oracle import estimator
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    E0 = 32
+    t = time.perf_counter()
+    estimator.estimate(w.T, w.r, w.seed, E0, 1, w.bins, 1, w.windows, chunk=E0)
+    dt = time.perf_counter() - t
+    E = int(max(E0, min(4096, E0 * budget_s / max(dt, 1e-3))))
+    E = max(E0, (E // E0) * E0)
+    t = time.perf_counter()
+    estimator.estimate(w.T, w.r, w.seed, E, 1, w.bins, 1, w.windows, chunk=min(E, 512))
+    dt = time.perf_counter() - t
+    return {"value": E * w.M ** 2 / dt, "unit": "samples·M²/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{E} samples of the M=8000 workload through the FP64 oracle "
+                      f"(sampling, complex128 propagation, direct count-space G(m) on the "
+                      f"{w.windows[0][1]}-count window), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="split_bf16")
+    ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
+    ap.add_argument("--compare-steps", type=int, default=2)
+    ap.add_argument("--chunk", type=int, default=65536)
+    ap.add_argument("--M", type=int, default=8000)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sample-sharded "
+              f"multi-GPU path is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2503_12749_amd as mp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t = time.perf_counter()
+    E_total = args.chunk * (args.warmup + args.steps)
+    w = synth.workload_m8000(E=E_total, chunk=args.chunk) if args.M == 8000 else None
+    if w is None:
+        M = args.M
+        r = synth.squeezing_uniform(M, 1.0)
+        mean, sd = synth.uniform_loss_moments(r, 0.95)
+        w = synth.Workload(f"M{M}_t0.95_r1", M, 0.95, r, synth.transmission(M, 0.95, synth.SEED_BASE + 5),
+                           E_total, E_total // 8192, synth.SEED_BASE + 5, synth.all_modes_bin(M), 1,
+                           [synth.count_window(mean, sd)], args.chunk)
+    log(f"[bench] workload {w.name}: Haar network ready in {time.perf_counter() - t:.1f} s")
+    ns = 8192
+    n_sub = E_total // ns
+
+    results = {}
+    for prec, steps in ((args.prec, args.steps), (args.compare, args.compare_steps)):
+        if not prec:
+            continue
+        pipe = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
+                                 n_sub=n_sub, samples_per_sub=ns, chunk=args.chunk)
+        secs, gemm_ms, g = timed_run(mp, torch, pipe, steps, args.warmup if prec == args.prec else 1)
+        t0 = time.perf_counter()
+        # statistics over the sub-ensembles completed so far
+        done_sub = g // ns
+        mp.mp_counts_finalize(1, "joint", pipe.K, done_sub, ns, pipe.acc, pipe.P_re, pipe.P_im,
+                              pipe.sigma)
+        torch.cuda.synchronize()
+        fin_s = time.perf_counter() - t0
+        P, _, sig = pipe.result()
+        E_run = done_sub * ns
+        crit = 1e-3 * P.max()
+        E_need = E_run * (sig.max() / crit) ** 2
+        per_sample = secs / (steps * args.chunk)
+        results[prec] = dict(
+            secs=secs, steps=steps, ms_per_step=1e3 * secs / steps,
+            value=steps * args.chunk * w.M ** 2 / secs,
+            gemm_ms=float(np.mean(gemm_ms)), gemm_ms_all=[round(x, 3) for x in gemm_ms],
+            sigma_max=float(sig.max()), P_max=float(P.max()), sumP=float(P.sum()),
+            E_run=E_run, E_needed=float(E_need),
+            seconds_to_criterion=float(E_need * per_sample + fin_s), finalize_s=fin_s,
+            mean=float((np.arange(w.windows[0][0], w.windows[0][0] + w.windows[0][1]) * P).sum()))
+        log(f"[bench] {prec}: {results[prec]['ms_per_step']:.1f} ms/step, GEMM {results[prec]['gemm_ms']:.1f} ms, "
+            f"{results[prec]['value']:.3e} samples*M^2/s, sigma_max {sig.max():.2e} (P_max {P.max():.2e}), "
+            f"E needed {E_need:.3g}")
+        del pipe
+        torch.cuda.empty_cache()
+
+    main_r = results[args.prec]
+    flops = 8.0 * w.M ** 2 * args.chunk
+    achieved = flops / (main_r["gemm_ms"] * 1e-3) / 1e12
+    peak = PEAKS_TFLOPS[args.prec]
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": f"gemm_{args.prec} (+ operand pack) in mp_propagate",
+            "algorithmic_flops_per_launch": flops}
+    if args.prec.startswith("split"):
+        roof["executed_mfma_frac"] = round(3 * achieved / peak, 4)
+    out = {
+        "metric": METRIC,
+        "value": main_r["value"],
+        "unit": "samples·M²/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"split_bf16": "split-bf16 (fp32 acc)", "fp32": "fp32", "fp64": "f64"}.get(args.prec, args.prec),
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: M={w.M}, Haar x t={w.t}, r=1, total counts on window "
+                        f"[{w.windows[0][0]}, {w.windows[0][0] + w.windows[0][1]}), "
+                        f"{args.chunk} samples per step, sub-ensembles of {ns}",
+            "precision": args.prec,
+            "seconds_to_criterion": main_r["seconds_to_criterion"],
+            "criterion": "max_m sigma_T(m) <= 1e-3 * max_m P(m)",
+            "E_needed": main_r["E_needed"],
+            "sigma_max": main_r["sigma_max"], "P_max": main_r["P_max"], "sum_P": main_r["sumP"],
+            "gemm_ms": main_r["gemm_ms"],
+        },
+        "roofline": roof,
+    }
+    if args.compare and args.compare in results:
+        c = results[args.compare]
+        out["config"]["compare"] = {
+            "precision": args.compare, "value": c["value"], "ms_per_step": c["ms_per_step"],
+            "gemm_ms": c["gemm_ms"], "seconds_to_criterion": c["seconds_to_criterion"],
+            "speedup_mixed_vs_compare": main_r["value"] / c["value"],
+            "gemm_tflops": 8.0 * w.M ** 2 * args.chunk / (c["gemm_ms"] * 1e-3) / 1e12,
+        }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

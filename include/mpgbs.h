@@ -1,0 +1,205 @@
+/*
+ * mpgbs.h -- C ABI of the MI355X (gfx950) matrix-P Gaussian-boson-sampling
+ * hot path: parity-projected phase-space estimates of total and grouped
+ * photon-count probabilities (Drummond, Dellios & Reid, "Matrix phase-space
+ * representations for Gaussian boson sampling", arXiv:2503.12749).
+ *
+ * Pipeline, one chunk of E phase-space samples at a time:
+ *   mp_sample          real amplitudes (alpha, beta) of squeezed inputs and
+ *                      the global photon number n = alpha . beta
+ *   mp_propagate       alpha' = T alpha, beta' = T* beta as one real GEMM
+ *   mp_binned_counts   occupations, parity weight and characteristic function
+ *                      on the count window, accumulated per sub-ensemble
+ * and once at the end:
+ *   mp_counts_finalize inverse DFT to P(m) and the sub-ensemble error sigma_T
+ *
+ * Conventions shared by every entry point
+ *   - Pointers marked "device" are HIP device (or managed) memory owned by the
+ *     caller; "host" pointers are read synchronously during the call.  The
+ *     library never allocates, frees or retains caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     asynchronously on it; arguments are validated on the host before any
+ *     launch, and a failed validation enqueues nothing.
+ *   - Every call returns an mp_status and never throws across the ABI.  The
+ *     message of the last non-MP_OK status of the calling thread is returned
+ *     by mp_last_error().
+ *   - Mode-major buffers use the padded leading dimension ldm = mp_ld_modes(M)
+ *     (M rounded up to a multiple of 128); padding rows hold zeros.
+ *   - Calls that share buffers must be ordered on one stream; calls on
+ *     different streams that write the same accumulator race.
+ */
+#ifndef MPGBS_H
+#define MPGBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MP_OK = 0,
+  MP_ERR_ARG = -1,         /* invalid scalar argument or null pointer */
+  MP_ERR_SHAPE = -2,       /* sizes inconsistent with each other */
+  MP_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  MP_ERR_UNSUPPORTED = -4, /* valid request outside what this build handles */
+  MP_ERR_WORKSPACE = -5    /* workspace missing or smaller than required */
+} mp_status;
+
+typedef enum {
+  MP_FP64 = 0,       /* FP64 samples, FP64 MFMA GEMM, FP64 characteristic function */
+  MP_FP32 = 1,       /* FP32 samples, FP32 MFMA GEMM, FP32 characteristic function */
+  MP_SPLIT_BF16 = 2, /* hi/lo BF16 operands, 3 BF16 MFMA products, FP32 accumulate */
+  MP_SPLIT_FP16 = 3  /* hi/lo FP16 operands (lo scaled by 2^11), FP32 accumulate */
+} mp_precision;
+
+typedef enum {
+  MP_JOINT = 0,              /* joint distribution of the d bin counts (d <= 2) */
+  MP_MARGINALS = 1,          /* d one-bin distributions (S = S_b alone) */
+  MP_MARGINALS_AND_TOTAL = 2 /* the d marginals plus the total over all bins */
+} mp_bin_mode;
+
+typedef enum {
+  MP_MATRIX_P = 0, /* parity-projected weight g0 (main text, eq. c-number-variable) */
+  MP_PLUS_P = 1    /* positive-P observable, g0 = 1 (Appendix A) */
+} mp_estimator;
+
+#define MP_MAX_BINS 8  /* bins per call */
+#define MP_MAX_RUNS 16 /* contiguous mode runs over all bins per call */
+
+/* ---------------------------------------------------------------- sizes */
+
+/* Padded leading dimension of mode-major buffers: M rounded up to 128. */
+int64_t mp_ld_modes(int32_t M);
+
+/* Bytes of the amplitude buffer `ab` of mp_sample / mp_propagate. */
+size_t mp_ab_bytes(int32_t M, int64_t E, mp_precision prec);
+
+/* Bytes of the propagated buffer `C` of mp_propagate / mp_binned_counts. */
+size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
+
+/* ---------------------------------------------------------------- S1 */
+
+/*
+ * Phase-space amplitudes of squeezed vacuum inputs (main text, the squeezed
+ * state as a real coherent-state integral with weight xi(alpha), sampled with
+ * the +P procedure that the parity-projected distribution P_2 reuses).
+ *
+ * Per mode j the pair (alpha_j, beta_j) is real Gaussian with variances
+ * sinh r_j cosh r_j and covariance sinh^2 r_j:
+ *   alpha_j = c+ w1 + c- w2,  beta_j = c+ w1 - c- w2,
+ *   c+ = sqrt(e^{2 r_j} - 1) / 2,  c- = sqrt(1 - e^{-2 r_j}) / 2.
+ * (w1, w2) are Box-Muller normals from one Philox4x64-10 call with counter
+ * (g, p, net, 0) and key (seed, 0) for global sample index g and mode pair
+ * p = j / 2: words 0,1 feed mode 2p and words 2,3 mode 2p+1, with
+ * u = ((x0 >> 11) + 1) 2^-53, v = (x1 >> 11) 2^-53,
+ * w1 = sqrt(-2 ln u) cos(2 pi v), w2 = sqrt(-2 ln u) sin(2 pi v).
+ * The draw of a sample depends only on (seed, net, g), never on chunking.
+ *
+ *   M      modes, >= 1                 g0     global index of the first sample
+ *   E      samples in this call, >= 1  r      device FP64[M], r_j >= 0 (0 = vacuum)
+ *   ab     device, mp_ab_bytes(M, E, prec) bytes, column-major with ld = ldm:
+ *          column k < E holds alpha of sample g0+k, column E+k its beta.
+ *          FP64 -> double, FP32 -> float, SPLIT_* -> a hi plane followed by a
+ *          lo plane of 16-bit values (x = hi + lo, resp. hi + lo 2^-11 for FP16).
+ *   n_out  device FP64[E]: n = sum_j alpha_j beta_j of the values as stored
+ *          (after rounding to `prec`).
+ */
+mp_status mp_sample(int32_t M, int64_t g0, int64_t E, const double* r, uint64_t seed,
+                    uint32_t net, mp_precision prec, void* ab, double* n_out, void* stream);
+
+/* ---------------------------------------------------------------- S2 */
+
+/* Workspace bytes mp_propagate needs (the packed transmission operand). */
+size_t mp_propagate_workspace(int32_t M, mp_precision prec);
+
+/*
+ * Linear-network propagation alpha' = T alpha, beta' = T* beta (main text,
+ * characteristics of the network equation; loss as a sub-unitary T).  Since
+ * alpha and beta are real this is one real GEMM
+ *     C = [Re T; Im T] (2M x M) * [alpha | beta] (M x 2E).
+ *
+ *   T   device FP64, complex M x M, row-major, interleaved (re, im):
+ *       T[2 (i M + j)] = Re T_ij maps input mode j to output mode i.
+ *   ab  device, as written by mp_sample with the same M, E, prec.
+ *   C   device, mp_c_bytes(M, E, prec) bytes, column-major with ld = 2 ldm:
+ *       column k: rows [0, ldm) = Re alpha'_k, rows [ldm, 2 ldm) = Im alpha'_k;
+ *       column E+k: rows [0, ldm) = Re beta'_k, rows [ldm, 2 ldm) = -Im beta'_k.
+ *       FP64 -> double, every other precision -> float.
+ *   workspace  device, >= mp_propagate_workspace(M, prec) bytes, 256-aligned;
+ *       overwritten (T is re-packed on every call).
+ */
+mp_status mp_propagate(int32_t M, int64_t E, const double* T, mp_precision prec,
+                       const void* ab, void* C, void* workspace, size_t ws_bytes,
+                       void* stream);
+
+/* ---------------------------------------------------------------- S3-S5 */
+
+/* Complex accumulator entries per sub-ensemble for a bin layout:
+ * joint -> prod K_b, marginals -> sum K_b (+ K_total). */
+int64_t mp_acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K);
+
+/* Workspace bytes mp_binned_counts needs for one call. */
+size_t mp_binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E,
+                           int32_t n_sub, int64_t samples_per_sub, int64_t e0);
+
+/*
+ * Grouped count observables (eq. General_GCP) of one chunk, accumulated per
+ * sub-ensemble (Appendix A).  For each sample:
+ *   n'_i = alpha'_i beta'_i,  n_b = sum_{i in S_b} n'_i,  n_S = sum_b n_b,
+ * and the generating function of eq. c-number-variable summed over patterns,
+ *   chi(z) = sum_m G(m) prod_b z_b^m_b = cosh(n + X) / cosh(n),
+ *   X = sum_b n_b (z_b - 1)       (MP_PLUS_P: chi = exp(X)),
+ * with the global n of the inputs, evaluated on z_b = exp(2 pi i k / K_b) and
+ * multiplied by z_b^(-m_lo_b) so that the window [m_lo_b, m_lo_b + K_b) maps
+ * to residues 0..K_b-1.  Sums over the samples of each sub-ensemble are added
+ * into acc (two-pass, deterministic: no floating-point atomics).
+ *
+ *   C, n        as written by mp_propagate / mp_sample for this chunk
+ *   d           bins, 1..MP_MAX_BINS (MP_JOINT: d <= 2)
+ *   bin_of_mode host int32[M], values in [-1, d); -1 = not counted.  Each bin
+ *               must be a union of contiguous mode runs, at most MP_MAX_RUNS
+ *               runs in total.
+ *   m_lo, K     host int32 per distribution (d of them, d+1 with the total
+ *               last); m_lo >= 0, 1 <= K <= 65536
+ *   n_sub, samples_per_sub  sub-ensembles N_R and their size N_S; global
+ *               sample g belongs to sub-ensemble g / N_S < n_sub
+ *   e0          global index of the chunk's first sample
+ *   acc         device FP64, n_sub * mp_acc_entries * 2 doubles (re, im), laid
+ *               out [sub-ensemble][distribution][k]; zeroed by the caller
+ *               before the first chunk.
+ *   workspace   device, >= mp_binned_workspace(...) bytes, 256-aligned.
+ */
+mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
+                           mp_precision prec, mp_estimator est, int32_t d,
+                           const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                           const int32_t* K, int32_t n_sub, int64_t samples_per_sub,
+                           int64_t e0, double* acc, void* workspace, size_t ws_bytes,
+                           void* stream);
+
+/*
+ * Inverse DFT of each sub-ensemble's mean characteristic function,
+ *   P_s(m_lo + l) = (1/K) sum_k chi_s(k) exp(-2 pi i k l / K),
+ * then P = mean_s P_s and sigma_T = sd_s(Re P_s) / sqrt(n_sub) (Appendix A;
+ * NaN when n_sub = 1).  Counts outside a window alias into it mod K.
+ *
+ *   acc     device, complete accumulators (all n_sub * samples_per_sub samples)
+ *   P_re, P_im, sigma  device FP64[mp_acc_entries]; P_im may be NULL.
+ *           Joint layout [k1][k2]; marginal layout concatenated per distribution.
+ */
+mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                             int64_t samples_per_sub, const double* acc, double* P_re,
+                             double* P_im, double* sigma, void* stream);
+
+/* Message of the calling thread's last non-MP_OK status ("" if none). */
+const char* mp_last_error(void);
+
+/* Library version string. */
+const char* mp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGBS_H */

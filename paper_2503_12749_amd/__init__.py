@@ -1,0 +1,194 @@
+"""MI355X matrix-P Gaussian-boson-sampling hot path (arXiv:2503.12749).
+
+Thin Python layer over libmpgbs.so (include/mpgbs.h).  The functions below
+keep the C entry-point names and only marshal arguments: every step of the
+path (sampling, propagation, occupations, characteristic function, sample
+reduction, inverse DFT) runs in the library's HIP kernels.  PyTorch provides
+device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import BIN_MODES, ESTIMATORS, MPError, PRECISIONS, i32_array
+
+__all__ = [
+    "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
+    "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
+    "mp_counts_finalize", "mp_version", "CountsPipeline", "MPError",
+]
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _mode(m) -> int:
+    return BIN_MODES[m] if isinstance(m, str) else int(m)
+
+
+def _est(e) -> int:
+    return ESTIMATORS[e] if isinstance(e, str) else int(e)
+
+
+def mp_ld_modes(M: int) -> int:
+    return int(_lib.load().mp_ld_modes(M))
+
+
+def mp_ab_bytes(M: int, E: int, prec) -> int:
+    return int(_lib.load().mp_ab_bytes(M, E, _prec(prec)))
+
+
+def mp_c_bytes(M: int, E: int, prec) -> int:
+    return int(_lib.load().mp_c_bytes(M, E, _prec(prec)))
+
+
+def mp_propagate_workspace(M: int, prec) -> int:
+    return int(_lib.load().mp_propagate_workspace(M, _prec(prec)))
+
+
+def mp_acc_entries(d: int, mode, K) -> int:
+    return int(_lib.load().mp_acc_entries(d, _mode(mode), i32_array(K)))
+
+
+def mp_binned_workspace(d: int, mode, K, E: int, n_sub: int, samples_per_sub: int, e0: int) -> int:
+    return int(_lib.load().mp_binned_workspace(d, _mode(mode), i32_array(K), E, n_sub,
+                                               samples_per_sub, e0))
+
+
+def mp_version() -> str:
+    return _lib.load().mp_version().decode()
+
+
+def mp_sample(M, g0, E, r, seed, net, prec, ab, n_out, stream=None):
+    """r: device float64[M]; ab: device buffer of mp_ab_bytes; n_out: device float64[E]."""
+    _lib.check(_lib.load().mp_sample(M, g0, E, _ptr(r), seed, net, _prec(prec), _ptr(ab),
+                                     _ptr(n_out), _stream(stream)))
+
+
+def mp_propagate(M, E, T, prec, ab, C, workspace, stream=None):
+    """T: device float64 view of the row-major complex M x M matrix."""
+    _lib.check(_lib.load().mp_propagate(M, E, _ptr(T), _prec(prec), _ptr(ab), _ptr(C),
+                                        _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                        _stream(stream)))
+
+
+def mp_binned_counts(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub,
+                     samples_per_sub, e0, acc, workspace, stream=None):
+    """bin_of_mode, m_lo, K: host integer sequences."""
+    _lib.check(_lib.load().mp_binned_counts(
+        M, E, _ptr(C), _ptr(n), _prec(prec), _est(est), d, i32_array(bin_of_mode), _mode(mode),
+        i32_array(m_lo), i32_array(K), n_sub, samples_per_sub, e0, _ptr(acc), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def mp_counts_finalize(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma, stream=None):
+    _lib.check(_lib.load().mp_counts_finalize(d, _mode(mode), i32_array(K), n_sub, samples_per_sub,
+                                              _ptr(acc), _ptr(P_re), _ptr(P_im), _ptr(sigma),
+                                              _stream(stream)))
+
+
+class CountsPipeline:
+    """Owns the device buffers of one workload and runs it chunk by chunk:
+    mp_sample -> mp_propagate -> mp_binned_counts per chunk, then
+    mp_counts_finalize.  All buffers are allocated once, in __init__."""
+
+    def __init__(self, T: np.ndarray, r: np.ndarray, *, prec="fp64", seed: int, net: int = 0,
+                 bin_of_mode=None, d: int = 1, mode="joint", windows, n_sub: int,
+                 samples_per_sub: int, chunk: int, est="matrix_p", device="cuda:0"):
+        import torch
+        self.torch = torch
+        T = np.ascontiguousarray(T, dtype=np.complex128)
+        self.M = int(T.shape[0])
+        assert T.shape == (self.M, self.M)
+        self.prec = _prec(prec)
+        self.est = _est(est)
+        self.mode = _mode(mode)
+        self.seed, self.net, self.d = int(seed), int(net), int(d)
+        self.bins = (np.zeros(self.M, np.int32) if bin_of_mode is None
+                     else np.asarray(bin_of_mode, dtype=np.int32))
+        self.m_lo = [int(w[0]) for w in windows]
+        self.K = [int(w[1]) for w in windows]
+        self.n_sub, self.ns, self.chunk = int(n_sub), int(samples_per_sub), int(chunk)
+        dev = torch.device(device)
+        self.device = dev
+        self.T = torch.from_numpy(T.view(np.float64).reshape(-1).copy()).to(dev)
+        self.r = torch.from_numpy(np.asarray(r, dtype=np.float64).copy()).to(dev)
+        self.ab = torch.empty(mp_ab_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
+        self.C = torch.empty(mp_c_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
+        self.n = torch.empty(self.chunk, dtype=torch.float64, device=dev)
+        self.ws_prop = torch.empty(mp_propagate_workspace(self.M, self.prec), dtype=torch.uint8, device=dev)
+        self.entries = mp_acc_entries(self.d, self.mode, self.K)
+        if self.entries < 0:
+            raise MPError(-1, "invalid bin layout")
+        # a chunk touches at most chunk // ns + 2 sub-ensembles, each adding at
+        # most one partial tile of 64 samples
+        blocks = -(-self.chunk // 64) + self.chunk // self.ns + 2
+        self.ws_counts = torch.empty(blocks * self.entries * 16 + 256, dtype=torch.uint8, device=dev)
+        self.acc = torch.zeros(self.n_sub * self.entries * 2, dtype=torch.float64, device=dev)
+        self.P_re = torch.empty(self.entries, dtype=torch.float64, device=dev)
+        self.P_im = torch.empty(self.entries, dtype=torch.float64, device=dev)
+        self.sigma = torch.empty(self.entries, dtype=torch.float64, device=dev)
+
+    def reset(self):
+        self.acc.zero_()
+
+    def run_chunk(self, g0: int, E: int, stream=None):
+        assert 1 <= E <= self.chunk
+        mp_sample(self.M, g0, E, self.r, self.seed, self.net, self.prec, self.ab, self.n, stream)
+        mp_propagate(self.M, E, self.T, self.prec, self.ab, self.C, self.ws_prop, stream)
+        self.counts_chunk(g0, E, stream)
+
+    def counts_chunk(self, g0: int, E: int, stream=None):
+        mp_binned_counts(self.M, E, self.C, self.n, self.prec, self.est, self.d, self.bins, self.mode,
+                         self.m_lo, self.K, self.n_sub, self.ns, g0, self.acc, self.ws_counts, stream)
+
+    def finalize(self, stream=None):
+        mp_counts_finalize(self.d, self.mode, self.K, self.n_sub, self.ns, self.acc, self.P_re,
+                           self.P_im, self.sigma, stream)
+
+    def run(self, E_total: int | None = None, g_start: int = 0, stream=None):
+        E_total = self.n_sub * self.ns if E_total is None else E_total
+        done = 0
+        while done < E_total:
+            c = min(self.chunk, E_total - done)
+            self.run_chunk(g_start + done, c, stream)
+            done += c
+        self.finalize(stream)
+
+    def result(self):
+        """(P_re, P_im, sigma) as numpy arrays (synchronises)."""
+        return (self.P_re.cpu().numpy(), self.P_im.cpu().numpy(), self.sigma.cpu().numpy())
+
+    def alpha_beta(self, E: int):
+        """Views of the last chunk's stored amplitudes as numpy (E, M) arrays
+        (FP64 and FP32 storage only; synchronises)."""
+        t = self.torch
+        ldm = mp_ld_modes(self.M)
+        dt = {0: t.float64, 1: t.float32}[self.prec]
+        v = self.ab.view(dt)[: ldm * 2 * E].reshape(2 * E, ldm)[:, : self.M].double().cpu().numpy()
+        return v[:E], v[E:]
+
+    def propagated(self, E: int):
+        """(alpha', beta') of the last chunk as complex numpy (E, M) arrays."""
+        t = self.torch
+        ldm = mp_ld_modes(self.M)
+        dt = t.float64 if self.prec == 0 else t.float32
+        v = self.C.view(dt)[: 2 * ldm * 2 * E].reshape(2 * E, 2 * ldm).double().cpu().numpy()
+        a = v[:E, : self.M] + 1j * v[:E, ldm: ldm + self.M]
+        b = v[E:, : self.M] - 1j * v[E:, ldm: ldm + self.M]
+        return a, b

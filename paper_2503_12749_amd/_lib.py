@@ -1,0 +1,79 @@
+"""ctypes binding of libmpgbs.so (include/mpgbs.h): argument marshalling only.
+
+The library is loaded from this package directory; there is no fallback of any
+kind, so a missing or unloadable library raises at import of the binding."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpgbs.so")
+
+MP_OK, MP_ERR_ARG, MP_ERR_SHAPE, MP_ERR_HIP, MP_ERR_UNSUPPORTED, MP_ERR_WORKSPACE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
+BIN_MODES = {"joint": 0, "marginals": 1, "marginals_and_total": 2}
+ESTIMATORS = {"matrix_p": 0, "plus_p": 1}
+MP_MAX_BINS = 8
+MP_MAX_RUNS = 16
+
+EXPORTS = [
+    "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
+    "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
+    "mp_counts_finalize", "mp_last_error", "mp_version",
+]
+
+
+class MPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libmpgbs status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the library once; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2503_12749_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_i32, c_i64, c_u64, c_u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "mp_ld_modes": (c_i64, [c_i32]),
+        "mp_ab_bytes": (sz, [c_i32, c_i64, ctypes.c_int]),
+        "mp_c_bytes": (sz, [c_i32, c_i64, ctypes.c_int]),
+        "mp_sample": (ctypes.c_int, [c_i32, c_i64, c_i64, vp, c_u64, c_u32, ctypes.c_int, vp, vp, vp]),
+        "mp_propagate_workspace": (sz, [c_i32, ctypes.c_int]),
+        "mp_propagate": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, vp, vp, vp, sz, vp]),
+        "mp_acc_entries": (c_i64, [c_i32, ctypes.c_int, i32p]),
+        "mp_binned_workspace": (sz, [c_i32, ctypes.c_int, i32p, c_i64, c_i32, c_i64, c_i64]),
+        "mp_binned_counts": (ctypes.c_int, [c_i32, c_i64, vp, vp, ctypes.c_int, ctypes.c_int, c_i32,
+                                            i32p, ctypes.c_int, i32p, i32p, c_i32, c_i64, c_i64,
+                                            vp, vp, sz, vp]),
+        "mp_counts_finalize": (ctypes.c_int, [c_i32, ctypes.c_int, i32p, c_i32, c_i64, vp, vp, vp,
+                                              vp, vp]),
+        "mp_last_error": (ctypes.c_char_p, []),
+        "mp_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != MP_OK:
+        raise MPError(status, load().mp_last_error().decode())
+
+
+def i32_array(values) -> ctypes.Array:
+    vals = [int(v) for v in values]
+    return (ctypes.c_int32 * max(1, len(vals)))(*vals)

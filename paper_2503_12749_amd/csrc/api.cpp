@@ -1,0 +1,169 @@
+// C ABI of libmpgbs: host-side argument validation and dispatch to the
+// kernels of sample.hip, propagate.hip and counts.hip.  Every entry point
+// validates synchronously, enqueues nothing on failure, and records a
+// thread-local message for mp_last_error().
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+
+namespace mp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint64_t seed,
+                        uint32_t net, mp_precision prec, void* ab, double* n_out,
+                        hipStream_t stream);
+size_t propagate_workspace(int32_t M, mp_precision prec);
+mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision prec,
+                           const void* ab, void* C, void* ws, hipStream_t stream);
+int64_t acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K);
+size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
+                        int64_t ns, int64_t e0);
+mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double* n,
+                               mp_precision prec, mp_estimator est, int32_t d,
+                               const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                               const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
+                               double* acc, void* ws, size_t ws_bytes, hipStream_t stream);
+mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                                 int64_t ns, const double* acc, double* P_re, double* P_im,
+                                 double* sigma, hipStream_t stream);
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static int n_dist_of(int32_t d, mp_bin_mode mode) {
+  if (mode == MP_JOINT) return d;
+  return d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
+}
+
+}  // namespace mp
+
+using namespace mp;
+
+extern "C" {
+
+int64_t mp_ld_modes(int32_t M) { return M < 1 ? -1 : ld_modes(M); }
+
+size_t mp_ab_bytes(int32_t M, int64_t E, mp_precision prec) {
+  if (M < 1 || E < 1 || !valid_prec(prec)) return 0;
+  return (size_t)ld_modes(M) * (size_t)(2 * E) * elem_bytes_ab(prec);
+}
+
+size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec) {
+  if (M < 1 || E < 1 || !valid_prec(prec)) return 0;
+  return (size_t)(2 * ld_modes(M)) * (size_t)(2 * E) * elem_bytes_c(prec);
+}
+
+mp_status mp_sample(int32_t M, int64_t g0, int64_t E, const double* r, uint64_t seed,
+                    uint32_t net, mp_precision prec, void* ab, double* n_out, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1, MP_ERR_ARG, "mp_sample: M = %d must be >= 1", M);
+  MP_CHECK_ARG(E >= 1, MP_ERR_ARG, "mp_sample: E = %lld must be >= 1", (long long)E);
+  MP_CHECK_ARG(g0 >= 0, MP_ERR_ARG, "mp_sample: g0 = %lld must be >= 0", (long long)g0);
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_sample: unknown precision %d", (int)prec);
+  MP_CHECK_ARG(r && ab && n_out, MP_ERR_ARG, "mp_sample: null pointer argument");
+  MP_CHECK_ARG(aligned(ab, 16), MP_ERR_ARG, "mp_sample: ab must be 16-byte aligned");
+  return sample_launch(M, g0, E, r, seed, net, prec, ab, n_out, (hipStream_t)stream);
+}
+
+size_t mp_propagate_workspace(int32_t M, mp_precision prec) {
+  if (M < 1 || !valid_prec(prec)) return 0;
+  return propagate_workspace(M, prec);
+}
+
+mp_status mp_propagate(int32_t M, int64_t E, const double* T, mp_precision prec, const void* ab,
+                       void* C, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1, MP_ERR_ARG, "mp_propagate: M = %d must be >= 1", M);
+  MP_CHECK_ARG(E >= 1, MP_ERR_ARG, "mp_propagate: E = %lld must be >= 1", (long long)E);
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_propagate: unknown precision %d", (int)prec);
+  MP_CHECK_ARG(T && ab && C, MP_ERR_ARG, "mp_propagate: null pointer argument");
+  MP_CHECK_ARG(aligned(ab, 16) && aligned(C, 16), MP_ERR_ARG,
+               "mp_propagate: ab and C must be 16-byte aligned");
+  const size_t need = propagate_workspace(M, prec);
+  MP_CHECK_ARG(workspace && ws_bytes >= need && aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_propagate: workspace of %zu bytes (256-aligned) needed, %zu given", need,
+               ws_bytes);
+  return propagate_launch(M, E, T, prec, ab, C, workspace, (hipStream_t)stream);
+}
+
+int64_t mp_acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K) {
+  if (!K || d < 1 || d > MP_MAX_BINS || mode < MP_JOINT || mode > MP_MARGINALS_AND_TOTAL) return -1;
+  if (mode == MP_JOINT && d > 2) return -1;
+  const int nd = n_dist_of(d, mode);
+  for (int q = 0; q < nd; ++q)
+    if (K[q] < 1 || K[q] > 65536) return -1;
+  return acc_entries(d, mode, K);
+}
+
+size_t mp_binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E,
+                           int32_t n_sub, int64_t samples_per_sub, int64_t e0) {
+  if (mp_acc_entries(d, mode, K) < 0) return 0;
+  return binned_workspace(d, mode, K, E, n_sub, samples_per_sub, e0);
+}
+
+mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
+                           mp_precision prec, mp_estimator est, int32_t d,
+                           const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                           const int32_t* K, int32_t n_sub, int64_t samples_per_sub, int64_t e0,
+                           double* acc, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1 && E >= 1, MP_ERR_ARG, "mp_binned_counts: M and E must be >= 1");
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_binned_counts: unknown precision %d", (int)prec);
+  MP_CHECK_ARG(est == MP_MATRIX_P || est == MP_PLUS_P, MP_ERR_ARG,
+               "mp_binned_counts: unknown estimator %d", (int)est);
+  MP_CHECK_ARG(d >= 1 && d <= MP_MAX_BINS, MP_ERR_ARG, "mp_binned_counts: d = %d outside [1, %d]",
+               d, MP_MAX_BINS);
+  MP_CHECK_ARG(mode >= MP_JOINT && mode <= MP_MARGINALS_AND_TOTAL, MP_ERR_ARG,
+               "mp_binned_counts: unknown bin mode %d", (int)mode);
+  MP_CHECK_ARG(C && n && bin_of_mode && m_lo && K && acc, MP_ERR_ARG,
+               "mp_binned_counts: null pointer argument");
+  MP_CHECK_ARG(n_sub >= 1 && samples_per_sub >= 1 && e0 >= 0, MP_ERR_ARG,
+               "mp_binned_counts: n_sub, samples_per_sub must be >= 1 and e0 >= 0");
+  for (int j = 0; j < M; ++j)
+    MP_CHECK_ARG(bin_of_mode[j] >= -1 && bin_of_mode[j] < d, MP_ERR_ARG,
+                 "mp_binned_counts: bin_of_mode[%d] = %d outside [-1, %d)", j, bin_of_mode[j], d);
+  const int nd = n_dist_of(d, mode);
+  for (int q = 0; q < nd; ++q) {
+    MP_CHECK_ARG(K[q] >= 1 && K[q] <= 65536, MP_ERR_ARG,
+                 "mp_binned_counts: K[%d] = %d outside [1, 65536]", q, K[q]);
+    MP_CHECK_ARG(m_lo[q] >= 0, MP_ERR_ARG, "mp_binned_counts: m_lo[%d] = %d < 0", q, m_lo[q]);
+  }
+  MP_CHECK_ARG(mode != MP_JOINT || d <= 2, MP_ERR_UNSUPPORTED,
+               "mp_binned_counts: joint distributions need d <= 2");
+  MP_CHECK_ARG(aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_binned_counts: workspace must be 256-byte aligned");
+  return binned_counts_launch(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub,
+                              samples_per_sub, e0, acc, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                             int64_t samples_per_sub, const double* acc, double* P_re,
+                             double* P_im, double* sigma, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(mp_acc_entries(d, mode, K) > 0, MP_ERR_ARG,
+               "mp_counts_finalize: invalid bin layout (d = %d, mode = %d)", d, (int)mode);
+  MP_CHECK_ARG(n_sub >= 1 && samples_per_sub >= 1, MP_ERR_ARG,
+               "mp_counts_finalize: n_sub and samples_per_sub must be >= 1");
+  MP_CHECK_ARG(acc && P_re && sigma, MP_ERR_ARG, "mp_counts_finalize: null pointer argument");
+  return counts_finalize_launch(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma,
+                                (hipStream_t)stream);
+}
+
+const char* mp_last_error(void) { return g_err; }
+
+const char* mp_version(void) { return "mpgbs 0.1 (gfx950)"; }
+
+}  // extern "C"

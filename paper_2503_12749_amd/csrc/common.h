@@ -1,0 +1,59 @@
+// Internal helpers of libmpgbs: status reporting, layout arithmetic, and the
+// small device utilities shared by the kernels of this library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/mpgbs.h"
+
+namespace mp {
+
+// Thread-local message of the last failed call (see mp_last_error).
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define MP_CHECK_ARG(cond, code, ...)      \
+  do {                                     \
+    if (!(cond)) {                         \
+      ::mp::set_error(__VA_ARGS__);        \
+      return code;                         \
+    }                                      \
+  } while (0)
+
+#define MP_HIP_LAUNCH_CHECK(what)                                                  \
+  do {                                                                             \
+    hipError_t e_ = hipGetLastError();                                             \
+    if (e_ != hipSuccess) {                                                        \
+      ::mp::set_error("%s: %s", what, hipGetErrorString(e_));                      \
+      return MP_ERR_HIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+constexpr int kLdAlign = 128;  // mode padding (GEMM tile multiple)
+
+inline int64_t ld_modes(int32_t M) { return ((int64_t)M + kLdAlign - 1) / kLdAlign * kLdAlign; }
+
+inline size_t elem_bytes_ab(mp_precision p) {
+  switch (p) {
+    case MP_FP64: return 8;
+    case MP_FP32: return 4;
+    default: return 4;  // hi + lo planes of 2 bytes each
+  }
+}
+
+inline size_t elem_bytes_c(mp_precision p) { return p == MP_FP64 ? 8 : 4; }
+
+inline bool valid_prec(int p) { return p >= MP_FP64 && p <= MP_SPLIT_FP16; }
+
+// Wave-wide sums (64 lanes) via cross-lane shuffles.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace mp

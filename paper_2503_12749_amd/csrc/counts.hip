@@ -1,0 +1,497 @@
+// Grouped photon-count observables: occupations, matrix-P parity weight and
+// characteristic function (fused), deterministic sub-ensemble reduction, and
+// the FP64 inverse DFT to P(m) with the sub-ensemble error sigma_T.
+//
+// Paper, eq. c-number-variable: per sample the pattern observable is
+// G(m) = g0(n_S, m) prod_i n_i^c_i e^{-n_i} / c_i!, with
+// g0 = (1 + pi_m e^{2 (n_S - n)}) / (1 + e^{-2n}).  Summed over the patterns of
+// each bin (multinomial theorem) and over all counts with weights z_b^m_b,
+//     chi(z) = (e^X + e^{-X - 2n}) / (1 + e^{-2n}) = cosh(n + X) / cosh(n),
+//     X = sum_b n_b (z_b - 1),
+// so the count distribution of the ensemble is the inverse DFT of the mean
+// chi on z = e^{2 pi i k / K}.  Each evaluation also carries the window shift
+// z^{-m_lo}, and both terms are formed as exp(real exponent) * cis(phase)
+// with the exponent shifted by -log(1 + e^{-2|n|}) so that nothing overflows
+// for either sign of n.  The positive-P variant (Appendix A) drops g0: chi = e^X.
+//
+// Sub-ensembles (Appendix A): samples g in [s N_S, (s+1) N_S) form
+// sub-ensemble s; P is the mean of the sub-ensemble estimates and sigma_T
+// their standard deviation over sqrt(N_R).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace mp {
+
+constexpr int kSBlk = 64;       // samples per workgroup of the fused kernel
+constexpr int kCountThreads = 256;
+constexpr int kEpt = 4;         // accumulator entries per thread per pass
+constexpr int kMaxDist = MP_MAX_BINS + 1;
+
+struct CountsParams {
+  int M;
+  int64_t ldm;
+  int64_t E;        // samples in the chunk
+  int64_t e0;       // global index of the chunk's first sample
+  int64_t ns;       // samples per sub-ensemble
+  int d;
+  int mode;         // mp_bin_mode
+  int est;          // mp_estimator
+  int n_runs;
+  int run_lo[MP_MAX_RUNS], run_hi[MP_MAX_RUNS], run_bin[MP_MAX_RUNS];
+  int n_dist;
+  int dist_src[kMaxDist];  // bin index feeding each distribution, -1 = total
+  int m_lo[kMaxDist], K[kMaxDist];
+  int off[kMaxDist + 1];   // entry offsets (prefix sums of K)
+  int entries;
+  // block -> (sub-ensemble, tile) arithmetic
+  int64_t s_first, s_last;
+  int t_first, t_mid, t_last, n_mid;
+};
+
+__host__ __device__ inline int64_t sub_lo(const CountsParams& p, int64_t s) {
+  int64_t a = s * p.ns;
+  return a > p.e0 ? a : p.e0;
+}
+__host__ __device__ inline int64_t sub_hi(const CountsParams& p, int64_t s) {
+  int64_t a = (s + 1) * p.ns, b = p.e0 + p.E;
+  return a < b ? a : b;
+}
+
+// Block b -> sub-ensemble s and global sample range [lo, hi).
+__device__ inline void block_samples(const CountsParams& p, int b, int64_t& s, int64_t& lo,
+                                     int64_t& hi) {
+  int tile;
+  if (b < p.t_first) {
+    s = p.s_first;
+    tile = b;
+  } else {
+    b -= p.t_first;
+    if (b < p.n_mid * p.t_mid) {
+      s = p.s_first + 1 + b / p.t_mid;
+      tile = b % p.t_mid;
+    } else {
+      s = p.s_last;
+      tile = b - p.n_mid * p.t_mid;
+    }
+  }
+  const int64_t a = sub_lo(p, s), z = sub_hi(p, s);
+  lo = a + (int64_t)tile * kSBlk;
+  hi = lo + kSBlk < z ? lo + kSBlk : z;
+}
+
+// One sample's partial n'_j sums over a mode range, wave-reduced.
+template <typename CT>
+__device__ inline void run_sum(const CT* __restrict__ ca, const CT* __restrict__ cb, int64_t ldm,
+                               int lo, int hi, int lane, double& re, double& im) {
+  double sr = 0.0, si = 0.0;
+  int j = lo + lane;
+  for (; j + 192 < hi; j += 256) {
+    double a[4], b[4], c[4], e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = (double)ca[j + 64 * u];
+      b[u] = (double)ca[ldm + j + 64 * u];
+      c[u] = (double)cb[j + 64 * u];
+      e[u] = (double)cb[ldm + j + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // alpha' = a + i b, beta' = c - i e  ->  n' = (a c + b e) + i (b c - a e)
+      sr += a[u] * c[u] + b[u] * e[u];
+      si += b[u] * c[u] - a[u] * e[u];
+    }
+  }
+  for (; j < hi; j += 64) {
+    const double a = (double)ca[j], b = (double)ca[ldm + j];
+    const double c = (double)cb[j], e = (double)cb[ldm + j];
+    sr += a * c + b * e;
+    si += b * c - a * e;
+  }
+  re = wave_sum(sr);
+  im = wave_sum(si);
+}
+
+__device__ inline double reduce_2pi(double ph) {
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+  return ph - kTwoPi * rint(ph * kInvTwoPi);
+}
+
+template <bool F64>
+__device__ inline void cis_exp(double ex, double ph, double& re, double& im) {
+  if constexpr (F64) {
+    const double mag = exp(ex);
+    double s, c;
+    sincos(ph, &s, &c);
+    re = mag * c;
+    im = mag * s;
+  } else {
+    const float mag = expf((float)ex);
+    float s, c;
+    sincosf((float)reduce_2pi(ph), &s, &c);
+    re = (double)(mag * c);
+    im = (double)(mag * s);
+  }
+}
+
+template <typename CT, bool F64>
+__global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, const CT* __restrict__ C,
+                                                              const double* __restrict__ nglob,
+                                                              double* __restrict__ partials) {
+  __shared__ double s_nb[kSBlk][kMaxDist][2];
+  __shared__ double s_c1[kSBlk], s_c2[kSBlk];
+  __shared__ int s_skip2[kSBlk];
+  int64_t sub, lo, hi;
+  block_samples(p, blockIdx.x, sub, lo, hi);
+  const int nsmp = (int)(hi - lo);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t ldc = 2 * p.ldm;
+
+  // Phase 1: per-sample bin occupations n_b (wave per sample, lanes over modes).
+  for (int i = wave; i < nsmp; i += kCountThreads / 64) {
+    const int64_t k = lo + i - p.e0;  // chunk-local sample index
+    const CT* ca = C + k * ldc;
+    const CT* cb = C + (p.E + k) * ldc;
+    double nb[MP_MAX_BINS][2];
+#pragma unroll
+    for (int b = 0; b < MP_MAX_BINS; ++b) nb[b][0] = nb[b][1] = 0.0;
+    for (int q = 0; q < p.n_runs; ++q) {
+      double re, im;
+      run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+      const int bq = p.run_bin[q];
+#pragma unroll
+      for (int b = 0; b < MP_MAX_BINS; ++b)
+        if (b == bq) {
+          nb[b][0] += re;
+          nb[b][1] += im;
+        }
+    }
+    if (lane == 0) {
+      double tr = 0.0, ti = 0.0;
+      for (int b = 0; b < p.d; ++b) {
+        tr += nb[b][0];
+        ti += nb[b][1];
+      }
+      for (int q = 0; q < p.n_dist; ++q) {
+        const int src = p.dist_src[q];  // -1: total over all bins
+        double vr = tr, vi = ti;
+#pragma unroll
+        for (int b = 0; b < MP_MAX_BINS; ++b)
+          if (b == src) {
+            vr = nb[b][0];
+            vi = nb[b][1];
+          }
+        s_nb[i][q][0] = vr;
+        s_nb[i][q][1] = vi;
+      }
+      const double n = nglob[k];
+      if (p.est == MP_PLUS_P) {
+        s_c1[i] = 0.0;
+        s_c2[i] = 0.0;
+        s_skip2[i] = 1;
+      } else {
+        const double L = log1p(exp(-2.0 * fabs(n)));
+        s_c1[i] = (n >= 0.0 ? 0.0 : 2.0 * n) - L;
+        s_c2[i] = (n >= 0.0 ? -2.0 * n : 0.0) - L;
+        // |e^{-X}| <= e^{2 |n_b|}: skip the parity partner when it underflows
+        double mx = 0.0;
+        for (int q = 0; q < p.n_dist; ++q) {
+          const double a = sqrt(s_nb[i][q][0] * s_nb[i][q][0] + s_nb[i][q][1] * s_nb[i][q][1]);
+          mx = a > mx ? a : mx;
+        }
+        s_skip2[i] = (2.0 * mx + s_c2[i] < -800.0) ? 1 : 0;
+      }
+    }
+  }
+  __syncthreads();
+
+  // Phase 2: characteristic function on the window grid, summed over samples.
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  for (int base = 0; base < p.entries; base += kCountThreads * kEpt) {
+    double ar[kEpt], ai[kEpt], cm1[kEpt], sn[kEpt], thl[kEpt];
+    int dq[kEpt];
+#pragma unroll
+    for (int u = 0; u < kEpt; ++u) {
+      ar[u] = ai[u] = 0.0;
+      const int e = base + threadIdx.x + u * kCountThreads;
+      int q = 0;
+      while (q + 1 < p.n_dist && e >= p.off[q + 1]) ++q;
+      dq[u] = (e < p.entries) ? q : -1;
+      const int K = p.K[q];
+      const int kk = (e < p.entries) ? e - p.off[q] : 0;
+      const double th = kTwoPi * (double)kk / (double)K;
+      double s, c;
+      sincos(th, &s, &c);
+      sn[u] = s;
+      cm1[u] = -2.0 * sin(0.5 * th) * sin(0.5 * th);  // cos(th) - 1 without cancellation
+      const int64_t red = ((int64_t)kk * (int64_t)p.m_lo[q]) % K;
+      thl[u] = kTwoPi * (double)red / (double)K;     // th * m_lo reduced mod 2 pi
+    }
+    for (int i = 0; i < nsmp; ++i) {
+      const double c1 = s_c1[i], c2 = s_c2[i];
+      const bool skip2 = s_skip2[i] != 0;
+#pragma unroll
+      for (int u = 0; u < kEpt; ++u) {
+        if (dq[u] < 0) continue;
+        const double nr = s_nb[i][dq[u]][0], ni = s_nb[i][dq[u]][1];
+        const double xr = cm1[u] * nr - sn[u] * ni;
+        const double xi = cm1[u] * ni + sn[u] * nr;
+        double tr, ti;
+        cis_exp<F64>(xr + c1, xi - thl[u], tr, ti);
+        ar[u] += tr;
+        ai[u] += ti;
+        if (!skip2) {
+          cis_exp<F64>(c2 - xr, -xi - thl[u], tr, ti);
+          ar[u] += tr;
+          ai[u] += ti;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kEpt; ++u) {
+      const int e = base + threadIdx.x + u * kCountThreads;
+      if (e < p.entries) {
+        double* dst = partials + ((int64_t)blockIdx.x * p.entries + e) * 2;
+        dst[0] = ar[u];
+        dst[1] = ai[u];
+      }
+    }
+  }
+}
+
+// acc[s] += sum over the tiles of s of the partials, in tile order.
+__global__ void counts_reduce(CountsParams p, const double* __restrict__ partials,
+                              double* __restrict__ acc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p.entries) return;
+  const int64_t s = p.s_first + blockIdx.y;
+  int b0, nt;
+  if (s == p.s_first) {
+    b0 = 0;
+    nt = p.t_first;
+  } else if (s == p.s_last) {
+    b0 = p.t_first + p.n_mid * p.t_mid;
+    nt = p.t_last;
+  } else {
+    b0 = p.t_first + (int)(s - p.s_first - 1) * p.t_mid;
+    nt = p.t_mid;
+  }
+  double re = 0.0, im = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const double* src = partials + ((int64_t)(b0 + t) * p.entries + e) * 2;
+    re += src[0];
+    im += src[1];
+  }
+  double* dst = acc + (s * (int64_t)p.entries + e) * 2;
+  dst[0] += re;
+  dst[1] += im;
+}
+
+// ---------------------------------------------------------------- finalize
+
+struct FinalParams {
+  int n_dist;
+  int K[kMaxDist];
+  int off[kMaxDist + 1];
+  int entries;
+  int n_sub;
+  double inv_ns;
+  int joint2;  // 1: one 2-D distribution K[0] x K[1]
+};
+
+// One workgroup per output point; threads split the frequency sum, and the
+// sub-ensemble estimates are folded with Welford's update.
+__global__ __launch_bounds__(256) void counts_finalize(FinalParams p, const double* __restrict__ acc,
+                                                       double* __restrict__ P_re,
+                                                       double* __restrict__ P_im,
+                                                       double* __restrict__ sigma) {
+  __shared__ double red_r[256], red_i[256];
+  const int e = blockIdx.x;
+  int q = 0, l1 = 0, l2 = 0, K1 = 1, K2 = 1, nterms;
+  if (p.joint2) {
+    K1 = p.K[0];
+    K2 = p.K[1];
+    l1 = e / K2;
+    l2 = e % K2;
+    nterms = K1 * K2;
+  } else {
+    while (q + 1 < p.n_dist && e >= p.off[q + 1]) ++q;
+    K1 = p.K[q];
+    l1 = e - p.off[q];
+    nterms = K1;
+  }
+  double mean_r = 0.0, mean_i = 0.0, m2 = 0.0;
+  for (int s = 0; s < p.n_sub; ++s) {
+    const double* a = acc + ((int64_t)s * p.entries + (p.joint2 ? 0 : p.off[q])) * 2;
+    double sr = 0.0, si = 0.0;
+    for (int t = threadIdx.x; t < nterms; t += 256) {
+      int k1 = t, k2 = 0;
+      double frac;
+      if (p.joint2) {
+        k1 = t / K2;
+        k2 = t % K2;
+        frac = (double)(((int64_t)k1 * l1) % K1) / K1 + (double)(((int64_t)k2 * l2) % K2) / K2;
+      } else {
+        frac = (double)(((int64_t)k1 * l1) % K1) / K1;
+      }
+      double sw, cw;
+      sincospi(-2.0 * frac, &sw, &cw);
+      const double xr = a[2 * t], xi = a[2 * t + 1];
+      sr += xr * cw - xi * sw;
+      si += xr * sw + xi * cw;
+    }
+    red_r[threadIdx.x] = sr;
+    red_i[threadIdx.x] = si;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        red_r[threadIdx.x] += red_r[threadIdx.x + w];
+        red_i[threadIdx.x] += red_i[threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double ps_r = red_r[0] * p.inv_ns / nterms, ps_i = red_i[0] * p.inv_ns / nterms;
+      const double dr = ps_r - mean_r;
+      mean_r += dr / (s + 1);
+      mean_i += (ps_i - mean_i) / (s + 1);
+      m2 += dr * (ps_r - mean_r);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    P_re[e] = mean_r;
+    if (P_im) P_im[e] = mean_i;
+    sigma[e] = p.n_sub > 1 ? sqrt(m2 / (p.n_sub - 1) / p.n_sub) : __builtin_nan("");
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+static int64_t entries_of(int d, mp_bin_mode mode, const int32_t* K) {
+  if (mode == MP_JOINT) {
+    int64_t e = 1;
+    for (int b = 0; b < d; ++b) e *= K[b];
+    return e;
+  }
+  int nd = d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
+  int64_t e = 0;
+  for (int q = 0; q < nd; ++q) e += K[q];
+  return e;
+}
+
+int64_t acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K) {
+  if (!K || d < 1 || d > MP_MAX_BINS) return -1;
+  return entries_of(d, mode, K);
+}
+
+// Fills the tiling part of the parameters; returns the number of blocks.
+static int64_t plan_tiles(CountsParams& p) {
+  p.s_first = p.e0 / p.ns;
+  p.s_last = (p.e0 + p.E - 1) / p.ns;
+  auto tiles = [&](int64_t s) { return (int)((sub_hi(p, s) - sub_lo(p, s) + kSBlk - 1) / kSBlk); };
+  p.t_first = tiles(p.s_first);
+  p.t_mid = (int)((p.ns + kSBlk - 1) / kSBlk);
+  p.n_mid = p.s_last > p.s_first + 1 ? (int)(p.s_last - p.s_first - 1) : 0;
+  p.t_last = p.s_last != p.s_first ? tiles(p.s_last) : 0;
+  return (int64_t)p.t_first + (int64_t)p.n_mid * p.t_mid + p.t_last;
+}
+
+size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
+                        int64_t ns, int64_t e0) {
+  if (!K || d < 1 || d > MP_MAX_BINS || E < 1 || ns < 1 || e0 < 0) return 0;
+  CountsParams p{};
+  p.E = E;
+  p.e0 = e0;
+  p.ns = ns;
+  const int64_t blocks = plan_tiles(p);
+  return (size_t)blocks * (size_t)entries_of(d, mode, K) * 16;
+}
+
+mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double* n,
+                               mp_precision prec, mp_estimator est, int32_t d,
+                               const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                               const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
+                               double* acc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  CountsParams p{};
+  p.M = M;
+  p.ldm = ld_modes(M);
+  p.E = E;
+  p.e0 = e0;
+  p.ns = ns;
+  p.d = d;
+  p.mode = mode;
+  p.est = est;
+  MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
+               "mp_binned_counts: the joint distribution of d = %d bins is not supported by this "
+               "build (use d = 1 or the marginal modes)", d);
+  // contiguous runs of each bin
+  p.n_runs = 0;
+  for (int j = 0; j < M;) {
+    const int b = bin_of_mode[j];
+    int j2 = j + 1;
+    while (j2 < M && bin_of_mode[j2] == b) ++j2;
+    if (b >= 0) {
+      MP_CHECK_ARG(p.n_runs < MP_MAX_RUNS, MP_ERR_UNSUPPORTED,
+                   "mp_binned_counts: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
+      p.run_lo[p.n_runs] = j;
+      p.run_hi[p.n_runs] = j2;
+      p.run_bin[p.n_runs] = b;
+      ++p.n_runs;
+    }
+    j = j2;
+  }
+  p.n_dist = mode == MP_JOINT ? 1 : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
+  p.off[0] = 0;
+  for (int q = 0; q < p.n_dist; ++q) {
+    p.dist_src[q] = q < d ? q : -1;
+    p.m_lo[q] = m_lo[q];
+    p.K[q] = K[q];
+    p.off[q + 1] = p.off[q] + K[q];
+  }
+  p.entries = p.off[p.n_dist];
+  const int64_t blocks = plan_tiles(p);
+  MP_CHECK_ARG(p.s_last < n_sub, MP_ERR_SHAPE,
+               "mp_binned_counts: samples [%lld, %lld) exceed n_sub * samples_per_sub = %lld",
+               (long long)e0, (long long)(e0 + E), (long long)n_sub * ns);
+  const size_t need = (size_t)blocks * (size_t)p.entries * 16;
+  MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,
+               "mp_binned_counts: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  MP_CHECK_ARG(blocks < 0x7FFFFFFF, MP_ERR_UNSUPPORTED, "mp_binned_counts: chunk too large");
+  if (prec == MP_FP64) {
+    hipLaunchKernelGGL((counts_fused<double, true>), dim3((unsigned)blocks), dim3(kCountThreads), 0,
+                       stream, p, (const double*)C, n, (double*)ws);
+  } else {
+    hipLaunchKernelGGL((counts_fused<float, false>), dim3((unsigned)blocks), dim3(kCountThreads), 0,
+                       stream, p, (const float*)C, n, (double*)ws);
+  }
+  MP_HIP_LAUNCH_CHECK("mp_binned_counts fused launch");
+  const int ns_touched = (int)(p.s_last - p.s_first + 1);
+  hipLaunchKernelGGL(counts_reduce, dim3((p.entries + 255) / 256, ns_touched), dim3(256), 0, stream,
+                     p, (const double*)ws, acc);
+  MP_HIP_LAUNCH_CHECK("mp_binned_counts reduce launch");
+  return MP_OK;
+}
+
+mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                                 int64_t ns, const double* acc, double* P_re, double* P_im,
+                                 double* sigma, hipStream_t stream) {
+  FinalParams p{};
+  p.joint2 = (mode == MP_JOINT && d == 2) ? 1 : 0;
+  p.n_dist = mode == MP_JOINT ? (p.joint2 ? 2 : 1) : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
+  p.off[0] = 0;
+  for (int q = 0; q < p.n_dist; ++q) {
+    p.K[q] = K[q];
+    p.off[q + 1] = p.off[q] + K[q];
+  }
+  p.entries = (int)entries_of(d, mode, K);
+  p.n_sub = n_sub;
+  p.inv_ns = 1.0 / (double)ns;
+  hipLaunchKernelGGL(counts_finalize, dim3(p.entries), dim3(256), 0, stream, p, acc, P_re, P_im,
+                     sigma);
+  MP_HIP_LAUNCH_CHECK("mp_counts_finalize launch");
+  return MP_OK;
+}
+
+}  // namespace mp

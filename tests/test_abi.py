@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports every symbol include/mpgbs.h declares, and
+validates arguments on the host (CPU only: no call here reaches a kernel)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpgbs.h")
+
+
+def _lib():
+    from paper_2503_12749_amd import _lib
+    return _lib.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib()
+    names = _declared()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2503_12749_amd import _lib as binding
+    assert sorted(binding.EXPORTS) == names
+
+
+def test_sizes():
+    import paper_2503_12749_amd as mp
+    assert mp.mp_ld_modes(1) == 128 and mp.mp_ld_modes(128) == 128 and mp.mp_ld_modes(8000) == 8064
+    assert mp.mp_ld_modes(0) == -1
+    assert mp.mp_ab_bytes(16, 10, "fp64") == 128 * 20 * 8
+    assert mp.mp_ab_bytes(16, 10, "split_bf16") == 128 * 20 * 4
+    assert mp.mp_c_bytes(16, 10, "fp32") == 256 * 20 * 4
+    assert mp.mp_c_bytes(16, 0, "fp32") == 0
+    assert mp.mp_propagate_workspace(16, "fp64") == 256 * 128 * 8
+    assert mp.mp_acc_entries(1, "joint", [128]) == 128
+    assert mp.mp_acc_entries(2, "joint", [16, 8]) == 128
+    assert mp.mp_acc_entries(3, "marginals_and_total", [4, 5, 6, 7]) == 22
+    assert mp.mp_acc_entries(3, "joint", [4, 4, 4]) == -1
+    assert mp.mp_acc_entries(1, "joint", [0]) == -1
+    # E = 1000 samples from e0 = 500 with N_S = 300: sub-ensembles 1..5
+    ws = mp.mp_binned_workspace(1, "joint", [64], 1000, 10, 300, 500)
+    # 100 + 300 + 300 + 300 samples in tiles of 64 -> 2 + 5 + 5 + 5 partial blocks
+    assert ws == (2 + 5 + 5 + 5) * 64 * 16
+    assert "gfx950" in mp.mp_version()
+
+
+def _call_sample(**kw):
+    lib = _lib()
+    a = dict(M=4, g0=0, E=8, r=1, seed=1, net=0, prec=0, ab=16, n=16)
+    a.update(kw)
+    p = lambda v: ctypes.c_void_p(v)
+    return lib.mp_sample(a["M"], a["g0"], a["E"], p(a["r"]), a["seed"], a["net"], a["prec"],
+                         p(a["ab"]), p(a["n"]), None)
+
+
+def test_host_validation_rejects_bad_arguments():
+    lib = _lib()
+    assert _call_sample(M=0) == -1
+    assert b"M = 0" in lib.mp_last_error()
+    assert _call_sample(E=0) == -1
+    assert _call_sample(g0=-5) == -1
+    assert _call_sample(prec=7) == -1
+    assert _call_sample(r=0) == -1
+    assert _call_sample(ab=17) == -1   # misaligned
+    vp = ctypes.c_void_p
+    # propagate: missing workspace
+    assert lib.mp_propagate(16, 4, vp(16), 0, vp(16), vp(16), vp(0), 0, None) == -5
+    assert lib.mp_propagate(16, 4, vp(16), 0, vp(16), vp(16), vp(256), 10, None) == -5
+    # binned counts: bin index out of range, too many runs, bad K
+    i32 = lambda xs: (ctypes.c_int32 * len(xs))(*xs)
+    bins = i32([0, 1, 5, 0])
+    st = lib.mp_binned_counts(4, 8, vp(16), vp(16), 0, 0, 2, bins, 1, i32([0, 0]), i32([8, 8]), 1,
+                              8, 0, vp(16), vp(256), 1 << 20, None)
+    assert st == -1 and b"bin_of_mode[2]" in lib.mp_last_error()
+    alt = i32([j % 2 for j in range(40)])
+    st = lib.mp_binned_counts(40, 8, vp(16), vp(16), 0, 0, 2, alt, 1, i32([0, 0]), i32([8, 8]), 1,
+                              8, 0, vp(16), vp(256), 1 << 20, None)
+    assert st == -4 and b"runs" in lib.mp_last_error()
+    st = lib.mp_binned_counts(4, 8, vp(16), vp(16), 0, 0, 1, i32([0] * 4), 0, i32([0]), i32([0]), 1,
+                              8, 0, vp(16), vp(256), 1 << 20, None)
+    assert st == -1
+    # samples beyond n_sub * samples_per_sub
+    st = lib.mp_binned_counts(4, 8, vp(16), vp(16), 0, 0, 1, i32([0] * 4), 0, i32([0]), i32([8]), 1,
+                              4, 0, vp(16), vp(256), 1 << 20, None)
+    assert st == -2
+    # workspace too small
+    st = lib.mp_binned_counts(4, 8, vp(16), vp(16), 0, 0, 1, i32([0] * 4), 0, i32([0]), i32([8]), 1,
+                              8, 0, vp(16), vp(256), 16, None)
+    assert st == -5
+    st = lib.mp_counts_finalize(1, 0, i32([8]), 0, 8, vp(16), vp(16), vp(16), vp(16), None)
+    assert st == -1

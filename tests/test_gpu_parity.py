@@ -1,0 +1,233 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on
+identical seeded inputs and identical Philox noise.
+
+Tolerances
+  FP64 path: every binned probability within 1e-10 relative, with an
+  absolute floor of 1e-14 * max P for tail bins (FP64 rounding of the sums);
+  intermediate buffers within a few hundred ulps of their magnitude.
+  FP32 / split-BF16 paths: operands are rounded to 24 / ~16 significant bits,
+  so propagated amplitudes carry relative errors ~ sqrt(M) 2^-24 (FP32) and
+  ~ sqrt(M) 2^-17 (split BF16) of the column norm; the probabilities must stay
+  far inside the sampling error sigma_T.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator as oest
+from oracle import exact, sampler as osamp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_12749_amd as mp  # noqa: F401  (fails loudly if the library is missing)
+    yield
+
+
+def _pipe(T, r, **kw):
+    import paper_2503_12749_amd as mp
+    return mp.CountsPipeline(T, r, device=DEV, **kw)
+
+
+def _p_close(P, ref, rel=1e-10, floor=1e-14, scale=None):
+    scale = np.abs(ref).max() if scale is None else scale
+    tol = rel * np.maximum(np.abs(ref), 1e-4 * scale) + floor * scale
+    bad = np.abs(P - ref) > tol
+    assert not bad.any(), (np.flatnonzero(bad)[:10], (P - ref)[bad][:5], ref[bad][:5])
+
+
+def test_sampler_matches_oracle_fp64():
+    r = np.concatenate([np.linspace(0.2, 1.5, 37), [0.0, 0.0]])
+    M = r.size
+    T = np.eye(M, dtype=np.complex128)
+    p = _pipe(T, r, prec="fp64", seed=4242, windows=[(0, 64)], n_sub=1, samples_per_sub=1000,
+              chunk=300)
+    g0, E = 123, 257
+    import paper_2503_12749_amd as mp
+    mp.mp_sample(M, g0, E, p.r, p.seed, 3, "fp64", p.ab, p.n)
+    a_gpu, b_gpu = p.alpha_beta(E)
+    a, b, n = osamp.sample(r, g0, E, 4242, net=3)
+    np.testing.assert_allclose(a_gpu, a, rtol=0, atol=1e-14 * np.abs(a).max())
+    np.testing.assert_allclose(b_gpu, b, rtol=0, atol=1e-14 * np.abs(b).max())
+    np.testing.assert_allclose(p.n[:E].cpu().numpy(), n, rtol=0, atol=1e-13 * np.abs(n).max())
+    assert np.all(a_gpu[:, -2:] == 0) and np.all(b_gpu[:, -2:] == 0)
+    # padding rows of the mode-major layout are zero
+    ldm = mp.mp_ld_modes(M)
+    raw = p.ab.view(torch.float64)[: ldm * 2 * E].reshape(2 * E, ldm)
+    assert torch.all(raw[:, M:] == 0)
+
+
+@pytest.mark.parametrize("M,E", [(16, 1000), (200, 333), (1, 7), (257, 130)])
+def test_propagate_fp64_matches_oracle(M, E):
+    T = 0.8 * synth.haar_unitary(M, 100 + M)
+    r = synth.squeezing_random_uniform(M, 0.3, 1.2, M)
+    p = _pipe(T, r, prec="fp64", seed=9, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
+    import paper_2503_12749_amd as mp
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, "fp64", p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, "fp64", p.ab, p.C, p.ws_prop)
+    ag, bg = p.propagated(E)
+    a, b, n = osamp.sample(r, 0, E, 9)
+    ao, bo = oest.propagate(T, a, b)
+    scale = np.abs(ao).max()
+    np.testing.assert_allclose(ag, ao, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(bg, bo, rtol=0, atol=1e-13 * scale)
+    # invariant of T = t U: sum_j alpha'_j beta'_j = t^2 n
+    np.testing.assert_allclose((ag * bg).sum(1), 0.64 * n, rtol=0, atol=1e-12 * np.abs(n).max())
+
+
+def _oracle(w_T, r, seed, E, n_sub, bins, d, windows, mode="joint", plus_p=False):
+    return oest.estimate(w_T, r, seed, E, n_sub, bins, d, windows, mode=mode, plus_p=plus_p,
+                         chunk=4000)
+
+
+def test_small_workload_fp64_parity():
+    """M = 16, Haar x 0.5, r = 1, E = 1e4 (10 x 1e3), total counts on m = 0..127."""
+    w = synth.workload_small()
+    p = _pipe(w.T, w.r, prec="fp64", seed=w.seed, windows=w.windows, n_sub=w.n_sub,
+              samples_per_sub=w.samples_per_sub, chunk=w.chunk)
+    p.run()
+    P, Pi, s = p.result()
+    ref = _oracle(w.T, w.r, w.seed, w.E, w.n_sub, w.bins, 1, w.windows)
+    _p_close(P, ref["P"])
+    _p_close(Pi, ref["P_complex"].imag, scale=ref["P"].max())
+    np.testing.assert_allclose(s, ref["sigma"], rtol=1e-7, atol=1e-14 * ref["P"].max())
+    assert abs(P.sum() - 1) < 1e-12
+
+
+def test_chunking_and_subensemble_boundaries():
+    """Chunks that straddle sub-ensembles (N_S = 100, chunks of 130, ragged M)
+    give the oracle's result; a second run is bit-identical."""
+    M = 200
+    T = 0.9 * synth.haar_unitary(M, 77)
+    r = synth.squeezing_random_uniform(M, 0.2, 0.6, 77)
+    mean, sd = synth.uniform_loss_moments(r, 0.9)
+    win = [synth.count_window(mean, sd, align=16)]
+    p = _pipe(T, r, prec="fp64", seed=55, windows=win, n_sub=7, samples_per_sub=100, chunk=130)
+    p.run()
+    P1 = p.acc.clone()
+    P, Pi, s = p.result()
+    p.reset()
+    p.run()
+    assert torch.equal(P1, p.acc)
+    ref = _oracle(T, r, 55, 700, 7, np.zeros(M, int), 1, win)
+    _p_close(P, ref["P"])
+    np.testing.assert_allclose(s, ref["sigma"], rtol=1e-7, atol=1e-14 * ref["P"].max())
+
+
+def _fold(P_full, m_full, m_lo, K):
+    """Oracle probabilities on counts m_full folded into the window's residues:
+    entry l collects every m with m = m_lo + l (mod K)."""
+    out = np.zeros(K)
+    np.add.at(out, (m_full - m_lo) % K, P_full)
+    return out
+
+
+def test_marginals_total_uncounted_and_vacuum():
+    """Three bins (one split into two runs), uncounted and vacuum modes,
+    marginal distributions plus the total, with window offsets; counts outside
+    a window alias into it mod K."""
+    M = 40
+    T = 0.85 * synth.haar_unitary(M, 5)
+    r = synth.squeezing_random_uniform(M, 0.3, 1.0, 5)
+    r[[3, 17]] = 0.0
+    bins = np.array([0] * 10 + [1] * 10 + [-1] * 5 + [2] * 10 + [0] * 5, dtype=np.int32)
+    wins = [(2, 64), (0, 48), (1, 40), (10, 96)]
+    p = _pipe(T, r, prec="fp64", seed=8, bin_of_mode=bins, d=3, mode="marginals_and_total",
+              windows=wins, n_sub=4, samples_per_sub=500, chunk=700)
+    p.run()
+    P, Pi, s = p.result()
+    off = np.cumsum([0] + [k for _, k in wins])
+    full = [(0, 160)] * 3
+    ref = _oracle(T, r, 8, 2000, 4, bins, 3, full, mode="marginals")
+    m = np.arange(160)
+    for b in range(3):
+        lo, K = wins[b]
+        _p_close(P[off[b]:off[b + 1]], _fold(ref["P"][b], m, lo, K))
+    tot = _oracle(T, r, 8, 2000, 4, np.where(bins >= 0, 0, -1), 1, [(0, 200)])
+    _p_close(P[off[3]:], _fold(tot["P"], np.arange(200), *wins[3]))
+
+
+def test_plus_p_estimator_parity():
+    M = 12
+    T = 0.7 * synth.haar_unitary(M, 3)
+    r = np.full(M, 0.5)
+    p = _pipe(T, r, prec="fp64", seed=2, windows=[(0, 64)], n_sub=5, samples_per_sub=400,
+              chunk=2000, est="plus_p")
+    p.run()
+    P, _, s = p.result()
+    ref = _oracle(T, r, 2, 2000, 5, np.zeros(M, int), 1, [(0, 64)], plus_p=True)
+    _p_close(P, ref["P"])
+
+
+def test_single_mode_negative_n_and_tiny_chunk():
+    """M = 1 (n = alpha beta often negative), E below one tile."""
+    T = np.array([[0.6 * np.exp(0.3j)]])
+    r = np.array([0.5])
+    p = _pipe(T, r, prec="fp64", seed=1, windows=[(0, 32)], n_sub=1, samples_per_sub=7, chunk=7)
+    p.run()
+    P, _, _ = p.result()
+    ref = _oracle(T, r, 1, 7, 1, np.zeros(1, int), 1, [(0, 32)])
+    _p_close(P, ref["P"])
+
+
+def test_lossless_odd_counts_vanish():
+    M = 24
+    U = synth.haar_unitary(M, 31)
+    p = _pipe(U, np.full(M, 0.5), prec="fp64", seed=3, windows=[(0, 64)], n_sub=4,
+              samples_per_sub=500, chunk=2000)
+    p.run()
+    P, _, s = p.result()
+    assert np.abs(P[1::2]).max() < 1e-13
+    ref = exact.lossless_uniform_total(M, 0.5, np.arange(64))
+    bulk = ref > 1e-3 * ref.max()
+    assert np.all(np.abs(P - ref)[bulk] < 5 * s[bulk])
+
+
+@pytest.mark.parametrize("prec,rel", [("fp32", 2e-6), ("split_bf16", 2e-5)])
+def test_reduced_precision_propagation(prec, rel):
+    M, E = 300, 200
+    T = 0.95 * synth.haar_unitary(M, 12)
+    r = np.full(M, 1.0)
+    p = _pipe(T, r, prec=prec, seed=5, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
+    import paper_2503_12749_amd as mp
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, prec, p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, prec, p.ab, p.C, p.ws_prop)
+    ag, bg = p.propagated(E)
+    a, b, n = osamp.sample(r, 0, E, 5)
+    ao, bo = oest.propagate(T, a, b)
+    norm = np.linalg.norm(ao, axis=1, keepdims=True)
+    assert np.abs(ag - ao).max() / norm.max() < rel
+    assert np.abs(bg - bo).max() / norm.max() < rel
+    nS = (ag * bg).sum(1)
+    assert np.abs(nS - 0.9025 * n).max() < 50 * rel * np.abs(n).max()
+
+
+@pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6)])
+def test_reduced_precision_counts_within_sigma(prec, floor):
+    """M = 300, t = 0.9, r = 1: the reduced-precision estimate differs from the
+    FP64 oracle on the same noise by far less than sigma_T.  Besides the
+    operand rounding, the FP32 evaluation of chi (relative error ~1e-7 per
+    term) leaves an absolute floor of order 1e-8 * max P on every bin, tails
+    included."""
+    M = 300
+    T = 0.9 * synth.haar_unitary(M, 44)
+    r = np.full(M, 1.0)
+    mean, sd = synth.uniform_loss_moments(r, 0.9)
+    win = [synth.count_window(mean, sd)]
+    p = _pipe(T, r, prec=prec, seed=6, windows=win, n_sub=8, samples_per_sub=500, chunk=4000)
+    p.run()
+    P, _, s = p.result()
+    ref = _oracle(T, r, 6, 4000, 8, np.zeros(M, int), 1, win)
+    err = np.abs(P - ref["P"])
+    print(f"{prec}: max |dP| = {err.max():.3e}, max |dP|/sigma over the bulk = "
+          f"{(err / ref['sigma'])[ref['P'] > 1e-3 * ref['P'].max()].max():.3e}")
+    assert np.all(err <= 0.05 * ref["sigma"] + floor * ref["P"].max())
