@@ -51,7 +51,7 @@ typedef enum {
   MP_FP64 = 0,       /* FP64 samples, FP64 MFMA GEMM, FP64 characteristic function */
   MP_FP32 = 1,       /* FP32 samples, FP32 MFMA GEMM, FP32 characteristic function */
   MP_SPLIT_BF16 = 2, /* hi/lo BF16 operands, 3 BF16 MFMA products, FP32 accumulate */
-  MP_SPLIT_FP16 = 3  /* hi/lo FP16 operands (lo scaled by 2^11), FP32 accumulate */
+  MP_SPLIT_FP16 = 3  /* hi/lo FP16 operands, 3 FP16 MFMA products, FP32 accumulate */
 } mp_precision;
 
 typedef enum {
@@ -102,7 +102,8 @@ size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
  *   ab     device, mp_ab_bytes(M, E, prec) bytes, column-major with ld = ldm:
  *          column k < E holds alpha of sample g0+k, column E+k its beta.
  *          FP64 -> double, FP32 -> float, SPLIT_* -> a hi plane followed by a
- *          lo plane of 16-bit values (x = hi + lo, resp. hi + lo 2^-11 for FP16).
+ *          lo plane of 16-bit values with x = hi + lo (hi = x rounded, lo = the
+ *          rounded remainder).
  *   n_out  device FP64[E]: n = sum_j alpha_j beta_j of the values as stored
  *          (after rounding to `prec`).
  */

@@ -16,6 +16,8 @@
 // workgroups sharing one L2 reuse the same rows of A and columns of B.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "common.h"
 
 namespace mp {
@@ -45,7 +47,7 @@ __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint3
 // A[i][j] (row-major, 2 ldm x ldm) from T (row-major complex M x M).
 template <int PREC>
 __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t ldm,
-                                  void* __restrict__ A) {
+                                  void* __restrict__ A, int scale_exp) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = 2 * ldm * ldm;
   if (idx >= total) return;
@@ -63,8 +65,10 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
     ((uint16_t*)A)[idx] = hi;
     ((uint16_t*)A)[idx + total] = lo;
   } else {
-    _Float16 hi = (_Float16)v;
-    _Float16 lo = (_Float16)((v - (double)hi) * 2048.0);
+    // FP16: A is packed as T * 2^scale_exp so that both halves stay normal
+    const double x = ldexp(v, scale_exp);
+    _Float16 hi = (_Float16)x;
+    _Float16 lo = (_Float16)(x - (double)hi);
     ((_Float16*)A)[idx] = hi;
     ((_Float16*)A)[idx + total] = lo;
   }
@@ -387,6 +391,583 @@ __global__ __launch_bounds__(kThreads) void gemm_split_bf16(const uint16_t* __re
   }
 }
 
+// ---------------------------------------------------------------- split, 256 x 256
+
+// Split-precision GEMM with a 256 x 256 workgroup tile: four waves of
+// 128 x 128 (4 x 4 MFMA 32x32x16 tiles, 256 accumulator registers per lane),
+// BK = 32, two LDS stages of four 256 x 32 planes (A hi/lo, B hi/lo).  Rows
+// of a plane are 64 bytes without padding; 16-byte chunk c of row r is
+// stored at chunk c ^ f(r), f(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1), which keeps
+// both the 16-byte fragment reads (32 consecutive rows, one chunk) and the
+// staging writes free of bank conflicts for 32- and 64-bank LDS.  Within a
+// k16 step the three products run as three sweeps over the 16 tiles, so
+// consecutive MFMAs never depend on each other.  `out_scale` undoes the
+// power-of-two prescale of the packed A operand.
+template <typename H>
+struct SplitMfma;
+template <>
+struct SplitMfma<__bf16> {
+  typedef bf16x8 frag;
+  __device__ static inline f32x16 mma(frag a, frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct SplitMfma<_Float16> {
+  typedef f16x8 frag;
+  __device__ static inline f32x16 mma(frag a, frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ inline int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+
+constexpr int S_BM = 256, S_BN = 256, S_BK = 32;
+constexpr int S_PLANE = S_BM * S_BK;  // elements of one LDS plane
+
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_256(const uint16_t* __restrict__ A,
+                                                              const uint16_t* __restrict__ B,
+                                                              float* __restrict__ C, int64_t ldm,
+                                                              int64_t ncols, float out_scale) {
+  typedef typename SplitMfma<H>::frag frag;
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2][4][S_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int64_t planeA = 2 * ldm * ldm, planeB = ldm * ncols;
+
+  // staging: thread tid moves 16-byte vector vi = tid + 256 i (i < 4) of each
+  // plane: row vi >> 2, chunk vi & 3
+  const uint16_t* src[4];
+  int64_t nvalid[4];
+  src[0] = A + m0 * ldm;
+  src[1] = A + planeA + m0 * ldm;
+  src[2] = B + n0 * ldm;
+  src[3] = B + planeB + n0 * ldm;
+  nvalid[0] = nvalid[1] = S_BM;
+  nvalid[2] = nvalid[3] = ncols - n0;
+  u32x4 stage[4][4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int vi = tid + i * kThreads;
+        const int row = vi >> 2, c = vi & 3;
+        if (row < nvalid[p])
+          stage[p][i] = *(const u32x4*)(src[p] + (int64_t)row * ldm + k0 + c * 8);
+        else
+          stage[p][i] = u32x4{0, 0, 0, 0};
+      }
+  };
+  auto lstore = [&](int st) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int vi = tid + i * kThreads;
+        const int row = vi >> 2, c = vi & 3;
+        *(u32x4*)(&lds[st][p][row * S_BK + ((c ^ swz(row)) << 3)]) = stage[p][i];
+      }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = (int)(ldm / S_BK);
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) gload((int64_t)(kt + 1) * S_BK);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      frag ah[4], al[4], bh[4], bl[4];
+      const int chunk = 2 * lh + s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ra = wm * 128 + i * 32 + lr;
+        const int rb = wn * 128 + i * 32 + lr;
+        const int oa = ra * S_BK + ((chunk ^ swz(ra)) << 3);
+        const int ob = rb * S_BK + ((chunk ^ swz(rb)) << 3);
+        ah[i] = *(const frag*)(&lds[cur][0][oa]);
+        al[i] = *(const frag*)(&lds[cur][1][oa]);
+        bh[i] = *(const frag*)(&lds[cur][2][ob]);
+        bl[i] = *(const frag*)(&lds[cur][3][ob]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al[i], bh[j], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bl[j], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bh[j], acc[i][j]);
+    }
+    // stage cur ^ 1 was last read before the previous barrier
+    if (kt + 1 < KT) lstore(cur ^ 1);
+    __syncthreads();
+  }
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
+// Same tile and LDS layout as gemm_split_256, fed by gfx950's direct
+// global-to-LDS loads (global_load_lds_dwordx4): lane l of a wave writes the
+// 16 bytes at LDS slot base + 16 l, so each lane fetches the global chunk that
+// the swizzled layout puts in its slot.  Wave w fills plane w (A hi, A lo,
+// B hi, B lo) of the next stage while all waves compute on the current one;
+// no staging registers and no LDS stores in the shader.  Columns of B past
+// the end are clamped to the last valid column (their outputs are dropped).
+// Both k16 fragment sets of a slab are read up front so that the LDS reads
+// of the second step overlap the MFMAs of the first.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_dma(const uint16_t* __restrict__ A,
+                                                                  const uint16_t* __restrict__ B,
+                                                                  float* __restrict__ C,
+                                                                  int64_t ldm, int64_t ncols,
+                                                                  float out_scale) {
+  typedef typename SplitMfma<H>::frag frag;
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  // this wave's plane: source rows and their lane offsets within one 16-row load
+  const uint16_t* plane_src;
+  int64_t row_limit;
+  if (wave < 2) {
+    plane_src = A + (wave == 1 ? 2 * ldm * ldm : 0) + m0 * ldm;
+    row_limit = S_BM;
+  } else {
+    plane_src = B + (wave == 3 ? ldm * ncols : 0) + n0 * ldm;
+    row_limit = ncols - n0;
+  }
+  // load q (0..15) covers rows 16 q .. 16 q + 15; lane l -> row 16 q + l / 4,
+  // physical chunk l % 4, logical chunk (l % 4) ^ swz(row); swz(row) depends
+  // only on row % 16, so the per-lane chunk offset is the same for every q
+  const int lrow = lane >> 2;
+  const int lchunk = (lane & 3) ^ swz(lrow);
+  auto issue = [&](int st, int64_t k0) {
+    lds_void* dst = (lds_void*)&lds[st][wave][0];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      int64_t row = 16 * q + lrow;
+      row = row < row_limit ? row : row_limit - 1;
+      const uint16_t* g = plane_src + row * ldm + k0 + lchunk * 8;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)((char*)dst + q * 1024), 16, 0, 0);
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = (int)(ldm / S_BK);
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    // stage cur ^ 1 was last read before the previous barrier
+    if (kt + 1 < KT) issue(cur ^ 1, (int64_t)(kt + 1) * S_BK);
+    frag ah[2][4], al[2][4], bh[2][4], bl[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int chunk = 2 * lh + s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ra = wm * 128 + i * 32 + lr;
+        const int rb = wn * 128 + i * 32 + lr;
+        const int oa = ra * S_BK + ((chunk ^ swz(ra)) << 3);
+        const int ob = rb * S_BK + ((chunk ^ swz(rb)) << 3);
+        al[s][i] = *(const frag*)(&lds[cur][1][oa]);
+        bh[s][i] = *(const frag*)(&lds[cur][2][ob]);
+        ah[s][i] = *(const frag*)(&lds[cur][0][oa]);
+        bl[s][i] = *(const frag*)(&lds[cur][3][ob]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al[s][i], bh[s][j], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[s][i], bl[s][j], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[s][i], bh[s][j], acc[i][j]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage have landed
+    __syncthreads();
+  }
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
+// Deeper-prefetch variant: BK = 16 and a ring of four LDS stages (4 planes of
+// 256 rows x 32 bytes = 32 KB per stage), so the direct-to-LDS loads of slab
+// kt + 3 are in flight while slab kt is multiplied; the wait before each
+// barrier only drains the loads of slab kt + 1 (vmcnt counts the loads issued
+// after it).  Rows hold two 16-byte chunks; chunk c of row r sits at
+// c ^ g(r), g(r) = ((r >> 2) ^ (r >> 3)) & 1, conflict-free for 32- and
+// 64-bank LDS.
+__device__ inline int swz2(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
+
+constexpr int R_BK = 16, R_STAGES = 4;
+constexpr int R_PLANE = S_BM * R_BK;  // elements of one plane of one stage
+
+// Workgroup barrier without the memory fence of __syncthreads: the fence
+// would drain every in-flight direct-to-LDS load.  LDS visibility is ensured
+// by the explicit vmcnt waits before it; the empty asm statements stop the
+// compiler from moving LDS accesses across the barrier.
+__device__ inline void barrier_no_fence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int N>
+__device__ inline void wait_vm() {
+  // s_waitcnt vmcnt(N), expcnt and lgkmcnt unconstrained (gfx9 encoding)
+  __builtin_amdgcn_s_waitcnt(((N & 15) | ((N >> 4) << 14)) | (7 << 4) | (15 << 8));
+}
+
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_ring(const uint16_t* __restrict__ A,
+                                                                   const uint16_t* __restrict__ B,
+                                                                   float* __restrict__ C,
+                                                                   int64_t ldm, int64_t ncols,
+                                                                   float out_scale) {
+  typedef typename SplitMfma<H>::frag frag;
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[R_STAGES][4][R_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  const uint16_t* plane_src;
+  int64_t row_limit;
+  if (wave < 2) {
+    plane_src = A + (wave == 1 ? 2 * ldm * ldm : 0) + m0 * ldm;
+    row_limit = S_BM;
+  } else {
+    plane_src = B + (wave == 3 ? ldm * ncols : 0) + n0 * ldm;
+    row_limit = ncols - n0;
+  }
+  // load q (0..7) covers rows 32 q .. 32 q + 31: lane l -> row 32 q + l / 2,
+  // physical chunk l % 2, logical chunk (l % 2) ^ swz2(row); swz2 depends on
+  // row % 16 only
+  const int lrow = lane >> 1;
+  const int lchunk = (lane & 1) ^ swz2(lrow);
+  const uint16_t* lsrc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int64_t row = 32 * q + lrow;
+    row = row < row_limit ? row : row_limit - 1;
+    lsrc[q] = plane_src + row * ldm + lchunk * 8;
+  }
+  auto issue = [&](int st, int64_t k0) {
+    char* dst = (char*)&lds[st][wave][0];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(lsrc[q] + k0), (lds_void*)(dst + q * 1024), 16,
+                                       0, 0);
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = (int)(ldm / R_BK);  // >= 8
+  issue(0, 0);
+  issue(1, R_BK);
+  issue(2, 2 * R_BK);
+  wait_vm<16>();
+  barrier_no_fence();
+  const int oa_row[4] = {wm * 128 + lr, wm * 128 + 32 + lr, wm * 128 + 64 + lr, wm * 128 + 96 + lr};
+  const int ob_row[4] = {wn * 128 + lr, wn * 128 + 32 + lr, wn * 128 + 64 + lr, wn * 128 + 96 + lr};
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 3;
+    // stage (kt + 3) & 3 was last read in iteration kt - 1, before its barrier
+    if (kt + 3 < KT) issue((kt + 3) & 3, (int64_t)(kt + 3) * R_BK);
+    frag ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int oa = oa_row[i] * R_BK + ((lh ^ swz2(oa_row[i])) << 3);
+      const int ob = ob_row[i] * R_BK + ((lh ^ swz2(ob_row[i])) << 3);
+      al[i] = *(const frag*)(&lds[cur][1][oa]);
+      bh[i] = *(const frag*)(&lds[cur][2][ob]);
+      ah[i] = *(const frag*)(&lds[cur][0][oa]);
+      bl[i] = *(const frag*)(&lds[cur][3][ob]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al[i], bh[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bl[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bh[j], acc[i][j]);
+    // stage of slab kt + 1 must have landed: loads of later slabs may stay in flight
+    const int later = (kt + 3 < KT ? kt + 3 : KT - 1) - (kt + 1);
+    if (later >= 2)
+      wait_vm<16>();
+    else if (later == 1)
+      wait_vm<8>();
+    else
+      wait_vm<0>();
+    barrier_no_fence();
+  }
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
+// Ping-pong schedule of the two-stage direct-to-LDS kernel.  Fragments of a
+// slab's two k16 steps live in two register sets F0, F1.  Per slab kt:
+//   read F1 (kt, step 1) | MFMAs on F0 | drain own loads of slab kt + 1 |
+//   barrier | load slab kt + 2 into the stage just freed |
+//   read F0 (kt + 1, step 0) | MFMAs on F1.
+// The barrier sits between two MFMA groups, and the LDS reads after it
+// overlap the second group, so neither the barrier nor the LDS latency
+// leaves the matrix pipe idle for a whole fragment round trip.
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t* __restrict__ A,
+                                                                 const uint16_t* __restrict__ B,
+                                                                 float* __restrict__ C,
+                                                                 int64_t ldm, int64_t ncols,
+                                                                 float out_scale) {
+  typedef typename SplitMfma<H>::frag frag;
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  const uint16_t* plane_src;
+  int64_t row_limit;
+  if (wave < 2) {
+    plane_src = A + (wave == 1 ? 2 * ldm * ldm : 0) + m0 * ldm;
+    row_limit = S_BM;
+  } else {
+    plane_src = B + (wave == 3 ? ldm * ncols : 0) + n0 * ldm;
+    row_limit = ncols - n0;
+  }
+  const int lrow = lane >> 2;
+  const int lchunk = (lane & 3) ^ swz(lrow);
+  auto issue = [&](int st, int64_t k0) {
+    char* dst = (char*)&lds[st][wave][0];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      int64_t row = 16 * q + lrow;
+      row = row < row_limit ? row : row_limit - 1;
+      const uint16_t* g = plane_src + row * ldm + k0 + lchunk * 8;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
+    }
+  };
+  int oa[2][4], ob[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+      oa[s][i] = ra * S_BK + (((2 * lh + s) ^ swz(ra)) << 3);
+      ob[s][i] = rb * S_BK + (((2 * lh + s) ^ swz(rb)) << 3);
+    }
+  frag ah0[4], al0[4], bh0[4], bl0[4], ah1[4], al1[4], bh1[4], bl1[4];
+  auto read0 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      al0[i] = *(const frag*)(&lds[st][1][oa[0][i]]);
+      bh0[i] = *(const frag*)(&lds[st][2][ob[0][i]]);
+      ah0[i] = *(const frag*)(&lds[st][0][oa[0][i]]);
+      bl0[i] = *(const frag*)(&lds[st][3][ob[0][i]]);
+    }
+  };
+  auto read1 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      al1[i] = *(const frag*)(&lds[st][1][oa[1][i]]);
+      bh1[i] = *(const frag*)(&lds[st][2][ob[1][i]]);
+      ah1[i] = *(const frag*)(&lds[st][0][oa[1][i]]);
+      bl1[i] = *(const frag*)(&lds[st][3][ob[1][i]]);
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = (int)(ldm / S_BK);  // >= 4
+  issue(0, 0);
+  wait_vm<0>();
+  barrier_no_fence();
+  issue(1, S_BK);
+  read0(0);
+  // scheduling-group masks: MFMA, LDS read, global (direct-to-LDS) load
+  constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    // phase A: MFMAs on F0 with the reads of F1 threaded between them
+    read1(cur);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al0[i], bh0[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah0[i], bl0[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah0[i], bh0[j], acc[i][j]);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    // own loads of slab kt + 1 landed, own reads of stage cur complete
+    __builtin_amdgcn_s_waitcnt(0);
+    barrier_no_fence();
+    __builtin_amdgcn_sched_barrier(0);
+    // phase B: MFMAs on F1 with the next loads and the reads of F0 threaded in.
+    // In the last two slabs the loads repeat the final slab into the stage
+    // just freed and the reads fetch unused fragments: both stay in bounds
+    // and keep the loop free of branches around the MFMA stream.
+    issue(cur, (int64_t)min(kt + 2, KT - 1) * S_BK);
+    read0(cur ^ 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al1[i], bh1[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bl1[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bh1[j], acc[i][j]);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 size_t propagate_workspace(int32_t M, mp_precision prec) {
@@ -399,10 +980,29 @@ size_t propagate_workspace(int32_t M, mp_precision prec) {
   }
 }
 
-static int grid_tiles(int64_t ldm, int64_t ncols) {
-  int64_t tiles = (2 * ldm / BM) * ((ncols + BN - 1) / BN);
+// Split-GEMM variant: 3 = two-stage direct-to-LDS ping-pong (default),
+// 2 = four-stage direct-to-LDS ring, 1 = two-stage direct-to-LDS,
+// 0 = register staging.
+static int split_variant() {
+  static int v = [] {
+    const char* e = getenv("MPGBS_SPLIT_VARIANT");
+    return e ? atoi(e) : 3;
+  }();
+  return v;
+}
+
+static int grid_tiles(int64_t ldm, int64_t ncols, int bm, int bn) {
+  int64_t tiles = (2 * ldm / bm) * ((ncols + bn - 1) / bn);
   int64_t per = (tiles + kXcds - 1) / kXcds;
   return (int)(per * kXcds);
+}
+
+// Power-of-two prescale of T for the FP16 split operand: |T_ij| ~ M^-1/2 for
+// a spread-out network, so 2^floor(log2(M)/2) brings typical entries near 1.
+static int fp16_scale_exp(int32_t M) {
+  int e = 0;
+  while ((1LL << (2 * (e + 1))) <= (long long)M) ++e;
+  return e;
 }
 
 mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision prec,
@@ -411,29 +1011,64 @@ mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision p
   const int64_t ncols = 2 * E;
   const int64_t pack_total = 2 * ldm * ldm;
   const int pack_blocks = (int)((pack_total + 255) / 256);
-  const int grid = grid_tiles(ldm, ncols);
   switch (prec) {
     case MP_FP64:
       hipLaunchKernelGGL(pack_transmission<MP_FP64>, dim3(pack_blocks), dim3(256), 0, stream, T, M,
-                         ldm, ws);
-      hipLaunchKernelGGL(gemm_f64, dim3(grid), dim3(kThreads), 0, stream, (const double*)ws,
-                         (const double*)ab, (double*)C, ldm, ncols);
+                         ldm, ws, 0);
+      hipLaunchKernelGGL(gemm_f64, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
+                         (const double*)ws, (const double*)ab, (double*)C, ldm, ncols);
       break;
     case MP_FP32:
       hipLaunchKernelGGL(pack_transmission<MP_FP32>, dim3(pack_blocks), dim3(256), 0, stream, T, M,
-                         ldm, ws);
-      hipLaunchKernelGGL(gemm_f32, dim3(grid), dim3(kThreads), 0, stream, (const float*)ws,
-                         (const float*)ab, (float*)C, ldm, ncols);
+                         ldm, ws, 0);
+      hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
+                         (const float*)ws, (const float*)ab, (float*)C, ldm, ncols);
       break;
     case MP_SPLIT_BF16:
       hipLaunchKernelGGL(pack_transmission<MP_SPLIT_BF16>, dim3(pack_blocks), dim3(256), 0, stream,
-                         T, M, ldm, ws);
-      hipLaunchKernelGGL(gemm_split_bf16, dim3(grid), dim3(kThreads), 0, stream,
-                         (const uint16_t*)ws, (const uint16_t*)ab, (float*)C, ldm, ncols);
+                         T, M, ldm, ws, 0);
+      if (split_variant() == 3)
+        hipLaunchKernelGGL(gemm_split_256_pp<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, 1.0f);
+      else if (split_variant() == 2)
+        hipLaunchKernelGGL(gemm_split_256_ring<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, 1.0f);
+      else if (split_variant() == 1)
+        hipLaunchKernelGGL(gemm_split_256_dma<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, 1.0f);
+      else
+        hipLaunchKernelGGL(gemm_split_256<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, 1.0f);
       break;
+    case MP_SPLIT_FP16: {
+      const int e = fp16_scale_exp(M);
+      hipLaunchKernelGGL(pack_transmission<MP_SPLIT_FP16>, dim3(pack_blocks), dim3(256), 0, stream,
+                         T, M, ldm, ws, e);
+      if (split_variant() == 3)
+        hipLaunchKernelGGL(gemm_split_256_pp<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+      else if (split_variant() == 2)
+        hipLaunchKernelGGL(gemm_split_256_ring<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+      else if (split_variant() == 1)
+        hipLaunchKernelGGL(gemm_split_256_dma<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+      else
+        hipLaunchKernelGGL(gemm_split_256<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+      break;
+    }
     default:
-      set_error("mp_propagate: precision %d not supported by this build", (int)prec);
-      return MP_ERR_UNSUPPORTED;
+      set_error("mp_propagate: unknown precision %d", (int)prec);
+      return MP_ERR_ARG;
   }
   MP_HIP_LAUNCH_CHECK("mp_propagate launch");
   return MP_OK;

@@ -84,14 +84,14 @@ __device__ inline double store_pair(void* ab, int64_t plane, int64_t off, double
     return bf16_val(h0) + bf16_val(l0);
   } else {
     const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
-    const _Float16 l0 = (_Float16)((x0 - (double)h0) * 2048.0);
-    const _Float16 l1 = (_Float16)((x1 - (double)h1) * 2048.0);
+    const _Float16 l0 = (_Float16)(x0 - (double)h0);
+    const _Float16 l1 = (_Float16)(x1 - (double)h1);
     _Float16* p = (_Float16*)ab;
     typedef __attribute__((ext_vector_type(2))) _Float16 h2;
     *(h2*)(p + off) = h2{h0, h1};
     *(h2*)(p + plane + off) = h2{l0, l1};
-    y1 = (double)h1 + (double)l1 * 0x1p-11;
-    return (double)h0 + (double)l0 * 0x1p-11;
+    y1 = (double)h1 + (double)l1;
+    return (double)h0 + (double)l0;
   }
 }
 

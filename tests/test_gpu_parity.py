@@ -192,7 +192,7 @@ def test_lossless_odd_counts_vanish():
     assert np.all(np.abs(P - ref)[bulk] < 5 * s[bulk])
 
 
-@pytest.mark.parametrize("prec,rel", [("fp32", 2e-6), ("split_bf16", 2e-5)])
+@pytest.mark.parametrize("prec,rel", [("fp32", 2e-6), ("split_bf16", 2e-5), ("split_fp16", 4e-6)])
 def test_reduced_precision_propagation(prec, rel):
     M, E = 300, 200
     T = 0.95 * synth.haar_unitary(M, 12)
@@ -211,7 +211,7 @@ def test_reduced_precision_propagation(prec, rel):
     assert np.abs(nS - 0.9025 * n).max() < 50 * rel * np.abs(n).max()
 
 
-@pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6)])
+@pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6), ("split_fp16", 1e-6)])
 def test_reduced_precision_counts_within_sigma(prec, floor):
     """M = 300, t = 0.9, r = 1: the reduced-precision estimate differs from the
     FP64 oracle on the same noise by far less than sigma_T.  Besides the
