@@ -131,7 +131,7 @@ def main():
         # statistics over the sub-ensembles completed so far
         done_sub = g // ns
         mp.mp_counts_finalize(1, "joint", pipe.K, done_sub, ns, pipe.acc, pipe.P_re, pipe.P_im,
-                              pipe.sigma)
+                              pipe.sigma, None)
         torch.cuda.synchronize()
         fin_s = time.perf_counter() - t0
         P, _, sig = pipe.result()

@@ -188,10 +188,17 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
  *   acc     device, complete accumulators (all n_sub * samples_per_sub samples)
  *   P_re, P_im, sigma  device FP64[mp_acc_entries]; P_im may be NULL.
  *           Joint layout [k1][k2]; marginal layout concatenated per distribution.
+ *   workspace  device, >= mp_finalize_workspace(...) bytes, 256-aligned (may be
+ *           NULL when that size is 0).  The joint two-bin transform runs
+ *           separably over the rows and columns of acc that hold nonzero
+ *           values (the frequency bands the chunks touched); K[0] <= 4096.
  */
+size_t mp_finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
+
 mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                              int64_t samples_per_sub, const double* acc, double* P_re,
-                             double* P_im, double* sigma, void* stream);
+                             double* P_im, double* sigma, void* workspace, size_t ws_bytes,
+                             void* stream);
 
 /* Message of the calling thread's last non-MP_OK status ("" if none). */
 const char* mp_last_error(void);

@@ -18,7 +18,7 @@ from ._lib import BIN_MODES, ESTIMATORS, MPError, PRECISIONS, i32_array
 __all__ = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
     "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
-    "mp_counts_finalize", "mp_version", "CountsPipeline", "MPError",
+    "mp_counts_finalize", "mp_finalize_workspace", "mp_version", "CountsPipeline", "MPError",
 ]
 
 
@@ -96,10 +96,16 @@ def mp_binned_counts(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub
         workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
-def mp_counts_finalize(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma, stream=None):
+def mp_finalize_workspace(d: int, mode, K, n_sub: int) -> int:
+    return int(_lib.load().mp_finalize_workspace(d, _mode(mode), i32_array(K), n_sub))
+
+
+def mp_counts_finalize(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma, workspace=None,
+                       stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _lib.check(_lib.load().mp_counts_finalize(d, _mode(mode), i32_array(K), n_sub, samples_per_sub,
                                               _ptr(acc), _ptr(P_re), _ptr(P_im), _ptr(sigma),
-                                              _stream(stream)))
+                                              _ptr(workspace), nbytes, _stream(stream)))
 
 
 class CountsPipeline:
@@ -138,11 +144,16 @@ class CountsPipeline:
         # a chunk touches at most chunk // ns + 2 sub-ensembles, each adding at
         # most one partial tile of 64 samples
         blocks = -(-self.chunk // 64) + self.chunk // self.ns + 2
-        self.ws_counts = torch.empty(blocks * self.entries * 16 + 256, dtype=torch.uint8, device=dev)
+        wbytes = blocks * self.entries * 16 + 256
+        if self.mode == 0 and self.d == 2:
+            wbytes = mp_binned_workspace(2, 0, self.K, self.chunk, self.n_sub, self.ns, 0)
+        self.ws_counts = torch.empty(wbytes, dtype=torch.uint8, device=dev)
         self.acc = torch.zeros(self.n_sub * self.entries * 2, dtype=torch.float64, device=dev)
         self.P_re = torch.empty(self.entries, dtype=torch.float64, device=dev)
         self.P_im = torch.empty(self.entries, dtype=torch.float64, device=dev)
         self.sigma = torch.empty(self.entries, dtype=torch.float64, device=dev)
+        fw = mp_finalize_workspace(self.d, self.mode, self.K, self.n_sub)
+        self.ws_final = torch.empty(fw, dtype=torch.uint8, device=dev) if fw else None
 
     def reset(self):
         self.acc.zero_()
@@ -159,7 +170,7 @@ class CountsPipeline:
 
     def finalize(self, stream=None):
         mp_counts_finalize(self.d, self.mode, self.K, self.n_sub, self.ns, self.acc, self.P_re,
-                           self.P_im, self.sigma, stream)
+                           self.P_im, self.sigma, self.ws_final, stream)
 
     def run(self, E_total: int | None = None, g_start: int = 0, stream=None):
         E_total = self.n_sub * self.ns if E_total is None else E_total

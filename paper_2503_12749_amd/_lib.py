@@ -20,7 +20,7 @@ MP_MAX_RUNS = 16
 EXPORTS = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
     "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
-    "mp_counts_finalize", "mp_last_error", "mp_version",
+    "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
 ]
 
 
@@ -56,8 +56,9 @@ def load() -> ctypes.CDLL:
         "mp_binned_counts": (ctypes.c_int, [c_i32, c_i64, vp, vp, ctypes.c_int, ctypes.c_int, c_i32,
                                             i32p, ctypes.c_int, i32p, i32p, c_i32, c_i64, c_i64,
                                             vp, vp, sz, vp]),
+        "mp_finalize_workspace": (sz, [c_i32, ctypes.c_int, i32p, c_i32]),
         "mp_counts_finalize": (ctypes.c_int, [c_i32, ctypes.c_int, i32p, c_i32, c_i64, vp, vp, vp,
-                                              vp, vp]),
+                                              vp, vp, sz, vp]),
         "mp_last_error": (ctypes.c_char_p, []),
         "mp_version": (ctypes.c_char_p, []),
     }

@@ -39,7 +39,8 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
                                double* acc, void* ws, size_t ws_bytes, hipStream_t stream);
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
-                                 double* sigma, hipStream_t stream);
+                                 double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
 
 static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -149,17 +150,25 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
                               samples_per_sub, e0, acc, workspace, ws_bytes, (hipStream_t)stream);
 }
 
+size_t mp_finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub) {
+  if (mp_acc_entries(d, mode, K) < 0 || n_sub < 1) return 0;
+  return finalize_workspace(d, mode, K, n_sub);
+}
+
 mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                              int64_t samples_per_sub, const double* acc, double* P_re,
-                             double* P_im, double* sigma, void* stream) {
+                             double* P_im, double* sigma, void* workspace, size_t ws_bytes,
+                             void* stream) {
   clear_error();
   MP_CHECK_ARG(mp_acc_entries(d, mode, K) > 0, MP_ERR_ARG,
                "mp_counts_finalize: invalid bin layout (d = %d, mode = %d)", d, (int)mode);
   MP_CHECK_ARG(n_sub >= 1 && samples_per_sub >= 1, MP_ERR_ARG,
                "mp_counts_finalize: n_sub and samples_per_sub must be >= 1");
   MP_CHECK_ARG(acc && P_re && sigma, MP_ERR_ARG, "mp_counts_finalize: null pointer argument");
+  MP_CHECK_ARG(workspace == nullptr || aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_counts_finalize: workspace must be 256-byte aligned");
   return counts_finalize_launch(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma,
-                                (hipStream_t)stream);
+                                workspace, ws_bytes, (hipStream_t)stream);
 }
 
 const char* mp_last_error(void) { return g_err; }

@@ -288,6 +288,283 @@ __global__ void counts_reduce(CountsParams p, const double* __restrict__ partial
   dst[1] += im;
 }
 
+// ---------------------------------------------------------------- joint, d = 2
+
+// Joint distribution of two bins.  Per sample the generating function
+// factorises,
+//     chi(z1, z2) = e^{c1} u1(z1) u2(z2) + e^{c2} v1(z1) v2(z2),
+//     u_b = e^{X_b} z_b^{-m_lo_b},  v_b = e^{-X_b} z_b^{-m_lo_b},
+// so the sum over a sub-ensemble is a sum of rank-1 outer products.  For
+// theta in [0, pi] the exponent of |u_b| is
+//     f_b(theta) = -(1 - cos theta) Re n_b + |sin theta| |Im n_b|
+// (v_b: the same about theta = pi, plus 2 Re n_b), which rises to its maximum
+// at tan theta* = |Im n_b| / Re n_b and then falls monotonically.  Each sample
+// gets, per term and bin, the half-width of the band around theta = 0 (u) or
+// pi (v) outside which its term is below e^-46 (~1e-20) for every value of the
+// other bin; the chunk's band is the maximum over its samples.  Terms outside
+// the band are bounded by that threshold, not approximated.
+
+constexpr double kLogEps = -46.0;
+
+struct Joint2Params {
+  int M;
+  int64_t ldm, E, e0, ns;
+  int est;
+  int n_runs;
+  int run_lo[MP_MAX_RUNS], run_hi[MP_MAX_RUNS], run_bin[MP_MAX_RUNS];
+  int m_lo[2], K[2];
+  int64_t s_first, s_last;
+};
+
+__device__ inline double fmax_exponent(double R, double I) {
+  // max over theta of -(1 - cos t) R + |sin t| |I|
+  if (R <= 0.0) return 2.0 * fabs(R) + fabs(I);
+  const double t = atan2(fabs(I), R);
+  return -(1.0 - cos(t)) * R + sin(t) * fabs(I);
+}
+
+// Smallest h such that f(theta_k) + offset < kLogEps for every grid point at
+// circular distance > h from theta = 0; -1 when no point reaches the threshold.
+__device__ inline int band_halfwidth(double R, double I, double offset, int K) {
+  const double fmax = fmax_exponent(R, I);
+  if (fmax + offset < kLogEps) return -1;
+  const int half = K / 2;
+  if (R <= 0.0) return half;
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  auto f = [&](int k) {
+    const double t = kTwoPi * k / K;
+    return -(1.0 - cos(t)) * R + fabs(sin(t)) * fabs(I) + offset;
+  };
+  if (f(half) >= kLogEps) return half;
+  // f decreases on [theta*, pi]: search the last k >= k* with f(k) >= eps
+  int lo = (int)floor(atan2(fabs(I), R) / kTwoPi * K);  // f(lo) may be >= eps
+  int hi = half;                                      // f(hi) < eps
+  if (f(lo) < kLogEps) return lo > 0 ? lo : 0;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (f(mid) >= kLogEps) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Per-sample record: n1, n2 (complex), c1, c2; and the chunk bands
+// band[0..3] = u1, u2, v1, v2 half-widths (atomic max, -1 = empty).
+template <typename CT>
+__global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const CT* __restrict__ C,
+                                                          const double* __restrict__ nglob,
+                                                          double* __restrict__ rec,
+                                                          int* __restrict__ band) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  if (k >= p.E) return;
+  const int64_t ldc = 2 * p.ldm;
+  const CT* ca = C + k * ldc;
+  const CT* cb = C + (p.E + k) * ldc;
+  double R1 = 0.0, I1 = 0.0, R2 = 0.0, I2 = 0.0;
+  for (int q = 0; q < p.n_runs; ++q) {
+    double re, im;
+    run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+    const bool first = p.run_bin[q] == 0;
+    R1 += first ? re : 0.0;
+    I1 += first ? im : 0.0;
+    R2 += first ? 0.0 : re;
+    I2 += first ? 0.0 : im;
+  }
+  if (lane != 0) return;
+  const double n = nglob[k];
+  double c1 = 0.0, c2 = 0.0;
+  bool with_v = p.est != MP_PLUS_P;
+  if (with_v) {
+    const double L = log1p(exp(-2.0 * fabs(n)));
+    c1 = (n >= 0.0 ? 0.0 : 2.0 * n) - L;
+    c2 = (n >= 0.0 ? -2.0 * n : 0.0) - L;
+  }
+  double* r = rec + k * 6;
+  r[0] = R1;
+  r[1] = I1;
+  r[2] = R2;
+  r[3] = I2;
+  r[4] = c1;
+  r[5] = with_v ? c2 : -INFINITY;
+  const int hu1 = band_halfwidth(R1, I1, c1 + fmax_exponent(R2, I2), p.K[0]);
+  const int hu2 = band_halfwidth(R2, I2, c1 + fmax_exponent(R1, I1), p.K[1]);
+  atomicMax(&band[0], hu1);
+  atomicMax(&band[1], hu2);
+  if (with_v) {
+    // about theta = pi: exponent 2 R_b + f_b(phi) with Im n_b -> -Im n_b
+    const double off = c2 + 2.0 * R1 + 2.0 * R2;
+    // +1: for odd K the grid is not symmetric about theta = pi
+    int hv1 = band_halfwidth(R1, I1, off + fmax_exponent(R2, I2), p.K[0]);
+    int hv2 = band_halfwidth(R2, I2, off + fmax_exponent(R1, I1), p.K[1]);
+    hv1 = hv1 < 0 ? hv1 : min(hv1 + 1, p.K[0] / 2);
+    hv2 = hv2 < 0 ? hv2 : min(hv2 + 1, p.K[1] / 2);
+    atomicMax(&band[2], hv1);
+    atomicMax(&band[3], hv2);
+  }
+}
+
+__global__ void joint2_band_init(int* band) {
+  if (threadIdx.x < 4) band[threadIdx.x] = -1;
+}
+
+// circular distance of k from the centre c on a grid of K points
+__device__ inline int circ_dist(int k, int c, int K) {
+  int d = k - c;
+  d = ((d % K) + K) % K;
+  return d <= K / 2 ? d : K - d;
+}
+
+template <bool F64>
+__device__ inline void factor(double R, double I, double c, int k, int K, int m_lo, double sign,
+                              double& fr, double& fi) {
+  // e^{sign X(theta_k) + c} z^{-m_lo}, X = n (e^{i theta} - 1)
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  const double th = kTwoPi * (double)k / (double)K;
+  const double sh = sin(0.5 * th);
+  const double cm1 = -2.0 * sh * sh, sn = sin(th);
+  const double xr = cm1 * R - sn * I, xi = cm1 * I + sn * R;
+  const int64_t red = ((int64_t)k * (int64_t)m_lo) % K;
+  const double thl = kTwoPi * (double)red / (double)K;
+  cis_exp<F64>(sign * xr + c, sign * xi - thl, fr, fi);
+}
+
+constexpr int kJT = 16;    // output tile kJT x kJT per workgroup
+constexpr int kJS = 64;    // samples staged per round
+
+// acc[s][k1][k2] += sum over the chunk's samples of sub-ensemble s of the
+// band-limited outer products.  Grid: (tiles over K1 x K2, sub-ensembles).
+template <bool F64>
+__global__ __launch_bounds__(256) void joint2_accumulate(Joint2Params p, const double* __restrict__ rec,
+                                                         const int* __restrict__ band,
+                                                         double* __restrict__ acc) {
+  __shared__ double f1[kJS][kJT][2], f2[kJS][kJT][2];
+  const int K1 = p.K[0], K2 = p.K[1];
+  const int tiles2 = (K2 + kJT - 1) / kJT;
+  const int t1 = blockIdx.x / tiles2, t2 = blockIdx.x % tiles2;
+  const int64_t s = p.s_first + blockIdx.y;
+  const int tid = threadIdx.x, r1 = tid / kJT, r2 = tid % kJT;
+  const int k1 = t1 * kJT + r1, k2 = t2 * kJT + r2;
+  int64_t lo = s * p.ns, hi = (s + 1) * p.ns;
+  lo = lo > p.e0 ? lo : p.e0;
+  hi = hi < p.e0 + p.E ? hi : p.e0 + p.E;
+  double ar = 0.0, ai = 0.0;
+  for (int term = 0; term < 2; ++term) {
+    const int h1 = band[term == 0 ? 0 : 2], h2 = band[term == 0 ? 1 : 3];
+    if (h1 < 0 || h2 < 0) continue;
+    const int c1 = term == 0 ? 0 : K1 / 2, c2 = term == 0 ? 0 : K2 / 2;
+    // does the tile meet the band box?  (tile-uniform decision)
+    bool any1 = false, any2 = false;
+    for (int q = 0; q < kJT; ++q) {
+      any1 |= (t1 * kJT + q < K1) && circ_dist(t1 * kJT + q, c1, K1) <= h1;
+      any2 |= (t2 * kJT + q < K2) && circ_dist(t2 * kJT + q, c2, K2) <= h2;
+    }
+    if (!any1 || !any2) continue;
+    const double sign = term == 0 ? 1.0 : -1.0;
+    const bool mine = k1 < K1 && k2 < K2 && circ_dist(k1, c1, K1) <= h1 && circ_dist(k2, c2, K2) <= h2;
+    for (int64_t base = lo; base < hi; base += kJS) {
+      const int nsmp = (int)(hi - base < kJS ? hi - base : kJS);
+      // stage the factors of nsmp samples for the tile's kJT k1 and kJT k2 values
+      for (int w = tid; w < 2 * kJS * kJT; w += 256) {
+        const int which = w / (kJS * kJT), rem = w % (kJS * kJT);
+        const int i = rem / kJT, q = rem % kJT;
+        double fr = 0.0, fi = 0.0;
+        if (i < nsmp) {
+          const double* r = rec + (base + i - p.e0) * 6;
+          const double cterm = term == 0 ? r[4] : r[5];
+          if (which == 0) {
+            const int kk = t1 * kJT + q;
+            if (kk < K1 && cterm > -INFINITY)
+              factor<F64>(r[0], r[1], cterm, kk, K1, p.m_lo[0], sign, fr, fi);
+          } else {
+            const int kk = t2 * kJT + q;
+            if (kk < K2 && cterm > -INFINITY)
+              factor<F64>(r[2], r[3], 0.0, kk, K2, p.m_lo[1], sign, fr, fi);
+          }
+        }
+        double(*dst)[kJT][2] = which == 0 ? f1 : f2;
+        dst[i][q][0] = fr;
+        dst[i][q][1] = fi;
+      }
+      __syncthreads();
+      if (mine) {
+        for (int i = 0; i < nsmp; ++i) {
+          const double xr = f1[i][r1][0], xi = f1[i][r1][1];
+          const double yr = f2[i][r2][0], yi = f2[i][r2][1];
+          ar += xr * yr - xi * yi;
+          ai += xr * yi + xi * yr;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (k1 < K1 && k2 < K2 && (ar != 0.0 || ai != 0.0)) {
+    double* dst = acc + ((int64_t)s * K1 * K2 + (int64_t)k1 * K2 + k2) * 2;
+    dst[0] += ar;
+    dst[1] += ai;
+  }
+}
+
+mp_status joint2_launch(int32_t M, int64_t E, const void* C, const double* n, mp_precision prec,
+                        mp_estimator est, const int32_t* bin_of_mode, const int32_t* m_lo,
+                        const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0, double* acc,
+                        void* ws, size_t ws_bytes, hipStream_t stream) {
+  Joint2Params p{};
+  p.M = M;
+  p.ldm = ld_modes(M);
+  p.E = E;
+  p.e0 = e0;
+  p.ns = ns;
+  p.est = est;
+  p.n_runs = 0;
+  for (int j = 0; j < M;) {
+    const int b = bin_of_mode[j];
+    int j2 = j + 1;
+    while (j2 < M && bin_of_mode[j2] == b) ++j2;
+    if (b >= 0) {
+      MP_CHECK_ARG(p.n_runs < MP_MAX_RUNS, MP_ERR_UNSUPPORTED,
+                   "mp_binned_counts: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
+      p.run_lo[p.n_runs] = j;
+      p.run_hi[p.n_runs] = j2;
+      p.run_bin[p.n_runs] = b;
+      ++p.n_runs;
+    }
+    j = j2;
+  }
+  for (int b = 0; b < 2; ++b) {
+    p.m_lo[b] = m_lo[b];
+    p.K[b] = K[b];
+  }
+  p.s_first = e0 / ns;
+  p.s_last = (e0 + E - 1) / ns;
+  MP_CHECK_ARG(p.s_last < n_sub, MP_ERR_SHAPE,
+               "mp_binned_counts: samples [%lld, %lld) exceed n_sub * samples_per_sub = %lld",
+               (long long)e0, (long long)(e0 + E), (long long)n_sub * ns);
+  const size_t need = 256 + (size_t)E * 48;
+  MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,
+               "mp_binned_counts: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int* band = (int*)ws;
+  double* rec = (double*)((char*)ws + 256);
+  hipLaunchKernelGGL(joint2_band_init, dim3(1), dim3(64), 0, stream, band);
+  const unsigned blocks = (unsigned)((E + 3) / 4);
+  if (prec == MP_FP64)
+    hipLaunchKernelGGL(joint2_occupations<double>, dim3(blocks), dim3(256), 0, stream, p,
+                       (const double*)C, n, rec, band);
+  else
+    hipLaunchKernelGGL(joint2_occupations<float>, dim3(blocks), dim3(256), 0, stream, p,
+                       (const float*)C, n, rec, band);
+  MP_HIP_LAUNCH_CHECK("mp_binned_counts joint occupations launch");
+  const unsigned tiles = (unsigned)(((K[0] + kJT - 1) / kJT) * ((K[1] + kJT - 1) / kJT));
+  const unsigned nst = (unsigned)(p.s_last - p.s_first + 1);
+  if (prec == MP_FP64)
+    hipLaunchKernelGGL(joint2_accumulate<true>, dim3(tiles, nst), dim3(256), 0, stream, p, rec,
+                       band, acc);
+  else
+    hipLaunchKernelGGL(joint2_accumulate<false>, dim3(tiles, nst), dim3(256), 0, stream, p, rec,
+                       band, acc);
+  MP_HIP_LAUNCH_CHECK("mp_binned_counts joint accumulate launch");
+  return MP_OK;
+}
+
 // ---------------------------------------------------------------- finalize
 
 struct FinalParams {
@@ -367,6 +644,108 @@ __global__ __launch_bounds__(256) void counts_finalize(FinalParams p, const doub
   }
 }
 
+// Joint (d = 2) inverse transform.  The accumulators are exactly zero
+// outside the frequency bands that any chunk touched, so the 2-D inverse DFT
+// is done separably over the nonzero rows and columns only:
+//   flags:   row k1 / column k2 nonzero in any sub-ensemble
+//   rows:    T_s[k1][l2] = sum_{k2 nonzero} chi_s[k1][k2] e^{-2 pi i k2 l2 / K2}
+//   columns: P_s[l1][l2] = sum_{k1 nonzero} T_s[k1][l2] e^{-2 pi i k1 l1 / K1}
+//            / (K1 K2 N_S), folded over s with Welford's update.
+__global__ void joint2_flags(const double* __restrict__ acc, int n_sub, int K1, int K2,
+                             int* __restrict__ rowf, int* __restrict__ colf) {
+  const int64_t total = (int64_t)n_sub * K1 * K2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (acc[2 * e] != 0.0 || acc[2 * e + 1] != 0.0) {
+      const int64_t kk = e % ((int64_t)K1 * K2);
+      atomicOr(&rowf[kk / K2], 1);
+      atomicOr(&colf[kk % K2], 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void joint2_rows(const double* __restrict__ acc, int K1, int K2,
+                                                   const int* __restrict__ rowf,
+                                                   const int* __restrict__ colf,
+                                                   double* __restrict__ T) {
+  const int k1 = blockIdx.x;
+  const int64_t s = blockIdx.y;
+  if (!rowf[k1]) return;
+  const double* a = acc + (s * K1 * K2 + (int64_t)k1 * K2) * 2;
+  double* t = T + (s * K1 * K2 + (int64_t)k1 * K2) * 2;
+  for (int l2 = threadIdx.x; l2 < K2; l2 += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int k2 = 0; k2 < K2; ++k2) {
+      if (!colf[k2]) continue;
+      const double xr = a[2 * k2], xi = a[2 * k2 + 1];
+      double sw, cw;
+      sincospi(-2.0 * (double)(((int64_t)k2 * l2) % K2) / K2, &sw, &cw);
+      sr += xr * cw - xi * sw;
+      si += xr * sw + xi * cw;
+    }
+    t[2 * l2] = sr;
+    t[2 * l2 + 1] = si;
+  }
+}
+
+__global__ __launch_bounds__(256) void joint2_columns(const double* __restrict__ T, int n_sub,
+                                                      int K1, int K2, double scale,
+                                                      const int* __restrict__ rowf,
+                                                      double* __restrict__ P_re,
+                                                      double* __restrict__ P_im,
+                                                      double* __restrict__ sigma) {
+  __shared__ int rows[4096];
+  __shared__ double tw[4096][2];
+  __shared__ int nrows;
+  const int l1 = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int k1 = 0; k1 < K1; ++k1)
+      if (rowf[k1]) rows[c++] = k1;
+    nrows = c;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nrows; q += blockDim.x) {
+    double sw, cw;
+    sincospi(-2.0 * (double)(((int64_t)rows[q] * l1) % K1) / K1, &sw, &cw);
+    tw[q][0] = cw;
+    tw[q][1] = sw;
+  }
+  __syncthreads();
+  for (int l2 = blockIdx.y * blockDim.x + threadIdx.x; l2 < K2; l2 += gridDim.y * blockDim.x) {
+    double mean_r = 0.0, mean_i = 0.0, m2 = 0.0;
+    for (int s = 0; s < n_sub; ++s) {
+      const double* t = T + ((int64_t)s * K1 * K2 + l2) * 2;
+      double sr = 0.0, si = 0.0;
+      for (int q = 0; q < nrows; ++q) {
+        const double xr = t[(int64_t)rows[q] * K2 * 2], xi = t[(int64_t)rows[q] * K2 * 2 + 1];
+        sr += xr * tw[q][0] - xi * tw[q][1];
+        si += xr * tw[q][1] + xi * tw[q][0];
+      }
+      sr *= scale;
+      si *= scale;
+      const double dr = sr - mean_r;
+      mean_r += dr / (s + 1);
+      mean_i += (si - mean_i) / (s + 1);
+      m2 += dr * (sr - mean_r);
+    }
+    const int64_t e = (int64_t)l1 * K2 + l2;
+    P_re[e] = mean_r;
+    if (P_im) P_im[e] = mean_i;
+    sigma[e] = n_sub > 1 ? sqrt(m2 / (n_sub - 1) / n_sub) : __builtin_nan("");
+  }
+}
+
+__global__ void fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub) {
+  if (!(mode == MP_JOINT && d == 2)) return 0;
+  return 256 + ((size_t)K[0] + K[1]) * 4 + (size_t)n_sub * K[0] * K[1] * 16 + 256;
+}
+
 // ---------------------------------------------------------------- host side
 
 static int64_t entries_of(int d, mp_bin_mode mode, const int32_t* K) {
@@ -401,6 +780,7 @@ static int64_t plan_tiles(CountsParams& p) {
 size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
                         int64_t ns, int64_t e0) {
   if (!K || d < 1 || d > MP_MAX_BINS || E < 1 || ns < 1 || e0 < 0) return 0;
+  if (mode == MP_JOINT && d == 2) return 256 + (size_t)E * 48;
   CountsParams p{};
   p.E = E;
   p.e0 = e0;
@@ -423,9 +803,11 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
   p.d = d;
   p.mode = mode;
   p.est = est;
+  if (mode == MP_JOINT && d == 2)
+    return joint2_launch(M, E, C, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
+                         ws_bytes, stream);
   MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
-               "mp_binned_counts: the joint distribution of d = %d bins is not supported by this "
-               "build (use d = 1 or the marginal modes)", d);
+               "mp_binned_counts: joint distributions need d <= 2 (d = %d)", d);
   // contiguous runs of each bin
   p.n_runs = 0;
   for (int j = 0; j < M;) {
@@ -476,7 +858,29 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
 
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
-                                 double* sigma, hipStream_t stream) {
+                                 double* sigma, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (mode == MP_JOINT && d == 2) {
+    const size_t need = finalize_workspace(d, mode, K, n_sub);
+    MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,
+                 "mp_counts_finalize: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    MP_CHECK_ARG(K[0] <= 4096, MP_ERR_UNSUPPORTED,
+                 "mp_counts_finalize: joint windows need K[0] <= 4096");
+    const int K1 = K[0], K2 = K[1];
+    int* rowf = (int*)((char*)ws + 256);
+    int* colf = rowf + K1;
+    size_t toff = (256 + ((size_t)K1 + K2) * 4 + 255) / 256 * 256;
+    double* T = (double*)((char*)ws + toff);
+    hipLaunchKernelGGL(fill_int, dim3((K1 + K2 + 255) / 256), dim3(256), 0, stream, rowf, K1 + K2, 0);
+    hipLaunchKernelGGL(joint2_flags, dim3(2048), dim3(256), 0, stream, acc, n_sub, K1, K2, rowf,
+                       colf);
+    hipLaunchKernelGGL(joint2_rows, dim3(K1, n_sub), dim3(256), 0, stream, acc, K1, K2, rowf, colf,
+                       T);
+    const double scale = 1.0 / ((double)K1 * (double)K2 * (double)ns);
+    hipLaunchKernelGGL(joint2_columns, dim3(K1, (K2 + 255) / 256), dim3(256), 0, stream, T, n_sub,
+                       K1, K2, scale, rowf, P_re, P_im, sigma);
+    MP_HIP_LAUNCH_CHECK("mp_counts_finalize joint launch");
+    return MP_OK;
+  }
   FinalParams p{};
   p.joint2 = (mode == MP_JOINT && d == 2) ? 1 : 0;
   p.n_dist = mode == MP_JOINT ? (p.joint2 ? 2 : 1) : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);

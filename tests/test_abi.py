@@ -96,5 +96,10 @@ def test_host_validation_rejects_bad_arguments():
     st = lib.mp_binned_counts(4, 8, vp(16), vp(16), 0, 0, 1, i32([0] * 4), 0, i32([0]), i32([8]), 1,
                               8, 0, vp(16), vp(256), 16, None)
     assert st == -5
-    st = lib.mp_counts_finalize(1, 0, i32([8]), 0, 8, vp(16), vp(16), vp(16), vp(16), None)
+    st = lib.mp_counts_finalize(1, 0, i32([8]), 0, 8, vp(16), vp(16), vp(16), vp(16), vp(0), 0, None)
     assert st == -1
+    # joint two-bin finalize needs a workspace
+    assert lib.mp_finalize_workspace(2, 0, i32([16, 8]), 3) >= 3 * 16 * 8 * 16
+    st = lib.mp_counts_finalize(2, 0, i32([16, 8]), 3, 8, vp(256), vp(256), vp(256), vp(256), vp(0),
+                                0, None)
+    assert st == -5

@@ -231,3 +231,76 @@ def test_reduced_precision_counts_within_sigma(prec, floor):
     print(f"{prec}: max |dP| = {err.max():.3e}, max |dP|/sigma over the bulk = "
           f"{(err / ref['sigma'])[ref['P'] > 1e-3 * ref['P'].max()].max():.3e}")
     assert np.all(err <= 0.05 * ref["sigma"] + floor * ref["P"].max())
+
+
+def test_joint_two_bins_lossless_fp64():
+    """Joint counts of two bins of a lossless network: both characteristic-
+    function bands (around theta = 0 and theta = pi) contribute; odd totals
+    vanish."""
+    M = 8
+    U = synth.haar_unitary(M, 13)
+    r = np.full(M, 0.5)
+    bins = np.array([0] * 4 + [1] * 4, dtype=np.int32)
+    wins = [(0, 32), (0, 32)]
+    p = _pipe(U, r, prec="fp64", seed=21, bin_of_mode=bins, d=2, mode="joint", windows=wins,
+              n_sub=4, samples_per_sub=500, chunk=2000)
+    p.run()
+    P, _, s = p.result()
+    P = P.reshape(32, 32)
+    ref = _oracle(U, r, 21, 2000, 4, bins, 2, wins)
+    _p_close(P, ref["P"])
+    odd = (np.add.outer(np.arange(32), np.arange(32)) % 2) == 1
+    assert np.abs(P[odd]).max() < 1e-13
+
+
+def test_joint_two_bins_lossy_offsets_fp64():
+    """Lossy network, window offsets and aliasing, chunks across sub-ensembles."""
+    M = 40
+    T = 0.85 * synth.haar_unitary(M, 17)
+    r = synth.squeezing_random_uniform(M, 0.4, 0.9, 17)
+    bins = np.array([0] * 20 + [1] * 20, dtype=np.int32)
+    wins = [(3, 48), (1, 40)]
+    p = _pipe(T, r, prec="fp64", seed=23, bin_of_mode=bins, d=2, mode="joint", windows=wins,
+              n_sub=5, samples_per_sub=400, chunk=700)
+    p.run()
+    P, _, s = p.result()
+    P = P.reshape(48, 40)
+    full = _oracle(T, r, 23, 2000, 5, bins, 2, [(0, 96), (0, 96)])
+    ref = np.zeros((48, 40))
+    m = np.arange(96)
+    np.add.at(ref, ((m[:, None] - 3) % 48, (m[None, :] - 1) % 40), full["P"])
+    _p_close(P, ref)
+    # sigma_T of the folded cells from the oracle's folded sub-ensemble estimates
+    Ps = np.zeros((5, 48, 40))
+    for k in range(5):
+        np.add.at(Ps[k], ((m[:, None] - 3) % 48, (m[None, :] - 1) % 40), full["Ps"][k].real)
+    sref = Ps.std(axis=0, ddof=1) / np.sqrt(5)
+    np.testing.assert_allclose(s.reshape(48, 40), sref, rtol=1e-6, atol=1e-13 * ref.max())
+
+
+def test_joint_m1000_fp32_subwindow():
+    """Two halves of a 1000-mode network (Haar x 0.9, r = 1), FP32 path, the
+    K = 768 windows of the two-bin workload; checked on a 40 x 40 block around
+    the peak against the oracle on the same noise."""
+    M = 1000
+    T = 0.9 * synth.haar_unitary(M, synth.SEED_BASE + 1)
+    r = np.full(M, 1.0)
+    bins = synth.contiguous_bins(M, 2)
+    mean, sd = synth.uniform_loss_moments(r, 0.9, frac=0.5)
+    w = synth.count_window(mean, sd, nsig=9.0)
+    wins = [w, w]
+    E, nsub = 4096, 4
+    p = _pipe(T, r, prec="fp32", seed=synth.SEED_BASE + 1, bin_of_mode=bins, d=2, mode="joint",
+              windows=wins, n_sub=nsub, samples_per_sub=E // nsub, chunk=E)
+    p.run()
+    P, _, s = p.result()
+    K = w[1]
+    P = P.reshape(K, K)
+    c = int(round(mean))
+    blk = np.arange(c - 20, c + 20)
+    ref = _oracle(T, r, synth.SEED_BASE + 1, E, nsub, bins, 2, [(c - 20, 40), (c - 20, 40)])
+    got = P[np.ix_(blk - w[0], blk - w[0])]
+    err = np.abs(got - ref["P"])
+    print(f"joint m1000 fp32: max|dP| = {err.max():.3e}, max sigma = {ref['sigma'].max():.3e}")
+    assert np.all(err <= 0.05 * ref["sigma"] + 1e-7 * ref["P"].max())
+    assert abs(P.sum() - 1) < 1e-6
