@@ -200,6 +200,52 @@ mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int3
                              double* P_im, double* sigma, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* ---------------------------------------------------------------- batching */
+
+/* One network of a batched plan: total counts of all M outputs on the window
+ * [m_lo, m_lo + K), E samples in n_sub sub-ensembles, noise stream `net`. */
+typedef struct {
+  int32_t M;
+  const double* T; /* device, complex M x M row-major interleaved (as mp_propagate) */
+  const double* r; /* device FP64[M] */
+  uint64_t seed;
+  uint32_t net;
+  int64_t E;       /* samples; a multiple of n_sub */
+  int32_t n_sub;
+  int32_t m_lo;
+  int32_t K;
+} mp_net_desc;
+
+/*
+ * Plan for many independent networks of uneven size (the batched form of the
+ * matrix-P pass).  Creation copies r, packs every T (T and r may be freed
+ * afterwards), allocates all buffers (the plan owns them), chooses the
+ * grouped-GEMM work-list order with a timing autotuner (cached in the JSON
+ * file `tune_cache` when it is not NULL), and captures the whole pass in a
+ * hipGraph: accumulators cleared by fill kernels, sampling, ONE persistent
+ * grouped split-precision GEMM launch over all networks' tiles per pass (FP64
+ * and FP32 plans launch one GEMM per network instead), counts and inverse
+ * DFT per network.  E must be <= chunk or a multiple of it; each pass covers
+ * `chunk` samples of every network.  Synchronous; not thread-safe per plan.
+ */
+mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets,
+                         mp_precision prec, mp_estimator est, int64_t chunk,
+                         const char* tune_cache);
+
+/* Replays the captured pass after the work already queued on `stream`; the
+ * stream waits for the replay.  Results are overwritten by each replay. */
+mp_status mp_plan_launch(void* plan, void* stream);
+
+/* Device pointers (owned by the plan) to network i's P_re, P_im, sigma[K]. */
+mp_status mp_plan_result(void* plan, int32_t i, const double** P_re, const double** P_im,
+                         const double** sigma);
+
+/* Chosen work-list order, its tuned GEMM time (ms) and the plan's device bytes. */
+mp_status mp_plan_info(void* plan, int32_t* order, double* tuned_ms, size_t* device_bytes);
+
+/* Waits for the plan's stream and frees everything the plan owns. */
+mp_status mp_plan_destroy(void* plan);
+
 /* Message of the calling thread's last non-MP_OK status ("" if none). */
 const char* mp_last_error(void);
 

@@ -18,7 +18,7 @@ from ._lib import BIN_MODES, ESTIMATORS, MPError, PRECISIONS, i32_array
 __all__ = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
     "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
-    "mp_counts_finalize", "mp_finalize_workspace", "mp_version", "CountsPipeline", "MPError",
+    "mp_counts_finalize", "mp_finalize_workspace", "mp_version", "CountsPipeline", "Plan", "MPError",
 ]
 
 
@@ -203,3 +203,85 @@ class CountsPipeline:
         a = v[:E, : self.M] + 1j * v[:E, ldm: ldm + self.M]
         b = v[E:, : self.M] - 1j * v[E:, ldm: ldm + self.M]
         return a, b
+
+
+_HIP = None
+
+
+def _hip_runtime():
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _HIP.hipMemcpy.restype = ctypes.c_int
+    return _HIP
+
+
+class Plan:
+    """Batched plan over many networks (mp_plan_create / mp_plan_launch):
+    one captured hipGraph per plan, one persistent grouped GEMM launch per
+    pass.  `nets` is a list of dicts with keys T (complex numpy M x M), r,
+    seed, net, E, n_sub, window=(m_lo, K)."""
+
+    def __init__(self, nets, *, prec="split_fp16", est="matrix_p", chunk=None, tune_cache=None,
+                 device="cuda:0"):
+        import torch
+        self.torch = torch
+        dev = torch.device(device)
+        keep = []
+        descs = (_lib.NetDesc * len(nets))()
+        for i, n in enumerate(nets):
+            T = np.ascontiguousarray(n["T"], dtype=np.complex128)
+            M = T.shape[0]
+            Td = torch.from_numpy(T.view(np.float64).reshape(-1).copy()).to(dev)
+            rd = torch.from_numpy(np.asarray(n["r"], dtype=np.float64).copy()).to(dev)
+            keep += [Td, rd]
+            m_lo, K = n["window"]
+            descs[i] = _lib.NetDesc(M, Td.data_ptr(), rd.data_ptr(), int(n["seed"]), int(n["net"]),
+                                    int(n["E"]), int(n["n_sub"]), int(m_lo), int(K))
+        chunk = max(int(n["E"]) for n in nets) if chunk is None else int(chunk)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        path = None if tune_cache is None else str(tune_cache).encode()
+        _lib.check(_lib.load().mp_plan_create(ctypes.byref(h), len(nets), descs, _prec(prec),
+                                              _est(est), chunk, path))
+        self.handle = h
+        self.K = [int(n["window"][1]) for n in nets]
+        del keep
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().mp_plan_launch(self.handle, _stream(stream)))
+
+    def result(self, i):
+        """(P_re, P_im, sigma) of network i as numpy arrays (synchronises)."""
+        t = self.torch
+        pr, pi, sg = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _lib.check(_lib.load().mp_plan_result(self.handle, i, ctypes.byref(pr), ctypes.byref(pi),
+                                              ctypes.byref(sg)))
+        t.cuda.synchronize()
+        K = self.K[i]
+        out = []
+        hip = _hip_runtime()
+        for ptr in (pr, pi, sg):
+            buf = (ctypes.c_double * K)()
+            if hip.hipMemcpy(buf, ctypes.c_void_p(ptr.value), ctypes.c_size_t(8 * K), 2) != 0:
+                raise MPError(-3, "hipMemcpy of plan results failed")
+            out.append(np.frombuffer(buf, dtype=np.float64).copy())
+        return tuple(out)
+
+    def info(self):
+        o, ms, b = ctypes.c_int32(), ctypes.c_double(), ctypes.c_size_t()
+        _lib.check(_lib.load().mp_plan_info(self.handle, ctypes.byref(o), ctypes.byref(ms),
+                                            ctypes.byref(b)))
+        return {"order": o.value, "tuned_ms": ms.value, "device_bytes": b.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.check(_lib.load().mp_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

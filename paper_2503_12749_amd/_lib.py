@@ -21,7 +21,14 @@ EXPORTS = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
     "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
     "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
+    "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_destroy",
 ]
+
+
+class NetDesc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("T", ctypes.c_void_p), ("r", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("net", ctypes.c_uint32), ("E", ctypes.c_int64),
+                ("n_sub", ctypes.c_int32), ("m_lo", ctypes.c_int32), ("K", ctypes.c_int32)]
 
 
 class MPError(RuntimeError):
@@ -59,6 +66,15 @@ def load() -> ctypes.CDLL:
         "mp_finalize_workspace": (sz, [c_i32, ctypes.c_int, i32p, c_i32]),
         "mp_counts_finalize": (ctypes.c_int, [c_i32, ctypes.c_int, i32p, c_i32, c_i64, vp, vp, vp,
                                               vp, vp, sz, vp]),
+        "mp_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), c_i32,
+                                          ctypes.POINTER(NetDesc), ctypes.c_int, ctypes.c_int, c_i64,
+                                          ctypes.c_char_p]),
+        "mp_plan_launch": (ctypes.c_int, [vp, vp]),
+        "mp_plan_result": (ctypes.c_int, [vp, c_i32, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+        "mp_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(sz)]),
+        "mp_plan_destroy": (ctypes.c_int, [vp]),
         "mp_last_error": (ctypes.c_char_p, []),
         "mp_version": (ctypes.c_char_p, []),
     }

@@ -35,6 +35,15 @@ void clear_error();
 
 constexpr int kLdAlign = 128;  // mode padding (GEMM tile multiple)
 
+// One network of a grouped split-precision GEMM launch.
+struct GroupNet {
+  const uint16_t* A;  // packed [Re T; Im T] hi plane, lo plane after it
+  const uint16_t* B;  // sampled amplitudes, hi plane then lo plane
+  float* C;
+  int64_t ldm, ncols;
+  float out_scale;
+};
+
 inline int64_t ld_modes(int32_t M) { return ((int64_t)M + kLdAlign - 1) / kLdAlign * kLdAlign; }
 
 inline size_t elem_bytes_ab(mp_precision p) {

@@ -1,0 +1,511 @@
+// Batched plans: many independent networks (uneven M) run as one pass that is
+// captured once in a hipGraph and replayed.  The pass is
+//   zero accumulators (fill kernels; no memset nodes) -> sample every network
+//   -> one persistent grouped split-precision GEMM launch over all networks'
+//   tiles -> occupations/characteristic function per network -> inverse DFT.
+// A plan owns all of its device memory (allocated in mp_plan_create).
+//
+// Autotuning: the grouped launch's work-list order decides which tiles share
+// an XCD's L2 at the same time.  Candidate orders are timed on the plan's own
+// data at creation and the fastest is kept; results are cached in a small
+// JSON file keyed by precision and the networks' (M, samples per chunk).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace mp {
+
+
+mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint64_t seed,
+                        uint32_t net, mp_precision prec, void* ab, double* n_out,
+                        hipStream_t stream);
+size_t propagate_workspace(int32_t M, mp_precision prec);
+int split_scale_exp(int32_t M, mp_precision prec);
+mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
+                      hipStream_t stream);
+mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                             const void* ab, void* C, hipStream_t stream);
+mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
+                         mp_precision prec, hipStream_t stream);
+size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
+                        int64_t ns, int64_t e0);
+mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double* n,
+                               mp_precision prec, mp_estimator est, int32_t d,
+                               const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                               const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
+                               double* acc, void* ws, size_t ws_bytes, hipStream_t stream);
+mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                                 int64_t ns, const double* acc, double* P_re, double* P_im,
+                                 double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
+
+__global__ void fill_zero_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+constexpr int kOrders = 3;  // autotuner candidates
+constexpr int kXcdsPlan = 8;
+constexpr int kTileRows = 256, kTileCols = 256;
+
+struct PlanNet {
+  mp_net_desc d;
+  int64_t ldm = 0, chunk = 0;
+  double* r = nullptr;
+  double* n = nullptr;
+  double* acc = nullptr;
+  double* P_re = nullptr;
+  double* P_im = nullptr;
+  double* sigma = nullptr;
+  void* ab = nullptr;
+  void* C = nullptr;
+  void* packed = nullptr;
+  void* ws_counts = nullptr;
+  size_t ws_counts_bytes = 0;
+  std::vector<int32_t> bins;
+};
+
+struct Plan {
+  std::vector<PlanNet> nets;
+  mp_precision prec;
+  mp_estimator est;
+  int64_t chunk = 0;
+  int passes = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> allocs;
+  // grouped launch, one per pass
+  std::vector<GroupNet*> d_nets;
+  std::vector<int4*> d_items;
+  std::vector<int> n_items;
+  int grid = 0;
+  int order = 0;
+  double tuned_ms = 0.0;
+  size_t bytes = 0;
+};
+
+static void* plan_alloc(Plan* p, size_t bytes) {
+  void* ptr = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) return nullptr;
+  p->allocs.push_back(ptr);
+  p->bytes += bytes;
+  return ptr;
+}
+
+static void plan_free(Plan* p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->stream) hipStreamSynchronize(p->stream);
+  for (void* a : p->allocs) hipFree(a);
+  if (p->stream) hipStreamDestroy(p->stream);
+  delete p;
+}
+
+// Work list of one pass in the given order.  Slot it * grid + w is processed
+// by workgroup w (on XCD w % 8) in its it-th round.
+static std::vector<int4> build_items(const Plan* p, int pass, int order, int grid) {
+  struct T4 { int net, tm, tn; };
+  std::vector<T4> seq;
+  std::vector<int> idx(p->nets.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return p->nets[a].d.M > p->nets[b].d.M; });
+  const int gm = order == 1 ? 4 : 8;  // group rows x cols: 8 x 4 or 4 x 8
+  const int gn = 32 / gm;
+  for (int i : idx) {
+    const PlanNet& n = p->nets[i];
+    const int64_t e_this = std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk);
+    if (e_this <= 0) continue;
+    const int tiles_m = (int)(2 * n.ldm / kTileRows);
+    const int tiles_n = (int)((2 * e_this + kTileCols - 1) / kTileCols);
+    if (order == 2) {
+      for (int tn = 0; tn < tiles_n; ++tn)
+        for (int tm = 0; tm < tiles_m; ++tm) seq.push_back({i, tm, tn});
+    } else {
+      for (int bm = 0; bm < tiles_m; bm += gm)
+        for (int bn = 0; bn < tiles_n; bn += gn)
+          for (int tn = bn; tn < std::min(bn + gn, tiles_n); ++tn)
+            for (int tm = bm; tm < std::min(bm + gm, tiles_m); ++tm) seq.push_back({i, tm, tn});
+    }
+  }
+  const int n = (int)seq.size();
+  const int rounds = (n + grid - 1) / grid;
+  std::vector<int4> items((size_t)rounds * grid, int4{-1, 0, 0, 0});
+  if (order == 2) {
+    for (int q = 0; q < n; ++q) items[q] = int4{seq[q].net, seq[q].tm, seq[q].tn, 0};
+    return items;
+  }
+  // groups of consecutive sequence entries go to the workgroups of one XCD:
+  // round it, XCD x, slot j (j-th workgroup of that XCD) <- seq[(it*8 + x)*per + j]
+  const int per = grid / kXcdsPlan;
+  for (int q = 0; q < n; ++q) {
+    const int g = q / per, j = q % per;
+    const int it = g / kXcdsPlan, x = g % kXcdsPlan;
+    const int slot = it * grid + x + kXcdsPlan * j;
+    items[slot] = int4{seq[q].net, seq[q].tm, seq[q].tn, 0};
+  }
+  return items;
+}
+
+
+// ---------------------------------------------------------------- tuning cache
+
+static std::string tune_key(const Plan* p) {
+  std::string k = "prec" + std::to_string((int)p->prec) + ":";
+  for (const PlanNet& n : p->nets)
+    k += std::to_string(n.d.M) + "x" + std::to_string(n.chunk) + ",";
+  return k;
+}
+
+// The cache is a flat JSON object {"<key>": {"order": o, "ms": t}, ...}.
+static bool cache_lookup(const char* path, const std::string& key, int& order, double& ms) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  fclose(f);
+  const std::string pat = "\"" + key + "\": {\"order\": ";
+  const size_t at = text.find(pat);
+  if (at == std::string::npos) return false;
+  return sscanf(text.c_str() + at + pat.size(), "%d, \"ms\": %lf", &order, &ms) == 2;
+}
+
+static void cache_store(const char* path, const std::string& key, int order, double ms) {
+  if (!path) return;
+  std::string text;
+  if (FILE* f = fopen(path, "r")) {
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    fclose(f);
+  }
+  size_t end = text.rfind('}');
+  std::string body = end == std::string::npos ? "" : text.substr(text.find('{') + 1, end - text.find('{') - 1);
+  while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
+  char entry[1024];
+  snprintf(entry, sizeof(entry), "\"%s\": {\"order\": %d, \"ms\": %.4f}", key.c_str(), order, ms);
+  const std::string out = "{" + body + (body.empty() ? "\n  " : ",\n  ") + entry + "\n}\n";
+  const std::string tmp = std::string(path) + ".tmp";
+  if (FILE* f = fopen(tmp.c_str(), "w")) {
+    fwrite(out.data(), 1, out.size(), f);
+    fclose(f);
+    rename(tmp.c_str(), path);
+  }
+}
+
+// ---------------------------------------------------------------- pass
+
+static mp_status upload_items(Plan* p, int order) {
+  for (int pass = 0; pass < p->passes; ++pass) {
+    std::vector<int4> items = build_items(p, pass, order, p->grid);
+    const size_t bytes = items.size() * sizeof(int4);
+    if ((int)items.size() > p->n_items[pass]) {
+      set_error("mp_plan: work list grew between orders");
+      return MP_ERR_HIP;
+    }
+    std::vector<int4> padded = items;
+    padded.resize(p->n_items[pass], int4{-1, 0, 0, 0});
+    if (hipMemcpy(p->d_items[pass], padded.data(), padded.size() * sizeof(int4),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("mp_plan: work list upload failed");
+      return MP_ERR_HIP;
+    }
+    (void)bytes;
+  }
+  return MP_OK;
+}
+
+static bool split(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16; }
+
+// Enqueues one full pass of every network on the plan stream.
+static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
+  mp_status st;
+  for (int pass = 0; pass < p->passes; ++pass) {
+    if (!gemm_only) {
+      if (pass == 0)
+        for (PlanNet& n : p->nets) {
+          const int64_t cnt = (int64_t)n.d.n_sub * n.d.K * 2;
+          hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                             p->stream, n.acc, cnt);
+        }
+      for (PlanNet& n : p->nets) {
+        const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
+        if (e <= 0) continue;
+        if ((st = sample_launch(n.d.M, g0, e, n.r, n.d.seed, n.d.net, p->prec, n.ab, n.n,
+                                p->stream)) != MP_OK)
+          return st;
+      }
+    }
+    if (split(p->prec)) {
+      if ((st = grouped_launch(p->d_nets[pass], p->d_items[pass], p->n_items[pass], p->grid,
+                               p->prec, p->stream)) != MP_OK)
+        return st;
+    } else {
+      for (PlanNet& n : p->nets) {
+        const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
+        if (e <= 0) continue;
+        if ((st = gemm_packed_launch(n.d.M, e, n.packed, p->prec, n.ab, n.C, p->stream)) != MP_OK)
+          return st;
+      }
+    }
+    if (gemm_only) continue;
+    for (PlanNet& n : p->nets) {
+      const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
+      if (e <= 0) continue;
+      const int32_t m_lo = n.d.m_lo, K = n.d.K;
+      if ((st = binned_counts_launch(n.d.M, e, n.C, n.n, p->prec, p->est, 1, n.bins.data(),
+                                     MP_JOINT, &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
+                                     n.ws_counts, n.ws_counts_bytes, p->stream)) != MP_OK)
+        return st;
+    }
+  }
+  if (!gemm_only)
+    for (PlanNet& n : p->nets) {
+      const int32_t K = n.d.K;
+      if ((st = counts_finalize_launch(1, MP_JOINT, &K, n.d.n_sub, n.d.E / n.d.n_sub, n.acc,
+                                       n.P_re, n.P_im, n.sigma, nullptr, 0, p->stream)) != MP_OK)
+        return st;
+    }
+  return MP_OK;
+}
+
+}  // namespace mp
+
+using namespace mp;
+
+extern "C" {
+
+mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp_precision prec,
+                         mp_estimator est, int64_t chunk, const char* tune_cache) {
+  clear_error();
+  MP_CHECK_ARG(plan && nets && n_net >= 1, MP_ERR_ARG, "mp_plan_create: null argument or n_net < 1");
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_plan_create: unknown precision %d", (int)prec);
+  MP_CHECK_ARG(est == MP_MATRIX_P || est == MP_PLUS_P, MP_ERR_ARG, "mp_plan_create: unknown estimator");
+  MP_CHECK_ARG(chunk >= 1, MP_ERR_ARG, "mp_plan_create: chunk must be >= 1");
+  *plan = nullptr;
+  for (int i = 0; i < n_net; ++i) {
+    const mp_net_desc& d = nets[i];
+    MP_CHECK_ARG(d.M >= 1 && d.T && d.r && d.E >= 1 && d.n_sub >= 1, MP_ERR_ARG,
+                 "mp_plan_create: network %d has an invalid size or a null pointer", i);
+    MP_CHECK_ARG(d.E % d.n_sub == 0, MP_ERR_SHAPE,
+                 "mp_plan_create: network %d: E = %lld not a multiple of n_sub = %d", i,
+                 (long long)d.E, d.n_sub);
+    MP_CHECK_ARG(d.E <= chunk || d.E % chunk == 0, MP_ERR_SHAPE,
+                 "mp_plan_create: network %d: E = %lld must be <= chunk or a multiple of it", i,
+                 (long long)d.E);
+    MP_CHECK_ARG(d.K >= 1 && d.K <= 65536 && d.m_lo >= 0, MP_ERR_ARG,
+                 "mp_plan_create: network %d: window K in [1, 65536] and m_lo >= 0 required", i);
+  }
+  Plan* p = new Plan();
+  p->prec = prec;
+  p->est = est;
+  p->chunk = chunk;
+  if (hipStreamCreate(&p->stream) != hipSuccess) {
+    delete p;
+    set_error("mp_plan_create: hipStreamCreate failed");
+    return MP_ERR_HIP;
+  }
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  p->grid = std::max(kXcdsPlan, (cus / kXcdsPlan) * kXcdsPlan);
+  const size_t eb = (prec == MP_FP64) ? 8 : 4;
+  int64_t max_e = 0;
+  for (int i = 0; i < n_net; ++i) {
+    PlanNet n;
+    n.d = nets[i];
+    n.ldm = ld_modes(n.d.M);
+    n.chunk = std::min<int64_t>(chunk, n.d.E);
+    n.bins.assign(n.d.M, 0);
+    max_e = std::max<int64_t>(max_e, n.d.E);
+    n.r = (double*)plan_alloc(p, (size_t)n.d.M * 8);
+    n.n = (double*)plan_alloc(p, (size_t)n.chunk * 8);
+    n.acc = (double*)plan_alloc(p, (size_t)n.d.n_sub * n.d.K * 16);
+    n.P_re = (double*)plan_alloc(p, (size_t)n.d.K * 8);
+    n.P_im = (double*)plan_alloc(p, (size_t)n.d.K * 8);
+    n.sigma = (double*)plan_alloc(p, (size_t)n.d.K * 8);
+    n.ab = plan_alloc(p, (size_t)n.ldm * 2 * n.chunk * (prec == MP_FP64 ? 8 : 4));
+    n.C = plan_alloc(p, (size_t)2 * n.ldm * 2 * n.chunk * eb);
+    n.packed = plan_alloc(p, propagate_workspace(n.d.M, prec));
+    const int32_t K = n.d.K;
+    const int64_t ns = n.d.E / n.d.n_sub;
+    size_t wsb = 0;
+    for (int64_t g0 = 0; g0 < n.d.E; g0 += n.chunk)
+      wsb = std::max(wsb, binned_workspace(1, MP_JOINT, &K, std::min<int64_t>(n.chunk, n.d.E - g0),
+                                           n.d.n_sub, ns, g0));
+    n.ws_counts_bytes = wsb;
+    n.ws_counts = plan_alloc(p, wsb);
+    if (!n.r || !n.n || !n.acc || !n.P_re || !n.P_im || !n.sigma || !n.ab || !n.C || !n.packed ||
+        !n.ws_counts) {
+      plan_free(p);
+      set_error("mp_plan_create: device allocation failed (network %d)", i);
+      return MP_ERR_HIP;
+    }
+    hipMemcpyAsync(n.r, n.d.r, (size_t)n.d.M * 8, hipMemcpyDeviceToDevice, p->stream);
+    mp_status st = pack_launch(n.d.M, n.d.T, prec, n.packed, p->stream);
+    if (st != MP_OK) {
+      plan_free(p);
+      return st;
+    }
+    p->nets.push_back(n);
+  }
+  p->passes = (int)((max_e + chunk - 1) / chunk);
+  // grouped launch tables, one per pass
+  if (split(prec)) {
+    for (int pass = 0; pass < p->passes; ++pass) {
+      std::vector<GroupNet> g(p->nets.size());
+      for (size_t i = 0; i < p->nets.size(); ++i) {
+        PlanNet& n = p->nets[i];
+        const int64_t e = std::max<int64_t>(0, std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk));
+        const float sc = ldexpf(1.0f, -split_scale_exp(n.d.M, prec));
+        g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, (float*)n.C, n.ldm, 2 * e, sc};
+      }
+      GroupNet* dn = (GroupNet*)plan_alloc(p, g.size() * sizeof(GroupNet));
+      size_t max_items = 0;
+      for (int o = 0; o < kOrders; ++o) max_items = std::max(max_items, build_items(p, pass, o, p->grid).size());
+      int4* di = (int4*)plan_alloc(p, max_items * sizeof(int4));
+      if (!dn || !di) {
+        plan_free(p);
+        set_error("mp_plan_create: device allocation failed (work lists)");
+        return MP_ERR_HIP;
+      }
+      hipMemcpy(dn, g.data(), g.size() * sizeof(GroupNet), hipMemcpyHostToDevice);
+      p->d_nets.push_back(dn);
+      p->d_items.push_back(di);
+      p->n_items.push_back((int)max_items);
+    }
+    // autotune the work-list order on this plan's data
+    const std::string key = tune_key(p);
+    int order = 0;
+    double ms = 0.0;
+    if (!cache_lookup(tune_cache, key, order, ms)) {
+      // a valid work list must be on the device before the first grouped launch
+      mp_status st = upload_items(p, 0);
+      if (st == MP_OK) st = enqueue_pass(p);  // real data in every buffer
+      if (st != MP_OK) {
+        plan_free(p);
+        return st;
+      }
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      double best = 1e30;
+      for (int o = 0; o < kOrders; ++o) {
+        if ((st = upload_items(p, o)) != MP_OK) break;
+        enqueue_pass(p, true);  // warm
+        hipEventRecord(a, p->stream);
+        for (int rep = 0; rep < 2; ++rep) enqueue_pass(p, true);
+        hipEventRecord(b, p->stream);
+        hipEventSynchronize(b);
+        float t = 0.f;
+        hipEventElapsedTime(&t, a, b);
+        if (t / 2 < best) {
+          best = t / 2;
+          order = o;
+        }
+      }
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+      if (st != MP_OK) {
+        plan_free(p);
+        return st;
+      }
+      ms = best;
+      cache_store(tune_cache, key, order, ms);
+    }
+    p->order = order;
+    p->tuned_ms = ms;
+    mp_status st = upload_items(p, order);
+    if (st != MP_OK) {
+      plan_free(p);
+      return st;
+    }
+  }
+  // capture the full pass once
+  if (hipStreamSynchronize(p->stream) != hipSuccess ||
+      hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    plan_free(p);
+    set_error("mp_plan_create: stream capture could not start");
+    return MP_ERR_HIP;
+  }
+  mp_status st = enqueue_pass(p);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(p->stream, &graph);
+  if (st != MP_OK || ce != hipSuccess || !graph) {
+    if (graph) hipGraphDestroy(graph);
+    plan_free(p);
+    if (st == MP_OK) set_error("mp_plan_create: stream capture failed: %s", hipGetErrorString(ce));
+    return st == MP_OK ? MP_ERR_HIP : st;
+  }
+  p->graph = graph;
+  if (hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    plan_free(p);
+    set_error("mp_plan_create: graph instantiation failed");
+    return MP_ERR_HIP;
+  }
+  *plan = p;
+  return MP_OK;
+}
+
+mp_status mp_plan_launch(void* plan, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(plan, MP_ERR_ARG, "mp_plan_launch: null plan");
+  Plan* p = (Plan*)plan;
+  // order the replay after the caller's stream and make the caller wait for it
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    set_error("mp_plan_launch: event creation failed");
+    return MP_ERR_HIP;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEventRecord(ev, s);
+  hipStreamWaitEvent(p->stream, ev, 0);
+  const hipError_t e = hipGraphLaunch(p->exec, p->stream);
+  hipEventRecord(ev, p->stream);
+  hipStreamWaitEvent(s, ev, 0);
+  hipEventDestroy(ev);
+  if (e != hipSuccess) {
+    set_error("mp_plan_launch: %s", hipGetErrorString(e));
+    return MP_ERR_HIP;
+  }
+  return MP_OK;
+}
+
+mp_status mp_plan_result(void* plan, int32_t i, const double** P_re, const double** P_im,
+                         const double** sigma) {
+  clear_error();
+  MP_CHECK_ARG(plan, MP_ERR_ARG, "mp_plan_result: null plan");
+  Plan* p = (Plan*)plan;
+  MP_CHECK_ARG(i >= 0 && i < (int)p->nets.size(), MP_ERR_ARG, "mp_plan_result: network %d", i);
+  if (P_re) *P_re = p->nets[i].P_re;
+  if (P_im) *P_im = p->nets[i].P_im;
+  if (sigma) *sigma = p->nets[i].sigma;
+  return MP_OK;
+}
+
+mp_status mp_plan_info(void* plan, int32_t* order, double* tuned_ms, size_t* device_bytes) {
+  clear_error();
+  MP_CHECK_ARG(plan, MP_ERR_ARG, "mp_plan_info: null plan");
+  Plan* p = (Plan*)plan;
+  if (order) *order = p->order;
+  if (tuned_ms) *tuned_ms = p->tuned_ms;
+  if (device_bytes) *device_bytes = p->bytes;
+  return MP_OK;
+}
+
+mp_status mp_plan_destroy(void* plan) {
+  clear_error();
+  if (plan) plan_free((Plan*)plan);
+  return MP_OK;
+}
+
+}  // extern "C"

@@ -811,17 +811,11 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_ring(const uint16_
 // overlap the second group, so neither the barrier nor the LDS latency
 // leaves the matrix pipe idle for a whole fragment round trip.
 template <typename H>
-__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t* __restrict__ A,
-                                                                 const uint16_t* __restrict__ B,
-                                                                 float* __restrict__ C,
-                                                                 int64_t ldm, int64_t ncols,
-                                                                 float out_scale) {
+__device__ inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
+                                     const uint16_t* __restrict__ B, float* __restrict__ C,
+                                     int64_t ldm, int64_t ncols, int64_t m0, int64_t n0,
+                                     float out_scale) {
   typedef typename SplitMfma<H>::frag frag;
-  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
-  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lh = lane >> 5;
@@ -968,6 +962,41 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
   }
 }
 
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t* __restrict__ A,
+                                                                 const uint16_t* __restrict__ B,
+                                                                 float* __restrict__ C,
+                                                                 int64_t ldm, int64_t ncols,
+                                                                 float out_scale) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  split_pp_tile<H>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN, out_scale);
+}
+
+// ---------------------------------------------------------------- grouped
+
+// Persistent grouped launch over many networks: one workgroup per CU walks a
+// work list of (network, tile) items with stride gridDim.x; the list is
+// ordered so that the items an XCD processes at the same time are
+// neighbouring tiles of one network.
+
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet* __restrict__ nets,
+                                                                  const int4* __restrict__ items,
+                                                                  int n_items) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];  // (net, tile_m, tile_n, unused); net < 0: idle slot
+    if (w.x < 0) continue;
+    const GroupNet g = nets[w.x];
+    split_pp_tile<H>(lds, g.A, g.B, g.C, g.ldm, g.ncols, (int64_t)w.y * S_BM, (int64_t)w.z * S_BN,
+                     g.out_scale);
+    __syncthreads();  // the next item reuses the LDS stages
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 size_t propagate_workspace(int32_t M, mp_precision prec) {
@@ -1003,6 +1032,82 @@ static int fp16_scale_exp(int32_t M) {
   int e = 0;
   while ((1LL << (2 * (e + 1))) <= (long long)M) ++e;
   return e;
+}
+
+// ---- used by plans (plan.hip)
+
+int split_scale_exp(int32_t M, mp_precision prec) {
+  return prec == MP_SPLIT_FP16 ? fp16_scale_exp(M) : 0;
+}
+
+mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
+                      hipStream_t stream) {
+  const int64_t ldm = ld_modes(M);
+  const int blocks = (int)((2 * ldm * ldm + 255) / 256);
+  switch (prec) {
+    case MP_FP64:
+      hipLaunchKernelGGL(pack_transmission<MP_FP64>, dim3(blocks), dim3(256), 0, stream, T, M, ldm,
+                         packed, 0);
+      break;
+    case MP_FP32:
+      hipLaunchKernelGGL(pack_transmission<MP_FP32>, dim3(blocks), dim3(256), 0, stream, T, M, ldm,
+                         packed, 0);
+      break;
+    case MP_SPLIT_BF16:
+      hipLaunchKernelGGL(pack_transmission<MP_SPLIT_BF16>, dim3(blocks), dim3(256), 0, stream, T,
+                         M, ldm, packed, 0);
+      break;
+    case MP_SPLIT_FP16:
+      hipLaunchKernelGGL(pack_transmission<MP_SPLIT_FP16>, dim3(blocks), dim3(256), 0, stream, T,
+                         M, ldm, packed, fp16_scale_exp(M));
+      break;
+  }
+  MP_HIP_LAUNCH_CHECK("plan pack launch");
+  return MP_OK;
+}
+
+// GEMM on an already packed operand (one network).
+mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                             const void* ab, void* C, hipStream_t stream) {
+  const int64_t ldm = ld_modes(M), ncols = 2 * E;
+  switch (prec) {
+    case MP_FP64:
+      hipLaunchKernelGGL(gemm_f64, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
+                         (const double*)packed, (const double*)ab, (double*)C, ldm, ncols);
+      break;
+    case MP_FP32:
+      hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
+                         (const float*)packed, (const float*)ab, (float*)C, ldm, ncols);
+      break;
+    case MP_SPLIT_BF16:
+      hipLaunchKernelGGL(gemm_split_256_pp<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                         dim3(kThreads), 0, stream, (const uint16_t*)packed, (const uint16_t*)ab,
+                         (float*)C, ldm, ncols, 1.0f);
+      break;
+    case MP_SPLIT_FP16:
+      hipLaunchKernelGGL(gemm_split_256_pp<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                         dim3(kThreads), 0, stream, (const uint16_t*)packed, (const uint16_t*)ab,
+                         (float*)C, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
+      break;
+  }
+  MP_HIP_LAUNCH_CHECK("plan gemm launch");
+  return MP_OK;
+}
+
+mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
+                         mp_precision prec, hipStream_t stream) {
+  if (prec == MP_SPLIT_BF16)
+    hipLaunchKernelGGL(gemm_split_grouped<__bf16>, dim3(grid), dim3(kThreads), 0, stream, d_nets,
+                       d_items, n_items);
+  else if (prec == MP_SPLIT_FP16)
+    hipLaunchKernelGGL(gemm_split_grouped<_Float16>, dim3(grid), dim3(kThreads), 0, stream, d_nets,
+                       d_items, n_items);
+  else {
+    set_error("grouped GEMM: split precisions only");
+    return MP_ERR_UNSUPPORTED;
+  }
+  MP_HIP_LAUNCH_CHECK("plan grouped gemm launch");
+  return MP_OK;
 }
 
 mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision prec,

@@ -1,0 +1,102 @@
+"""Batched plans: one captured hipGraph, one persistent grouped GEMM launch
+over networks of uneven M.  A plan's result for each network must equal the
+single-network pipeline on the same noise (the grouped launch runs the same
+tile code), replays must be identical, and the autotuner's choice must be
+cached and reused."""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator as oest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_12749_amd  # noqa: F401
+    yield
+
+
+def _nets(Ms, E, n_sub, seed0=900):
+    rng = np.random.default_rng(seed0)
+    nets = []
+    for i, M in enumerate(Ms):
+        t = float(rng.uniform(0.85, 0.99))
+        r = np.ones(M)
+        mean, sd = synth.uniform_loss_moments(r, t)
+        nets.append(dict(T=synth.transmission(M, t, seed0 + i), r=r, seed=seed0, net=i, E=E,
+                         n_sub=n_sub, window=synth.count_window(mean, sd), t=t))
+    return nets
+
+
+def _single(n, prec):
+    import paper_2503_12749_amd as mp
+    p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
+                          windows=[n["window"]], n_sub=n["n_sub"],
+                          samples_per_sub=n["E"] // n["n_sub"], chunk=n["E"])
+    p.run()
+    return p.result()
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+def test_plan_equals_single_network_runs(prec, tmp_path):
+    import paper_2503_12749_amd as mp
+    nets = _nets([60, 130, 300, 520], E=4096, n_sub=4)
+    cache = tmp_path / "tune.json"
+    plan = mp.Plan(nets, prec=prec, tune_cache=cache)
+    info = plan.info()
+    assert 0 <= info["order"] < 3 and info["tuned_ms"] > 0
+    first = []
+    for rep in range(3):
+        plan.launch()
+        # eager work between replays
+        x = torch.randn(1 << 20, device="cuda:0")
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum())
+        res = [plan.result(i) for i in range(len(nets))]
+        if rep == 0:
+            first = res
+        for a, b in zip(res, first):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    for i, n in enumerate(nets):
+        P, Pi, s = _single(n, prec)
+        assert np.array_equal(first[i][0], P), i
+        assert np.array_equal(first[i][2], s), i
+        assert abs(P.sum() - 1) < 1e-8
+    # the cache holds the choice and a second plan reuses it
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    plan2 = mp.Plan(nets, prec=prec, tune_cache=cache)
+    assert plan2.info()["order"] == info["order"]
+    assert plan2.info()["tuned_ms"] == pytest.approx(info["tuned_ms"], rel=1e-3)
+    plan.close()
+    plan2.close()
+
+
+def test_plan_chunked_passes_and_fp64_oracle():
+    """FP64 plan (one GEMM per network inside the graph) over two passes per
+    network against the oracle."""
+    import paper_2503_12749_amd as mp
+    nets = _nets([16, 40, 70], E=2000, n_sub=4, seed0=77)
+    plan = mp.Plan(nets, prec="fp64", chunk=1000)
+    plan.launch()
+    for i, n in enumerate(nets):
+        P, _, s = plan.result(i)
+        ref = oest.estimate(n["T"], n["r"], n["seed"], n["E"], n["n_sub"], np.zeros(len(n["r"]), int),
+                            1, [n["window"]], net=n["net"], chunk=1000)
+        tol = 1e-10 * np.maximum(np.abs(ref["P"]), 1e-4 * ref["P"].max()) + 1e-14 * ref["P"].max()
+        assert np.all(np.abs(P - ref["P"]) <= tol), i
+    plan.close()
+
+
+def test_plan_rejects_bad_networks():
+    import paper_2503_12749_amd as mp
+    nets = _nets([32], E=1000, n_sub=3)
+    with pytest.raises(mp.MPError):
+        mp.Plan(nets, prec="split_fp16")
