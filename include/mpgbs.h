@@ -246,6 +246,49 @@ mp_status mp_plan_info(void* plan, int32_t* order, double* tuned_ms, size_t* dev
 /* Waits for the plan's stream and frees everything the plan owns. */
 mp_status mp_plan_destroy(void* plan);
 
+/* ---------------------------------------------------------------- surrogate */
+
+/*
+ * Small MLP trained on method outputs (sweep parameters -> moments of a bin's
+ * count distribution) to screen parameter sweeps; the method judges and
+ * replaces its predictions.  Layer l maps width[l] -> width[l+1] as
+ * y = x W_l + b_l with W_l row-major (width[l] x width[l+1]) followed by b_l,
+ * layers concatenated in one FP32 vector `params`; SiLU on hidden layers,
+ * linear output.  Forward and backward read weights from `w16`, a BF16 copy
+ * of params (same indexing), and accumulate in FP32.  All arrays are device
+ * memory; X is batch x width[0], Y batch x width[n_layers], row-major FP32.
+ * Widths <= 1024, n_layers <= MP_MLP_MAX_LAYERS.
+ */
+#define MP_MLP_MAX_LAYERS 8
+typedef struct {
+  int32_t n_layers;
+  int32_t width[MP_MLP_MAX_LAYERS + 1];
+} mp_mlp_shape;
+
+int64_t mp_mlp_param_count(const mp_mlp_shape* shape);
+size_t mp_mlp_workspace(const mp_mlp_shape* shape, int32_t batch);
+
+/* w16 = BF16(params), round to nearest even. */
+mp_status mp_mlp_round(const mp_mlp_shape* shape, const float* params, uint16_t* w16,
+                       void* stream);
+
+/* Y = MLP(X). */
+mp_status mp_mlp_forward(const mp_mlp_shape* shape, const uint16_t* w16, const float* params,
+                         const float* X, int32_t batch, float* Y, void* workspace,
+                         size_t ws_bytes, void* stream);
+
+/* loss = mean over all entries of (MLP(X) - Y)^2 (device float[1]) and its
+ * gradient with respect to every parameter (grads, FP32, params' layout). */
+mp_status mp_mlp_loss_grad(const mp_mlp_shape* shape, const uint16_t* w16, const float* params,
+                           const float* X, const float* Y, int32_t batch, float* grads,
+                           float* loss, void* workspace, size_t ws_bytes, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on params with moments m, v;
+ * refreshes w16. */
+mp_status mp_mlp_adam(const mp_mlp_shape* shape, float* params, const float* grads, float* m,
+                      float* v, uint16_t* w16, float lr, float beta1, float beta2, float eps,
+                      int32_t step, void* stream);
+
 /* Message of the calling thread's last non-MP_OK status ("" if none). */
 const char* mp_last_error(void);
 

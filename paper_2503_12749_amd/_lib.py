@@ -22,7 +22,15 @@ EXPORTS = [
     "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
     "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
     "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_destroy",
+    "mp_mlp_param_count", "mp_mlp_workspace", "mp_mlp_round", "mp_mlp_forward", "mp_mlp_loss_grad",
+    "mp_mlp_adam",
 ]
+
+MP_MLP_MAX_LAYERS = 8
+
+
+class MlpShape(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("width", ctypes.c_int32 * (MP_MLP_MAX_LAYERS + 1))]
 
 
 class NetDesc(ctypes.Structure):
@@ -75,6 +83,14 @@ def load() -> ctypes.CDLL:
         "mp_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(sz)]),
         "mp_plan_destroy": (ctypes.c_int, [vp]),
+        "mp_mlp_param_count": (c_i64, [ctypes.POINTER(MlpShape)]),
+        "mp_mlp_workspace": (sz, [ctypes.POINTER(MlpShape), c_i32]),
+        "mp_mlp_round": (ctypes.c_int, [ctypes.POINTER(MlpShape), vp, vp, vp]),
+        "mp_mlp_forward": (ctypes.c_int, [ctypes.POINTER(MlpShape), vp, vp, vp, c_i32, vp, vp, sz, vp]),
+        "mp_mlp_loss_grad": (ctypes.c_int, [ctypes.POINTER(MlpShape), vp, vp, vp, vp, c_i32, vp, vp,
+                                            vp, sz, vp]),
+        "mp_mlp_adam": (ctypes.c_int, [ctypes.POINTER(MlpShape), vp, vp, vp, vp, vp, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, c_i32, vp]),
         "mp_last_error": (ctypes.c_char_p, []),
         "mp_version": (ctypes.c_char_p, []),
     }

@@ -42,7 +42,26 @@ mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, 
                                  double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
 size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
 
+int64_t mlp_param_count(const mp_mlp_shape* s);
+size_t mlp_workspace(const mp_mlp_shape* s, int32_t batch);
+mp_status mlp_forward(const mp_mlp_shape* s, const uint16_t* w16, const float* params,
+                      const float* X, int32_t batch, float* Y, void* ws, hipStream_t st);
+mp_status mlp_loss_grad(const mp_mlp_shape* s, const uint16_t* w16, const float* params,
+                        const float* X, const float* Y, int32_t batch, float* grads, float* loss,
+                        void* ws, hipStream_t st);
+mp_status mlp_adam_launch(int64_t n, float* params, const float* grads, float* m, float* v,
+                          uint16_t* w16, float lr, float b1, float b2, float eps, int32_t step,
+                          hipStream_t st);
+mp_status mlp_round_launch(int64_t n, const float* params, uint16_t* w16, hipStream_t st);
+
 static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static bool valid_shape(const mp_mlp_shape* s) {
+  if (!s || s->n_layers < 1 || s->n_layers > MP_MLP_MAX_LAYERS) return false;
+  for (int l = 0; l <= s->n_layers; ++l)
+    if (s->width[l] < 1 || s->width[l] > 1024) return false;
+  return true;
+}
 
 static int n_dist_of(int32_t d, mp_bin_mode mode) {
   if (mode == MP_JOINT) return d;
@@ -169,6 +188,61 @@ mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int3
                "mp_counts_finalize: workspace must be 256-byte aligned");
   return counts_finalize_launch(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma,
                                 workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int64_t mp_mlp_param_count(const mp_mlp_shape* shape) {
+  return valid_shape(shape) ? mlp_param_count(shape) : -1;
+}
+
+size_t mp_mlp_workspace(const mp_mlp_shape* shape, int32_t batch) {
+  return (valid_shape(shape) && batch >= 1) ? mlp_workspace(shape, batch) : 0;
+}
+
+mp_status mp_mlp_round(const mp_mlp_shape* shape, const float* params, uint16_t* w16,
+                       void* stream) {
+  clear_error();
+  MP_CHECK_ARG(valid_shape(shape), MP_ERR_ARG, "mp_mlp_round: invalid shape");
+  MP_CHECK_ARG(params && w16, MP_ERR_ARG, "mp_mlp_round: null pointer argument");
+  return mlp_round_launch(mlp_param_count(shape), params, w16, (hipStream_t)stream);
+}
+
+mp_status mp_mlp_forward(const mp_mlp_shape* shape, const uint16_t* w16, const float* params,
+                         const float* X, int32_t batch, float* Y, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(valid_shape(shape), MP_ERR_ARG, "mp_mlp_forward: invalid shape");
+  MP_CHECK_ARG(batch >= 1, MP_ERR_ARG, "mp_mlp_forward: batch must be >= 1");
+  MP_CHECK_ARG(w16 && params && X && Y, MP_ERR_ARG, "mp_mlp_forward: null pointer argument");
+  MP_CHECK_ARG(workspace && ws_bytes >= mlp_workspace(shape, batch), MP_ERR_WORKSPACE,
+               "mp_mlp_forward: workspace of %zu bytes needed", mlp_workspace(shape, batch));
+  return mlp_forward(shape, w16, params, X, batch, Y, workspace, (hipStream_t)stream);
+}
+
+mp_status mp_mlp_loss_grad(const mp_mlp_shape* shape, const uint16_t* w16, const float* params,
+                           const float* X, const float* Y, int32_t batch, float* grads,
+                           float* loss, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(valid_shape(shape), MP_ERR_ARG, "mp_mlp_loss_grad: invalid shape");
+  MP_CHECK_ARG(batch >= 1, MP_ERR_ARG, "mp_mlp_loss_grad: batch must be >= 1");
+  MP_CHECK_ARG(w16 && params && X && Y && grads && loss, MP_ERR_ARG,
+               "mp_mlp_loss_grad: null pointer argument");
+  MP_CHECK_ARG(workspace && ws_bytes >= mlp_workspace(shape, batch), MP_ERR_WORKSPACE,
+               "mp_mlp_loss_grad: workspace of %zu bytes needed", mlp_workspace(shape, batch));
+  return mlp_loss_grad(shape, w16, params, X, Y, batch, grads, loss, workspace,
+                       (hipStream_t)stream);
+}
+
+mp_status mp_mlp_adam(const mp_mlp_shape* shape, float* params, const float* grads, float* m,
+                      float* v, uint16_t* w16, float lr, float beta1, float beta2, float eps,
+                      int32_t step, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(valid_shape(shape), MP_ERR_ARG, "mp_mlp_adam: invalid shape");
+  MP_CHECK_ARG(params && grads && m && v && w16, MP_ERR_ARG, "mp_mlp_adam: null pointer argument");
+  MP_CHECK_ARG(step >= 1 && lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f &&
+                   beta2 < 1.0f && eps > 0.0f,
+               MP_ERR_ARG, "mp_mlp_adam: invalid hyper-parameters");
+  return mlp_adam_launch(mlp_param_count(shape), params, grads, m, v, w16, lr, beta1, beta2, eps,
+                         step, (hipStream_t)stream);
 }
 
 const char* mp_last_error(void) { return g_err; }
