@@ -76,10 +76,46 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
 
 // ---------------------------------------------------------------- tile order
 
-// Maps the linear block id to (tile_m, tile_n).  Blocks are dispatched to the
-// XCDs round-robin, so block b runs on XCD b % 8; each XCD gets one
-// contiguous range of the grouped tile sequence.
-__device__ inline bool tile_of_block(int tiles_m, int tiles_n, int& tm, int& tn) {
+// Tile order.  Blocks are dispatched to the XCDs round-robin, so block b
+// runs on XCD b % 8 and, with one workgroup per CU, the 32 blocks
+// b / 8 = 32 s .. 32 s + 31 of every XCD run together in "step" s.
+//
+// Order 1 (default): in each step all eight XCDs work on the same group of 8
+// row tiles, each XCD on its own 4 column tiles, and consecutive steps move
+// along the columns.  The A rows of a group are then shared by every XCD
+// through the infinity cache (MALL) and fetched from HBM about once per
+// group, instead of once per XCD and column block.
+// Order 0: each XCD takes one contiguous range of a sequence grouped by 8
+// row tiles (XCD-local L2 reuse only).
+constexpr int kStepRows = 8, kStepColsPerXcd = 4;
+
+static int tile_order() {
+  static int v = [] {
+    const char* e = getenv("MPGBS_TILE_ORDER");
+    return e ? atoi(e) : 1;
+  }();
+  return v;
+}
+
+__device__ inline bool tile_of_block_mall(int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int b = blockIdx.x, x = b % kXcds, q = b / kXcds;
+  const int per_xcd = kStepRows * kStepColsPerXcd;   // 32 blocks of one XCD per step
+  const int s = q / per_xcd, j = q % per_xcd;
+  const int cols_per_step = kXcds * kStepColsPerXcd;  // 32 column tiles per step
+  const int n_cg = (tiles_n + cols_per_step - 1) / cols_per_step;
+  const int rg = s / n_cg, cg = s % n_cg;
+  tm = rg * kStepRows + j % kStepRows;
+  tn = cg * cols_per_step + x * kStepColsPerXcd + j / kStepRows;
+  return tm < tiles_m && tn < tiles_n;
+}
+
+__host__ __device__ inline int mall_grid_blocks(int tiles_m, int tiles_n) {
+  const int n_cg = (tiles_n + kXcds * kStepColsPerXcd - 1) / (kXcds * kStepColsPerXcd);
+  const int n_rg = (tiles_m + kStepRows - 1) / kStepRows;
+  return n_rg * n_cg * kXcds * kStepRows * kStepColsPerXcd;
+}
+
+__device__ inline bool tile_of_block_grouped(int tiles_m, int tiles_n, int& tm, int& tn) {
   int total = tiles_m * tiles_n;
   int per_xcd = (total + kXcds - 1) / kXcds;
   int b = blockIdx.x;
@@ -93,6 +129,11 @@ __device__ inline bool tile_of_block(int tiles_m, int tiles_n, int& tm, int& tn)
   tm = first_m + r % gsize;
   tn = r / gsize;
   return true;
+}
+
+__device__ inline bool tile_of_block(int tiles_m, int tiles_n, int order, int& tm, int& tn) {
+  return order == 1 ? tile_of_block_mall(tiles_m, tiles_n, tm, tn)
+                    : tile_of_block_grouped(tiles_m, tiles_n, tm, tn);
 }
 
 // ---------------------------------------------------------------- loaders
@@ -141,13 +182,13 @@ struct Slab {
 __global__ __launch_bounds__(kThreads) void gemm_f64(const double* __restrict__ A,
                                                      const double* __restrict__ B,
                                                      double* __restrict__ C, int64_t ldm,
-                                                     int64_t ncols) {
+                                                     int64_t ncols, int order) {
   constexpr int BK = 16, LDK = BK + 2;
   __shared__ __attribute__((aligned(16))) double sA[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) double sB[2][BN * LDK];
   const int tiles_m = (int)(2 * ldm / BM), tiles_n = (int)((ncols + BN - 1) / BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -221,13 +262,13 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(const double* __restrict__ 
 __global__ __launch_bounds__(kThreads) void gemm_f32(const float* __restrict__ A,
                                                      const float* __restrict__ B,
                                                      float* __restrict__ C, int64_t ldm,
-                                                     int64_t ncols) {
+                                                     int64_t ncols, int order) {
   constexpr int BK = 32, LDK = BK + 4;
   __shared__ __attribute__((aligned(16))) float sA[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) float sB[2][BN * LDK];
   const int tiles_m = (int)(2 * ldm / BM), tiles_n = (int)((ncols + BN - 1) / BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -301,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f32(const float* __restrict__ A
 __global__ __launch_bounds__(kThreads) void gemm_split_bf16(const uint16_t* __restrict__ A,
                                                             const uint16_t* __restrict__ B,
                                                             float* __restrict__ C, int64_t ldm,
-                                                            int64_t ncols) {
+                                                            int64_t ncols, int order) {
   constexpr int BK = 32, LDK = BK + 8;
   __shared__ __attribute__((aligned(16))) uint16_t sAh[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) uint16_t sAl[2][BM * LDK];
@@ -309,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void gemm_split_bf16(const uint16_t* __re
   __shared__ __attribute__((aligned(16))) uint16_t sBl[2][BN * LDK];
   const int tiles_m = (int)(2 * ldm / BM), tiles_n = (int)((ncols + BN - 1) / BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -429,12 +470,12 @@ template <typename H>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_256(const uint16_t* __restrict__ A,
                                                               const uint16_t* __restrict__ B,
                                                               float* __restrict__ C, int64_t ldm,
-                                                              int64_t ncols, float out_scale) {
+                                                              int64_t ncols, float out_scale, int order) {
   typedef typename SplitMfma<H>::frag frag;
   __shared__ __attribute__((aligned(16))) uint16_t lds[2][4][S_PLANE];
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -556,12 +597,12 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_dma(const uint16_t
                                                                   const uint16_t* __restrict__ B,
                                                                   float* __restrict__ C,
                                                                   int64_t ldm, int64_t ncols,
-                                                                  float out_scale) {
+                                                                  float out_scale, int order) {
   typedef typename SplitMfma<H>::frag frag;
   __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -693,12 +734,12 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_ring(const uint16_
                                                                    const uint16_t* __restrict__ B,
                                                                    float* __restrict__ C,
                                                                    int64_t ldm, int64_t ncols,
-                                                                   float out_scale) {
+                                                                   float out_scale, int order) {
   typedef typename SplitMfma<H>::frag frag;
   __shared__ __attribute__((aligned(1024))) uint16_t lds[R_STAGES][4][R_PLANE];
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -967,11 +1008,11 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
                                                                  const uint16_t* __restrict__ B,
                                                                  float* __restrict__ C,
                                                                  int64_t ldm, int64_t ncols,
-                                                                 float out_scale) {
+                                                                 float out_scale, int order) {
   __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
   split_pp_tile<H>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN, out_scale);
 }
 
@@ -1021,8 +1062,10 @@ static int split_variant() {
 }
 
 static int grid_tiles(int64_t ldm, int64_t ncols, int bm, int bn) {
-  int64_t tiles = (2 * ldm / bm) * ((ncols + bn - 1) / bn);
-  int64_t per = (tiles + kXcds - 1) / kXcds;
+  const int tiles_m = (int)(2 * ldm / bm), tiles_n = (int)((ncols + bn - 1) / bn);
+  if (tile_order() == 1) return mall_grid_blocks(tiles_m, tiles_n);
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  const int64_t per = (tiles + kXcds - 1) / kXcds;
   return (int)(per * kXcds);
 }
 
@@ -1073,21 +1116,21 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
   switch (prec) {
     case MP_FP64:
       hipLaunchKernelGGL(gemm_f64, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const double*)packed, (const double*)ab, (double*)C, ldm, ncols);
+                         (const double*)packed, (const double*)ab, (double*)C, ldm, ncols, tile_order());
       break;
     case MP_FP32:
       hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const float*)packed, (const float*)ab, (float*)C, ldm, ncols);
+                         (const float*)packed, (const float*)ab, (float*)C, ldm, ncols, tile_order());
       break;
     case MP_SPLIT_BF16:
       hipLaunchKernelGGL(gemm_split_256_pp<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                          dim3(kThreads), 0, stream, (const uint16_t*)packed, (const uint16_t*)ab,
-                         (float*)C, ldm, ncols, 1.0f);
+                         (float*)C, ldm, ncols, 1.0f, tile_order());
       break;
     case MP_SPLIT_FP16:
       hipLaunchKernelGGL(gemm_split_256_pp<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                          dim3(kThreads), 0, stream, (const uint16_t*)packed, (const uint16_t*)ab,
-                         (float*)C, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
+                         (float*)C, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)), tile_order());
       break;
   }
   MP_HIP_LAUNCH_CHECK("plan gemm launch");
@@ -1121,13 +1164,13 @@ mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision p
       hipLaunchKernelGGL(pack_transmission<MP_FP64>, dim3(pack_blocks), dim3(256), 0, stream, T, M,
                          ldm, ws, 0);
       hipLaunchKernelGGL(gemm_f64, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const double*)ws, (const double*)ab, (double*)C, ldm, ncols);
+                         (const double*)ws, (const double*)ab, (double*)C, ldm, ncols, tile_order());
       break;
     case MP_FP32:
       hipLaunchKernelGGL(pack_transmission<MP_FP32>, dim3(pack_blocks), dim3(256), 0, stream, T, M,
                          ldm, ws, 0);
       hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const float*)ws, (const float*)ab, (float*)C, ldm, ncols);
+                         (const float*)ws, (const float*)ab, (float*)C, ldm, ncols, tile_order());
       break;
     case MP_SPLIT_BF16:
       hipLaunchKernelGGL(pack_transmission<MP_SPLIT_BF16>, dim3(pack_blocks), dim3(256), 0, stream,
@@ -1135,19 +1178,19 @@ mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision p
       if (split_variant() == 3)
         hipLaunchKernelGGL(gemm_split_256_pp<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f);
+                           (float*)C, ldm, ncols, 1.0f, tile_order());
       else if (split_variant() == 2)
         hipLaunchKernelGGL(gemm_split_256_ring<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f);
+                           (float*)C, ldm, ncols, 1.0f, tile_order());
       else if (split_variant() == 1)
         hipLaunchKernelGGL(gemm_split_256_dma<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f);
+                           (float*)C, ldm, ncols, 1.0f, tile_order());
       else
         hipLaunchKernelGGL(gemm_split_256<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f);
+                           (float*)C, ldm, ncols, 1.0f, tile_order());
       break;
     case MP_SPLIT_FP16: {
       const int e = fp16_scale_exp(M);
@@ -1156,19 +1199,19 @@ mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision p
       if (split_variant() == 3)
         hipLaunchKernelGGL(gemm_split_256_pp<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
       else if (split_variant() == 2)
         hipLaunchKernelGGL(gemm_split_256_ring<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
       else if (split_variant() == 1)
         hipLaunchKernelGGL(gemm_split_256_dma<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
       else
         hipLaunchKernelGGL(gemm_split_256<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
                            dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e));
+                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
       break;
     }
     default:
