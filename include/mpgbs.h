@@ -283,11 +283,13 @@ mp_status mp_mlp_loss_grad(const mp_mlp_shape* shape, const uint16_t* w16, const
                            const float* X, const float* Y, int32_t batch, float* grads,
                            float* loss, void* workspace, size_t ws_bytes, void* stream);
 
-/* One Adam step (bias-corrected, step >= 1) on params with moments m, v;
+/* One Adam step (bias-corrected, step >= 1) with decoupled weight decay on
+ * params with moments m, v:
+ *   p -= lr * (m_hat / (sqrt(v_hat) + eps) + weight_decay * p);
  * refreshes w16. */
 mp_status mp_mlp_adam(const mp_mlp_shape* shape, float* params, const float* grads, float* m,
                       float* v, uint16_t* w16, float lr, float beta1, float beta2, float eps,
-                      int32_t step, void* stream);
+                      float weight_decay, int32_t step, void* stream);
 
 /* Message of the calling thread's last non-MP_OK status ("" if none). */
 const char* mp_last_error(void);

@@ -90,7 +90,8 @@ def load() -> ctypes.CDLL:
         "mp_mlp_loss_grad": (ctypes.c_int, [ctypes.POINTER(MlpShape), vp, vp, vp, vp, c_i32, vp, vp,
                                             vp, sz, vp]),
         "mp_mlp_adam": (ctypes.c_int, [ctypes.POINTER(MlpShape), vp, vp, vp, vp, vp, ctypes.c_float,
-                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, c_i32, vp]),
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       c_i32, vp]),
         "mp_last_error": (ctypes.c_char_p, []),
         "mp_version": (ctypes.c_char_p, []),
     }

@@ -50,8 +50,8 @@ mp_status mlp_loss_grad(const mp_mlp_shape* s, const uint16_t* w16, const float*
                         const float* X, const float* Y, int32_t batch, float* grads, float* loss,
                         void* ws, hipStream_t st);
 mp_status mlp_adam_launch(int64_t n, float* params, const float* grads, float* m, float* v,
-                          uint16_t* w16, float lr, float b1, float b2, float eps, int32_t step,
-                          hipStream_t st);
+                          uint16_t* w16, float lr, float b1, float b2, float eps, float wd,
+                          int32_t step, hipStream_t st);
 mp_status mlp_round_launch(int64_t n, const float* params, uint16_t* w16, hipStream_t st);
 
 static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -234,15 +234,15 @@ mp_status mp_mlp_loss_grad(const mp_mlp_shape* shape, const uint16_t* w16, const
 
 mp_status mp_mlp_adam(const mp_mlp_shape* shape, float* params, const float* grads, float* m,
                       float* v, uint16_t* w16, float lr, float beta1, float beta2, float eps,
-                      int32_t step, void* stream) {
+                      float weight_decay, int32_t step, void* stream) {
   clear_error();
   MP_CHECK_ARG(valid_shape(shape), MP_ERR_ARG, "mp_mlp_adam: invalid shape");
   MP_CHECK_ARG(params && grads && m && v && w16, MP_ERR_ARG, "mp_mlp_adam: null pointer argument");
   MP_CHECK_ARG(step >= 1 && lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f &&
-                   beta2 < 1.0f && eps > 0.0f,
+                   beta2 < 1.0f && eps > 0.0f && weight_decay >= 0.0f,
                MP_ERR_ARG, "mp_mlp_adam: invalid hyper-parameters");
   return mlp_adam_launch(mlp_param_count(shape), params, grads, m, v, w16, lr, beta1, beta2, eps,
-                         step, (hipStream_t)stream);
+                         weight_decay, step, (hipStream_t)stream);
 }
 
 const char* mp_last_error(void) { return g_err; }

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void mlp_mse(const float* __restrict__ Yp,
 
 __global__ void mlp_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g,
                          float* __restrict__ m, float* __restrict__ v, uint16_t* __restrict__ p16,
-                         float lr, float b1, float b2, float eps, float c1, float c2) {
+                         float lr, float b1, float b2, float eps, float wd, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -114,7 +114,8 @@ __global__ void mlp_adam(int64_t n, float* __restrict__ p, const float* __restri
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  // Adam with decoupled weight decay
+  const float pi = p[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
   p[i] = pi;
   p16[i] = to_bf16(pi);
 }
@@ -221,11 +222,11 @@ mp_status mlp_loss_grad(const mp_mlp_shape* s, const uint16_t* w16, const float*
 }
 
 mp_status mlp_adam_launch(int64_t n, float* params, const float* grads, float* m, float* v,
-                          uint16_t* w16, float lr, float b1, float b2, float eps, int32_t step,
-                          hipStream_t st) {
+                          uint16_t* w16, float lr, float b1, float b2, float eps, float wd,
+                          int32_t step, hipStream_t st) {
   const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
   hipLaunchKernelGGL(mlp_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, params,
-                     grads, m, v, w16, lr, b1, b2, eps, c1, c2);
+                     grads, m, v, w16, lr, b1, b2, eps, wd, c1, c2);
   MP_HIP_LAUNCH_CHECK("mlp adam launch");
   return MP_OK;
 }

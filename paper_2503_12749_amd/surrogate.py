@@ -2,20 +2,21 @@
 
 A 4-layer MLP (5 -> 256 -> 256 -> 256 -> 8, SiLU, BF16 weight copies, FP32
 accumulation) maps sweep parameters (modes M, transmission t, mean and spread
-of the squeezing profile, number of bins d) to the first eight cumulants of
-the photon count of the first of d equal mode bins, per mode of that bin.
-Training data come from the method itself (CountsPipeline runs); training,
-inference and the Adam updates run in the library's HIP kernels
-(mp_mlp_*).  Screening: the network ranks candidate squeezing profiles at a
-size outside its training range, and the method, run on the selected
-candidates, judges the predictions and replaces any that miss.
-
-Cumulants per mode of a bin are size-independent to leading order (the count
-of a large bin is a sum of many weakly dependent contributions), which is what
-lets a network trained at M <= 2000 screen at M = 8000.
+of the squeezing profile, number of equal bins d) to the first four cumulants
+per mode of two counts: that of the first bin (M / d modes) and the total.
+Each target is a ratio to the value it would have for independent modes (the
+single-mode photon-number law of a squeezed vacuum after uniform loss t^2,
+averaged over the run's squeezing profile), so the network learns the
+correction that the network's mode correlations make, a number of order one
+whose dependence on M is weak.  Training data come from the method itself
+(CountsPipeline runs); training, inference and the Adam updates run in the
+library's HIP kernels (mp_mlp_*).  Screening: the network ranks candidate
+squeezing profiles at a size outside its training range, and the method, run
+on the selected candidates, judges the predictions and replaces any that
+miss.
 
 Run as a module to generate data, train and screen:
-    python -m paper_2503_12749_amd.surrogate --sweeps 20000 --E 10000
+    python -m paper_2503_12749_amd.surrogate --sweeps 4000 --E 4096
 """
 from __future__ import annotations
 
@@ -31,35 +32,71 @@ from . import CountsPipeline, _lib, _ptr, _stream
 from ._lib import MlpShape
 
 WIDTH = (5, 256, 256, 256, 8)
-N_CUM = 8
+N_CUM = 4           # cumulants per count
+TRUNC_SIGMA = 7.0   # cumulants are taken over mean +- 7 sd of the distribution
 
 
 # ---------------------------------------------------------------- features / targets
 
 def features(M, t, rbar, sr, d):
-    """Network inputs, each of order one."""
-    return np.array([math.log(M) / math.log(2000.0), (t - 0.9) * 10.0, rbar - 1.0, sr * 3.0,
-                     1.0 / d], dtype=np.float64)
+    """Network inputs, each of order one; 1/sqrt(M) is the scale of the
+    finite-size corrections."""
+    return np.array([10.0 / math.sqrt(M), (t - 0.9) * 10.0, rbar - 1.0, sr * 3.0, 1.0 / d],
+                    dtype=np.float64)
 
 
-def cumulants_from_distribution(m, P, kmax=N_CUM):
-    """Cumulants kappa_1..kappa_kmax of a count distribution given on counts m
-    (central moments, then the moment-cumulant recursion)."""
-    P = np.asarray(P, dtype=np.float64)
+def independent_mode_baseline(t, r, d):
+    """Per-mode mean and variances of the counts for independent modes.
+
+    A squeezed vacuum of squeezing r has mean N = sinh^2 r and photon-number
+    variance 2N(N+1); after uniform loss t^2 a mode's count has mean t^2 N and
+    variance t^2 N + t^4 N (2N + 1).  For the bin of M/d modes the excess
+    term is diluted by the fraction of each input's light that stays in the
+    bin (1/d for a uniform spread).  Returns (mean, var_bin, var_total) per
+    mode, averaged over the profile r."""
+    N = np.sinh(np.asarray(r, dtype=np.float64)) ** 2
+    EN, EN2 = float(N.mean()), float((N * (2.0 * N + 1.0)).mean())
+    t2 = t * t
+    return t2 * EN, t2 * EN + t2 * t2 * EN2 / d, t2 * EN + t2 * t2 * EN2
+
+
+def cumulants(m, P, kmax=N_CUM, trunc=TRUNC_SIGMA):
+    """kappa_1..kappa_kmax (kmax <= 4) of a count distribution P on counts m,
+    over the counts within trunc standard deviations of the mean (outside that
+    range the estimate holds only sampling noise)."""
     m = np.asarray(m, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
     P = P / P.sum()
     mu = float((m * P).sum())
-    c = [1.0, 0.0] + [float(((m - mu) ** k * P).sum()) for k in range(2, kmax + 1)]
-    kap = [0.0, mu]
-    for n in range(2, kmax + 1):
-        v = c[n]
-        for k in range(2, n - 1):
-            v -= math.comb(n - 1, k - 1) * kap[k] * c[n - k]
-        kap.append(v)
-    return np.array(kap[1:])
+    sd = math.sqrt(max(float(((m - mu) ** 2 * P).sum()), 0.0))
+    keep = np.abs(m - mu) <= trunc * sd
+    m, P = m[keep], P[keep] / P[keep].sum()
+    mu = float((m * P).sum())
+    c = [float(((m - mu) ** k * P).sum()) for k in range(5)]
+    kap = [mu, c[2], c[3], c[4] - 3.0 * c[2] ** 2]
+    return np.array(kap[:kmax])
+
+
+def targets(M, t, r, d, kap_bin, kap_tot):
+    """Cumulants per mode over the independent-mode baseline."""
+    mean, vb, vt = independent_mode_baseline(t, r, d)
+    kb = np.asarray(kap_bin) / (M // d)
+    kt = np.asarray(kap_tot) / M
+    return np.array([kb[0] / mean, kb[1] / vb, kb[2] / vb, kb[3] / vb,
+                     kt[0] / mean, kt[1] / vt, kt[2] / vt, kt[3] / vt])
+
+
+def moments_from_targets(M, t, r, d, y):
+    """Inverse of targets(): (bin cumulants, total cumulants) of the counts."""
+    mean, vb, vt = independent_mode_baseline(t, r, d)
+    y = np.asarray(y, dtype=np.float64)
+    kb = np.array([y[0] * mean, y[1] * vb, y[2] * vb, y[3] * vb]) * (M // d)
+    kt = np.array([y[4] * mean, y[5] * vt, y[6] * vt, y[7] * vt]) * M
+    return kb, kt
 
 
 def squeezing_profile(M, rbar, sr, seed):
+    """r_j = clip(rbar + sr w_j, 0.5, 1.5), w_j standard normal (seeded)."""
     rng = np.random.Generator(np.random.Philox(key=[int(seed) & (2**64 - 1), 0x53]))
     return np.clip(rbar + sr * rng.standard_normal(M), 0.5, 1.5)
 
@@ -81,26 +118,40 @@ class MethodRunner:
             self._haar[M] = self.synth.haar_unitary(M, self.seed + M)
         return self._haar[M]
 
-    def run(self, M, t, rbar, sr, d, E, net, n_sub=10, chunk=None):
-        """Cumulants per mode of bin 0 (the first M // d modes) and the run's
-        distribution (m, P, sigma)."""
-        r = squeezing_profile(M, rbar, sr, self.seed * 7919 + net)
+    def profile(self, M, rbar, sr, net):
+        return squeezing_profile(M, rbar, sr, self.seed * 7919 + net)
+
+    def run(self, M, t, rbar, sr, d, E, net, n_sub=8, chunk=None):
+        """One method run: the marginal of bin 0 (the first M // d modes) and
+        the total count from the same samples.  Returns the 8 targets and the
+        two distributions as (m, P, sigma) triples."""
+        r = self.profile(M, rbar, sr, net)
         Mb = M // d
-        bins = np.full(M, -1, dtype=np.int32)
-        bins[:Mb] = 0
-        # rough moments of bin 0 (network correlations ignored, hence the margin)
-        mean, sd = self.synth.uniform_loss_moments(r, t, frac=Mb / M)
-        win = self.synth.count_window(mean, sd * 1.6 + 2.0, nsig=10.0)
+        d_run = 1 if d == 1 else 2
+        bins = np.zeros(M, dtype=np.int32)
+        bins[Mb:] = 1
+        # windows from the independent-mode moments, widened for the
+        # correlations that the network adds
+        spans = [(Mb / M, 1.6)] + ([((M - Mb) / M, 1.6)] if d > 1 else []) + [(1.0, 1.2)]
+        wins = []
+        for frac, widen in spans:
+            mean, sd = self.synth.uniform_loss_moments(r, t, frac=frac)
+            wins.append(self.synth.count_window(mean, sd * widen + 2.0, nsig=10.0))
         ns = E // n_sub
         E = ns * n_sub  # whole sub-ensembles only
         chunk = min(chunk or E, E)
         p = CountsPipeline(t * self.haar(M), r, prec=self.prec, seed=self.seed, net=net,
-                           bin_of_mode=bins, d=1, windows=[win], n_sub=n_sub,
-                           samples_per_sub=ns, chunk=chunk, device=self.device)
+                           bin_of_mode=bins, d=d_run, mode="marginals_and_total", windows=wins,
+                           n_sub=n_sub, samples_per_sub=ns, chunk=chunk, device=self.device)
         p.run(E)
         P, _, s = p.result()
-        m = np.arange(win[0], win[0] + win[1])
-        return cumulants_from_distribution(m, P) / Mb, (m, P, s)
+        out, off = [], 0
+        for lo, K in wins:
+            out.append((np.arange(lo, lo + K), P[off: off + K], s[off: off + K]))
+            off += K
+        kb = cumulants(out[0][0], out[0][1])
+        kt = cumulants(out[-1][0], out[-1][1])
+        return targets(M, t, r, d, kb, kt), (out[0], out[-1])
 
 
 def sample_sweeps(n, rng, M_range=(100, 2000), t_range=(0.8, 0.99), bins=(1, 2, 4),
@@ -119,12 +170,12 @@ def sample_sweeps(n, rng, M_range=(100, 2000), t_range=(0.8, 0.99), bins=(1, 2, 
     return out
 
 
-def generate(runner, sweeps, E, log_every=0):
+def generate(runner, sweeps, E, net0=0, log_every=0):
     X = np.stack([features(*s) for s in sweeps])
-    Y = np.empty((len(sweeps), N_CUM))
+    Y = np.empty((len(sweeps), 2 * N_CUM))
     t0 = time.perf_counter()
     for i, s in enumerate(sweeps):
-        Y[i], _ = runner.run(*s, E=E, net=i)
+        Y[i], _ = runner.run(*s, E=E, net=net0 + i)
         if log_every and (i + 1) % log_every == 0:
             print(f"[surrogate] {i + 1}/{len(sweeps)} sweeps, {time.perf_counter() - t0:.1f} s",
                   flush=True)
@@ -180,7 +231,7 @@ class Mlp:
                                         _ptr(self.ws), self.ws.numel(), _stream(None)))
         return float(self.loss.item()), self.grads.cpu().numpy().astype(np.float64)
 
-    def step_raw(self, Xd, Yd, batch, lr):
+    def step_raw(self, Xd, Yd, batch, lr, weight_decay=0.0):
         lib = _lib.load()
         _lib.check(lib.mp_mlp_loss_grad(ctypes.byref(self.shape), _ptr(self.w16), _ptr(self.params),
                                         _ptr(Xd), _ptr(Yd), batch, _ptr(self.grads), _ptr(self.loss),
@@ -188,7 +239,7 @@ class Mlp:
         self.step_count += 1
         _lib.check(lib.mp_mlp_adam(ctypes.byref(self.shape), _ptr(self.params), _ptr(self.grads),
                                    _ptr(self.m), _ptr(self.v), _ptr(self.w16), lr, 0.9, 0.999, 1e-8,
-                                   self.step_count, _stream(None)))
+                                   weight_decay, self.step_count, _stream(None)))
 
     def predict_raw(self, X):
         lib = _lib.load()
@@ -203,7 +254,11 @@ class Mlp:
         return out
 
     # normalised interface
-    def fit(self, X, Y, steps=3000, batch=256, lr=2e-3, seed=0, log_every=0):
+    def fit(self, X, Y, steps=300, batch=256, lr=2e-3, weight_decay=1.0, seed=0, log_every=0):
+        """Mini-batch Adam with decoupled weight decay and a cosine learning
+        rate.  The sweeps are noisy method estimates and the targets vary
+        slowly, so training is short and strongly regularised: longer runs fit
+        the noise and extrapolate worse in M."""
         self.x_mean, self.x_std = X.mean(0), X.std(0) + 1e-8
         self.y_mean, self.y_std = Y.mean(0), Y.std(0) + 1e-12
         Xn = (X - self.x_mean) / self.x_std
@@ -215,7 +270,7 @@ class Mlp:
         for s in range(steps):
             idx = self.torch.from_numpy(rng.choice(len(X), batch, replace=False)).to(self.device)
             lr_s = lr * 0.5 * (1 + math.cos(math.pi * s / steps))
-            self.step_raw(Xd[idx].contiguous(), Yd[idx].contiguous(), batch, lr_s)
+            self.step_raw(Xd[idx].contiguous(), Yd[idx].contiguous(), batch, lr_s, weight_decay)
             if log_every and (s % log_every == 0 or s == steps - 1):
                 hist.append((s, float(self.loss.item())))
         return hist
@@ -227,28 +282,34 @@ class Mlp:
 
 # ---------------------------------------------------------------- screening
 
-def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_sigma=4.0):
-    """Ranks candidate (rbar, sr) profiles by predicted mean count per mode
-    closest to the middle of the candidates' range, runs the method on the
-    `top` best, and keeps the method's value wherever the prediction misses
-    by more than tol_sigma of the method's error."""
-    X = np.stack([features(M, t, rb, sr, d) for rb, sr in candidates])
+def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_sigma=4.0, net0=100000):
+    """Predicts the bin-0 cumulants of every candidate (rbar, sr) profile,
+    selects the `top` candidates whose Fano factor (variance / mean) is
+    closest to the middle of the predicted range, runs the method on them,
+    and keeps the method's value wherever the predicted mean misses by more
+    than tol_sigma of the method's own error."""
+    profs = [runner.profile(M, rb, sr, net0 + q) for q, (rb, sr) in enumerate(candidates)]
     t0 = time.perf_counter()
-    pred = mlp.predict(X)
+    X = np.stack([features(M, t, rb, sr, d) for rb, sr in candidates])
+    y = mlp.predict(X)
+    mom = [moments_from_targets(M, t, r, d, yq) for r, yq in zip(profs, y)]
     t_pred = time.perf_counter() - t0
-    target = 0.5 * (pred[:, 0].min() + pred[:, 0].max())
-    order = np.argsort(np.abs(pred[:, 0] - target))[:top]
+    fano = np.array([kb[1] / kb[0] for kb, _ in mom])
+    target = 0.5 * (fano.min() + fano.max())
+    order = np.argsort(np.abs(fano - target))[:top]
     judged = []
     t0 = time.perf_counter()
     for q in order:
         rb, sr = candidates[q]
-        y, (m, P, s) = runner.run(M, t, rb, sr, d, E=E_judge, net=100000 + int(q),
-                                  chunk=min(E_judge, 65536), n_sub=max(2, E_judge // 8192))
-        Mb = M // d
-        sig_mean = float(np.sqrt(((m - y[0] * Mb) ** 2 * s ** 2).sum())) / Mb
-        miss = abs(pred[q, 0] - y[0]) > tol_sigma * max(sig_mean, 1e-12)
-        judged.append(dict(candidate=[rb, sr], predicted=pred[q].tolist(), method=y.tolist(),
-                           sigma_mean_per_mode=sig_mean, fallback=bool(miss)))
+        yq, ((m, P, s), _) = runner.run(M, t, rb, sr, d, E=E_judge, net=net0 + int(q),
+                                        chunk=min(E_judge, 65536), n_sub=max(2, E_judge // 8192))
+        kb, _ = moments_from_targets(M, t, profs[q], d, yq)
+        pb, _ = mom[q]
+        sig_mean = float(np.sqrt(((m - kb[0]) ** 2 * s ** 2).sum()))
+        miss = abs(pb[0] - kb[0]) > tol_sigma * max(sig_mean, 1e-12)
+        judged.append(dict(candidate=[rb, sr], predicted_mean=float(pb[0]),
+                           predicted_var=float(pb[1]), method_mean=float(kb[0]),
+                           method_var=float(kb[1]), sigma_mean=sig_mean, fallback=bool(miss)))
     t_method = time.perf_counter() - t0
     return dict(t_predict_s=t_pred, t_method_s=t_method, n_candidates=len(candidates),
                 judged=judged)
@@ -256,11 +317,11 @@ def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_sigma=4.0):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--sweeps", type=int, default=20000)
-    ap.add_argument("--E", type=int, default=10000)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--sweeps", type=int, default=4000)
+    ap.add_argument("--E", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--screen-M", type=int, default=8000)
-    ap.add_argument("--screen-E", type=int, default=1_000_000)
+    ap.add_argument("--screen-E", type=int, default=1_048_576)
     ap.add_argument("--candidates", type=int, default=256)
     ap.add_argument("--top", type=int, default=8)
     ap.add_argument("--out", default=None)
@@ -277,7 +338,7 @@ def main():
     t_train = time.perf_counter() - t0
     cands = [(float(a), float(b)) for a in np.linspace(0.6, 1.4, 16) for b in np.linspace(0.0, 0.3, 16)]
     cands = cands[: args.candidates]
-    res = screen(mlp, runner, args.screen_M, 0.95, 1, cands, args.screen_E, args.top)
+    res = screen(mlp, runner, args.screen_M, 0.95, 4, cands, args.screen_E, args.top)
     res.update(t_generate_s=t_gen, t_train_s=t_train, loss_history=hist, sweeps=args.sweeps,
                E=args.E)
     text = json.dumps(res, indent=1)
