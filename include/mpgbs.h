@@ -135,6 +135,21 @@ mp_status mp_propagate(int32_t M, int64_t E, const double* T, mp_precision prec,
                        const void* ab, void* C, void* workspace, size_t ws_bytes,
                        void* stream);
 
+/*
+ * The two halves of mp_propagate, for callers that propagate many chunks
+ * through one network: mp_pack_transmission writes the packed operand
+ * [Re T; Im T] in the GEMM's storage precision into `workspace` (same size
+ * and alignment rules as mp_propagate's workspace), and mp_propagate_packed
+ * runs the GEMM of mp_propagate on it.  The workspace must hold the packing
+ * of the same M and prec, written by a call ordered before this one (same
+ * stream, or synchronised); the library cannot check that.  Same layouts of
+ * ab and C as mp_propagate.
+ */
+mp_status mp_pack_transmission(int32_t M, const double* T, mp_precision prec, void* workspace,
+                               size_t ws_bytes, void* stream);
+mp_status mp_propagate_packed(int32_t M, int64_t E, mp_precision prec, const void* ab, void* C,
+                              const void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- S3-S5 */
 
 /* Complex accumulator entries per sub-ensemble for a bin layout:

@@ -17,7 +17,7 @@ from ._lib import BIN_MODES, ESTIMATORS, MPError, PRECISIONS, i32_array
 
 __all__ = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
-    "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
+    "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
     "mp_counts_finalize", "mp_finalize_workspace", "mp_version", "CountsPipeline", "Plan", "MPError",
 ]
 
@@ -87,6 +87,18 @@ def mp_propagate(M, E, T, prec, ab, C, workspace, stream=None):
                                         _stream(stream)))
 
 
+def mp_pack_transmission(M, T, prec, workspace, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().mp_pack_transmission(M, _ptr(T), _prec(prec), _ptr(workspace), nbytes,
+                                                _stream(stream)))
+
+
+def mp_propagate_packed(M, E, prec, ab, C, workspace, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().mp_propagate_packed(M, E, _prec(prec), _ptr(ab), _ptr(C),
+                                               _ptr(workspace), nbytes, _stream(stream)))
+
+
 def mp_binned_counts(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub,
                      samples_per_sub, e0, acc, workspace, stream=None):
     """bin_of_mode, m_lo, K: host integer sequences."""
@@ -110,8 +122,9 @@ def mp_counts_finalize(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigm
 
 class CountsPipeline:
     """Owns the device buffers of one workload and runs it chunk by chunk:
-    mp_sample -> mp_propagate -> mp_binned_counts per chunk, then
-    mp_counts_finalize.  All buffers are allocated once, in __init__."""
+    mp_sample -> mp_propagate_packed -> mp_binned_counts per chunk, then
+    mp_counts_finalize.  All buffers are allocated once, in __init__, and T is
+    packed once, on the first chunk after construction."""
 
     def __init__(self, T: np.ndarray, r: np.ndarray, *, prec="fp64", seed: int, net: int = 0,
                  bin_of_mode=None, d: int = 1, mode="joint", windows, n_sub: int,
@@ -138,6 +151,7 @@ class CountsPipeline:
         self.C = torch.empty(mp_c_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
         self.n = torch.empty(self.chunk, dtype=torch.float64, device=dev)
         self.ws_prop = torch.empty(mp_propagate_workspace(self.M, self.prec), dtype=torch.uint8, device=dev)
+        self.packed = False
         self.entries = mp_acc_entries(self.d, self.mode, self.K)
         if self.entries < 0:
             raise MPError(-1, "invalid bin layout")
@@ -160,8 +174,11 @@ class CountsPipeline:
 
     def run_chunk(self, g0: int, E: int, stream=None):
         assert 1 <= E <= self.chunk
+        if not self.packed:
+            mp_pack_transmission(self.M, self.T, self.prec, self.ws_prop, stream)
+            self.packed = True
         mp_sample(self.M, g0, E, self.r, self.seed, self.net, self.prec, self.ab, self.n, stream)
-        mp_propagate(self.M, E, self.T, self.prec, self.ab, self.C, self.ws_prop, stream)
+        mp_propagate_packed(self.M, E, self.prec, self.ab, self.C, self.ws_prop, stream)
         self.counts_chunk(g0, E, stream)
 
     def counts_chunk(self, g0: int, E: int, stream=None):

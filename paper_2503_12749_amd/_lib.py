@@ -19,7 +19,7 @@ MP_MAX_RUNS = 16
 
 EXPORTS = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
-    "mp_propagate", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
+    "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
     "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
     "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_destroy",
     "mp_mlp_param_count", "mp_mlp_workspace", "mp_mlp_round", "mp_mlp_forward", "mp_mlp_loss_grad",
@@ -66,6 +66,8 @@ def load() -> ctypes.CDLL:
         "mp_sample": (ctypes.c_int, [c_i32, c_i64, c_i64, vp, c_u64, c_u32, ctypes.c_int, vp, vp, vp]),
         "mp_propagate_workspace": (sz, [c_i32, ctypes.c_int]),
         "mp_propagate": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, vp, vp, vp, sz, vp]),
+        "mp_pack_transmission": (ctypes.c_int, [c_i32, vp, ctypes.c_int, vp, sz, vp]),
+        "mp_propagate_packed": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, vp, vp, vp, sz, vp]),
         "mp_acc_entries": (c_i64, [c_i32, ctypes.c_int, i32p]),
         "mp_binned_workspace": (sz, [c_i32, ctypes.c_int, i32p, c_i64, c_i32, c_i64, c_i64]),
         "mp_binned_counts": (ctypes.c_int, [c_i32, c_i64, vp, vp, ctypes.c_int, ctypes.c_int, c_i32,

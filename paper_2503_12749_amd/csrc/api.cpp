@@ -27,6 +27,10 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
                         uint32_t net, mp_precision prec, void* ab, double* n_out,
                         hipStream_t stream);
 size_t propagate_workspace(int32_t M, mp_precision prec);
+mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
+                      hipStream_t stream);
+mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                             const void* ab, void* C, hipStream_t stream);
 mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision prec,
                            const void* ab, void* C, void* ws, hipStream_t stream);
 int64_t acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K);
@@ -117,6 +121,37 @@ mp_status mp_propagate(int32_t M, int64_t E, const double* T, mp_precision prec,
                "mp_propagate: workspace of %zu bytes (256-aligned) needed, %zu given", need,
                ws_bytes);
   return propagate_launch(M, E, T, prec, ab, C, workspace, (hipStream_t)stream);
+}
+
+mp_status mp_pack_transmission(int32_t M, const double* T, mp_precision prec, void* workspace,
+                               size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1, MP_ERR_ARG, "mp_pack_transmission: M = %d must be >= 1", M);
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_pack_transmission: unknown precision %d",
+               (int)prec);
+  MP_CHECK_ARG(T, MP_ERR_ARG, "mp_pack_transmission: null pointer argument");
+  const size_t need = propagate_workspace(M, prec);
+  MP_CHECK_ARG(workspace && ws_bytes >= need && aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_pack_transmission: workspace of %zu bytes (256-aligned) needed, %zu given",
+               need, ws_bytes);
+  return pack_launch(M, T, prec, workspace, (hipStream_t)stream);
+}
+
+mp_status mp_propagate_packed(int32_t M, int64_t E, mp_precision prec, const void* ab, void* C,
+                              const void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1, MP_ERR_ARG, "mp_propagate_packed: M = %d must be >= 1", M);
+  MP_CHECK_ARG(E >= 1, MP_ERR_ARG, "mp_propagate_packed: E = %lld must be >= 1", (long long)E);
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_propagate_packed: unknown precision %d",
+               (int)prec);
+  MP_CHECK_ARG(ab && C, MP_ERR_ARG, "mp_propagate_packed: null pointer argument");
+  MP_CHECK_ARG(aligned(ab, 16) && aligned(C, 16), MP_ERR_ARG,
+               "mp_propagate_packed: ab and C must be 16-byte aligned");
+  const size_t need = propagate_workspace(M, prec);
+  MP_CHECK_ARG(workspace && ws_bytes >= need && aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_propagate_packed: packed workspace of %zu bytes (256-aligned) needed, %zu given",
+               need, ws_bytes);
+  return gemm_packed_launch(M, E, workspace, prec, ab, C, (hipStream_t)stream);
 }
 
 int64_t mp_acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K) {

@@ -1105,11 +1105,31 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
                          M, ldm, packed, fp16_scale_exp(M));
       break;
   }
-  MP_HIP_LAUNCH_CHECK("plan pack launch");
+  MP_HIP_LAUNCH_CHECK("transmission pack launch");
   return MP_OK;
 }
 
 // GEMM on an already packed operand (one network).
+template <typename H>
+static void split_gemm(int variant, int grid, hipStream_t stream, const void* packed,
+                       const void* ab, void* C, int64_t ldm, int64_t ncols, float scale) {
+  const uint16_t* A = (const uint16_t*)packed;
+  const uint16_t* B = (const uint16_t*)ab;
+  float* Cf = (float*)C;
+  if (variant == 3)
+    hipLaunchKernelGGL(gemm_split_256_pp<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf, ldm,
+                       ncols, scale, tile_order());
+  else if (variant == 2)
+    hipLaunchKernelGGL(gemm_split_256_ring<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf,
+                       ldm, ncols, scale, tile_order());
+  else if (variant == 1)
+    hipLaunchKernelGGL(gemm_split_256_dma<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf,
+                       ldm, ncols, scale, tile_order());
+  else
+    hipLaunchKernelGGL(gemm_split_256<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf, ldm,
+                       ncols, scale, tile_order());
+}
+
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
                              const void* ab, void* C, hipStream_t stream) {
   const int64_t ldm = ld_modes(M), ncols = 2 * E;
@@ -1123,17 +1143,15 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
                          (const float*)packed, (const float*)ab, (float*)C, ldm, ncols, tile_order());
       break;
     case MP_SPLIT_BF16:
-      hipLaunchKernelGGL(gemm_split_256_pp<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                         dim3(kThreads), 0, stream, (const uint16_t*)packed, (const uint16_t*)ab,
-                         (float*)C, ldm, ncols, 1.0f, tile_order());
+      split_gemm<__bf16>(split_variant(), grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab,
+                         C, ldm, ncols, 1.0f);
       break;
     case MP_SPLIT_FP16:
-      hipLaunchKernelGGL(gemm_split_256_pp<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                         dim3(kThreads), 0, stream, (const uint16_t*)packed, (const uint16_t*)ab,
-                         (float*)C, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)), tile_order());
+      split_gemm<_Float16>(split_variant(), grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab,
+                           C, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
       break;
   }
-  MP_HIP_LAUNCH_CHECK("plan gemm launch");
+  MP_HIP_LAUNCH_CHECK("mp_propagate gemm launch");
   return MP_OK;
 }
 
@@ -1155,71 +1173,9 @@ mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_item
 
 mp_status propagate_launch(int32_t M, int64_t E, const double* T, mp_precision prec,
                            const void* ab, void* C, void* ws, hipStream_t stream) {
-  const int64_t ldm = ld_modes(M);
-  const int64_t ncols = 2 * E;
-  const int64_t pack_total = 2 * ldm * ldm;
-  const int pack_blocks = (int)((pack_total + 255) / 256);
-  switch (prec) {
-    case MP_FP64:
-      hipLaunchKernelGGL(pack_transmission<MP_FP64>, dim3(pack_blocks), dim3(256), 0, stream, T, M,
-                         ldm, ws, 0);
-      hipLaunchKernelGGL(gemm_f64, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const double*)ws, (const double*)ab, (double*)C, ldm, ncols, tile_order());
-      break;
-    case MP_FP32:
-      hipLaunchKernelGGL(pack_transmission<MP_FP32>, dim3(pack_blocks), dim3(256), 0, stream, T, M,
-                         ldm, ws, 0);
-      hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const float*)ws, (const float*)ab, (float*)C, ldm, ncols, tile_order());
-      break;
-    case MP_SPLIT_BF16:
-      hipLaunchKernelGGL(pack_transmission<MP_SPLIT_BF16>, dim3(pack_blocks), dim3(256), 0, stream,
-                         T, M, ldm, ws, 0);
-      if (split_variant() == 3)
-        hipLaunchKernelGGL(gemm_split_256_pp<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f, tile_order());
-      else if (split_variant() == 2)
-        hipLaunchKernelGGL(gemm_split_256_ring<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f, tile_order());
-      else if (split_variant() == 1)
-        hipLaunchKernelGGL(gemm_split_256_dma<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f, tile_order());
-      else
-        hipLaunchKernelGGL(gemm_split_256<__bf16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, 1.0f, tile_order());
-      break;
-    case MP_SPLIT_FP16: {
-      const int e = fp16_scale_exp(M);
-      hipLaunchKernelGGL(pack_transmission<MP_SPLIT_FP16>, dim3(pack_blocks), dim3(256), 0, stream,
-                         T, M, ldm, ws, e);
-      if (split_variant() == 3)
-        hipLaunchKernelGGL(gemm_split_256_pp<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
-      else if (split_variant() == 2)
-        hipLaunchKernelGGL(gemm_split_256_ring<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
-      else if (split_variant() == 1)
-        hipLaunchKernelGGL(gemm_split_256_dma<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
-      else
-        hipLaunchKernelGGL(gemm_split_256<_Float16>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const uint16_t*)ws, (const uint16_t*)ab,
-                           (float*)C, ldm, ncols, ldexpf(1.0f, -e), tile_order());
-      break;
-    }
-    default:
-      set_error("mp_propagate: unknown precision %d", (int)prec);
-      return MP_ERR_ARG;
-  }
-  MP_HIP_LAUNCH_CHECK("mp_propagate launch");
-  return MP_OK;
+  const mp_status st = pack_launch(M, T, prec, ws, stream);
+  if (st != MP_OK) return st;
+  return gemm_packed_launch(M, E, ws, prec, ab, C, stream);
 }
 
 }  // namespace mp

@@ -13,9 +13,12 @@
 // pair) with counter (g, p, net, 0) and key (seed, 0); Box-Muller on words
 // (0,1) for mode 2p and (2,3) for mode 2p+1.
 //
-// One wavefront per sample: lanes stride over mode pairs, so the column of
-// the sample (contiguous over modes) is written with coalesced stores, and
-// n = alpha . beta is reduced across the wave with shuffles.
+// One wavefront per group of samples: lanes stride over mode pairs, so each
+// sample's column (contiguous over modes) is written with coalesced stores,
+// and n = alpha . beta is reduced across the wave with shuffles.  The FP64
+// path evaluates Box-Muller in FP64; the FP32 and split paths evaluate the
+// angle in FP32 (error ~1e-7 of the radius, at the level of their storage
+// rounding).
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -51,49 +54,76 @@ __device__ inline void box_muller(uint64_t xe, uint64_t xo, double& w1, double& 
   w2 = rho * s;
 }
 
+// The same transform for the paths that store FP32 or split 16-bit
+// amplitudes.  The radius takes its logarithm in FP64 (u keeps all 53 bits;
+// in FP32 the rounding of u near 1 would swamp -ln u).  The angle
+// 2 pi v = pi x 2^-52 (x = xo >> 11) is reduced on the integer: its top two
+// bits give the quarter turn q, the other 51 bits the fraction f in [0, 1/2)
+// with angle = q pi/2 + pi f, so the FP32 sincospi sees f to 2^-25 absolute
+// (angle error ~1e-7 rad).
+__device__ inline void box_muller_f32(uint64_t xe, uint64_t xo, float& w1, float& w2) {
+  const double u = (double)((xe >> 11) + 1ull) * 0x1p-53;
+  const float rho = sqrtf((float)(-2.0 * log(u)));
+  const uint64_t x = xo >> 11;
+  const uint32_t q = (uint32_t)(x >> 51);
+  const float f = (float)(x & ((1ull << 51) - 1ull)) * 0x1p-52f;
+  float s, c;
+  sincospif(f, &s, &c);
+  const float cq = (q & 1u) ? -s : c;  // cos(q pi/2 + pi f) for q = 0, 1
+  const float sq = (q & 1u) ? c : s;
+  const float sign = (q & 2u) ? -1.0f : 1.0f;  // q = 2, 3: half a turn more
+  w1 = rho * (sign * cq);
+  w2 = rho * (sign * sq);
+}
+
 __device__ inline uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-__device__ inline double bf16_val(uint16_t h) { return (double)__uint_as_float(((uint32_t)h) << 16); }
+__device__ inline float bf16_val(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// Rounds x to the storage precision, stores it, and returns the stored value.
+// Stores the amplitudes of modes (2p, 2p+1) of one column in the storage
+// precision and returns the stored values (hi + lo for the split forms).
+__device__ inline void store_pair_f64(void* ab, int64_t off, double x0, double x1) {
+  typedef __attribute__((ext_vector_type(2))) double d2;
+  *(d2*)((double*)ab + off) = d2{x0, x1};
+}
+
 template <int PREC>
-__device__ inline double store_pair(void* ab, int64_t plane, int64_t off, double x0, double x1,
-                                    double& y1) {
-  if constexpr (PREC == MP_FP64) {
-    typedef __attribute__((ext_vector_type(2))) double d2;
-    *(d2*)((double*)ab + off) = d2{x0, x1};
-    y1 = x1;
-    return x0;
-  } else if constexpr (PREC == MP_FP32) {
+__device__ inline void store_pair_f32(void* ab, int64_t plane, int64_t off, float x0, float x1,
+                                      double& y0, double& y1) {
+  if constexpr (PREC == MP_FP32) {
     typedef __attribute__((ext_vector_type(2))) float f2;
-    const float f0 = (float)x0, f1 = (float)x1;
-    *(f2*)((float*)ab + off) = f2{f0, f1};
-    y1 = f1;
-    return f0;
+    *(f2*)((float*)ab + off) = f2{x0, x1};
+    y0 = x0;
+    y1 = x1;
   } else if constexpr (PREC == MP_SPLIT_BF16) {
-    const uint16_t h0 = bf16_rne((float)x0), h1 = bf16_rne((float)x1);
-    const uint16_t l0 = bf16_rne((float)(x0 - bf16_val(h0)));
-    const uint16_t l1 = bf16_rne((float)(x1 - bf16_val(h1)));
-    uint16_t* p = (uint16_t*)ab;
-    *(uint32_t*)(p + off) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-    *(uint32_t*)(p + plane + off) = (uint32_t)l0 | ((uint32_t)l1 << 16);
-    y1 = bf16_val(h1) + bf16_val(l1);
-    return bf16_val(h0) + bf16_val(l0);
+    // x - hi is exact in FP32 (at most 16 significant bits remain)
+    const uint16_t h0 = bf16_rne(x0), h1 = bf16_rne(x1);
+    const uint16_t l0 = bf16_rne(x0 - bf16_val(h0)), l1 = bf16_rne(x1 - bf16_val(h1));
+    uint16_t* q = (uint16_t*)ab;
+    *(uint32_t*)(q + off) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    *(uint32_t*)(q + plane + off) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    y0 = (double)bf16_val(h0) + (double)bf16_val(l0);
+    y1 = (double)bf16_val(h1) + (double)bf16_val(l1);
   } else {
     const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
-    const _Float16 l0 = (_Float16)(x0 - (double)h0);
-    const _Float16 l1 = (_Float16)(x1 - (double)h1);
-    _Float16* p = (_Float16*)ab;
+    const _Float16 l0 = (_Float16)(x0 - (float)h0), l1 = (_Float16)(x1 - (float)h1);
+    _Float16* q = (_Float16*)ab;
     typedef __attribute__((ext_vector_type(2))) _Float16 h2;
-    *(h2*)(p + off) = h2{h0, h1};
-    *(h2*)(p + plane + off) = h2{l0, l1};
-    y1 = (double)h1 + (double)l1;
-    return (double)h0 + (double)l0;
+    *(h2*)(q + off) = h2{h0, h1};
+    *(h2*)(q + plane + off) = h2{l0, l1};
+    y0 = (double)(float)h0 + (double)(float)l0;
+    y1 = (double)(float)h1 + (double)(float)l1;
   }
 }
+
+// Each wavefront owns kWaveSamples consecutive samples; its lanes stride over
+// mode pairs, so the coefficients c+, c- of a lane's modes are computed once
+// and reused for all of the wave's samples, and every store of one sample's
+// column is coalesced across the wave.
+constexpr int kWaveSamples = 8;
 
 template <int PREC>
 __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t g0, int64_t E,
@@ -101,47 +131,73 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
                                                      uint32_t net, void* __restrict__ ab,
                                                      double* __restrict__ n_out) {
   const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= E) return;
-  const uint64_t g = (uint64_t)(g0 + k);
+  const int64_t k0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kWaveSamples;
+  if (k0 >= E) return;
+  const int nk = (int)(E - k0 < kWaveSamples ? E - k0 : kWaveSamples);
   const int64_t plane = ldm * 2 * E;
-  const int64_t col_a = k * ldm, col_b = (E + k) * ldm;
-  double nsum = 0.0;
+  double nsum[kWaveSamples];
+#pragma unroll
+  for (int s = 0; s < kWaveSamples; ++s) nsum[s] = 0.0;
   for (int64_t p = lane; p < ldm / 2; p += 64) {
     const int64_t j0 = 2 * p;
-    double a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    // c+ = sqrt(e^{2r} - 1) / 2, c- = sqrt(1 - e^{-2r}) / 2; zero on padding
+    double cp0 = 0.0, cm0 = 0.0, cp1 = 0.0, cm1 = 0.0;
     if (j0 < M) {
-      uint64_t c0 = g, c1 = (uint64_t)p, c2 = net, c3 = 0;
-      philox4x64_10(c0, c1, c2, c3, seed, 0);
-      double w1, w2;
-      box_muller(c0, c1, w1, w2);
-      double rj = r[j0];
-      double cp = 0.5 * sqrt(expm1(2.0 * rj)), cm = 0.5 * sqrt(-expm1(-2.0 * rj));
-      a0 = cp * w1 + cm * w2;
-      b0 = cp * w1 - cm * w2;
-      if (j0 + 1 < M) {
-        box_muller(c2, c3, w1, w2);
-        rj = r[j0 + 1];
-        cp = 0.5 * sqrt(expm1(2.0 * rj));
-        cm = 0.5 * sqrt(-expm1(-2.0 * rj));
-        a1 = cp * w1 + cm * w2;
-        b1 = cp * w1 - cm * w2;
+      const double r0 = r[j0];
+      cp0 = 0.5 * sqrt(expm1(2.0 * r0));
+      cm0 = 0.5 * sqrt(-expm1(-2.0 * r0));
+    }
+    if (j0 + 1 < M) {
+      const double r1 = r[j0 + 1];
+      cp1 = 0.5 * sqrt(expm1(2.0 * r1));
+      cm1 = 0.5 * sqrt(-expm1(-2.0 * r1));
+    }
+#pragma unroll
+    for (int s = 0; s < kWaveSamples; ++s) {
+      if (s >= nk) break;
+      const int64_t k = k0 + s;
+      const int64_t col_a = k * ldm + j0, col_b = (E + k) * ldm + j0;
+      uint64_t c0 = (uint64_t)(g0 + k), c1 = (uint64_t)p, c2 = net, c3 = 0;
+      if (j0 < M) philox4x64_10(c0, c1, c2, c3, seed, 0);
+      if constexpr (PREC == MP_FP64) {
+        double w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0;
+        if (j0 < M) {
+          box_muller(c0, c1, w1, w2);
+          if (j0 + 1 < M) box_muller(c2, c3, w3, w4);
+        }
+        const double a0 = cp0 * w1 + cm0 * w2, b0 = cp0 * w1 - cm0 * w2;
+        const double a1 = cp1 * w3 + cm1 * w4, b1 = cp1 * w3 - cm1 * w4;
+        store_pair_f64(ab, col_a, a0, a1);
+        store_pair_f64(ab, col_b, b0, b1);
+        nsum[s] += a0 * b0 + a1 * b1;
+      } else {
+        float w1 = 0.0f, w2 = 0.0f, w3 = 0.0f, w4 = 0.0f;
+        if (j0 < M) {
+          box_muller_f32(c0, c1, w1, w2);
+          if (j0 + 1 < M) box_muller_f32(c2, c3, w3, w4);
+        }
+        const float fp0 = (float)cp0, fm0 = (float)cm0, fp1 = (float)cp1, fm1 = (float)cm1;
+        const float a0 = fp0 * w1 + fm0 * w2, b0 = fp0 * w1 - fm0 * w2;
+        const float a1 = fp1 * w3 + fm1 * w4, b1 = fp1 * w3 - fm1 * w4;
+        double ya0, ya1, yb0, yb1;
+        store_pair_f32<PREC>(ab, plane, col_a, a0, a1, ya0, ya1);
+        store_pair_f32<PREC>(ab, plane, col_b, b0, b1, yb0, yb1);
+        nsum[s] += ya0 * yb0 + ya1 * yb1;
       }
     }
-    double ya1, yb1;
-    const double ya0 = store_pair<PREC>(ab, plane, col_a + j0, a0, a1, ya1);
-    const double yb0 = store_pair<PREC>(ab, plane, col_b + j0, b0, b1, yb1);
-    nsum += ya0 * yb0 + ya1 * yb1;
   }
-  nsum = wave_sum(nsum);
-  if (lane == 0) n_out[k] = nsum;
+#pragma unroll
+  for (int s = 0; s < kWaveSamples; ++s) {
+    const double v = wave_sum(nsum[s]);
+    if (lane == 0 && s < nk) n_out[k0 + s] = v;
+  }
 }
 
 mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint64_t seed,
                         uint32_t net, mp_precision prec, void* ab, double* n_out,
                         hipStream_t stream) {
   const int64_t ldm = ld_modes(M);
-  const int64_t blocks = (E + 3) / 4;
+  const int64_t blocks = (E + 4 * kWaveSamples - 1) / (4 * kWaveSamples);
   if (blocks > 0x7FFFFFFF) {
     set_error("mp_sample: E too large for one launch");
     return MP_ERR_UNSUPPORTED;

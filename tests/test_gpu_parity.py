@@ -211,6 +211,52 @@ def test_reduced_precision_propagation(prec, rel):
     assert np.abs(nS - 0.9025 * n).max() < 50 * rel * np.abs(n).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16"])
+def test_pack_once_then_propagate_matches_propagate(prec):
+    """mp_pack_transmission + mp_propagate_packed give the same bits as
+    mp_propagate, over several tiles with ragged edges."""
+    import paper_2503_12749_amd as mp
+    M, E = 333, 301
+    T = 0.9 * synth.haar_unitary(M, 19)
+    r = np.linspace(0.5, 1.5, M)
+    p = _pipe(T, r, prec=prec, seed=8, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, prec, p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, prec, p.ab, p.C, p.ws_prop)
+    ref = p.C.clone()
+    p.C.zero_()
+    ws = torch.empty_like(p.ws_prop)
+    mp.mp_pack_transmission(M, p.T, prec, ws)
+    mp.mp_propagate_packed(M, E, prec, p.ab, p.C, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(p.C, ref)
+
+
+def test_sampler_fp32_matches_oracle():
+    """The FP32 path draws the same noise and evaluates the Box-Muller angle in
+    FP32: each amplitude within 5e-7 of the scale of its terms (FP32 rounding
+    of the coefficients, the radius and the products, plus an angle error of
+    ~1e-7 rad times the radius), and n equal to the sum over the stored
+    values.  E = 261 leaves a ragged group of samples."""
+    import paper_2503_12749_amd as mp
+    r = np.concatenate([np.linspace(0.2, 1.5, 139), [0.0]])
+    M = r.size
+    p = _pipe(np.eye(M, dtype=np.complex128), r, prec="fp32", seed=77, windows=[(0, 64)],
+              n_sub=1, samples_per_sub=1000, chunk=300)
+    g0, E = 5, 261
+    mp.mp_sample(M, g0, E, p.r, p.seed, 2, "fp32", p.ab, p.n)
+    a_gpu, b_gpu = p.alpha_beta(E)
+    a, b, _ = osamp.sample(r, g0, E, 77, net=2)
+    w1, w2 = osamp.normals(M, g0, E, 77, net=2)
+    cp = np.sqrt(np.expm1(2 * r)) / 2
+    cm = np.sqrt(-np.expm1(-2 * r)) / 2
+    rho = np.hypot(w1, w2)
+    tol = 5e-7 * (cp * np.abs(w1) + cm * np.abs(w2) + (cp + cm) * rho)
+    assert np.all(np.abs(a_gpu - a) <= tol)
+    assert np.all(np.abs(b_gpu - b) <= tol)
+    n_gpu = p.n[:E].cpu().numpy()
+    np.testing.assert_allclose(n_gpu, (a_gpu * b_gpu).sum(1), rtol=1e-12, atol=1e-12)
+
+
 @pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6), ("split_fp16", 1e-6)])
 def test_reduced_precision_counts_within_sigma(prec, floor):
     """M = 300, t = 0.9, r = 1: the reduced-precision estimate differs from the
