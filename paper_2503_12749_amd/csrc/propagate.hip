@@ -852,7 +852,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_ring(const uint16_
 // overlap the second group, so neither the barrier nor the LDS latency
 // leaves the matrix pipe idle for a whole fragment round trip.
 template <typename H>
-__device__ inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
+__device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
                                      const uint16_t* __restrict__ B, float* __restrict__ C,
                                      int64_t ldm, int64_t ncols, int64_t m0, int64_t n0,
                                      float out_scale) {
