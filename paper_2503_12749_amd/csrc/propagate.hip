@@ -1016,6 +1016,149 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
   split_pp_tile<H>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN, out_scale);
 }
 
+// ---------------------------------------------------------------- FP32, 256 x 256
+
+// FP32 twin of the split ping-pong kernel: the same 256 x 256 tile, four
+// waves of 128 x 128, two direct-to-LDS stages and the same swizzled LDS
+// rows (BK = 16 floats = 64 bytes per row), with v_mfma_f32_32x32x2f32.
+// Lane half h supplies k = 8 h + s at step s (s = 0..7) of a slab, the same
+// permutation on both operands; F0 holds steps 0-3 (chunk 2 h) and F1 steps
+// 4-7 (chunk 2 h + 1).  Wave w loads half (w & 1) of operand w >> 1.
+constexpr int F_BK = 16;
+constexpr int F_PLANE = S_BM * F_BK;  // floats of one LDS operand plane
+
+__global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restrict__ A,
+                                                           const float* __restrict__ B,
+                                                           float* __restrict__ C, int64_t ldm,
+                                                           int64_t ncols, int order) {
+  __shared__ __attribute__((aligned(1024))) float lds[2][2][F_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  const int op = wave >> 1, half = wave & 1;
+  const float* src = op == 0 ? A + m0 * ldm : B + n0 * ldm;
+  const int64_t row_limit = op == 0 ? S_BM : ncols - n0;
+  const int lrow = lane >> 2;
+  // lane l writes LDS slot 16 l of each 1 KB block: row 16 q + l / 4 of the
+  // wave's half, slot l % 4, which holds global chunk (l % 4) ^ swz(row)
+  auto issue = [&](int st, int64_t k0) {
+    char* dst = (char*)&lds[st][op][0] + half * (128 * F_BK * 4);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = half * 128 + 16 * q + lrow;
+      const int64_t row = r < row_limit ? r : row_limit - 1;
+      const float* g = src + row * ldm + k0 + (((lane & 3) ^ swz(r)) << 2);
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
+    }
+  };
+  int oa[2][4], ob[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+      oa[s][i] = ra * F_BK + (((2 * lh + s) ^ swz(ra)) << 2);
+      ob[s][i] = rb * F_BK + (((2 * lh + s) ^ swz(rb)) << 2);
+    }
+  f32x4 a0[4], b0[4], a1[4], b1[4];
+  auto read0 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a0[i] = *(const f32x4*)(&lds[st][0][oa[0][i]]);
+      b0[i] = *(const f32x4*)(&lds[st][1][ob[0][i]]);
+    }
+  };
+  auto read1 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a1[i] = *(const f32x4*)(&lds[st][0][oa[1][i]]);
+      b1[i] = *(const f32x4*)(&lds[st][1][ob[1][i]]);
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = (int)(ldm / F_BK);  // >= 8
+  issue(0, 0);
+  wait_vm<0>();
+  barrier_no_fence();
+  issue(1, F_BK);
+  read0(0);
+  constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    // phase A: steps 0-3 on F0 with the reads of F1 threaded between them
+    read1(cur);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i][s], b0[j][s], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 32, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);  // own loads of slab kt + 1 landed, reads of stage cur done
+    barrier_no_fence();
+    __builtin_amdgcn_sched_barrier(0);
+    // phase B: steps 4-7 on F1 with the loads of slab kt + 2 and the reads of
+    // F0 of slab kt + 1 threaded in (the last two slabs repeat the final slab
+    // into the freed stage, in bounds, so the loop has no branches)
+    issue(cur, (int64_t)min(kt + 2, KT - 1) * F_BK);
+    read0(cur ^ 1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[i][s], b1[j][s], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 4, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]};
+      }
+  }
+}
+
 // ---------------------------------------------------------------- grouped
 
 // Persistent grouped launch over many networks: one workgroup per CU walks a
@@ -1057,6 +1200,16 @@ static int split_variant() {
   static int v = [] {
     const char* e = getenv("MPGBS_SPLIT_VARIANT");
     return e ? atoi(e) : 3;
+  }();
+  return v;
+}
+
+// FP32 GEMM variant: 1 = 256 x 256 direct-to-LDS ping-pong (default),
+// 0 = 128 x 128 register staging.
+static int f32_variant() {
+  static int v = [] {
+    const char* e = getenv("MPGBS_F32_VARIANT");
+    return e ? atoi(e) : 1;
   }();
   return v;
 }
@@ -1139,8 +1292,14 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
                          (const double*)packed, (const double*)ab, (double*)C, ldm, ncols, tile_order());
       break;
     case MP_FP32:
-      hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const float*)packed, (const float*)ab, (float*)C, ldm, ncols, tile_order());
+      if (f32_variant() == 1)
+        hipLaunchKernelGGL(gemm_f32_pp, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)), dim3(kThreads), 0,
+                           stream, (const float*)packed, (const float*)ab, (float*)C, ldm, ncols,
+                           tile_order());
+      else
+        hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0,
+                           stream, (const float*)packed, (const float*)ab, (float*)C, ldm, ncols,
+                           tile_order());
       break;
     case MP_SPLIT_BF16:
       split_gemm<__bf16>(split_variant(), grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab,
