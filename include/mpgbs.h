@@ -99,11 +99,14 @@ size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
  *
  *   M      modes, >= 1                 g0     global index of the first sample
  *   E      samples in this call, >= 1  r      device FP64[M], r_j >= 0 (0 = vacuum)
- *   ab     device, mp_ab_bytes(M, E, prec) bytes, column-major with ld = ldm:
- *          column k < E holds alpha of sample g0+k, column E+k its beta.
- *          FP64 -> double, FP32 -> float, SPLIT_* -> a hi plane followed by a
- *          lo plane of 16-bit values with x = hi + lo (hi = x rounded, lo = the
- *          rounded remainder).
+ *   ab     device, mp_ab_bytes(M, E, prec) bytes, column-major: column k < E
+ *          holds alpha of sample g0+k, column E+k its beta (column stride ldm
+ *          for FP64 and FP32).
+ *          FP64 -> double, FP32 -> float.  SPLIT_* -> 16-bit values with
+ *          x = hi + lo (hi = x rounded, lo = the rounded remainder), column
+ *          stride 2 ldm: mode j of a column has hi at 64 (j / 32) + j % 32 and
+ *          lo 32 values further (blocks of 32 hi values, each followed by
+ *          its 32 lo values).
  *   n_out  device FP64[E]: n = sum_j alpha_j beta_j of the values as stored
  *          (after rounding to `prec`).
  */

@@ -37,8 +37,8 @@ constexpr int kLdAlign = 128;  // mode padding (GEMM tile multiple)
 
 // One network of a grouped split-precision GEMM launch.
 struct GroupNet {
-  const uint16_t* A;  // packed [Re T; Im T] hi plane, lo plane after it
-  const uint16_t* B;  // sampled amplitudes, hi plane then lo plane
+  const uint16_t* A;  // packed [Re T; Im T], hi and lo interleaved in 32-blocks
+  const uint16_t* B;  // sampled amplitudes, hi and lo interleaved in 32-blocks
   float* C;
   int64_t ldm, ncols;
   float out_scale;
@@ -50,7 +50,7 @@ inline size_t elem_bytes_ab(mp_precision p) {
   switch (p) {
     case MP_FP64: return 8;
     case MP_FP32: return 4;
-    default: return 4;  // hi + lo planes of 2 bytes each
+    default: return 4;  // hi + lo values of 2 bytes each
   }
 }
 

@@ -9,11 +9,17 @@
 // modes) and C column-major.  Both operands are K-contiguous, so every lane of
 // a wavefront feeds its MFMA fragment from one 16-byte LDS read.
 //
-// Kernels: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_32x32x2) and split
-// BF16 (three v_mfma_f32_32x32x16_bf16 products hi*hi + hi*lo + lo*hi with
-// FP32 accumulation).  Tile 128 x 128 per 256-thread workgroup, four waves of
-// 64 x 64, LDS double buffering, and a tile order grouped per XCD so that the
-// workgroups sharing one L2 reuse the same rows of A and columns of B.
+// Kernels: FP64 (v_mfma_f64_16x16x4, 128 x 128 tiles), FP32
+// (v_mfma_f32_32x32x2, 256 x 256 tiles) and split BF16/FP16 (three
+// v_mfma_f32_32x32x16 products hi*hi + hi*lo + lo*hi with FP32 accumulation,
+// 256 x 256 tiles).  The 256 x 256 kernels feed LDS with direct global-to-LDS
+// loads in a two-stage ping-pong schedule, and every tile order keeps the
+// workgroups of one XCD on neighbouring tiles that share rows of A and
+// columns of B in its L2.
+//
+// Split operands are stored interleaved: each row of A (and each column of
+// B) alternates a block of 32 hi values with the block of the 32 matching lo
+// values, so one 32-deep k-slab of a row is one full 128-byte line.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -44,7 +50,11 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// A[i][j] (row-major, 2 ldm x ldm) from T (row-major complex M x M).
+// A[i][j] (row-major, 2 ldm x ldm) from T (row-major complex M x M).  Split
+// precisions store row i as 2 ldm values: for k-block b = j / 32 the 32 hi
+// values at 64 b .. 64 b + 31 and the 32 lo values right after them.
+__host__ __device__ inline int64_t split_offset(int64_t j) { return 64 * (j >> 5) + (j & 31); }
+
 template <int PREC>
 __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t ldm,
                                   void* __restrict__ A, int scale_exp) {
@@ -62,15 +72,17 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
   } else if constexpr (PREC == MP_SPLIT_BF16) {
     uint16_t hi = f32_to_bf16_rne((float)v);
     uint16_t lo = f32_to_bf16_rne((float)(v - (double)bf16_to_f32(hi)));
-    ((uint16_t*)A)[idx] = hi;
-    ((uint16_t*)A)[idx + total] = lo;
+    const int64_t at = row * 2 * ldm + split_offset(j);
+    ((uint16_t*)A)[at] = hi;
+    ((uint16_t*)A)[at + 32] = lo;
   } else {
     // FP16: A is packed as T * 2^scale_exp so that both halves stay normal
     const double x = ldexp(v, scale_exp);
     _Float16 hi = (_Float16)x;
     _Float16 lo = (_Float16)(x - (double)hi);
-    ((_Float16*)A)[idx] = hi;
-    ((_Float16*)A)[idx + total] = lo;
+    const int64_t at = row * 2 * ldm + split_offset(j);
+    ((_Float16*)A)[at] = hi;
+    ((_Float16*)A)[at + 32] = lo;
   }
 }
 
@@ -333,114 +345,21 @@ __global__ __launch_bounds__(kThreads) void gemm_f32(const float* __restrict__ A
   }
 }
 
-// ---------------------------------------------------------------- split BF16
-
-// v_mfma_f32_32x32x16_bf16: lane l holds A[l%32][8 (l/32) + e], e = 0..7, and
-// the same for B; outputs as in the 32x32 FP32 form.  Within one BK = 32 slab
-// lane half h supplies k = 16h + 8s + e at step s (s = 0, 1).  Each operand is
-// x = hi + lo (both BF16); the product keeps hi*hi + hi*lo + lo*hi.
-__global__ __launch_bounds__(kThreads) void gemm_split_bf16(const uint16_t* __restrict__ A,
-                                                            const uint16_t* __restrict__ B,
-                                                            float* __restrict__ C, int64_t ldm,
-                                                            int64_t ncols, int order) {
-  constexpr int BK = 32, LDK = BK + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t sAh[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sAl[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sBh[2][BN * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sBl[2][BN * LDK];
-  const int tiles_m = (int)(2 * ldm / BM), tiles_n = (int)((ncols + BN - 1) / BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 31, lh = lane >> 5;
-  const int64_t planeA = 2 * ldm * ldm, planeB = ldm * ncols;
-  const uint16_t* Al = A + planeA;
-  const uint16_t* Bl = B + planeB;
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  Slab<uint16_t, BK> lah, lal, lbh, lbl;
-  const int KT = (int)(ldm / BK);
-  lah.load(A, ldm, m0, 0, 2 * ldm);
-  lal.load(Al, ldm, m0, 0, 2 * ldm);
-  lbh.load(B, ldm, n0, 0, ncols);
-  lbl.load(Bl, ldm, n0, 0, ncols);
-  lah.store<LDK>(sAh[0]);
-  lal.store<LDK>(sAl[0]);
-  lbh.store<LDK>(sBh[0]);
-  lbl.store<LDK>(sBl[0]);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) {
-      const int64_t k0 = (int64_t)(kt + 1) * BK;
-      lah.load(A, ldm, m0, k0, 2 * ldm);
-      lal.load(Al, ldm, m0, k0, 2 * ldm);
-      lbh.load(B, ldm, n0, k0, ncols);
-      lbl.load(Bl, ldm, n0, k0, ncols);
-    }
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      bf16x8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int offA = (wm * 64 + i * 32 + lr) * LDK + 16 * lh + 8 * s;
-        const int offB = (wn * 64 + i * 32 + lr) * LDK + 16 * lh + 8 * s;
-        ah[i] = *(const bf16x8*)(sAh[cur] + offA);
-        al[i] = *(const bf16x8*)(sAl[cur] + offA);
-        bh[i] = *(const bf16x8*)(sBh[cur] + offB);
-        bl[i] = *(const bf16x8*)(sBl[cur] + offB);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    }
-    if (kt + 1 < KT) {
-      lah.store<LDK>(sAh[cur ^ 1]);
-      lal.store<LDK>(sAl[cur ^ 1]);
-      lbh.store<LDK>(sBh[cur ^ 1]);
-      lbl.store<LDK>(sBl[cur ^ 1]);
-    }
-    __syncthreads();
-  }
-  const int64_t ldc = 2 * ldm;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    int64_t col = n0 + wn * 64 + j * 32 + lr;
-    if (col >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        int64_t row = m0 + wm * 64 + i * 32 + 8 * g + 4 * lh;
-        *(f32x4*)(C + col * ldc + row) =
-            f32x4{acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]};
-      }
-  }
-}
-
 // ---------------------------------------------------------------- split, 256 x 256
 
-// Split-precision GEMM with a 256 x 256 workgroup tile: four waves of
-// 128 x 128 (4 x 4 MFMA 32x32x16 tiles, 256 accumulator registers per lane),
-// BK = 32, two LDS stages of four 256 x 32 planes (A hi/lo, B hi/lo).  Rows
-// of a plane are 64 bytes without padding; 16-byte chunk c of row r is
-// stored at chunk c ^ f(r), f(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1), which keeps
-// both the 16-byte fragment reads (32 consecutive rows, one chunk) and the
-// staging writes free of bank conflicts for 32- and 64-bank LDS.  Within a
+// v_mfma_f32_32x32x16_bf16 (and _f16): lane l holds A[l%32][8 (l/32) + e],
+// e = 0..7, and the same for B; output register r is row 8 (r/4) + 4 (l/32)
+// + r%4, column l%32.  Within one BK = 32 slab lane half h supplies
+// k = 16 h + 8 s + e at step s (s = 0, 1), the same permutation on both
+// operands.  Each operand is x = hi + lo; the product keeps
+// hi*hi + hi*lo + lo*hi.
+//
+// Tile 256 x 256 per 256-thread workgroup: four waves of 128 x 128 (4 x 4
+// MFMA tiles, 256 accumulator registers per lane), two LDS stages of four
+// 256 x 32 planes (A hi/lo, B hi/lo).  Rows of a plane are 64 bytes without
+// padding; 16-byte chunk c of row r is stored at chunk c ^ f(r),
+// f(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1), which keeps the 16-byte fragment
+// reads (32 consecutive rows, one chunk) free of bank conflicts.  Within a
 // k16 step the three products run as three sweeps over the 16 tiles, so
 // consecutive MFMAs never depend on each other.  `out_scale` undoes the
 // power-of-two prescale of the packed A operand.
@@ -466,252 +385,11 @@ __device__ inline int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
 constexpr int S_BM = 256, S_BN = 256, S_BK = 32;
 constexpr int S_PLANE = S_BM * S_BK;  // elements of one LDS plane
 
-template <typename H>
-__global__ __launch_bounds__(kThreads, 1) void gemm_split_256(const uint16_t* __restrict__ A,
-                                                              const uint16_t* __restrict__ B,
-                                                              float* __restrict__ C, int64_t ldm,
-                                                              int64_t ncols, float out_scale, int order) {
-  typedef typename SplitMfma<H>::frag frag;
-  __shared__ __attribute__((aligned(16))) uint16_t lds[2][4][S_PLANE];
-  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 31, lh = lane >> 5;
-  const int64_t planeA = 2 * ldm * ldm, planeB = ldm * ncols;
-
-  // staging: thread tid moves 16-byte vector vi = tid + 256 i (i < 4) of each
-  // plane: row vi >> 2, chunk vi & 3
-  const uint16_t* src[4];
-  int64_t nvalid[4];
-  src[0] = A + m0 * ldm;
-  src[1] = A + planeA + m0 * ldm;
-  src[2] = B + n0 * ldm;
-  src[3] = B + planeB + n0 * ldm;
-  nvalid[0] = nvalid[1] = S_BM;
-  nvalid[2] = nvalid[3] = ncols - n0;
-  u32x4 stage[4][4];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int vi = tid + i * kThreads;
-        const int row = vi >> 2, c = vi & 3;
-        if (row < nvalid[p])
-          stage[p][i] = *(const u32x4*)(src[p] + (int64_t)row * ldm + k0 + c * 8);
-        else
-          stage[p][i] = u32x4{0, 0, 0, 0};
-      }
-  };
-  auto lstore = [&](int st) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int vi = tid + i * kThreads;
-        const int row = vi >> 2, c = vi & 3;
-        *(u32x4*)(&lds[st][p][row * S_BK + ((c ^ swz(row)) << 3)]) = stage[p][i];
-      }
-  };
-
-  f32x16 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  const int KT = (int)(ldm / S_BK);
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) gload((int64_t)(kt + 1) * S_BK);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      frag ah[4], al[4], bh[4], bl[4];
-      const int chunk = 2 * lh + s;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ra = wm * 128 + i * 32 + lr;
-        const int rb = wn * 128 + i * 32 + lr;
-        const int oa = ra * S_BK + ((chunk ^ swz(ra)) << 3);
-        const int ob = rb * S_BK + ((chunk ^ swz(rb)) << 3);
-        ah[i] = *(const frag*)(&lds[cur][0][oa]);
-        al[i] = *(const frag*)(&lds[cur][1][oa]);
-        bh[i] = *(const frag*)(&lds[cur][2][ob]);
-        bl[i] = *(const frag*)(&lds[cur][3][ob]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al[i], bh[j], acc[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bl[j], acc[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bh[j], acc[i][j]);
-    }
-    // stage cur ^ 1 was last read before the previous barrier
-    if (kt + 1 < KT) lstore(cur ^ 1);
-    __syncthreads();
-  }
-  const int64_t ldc = 2 * ldm;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t col = n0 + wn * 128 + j * 32 + lr;
-    if (col >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
-        *(f32x4*)(C + col * ldc + row) =
-            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
-                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
-      }
-  }
-}
-
-// Same tile and LDS layout as gemm_split_256, fed by gfx950's direct
-// global-to-LDS loads (global_load_lds_dwordx4): lane l of a wave writes the
-// 16 bytes at LDS slot base + 16 l, so each lane fetches the global chunk that
-// the swizzled layout puts in its slot.  Wave w fills plane w (A hi, A lo,
-// B hi, B lo) of the next stage while all waves compute on the current one;
-// no staging registers and no LDS stores in the shader.  Columns of B past
-// the end are clamped to the last valid column (their outputs are dropped).
-// Both k16 fragment sets of a slab are read up front so that the LDS reads
-// of the second step overlap the MFMAs of the first.
+// Operands reach LDS through gfx950's direct global-to-LDS loads
+// (global_load_lds_dwordx4): lane l of a wave writes the 16 bytes at LDS slot
+// base + 16 l, so each lane fetches the global chunk that the swizzled layout
+// puts in its slot; no staging registers and no LDS stores in the shader.
 typedef __attribute__((address_space(3))) void lds_void;
-
-template <typename H>
-__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_dma(const uint16_t* __restrict__ A,
-                                                                  const uint16_t* __restrict__ B,
-                                                                  float* __restrict__ C,
-                                                                  int64_t ldm, int64_t ncols,
-                                                                  float out_scale, int order) {
-  typedef typename SplitMfma<H>::frag frag;
-  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
-  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 31, lh = lane >> 5;
-
-  // this wave's plane: source rows and their lane offsets within one 16-row load
-  const uint16_t* plane_src;
-  int64_t row_limit;
-  if (wave < 2) {
-    plane_src = A + (wave == 1 ? 2 * ldm * ldm : 0) + m0 * ldm;
-    row_limit = S_BM;
-  } else {
-    plane_src = B + (wave == 3 ? ldm * ncols : 0) + n0 * ldm;
-    row_limit = ncols - n0;
-  }
-  // load q (0..15) covers rows 16 q .. 16 q + 15; lane l -> row 16 q + l / 4,
-  // physical chunk l % 4, logical chunk (l % 4) ^ swz(row); swz(row) depends
-  // only on row % 16, so the per-lane chunk offset is the same for every q
-  const int lrow = lane >> 2;
-  const int lchunk = (lane & 3) ^ swz(lrow);
-  auto issue = [&](int st, int64_t k0) {
-    lds_void* dst = (lds_void*)&lds[st][wave][0];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      int64_t row = 16 * q + lrow;
-      row = row < row_limit ? row : row_limit - 1;
-      const uint16_t* g = plane_src + row * ldm + k0 + lchunk * 8;
-      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)((char*)dst + q * 1024), 16, 0, 0);
-    }
-  };
-
-  f32x16 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  const int KT = (int)(ldm / S_BK);
-  issue(0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    // stage cur ^ 1 was last read before the previous barrier
-    if (kt + 1 < KT) issue(cur ^ 1, (int64_t)(kt + 1) * S_BK);
-    frag ah[2][4], al[2][4], bh[2][4], bl[2][4];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int chunk = 2 * lh + s;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ra = wm * 128 + i * 32 + lr;
-        const int rb = wn * 128 + i * 32 + lr;
-        const int oa = ra * S_BK + ((chunk ^ swz(ra)) << 3);
-        const int ob = rb * S_BK + ((chunk ^ swz(rb)) << 3);
-        al[s][i] = *(const frag*)(&lds[cur][1][oa]);
-        bh[s][i] = *(const frag*)(&lds[cur][2][ob]);
-        ah[s][i] = *(const frag*)(&lds[cur][0][oa]);
-        bl[s][i] = *(const frag*)(&lds[cur][3][ob]);
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al[s][i], bh[s][j], acc[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[s][i], bl[s][j], acc[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[s][i], bh[s][j], acc[i][j]);
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage have landed
-    __syncthreads();
-  }
-  const int64_t ldc = 2 * ldm;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t col = n0 + wn * 128 + j * 32 + lr;
-    if (col >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
-        *(f32x4*)(C + col * ldc + row) =
-            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
-                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
-      }
-  }
-}
-
-// Deeper-prefetch variant: BK = 16 and a ring of four LDS stages (4 planes of
-// 256 rows x 32 bytes = 32 KB per stage), so the direct-to-LDS loads of slab
-// kt + 3 are in flight while slab kt is multiplied; the wait before each
-// barrier only drains the loads of slab kt + 1 (vmcnt counts the loads issued
-// after it).  Rows hold two 16-byte chunks; chunk c of row r sits at
-// c ^ g(r), g(r) = ((r >> 2) ^ (r >> 3)) & 1, conflict-free for 32- and
-// 64-bank LDS.
-__device__ inline int swz2(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
-
-constexpr int R_BK = 16, R_STAGES = 4;
-constexpr int R_PLANE = S_BM * R_BK;  // elements of one plane of one stage
 
 // Workgroup barrier without the memory fence of __syncthreads: the fence
 // would drain every in-flight direct-to-LDS load.  LDS visibility is ensured
@@ -727,120 +405,6 @@ template <int N>
 __device__ inline void wait_vm() {
   // s_waitcnt vmcnt(N), expcnt and lgkmcnt unconstrained (gfx9 encoding)
   __builtin_amdgcn_s_waitcnt(((N & 15) | ((N >> 4) << 14)) | (7 << 4) | (15 << 8));
-}
-
-template <typename H>
-__global__ __launch_bounds__(kThreads, 1) void gemm_split_256_ring(const uint16_t* __restrict__ A,
-                                                                   const uint16_t* __restrict__ B,
-                                                                   float* __restrict__ C,
-                                                                   int64_t ldm, int64_t ncols,
-                                                                   float out_scale, int order) {
-  typedef typename SplitMfma<H>::frag frag;
-  __shared__ __attribute__((aligned(1024))) uint16_t lds[R_STAGES][4][R_PLANE];
-  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 31, lh = lane >> 5;
-
-  const uint16_t* plane_src;
-  int64_t row_limit;
-  if (wave < 2) {
-    plane_src = A + (wave == 1 ? 2 * ldm * ldm : 0) + m0 * ldm;
-    row_limit = S_BM;
-  } else {
-    plane_src = B + (wave == 3 ? ldm * ncols : 0) + n0 * ldm;
-    row_limit = ncols - n0;
-  }
-  // load q (0..7) covers rows 32 q .. 32 q + 31: lane l -> row 32 q + l / 2,
-  // physical chunk l % 2, logical chunk (l % 2) ^ swz2(row); swz2 depends on
-  // row % 16 only
-  const int lrow = lane >> 1;
-  const int lchunk = (lane & 1) ^ swz2(lrow);
-  const uint16_t* lsrc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    int64_t row = 32 * q + lrow;
-    row = row < row_limit ? row : row_limit - 1;
-    lsrc[q] = plane_src + row * ldm + lchunk * 8;
-  }
-  auto issue = [&](int st, int64_t k0) {
-    char* dst = (char*)&lds[st][wave][0];
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      __builtin_amdgcn_global_load_lds((const void*)(lsrc[q] + k0), (lds_void*)(dst + q * 1024), 16,
-                                       0, 0);
-  };
-
-  f32x16 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  const int KT = (int)(ldm / R_BK);  // >= 8
-  issue(0, 0);
-  issue(1, R_BK);
-  issue(2, 2 * R_BK);
-  wait_vm<16>();
-  barrier_no_fence();
-  const int oa_row[4] = {wm * 128 + lr, wm * 128 + 32 + lr, wm * 128 + 64 + lr, wm * 128 + 96 + lr};
-  const int ob_row[4] = {wn * 128 + lr, wn * 128 + 32 + lr, wn * 128 + 64 + lr, wn * 128 + 96 + lr};
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 3;
-    // stage (kt + 3) & 3 was last read in iteration kt - 1, before its barrier
-    if (kt + 3 < KT) issue((kt + 3) & 3, (int64_t)(kt + 3) * R_BK);
-    frag ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int oa = oa_row[i] * R_BK + ((lh ^ swz2(oa_row[i])) << 3);
-      const int ob = ob_row[i] * R_BK + ((lh ^ swz2(ob_row[i])) << 3);
-      al[i] = *(const frag*)(&lds[cur][1][oa]);
-      bh[i] = *(const frag*)(&lds[cur][2][ob]);
-      ah[i] = *(const frag*)(&lds[cur][0][oa]);
-      bl[i] = *(const frag*)(&lds[cur][3][ob]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al[i], bh[j], acc[i][j]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bl[j], acc[i][j]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah[i], bh[j], acc[i][j]);
-    // stage of slab kt + 1 must have landed: loads of later slabs may stay in flight
-    const int later = (kt + 3 < KT ? kt + 3 : KT - 1) - (kt + 1);
-    if (later >= 2)
-      wait_vm<16>();
-    else if (later == 1)
-      wait_vm<8>();
-    else
-      wait_vm<0>();
-    barrier_no_fence();
-  }
-  const int64_t ldc = 2 * ldm;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t col = n0 + wn * 128 + j * 32 + lr;
-    if (col >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
-        *(f32x4*)(C + col * ldc + row) =
-            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
-                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
-      }
-  }
 }
 
 // Ping-pong schedule of the two-stage direct-to-LDS kernel.  Fragments of a
@@ -863,11 +427,13 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
 
   const uint16_t* plane_src;
   int64_t row_limit;
+  // wave w fills plane w: hi or lo (+32) half of the interleaved rows of A
+  // (w < 2) or of the columns of B; both have 2 ldm values per row
   if (wave < 2) {
-    plane_src = A + (wave == 1 ? 2 * ldm * ldm : 0) + m0 * ldm;
+    plane_src = A + (wave == 1 ? 32 : 0) + m0 * 2 * ldm;
     row_limit = S_BM;
   } else {
-    plane_src = B + (wave == 3 ? ldm * ncols : 0) + n0 * ldm;
+    plane_src = B + (wave == 3 ? 32 : 0) + n0 * 2 * ldm;
     row_limit = ncols - n0;
   }
   const int lrow = lane >> 2;
@@ -878,7 +444,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     for (int q = 0; q < 16; ++q) {
       int64_t row = 16 * q + lrow;
       row = row < row_limit ? row : row_limit - 1;
-      const uint16_t* g = plane_src + row * ldm + k0 + lchunk * 8;
+      const uint16_t* g = plane_src + row * 2 * ldm + 2 * k0 + lchunk * 8;
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
     }
   };
@@ -1019,13 +585,19 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
 // ---------------------------------------------------------------- FP32, 256 x 256
 
 // FP32 twin of the split ping-pong kernel: the same 256 x 256 tile, four
-// waves of 128 x 128, two direct-to-LDS stages and the same swizzled LDS
-// rows (BK = 16 floats = 64 bytes per row), with v_mfma_f32_32x32x2f32.
-// Lane half h supplies k = 8 h + s at step s (s = 0..7) of a slab, the same
-// permutation on both operands; F0 holds steps 0-3 (chunk 2 h) and F1 steps
-// 4-7 (chunk 2 h + 1).  Wave w loads half (w & 1) of operand w >> 1.
-constexpr int F_BK = 16;
+// waves of 128 x 128, two direct-to-LDS stages, v_mfma_f32_32x32x2f32.
+// BK = 32 floats, so an LDS row is one 128-byte line of 8 chunks; chunk c of
+// row r sits at c ^ ((r >> 1) & 7), conflict-free for the 16-byte fragment
+// reads (16 consecutive rows per LDS cycle: even and odd rows fall in
+// different bank halves, and the XOR spreads each half over 8 chunk slots).
+// Lane half h supplies k = 16 h + 8 f + s at step s of fragment set f
+// (f = 0, 1; s = 0..7), the same permutation on both operands; set f is
+// chunks 4 h + 2 f and 4 h + 2 f + 1.  Wave w loads half (w & 1) of operand
+// w >> 1.
+constexpr int F_BK = 32;
 constexpr int F_PLANE = S_BM * F_BK;  // floats of one LDS operand plane
+
+__device__ inline int swz8(int r) { return (r >> 1) & 7; }
 
 __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restrict__ A,
                                                            const float* __restrict__ B,
@@ -1043,42 +615,49 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
   const int op = wave >> 1, half = wave & 1;
   const float* src = op == 0 ? A + m0 * ldm : B + n0 * ldm;
   const int64_t row_limit = op == 0 ? S_BM : ncols - n0;
-  const int lrow = lane >> 2;
-  // lane l writes LDS slot 16 l of each 1 KB block: row 16 q + l / 4 of the
-  // wave's half, slot l % 4, which holds global chunk (l % 4) ^ swz(row)
+  const int lrow = lane >> 3;
+  // lane l writes LDS slot 16 l of each 1 KB block (8 rows): row 8 q + l / 8
+  // of the wave's half, slot l % 8, which holds global chunk (l % 8) ^ swz8(row)
   auto issue = [&](int st, int64_t k0) {
     char* dst = (char*)&lds[st][op][0] + half * (128 * F_BK * 4);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = half * 128 + 16 * q + lrow;
+    for (int q = 0; q < 16; ++q) {
+      const int r = half * 128 + 8 * q + lrow;
       const int64_t row = r < row_limit ? r : row_limit - 1;
-      const float* g = src + row * ldm + k0 + (((lane & 3) ^ swz(r)) << 2);
+      const float* g = src + row * ldm + k0 + (((lane & 7) ^ swz8(r)) << 2);
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
     }
   };
-  int oa[2][4], ob[2][4];
+  int oa[2][2][4], ob[2][2][4];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int f = 0; f < 2; ++f)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
-      oa[s][i] = ra * F_BK + (((2 * lh + s) ^ swz(ra)) << 2);
-      ob[s][i] = rb * F_BK + (((2 * lh + s) ^ swz(rb)) << 2);
-    }
-  f32x4 a0[4], b0[4], a1[4], b1[4];
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+        const int c = 4 * lh + 2 * f + t;
+        oa[f][t][i] = ra * F_BK + ((c ^ swz8(ra)) << 2);
+        ob[f][t][i] = rb * F_BK + ((c ^ swz8(rb)) << 2);
+      }
+  f32x4 a0[2][4], b0[2][4], a1[2][4], b1[2][4];
   auto read0 = [&](int st) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a0[i] = *(const f32x4*)(&lds[st][0][oa[0][i]]);
-      b0[i] = *(const f32x4*)(&lds[st][1][ob[0][i]]);
-    }
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a0[t][i] = *(const f32x4*)(&lds[st][0][oa[0][t][i]]);
+        b0[t][i] = *(const f32x4*)(&lds[st][1][ob[0][t][i]]);
+      }
   };
   auto read1 = [&](int st) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a1[i] = *(const f32x4*)(&lds[st][0][oa[1][i]]);
-      b1[i] = *(const f32x4*)(&lds[st][1][ob[1][i]]);
-    }
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a1[t][i] = *(const f32x4*)(&lds[st][0][oa[1][t][i]]);
+        b1[t][i] = *(const f32x4*)(&lds[st][1][ob[1][t][i]]);
+      }
   };
 
   f32x16 acc[4][4];
@@ -1089,7 +668,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int KT = (int)(ldm / F_BK);  // >= 8
+  const int KT = (int)(ldm / F_BK);  // >= 4
   issue(0, 0);
   wait_vm<0>();
   barrier_no_fence();
@@ -1098,48 +677,50 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
   constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
-    // phase A: steps 0-3 on F0 with the reads of F1 threaded between them
+    // phase A: set 0 (steps 0-7) with the reads of set 1 threaded between them
     read1(cur);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i][s], b0[j][s], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[s >> 2][i][s & 3], b0[s >> 2][j][s & 3],
+                                                           acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 16; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 4, 0);
       __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(kSgMfma, 32, 0);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 64, 0);
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);  // own loads of slab kt + 1 landed, reads of stage cur done
     barrier_no_fence();
     __builtin_amdgcn_sched_barrier(0);
-    // phase B: steps 4-7 on F1 with the loads of slab kt + 2 and the reads of
-    // F0 of slab kt + 1 threaded in (the last two slabs repeat the final slab
-    // into the freed stage, in bounds, so the loop has no branches)
+    // phase B: set 1 (steps 8-15) with the loads of slab kt + 2 and the reads
+    // of set 0 of slab kt + 1 threaded in (the last two slabs repeat the final
+    // slab into the freed stage, in bounds, so the loop has no branches)
     issue(cur, (int64_t)min(kt + 2, KT - 1) * F_BK);
     read0(cur ^ 1);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[i][s], b1[j][s], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[s >> 2][i][s & 3], b1[s >> 2][j][s & 3],
+                                                           acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 16; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 1);
       __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 16; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 4, 1);
       __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
     }
-    __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 1);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 32, 1);
     __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
@@ -1191,17 +772,6 @@ size_t propagate_workspace(int32_t M, mp_precision prec) {
     case MP_FP32: return elems * 4;
     default: return elems * 4;  // two 16-bit planes
   }
-}
-
-// Split-GEMM variant: 3 = two-stage direct-to-LDS ping-pong (default),
-// 2 = four-stage direct-to-LDS ring, 1 = two-stage direct-to-LDS,
-// 0 = register staging.
-static int split_variant() {
-  static int v = [] {
-    const char* e = getenv("MPGBS_SPLIT_VARIANT");
-    return e ? atoi(e) : 3;
-  }();
-  return v;
 }
 
 // FP32 GEMM variant: 1 = 256 x 256 direct-to-LDS ping-pong (default),
@@ -1264,23 +834,11 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
 
 // GEMM on an already packed operand (one network).
 template <typename H>
-static void split_gemm(int variant, int grid, hipStream_t stream, const void* packed,
-                       const void* ab, void* C, int64_t ldm, int64_t ncols, float scale) {
-  const uint16_t* A = (const uint16_t*)packed;
-  const uint16_t* B = (const uint16_t*)ab;
-  float* Cf = (float*)C;
-  if (variant == 3)
-    hipLaunchKernelGGL(gemm_split_256_pp<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf, ldm,
-                       ncols, scale, tile_order());
-  else if (variant == 2)
-    hipLaunchKernelGGL(gemm_split_256_ring<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf,
-                       ldm, ncols, scale, tile_order());
-  else if (variant == 1)
-    hipLaunchKernelGGL(gemm_split_256_dma<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf,
-                       ldm, ncols, scale, tile_order());
-  else
-    hipLaunchKernelGGL(gemm_split_256<H>, dim3(grid), dim3(kThreads), 0, stream, A, B, Cf, ldm,
-                       ncols, scale, tile_order());
+static void split_gemm(int grid, hipStream_t stream, const void* packed, const void* ab, void* C,
+                       int64_t ldm, int64_t ncols, float scale) {
+  hipLaunchKernelGGL(gemm_split_256_pp<H>, dim3(grid), dim3(kThreads), 0, stream,
+                     (const uint16_t*)packed, (const uint16_t*)ab, (float*)C, ldm, ncols, scale,
+                     tile_order());
 }
 
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
@@ -1302,12 +860,12 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
                            tile_order());
       break;
     case MP_SPLIT_BF16:
-      split_gemm<__bf16>(split_variant(), grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab,
-                         C, ldm, ncols, 1.0f);
+      split_gemm<__bf16>(grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab, C, ldm, ncols,
+                         1.0f);
       break;
     case MP_SPLIT_FP16:
-      split_gemm<_Float16>(split_variant(), grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab,
-                           C, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
+      split_gemm<_Float16>(grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab, C, ldm, ncols,
+                           ldexpf(1.0f, -fp16_scale_exp(M)));
       break;
   }
   MP_HIP_LAUNCH_CHECK("mp_propagate gemm launch");

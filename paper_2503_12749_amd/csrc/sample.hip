@@ -90,9 +90,12 @@ __device__ inline void store_pair_f64(void* ab, int64_t off, double x0, double x
   *(d2*)((double*)ab + off) = d2{x0, x1};
 }
 
+// Split storage: element j of a column sits at 64 (j / 32) + j % 32 (hi) and
+// 32 further (lo); off is the hi position of the even mode 2p, whose partner
+// 2p + 1 shares its block.
 template <int PREC>
-__device__ inline void store_pair_f32(void* ab, int64_t plane, int64_t off, float x0, float x1,
-                                      double& y0, double& y1) {
+__device__ inline void store_pair_f32(void* ab, int64_t off, float x0, float x1, double& y0,
+                                      double& y1) {
   if constexpr (PREC == MP_FP32) {
     typedef __attribute__((ext_vector_type(2))) float f2;
     *(f2*)((float*)ab + off) = f2{x0, x1};
@@ -104,7 +107,7 @@ __device__ inline void store_pair_f32(void* ab, int64_t plane, int64_t off, floa
     const uint16_t l0 = bf16_rne(x0 - bf16_val(h0)), l1 = bf16_rne(x1 - bf16_val(h1));
     uint16_t* q = (uint16_t*)ab;
     *(uint32_t*)(q + off) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-    *(uint32_t*)(q + plane + off) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    *(uint32_t*)(q + off + 32) = (uint32_t)l0 | ((uint32_t)l1 << 16);
     y0 = (double)bf16_val(h0) + (double)bf16_val(l0);
     y1 = (double)bf16_val(h1) + (double)bf16_val(l1);
   } else {
@@ -113,7 +116,7 @@ __device__ inline void store_pair_f32(void* ab, int64_t plane, int64_t off, floa
     _Float16* q = (_Float16*)ab;
     typedef __attribute__((ext_vector_type(2))) _Float16 h2;
     *(h2*)(q + off) = h2{h0, h1};
-    *(h2*)(q + plane + off) = h2{l0, l1};
+    *(h2*)(q + off + 32) = h2{l0, l1};
     y0 = (double)(float)h0 + (double)(float)l0;
     y1 = (double)(float)h1 + (double)(float)l1;
   }
@@ -134,7 +137,6 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
   const int64_t k0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kWaveSamples;
   if (k0 >= E) return;
   const int nk = (int)(E - k0 < kWaveSamples ? E - k0 : kWaveSamples);
-  const int64_t plane = ldm * 2 * E;
   double nsum[kWaveSamples];
 #pragma unroll
   for (int s = 0; s < kWaveSamples; ++s) nsum[s] = 0.0;
@@ -156,7 +158,12 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
     for (int s = 0; s < kWaveSamples; ++s) {
       if (s >= nk) break;
       const int64_t k = k0 + s;
-      const int64_t col_a = k * ldm + j0, col_b = (E + k) * ldm + j0;
+      // column stride ldm (FP64, FP32) or 2 ldm (split, hi and lo interleaved)
+      const int64_t col_a = (PREC == MP_FP64 || PREC == MP_FP32) ? k * ldm + j0
+                                                                 : k * 2 * ldm + 64 * (j0 >> 5) + (j0 & 31);
+      const int64_t col_b = (PREC == MP_FP64 || PREC == MP_FP32)
+                                ? (E + k) * ldm + j0
+                                : (E + k) * 2 * ldm + 64 * (j0 >> 5) + (j0 & 31);
       uint64_t c0 = (uint64_t)(g0 + k), c1 = (uint64_t)p, c2 = net, c3 = 0;
       if (j0 < M) philox4x64_10(c0, c1, c2, c3, seed, 0);
       if constexpr (PREC == MP_FP64) {
@@ -180,8 +187,8 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
         const float a0 = fp0 * w1 + fm0 * w2, b0 = fp0 * w1 - fm0 * w2;
         const float a1 = fp1 * w3 + fm1 * w4, b1 = fp1 * w3 - fm1 * w4;
         double ya0, ya1, yb0, yb1;
-        store_pair_f32<PREC>(ab, plane, col_a, a0, a1, ya0, ya1);
-        store_pair_f32<PREC>(ab, plane, col_b, b0, b1, yb0, yb1);
+        store_pair_f32<PREC>(ab, col_a, a0, a1, ya0, ya1);
+        store_pair_f32<PREC>(ab, col_b, b0, b1, yb0, yb1);
         nsum[s] += ya0 * yb0 + ya1 * yb1;
       }
     }
