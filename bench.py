@@ -32,6 +32,32 @@ METRIC = "samples·M²/s and seconds to binned P(m) at 1σ≤1e-3, M=8000, mixed
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0}
 HBM_PEAK_GBS = 8000.0
 
+# FETCH_SIZE / WRITE_SIZE of the GEMM kernel at this workload (rocprofv3 --pmc,
+# one counter per run, per dispatch), scaled by the factors a 1 GiB copy gives
+# (fetch x2, write x1); valid only for the GEMM source they were taken from.
+# Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
+TRAFFIC = {
+    "split_bf16": {"source_sha256_16": "948a23a9be33d9ef",
+                   "fetch_bytes": 1.153e8 * 1024 * 2, "write_bytes": 8.261e6 * 1024},
+    "fp32": {"source_sha256_16": "948a23a9be33d9ef",
+             "fetch_bytes": 4.906e7 * 1024 * 2, "write_bytes": 8.258e6 * 1024},
+}
+
+
+def gemm_traffic_gb(prec):
+    """Counter-derived bytes per GEMM launch in GB, or None when the GEMM
+    source has changed since the counters were taken."""
+    import hashlib
+    rec = TRAFFIC.get(prec)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2503_12749_amd", "csrc", "propagate.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    if digest != rec["source_sha256_16"]:
+        return None
+    return round((rec["fetch_bytes"] + rec["write_bytes"]) / 1e9, 2)
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -92,29 +118,8 @@ def cpu_baseline(w, budget_s):
                       f"{w.windows[0][1]}-count window), {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="split_bf16")
-    ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
-    ap.add_argument("--compare-steps", type=int, default=2)
-    ap.add_argument("--chunk", type=int, default=65536)
-    ap.add_argument("--M", type=int, default=8000)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sample-sharded "
-              f"multi-GPU path is a design, not part of this build.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import synth
-    import paper_2503_12749_amd as mp
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+def run_m8000(args, mp, torch, synth):
+    """The headline workload (see the module docstring)."""
     t = time.perf_counter()
     E_total = args.chunk * (args.warmup + args.steps)
     w = synth.workload_m8000(E=E_total, chunk=args.chunk) if args.M == 8000 else None
@@ -172,7 +177,9 @@ def main():
     achieved = flops / (main_r["gemm_ms"] * 1e-3) / 1e12
     peak = PEAKS_TFLOPS[args.prec]
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": gemm_traffic_gb(args.prec) if w.M == 8000 and args.chunk == 65536 else None,
+            "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, calibrated on a 1 GiB copy)",
             "kernel": f"gemm_{args.prec} (mp_propagate_packed)",
             "algorithmic_flops_per_launch": flops}
     if args.prec.startswith("split"):
@@ -214,6 +221,268 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    return out
+
+
+
+def _timed(torch, fn):
+    """Wall time of fn() between two device synchronisations, in seconds."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def _envelope(metric, value, unit, ms, workload, dtype, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": {"workload": workload}}
+    out["config"].update(extra)
+    return out
+
+
+def run_joint_m1000(args, mp, torch, synth):
+    """M = 1000, Haar x 0.9, r = 1, E = 1.2e6 in chunks of 1e5 (120 sub-ensembles
+    of 1e4), FP32: the total-count run and the two-bin joint run (halves of
+    500 modes) on the same noise, each timed as a whole job (pack, all chunks,
+    finalize) after one untimed run."""
+    w = synth.workload_m1000()
+    bins2 = synth.contiguous_bins(w.M, 2)
+    mh, sh = synth.uniform_loss_moments(w.r, w.t, frac=0.5)
+    wh = synth.count_window(mh, sh)
+    res = {}
+    for name, kw in (("total", dict(windows=w.windows)),
+                     ("joint2", dict(bin_of_mode=bins2, d=2, mode="joint", windows=[wh, wh]))):
+        p = mp.CountsPipeline(w.T, w.r, prec="fp32", seed=w.seed, n_sub=w.n_sub,
+                              samples_per_sub=w.samples_per_sub, chunk=w.chunk, **kw)
+        p.run()
+
+        def job():
+            p.reset()
+            p.packed = False
+            p.run()
+        secs = _timed(torch, job)
+        P, _, sig = p.result()
+        res[name] = dict(s=secs, P=P, sigma=sig)
+        log(f"[bench] joint_m1000 {name}: {secs:.3f} s for E={w.E}")
+        del p
+        torch.cuda.empty_cache()
+    K = wh[1]
+    Pj = res["joint2"]["P"].reshape(K, K)
+    Pt, st = res["total"]["P"], res["total"]["sigma"]
+    m_tot = np.arange(w.windows[0][0], w.windows[0][0] + w.windows[0][1])
+    diag = np.zeros_like(Pt)
+    sums = np.add.outer(np.arange(K), np.arange(K)) + 2 * wh[0]
+    ok = (sums >= m_tot[0]) & (sums <= m_tot[-1])
+    np.add.at(diag, sums[ok] - m_tot[0], Pj[ok])
+    sj = res["joint2"]["s"]
+    return _envelope(
+        "samples·M²/s of the two-bin joint run, M=1000, FP32", w.E * w.M ** 2 / sj, "samples·M²/s",
+        1e3 * sj / (w.E / w.chunk),
+        f"M1000_t0.9_r1: E={w.E} in chunks of {w.chunk}, {w.n_sub} sub-ensembles, total window "
+        f"{tuple(w.windows[0])}, joint windows {tuple(wh)} x {tuple(wh)}", "fp32",
+        total_run_s=res["total"]["s"], joint_run_s=sj,
+        total_samples_M2_per_s=w.E * w.M ** 2 / res["total"]["s"],
+        joint_vs_total_max_abs=float(np.abs(diag - Pt).max()), total_sigma_max=float(st.max()),
+        joint_sum_P=float(Pj.sum()), joint_P_max=float(Pj.max()))
+
+
+def run_precision_m4000(args, mp, torch, synth):
+    """M = 4000, Haar x 0.95, r_j ~ U[0.5, 1.5], four equal mode blocks (their
+    marginals and the total), E = 983040 in chunks of 65536 (120 sub-ensembles
+    of 8192): every precision on the same noise, each result compared with
+    the FP64 GPU path (itself pinned to the oracle) bin by bin, in units of
+    the FP64 run's sigma_T."""
+    M, t = 4000, 0.95
+    seed = synth.SEED_BASE + 2
+    r = synth.squeezing_random_uniform(M, 0.5, 1.5, seed)
+    T = synth.transmission(M, t, seed)
+    bins = synth.contiguous_bins(M, 4)
+    N = np.sinh(r) ** 2
+    wins = []
+    for b in range(4):
+        mb = t * t * N[bins == b].sum()
+        sb = np.sqrt(mb + (t * t) ** 2 * (N[bins == b] * (2 * N[bins == b] + 1)).sum())
+        wins.append(synth.count_window(mb, sb * 1.3))
+    mt, stt = synth.uniform_loss_moments(r, t)
+    wins.append(synth.count_window(mt, stt))
+    chunk, ns = 65536, 8192
+    E = 15 * chunk
+    res = {}
+    for prec in ("fp64", "fp32", "split_bf16", "split_fp16"):
+        p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=4,
+                              mode="marginals_and_total", windows=wins, n_sub=E // ns,
+                              samples_per_sub=ns, chunk=chunk)
+        p.run_chunk(0, chunk)  # untimed: first launches
+        p.reset()
+
+        def job():
+            p.packed = False
+            p.run()
+        secs = _timed(torch, job)
+        res[prec] = (secs,) + p.result()
+        log(f"[bench] precision_m4000 {prec}: {secs:.3f} s")
+        del p
+        torch.cuda.empty_cache()
+    off = np.cumsum([0] + [k for _, k in wins])
+    s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
+    per = {}
+    for prec in ("fp32", "split_bf16", "split_fp16"):
+        secs, P = res[prec][0], res[prec][1]
+        rows = []
+        for b in range(5):
+            sl = slice(off[b], off[b + 1])
+            err = np.abs(P[sl] - P64[sl])
+            bulk = P64[sl] > 1e-3 * P64[sl].max()
+            rows.append({"dist": f"bin {b}" if b < 4 else "total", "max_abs_err": float(err.max()),
+                         "max_err_over_sigma": float((err / sig64[sl])[bulk].max()),
+                         "sigma_max": float(sig64[sl].max())})
+        per[prec] = {"run_s": secs, "samples_M2_per_s": E * M ** 2 / secs,
+                     "speedup_vs_fp64": s64 / secs, "per_distribution": rows}
+    sb = res["split_bf16"][0]
+    return _envelope(
+        "samples·M²/s, M=4000 four-bin run, split-BF16 (error vs FP64 per bin in config)",
+        E * M ** 2 / sb, "samples·M²/s", 1e3 * sb / (E / chunk),
+        f"M4000_t0.95_rU[0.5,1.5]: 4 equal bins + total, E={E} in chunks of {chunk}, "
+        f"{E // ns} sub-ensembles", "split-bf16 (fp32 acc)",
+        fp64_run_s=s64, fp64_samples_M2_per_s=E * M ** 2 / s64, precisions=per)
+
+
+def run_batched(args, mp, torch, synth):
+    """16 networks (4 each of M = 500, 1000, 2000, 4000), t ~ U[0.85, 0.99],
+    r = 1, E = 2e5 each (20 sub-ensembles of 1e4), split-FP16: one plan (a
+    captured hipGraph with one persistent grouped GEMM launch per pass over
+    chunks of 1e5) against the same networks run one after another through
+    CountsPipeline."""
+    rng = np.random.default_rng(synth.SEED_BASE + 7)
+    Ms = [500] * 4 + [1000] * 4 + [2000] * 4 + [4000] * 4
+    E, n_sub, chunk = 200_000, 20, 100_000
+    nets = []
+    for i, M in enumerate(Ms):
+        t = float(rng.uniform(0.85, 0.99))
+        r = np.ones(M)
+        mean, sd = synth.uniform_loss_moments(r, t)
+        nets.append(dict(T=synth.transmission(M, t, synth.SEED_BASE + 100 + i), r=r,
+                         seed=synth.SEED_BASE + 7, net=i, E=E, n_sub=n_sub,
+                         window=synth.count_window(mean, sd)))
+    log("[bench] batched: networks ready, creating the plan (autotunes the work-list order)")
+    t0 = time.perf_counter()
+    plan = mp.Plan(nets, prec="split_fp16", chunk=chunk)
+    create_s = time.perf_counter() - t0
+    plan.launch()
+    plan_s = min(_timed(torch, plan.launch) for _ in range(3))
+    info = plan.info()
+    seq_s, max_diff = 0.0, 0.0
+    for i, n in enumerate(nets):
+        p = mp.CountsPipeline(n["T"], n["r"], prec="split_fp16", seed=n["seed"], net=n["net"],
+                              windows=[n["window"]], n_sub=n_sub, samples_per_sub=E // n_sub,
+                              chunk=chunk)
+        p.run()
+
+        def job():
+            p.reset()
+            p.packed = False
+            p.run()
+        seq_s += _timed(torch, job)
+        P = p.result()[0]
+        max_diff = max(max_diff, float(np.abs(P - plan.result(i)[0]).max()))
+        del p
+        torch.cuda.empty_cache()
+    plan.close()
+    work = sum(E * M ** 2 for M in Ms)
+    flops = 8.0 * work
+    log(f"[bench] batched: plan {plan_s:.3f} s, sequential {seq_s:.3f} s")
+    return _envelope(
+        "samples·M²/s over 16 uneven networks in one plan, split-FP16", work / plan_s,
+        "samples·M²/s", 1e3 * plan_s,
+        "16 networks: 4 x M in {500, 1000, 2000, 4000}, t ~ U[0.85, 0.99], r = 1, E = 2e5 "
+        "each in chunks of 1e5, total counts", "split-fp16 (fp32 acc)",
+        plan_s=plan_s, sequential_s=seq_s, speedup_vs_sequential=seq_s / plan_s,
+        plan_create_s=create_s, plan_info=info, max_abs_diff_plan_vs_sequential=max_diff,
+        algorithmic_tflops_whole_job=flops / plan_s / 1e12)
+
+
+def run_surrogate(args, mp, torch, synth):
+    """The learned surrogate end to end: method-generated training sweeps
+    (M in [100, 2000], t in [0.8, 0.99], rbar in [0.5, 1.5], s_r in [0, 0.3],
+    d in {1, 2, 4}; E = 4096 each), GPU training, then screening of 256
+    candidate profiles at M = 8000, t = 0.95, d = 4 with the method
+    (E = 2^20 per judged candidate) as judge."""
+    from paper_2503_12749_amd import surrogate as sg
+    rng = np.random.default_rng(2503)
+    runner = sg.MethodRunner()
+    sweeps = sg.sample_sweeps(args.sweeps, rng)
+    t0 = time.perf_counter()
+    X, Y = sg.generate(runner, sweeps, E=4096, log_every=max(1, args.sweeps // 10))
+    gen_s = time.perf_counter() - t0
+    net = sg.Mlp(seed=3)
+    t0 = time.perf_counter()
+    hist = net.fit(X, Y, steps=300, batch=256, lr=2e-3, weight_decay=1.0, seed=2, log_every=50)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    cands = [(float(a), float(b)) for a in np.linspace(0.6, 1.4, 16) for b in np.linspace(0.0, 0.3, 16)]
+    log("[bench] surrogate: screening at M=8000")
+    res = sg.screen(net, runner, 8000, 0.95, 4, cands, 1 << 20, 8)
+    errs = []
+    for j in res["judged"]:
+        errs.append({"mean_rel_err": abs(j["predicted_mean"] - j["method_mean"]) / j["method_mean"],
+                     "var_rel_err": abs(j["predicted_var"] - j["method_var"]) / j["method_var"],
+                     "fallback": j["fallback"]})
+    per_method = res["t_method_s"] / len(res["judged"])
+    return _envelope(
+        "candidates screened per second by the surrogate, M=8000 (method time per candidate in config)",
+        len(cands) / res["t_predict_s"], "candidates/s", 1e3 * res["t_predict_s"],
+        f"surrogate: {args.sweeps} training sweeps at E=4096, screening 256 profiles at M=8000, "
+        f"t=0.95, d=4, judge E=2^20", "bf16 weights, fp32 accumulate",
+        generate_s=gen_s, train_s=train_s, loss_first_last=[hist[0][1], hist[-1][1]],
+        predict_s_256=res["t_predict_s"], method_s_per_candidate=per_method,
+        speedup_vs_method=per_method * len(cands) / res["t_predict_s"], judged=errs)
+
+
+def run_copy(args, mp, torch, synth):
+    """A plain 1 GiB device-to-device copy, three times: the reference for
+    scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    secs = [_timed(torch, lambda: dst.copy_(src)) for _ in range(3)]
+    return _envelope("GB/s of a 1 GiB device copy (counter calibration)", 2 * n / min(secs) / 1e9,
+                     "GB/s", 1e3 * min(secs), "1 GiB device-to-device copy", "u8",
+                     bytes_read=n, bytes_written=n)
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="split_bf16")
+    ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
+    ap.add_argument("--compare-steps", type=int, default=2)
+    ap.add_argument("--chunk", type=int, default=65536)
+    ap.add_argument("--M", type=int, default=8000)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="m8000",
+                    choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate", "copy"],
+                    help="m8000 (default) is the headline metric; the others measure the other "
+                         "configurations of the hot path and print their own JSON line")
+    ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sample-sharded "
+              f"multi-GPU path is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2503_12749_amd as mp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    runners = {"m8000": run_m8000, "joint_m1000": run_joint_m1000,
+               "precision_m4000": run_precision_m4000, "batched": run_batched,
+               "surrogate": run_surrogate, "copy": run_copy}
+    out = runners[args.workload](args, mp, torch, synth)
     print(json.dumps(out), flush=True)
 
 
