@@ -424,11 +424,8 @@ def run_surrogate(args, mp, torch, synth):
     cands = [(float(a), float(b)) for a in np.linspace(0.6, 1.4, 16) for b in np.linspace(0.0, 0.3, 16)]
     log("[bench] surrogate: screening at M=8000")
     res = sg.screen(net, runner, 8000, 0.95, 4, cands, 1 << 20, 8)
-    errs = []
-    for j in res["judged"]:
-        errs.append({"mean_rel_err": abs(j["predicted_mean"] - j["method_mean"]) / j["method_mean"],
-                     "var_rel_err": abs(j["predicted_var"] - j["method_var"]) / j["method_var"],
-                     "fallback": j["fallback"]})
+    errs = [{k: j[k] for k in ("mean_rel_err", "var_rel_err", "baseline_mean_rel_err",
+                               "baseline_var_rel_err", "fallback")} for j in res["judged"]]
     per_method = res["t_method_s"] / len(res["judged"])
     return _envelope(
         "candidates screened per second by the surrogate, M=8000 (method time per candidate in config)",
@@ -437,7 +434,9 @@ def run_surrogate(args, mp, torch, synth):
         f"t=0.95, d=4, judge E=2^20", "bf16 weights, fp32 accumulate",
         generate_s=gen_s, train_s=train_s, loss_first_last=[hist[0][1], hist[-1][1]],
         predict_s_256=res["t_predict_s"], method_s_per_candidate=per_method,
-        speedup_vs_method=per_method * len(cands) / res["t_predict_s"], judged=errs)
+        speedup_vs_method=per_method * len(cands) / res["t_predict_s"],
+        fallback_rule="method replaces a prediction off by > 1 % (mean) or > 5 % (variance)",
+        judged=errs)
 
 
 def run_copy(args, mp, torch, synth):

@@ -282,12 +282,15 @@ class Mlp:
 
 # ---------------------------------------------------------------- screening
 
-def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_sigma=4.0, net0=100000):
+def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_mean=0.01, tol_var=0.05,
+           net0=100000):
     """Predicts the bin-0 cumulants of every candidate (rbar, sr) profile,
     selects the `top` candidates whose Fano factor (variance / mean) is
-    closest to the middle of the predicted range, runs the method on them,
-    and keeps the method's value wherever the predicted mean misses by more
-    than tol_sigma of the method's own error."""
+    closest to the middle of the predicted range, and runs the method on
+    them.  The method's values replace a prediction (fallback) when the
+    predicted mean or variance misses the method's by more than tol_mean or
+    tol_var relative.  Each judged entry also carries the error of the
+    independent-mode baseline alone, the part the network corrects."""
     profs = [runner.profile(M, rb, sr, net0 + q) for q, (rb, sr) in enumerate(candidates)]
     t0 = time.perf_counter()
     X = np.stack([features(M, t, rb, sr, d) for rb, sr in candidates])
@@ -305,11 +308,17 @@ def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_sigma=4.0, net0=1
                                         chunk=min(E_judge, 65536), n_sub=max(2, E_judge // 8192))
         kb, _ = moments_from_targets(M, t, profs[q], d, yq)
         pb, _ = mom[q]
+        base, _ = moments_from_targets(M, t, profs[q], d, np.ones(2 * N_CUM))
         sig_mean = float(np.sqrt(((m - kb[0]) ** 2 * s ** 2).sum()))
-        miss = abs(pb[0] - kb[0]) > tol_sigma * max(sig_mean, 1e-12)
+        e_mean = abs(pb[0] - kb[0]) / kb[0]
+        e_var = abs(pb[1] - kb[1]) / kb[1]
         judged.append(dict(candidate=[rb, sr], predicted_mean=float(pb[0]),
                            predicted_var=float(pb[1]), method_mean=float(kb[0]),
-                           method_var=float(kb[1]), sigma_mean=sig_mean, fallback=bool(miss)))
+                           method_var=float(kb[1]), sigma_mean=sig_mean,
+                           mean_rel_err=float(e_mean), var_rel_err=float(e_var),
+                           baseline_mean_rel_err=float(abs(base[0] - kb[0]) / kb[0]),
+                           baseline_var_rel_err=float(abs(base[1] - kb[1]) / kb[1]),
+                           fallback=bool(e_mean > tol_mean or e_var > tol_var)))
     t_method = time.perf_counter() - t0
     return dict(t_predict_s=t_pred, t_method_s=t_method, n_candidates=len(candidates),
                 judged=judged)
