@@ -460,7 +460,7 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=65536)
     ap.add_argument("--M", type=int, default=8000)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="m8000",
                     choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate", "copy"],
