@@ -27,6 +27,11 @@ constexpr int kSBlk = 64;       // samples per workgroup of the fused kernel
 constexpr int kCountThreads = 256;
 constexpr int kEpt = 4;         // accumulator entries per thread per pass
 constexpr int kMaxDist = MP_MAX_BINS + 1;
+// Terms of a sample's characteristic function with log-magnitude below kLogEps
+// (e^-46 ~ 1e-20) are not evaluated.  The magnitude test is exact, so each
+// sub-ensemble mean of chi changes by less than 1e-20 per grid point and P(m)
+// (an average of those means) by less than 1e-20 absolute.
+constexpr double kLogEps = -46.0;
 
 struct CountsParams {
   int M;
@@ -235,13 +240,19 @@ __global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, co
       for (int u = 0; u < kEpt; ++u) {
         if (dq[u] < 0) continue;
         const double nr = s_nb[i][dq[u]][0], ni = s_nb[i][dq[u]][1];
+        // log-magnitudes of the two terms are xr + c1 and c2 - xr; a term
+        // below e^kLogEps is skipped
         const double xr = cm1[u] * nr - sn[u] * ni;
+        const bool t1 = xr + c1 > kLogEps, t2 = !skip2 && c2 - xr > kLogEps;
+        if (!(t1 || t2)) continue;
         const double xi = cm1[u] * ni + sn[u] * nr;
         double tr, ti;
-        cis_exp<F64>(xr + c1, xi - thl[u], tr, ti);
-        ar[u] += tr;
-        ai[u] += ti;
-        if (!skip2) {
+        if (t1) {
+          cis_exp<F64>(xr + c1, xi - thl[u], tr, ti);
+          ar[u] += tr;
+          ai[u] += ti;
+        }
+        if (t2) {
           cis_exp<F64>(c2 - xr, -xi - thl[u], tr, ti);
           ar[u] += tr;
           ai[u] += ti;
@@ -304,7 +315,6 @@ __global__ void counts_reduce(CountsParams p, const double* __restrict__ partial
 // other bin; the chunk's band is the maximum over its samples.  Terms outside
 // the band are bounded by that threshold, not approximated.
 
-constexpr double kLogEps = -46.0;
 
 struct Joint2Params {
   int M;
