@@ -439,6 +439,159 @@ def run_surrogate(args, mp, torch, synth):
         judged=errs)
 
 
+def _golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        return json.load(f)
+
+
+def run_plusp_m20(args, mp, torch, synth):
+    """Appendix A comparison: a lossless 20-mode Haar network with r = 0.5 on
+    every mode, E = 2.4e8 samples (120 sub-ensembles of 2e6) through the FP64
+    path.  From the same samples: the total-count distribution with the
+    matrix-P and the +P estimators (errors against the exact law at
+    E = 2.4e5 and 2.4e8), and densities of the per-sample observables
+    G_+(3), G_+(4) (bins of 0.05) and G_0(4) (bins of 0.001)."""
+    M, r0 = 20, 0.5
+    seed = synth.SEED_BASE + 11
+    T = synth.haar_unitary(M, seed)
+    r = np.full(M, r0)
+    n_sub, ns, chunk = 120, 2_000_000, 1_000_000
+    E = n_sub * ns
+    small = 240_000  # the smaller ensemble of the comparison: 120 x 2000
+    win = (0, 64)
+    ref = np.asarray(_golden("lossless_m20_r0.5.json")["P"])
+    hists = {"G+(3)": ("plus_p", 3, -20.0 + 1e-9, 0.05, 800),
+             "G+(4)": ("plus_p", 4, -20.0 + 1e-9, 0.05, 800),
+             "G0(4)": ("matrix_p", 4, -0.05 + 1e-9, 0.001, 500)}
+    pipes = {est: mp.CountsPipeline(T, r, prec="fp64", seed=seed, windows=[win], n_sub=n_sub,
+                                    samples_per_sub=ns, chunk=chunk, est=est)
+             for est in ("matrix_p", "plus_p")}
+    p = pipes["matrix_p"]
+    nq = torch.empty(chunk * 2, dtype=torch.float64, device="cuda:0")
+    hbuf = {k: torch.zeros(n_sub * (v[4] + 2), dtype=torch.float64, device="cuda:0")
+            for k, v in hists.items()}
+    allm = np.zeros(M, dtype=np.int32)
+    # the small ensemble: its own sub-ensembles (120 x 2000) over the first samples
+    small_p = {est: mp.CountsPipeline(T, r, prec="fp64", seed=seed, windows=[win], n_sub=120,
+                                      samples_per_sub=small // 120, chunk=small, est=est)
+               for est in ("matrix_p", "plus_p")}
+    for est, sp in small_p.items():
+        sp.run()
+    t0 = time.perf_counter()
+    mp.mp_pack_transmission(M, p.T, "fp64", p.ws_prop)
+    for g in range(0, E, chunk):
+        mp.mp_sample(M, g, chunk, p.r, seed, 0, "fp64", p.ab, p.n)
+        mp.mp_propagate_packed(M, chunk, "fp64", p.ab, p.C, p.ws_prop)
+        for est, q in pipes.items():
+            mp.mp_binned_counts(M, chunk, p.C, p.n, "fp64", est, 1, allm, "joint", [win[0]],
+                                [win[1]], n_sub, ns, g, q.acc, q.ws_counts)
+        mp.mp_occupations(M, chunk, p.C, "fp64", 1, allm, "marginals", nq)
+        for k, (est, m, lo, w, nb) in hists.items():
+            mp.mp_observable_histogram(chunk, p.n, nq, 1, 0, m, est, lo, w, nb, n_sub, ns, g,
+                                       hbuf[k])
+        if (g // chunk) % 40 == 0:
+            log(f"[bench] plusp_m20: {g + chunk} / {E} samples")
+    for q in pipes.values():
+        q.finalize()
+    torch.cuda.synchronize()
+    run_s = time.perf_counter() - t0
+    res = {}
+    for label, group in (("E=2.4e5", small_p), ("E=2.4e8", pipes)):
+        for est, q in group.items():
+            P, _, sig = q.result()
+            err = np.abs(P - ref)
+            bulk = ref > 1e-6 * ref.max()
+            res[f"{est} {label}"] = {"max_abs_err_vs_exact": float(err.max()),
+                                     "sigma_T_max": float(np.nanmax(sig)),
+                                     "max_err_over_sigma_bulk": float((err / sig)[bulk].max()),
+                                     "max_abs_P_odd_m": float(np.abs(P[1::2]).max()),
+                                     "sum_P": float(P.sum())}
+    dens = {}
+    for k, (est, m, lo, w, nb) in hists.items():
+        d = torch.empty(nb + 2, dtype=torch.float64, device="cuda:0")
+        s = torch.empty(nb + 2, dtype=torch.float64, device="cuda:0")
+        mp.mp_subensemble_stats(n_sub, ns, nb + 2, 1, 1.0 / w, hbuf[k], d, s)
+        counts = hbuf[k].cpu().numpy().reshape(n_sub, nb + 2).sum(0)
+        dd = d.cpu().numpy()
+        centers = lo + w * (np.arange(nb) + 0.5)
+        occupied = np.flatnonzero(counts[1:-1])
+        inner = (centers > -0.5) & (centers < 0.5)
+        entry = {"below_range": int(counts[0]), "above_range": int(counts[-1]),
+                 "lowest_occupied_bin_center": float(centers[occupied[0]]) if occupied.size else None,
+                 "highest_occupied_bin_center": float(centers[occupied[-1]]) if occupied.size else None,
+                 "fraction_outside_[-0.5,0.5]": float(1.0 - counts[1:-1][inner].sum() / E)}
+        if k == "G0(4)":
+            lo_peak = (centers < 0.1)
+            hi_peak = (centers > 0.3)
+            entry["peak_near_0"] = float(centers[lo_peak][np.argmax(dd[1:-1][lo_peak])])
+            entry["peak_high"] = float(centers[hi_peak][np.argmax(dd[1:-1][hi_peak])])
+        dens[k] = entry
+    mpe = res["matrix_p E=2.4e8"]["max_abs_err_vs_exact"]
+    ppe = res["plus_p E=2.4e8"]["max_abs_err_vs_exact"]
+    return _envelope(
+        "max |P - P_exact|, +P over matrix-P, lossless M=20, r=0.5, E=2.4e8", ppe / mpe,
+        "ratio", 1e3 * run_s,
+        "M20_r0.5 lossless Haar, FP64, E=2.4e8 in 120 sub-ensembles of 2e6 (comparison at 2.4e5: "
+        "120 x 2000), total counts m = 0..63", "f64",
+        run_s=run_s, estimators=res, densities=dens,
+        density_bins={k: {"estimator": v[0], "m": v[1], "o_min": v[2], "width": v[3],
+                          "n_bins": v[4]} for k, v in hists.items()})
+
+
+def run_moments_m1000(args, mp, torch, synth):
+    """Many tests from one ensemble (main text): the M = 1000, t = 0.9, r = 1
+    FP32 workload (E = 1.2e6, chunks of 1e5) yields the two half-bin
+    marginals and the total count distribution and, from the same samples,
+    the normally ordered moments k = 1..4 of the halves and the total.  The
+    first two are compared with the closed forms; timing with and without the
+    moments."""
+    w = synth.workload_m1000()
+    bins = synth.contiguous_bins(w.M, 2)
+    mh, sh = synth.uniform_loss_moments(w.r, w.t, frac=0.5)
+    wh = synth.count_window(mh, sh)
+    wins = [wh, wh, tuple(w.windows[0])]
+    kmax, nd = 4, 3
+    p = mp.CountsPipeline(w.T, w.r, prec="fp32", seed=w.seed, bin_of_mode=bins, d=2,
+                          mode="marginals_and_total", windows=wins, n_sub=w.n_sub,
+                          samples_per_sub=w.samples_per_sub, chunk=w.chunk)
+    nq = torch.empty(w.chunk * nd * 2, dtype=torch.float64, device="cuda:0")
+    acc = torch.zeros(w.n_sub * nd * kmax * 2, dtype=torch.float64, device="cuda:0")
+
+    def job(with_moments):
+        p.reset()
+        acc.zero_()
+        p.packed = False
+        for g in range(0, w.E, w.chunk):
+            p.run_chunk(g, w.chunk)
+            if with_moments:
+                mp.mp_occupations(w.M, w.chunk, p.C, "fp32", 2, bins, "marginals_and_total", nq)
+                mp.mp_moments_accumulate(w.chunk, p.n, nq, nd, kmax, "matrix_p", w.n_sub,
+                                         w.samples_per_sub, g, acc)
+        p.finalize()
+    job(True)
+    base_s = _timed(torch, lambda: job(False))
+    full_s = _timed(torch, lambda: job(True))
+    mean = torch.empty(nd * kmax * 2, dtype=torch.float64, device="cuda:0")
+    sig = torch.empty(nd * kmax, dtype=torch.float64, device="cuda:0")
+    mp.mp_subensemble_stats(w.n_sub, w.samples_per_sub, nd * kmax, 2, 1.0, acc, mean, sig)
+    mom = mean.cpu().numpy().reshape(nd, kmax, 2)[..., 0]
+    smom = sig.cpu().numpy().reshape(nd, kmax)
+    gold = _golden("m1000_count_moments.json")["dists"]
+    rows = []
+    for q in range(nd):
+        mu, var = gold[q]["mean"], gold[q]["var"]
+        f2_exact = var - mu + mu * mu  # <:n^2:> = Var - mean + mean^2
+        rows.append({"dist": gold[q]["name"], "moments": mom[q].tolist(), "sigma_T": smom[q].tolist(),
+                     "k1_minus_exact_over_sigma": float((mom[q][0] - mu) / smom[q][0]),
+                     "k2_minus_exact_over_sigma": float((mom[q][1] - f2_exact) / smom[q][1])})
+    return _envelope(
+        "extra time of moments k=1..4 for 2 bins + total from the counts ensemble, M=1000, FP32",
+        (full_s - base_s) / base_s, "fraction of the counts run", 1e3 * full_s,
+        f"M1000_t0.9_r1: E={w.E} in chunks of {w.chunk}, {w.n_sub} sub-ensembles, halves "
+        f"window {tuple(wh)}, total window {tuple(w.windows[0])}", "fp32 (fp64 moments)",
+        counts_run_s=base_s, counts_and_moments_run_s=full_s, moments=rows)
+
+
 def run_copy(args, mp, torch, synth):
     """A plain 1 GiB device-to-device copy, three times: the reference for
     scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
@@ -463,7 +616,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="m8000",
-                    choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate", "copy"],
+                    choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate",
+                             "plusp_m20", "moments_m1000", "copy"],
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
@@ -480,7 +634,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     runners = {"m8000": run_m8000, "joint_m1000": run_joint_m1000,
                "precision_m4000": run_precision_m4000, "batched": run_batched,
-               "surrogate": run_surrogate, "copy": run_copy}
+               "surrogate": run_surrogate, "plusp_m20": run_plusp_m20,
+               "moments_m1000": run_moments_m1000, "copy": run_copy}
     out = runners[args.workload](args, mp, torch, synth)
     print(json.dumps(out), flush=True)
 

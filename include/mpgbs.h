@@ -218,6 +218,79 @@ mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int3
                              double* P_im, double* sigma, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* ---------------------------------------------------------------- per-sample observables */
+
+#define MP_MAX_MOMENTS 8 /* orders per mp_moments_accumulate call */
+
+/*
+ * Occupation of each distribution for every sample of a chunk (main text:
+ * the grouped occupations n_S = sum over the counted modes of alpha'_j
+ * beta'_j that enter the pattern observables): n_q sums over the modes of
+ * bin q (q < d) or over all d bins (the total, q = d, with
+ * MP_MARGINALS_AND_TOTAL).  The same ensemble then serves every statistic
+ * below.
+ *
+ *   C, M, E, prec  as written by mp_propagate for this chunk
+ *   d, bin_of_mode as for mp_binned_counts (host int32[M]); at most
+ *                  MP_MAX_RUNS contiguous mode runs
+ *   mode           MP_MARGINALS (n_dist = d) or MP_MARGINALS_AND_TOTAL
+ *                  (n_dist = d + 1); MP_JOINT is rejected
+ *   nq             device FP64, E * n_dist * 2, written: (Re, Im) n_q of chunk
+ *                  sample k at nq[2 (k n_dist + q)]
+ */
+mp_status mp_occupations(int32_t M, int64_t E, const void* C, mp_precision prec, int32_t d,
+                         const int32_t* bin_of_mode, mp_bin_mode mode, double* nq, void* stream);
+
+/*
+ * Normally ordered moments <:n_q^k:>, k = 1..kmax (main text, eq. moment):
+ * per sample n_q^k, with the weight tanh n on odd orders for the
+ * parity-projected estimator (the M = 2 projector weights) and no weight for
+ * +P, summed per sub-ensemble in a fixed order.
+ *
+ *   n, nq          per-sample global n (mp_sample) and occupations
+ *                  (mp_occupations) of the chunk's E samples, n_dist of them
+ *   kmax           1..MP_MAX_MOMENTS
+ *   n_sub, samples_per_sub, e0  as for mp_binned_counts
+ *   acc            device FP64, n_sub * n_dist * kmax * 2 (re, im), layout
+ *                  [s][q][k - 1]; caller-zeroed, added into
+ * Means and sigma_T: mp_subensemble_stats(ncomp = 2, scale = 1).
+ */
+mp_status mp_moments_accumulate(int64_t E, const double* n, const double* nq, int32_t n_dist,
+                                int32_t kmax, mp_estimator est, int32_t n_sub,
+                                int64_t samples_per_sub, int64_t e0, double* acc, void* stream);
+
+/*
+ * Histogram of a per-sample observable (Appendix A, the binned probability
+ * density of stochastic trajectories, eq. gen_probability_density): Re G of
+ * distribution q at count m, G = g0 n_q^m e^{-n_q} / m! for the
+ * parity-projected estimator (eq. c-number-variable for one group) or
+ * n_q^m e^{-n_q} / m! for +P (eq. phase_space_projector), into n_bins bins
+ * of width `width` starting at o_min.  Bin 0 counts values below o_min, bin
+ * n_bins + 1 values at or above o_min + n_bins width and non-finite values.
+ *
+ *   hist           device FP64, n_sub * (n_bins + 2), layout [s][bin];
+ *                  caller-zeroed, added into; the counts are exact integers
+ * Densities and sigma_T: mp_subensemble_stats(ncomp = 1, scale = 1 / width).
+ */
+mp_status mp_observable_histogram(int64_t E, const double* n, const double* nq, int32_t n_dist,
+                                  int32_t q, int32_t m, mp_estimator est, double o_min,
+                                  double width, int32_t n_bins, int32_t n_sub,
+                                  int64_t samples_per_sub, int64_t e0, double* hist,
+                                  void* stream);
+
+/*
+ * Sub-ensemble statistics (Appendix A): for each of n_vals values,
+ *   mean_v  = (1 / n_sub) sum_s scale acc[s][v] / samples_per_sub,
+ *   sigma_v = sd over s of the real part of scale acc[s][v] / samples_per_sub,
+ *             divided by sqrt(n_sub) (NaN when n_sub = 1).
+ *   ncomp  1 (real acc, e.g. histograms) or 2 ((re, im) pairs)
+ *   acc    device FP64, n_sub * n_vals * ncomp
+ *   mean   device FP64, n_vals * ncomp;  sigma  device FP64, n_vals
+ */
+mp_status mp_subensemble_stats(int32_t n_sub, int64_t samples_per_sub, int64_t n_vals,
+                               int32_t ncomp, double scale, const double* acc, double* mean,
+                               double* sigma, void* stream);
+
 /* ---------------------------------------------------------------- batching */
 
 /* One network of a batched plan: total counts of all M outputs on the window

@@ -17,7 +17,8 @@ from ._lib import BIN_MODES, ESTIMATORS, MPError, PRECISIONS, i32_array
 
 __all__ = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
-    "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
+    "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_occupations",
+    "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
     "mp_counts_finalize", "mp_finalize_workspace", "mp_version", "CountsPipeline", "Plan", "MPError",
 ]
 
@@ -106,6 +107,34 @@ def mp_binned_counts(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub
         M, E, _ptr(C), _ptr(n), _prec(prec), _est(est), d, i32_array(bin_of_mode), _mode(mode),
         i32_array(m_lo), i32_array(K), n_sub, samples_per_sub, e0, _ptr(acc), _ptr(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def mp_occupations(M, E, C, prec, d, bin_of_mode, mode, nq, stream=None):
+    """bin_of_mode: host integer sequence; nq: device float64 (E * n_dist * 2)."""
+    _lib.check(_lib.load().mp_occupations(M, E, _ptr(C), _prec(prec), d, i32_array(bin_of_mode),
+                                          _mode(mode), _ptr(nq), _stream(stream)))
+
+
+def mp_moments_accumulate(E, n, nq, n_dist, kmax, est, n_sub, samples_per_sub, e0, acc,
+                          stream=None):
+    _lib.check(_lib.load().mp_moments_accumulate(E, _ptr(n), _ptr(nq), n_dist, kmax, _est(est),
+                                                 n_sub, samples_per_sub, e0, _ptr(acc),
+                                                 _stream(stream)))
+
+
+def mp_observable_histogram(E, n, nq, n_dist, q, m, est, o_min, width, n_bins, n_sub,
+                            samples_per_sub, e0, hist, stream=None):
+    _lib.check(_lib.load().mp_observable_histogram(E, _ptr(n), _ptr(nq), n_dist, q, m, _est(est),
+                                                   float(o_min), float(width), n_bins, n_sub,
+                                                   samples_per_sub, e0, _ptr(hist),
+                                                   _stream(stream)))
+
+
+def mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean, sigma,
+                         stream=None):
+    _lib.check(_lib.load().mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp,
+                                                float(scale), _ptr(acc), _ptr(mean), _ptr(sigma),
+                                                _stream(stream)))
 
 
 def mp_finalize_workspace(d: int, mode, K, n_sub: int) -> int:

@@ -4,6 +4,7 @@
 // thread-local message for mp_last_error().
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -45,6 +46,19 @@ mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, 
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
                                  double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
 size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
+mp_status occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, int32_t d,
+                             const int32_t* bin_of_mode, mp_bin_mode mode, double* nq,
+                             hipStream_t stream);
+mp_status moments_launch(int64_t E, const double* n, const double* nq, int32_t n_dist,
+                         int32_t kmax, mp_estimator est, int64_t ns, int64_t e0, double* acc,
+                         hipStream_t stream);
+mp_status histogram_launch(int64_t E, const double* n, const double* nq, int32_t n_dist, int32_t q,
+                           int32_t m, mp_estimator est, double o_min, double width,
+                           int32_t n_bins, int64_t ns, int64_t e0, double* hist,
+                           hipStream_t stream);
+mp_status subensemble_stats_launch(int32_t n_sub, int64_t ns, int64_t n_vals, int32_t ncomp,
+                                   double scale, const double* acc, double* mean, double* sigma,
+                                   hipStream_t stream);
 
 int64_t mlp_param_count(const mp_mlp_shape* s);
 size_t mlp_workspace(const mp_mlp_shape* s, int32_t batch);
@@ -223,6 +237,91 @@ mp_status mp_counts_finalize(int32_t d, mp_bin_mode mode, const int32_t* K, int3
                "mp_counts_finalize: workspace must be 256-byte aligned");
   return counts_finalize_launch(d, mode, K, n_sub, samples_per_sub, acc, P_re, P_im, sigma,
                                 workspace, ws_bytes, (hipStream_t)stream);
+}
+
+mp_status mp_occupations(int32_t M, int64_t E, const void* C, mp_precision prec, int32_t d,
+                         const int32_t* bin_of_mode, mp_bin_mode mode, double* nq, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1 && E >= 1, MP_ERR_ARG, "mp_occupations: M and E must be >= 1");
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_occupations: unknown precision %d", (int)prec);
+  MP_CHECK_ARG(d >= 1 && d <= MP_MAX_BINS, MP_ERR_ARG, "mp_occupations: d = %d outside [1, %d]", d,
+               MP_MAX_BINS);
+  MP_CHECK_ARG(mode == MP_MARGINALS || mode == MP_MARGINALS_AND_TOTAL, MP_ERR_ARG,
+               "mp_occupations: mode must be MP_MARGINALS or MP_MARGINALS_AND_TOTAL");
+  MP_CHECK_ARG(C && bin_of_mode && nq, MP_ERR_ARG, "mp_occupations: null pointer argument");
+  MP_CHECK_ARG(aligned(C, 16) && aligned(nq, 8), MP_ERR_ARG,
+               "mp_occupations: C must be 16-byte and nq 8-byte aligned");
+  for (int j = 0; j < M; ++j)
+    MP_CHECK_ARG(bin_of_mode[j] >= -1 && bin_of_mode[j] < d, MP_ERR_ARG,
+                 "mp_occupations: bin_of_mode[%d] = %d outside [-1, %d)", j, bin_of_mode[j], d);
+  return occupations_launch(M, E, C, prec, d, bin_of_mode, mode, nq, (hipStream_t)stream);
+}
+
+// Shared checks of the per-sample statistics calls.
+static bool sample_stat_args(const char* who, int64_t E, const double* n, const double* nq,
+                             int32_t n_dist, mp_estimator est, int32_t n_sub, int64_t ns,
+                             int64_t e0, const double* out) {
+  if (E < 1 || !n || !nq || !out) {
+    set_error("%s: E must be >= 1 and pointers non-null", who);
+    return false;
+  }
+  if (n_dist < 1 || n_dist > MP_MAX_BINS + 1) {
+    set_error("%s: n_dist = %d outside [1, %d]", who, n_dist, MP_MAX_BINS + 1);
+    return false;
+  }
+  if (est != MP_MATRIX_P && est != MP_PLUS_P) {
+    set_error("%s: unknown estimator %d", who, (int)est);
+    return false;
+  }
+  if (n_sub < 1 || ns < 1 || e0 < 0 || (e0 + E - 1) / ns >= n_sub) {
+    set_error("%s: samples [%lld, %lld) do not fit n_sub = %d sub-ensembles of %lld", who,
+              (long long)e0, (long long)(e0 + E), n_sub, (long long)ns);
+    return false;
+  }
+  return true;
+}
+
+mp_status mp_moments_accumulate(int64_t E, const double* n, const double* nq, int32_t n_dist,
+                                int32_t kmax, mp_estimator est, int32_t n_sub,
+                                int64_t samples_per_sub, int64_t e0, double* acc, void* stream) {
+  clear_error();
+  if (!sample_stat_args("mp_moments_accumulate", E, n, nq, n_dist, est, n_sub, samples_per_sub, e0,
+                        acc))
+    return MP_ERR_ARG;
+  MP_CHECK_ARG(kmax >= 1 && kmax <= MP_MAX_MOMENTS, MP_ERR_ARG,
+               "mp_moments_accumulate: kmax = %d outside [1, %d]", kmax, MP_MAX_MOMENTS);
+  return moments_launch(E, n, nq, n_dist, kmax, est, samples_per_sub, e0, acc, (hipStream_t)stream);
+}
+
+mp_status mp_observable_histogram(int64_t E, const double* n, const double* nq, int32_t n_dist,
+                                  int32_t q, int32_t m, mp_estimator est, double o_min,
+                                  double width, int32_t n_bins, int32_t n_sub,
+                                  int64_t samples_per_sub, int64_t e0, double* hist,
+                                  void* stream) {
+  clear_error();
+  if (!sample_stat_args("mp_observable_histogram", E, n, nq, n_dist, est, n_sub, samples_per_sub,
+                        e0, hist))
+    return MP_ERR_ARG;
+  MP_CHECK_ARG(q >= 0 && q < n_dist && m >= 0, MP_ERR_ARG,
+               "mp_observable_histogram: q = %d outside [0, %d) or m = %d < 0", q, n_dist, m);
+  MP_CHECK_ARG(n_bins >= 1 && width > 0.0 && std::isfinite(width) && std::isfinite(o_min),
+               MP_ERR_ARG, "mp_observable_histogram: need n_bins >= 1 and finite o_min, width > 0");
+  return histogram_launch(E, n, nq, n_dist, q, m, est, o_min, width, n_bins, samples_per_sub, e0,
+                          hist, (hipStream_t)stream);
+}
+
+mp_status mp_subensemble_stats(int32_t n_sub, int64_t samples_per_sub, int64_t n_vals,
+                               int32_t ncomp, double scale, const double* acc, double* mean,
+                               double* sigma, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(n_sub >= 1 && samples_per_sub >= 1 && n_vals >= 1, MP_ERR_ARG,
+               "mp_subensemble_stats: n_sub, samples_per_sub and n_vals must be >= 1");
+  MP_CHECK_ARG(ncomp == 1 || ncomp == 2, MP_ERR_ARG, "mp_subensemble_stats: ncomp = %d not 1 or 2",
+               ncomp);
+  MP_CHECK_ARG(acc && mean && sigma && std::isfinite(scale), MP_ERR_ARG,
+               "mp_subensemble_stats: null pointer or non-finite scale");
+  return subensemble_stats_launch(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean, sigma,
+                                  (hipStream_t)stream);
 }
 
 int64_t mp_mlp_param_count(const mp_mlp_shape* shape) {

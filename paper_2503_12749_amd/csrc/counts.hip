@@ -117,6 +117,47 @@ __device__ inline void run_sum(const CT* __restrict__ ca, const CT* __restrict__
   im = wave_sum(si);
 }
 
+// Occupations of one sample: nb[b] = sum of n'_j over the modes of bin b
+// (every lane holds the wave-reduced sums).
+template <typename CT>
+__device__ inline void sample_bin_sums(const CountsParams& p, const CT* __restrict__ ca,
+                                       const CT* __restrict__ cb, int lane,
+                                       double (&nb)[MP_MAX_BINS][2]) {
+#pragma unroll
+  for (int b = 0; b < MP_MAX_BINS; ++b) nb[b][0] = nb[b][1] = 0.0;
+  for (int q = 0; q < p.n_runs; ++q) {
+    double re, im;
+    run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+    const int bq = p.run_bin[q];
+#pragma unroll
+    for (int b = 0; b < MP_MAX_BINS; ++b)
+      if (b == bq) {
+        nb[b][0] += re;
+        nb[b][1] += im;
+      }
+  }
+}
+
+// Occupation feeding distribution q: bin dist_src[q], or the total over the
+// d bins when dist_src[q] = -1.
+__device__ inline void dist_occupation(const CountsParams& p, const double (&nb)[MP_MAX_BINS][2],
+                                       int q, double& vr, double& vi) {
+  double tr = 0.0, ti = 0.0;
+  for (int b = 0; b < p.d; ++b) {
+    tr += nb[b][0];
+    ti += nb[b][1];
+  }
+  vr = tr;
+  vi = ti;
+  const int src = p.dist_src[q];
+#pragma unroll
+  for (int b = 0; b < MP_MAX_BINS; ++b)
+    if (b == src) {
+      vr = nb[b][0];
+      vi = nb[b][1];
+    }
+}
+
 __device__ inline double reduce_2pi(double ph) {
   constexpr double kTwoPi = 6.283185307179586476925286766559;
   constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
@@ -159,37 +200,9 @@ __global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, co
     const CT* ca = C + k * ldc;
     const CT* cb = C + (p.E + k) * ldc;
     double nb[MP_MAX_BINS][2];
-#pragma unroll
-    for (int b = 0; b < MP_MAX_BINS; ++b) nb[b][0] = nb[b][1] = 0.0;
-    for (int q = 0; q < p.n_runs; ++q) {
-      double re, im;
-      run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
-      const int bq = p.run_bin[q];
-#pragma unroll
-      for (int b = 0; b < MP_MAX_BINS; ++b)
-        if (b == bq) {
-          nb[b][0] += re;
-          nb[b][1] += im;
-        }
-    }
+    sample_bin_sums<CT>(p, ca, cb, lane, nb);
     if (lane == 0) {
-      double tr = 0.0, ti = 0.0;
-      for (int b = 0; b < p.d; ++b) {
-        tr += nb[b][0];
-        ti += nb[b][1];
-      }
-      for (int q = 0; q < p.n_dist; ++q) {
-        const int src = p.dist_src[q];  // -1: total over all bins
-        double vr = tr, vi = ti;
-#pragma unroll
-        for (int b = 0; b < MP_MAX_BINS; ++b)
-          if (b == src) {
-            vr = nb[b][0];
-            vi = nb[b][1];
-          }
-        s_nb[i][q][0] = vr;
-        s_nb[i][q][1] = vi;
-      }
+      for (int q = 0; q < p.n_dist; ++q) dist_occupation(p, nb, q, s_nb[i][q][0], s_nb[i][q][1]);
       const double n = nglob[k];
       if (p.est == MP_PLUS_P) {
         s_c1[i] = 0.0;
@@ -787,6 +800,26 @@ static int64_t plan_tiles(CountsParams& p) {
   return (int64_t)p.t_first + (int64_t)p.n_mid * p.t_mid + p.t_last;
 }
 
+// Contiguous mode runs of the bins (modes with bin -1 are skipped); false if
+// there are more than MP_MAX_RUNS.
+static bool fill_runs(CountsParams& p, int32_t M, const int32_t* bin_of_mode) {
+  p.n_runs = 0;
+  for (int j = 0; j < M;) {
+    const int b = bin_of_mode[j];
+    int j2 = j + 1;
+    while (j2 < M && bin_of_mode[j2] == b) ++j2;
+    if (b >= 0) {
+      if (p.n_runs >= MP_MAX_RUNS) return false;
+      p.run_lo[p.n_runs] = j;
+      p.run_hi[p.n_runs] = j2;
+      p.run_bin[p.n_runs] = b;
+      ++p.n_runs;
+    }
+    j = j2;
+  }
+  return true;
+}
+
 size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
                         int64_t ns, int64_t e0) {
   if (!K || d < 1 || d > MP_MAX_BINS || E < 1 || ns < 1 || e0 < 0) return 0;
@@ -818,21 +851,9 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
                          ws_bytes, stream);
   MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
                "mp_binned_counts: joint distributions need d <= 2 (d = %d)", d);
-  // contiguous runs of each bin
-  p.n_runs = 0;
-  for (int j = 0; j < M;) {
-    const int b = bin_of_mode[j];
-    int j2 = j + 1;
-    while (j2 < M && bin_of_mode[j2] == b) ++j2;
-    if (b >= 0) {
-      MP_CHECK_ARG(p.n_runs < MP_MAX_RUNS, MP_ERR_UNSUPPORTED,
-                   "mp_binned_counts: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
-      p.run_lo[p.n_runs] = j;
-      p.run_hi[p.n_runs] = j2;
-      p.run_bin[p.n_runs] = b;
-      ++p.n_runs;
-    }
-    j = j2;
+  if (!fill_runs(p, M, bin_of_mode)) {
+    set_error("mp_binned_counts: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
+    return MP_ERR_UNSUPPORTED;
   }
   p.n_dist = mode == MP_JOINT ? 1 : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
   p.off[0] = 0;
@@ -905,6 +926,238 @@ mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, 
   hipLaunchKernelGGL(counts_finalize, dim3(p.entries), dim3(256), 0, stream, p, acc, P_re, P_im,
                      sigma);
   MP_HIP_LAUNCH_CHECK("mp_counts_finalize launch");
+  return MP_OK;
+}
+
+
+// ---------------------------------------------------------------- per-sample observables
+
+// Occupation of every distribution for every sample of the chunk (wave per
+// sample): nq[(k n_dist + q) 2 + {0, 1}] = (Re, Im) n_q of chunk sample k.
+template <typename CT>
+__global__ __launch_bounds__(256) void occupations_kernel(CountsParams p, const CT* __restrict__ C,
+                                                          double* __restrict__ nq) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  if (k >= p.E) return;
+  const int64_t ldc = 2 * p.ldm;
+  double nb[MP_MAX_BINS][2];
+  sample_bin_sums<CT>(p, C + k * ldc, C + (p.E + k) * ldc, lane, nb);
+  if (lane == 0)
+    for (int q = 0; q < p.n_dist; ++q) {
+      double vr, vi;
+      dist_occupation(p, nb, q, vr, vi);
+      nq[(k * p.n_dist + q) * 2] = vr;
+      nq[(k * p.n_dist + q) * 2 + 1] = vi;
+    }
+}
+
+struct SampleStatParams {
+  int64_t E, e0, ns;   // chunk size, first global sample, samples per sub-ensemble
+  int64_t s_first;     // first sub-ensemble the chunk touches
+  int n_dist;
+  int est;             // mp_estimator
+  int kmax;            // moments
+  int q, m, n_bins;    // histogram: distribution, count, bins
+  double o_min, inv_width;
+};
+
+// Normally ordered moments (eq. moment with the parity-projected weights):
+// per sample n_q^k, times tanh(n) for odd k on the matrix-P path (+P: 1).
+// Block (s, q): the chunk's samples of sub-ensemble s_first + blockIdx.x,
+// summed in a fixed order (strided per thread, then a tree in LDS) and added
+// to acc[s][q][k - 1] (re, im).
+__global__ __launch_bounds__(256) void moments_kernel(SampleStatParams p, const double* __restrict__ n,
+                                                      const double* __restrict__ nq,
+                                                      double* __restrict__ acc) {
+  __shared__ double red[256][2];
+  const int64_t s = p.s_first + blockIdx.x;
+  const int q = blockIdx.y;
+  int64_t lo = s * p.ns, hi = (s + 1) * p.ns;
+  lo = lo > p.e0 ? lo : p.e0;
+  hi = hi < p.e0 + p.E ? hi : p.e0 + p.E;
+  double sr[MP_MAX_MOMENTS], si[MP_MAX_MOMENTS];
+#pragma unroll
+  for (int o = 0; o < MP_MAX_MOMENTS; ++o) sr[o] = si[o] = 0.0;
+  for (int64_t g = lo + threadIdx.x; g < hi; g += 256) {
+    const int64_t k = g - p.e0;
+    const double zr = nq[(k * p.n_dist + q) * 2], zi = nq[(k * p.n_dist + q) * 2 + 1];
+    const double w = p.est == MP_PLUS_P ? 1.0 : tanh(n[k]);
+    double pr = 1.0, pi = 0.0;
+#pragma unroll
+    for (int o = 0; o < MP_MAX_MOMENTS; ++o) {
+      if (o < p.kmax) {
+        const double tr = pr * zr - pi * zi;
+        pi = pr * zi + pi * zr;
+        pr = tr;
+        const double f = (o & 1) ? 1.0 : w;  // order o + 1 odd -> weight w
+        sr[o] += f * pr;
+        si[o] += f * pi;
+      }
+    }
+  }
+  for (int o = 0; o < p.kmax; ++o) {
+    red[threadIdx.x][0] = sr[o];
+    red[threadIdx.x][1] = si[o];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        red[threadIdx.x][0] += red[threadIdx.x + w][0];
+        red[threadIdx.x][1] += red[threadIdx.x + w][1];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double* dst = acc + ((s * p.n_dist + q) * p.kmax + o) * 2;
+      dst[0] += red[0][0];
+      dst[1] += red[0][1];
+    }
+    __syncthreads();
+  }
+}
+
+// Per-sample count observable of distribution q at count m (eq.
+// c-number-variable for one bin: g0 n_q^m e^{-n_q} / m!, with g0 formed as in
+// counts_fused; +P: n_q^m e^{-n_q} / m!), real part, binned into n_bins equal
+// bins from o_min (bin 0: below, bin n_bins + 1: at or above the top or not
+// finite).  Counts are added as FP64 ones, exact and order-independent.
+__global__ __launch_bounds__(256) void histogram_kernel(SampleStatParams p, const double* __restrict__ n,
+                                                        const double* __restrict__ nq,
+                                                        double* __restrict__ hist) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= p.E) return;
+  const double zr = nq[(k * p.n_dist + p.q) * 2], zi = nq[(k * p.n_dist + p.q) * 2 + 1];
+  const double mag = sqrt(zr * zr + zi * zi);
+  // log(n_q^m / m!) as (real, phase); 0^0 = 1
+  double lr, lp;
+  if (p.m == 0) {
+    lr = 0.0;
+    lp = 0.0;
+  } else if (mag == 0.0) {
+    lr = -INFINITY;
+    lp = 0.0;
+  } else {
+    lr = p.m * log(mag);
+    lp = p.m * atan2(zi, zr);
+  }
+  lr -= lgamma((double)p.m + 1.0);
+  double G;
+  if (p.est == MP_PLUS_P) {
+    G = exp(lr - zr) * cos(lp - zi);
+  } else {
+    const double nn = n[k];
+    const double L = log1p(exp(-2.0 * fabs(nn)));
+    const double c1 = (nn >= 0.0 ? 0.0 : 2.0 * nn) - L;
+    const double c2 = (nn >= 0.0 ? -2.0 * nn : 0.0) - L;
+    const double par = (p.m & 1) ? -1.0 : 1.0;
+    G = exp(lr - zr + c1) * cos(lp - zi) + par * exp(lr + zr + c2) * cos(lp + zi);
+  }
+  int64_t b;
+  if (!(G == G) || G - G != 0.0) {
+    b = p.n_bins + 1;  // not finite
+  } else {
+    const double x = (G - p.o_min) * p.inv_width;
+    b = x < 0.0 ? 0 : (x >= (double)p.n_bins ? p.n_bins + 1 : (int64_t)x + 1);
+  }
+  const int64_t s = (p.e0 + k) / p.ns;
+  atomicAdd(hist + s * (p.n_bins + 2) + b, 1.0);
+}
+
+// Mean over sub-ensembles of scale * acc[s][v] / samples_per_sub and sigma_T =
+// sd of its real part over the sub-ensembles / sqrt(n_sub) (NaN for one).
+__global__ __launch_bounds__(256) void subensemble_stats_kernel(int n_sub, int64_t n_vals, int ncomp,
+                                                                double scale,
+                                                                const double* __restrict__ acc,
+                                                                double* __restrict__ mean,
+                                                                double* __restrict__ sigma) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= n_vals) return;
+  double m[2] = {0.0, 0.0};
+  for (int s = 0; s < n_sub; ++s)
+    for (int c = 0; c < ncomp; ++c) m[c] += acc[((int64_t)s * n_vals + v) * ncomp + c] * scale;
+  for (int c = 0; c < ncomp; ++c) {
+    m[c] /= n_sub;
+    mean[v * ncomp + c] = m[c];
+  }
+  double ss = 0.0;
+  for (int s = 0; s < n_sub; ++s) {
+    const double dlt = acc[((int64_t)s * n_vals + v) * ncomp] * scale - m[0];
+    ss += dlt * dlt;
+  }
+  sigma[v] = n_sub > 1 ? sqrt(ss / (n_sub - 1) / n_sub) : NAN;
+}
+
+mp_status occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, int32_t d,
+                             const int32_t* bin_of_mode, mp_bin_mode mode, double* nq,
+                             hipStream_t stream) {
+  CountsParams p{};
+  p.M = M;
+  p.ldm = ld_modes(M);
+  p.E = E;
+  p.d = d;
+  p.mode = mode;
+  if (!fill_runs(p, M, bin_of_mode)) {
+    set_error("mp_occupations: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
+    return MP_ERR_UNSUPPORTED;
+  }
+  p.n_dist = d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
+  for (int q = 0; q < p.n_dist; ++q) p.dist_src[q] = q < d ? q : -1;
+  const int64_t blocks = (E + 3) / 4;
+  if (prec == MP_FP64)
+    hipLaunchKernelGGL(occupations_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, p,
+                       (const double*)C, nq);
+  else
+    hipLaunchKernelGGL(occupations_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, stream, p,
+                       (const float*)C, nq);
+  MP_HIP_LAUNCH_CHECK("mp_occupations launch");
+  return MP_OK;
+}
+
+mp_status moments_launch(int64_t E, const double* n, const double* nq, int32_t n_dist,
+                         int32_t kmax, mp_estimator est, int64_t ns, int64_t e0, double* acc,
+                         hipStream_t stream) {
+  SampleStatParams p{};
+  p.E = E;
+  p.e0 = e0;
+  p.ns = ns;
+  p.s_first = e0 / ns;
+  p.n_dist = n_dist;
+  p.est = est;
+  p.kmax = kmax;
+  const int64_t n_touched = (e0 + E - 1) / ns - p.s_first + 1;
+  hipLaunchKernelGGL(moments_kernel, dim3((unsigned)n_touched, (unsigned)n_dist), dim3(256), 0,
+                     stream, p, n, nq, acc);
+  MP_HIP_LAUNCH_CHECK("mp_moments_accumulate launch");
+  return MP_OK;
+}
+
+mp_status histogram_launch(int64_t E, const double* n, const double* nq, int32_t n_dist, int32_t q,
+                           int32_t m, mp_estimator est, double o_min, double width,
+                           int32_t n_bins, int64_t ns, int64_t e0, double* hist,
+                           hipStream_t stream) {
+  SampleStatParams p{};
+  p.E = E;
+  p.e0 = e0;
+  p.ns = ns;
+  p.n_dist = n_dist;
+  p.est = est;
+  p.q = q;
+  p.m = m;
+  p.n_bins = n_bins;
+  p.o_min = o_min;
+  p.inv_width = 1.0 / width;
+  hipLaunchKernelGGL(histogram_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, stream, p,
+                     n, nq, hist);
+  MP_HIP_LAUNCH_CHECK("mp_observable_histogram launch");
+  return MP_OK;
+}
+
+mp_status subensemble_stats_launch(int32_t n_sub, int64_t ns, int64_t n_vals, int32_t ncomp,
+                                   double scale, const double* acc, double* mean, double* sigma,
+                                   hipStream_t stream) {
+  hipLaunchKernelGGL(subensemble_stats_kernel, dim3((unsigned)((n_vals + 255) / 256)), dim3(256), 0,
+                     stream, n_sub, n_vals, ncomp, scale / (double)ns, acc, mean, sigma);
+  MP_HIP_LAUNCH_CHECK("mp_subensemble_stats launch");
   return MP_OK;
 }
 

@@ -103,3 +103,32 @@ def test_host_validation_rejects_bad_arguments():
     st = lib.mp_counts_finalize(2, 0, i32([16, 8]), 3, 8, vp(256), vp(256), vp(256), vp(256), vp(0),
                                 0, None)
     assert st == -5
+
+
+def test_observable_calls_validate_on_the_host():
+    """The per-sample observable calls reject bad arguments before any launch
+    (so these checks run without a GPU)."""
+    lib = _lib()
+    vp = ctypes.c_void_p
+    i32 = lambda xs: (ctypes.c_int32 * len(xs))(*xs)
+    # occupations: joint mode rejected, bin index out of range, misaligned C
+    assert lib.mp_occupations(4, 8, vp(16), 1, 1, i32([0] * 4), 0, vp(16), None) == -1
+    assert lib.mp_occupations(4, 8, vp(16), 1, 2, i32([0, 2, 0, 0]), 1, vp(16), None) == -1
+    assert b"bin_of_mode[1]" in lib.mp_last_error()
+    assert lib.mp_occupations(4, 8, vp(17), 1, 1, i32([0] * 4), 1, vp(16), None) == -1
+    # moments: kmax range, samples beyond the sub-ensembles, unknown estimator
+    assert lib.mp_moments_accumulate(8, vp(16), vp(16), 1, 0, 0, 2, 4, 0, vp(16), None) == -1
+    assert lib.mp_moments_accumulate(8, vp(16), vp(16), 1, 9, 0, 2, 4, 0, vp(16), None) == -1
+    assert lib.mp_moments_accumulate(8, vp(16), vp(16), 1, 2, 0, 1, 4, 0, vp(16), None) == -1
+    assert b"do not fit" in lib.mp_last_error()
+    assert lib.mp_moments_accumulate(8, vp(16), vp(16), 1, 2, 5, 2, 4, 0, vp(16), None) == -1
+    # histogram: q outside, negative m, zero width, no bins
+    h = lambda **k: lib.mp_observable_histogram(
+        8, vp(16), vp(16), k.get("nd", 2), k.get("q", 0), k.get("m", 4), 0, k.get("lo", 0.0),
+        k.get("w", 0.1), k.get("nb", 10), 2, 4, 0, vp(16), None)
+    assert h(q=2) == -1 and h(m=-1) == -1 and h(w=0.0) == -1 and h(nb=0) == -1
+    assert h(lo=float("inf")) == -1 and h(nd=10) == -1
+    # stats: ncomp, counts
+    assert lib.mp_subensemble_stats(1, 1, 4, 3, 1.0, vp(16), vp(16), vp(16), None) == -1
+    assert lib.mp_subensemble_stats(0, 1, 4, 1, 1.0, vp(16), vp(16), vp(16), None) == -1
+    assert lib.mp_subensemble_stats(1, 1, 4, 1, float("nan"), vp(16), vp(16), vp(16), None) == -1

@@ -1,0 +1,165 @@
+"""Per-sample observables from one ensemble, through the C ABI, against the
+FP64 oracle on identical noise: bin occupations, normally ordered moments
+(matrix-P and +P weights), histograms of a per-sample count observable
+(Appendix A densities) and the sub-ensemble statistics kernel."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator as oest
+from oracle import sampler as osamp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_12749_amd  # noqa: F401
+    yield
+
+
+def _setup(M=45, E=700, seed=31, t=0.9, lossless=False):
+    """A ragged M, three bins (bin 1 split into two runs), uncounted modes."""
+    import paper_2503_12749_amd as mp
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.3, 1.2, M)
+    T = (1.0 if lossless else t) * synth.haar_unitary(M, seed)
+    bins = np.full(M, -1, dtype=np.int32)
+    bins[0:10] = 0
+    bins[10:18] = 1
+    bins[30:40] = 1
+    bins[18:26] = 2
+    p = mp.CountsPipeline(T, r, prec="fp64", seed=seed, windows=[(0, 64)], n_sub=1,
+                          samples_per_sub=E, chunk=E, device=DEV)
+    return mp, p, T, r, bins
+
+
+def _oracle_nq(T, r, bins, d, g0, E, seed):
+    a, b, n = osamp.sample(r, g0, E, seed)
+    ap, bp = oest.propagate(T, a, b)
+    nb = oest.bin_occupations(ap, bp, bins, d)
+    return n, np.concatenate([nb, nb.sum(1, keepdims=True)], axis=1)
+
+
+def test_occupations_match_oracle():
+    mp, p, T, r, bins = _setup()
+    E, d = 700, 3
+    mp.mp_sample(p.M, 0, E, p.r, p.seed, 0, "fp64", p.ab, p.n)
+    mp.mp_propagate(p.M, E, p.T, "fp64", p.ab, p.C, p.ws_prop)
+    nq = torch.empty(E * (d + 1) * 2, dtype=torch.float64, device=DEV)
+    mp.mp_occupations(p.M, E, p.C, "fp64", d, bins, "marginals_and_total", nq)
+    got = nq.cpu().numpy().reshape(E, d + 1, 2)
+    got = got[..., 0] + 1j * got[..., 1]
+    _, ref = _oracle_nq(T, r, bins, d, 0, E, p.seed)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # marginals only: the first d distributions, same values
+    nq2 = torch.empty(E * d * 2, dtype=torch.float64, device=DEV)
+    mp.mp_occupations(p.M, E, p.C, "fp64", d, bins, "marginals", nq2)
+    got2 = nq2.cpu().numpy().reshape(E, d, 2)
+    np.testing.assert_array_equal(got2, nq.cpu().numpy().reshape(E, d + 1, 2)[:, :d])
+
+
+@pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
+def test_moments_over_chunks_match_oracle(est):
+    """Two chunks (the second starting inside a sub-ensemble), six
+    sub-ensembles, moments k = 1..5 of three bins and the total."""
+    chunks = ((0, 530), (530, 670))
+    e_max = max(E for _, E in chunks)
+    mp, p, T, r, bins = _setup(E=e_max)
+    d, nd, kmax, n_sub, ns = 3, 4, 5, 6, 200
+    acc = torch.zeros(n_sub * nd * kmax * 2, dtype=torch.float64, device=DEV)
+    nq = torch.empty(e_max * nd * 2, dtype=torch.float64, device=DEV)
+    for g0, E in chunks:
+        mp.mp_sample(p.M, g0, E, p.r, p.seed, 0, "fp64", p.ab, p.n)
+        mp.mp_propagate(p.M, E, p.T, "fp64", p.ab, p.C, p.ws_prop)
+        mp.mp_occupations(p.M, E, p.C, "fp64", d, bins, "marginals_and_total", nq)
+        mp.mp_moments_accumulate(E, p.n, nq, nd, kmax, est, n_sub, ns, g0, acc)
+    mean = torch.empty(nd * kmax * 2, dtype=torch.float64, device=DEV)
+    sig = torch.empty(nd * kmax, dtype=torch.float64, device=DEV)
+    mp.mp_subensemble_stats(n_sub, ns, nd * kmax, 2, 1.0, acc, mean, sig)
+    n, nqo = _oracle_nq(T, r, bins, d, 0, n_sub * ns, p.seed)
+    for q in range(nd):
+        if est == "plus_p":
+            f = np.stack([nqo[:, q] ** k for k in range(1, kmax + 1)], axis=1)
+        else:
+            f = oest.factorial_moment_samples(n, nqo[:, q], kmax)
+        sums = f.reshape(n_sub, ns, kmax).sum(axis=1)
+        _, P, s = oest.subensemble_stats(sums, np.full(n_sub, ns))
+        got = mean.cpu().numpy().reshape(nd, kmax, 2)[q]
+        np.testing.assert_allclose(got[:, 0] + 1j * got[:, 1], P, rtol=1e-10,
+                                   atol=1e-13 * np.abs(P).max())
+        np.testing.assert_allclose(sig.cpu().numpy().reshape(nd, kmax)[q], s, rtol=1e-8)
+
+
+def _edges_clear(values, o_min, width, n_bins):
+    x = (values - o_min) / width
+    frac = np.abs(x - np.round(x))
+    return frac[(x > -1) & (x < n_bins + 1)].min() > 1e-7
+
+
+@pytest.mark.parametrize("est,m,o_min,width,n_bins,lossless", [
+    ("matrix_p", 4, -0.0501, 0.001, 500, True),   # bounded G_0(4) of a lossless network
+    ("plus_p", 4, -2.0001, 0.05, 80, True),       # long-tailed G_+(4): over- and underflow bins
+    ("plus_p", 3, -2.0001, 0.05, 80, True),
+    ("matrix_p", 5, -0.2001, 0.002, 300, False),  # lossy: odd count, complex occupations
+])
+def test_histogram_matches_oracle(est, m, o_min, width, n_bins, lossless):
+    """Counts per sub-ensemble equal the oracle's histogram of Re G(m) of the
+    total count exactly (edges placed away from every value)."""
+    M, E, n_sub = 20, 4000, 4
+    ns = E // n_sub
+    mp, p, T, r, _ = _setup(M=M, E=E, seed=41, lossless=lossless)
+    r = np.full(M, 0.5)
+    p.r.copy_(torch.from_numpy(r))
+    allm = np.zeros(M, dtype=np.int32)
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, "fp64", p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, "fp64", p.ab, p.C, p.ws_prop)
+    nq = torch.empty(E * 2, dtype=torch.float64, device=DEV)
+    mp.mp_occupations(M, E, p.C, "fp64", 1, allm, "marginals", nq)
+    hist = torch.zeros(n_sub * (n_bins + 2), dtype=torch.float64, device=DEV)
+    mp.mp_observable_histogram(E, p.n, nq, 1, 0, m, est, o_min, width, n_bins, n_sub, ns, 0, hist)
+    n, nqo = _oracle_nq(T, r, allm, 1, 0, E, p.seed)
+    G = oest.pattern_probability(n, nqo[:, :1], [np.array([m])], plus_p=(est == "plus_p"))[:, 0].real
+    assert _edges_clear(G, o_min, width, n_bins)
+    idx = np.clip(np.floor((G - o_min) / width).astype(np.int64) + 1, 0, n_bins + 1)
+    ref = np.zeros((n_sub, n_bins + 2))
+    np.add.at(ref, (np.arange(E) // ns, idx), 1.0)
+    got = hist.cpu().numpy().reshape(n_sub, n_bins + 2)
+    np.testing.assert_array_equal(got, ref)
+    if est == "matrix_p" and lossless:
+        # Appendix A: bounded in (0, 0.4), mass at ~0 and ~0.39
+        top = 0.39064
+        assert G.min() > 0 and G.max() < top
+        assert got[:, 0].sum() == 0 and got[:, -1].sum() == 0
+    # densities: hist / (N_S width), mean over sub-ensembles, sigma_T
+    dens = torch.empty(n_bins + 2, dtype=torch.float64, device=DEV)
+    sig = torch.empty(n_bins + 2, dtype=torch.float64, device=DEV)
+    mp.mp_subensemble_stats(n_sub, ns, n_bins + 2, 1, 1.0 / width, hist, dens, sig)
+    dref = ref / (ns * width)
+    np.testing.assert_allclose(dens.cpu().numpy(), dref.mean(0), rtol=1e-14, atol=0)
+    np.testing.assert_allclose(sig.cpu().numpy(), dref.std(0, ddof=1) / np.sqrt(n_sub),
+                               rtol=1e-12, atol=1e-14)
+
+
+def test_stats_single_subensemble_sigma_is_nan_and_bad_arguments_fail():
+    import paper_2503_12749_amd as mp
+    acc = torch.arange(6, dtype=torch.float64, device=DEV)  # one sub-ensemble, 3 complex values
+    sig = torch.empty(3, dtype=torch.float64, device=DEV)
+    mean6 = torch.empty(6, dtype=torch.float64, device=DEV)
+    mp.mp_subensemble_stats(1, 2, 3, 2, 1.0, acc, mean6, sig)
+    np.testing.assert_array_equal(mean6.cpu().numpy(), np.arange(6) / 2.0)
+    assert np.isnan(sig.cpu().numpy()).all()
+    with pytest.raises(mp.MPError):
+        mp.mp_subensemble_stats(1, 2, 3, 3, 1.0, acc, mean6, sig)
+    nq = torch.zeros(8, dtype=torch.float64, device=DEV)
+    n = torch.zeros(4, dtype=torch.float64, device=DEV)
+    hist = torch.zeros(10, dtype=torch.float64, device=DEV)
+    with pytest.raises(mp.MPError):  # samples beyond n_sub * samples_per_sub
+        mp.mp_observable_histogram(4, n, nq, 1, 0, 2, "matrix_p", 0.0, 0.1, 3, 1, 2, 0, hist)
+    with pytest.raises(mp.MPError):  # kmax too large
+        mp.mp_moments_accumulate(4, n, nq, 1, 9, "matrix_p", 2, 2, 0, hist)

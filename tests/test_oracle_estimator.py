@@ -170,3 +170,60 @@ def test_factorial_moments_vs_closed_form():
     f1, f2 = f[:, 0].real, f[:, 1].real
     assert abs(f1.mean() - mean) < 5 * f1.std() / np.sqrt(len(f1))
     assert abs((f2.mean() + mean - mean ** 2) - var) < 5 * f2.std() / np.sqrt(len(f2)) + 1e-9
+
+
+@pytest.mark.parametrize("plus_p", [False, True])
+def test_factorial_moments_orders_3_4_vs_exact_law(plus_p):
+    """Normally ordered moments <:n^k:> are the factorial moments of the
+    count, sum_m m!/(m-k)! P(m).  For T = t U the exact P(m) of the total
+    count follows from the uniform-loss generating function; the oracle's
+    per-sample moments (matrix-P weights tanh n on odd orders, or none for
+    +P) must average to it for k = 1..4."""
+    from scipy.special import gammaln
+    rng = np.random.default_rng(21)
+    M, t = 6, 0.9
+    r = rng.uniform(0.3, 0.8, M)
+    T = t * synth.haar_unitary(M, 31)
+    a, b, n = sampler.sample(r, 0, 400_000, 17)
+    ap, bp = estimator.propagate(T, a, b)
+    nS = estimator.bin_occupations(ap, bp, np.zeros(M, int), 1)[:, 0]
+    if plus_p:
+        f = np.stack([nS ** k for k in range(1, 5)], axis=1)
+    else:
+        f = estimator.factorial_moment_samples(n, nS, 4)
+    P = exact.uniform_loss_total(r, t, 256)
+    m = np.arange(256)
+    for k in range(1, 5):
+        ff = np.exp(gammaln(m + 1) - gammaln(np.maximum(m - k + 1, 1)))
+        ff[m < k] = 0.0
+        want = float((ff * P).sum())
+        x = f[:, k - 1].real
+        se = x.std() / np.sqrt(len(x))
+        assert abs(x.mean() - want) < 5 * se, (k, x.mean(), want, se)
+        xi = f[:, k - 1].imag  # complex per sample under loss; the mean is real
+        assert abs(xi.mean()) < 5 * xi.std() / np.sqrt(len(xi)) + 1e-12
+
+
+@pytest.mark.parametrize("plus_p", [False, True])
+def test_factorial_moments_are_derivatives_of_the_per_sample_law(plus_p):
+    """Per sample, sum_m m!/(m-k)! G(m) over the count-space observable is the
+    k-th derivative at z = 1 of its generating function, cosh(n + n_S (z-1)) /
+    cosh n (matrix-P) or e^{n_S (z-1)} (+P): n_S^k tanh(n)^(k odd) or n_S^k.
+    Two independent code paths (direct G(m) vs the moment formula) must agree
+    exactly, which fixes where the tanh weight goes."""
+    from scipy.special import gammaln
+    rng = np.random.default_rng(5)
+    E = 200
+    n = rng.normal(1.0, 2.0, E)
+    nS = (rng.normal(1.5, 1.5, E) + 1j * rng.normal(0, 0.5, E))
+    m = np.arange(160)
+    G = estimator.pattern_probability(n, nS[:, None], [m], plus_p=plus_p)
+    if plus_p:
+        f = np.stack([nS ** k for k in range(1, 6)], axis=1)
+    else:
+        f = estimator.factorial_moment_samples(n, nS, 5)
+    for k in range(1, 6):
+        ff = np.exp(gammaln(m + 1) - gammaln(np.maximum(m - k + 1, 1)))
+        ff[m < k] = 0.0
+        direct = (G * ff[None, :]).sum(axis=1)
+        np.testing.assert_allclose(direct, f[:, k - 1], rtol=1e-9, atol=1e-12)
