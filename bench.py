@@ -592,6 +592,74 @@ def run_moments_m1000(args, mp, torch, synth):
         counts_run_s=base_s, counts_and_moments_run_s=full_s, moments=rows)
 
 
+def run_scaling_appb(args, mp, torch, synth):
+    """Appendix B scaling workloads.  Run time: lossless Haar networks,
+    r = 0.89, M = 128 .. 8192, E = 1.2e6 (120 sub-ensembles of 1e4, chunks of
+    1.2e5), total counts on the printed windows [m_min, m_max], each job
+    timed whole (packing, all chunks, finalize) after one untimed chunk, for
+    the split-BF16 and FP32 paths.  Errors: max sigma_T for M = 16 .. 1024
+    with r_i = 0.89 + 0.1 w_i and t in {1, 0.995, 1 - 1/m_max} (printed
+    m_max), FP64, windows of +-9 sd around the closed-form mean."""
+    g = _golden("appB_cutoffs.json")
+    E, ns, chunk = 1_200_000, 10_000, 120_000
+    n_sub = E // ns
+    timing = []
+    for M, mmin, mmax in zip(g["timing_M"], g["timing_m_min"], g["timing_m_max"]):
+        seed = synth.SEED_BASE + 20
+        T = synth.haar_unitary(M, seed + M)
+        r = np.full(M, 0.89)
+        K = -(-(mmax - mmin + 1) // 64) * 64
+        row = {"M": M, "window": [mmin, K]}
+        for prec in ("split_bf16", "fp32"):
+            p = mp.CountsPipeline(T, r, prec=prec, seed=seed, windows=[(mmin, K)], n_sub=n_sub,
+                                  samples_per_sub=ns, chunk=chunk)
+            p.run_chunk(0, chunk)
+
+            def job():
+                p.reset()
+                p.packed = False
+                p.run()
+            secs = _timed(torch, job)
+            P, _, sig = p.result()
+            row[prec] = {"run_s": secs, "max_sigma_T": float(sig.max()), "sum_P": float(P.sum())}
+            del p
+            torch.cuda.empty_cache()
+        log(f"[bench] scaling M={M}: split {row['split_bf16']['run_s']:.3f} s, "
+            f"fp32 {row['fp32']['run_s']:.3f} s")
+        timing.append(row)
+    for a, b in zip(timing, timing[1:]):
+        b["exponent_vs_previous_M"] = float(np.log(b["split_bf16"]["run_s"] / a["split_bf16"]["run_s"])
+                                            / np.log(b["M"] / a["M"]))
+    errors = []
+    for M, mmax in zip(g["error_M"], g["error_m_max"]):
+        seed = synth.SEED_BASE + 30
+        r = synth.squeezing_gaussian(M, 0.89, 0.1, seed + M)
+        U = synth.haar_unitary(M, seed + 1000 + M)
+        row = {"M": M}
+        for name, t in (("t=1", 1.0), ("t=0.995", 0.995), ("t=1-1/m_max", 1.0 - 1.0 / mmax)):
+            mean, sd = synth.uniform_loss_moments(r, t)
+            win = synth.count_window(mean, sd)
+            p = mp.CountsPipeline(t * U, r, prec="fp64", seed=seed, windows=[win], n_sub=n_sub,
+                                  samples_per_sub=ns, chunk=chunk)
+            p.run()
+            P, _, sig = p.result()
+            row[name] = {"max_sigma_T": float(sig.max()), "window": list(win),
+                         "sum_P": float(P.sum())}
+            del p
+        log(f"[bench] scaling errors M={M}: " + ", ".join(f"{k} {v['max_sigma_T']:.2e}"
+                                                           for k, v in row.items() if k != "M"))
+        errors.append(row)
+        torch.cuda.empty_cache()
+    top = timing[-1]["split_bf16"]["run_s"]
+    return {"metric": "seconds for the lossless M=8192 total-count job (E=1.2e6), split-BF16",
+            "value": top, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": 1e3 * top, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "split-bf16 (fp32 acc)", "data": "synthetic",
+            "config": {"workload": "Appendix B: lossless Haar, r=0.89, M=128..8192, E=1.2e6; "
+                                   "max sigma_T for M=16..1024, r_i=0.89+0.1 w_i, three losses",
+                       "timing": timing, "errors": errors}}
+
+
 def run_copy(args, mp, torch, synth):
     """A plain 1 GiB device-to-device copy, three times: the reference for
     scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
@@ -617,7 +685,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="m8000",
                     choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate",
-                             "plusp_m20", "moments_m1000", "copy"],
+                             "plusp_m20", "moments_m1000", "scaling_appb", "copy"],
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
@@ -635,7 +703,8 @@ def main():
     runners = {"m8000": run_m8000, "joint_m1000": run_joint_m1000,
                "precision_m4000": run_precision_m4000, "batched": run_batched,
                "surrogate": run_surrogate, "plusp_m20": run_plusp_m20,
-               "moments_m1000": run_moments_m1000, "copy": run_copy}
+               "moments_m1000": run_moments_m1000, "scaling_appb": run_scaling_appb,
+               "copy": run_copy}
     out = runners[args.workload](args, mp, torch, synth)
     print(json.dumps(out), flush=True)
 
