@@ -198,6 +198,37 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
                            void* stream);
 
 /*
+ * mp_propagate_packed followed by mp_binned_counts without materialising C
+ * (the occupation-fused GEMM): each 256 x 256 GEMM tile covers the Re and Im
+ * rows of 128 modes and the alpha and beta columns of 128 samples, and its
+ * epilogue reduces alpha'_j beta'_j over the modes of every bin run in the
+ * tile to per-sample partials (16 bytes per run, block and sample, in
+ * `workspace`); the counting kernel then reads those partials instead of C.
+ * Same estimator, windows and accumulator layout as mp_binned_counts, with
+ * the modes MP_MARGINALS, MP_MARGINALS_AND_TOTAL and MP_JOINT with d = 1.
+ * The occupations are summed in FP32 within a tile and in FP64 across tiles,
+ * so results agree with the unfused path to FP32 rounding.
+ *
+ *   prec       MP_FP32, MP_SPLIT_BF16 or MP_SPLIT_FP16 (others:
+ *              MP_ERR_UNSUPPORTED)
+ *   ab, n      as written by mp_sample for this chunk
+ *   packed     device, as written by mp_pack_transmission(M, T, prec, ...),
+ *              packed_bytes >= mp_propagate_workspace(M, prec), 256-aligned
+ *   d ... e0, acc  as for mp_binned_counts
+ *   workspace  device, >= mp_propagate_counts_workspace(...) bytes,
+ *              256-aligned; overwritten
+ */
+size_t mp_propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                                     mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                                     int64_t samples_per_sub, int64_t e0);
+mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                              const void* ab, const double* n, const void* packed,
+                              size_t packed_bytes, int32_t d, const int32_t* bin_of_mode,
+                              mp_bin_mode mode, const int32_t* m_lo, const int32_t* K,
+                              int32_t n_sub, int64_t samples_per_sub, int64_t e0, double* acc,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Inverse DFT of each sub-ensemble's mean characteristic function,
  *   P_s(m_lo + l) = (1/K) sum_k chi_s(k) exp(-2 pi i k l / K),
  * then P = mean_s P_s and sigma_T = sd_s(Re P_s) / sqrt(n_sub) (Appendix A;

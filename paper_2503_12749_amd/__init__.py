@@ -137,6 +137,21 @@ def mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean
                                                 _stream(stream)))
 
 
+def mp_propagate_counts_workspace(M, E, d, bin_of_mode, mode, K, n_sub, samples_per_sub, e0):
+    return int(_lib.load().mp_propagate_counts_workspace(M, E, d, i32_array(bin_of_mode), _mode(mode),
+                                                         i32_array(K), n_sub, samples_per_sub, e0))
+
+
+def mp_propagate_counts(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K, n_sub,
+                        samples_per_sub, e0, acc, workspace, stream=None):
+    """Occupation-fused propagate + counts; bin_of_mode, m_lo, K: host sequences."""
+    _lib.check(_lib.load().mp_propagate_counts(
+        M, E, _prec(prec), _est(est), _ptr(ab), _ptr(n), _ptr(packed),
+        packed.numel() * packed.element_size(), d, i32_array(bin_of_mode), _mode(mode),
+        i32_array(m_lo), i32_array(K), n_sub, samples_per_sub, e0, _ptr(acc), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def mp_finalize_workspace(d: int, mode, K, n_sub: int) -> int:
     return int(_lib.load().mp_finalize_workspace(d, _mode(mode), i32_array(K), n_sub))
 
@@ -157,7 +172,8 @@ class CountsPipeline:
 
     def __init__(self, T: np.ndarray, r: np.ndarray, *, prec="fp64", seed: int, net: int = 0,
                  bin_of_mode=None, d: int = 1, mode="joint", windows, n_sub: int,
-                 samples_per_sub: int, chunk: int, est="matrix_p", device="cuda:0"):
+                 samples_per_sub: int, chunk: int, est="matrix_p", device="cuda:0",
+                 fused: bool = False):
         import torch
         self.torch = torch
         T = np.ascontiguousarray(T, dtype=np.complex128)
@@ -176,8 +192,11 @@ class CountsPipeline:
         self.device = dev
         self.T = torch.from_numpy(T.view(np.float64).reshape(-1).copy()).to(dev)
         self.r = torch.from_numpy(np.asarray(r, dtype=np.float64).copy()).to(dev)
+        self.fused = bool(fused)
         self.ab = torch.empty(mp_ab_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
-        self.C = torch.empty(mp_c_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
+        # the occupation-fused path never materialises C
+        self.C = None if self.fused else torch.empty(mp_c_bytes(self.M, self.chunk, self.prec),
+                                                      dtype=torch.uint8, device=dev)
         self.n = torch.empty(self.chunk, dtype=torch.float64, device=dev)
         self.ws_prop = torch.empty(mp_propagate_workspace(self.M, self.prec), dtype=torch.uint8, device=dev)
         self.packed = False
@@ -190,6 +209,10 @@ class CountsPipeline:
         wbytes = blocks * self.entries * 16 + 256
         if self.mode == 0 and self.d == 2:
             wbytes = mp_binned_workspace(2, 0, self.K, self.chunk, self.n_sub, self.ns, 0)
+        if self.fused:
+            # the GEMM's partials plus the counts blocks of the worst chunk alignment
+            wbytes += mp_propagate_counts_workspace(self.M, self.chunk, self.d, self.bins, self.mode,
+                                                    self.K, self.n_sub, self.ns, 0)
         self.ws_counts = torch.empty(wbytes, dtype=torch.uint8, device=dev)
         self.acc = torch.zeros(self.n_sub * self.entries * 2, dtype=torch.float64, device=dev)
         self.P_re = torch.empty(self.entries, dtype=torch.float64, device=dev)
@@ -207,6 +230,11 @@ class CountsPipeline:
             mp_pack_transmission(self.M, self.T, self.prec, self.ws_prop, stream)
             self.packed = True
         mp_sample(self.M, g0, E, self.r, self.seed, self.net, self.prec, self.ab, self.n, stream)
+        if self.fused:
+            mp_propagate_counts(self.M, E, self.prec, self.est, self.ab, self.n, self.ws_prop, self.d,
+                                self.bins, self.mode, self.m_lo, self.K, self.n_sub, self.ns, g0,
+                                self.acc, self.ws_counts, stream)
+            return
         mp_propagate_packed(self.M, E, self.prec, self.ab, self.C, self.ws_prop, stream)
         self.counts_chunk(g0, E, stream)
 

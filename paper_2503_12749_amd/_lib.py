@@ -22,7 +22,8 @@ EXPORTS = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
     "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_occupations",
     "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries",
-    "mp_binned_workspace", "mp_binned_counts", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
+    "mp_binned_workspace", "mp_binned_counts", "mp_propagate_counts_workspace",
+    "mp_propagate_counts", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
     "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_destroy",
     "mp_mlp_param_count", "mp_mlp_workspace", "mp_mlp_round", "mp_mlp_forward", "mp_mlp_loss_grad",
     "mp_mlp_adam",
@@ -70,6 +71,11 @@ def load() -> ctypes.CDLL:
         "mp_propagate": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, vp, vp, vp, sz, vp]),
         "mp_pack_transmission": (ctypes.c_int, [c_i32, vp, ctypes.c_int, vp, sz, vp]),
         "mp_propagate_packed": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, vp, vp, vp, sz, vp]),
+        "mp_propagate_counts_workspace": (sz, [c_i32, c_i64, c_i32, vp, ctypes.c_int, vp, c_i32,
+                                                c_i64, c_i64]),
+        "mp_propagate_counts": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                               sz, c_i32, vp, ctypes.c_int, vp, vp, c_i32, c_i64,
+                                               c_i64, vp, vp, sz, vp]),
         "mp_occupations": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, c_i32, vp, ctypes.c_int,
                                           vp, vp]),
         "mp_moments_accumulate": (ctypes.c_int, [c_i64, vp, vp, c_i32, c_i32, ctypes.c_int, c_i32,

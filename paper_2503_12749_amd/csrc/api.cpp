@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 
@@ -46,6 +47,15 @@ mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, 
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
                                  double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
 size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
+size_t propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                                  mp_bin_mode mode, const int32_t* K, int32_t n_sub, int64_t ns,
+                                  int64_t e0);
+mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                                  const void* ab, const double* n, const void* packed, int32_t d,
+                                  const int32_t* bin_of_mode, mp_bin_mode mode,
+                                  const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                  int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
 mp_status occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, int32_t d,
                              const int32_t* bin_of_mode, mp_bin_mode mode, double* nq,
                              hipStream_t stream);
@@ -216,6 +226,70 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
                "mp_binned_counts: workspace must be 256-byte aligned");
   return binned_counts_launch(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub,
                               samples_per_sub, e0, acc, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+// Shared argument checks of the fused and unfused counting calls.
+static mp_status counts_args(const char* who, int32_t M, int64_t E, mp_estimator est, int32_t d,
+                             const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                             const int32_t* K, int32_t n_sub, int64_t samples_per_sub,
+                             int64_t e0) {
+  MP_CHECK_ARG(M >= 1 && E >= 1, MP_ERR_ARG, "%s: M and E must be >= 1", who);
+  MP_CHECK_ARG(est == MP_MATRIX_P || est == MP_PLUS_P, MP_ERR_ARG, "%s: unknown estimator %d", who,
+               (int)est);
+  MP_CHECK_ARG(d >= 1 && d <= MP_MAX_BINS, MP_ERR_ARG, "%s: d = %d outside [1, %d]", who, d,
+               MP_MAX_BINS);
+  MP_CHECK_ARG(mode >= MP_JOINT && mode <= MP_MARGINALS_AND_TOTAL, MP_ERR_ARG,
+               "%s: unknown bin mode %d", who, (int)mode);
+  MP_CHECK_ARG(bin_of_mode && m_lo && K, MP_ERR_ARG, "%s: null pointer argument", who);
+  MP_CHECK_ARG(n_sub >= 1 && samples_per_sub >= 1 && e0 >= 0, MP_ERR_ARG,
+               "%s: n_sub, samples_per_sub must be >= 1 and e0 >= 0", who);
+  for (int j = 0; j < M; ++j)
+    MP_CHECK_ARG(bin_of_mode[j] >= -1 && bin_of_mode[j] < d, MP_ERR_ARG,
+                 "%s: bin_of_mode[%d] = %d outside [-1, %d)", who, j, bin_of_mode[j], d);
+  const int nd = n_dist_of(d, mode);
+  for (int q = 0; q < nd; ++q) {
+    MP_CHECK_ARG(K[q] >= 1 && K[q] <= 65536, MP_ERR_ARG, "%s: K[%d] = %d outside [1, 65536]", who,
+                 q, K[q]);
+    MP_CHECK_ARG(m_lo[q] >= 0, MP_ERR_ARG, "%s: m_lo[%d] = %d < 0", who, q, m_lo[q]);
+  }
+  return MP_OK;
+}
+
+size_t mp_propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                                     mp_bin_mode mode, const int32_t* K, int32_t n_sub,
+                                     int64_t samples_per_sub, int64_t e0) {
+  std::vector<int32_t> m_lo(MP_MAX_BINS + 1, 0);
+  if (counts_args("mp_propagate_counts_workspace", M, E, MP_MATRIX_P, d, bin_of_mode, mode,
+                  m_lo.data(), K, n_sub, samples_per_sub, e0) != MP_OK)
+    return 0;
+  return propagate_counts_workspace(M, E, d, bin_of_mode, mode, K, n_sub, samples_per_sub, e0);
+}
+
+mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                              const void* ab, const double* n, const void* packed,
+                              size_t packed_bytes, int32_t d, const int32_t* bin_of_mode,
+                              mp_bin_mode mode, const int32_t* m_lo, const int32_t* K,
+                              int32_t n_sub, int64_t samples_per_sub, int64_t e0, double* acc,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  const mp_status st = counts_args("mp_propagate_counts", M, E, est, d, bin_of_mode, mode, m_lo, K,
+                                   n_sub, samples_per_sub, e0);
+  if (st != MP_OK) return st;
+  MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16,
+               MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts: precision %d is not fused (FP32 and split precisions are)",
+               (int)prec);
+  MP_CHECK_ARG(ab && n && packed && acc, MP_ERR_ARG, "mp_propagate_counts: null pointer argument");
+  MP_CHECK_ARG(aligned(ab, 16), MP_ERR_ARG, "mp_propagate_counts: ab must be 16-byte aligned");
+  const size_t need_packed = propagate_workspace(M, prec);
+  MP_CHECK_ARG(packed_bytes >= need_packed && aligned(packed, 256), MP_ERR_WORKSPACE,
+               "mp_propagate_counts: packed operand of %zu bytes (256-aligned) needed, %zu given",
+               need_packed, packed_bytes);
+  MP_CHECK_ARG(aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_propagate_counts: workspace must be 256-byte aligned");
+  return propagate_counts_launch(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K,
+                                 n_sub, samples_per_sub, e0, acc, workspace, ws_bytes,
+                                 (hipStream_t)stream);
 }
 
 size_t mp_finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub) {

@@ -44,6 +44,30 @@ struct GroupNet {
   float out_scale;
 };
 
+// Output of the occupation-fused GEMM: per (slot, sample) the partial sums of
+// alpha'_j beta'_j over the modes of one bin run inside one 128-mode block.
+// Run q owns the slots slot_off[q] + (block - run_lo[q] / 128) for the blocks
+// it touches.  Each slot holds, per sample, (re, im) from the wave with the
+// Re rows of alpha' and (re, im) from the wave with the Im rows: four floats
+// at part[(slot * E + sample) * 4].
+struct FusedOut {
+  float* part;
+  int64_t E;
+  int n_runs;
+  int run_lo[MP_MAX_RUNS], run_hi[MP_MAX_RUNS], slot_off[MP_MAX_RUNS];
+};
+
+// Slots of the fused partials for a set of runs; fills slot_off and returns
+// the total.
+inline int64_t fused_slots(int n_runs, const int* run_lo, const int* run_hi, int* slot_off) {
+  int64_t s = 0;
+  for (int q = 0; q < n_runs; ++q) {
+    slot_off[q] = (int)s;
+    s += (run_hi[q] - 1) / 128 - run_lo[q] / 128 + 1;
+  }
+  return s;
+}
+
 inline int64_t ld_modes(int32_t M) { return ((int64_t)M + kLdAlign - 1) / kLdAlign * kLdAlign; }
 
 inline size_t elem_bytes_ab(mp_precision p) {

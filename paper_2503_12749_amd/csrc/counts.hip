@@ -19,6 +19,8 @@
 // their standard deviation over sqrt(N_R).
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace mp {
@@ -181,8 +183,49 @@ __device__ inline void cis_exp(double ex, double ph, double& re, double& im) {
   }
 }
 
-template <typename CT, bool F64>
-__global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, const CT* __restrict__ C,
+// Sources of a sample's bin sums for counts_fused: the propagated amplitudes C
+// (mp_propagate) or the per-block partials of the occupation-fused GEMM.
+template <typename CT>
+struct FromC {
+  const CT* C;
+  __device__ inline void bin_sums(const CountsParams& p, int64_t k, int lane,
+                                  double (&nb)[MP_MAX_BINS][2]) const {
+    const int64_t ldc = 2 * p.ldm;
+    sample_bin_sums<CT>(p, C + k * ldc, C + (p.E + k) * ldc, lane, nb);
+  }
+};
+
+struct FromPartials {
+  const float* part;  // FusedOut layout, E = p.E
+  __device__ inline void bin_sums(const CountsParams& p, int64_t k, int lane,
+                                  double (&nb)[MP_MAX_BINS][2]) const {
+#pragma unroll
+    for (int b = 0; b < MP_MAX_BINS; ++b) nb[b][0] = nb[b][1] = 0.0;
+    int slot0 = 0;
+    for (int q = 0; q < p.n_runs; ++q) {
+      const int first = p.run_lo[q] >> 7, nblk = ((p.run_hi[q] - 1) >> 7) - first + 1;
+      double sr = 0.0, si = 0.0;
+      for (int t = lane; t < nblk; t += 64) {
+        const float4 v = *(const float4*)(part + ((int64_t)(slot0 + t) * p.E + k) * 4);
+        sr += (double)v.x + (double)v.z;
+        si += (double)v.y + (double)v.w;
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      const int bq = p.run_bin[q];
+#pragma unroll
+      for (int b = 0; b < MP_MAX_BINS; ++b)
+        if (b == bq) {
+          nb[b][0] += sr;
+          nb[b][1] += si;
+        }
+      slot0 += nblk;
+    }
+  }
+};
+
+template <typename Src, bool F64>
+__global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, Src src,
                                                               const double* __restrict__ nglob,
                                                               double* __restrict__ partials) {
   __shared__ double s_nb[kSBlk][kMaxDist][2];
@@ -192,15 +235,13 @@ __global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, co
   block_samples(p, blockIdx.x, sub, lo, hi);
   const int nsmp = (int)(hi - lo);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t ldc = 2 * p.ldm;
 
-  // Phase 1: per-sample bin occupations n_b (wave per sample, lanes over modes).
+  // Phase 1: per-sample bin occupations n_b (wave per sample, lanes over modes
+  // or over the fused GEMM's block partials).
   for (int i = wave; i < nsmp; i += kCountThreads / 64) {
     const int64_t k = lo + i - p.e0;  // chunk-local sample index
-    const CT* ca = C + k * ldc;
-    const CT* cb = C + (p.E + k) * ldc;
     double nb[MP_MAX_BINS][2];
-    sample_bin_sums<CT>(p, ca, cb, lane, nb);
+    src.bin_sums(p, k, lane, nb);
     if (lane == 0) {
       for (int q = 0; q < p.n_dist; ++q) dist_occupation(p, nb, q, s_nb[i][q][0], s_nb[i][q][1]);
       const double n = nglob[k];
@@ -832,12 +873,11 @@ size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E
   return (size_t)blocks * (size_t)entries_of(d, mode, K) * 16;
 }
 
-mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double* n,
-                               mp_precision prec, mp_estimator est, int32_t d,
-                               const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
-                               const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
-                               double* acc, void* ws, size_t ws_bytes, hipStream_t stream) {
-  CountsParams p{};
+// Parameters of a d = 1, marginal or marginal + total accumulation.
+static mp_status setup_counts(CountsParams& p, const char* who, int32_t M, int64_t E, int32_t d,
+                              const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                              const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
+                              mp_estimator est, int64_t& blocks) {
   p.M = M;
   p.ldm = ld_modes(M);
   p.E = E;
@@ -846,13 +886,8 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
   p.d = d;
   p.mode = mode;
   p.est = est;
-  if (mode == MP_JOINT && d == 2)
-    return joint2_launch(M, E, C, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
-                         ws_bytes, stream);
-  MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
-               "mp_binned_counts: joint distributions need d <= 2 (d = %d)", d);
   if (!fill_runs(p, M, bin_of_mode)) {
-    set_error("mp_binned_counts: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
+    set_error("%s: bins form more than %d contiguous mode runs", who, MP_MAX_RUNS);
     return MP_ERR_UNSUPPORTED;
   }
   p.n_dist = mode == MP_JOINT ? 1 : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
@@ -864,26 +899,120 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
     p.off[q + 1] = p.off[q] + K[q];
   }
   p.entries = p.off[p.n_dist];
-  const int64_t blocks = plan_tiles(p);
-  MP_CHECK_ARG(p.s_last < n_sub, MP_ERR_SHAPE,
-               "mp_binned_counts: samples [%lld, %lld) exceed n_sub * samples_per_sub = %lld",
-               (long long)e0, (long long)(e0 + E), (long long)n_sub * ns);
+  blocks = plan_tiles(p);
+  if (p.s_last >= n_sub) {
+    set_error("%s: samples [%lld, %lld) exceed n_sub * samples_per_sub = %lld", who,
+              (long long)e0, (long long)(e0 + E), (long long)n_sub * ns);
+    return MP_ERR_SHAPE;
+  }
+  if (blocks >= 0x7FFFFFFF) {
+    set_error("%s: chunk too large", who);
+    return MP_ERR_UNSUPPORTED;
+  }
+  return MP_OK;
+}
+
+mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double* n,
+                               mp_precision prec, mp_estimator est, int32_t d,
+                               const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
+                               const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
+                               double* acc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (mode == MP_JOINT && d == 2)
+    return joint2_launch(M, E, C, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
+                         ws_bytes, stream);
+  MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
+               "mp_binned_counts: joint distributions need d <= 2 (d = %d)", d);
+  CountsParams p{};
+  int64_t blocks = 0;
+  const mp_status st = setup_counts(p, "mp_binned_counts", M, E, d, bin_of_mode, mode, m_lo, K,
+                                    n_sub, ns, e0, est, blocks);
+  if (st != MP_OK) return st;
   const size_t need = (size_t)blocks * (size_t)p.entries * 16;
   MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,
                "mp_binned_counts: workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  MP_CHECK_ARG(blocks < 0x7FFFFFFF, MP_ERR_UNSUPPORTED, "mp_binned_counts: chunk too large");
   if (prec == MP_FP64) {
-    hipLaunchKernelGGL((counts_fused<double, true>), dim3((unsigned)blocks), dim3(kCountThreads), 0,
-                       stream, p, (const double*)C, n, (double*)ws);
+    hipLaunchKernelGGL((counts_fused<FromC<double>, true>), dim3((unsigned)blocks),
+                       dim3(kCountThreads), 0, stream, p, FromC<double>{(const double*)C}, n,
+                       (double*)ws);
   } else {
-    hipLaunchKernelGGL((counts_fused<float, false>), dim3((unsigned)blocks), dim3(kCountThreads), 0,
-                       stream, p, (const float*)C, n, (double*)ws);
+    hipLaunchKernelGGL((counts_fused<FromC<float>, false>), dim3((unsigned)blocks),
+                       dim3(kCountThreads), 0, stream, p, FromC<float>{(const float*)C}, n,
+                       (double*)ws);
   }
   MP_HIP_LAUNCH_CHECK("mp_binned_counts fused launch");
   const int ns_touched = (int)(p.s_last - p.s_first + 1);
   hipLaunchKernelGGL(counts_reduce, dim3((p.entries + 255) / 256, ns_touched), dim3(256), 0, stream,
                      p, (const double*)ws, acc);
   MP_HIP_LAUNCH_CHECK("mp_binned_counts reduce launch");
+  return MP_OK;
+}
+
+mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                            const void* ab, const FusedOut& fo, hipStream_t stream);
+
+// Workspace of mp_propagate_counts: the GEMM's partials (slots x E x 16 B),
+// then the counts kernel's per-block partials.
+static void propagate_counts_sizes(const CountsParams& p, int64_t blocks, size_t& part_bytes,
+                                   size_t& total) {
+  int slot_off[MP_MAX_RUNS];
+  const int64_t slots = fused_slots(p.n_runs, p.run_lo, p.run_hi, slot_off);
+  part_bytes = ((size_t)slots * (size_t)p.E * 16 + 255) / 256 * 256;
+  total = part_bytes + (size_t)blocks * (size_t)p.entries * 16;
+}
+
+size_t propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                                  mp_bin_mode mode, const int32_t* K, int32_t n_sub, int64_t ns,
+                                  int64_t e0) {
+  CountsParams p{};
+  std::vector<int32_t> m_lo(MP_MAX_BINS + 1, 0);
+  int64_t blocks = 0;
+  if (setup_counts(p, "mp_propagate_counts_workspace", M, E, d, bin_of_mode, mode, m_lo.data(), K,
+                   n_sub, ns, e0, MP_MATRIX_P, blocks) != MP_OK)
+    return 0;
+  size_t part_bytes, total;
+  propagate_counts_sizes(p, blocks, part_bytes, total);
+  return total;
+}
+
+mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                                  const void* ab, const double* n, const void* packed, int32_t d,
+                                  const int32_t* bin_of_mode, mp_bin_mode mode,
+                                  const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                  int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts: joint distributions of several bins are not fused (d = %d)",
+               d);
+  CountsParams p{};
+  int64_t blocks = 0;
+  const mp_status st = setup_counts(p, "mp_propagate_counts", M, E, d, bin_of_mode, mode, m_lo, K,
+                                    n_sub, ns, e0, est, blocks);
+  if (st != MP_OK) return st;
+  size_t part_bytes, total;
+  propagate_counts_sizes(p, blocks, part_bytes, total);
+  MP_CHECK_ARG(ws && ws_bytes >= total, MP_ERR_WORKSPACE,
+               "mp_propagate_counts: workspace of %zu bytes needed, %zu given", total, ws_bytes);
+  FusedOut fo{};
+  fo.part = (float*)ws;
+  fo.E = E;
+  fo.n_runs = p.n_runs;
+  for (int q = 0; q < p.n_runs; ++q) {
+    fo.run_lo[q] = p.run_lo[q];
+    fo.run_hi[q] = p.run_hi[q];
+  }
+  fused_slots(p.n_runs, fo.run_lo, fo.run_hi, fo.slot_off);
+  double* blk = (double*)((char*)ws + part_bytes);
+  if (p.n_runs > 0) {
+    const mp_status sg = gemm_fused_launch(M, E, packed, prec, ab, fo, stream);
+    if (sg != MP_OK) return sg;
+  }
+  hipLaunchKernelGGL((counts_fused<FromPartials, false>), dim3((unsigned)blocks),
+                     dim3(kCountThreads), 0, stream, p, FromPartials{fo.part}, n, blk);
+  MP_HIP_LAUNCH_CHECK("mp_propagate_counts counts launch");
+  const int ns_touched = (int)(p.s_last - p.s_first + 1);
+  hipLaunchKernelGGL(counts_reduce, dim3((p.entries + 255) / 256, ns_touched), dim3(256), 0, stream,
+                     p, (const double*)blk, acc);
+  MP_HIP_LAUNCH_CHECK("mp_propagate_counts reduce launch");
   return MP_OK;
 }
 

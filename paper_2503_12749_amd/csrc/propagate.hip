@@ -407,6 +407,77 @@ __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt(((N & 15) | ((N >> 4) << 14)) | (7 << 4) | (15 << 8));
 }
 
+// Occupation-fused epilogue (see FusedOut).  The tile covers modes
+// [m0, m0 + 128) and samples [n0, n0 + 128): its waves hold, element for
+// element in the same register positions, a = Re alpha' (wm 0, wn 0),
+// c = Re beta' (wm 0, wn 1), b = Im alpha' (wm 1, wn 0) and e = -Im beta'
+// (wm 1, wn 1).  The beta waves publish their blocks through LDS; the alpha
+// waves form their halves of n = alpha' beta' = (a c + b e) + i (b c - a e),
+// sum them over the modes of every bin run in the block (lane halves hold
+// interleaved rows and are combined by a shuffle) and store per-sample
+// partials.  LDS layout: [wm][(i 4 + j) 4 + g][lane][4] floats, conflict-free
+// 16-byte accesses.
+__device__ __attribute__((always_inline)) inline void fused_epilogue(
+    f32x16 (&acc)[4][4], float* __restrict__ lds_f, const FusedOut& fo, int64_t m0, int64_t n0,
+    int wm, int wn, int lane, float out_scale) {
+  const int lr = lane & 31, lh = lane >> 5;
+  __syncthreads();  // every wave is done reading the operand stages
+  if (wn == 1) {
+    float* dst = lds_f + wm * 16384;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          *(f32x4*)(dst + ((((i * 4 + j) * 4 + g) * 64) + lane) * 4) =
+              f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                    acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+  }
+  __syncthreads();
+  if (wn != 0) return;
+  const float* cre = lds_f;          // Re beta'
+  const float* cim = lds_f + 16384;  // -Im beta'
+  const int blk = (int)m0;
+  for (int q = 0; q < fo.n_runs; ++q) {
+    const int lo = (fo.run_lo[q] > blk ? fo.run_lo[q] : blk) - blk;
+    const int hi = (fo.run_hi[q] < blk + 128 ? fo.run_hi[q] : blk + 128) - blk;
+    if (lo >= hi) continue;
+    const int64_t slot = fo.slot_off[q] + (blk >> 7) - (fo.run_lo[q] >> 7);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float pr = 0.0f, pi = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int off = ((((i * 4 + j) * 4 + g) * 64) + lane) * 4;
+          const f32x4 c = *(const f32x4*)(cre + off);
+          const f32x4 e = *(const f32x4*)(cim + off);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int mode = i * 32 + 8 * g + 4 * lh + rr;
+            const float x = (mode >= lo && mode < hi) ? acc[i][j][4 * g + rr] * out_scale : 0.0f;
+            if (wm == 0) {
+              pr = fmaf(x, c[rr], pr);
+              pi = fmaf(-x, e[rr], pi);
+            } else {
+              pr = fmaf(x, e[rr], pr);
+              pi = fmaf(x, c[rr], pi);
+            }
+          }
+        }
+      pr += __shfl_xor(pr, 32);
+      pi += __shfl_xor(pi, 32);
+      const int64_t smp = n0 + j * 32 + lr;
+      if (lh == 0 && smp < fo.E) {
+        typedef __attribute__((ext_vector_type(2))) float f32x2;
+        *(f32x2*)(fo.part + (slot * fo.E + smp) * 4 + 2 * wm) = f32x2{pr, pi};
+      }
+    }
+  }
+}
+
 // Ping-pong schedule of the two-stage direct-to-LDS kernel.  Fragments of a
 // slab's two k16 steps live in two register sets F0, F1.  Per slab kt:
 //   read F1 (kt, step 1) | MFMAs on F0 | drain own loads of slab kt + 1 |
@@ -415,26 +486,34 @@ __device__ inline void wait_vm() {
 // The barrier sits between two MFMA groups, and the LDS reads after it
 // overlap the second group, so neither the barrier nor the LDS latency
 // leaves the matrix pipe idle for a whole fragment round trip.
-template <typename H>
+// FUSED: the tile's rows are the Re rows of modes [m0, m0 + 128) followed by
+// their Im rows, its columns the alpha columns of samples [n0, n0 + 128)
+// followed by their beta columns, and the epilogue is fused_epilogue instead
+// of the store of C.
+template <typename H, bool FUSED>
 __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
                                      const uint16_t* __restrict__ B, float* __restrict__ C,
                                      int64_t ldm, int64_t ncols, int64_t m0, int64_t n0,
-                                     float out_scale) {
+                                     float out_scale, const FusedOut* fo) {
   typedef typename SplitMfma<H>::frag frag;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lh = lane >> 5;
 
   const uint16_t* plane_src;
-  int64_t row_limit;
+  int64_t row_limit, hi_off;
   // wave w fills plane w: hi or lo (+32) half of the interleaved rows of A
-  // (w < 2) or of the columns of B; both have 2 ldm values per row
+  // (w < 2) or of the columns of B; both have 2 ldm values per row.  Fused
+  // tiles take their second 128 rows from the Im rows (A: + ldm) or the beta
+  // columns (B: + E), and clamp sample offsets past the end of the chunk.
   if (wave < 2) {
     plane_src = A + (wave == 1 ? 32 : 0) + m0 * 2 * ldm;
-    row_limit = S_BM;
+    row_limit = FUSED ? 128 : S_BM;
+    hi_off = ldm;
   } else {
     plane_src = B + (wave == 3 ? 32 : 0) + n0 * 2 * ldm;
-    row_limit = ncols - n0;
+    row_limit = FUSED ? ncols / 2 - n0 : ncols - n0;
+    hi_off = ncols / 2;
   }
   const int lrow = lane >> 2;
   const int lchunk = (lane & 3) ^ swz(lrow);
@@ -442,8 +521,14 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     char* dst = (char*)&lds[st][wave][0];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      int64_t row = 16 * q + lrow;
-      row = row < row_limit ? row : row_limit - 1;
+      int64_t row;
+      if constexpr (FUSED) {
+        row = 16 * (q & 7) + lrow;
+        row = (row < row_limit ? row : row_limit - 1) + (q >= 8 ? hi_off : 0);
+      } else {
+        row = 16 * q + lrow;
+        row = row < row_limit ? row : row_limit - 1;
+      }
       const uint16_t* g = plane_src + row * 2 * ldm + 2 * k0 + lchunk * 8;
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
     }
@@ -552,6 +637,10 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
+  if constexpr (FUSED) {
+    fused_epilogue(acc, (float*)&lds[0][0][0], *fo, m0, n0, wm, wn, lane, out_scale);
+    return;
+  }
   const int64_t ldc = 2 * ldm;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -579,7 +668,24 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
   if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  split_pp_tile<H>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN, out_scale);
+  split_pp_tile<H, false>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN,
+                          out_scale, nullptr);
+}
+
+// Occupation-fused twin of gemm_split_256_pp: tile (tm, tn) covers modes
+// [128 tm, 128 tm + 128) and samples [128 tn, 128 tn + 128); no C is written.
+template <typename H>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __restrict__ A,
+                                                              const uint16_t* __restrict__ B,
+                                                              int64_t ldm, int64_t ncols,
+                                                              float out_scale, int order,
+                                                              FusedOut fo) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  split_pp_tile<H, true>(lds, A, B, nullptr, ldm, ncols, (int64_t)tm * 128, (int64_t)tn * 128,
+                         out_scale, &fo);
 }
 
 // ---------------------------------------------------------------- FP32, 256 x 256
@@ -599,22 +705,29 @@ constexpr int F_PLANE = S_BM * F_BK;  // floats of one LDS operand plane
 
 __device__ inline int swz8(int r) { return (r >> 1) & 7; }
 
+// FUSED: tile (tm, tn) covers modes [128 tm, 128 tm + 128) and samples
+// [128 tn, 128 tn + 128) as in gemm_split_occ, and the epilogue is
+// fused_epilogue.
+template <bool FUSED>
 __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restrict__ A,
                                                            const float* __restrict__ B,
                                                            float* __restrict__ C, int64_t ldm,
-                                                           int64_t ncols, int order) {
+                                                           int64_t ncols, int order, FusedOut fo) {
   __shared__ __attribute__((aligned(1024))) float lds[2][2][F_PLANE];
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
   if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * S_BM, n0 = (int64_t)tn * S_BN;
+  const int64_t m0 = (int64_t)tm * (FUSED ? 128 : S_BM), n0 = (int64_t)tn * (FUSED ? 128 : S_BN);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lh = lane >> 5;
 
   const int op = wave >> 1, half = wave & 1;
   const float* src = op == 0 ? A + m0 * ldm : B + n0 * ldm;
-  const int64_t row_limit = op == 0 ? S_BM : ncols - n0;
+  // fused tiles: the second half of the rows are the Im rows (A) or the beta
+  // columns (B), and sample offsets past the chunk are clamped
+  const int64_t row_limit = op == 0 ? (FUSED ? 128 : S_BM) : (FUSED ? ncols / 2 - n0 : ncols - n0);
+  const int64_t hi_off = op == 0 ? ldm : ncols / 2;
   const int lrow = lane >> 3;
   // lane l writes LDS slot 16 l of each 1 KB block (8 rows): row 8 q + l / 8
   // of the wave's half, slot l % 8, which holds global chunk (l % 8) ^ swz8(row)
@@ -623,7 +736,13 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int r = half * 128 + 8 * q + lrow;
-      const int64_t row = r < row_limit ? r : row_limit - 1;
+      int64_t row;
+      if constexpr (FUSED) {
+        const int64_t rr = 8 * q + lrow;  // row within the half
+        row = (rr < row_limit ? rr : row_limit - 1) + (half ? hi_off : 0);
+      } else {
+        row = r < row_limit ? r : row_limit - 1;
+      }
       const float* g = src + row * ldm + k0 + (((lane & 7) ^ swz8(r)) << 2);
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
     }
@@ -724,6 +843,10 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
     __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
+  if constexpr (FUSED) {
+    fused_epilogue(acc, &lds[0][0][0], fo, m0, n0, wm, wn, lane, 1.0f);
+    return;
+  }
   const int64_t ldc = 2 * ldm;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -756,8 +879,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet
     const int4 w = items[it];  // (net, tile_m, tile_n, unused); net < 0: idle slot
     if (w.x < 0) continue;
     const GroupNet g = nets[w.x];
-    split_pp_tile<H>(lds, g.A, g.B, g.C, g.ldm, g.ncols, (int64_t)w.y * S_BM, (int64_t)w.z * S_BN,
-                     g.out_scale);
+    split_pp_tile<H, false>(lds, g.A, g.B, g.C, g.ldm, g.ncols, (int64_t)w.y * S_BM,
+                            (int64_t)w.z * S_BN, g.out_scale, nullptr);
     __syncthreads();  // the next item reuses the LDS stages
   }
 }
@@ -851,9 +974,9 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
       break;
     case MP_FP32:
       if (f32_variant() == 1)
-        hipLaunchKernelGGL(gemm_f32_pp, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)), dim3(kThreads), 0,
-                           stream, (const float*)packed, (const float*)ab, (float*)C, ldm, ncols,
-                           tile_order());
+        hipLaunchKernelGGL(gemm_f32_pp<false>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                           dim3(kThreads), 0, stream, (const float*)packed, (const float*)ab,
+                           (float*)C, ldm, ncols, tile_order(), FusedOut{});
       else
         hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0,
                            stream, (const float*)packed, (const float*)ab, (float*)C, ldm, ncols,
@@ -885,6 +1008,35 @@ mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_item
     return MP_ERR_UNSUPPORTED;
   }
   MP_HIP_LAUNCH_CHECK("plan grouped gemm launch");
+  return MP_OK;
+}
+
+// GEMM with the occupation-fused epilogue on an already packed operand.
+mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                            const void* ab, const FusedOut& fo, hipStream_t stream) {
+  const int64_t ldm = ld_modes(M), ncols = 2 * E;
+  const int grid = grid_tiles(ldm, ncols, S_BM, S_BN);
+  switch (prec) {
+    case MP_FP32:
+      hipLaunchKernelGGL(gemm_f32_pp<true>, dim3(grid), dim3(kThreads), 0, stream,
+                         (const float*)packed, (const float*)ab, (float*)nullptr, ldm, ncols,
+                         tile_order(), fo);
+      break;
+    case MP_SPLIT_BF16:
+      hipLaunchKernelGGL(gemm_split_occ<__bf16>, dim3(grid), dim3(kThreads), 0, stream,
+                         (const uint16_t*)packed, (const uint16_t*)ab, ldm, ncols, 1.0f,
+                         tile_order(), fo);
+      break;
+    case MP_SPLIT_FP16:
+      hipLaunchKernelGGL(gemm_split_occ<_Float16>, dim3(grid), dim3(kThreads), 0, stream,
+                         (const uint16_t*)packed, (const uint16_t*)ab, ldm, ncols,
+                         ldexpf(1.0f, -fp16_scale_exp(M)), tile_order(), fo);
+      break;
+    default:
+      set_error("mp_propagate_counts: the fused path supports FP32 and the split precisions");
+      return MP_ERR_UNSUPPORTED;
+  }
+  MP_HIP_LAUNCH_CHECK("mp_propagate_counts fused gemm launch");
   return MP_OK;
 }
 

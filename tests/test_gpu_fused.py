@@ -1,0 +1,119 @@
+"""The occupation-fused GEMM path (mp_propagate_counts) against the unfused
+path (mp_propagate_packed + mp_binned_counts) on the same noise, and against
+the FP64 oracle.  The fused path sums the occupations in FP32 within a
+128-mode block and in FP64 across blocks instead of in FP64 per mode, so the
+two agree to FP32 rounding: far inside sigma_T."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator as oest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_12749_amd  # noqa: F401
+    yield
+
+
+def _bins(M):
+    """Three bins whose runs cross 128-mode blocks; bin 1 has two runs; a tail
+    of uncounted modes."""
+    b = np.full(M, -1, dtype=np.int32)
+    b[0:100] = 0
+    b[100:180] = 1
+    b[260:300] = 1
+    b[180:260] = 2
+    return b
+
+
+def _run(fused, prec, est, M=333, E=1000, n_sub=5, chunk=384, seed=71, t=0.9):
+    import paper_2503_12749_amd as mp
+    T = t * synth.haar_unitary(M, seed)
+    r = np.linspace(0.4, 1.2, M)
+    bins = _bins(M)
+    N = np.sinh(r) ** 2
+    wins = []
+    for b in range(3):
+        mb = t * t * N[bins == b].sum()
+        sb = np.sqrt(mb + (t * t) ** 2 * (N[bins == b] * (2 * N[bins == b] + 1)).sum())
+        wins.append(synth.count_window(mb, 1.5 * sb))
+    mt, st = synth.uniform_loss_moments(r[bins >= 0], t)
+    wins.append(synth.count_window(mt, 1.5 * st))
+    p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=3,
+                          mode="marginals_and_total", windows=wins, n_sub=n_sub,
+                          samples_per_sub=E // n_sub, chunk=chunk, est=est, device=DEV,
+                          fused=fused)
+    p.run()
+    P, Pi, s = p.result()
+    return P, s, T, r, bins, wins
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
+def test_fused_equals_unfused(prec, est):
+    Pf, sf, *_ = _run(True, prec, est)
+    Pu, su, *_ = _run(False, prec, est)
+    scale = np.abs(Pu).max()
+    assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-6 * scale), np.abs(Pf - Pu).max()
+    np.testing.assert_allclose(sf, su, rtol=1e-3, atol=1e-6 * scale)
+
+
+def test_fused_matches_oracle():
+    """Split-BF16 fused run against the FP64 oracle on the same noise, per
+    distribution (three bin marginals and the total): far inside sigma_T."""
+    P, s, T, r, bins, wins = _run(True, "split_bf16", "matrix_p")
+    mar = oest.estimate(T, r, 71, 1000, 5, bins, 3, wins[:3], mode="marginals", chunk=500)
+    tot = oest.estimate(T, r, 71, 1000, 5, np.where(bins >= 0, 0, -1), 1, wins[3:], mode="joint",
+                        chunk=500)
+    off = 0
+    for q in range(4):
+        K = wins[q][1]
+        if q < 3:
+            Pr, sr = mar["P"][q, :K], mar["sigma"][q, :K]
+        else:
+            Pr, sr = tot["P"], tot["sigma"]
+        got = P[off: off + K]
+        assert np.all(np.abs(got - Pr) <= 0.05 * sr + 1e-6 * np.abs(Pr).max()), q
+        off += K
+
+
+def test_full_size_m4000_fused_equals_unfused():
+    """M = 4000 (32 blocks of 128 modes), one chunk of 65536 samples over 8
+    sub-ensembles, total counts: fused and unfused split-BF16 agree."""
+    import paper_2503_12749_amd as mp
+    M, t, E, n_sub = 4000, 0.95, 65536, 8
+    T = t * synth.haar_unitary(M, 5)
+    r = np.full(M, 1.0)
+    mean, sd = synth.uniform_loss_moments(r, t)
+    win = synth.count_window(mean, sd)
+    out = []
+    for fused in (True, False):
+        p = mp.CountsPipeline(T, r, prec="split_bf16", seed=9, windows=[win], n_sub=n_sub,
+                              samples_per_sub=E // n_sub, chunk=E, device=DEV, fused=fused)
+        p.run()
+        out.append(p.result())
+        del p
+        torch.cuda.empty_cache()
+    (Pf, _, sf), (Pu, _, su) = out
+    assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-7 * Pu.max()), np.abs(Pf - Pu).max()
+
+
+def test_fused_rejects_unsupported_cases():
+    import paper_2503_12749_amd as mp
+    with pytest.raises(mp.MPError):
+        mp.CountsPipeline(np.eye(8, dtype=complex), np.ones(8), prec="fp64", seed=1,
+                          windows=[(0, 64)], n_sub=1, samples_per_sub=64, chunk=64, device=DEV,
+                          fused=True).run()
+    bins = np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.int32)
+    with pytest.raises(mp.MPError):
+        mp.CountsPipeline(np.eye(8, dtype=complex), np.ones(8), prec="fp32", seed=1, bin_of_mode=bins,
+                          d=2, mode="joint", windows=[(0, 32), (0, 32)], n_sub=1,
+                          samples_per_sub=64, chunk=64, device=DEV, fused=True).run()
