@@ -3,8 +3,9 @@
 Workload: M = 8000 modes, Haar network x t = 0.95, r = 1 on every mode,
 total-count distribution on the window [8083, 8083 + 3840) (mean 9972,
 sd 209), sub-ensembles of 8192 samples.  One step = one chunk of 65536
-samples through the whole path: mp_sample -> mp_propagate_packed (split-BF16
-MFMA GEMM) -> mp_binned_counts.  T is packed once per network
+samples through the whole path: mp_sample -> mp_propagate_counts (split-BF16
+MFMA GEMM whose epilogue forms the per-sample occupations, then the counting
+kernels; --unfused writes C and counts from it).  T is packed once per network
 (mp_pack_transmission, timed separately) and the inverse DFT
 (mp_counts_finalize) runs once after the timed steps; both enter the
 seconds-to-criterion figure.  The FP32 path is timed on the same workload for
@@ -37,18 +38,18 @@ HBM_PEAK_GBS = 8000.0
 # (fetch x2, write x1); valid only for the GEMM source they were taken from.
 # Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
 TRAFFIC = {
-    "split_bf16": {"source_sha256_16": "948a23a9be33d9ef",
-                   "fetch_bytes": 1.153e8 * 1024 * 2, "write_bytes": 8.261e6 * 1024},
-    "fp32": {"source_sha256_16": "948a23a9be33d9ef",
-             "fetch_bytes": 4.906e7 * 1024 * 2, "write_bytes": 8.258e6 * 1024},
+    ("split_bf16", True): {"source_sha256_16": "90ed4a70e5457d8b",
+                           "fetch_bytes": 1.101e8 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("fp32", True): {"source_sha256_16": "90ed4a70e5457d8b",
+                     "fetch_bytes": 6.948e7 * 1024 * 2, "write_bytes": 1.387e6 * 1024},
 }
 
 
-def gemm_traffic_gb(prec):
+def gemm_traffic_gb(prec, fused):
     """Counter-derived bytes per GEMM launch in GB, or None when the GEMM
     source has changed since the counters were taken."""
     import hashlib
-    rec = TRAFFIC.get(prec)
+    rec = TRAFFIC.get((prec, fused))
     if rec is None:
         return None
     src = os.path.join(ROOT, "paper_2503_12749_amd", "csrc", "propagate.hip")
@@ -84,9 +85,16 @@ def timed_run(mp, torch, pipe, steps, warmup, g_start=0):
     for i in range(steps):
         mp.mp_sample(pipe.M, g, E, pipe.r, pipe.seed, pipe.net, pipe.prec, pipe.ab, pipe.n)
         ev[i][0].record(stream)
-        mp.mp_propagate_packed(pipe.M, E, pipe.prec, pipe.ab, pipe.C, pipe.ws_prop)
-        ev[i][1].record(stream)
-        pipe.counts_chunk(g, E)
+        if pipe.fused:
+            # GEMM with the occupation epilogue, then the counting kernels
+            mp.mp_propagate_counts(pipe.M, E, pipe.prec, pipe.est, pipe.ab, pipe.n, pipe.ws_prop,
+                                   pipe.d, pipe.bins, pipe.mode, pipe.m_lo, pipe.K, pipe.n_sub,
+                                   pipe.ns, g, pipe.acc, pipe.ws_counts)
+            ev[i][1].record(stream)
+        else:
+            mp.mp_propagate_packed(pipe.M, E, pipe.prec, pipe.ab, pipe.C, pipe.ws_prop)
+            ev[i][1].record(stream)
+            pipe.counts_chunk(g, E)
         g += E
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
@@ -139,7 +147,8 @@ def run_m8000(args, mp, torch, synth):
         if not prec:
             continue
         pipe = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
-                                 n_sub=n_sub, samples_per_sub=ns, chunk=args.chunk)
+                                 n_sub=n_sub, samples_per_sub=ns, chunk=args.chunk,
+                                 fused=not args.unfused and prec != "fp64")
         secs, gemm_ms, g, pack_ms = timed_run(mp, torch, pipe, steps,
                                               args.warmup if prec == args.prec else 1)
         t0 = time.perf_counter()
@@ -178,9 +187,12 @@ def run_m8000(args, mp, torch, synth):
     peak = PEAKS_TFLOPS[args.prec]
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": gemm_traffic_gb(args.prec) if w.M == 8000 and args.chunk == 65536 else None,
+            "traffic": (gemm_traffic_gb(args.prec, not args.unfused)
+                        if w.M == 8000 and args.chunk == 65536 else None),
             "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, calibrated on a 1 GiB copy)",
-            "kernel": f"gemm_{args.prec} (mp_propagate_packed)",
+            "kernel": (f"gemm_{args.prec} with the occupation epilogue (mp_propagate_counts; the "
+                       f"timed call includes the counting kernels)" if not args.unfused
+                       else f"gemm_{args.prec} (mp_propagate_packed)"),
             "algorithmic_flops_per_launch": flops}
     if args.prec.startswith("split"):
         roof["executed_mfma_frac"] = round(3 * achieved / peak, 4)
@@ -683,6 +695,8 @@ def main():
     ap.add_argument("--M", type=int, default=8000)
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unfused", action="store_true",
+                    help="m8000: write C and count from it instead of the occupation-fused GEMM")
     ap.add_argument("--workload", default="m8000",
                     choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate",
                              "plusp_m20", "moments_m1000", "scaling_appb", "copy"],

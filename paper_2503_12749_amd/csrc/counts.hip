@@ -145,10 +145,12 @@ __device__ inline void sample_bin_sums(const CountsParams& p, const CT* __restri
 __device__ inline void dist_occupation(const CountsParams& p, const double (&nb)[MP_MAX_BINS][2],
                                        int q, double& vr, double& vi) {
   double tr = 0.0, ti = 0.0;
-  for (int b = 0; b < p.d; ++b) {
-    tr += nb[b][0];
-    ti += nb[b][1];
-  }
+#pragma unroll
+  for (int b = 0; b < MP_MAX_BINS; ++b)
+    if (b < p.d) {
+      tr += nb[b][0];
+      ti += nb[b][1];
+    }
   vr = tr;
   vi = ti;
   const int src = p.dist_src[q];
