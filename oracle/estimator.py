@@ -169,3 +169,39 @@ def factorial_moment_samples(n: np.ndarray, nS: np.ndarray, kmax: int):
     for k in range(1, kmax + 1):
         out[:, k - 1] = nS ** k * (th if k % 2 else 1.0)
     return out
+
+
+def pair_correlations(T, r, seed, E, n_sub, g0=0, net=0, chunk=2000):
+    """Normally ordered pair moments <:n_i n_j:> of single output modes from
+    the same ensemble (main text, eq. moment, with every output mode taken as
+    its own group): the mixed second derivative of the per-sample generating
+    function at z = 1 is n'_i n'_j, with the even-order weight 1 for both the
+    parity-projected and the +P estimator.  Each sub-ensemble sums
+    n'_i n'_j over its samples (a plain product of the occupation matrix with
+    itself); then the sub-ensemble statistics of Appendix A.
+
+    Samples g0 .. g0+E-1, n_sub equal sub-ensembles.  Returns dict(G2 = mean
+    (M, M) complex, sigma = sigma_T of the real part, Ps = sub-ensemble means,
+    abs_sums = per sub-ensemble sums of |n'_i||n'_j| (the scale of the
+    rounding error of any evaluation of the sums))."""
+    assert E % n_sub == 0
+    ns = E // n_sub
+    r = np.asarray(r, dtype=np.float64)
+    M = np.asarray(T).shape[0]
+    sums = np.zeros((n_sub, M, M), dtype=np.complex128)
+    abs_sums = np.zeros((n_sub, M, M))
+    done = 0
+    while done < E:
+        c = min(chunk, E - done)
+        alpha, beta, _ = sampler.sample(r, g0 + done, c, seed, net)
+        ap, bp = propagate(T, alpha, beta)
+        occ = ap * bp
+        sub = (np.arange(done, done + c)) // ns
+        for s in np.unique(sub):
+            x = occ[sub == s]
+            sums[s] += x.T @ x
+            a = np.abs(x)
+            abs_sums[s] += a.T @ a
+        done += c
+    Ps, P, sig = subensemble_stats(sums, np.full(n_sub, ns, dtype=np.float64))
+    return dict(G2=P, sigma=sig, Ps=Ps, abs_sums=abs_sums)

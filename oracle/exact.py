@@ -16,8 +16,8 @@ E3  any T, any bins: the same expectation is a Gaussian integral,
     W = T^T diag(z_b(i) - 1 over counted outputs i) T*,
     evaluated on the unit circle through eigenvalue factorisations whose
     principal square roots are analytic in the closed unit disk.
-E4  closed-form mean and variance of a bin count (Isserlis' theorem on the
-    same Gaussian).
+E4  closed-form mean and variance of a bin count, and the normally ordered
+    pair moments of single modes (Isserlis' theorem on the same Gaussian).
 Cutoffs m_min / m_max of Appendix B (first and last count at which the
 lossless law reaches a given level).
 
@@ -189,3 +189,18 @@ def count_moments(T: np.ndarray, r: np.ndarray, counted: np.ndarray):
     mean = float(np.real(np.diag(W)) @ N)
     var = mean + float(N @ (np.abs(W) ** 2) @ N) + float(A @ np.real(W * W) @ A)
     return mean, var
+
+
+def pair_moments(T: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """<:n_i n_j:> = <a_i^+ a_j^+ a_i a_j> of the lossy output of squeezed
+    vacua (Isserlis' theorem on the Gaussian state):
+        N_ii N_jj + |N_ij|^2 + |S_ij|^2,
+    N = T diag(sinh^2 r) T^+  (the <a^+ a> correlations, up to conjugation),
+    S = T diag(sinh r cosh r) T^T  (the <a a> correlations).
+    Shape (M, M), real."""
+    T = np.asarray(T, dtype=np.complex128)
+    A, N = input_moments(np.asarray(r, dtype=np.float64))
+    Nm = T @ (N[:, None] * T.conj().T)
+    Sm = T @ (A[:, None] * T.T)
+    d = np.real(np.diag(Nm))
+    return d[:, None] * d[None, :] + np.abs(Nm) ** 2 + np.abs(Sm) ** 2

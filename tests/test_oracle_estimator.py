@@ -227,3 +227,46 @@ def test_factorial_moments_are_derivatives_of_the_per_sample_law(plus_p):
         ff[m < k] = 0.0
         direct = (G * ff[None, :]).sum(axis=1)
         np.testing.assert_allclose(direct, f[:, k - 1], rtol=1e-9, atol=1e-12)
+
+
+def _lossy_network(M, seed, t):
+    """Haar unitary with mode-dependent input loss: sub-unitary, non-normal."""
+    return synth.haar_unitary(M, seed) * np.asarray(t)[None, :]
+
+
+def test_pair_correlations_are_count_space_mixed_moments():
+    """Per sub-ensemble, the pair estimator equals the mixed moments of the
+    count-space estimator with single-mode bins: sum m_1 m_2 G(m_1, m_2) for
+    two modes and sum m (m - 1) G(m) for one (eq. moment via the per-sample
+    law of eq. c-number-variable; the parity weights cancel exactly)."""
+    M, E, n_sub, K = 5, 400, 4, 40
+    r = np.array([0.3, 0.5, 0.45, 0.6, 0.35])
+    T = _lossy_network(M, 21, [0.9, 0.7, 1.0, 0.8, 0.95])
+    pc = estimator.pair_correlations(T, r, 5, E, n_sub, chunk=150)
+    m = np.arange(K, dtype=float)
+    for i in range(M):
+        for j in range(i, M):
+            bins = np.full(M, -1)
+            if i == j:
+                bins[i] = 0
+                e = estimator.estimate(T, r, 5, E, n_sub, bins, 1, [(0, K)], chunk=150)
+                ref = (e["Ps"] * (m * (m - 1))[None, :]).sum(axis=1)
+            else:
+                bins[i], bins[j] = 0, 1
+                e = estimator.estimate(T, r, 5, E, n_sub, bins, 2, [(0, K), (0, K)], chunk=150)
+                ref = (e["Ps"] * (m[:, None] * m[None, :])[None]).sum(axis=(1, 2))
+            np.testing.assert_allclose(pc["Ps"][:, i, j], ref, rtol=1e-9, atol=1e-13)
+            np.testing.assert_allclose(pc["Ps"][:, j, i], ref, rtol=1e-9, atol=1e-13)
+
+
+def test_pair_correlations_vs_gaussian_closed_form():
+    """Statistical agreement with Isserlis' closed form on a lossy,
+    non-uniformly squeezed network; the closed form of the transposed network
+    is rejected."""
+    r = np.array([0.5, 0.8, 0.3, 0.6])
+    T = _lossy_network(4, 31, [0.9, 0.6, 1.0, 0.75])
+    pc = estimator.pair_correlations(T, r, 12, 200000, 40, chunk=20000)
+    z = (pc["G2"].real - exact.pair_moments(T, r)) / pc["sigma"]
+    assert np.abs(z).max() < 4.5, z
+    z_wrong = (pc["G2"].real - exact.pair_moments(T.T, r)) / pc["sigma"]
+    assert np.abs(z_wrong).max() > 10

@@ -96,3 +96,37 @@ def test_appendix_b_cutoffs():
         assert abs(exact.cutoffs(M, g["r"], g["level"])[0] - mmin) <= tol
     for M, mmax in zip(g["error_M"], g["error_m_max"]):
         assert abs(exact.cutoffs(M, g["r"], g["level"])[1] - mmax) <= tol
+
+
+def test_pair_moments_vs_fock_and_single_mode():
+    """<:n_1 n_2:> and <:n_i^2:> against brute-force Fock probabilities at
+    M = 2 (lossy, asymmetric network); the squeezed-vacuum value
+    <a^+2 a^2> = 3 sinh^4 r + sinh^2 r for one lossless mode; a transposed
+    network changes them."""
+    r = np.array([0.4, 0.6])
+    T = _subunitary(2, 3)
+    Pf, tail = fock.binned_probabilities(T, r, np.array([0, 1]), 2, 30)
+    m = np.arange(Pf.shape[0], dtype=float)
+    G = exact.pair_moments(T, r)
+    tol = 1e-9 + 3600 * tail
+    assert abs((m[:, None] * m[None, :] * Pf).sum() - G[0, 1]) < tol
+    assert abs((m * (m - 1) * Pf.sum(axis=1)).sum() - G[0, 0]) < tol
+    assert abs((m * (m - 1) * Pf.sum(axis=0)).sum() - G[1, 1]) < tol
+    np.testing.assert_allclose(G, G.T, rtol=0, atol=1e-15)
+    assert np.abs(exact.pair_moments(T.T, r) - G).max() > 1e-3
+    for rr in (0.3, 1.1):
+        s = np.sinh(rr) ** 2
+        np.testing.assert_allclose(exact.pair_moments(np.eye(1), np.array([rr]))[0, 0],
+                                   3 * s * s + s, rtol=1e-14)
+
+
+def test_pair_moments_sum_to_count_factorial_moment():
+    """sum over counted i, j of <:n_i n_j:> = <N (N - 1)> = var + mean^2 - mean
+    of the bin count (closed-form mean and variance)."""
+    r = synth.squeezing_random_uniform(9, 0.4, 1.2, 3)
+    T = _subunitary(9, 6, 1.05)
+    G = exact.pair_moments(T, r)
+    for counted in (np.ones(9), (np.arange(9) % 3 == 0).astype(float)):
+        mean, var = exact.count_moments(T, r, counted)
+        sel = counted > 0
+        np.testing.assert_allclose(G[np.ix_(sel, sel)].sum(), var + mean * mean - mean, rtol=1e-12)
