@@ -604,6 +604,72 @@ def run_moments_m1000(args, mp, torch, synth):
         counts_run_s=base_s, counts_and_moments_run_s=full_s, moments=rows)
 
 
+def run_pairs_m1000(args, mp, torch, synth):
+    """Normally ordered pair moments <:n_i n_j:> of all 1000 output modes from
+    the M = 1000, t = 0.9, r = 1 FP32 ensemble (E = 1.2e6 in chunks of 1e5, 120
+    sub-ensembles of 1e4).  Each chunk: sample, propagate, mode occupations,
+    pair sums; the two pair kernels are timed with HIP events on the launch
+    stream; the whole job is timed after one untimed run.  The estimates are
+    compared with Isserlis' closed form at the stored entries (every diagonal
+    element and 2048 off-diagonal pairs)."""
+    w = synth.workload_m1000()
+    p = mp.PairPipeline(w.T, w.r, prec="fp32", seed=w.seed, n_sub=w.n_sub,
+                        samples_per_sub=w.samples_per_sub, chunk=w.chunk)
+    stream = torch.cuda.current_stream()
+    n_chunks = -(-w.E // w.chunk)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n_chunks)]
+
+    def job():
+        p.acc.zero_()
+        p.packed = False
+        for c, g in enumerate(range(0, w.E, w.chunk)):
+            E = min(w.chunk, w.E - g)
+            if not p.packed:
+                mp.mp_pack_transmission(p.M, p.T, p.prec, p.ws_prop)
+                p.packed = True
+            mp.mp_sample(p.M, g, E, p.r, p.seed, p.net, p.prec, p.ab, p.n)
+            mp.mp_propagate_packed(p.M, E, p.prec, p.ab, p.C, p.ws_prop)
+            ev[c][0].record(stream)
+            mp.mp_mode_occupations(p.M, E, p.C, p.prec, p.X)
+            ev[c][1].record(stream)
+            mp.mp_pair_correlations_accumulate(p.M, E, p.X, p.prec, p.n_sub, p.ns, g, p.acc)
+            ev[c][2].record(stream)
+        p.finalize()
+    job()
+    secs = _timed(torch, job)
+    occ_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    pair_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    G2, sig = p.result()
+    gold = _golden("m1000_pair_moments.json")
+    i, j = np.array(gold["i"]), np.array(gold["j"])
+    z = (G2.real[i, j] - np.array(gold["value"])) / sig[i, j]
+    diag = i == j
+    M, E_c = w.M, w.chunk
+    flops = 4.0 * M * (M + 1) * E_c  # 8 flops per complex product-sum, i <= j
+    nb = -(-M // 128)
+    executed = 8.0 * nb * (nb + 1) / 2 * 128 * 128 * E_c
+    achieved = flops / (pair_ms * 1e-3) / 1e12
+    occ_bytes = M * E_c * (16 + 8)  # C read (4 FP32 per mode), X written (2 FP32)
+    log(f"[bench] pairs m1000: job {secs:.3f} s, mode occupations {occ_ms:.3f} ms, pair sums "
+        f"{pair_ms:.3f} ms per chunk ({achieved:.1f} TFLOP/s), max |z| {np.abs(z).max():.2f}")
+    return _envelope(
+        "pair moments <:n_i n_j:> of all modes, M=1000, FP32: ensemble samples per second",
+        w.E / secs, "samples/s", 1e3 * secs,
+        f"M1000_t0.9_r1: E={w.E} in chunks of {w.chunk}, {w.n_sub} sub-ensembles, all "
+        f"{M * (M + 1) // 2} pairs i <= j", "fp32 (fp64 sums across chunks)",
+        job_s=secs, mode_occupations_ms_per_chunk=occ_ms, pair_sums_ms_per_chunk=pair_ms,
+        roofline={"bound": "mfma", "kernel": "pair_corr_f32", "achieved": round(achieved, 2),
+                  "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s",
+                  "frac": round(achieved / PEAKS_TFLOPS["fp32"], 4),
+                  "algorithmic_flops_per_launch": flops, "executed_flops_per_launch": executed,
+                  "traffic": None},
+        mode_occupations_GBps=occ_bytes / (occ_ms * 1e-3) / 1e9,
+        closed_form_check={"entries": int(len(z)), "max_abs_z": float(np.abs(z).max()),
+                           "rms_z": float(np.sqrt((z ** 2).mean())),
+                           "rms_z_diagonal": float(np.sqrt((z[diag] ** 2).mean())),
+                           "frac_within_3_sigma": float((np.abs(z) < 3).mean())})
+
+
 def run_scaling_appb(args, mp, torch, synth):
     """Appendix B scaling workloads.  Run time: lossless Haar networks,
     r = 0.89, M = 128 .. 8192, E = 1.2e6 (120 sub-ensembles of 1e4, chunks of
@@ -699,7 +765,7 @@ def main():
                     help="m8000: write C and count from it instead of the occupation-fused GEMM")
     ap.add_argument("--workload", default="m8000",
                     choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate",
-                             "plusp_m20", "moments_m1000", "scaling_appb", "copy"],
+                             "plusp_m20", "moments_m1000", "pairs_m1000", "scaling_appb", "copy"],
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
@@ -717,7 +783,8 @@ def main():
     runners = {"m8000": run_m8000, "joint_m1000": run_joint_m1000,
                "precision_m4000": run_precision_m4000, "batched": run_batched,
                "surrogate": run_surrogate, "plusp_m20": run_plusp_m20,
-               "moments_m1000": run_moments_m1000, "scaling_appb": run_scaling_appb,
+               "moments_m1000": run_moments_m1000, "pairs_m1000": run_pairs_m1000,
+               "scaling_appb": run_scaling_appb,
                "copy": run_copy}
     out = runners[args.workload](args, mp, torch, synth)
     print(json.dumps(out), flush=True)

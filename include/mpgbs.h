@@ -322,6 +322,40 @@ mp_status mp_subensemble_stats(int32_t n_sub, int64_t samples_per_sub, int64_t n
                                int32_t ncomp, double scale, const double* acc, double* mean,
                                double* sigma, void* stream);
 
+/*
+ * Normally ordered pair moments of single output modes, <:n_i n_j:> =
+ * <a_i^+ a_j^+ a_i a_j> (main text, eq. moment, with every output mode taken
+ * as its own group): per sample the mixed second derivative of the
+ * generating function at z = 1 is n'_i n'_j, n'_i = alpha'_i beta'_i, with
+ * weight 1 (an even order) for both estimators.  Two calls per chunk:
+ *
+ * mp_mode_occupations: n' of every (mode, sample) of a chunk.
+ *   C, M, E, prec  as written by mp_propagate for this chunk (32-byte aligned)
+ *   X              device, mp_mode_occupations_bytes(M, E, prec) bytes, FP64
+ *                  for MP_FP64 and FP32 otherwise; column-major with
+ *                  ld = round_up(M, 128): column k holds Re n'_{., k},
+ *                  column E + k holds Im n'_{., k}; padding modes are zero
+ *
+ * mp_pair_correlations_accumulate: for every sub-ensemble s touched by the
+ * chunk, acc[s][i][j] += sum over the chunk's samples k of s of
+ * n'_ik n'_jk (complex, symmetric in i, j; both triangles are written).
+ *   X              from mp_mode_occupations for this chunk (same M, E, prec)
+ *   n_sub, samples_per_sub, e0  as for mp_binned_counts
+ *   acc            device FP64, n_sub * M * M * 2 (re, im), layout [s][i][j],
+ *                  caller-zeroed, added into (16-byte aligned)
+ * FP64 runs FP64 FMAs; FP32 and the split precisions multiply FP32 values on
+ * the FP32 matrix cores, summing in FP32 over the chunk's samples of one
+ * sub-ensemble and in FP64 across chunks.  One workgroup owns each (tile,
+ * sub-ensemble), so the sums do not depend on scheduling.
+ * Means and sigma_T: mp_subensemble_stats(n_vals = M * M, ncomp = 2, scale = 1).
+ */
+size_t mp_mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec);
+mp_status mp_mode_occupations(int32_t M, int64_t E, const void* C, mp_precision prec, void* X,
+                              void* stream);
+mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, mp_precision prec,
+                                          int32_t n_sub, int64_t samples_per_sub, int64_t e0,
+                                          double* acc, void* stream);
+
 /* ---------------------------------------------------------------- batching */
 
 /* One network of a batched plan: total counts of all M outputs on the window

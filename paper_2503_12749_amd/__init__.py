@@ -18,8 +18,11 @@ from ._lib import BIN_MODES, ESTIMATORS, MPError, PRECISIONS, i32_array
 __all__ = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
     "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_occupations",
-    "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries", "mp_binned_workspace", "mp_binned_counts",
-    "mp_counts_finalize", "mp_finalize_workspace", "mp_version", "CountsPipeline", "Plan", "MPError",
+    "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries",
+    "mp_binned_workspace", "mp_binned_counts", "mp_counts_finalize", "mp_finalize_workspace",
+    "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
+    "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_version", "CountsPipeline",
+    "PairPipeline", "Plan", "MPError",
 ]
 
 
@@ -135,6 +138,21 @@ def mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean
     _lib.check(_lib.load().mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp,
                                                 float(scale), _ptr(acc), _ptr(mean), _ptr(sigma),
                                                 _stream(stream)))
+
+
+def mp_mode_occupations_bytes(M: int, E: int, prec) -> int:
+    return int(_lib.load().mp_mode_occupations_bytes(M, E, _prec(prec)))
+
+
+def mp_mode_occupations(M, E, C, prec, X, stream=None):
+    _lib.check(_lib.load().mp_mode_occupations(M, E, _ptr(C), _prec(prec), _ptr(X),
+                                               _stream(stream)))
+
+
+def mp_pair_correlations_accumulate(M, E, X, prec, n_sub, samples_per_sub, e0, acc, stream=None):
+    _lib.check(_lib.load().mp_pair_correlations_accumulate(M, E, _ptr(X), _prec(prec), n_sub,
+                                                           samples_per_sub, e0, _ptr(acc),
+                                                           _stream(stream)))
 
 
 def mp_propagate_counts_workspace(M, E, d, bin_of_mode, mode, K, n_sub, samples_per_sub, e0):
@@ -277,6 +295,75 @@ class CountsPipeline:
         a = v[:E, : self.M] + 1j * v[:E, ldm: ldm + self.M]
         b = v[E:, : self.M] - 1j * v[E:, ldm: ldm + self.M]
         return a, b
+
+
+class PairPipeline:
+    """Normally ordered pair moments <:n_i n_j:> of all output modes from one
+    ensemble: per chunk mp_sample -> mp_propagate_packed -> mp_mode_occupations
+    -> mp_pair_correlations_accumulate, then mp_subensemble_stats.  Buffers
+    are allocated once; T is packed on the first chunk."""
+
+    def __init__(self, T: np.ndarray, r: np.ndarray, *, prec="fp32", seed: int, net: int = 0,
+                 n_sub: int, samples_per_sub: int, chunk: int, device="cuda:0"):
+        import torch
+        T = np.ascontiguousarray(T, dtype=np.complex128)
+        self.M = int(T.shape[0])
+        assert T.shape == (self.M, self.M)
+        self.prec = _prec(prec)
+        self.seed, self.net = int(seed), int(net)
+        self.n_sub, self.ns, self.chunk = int(n_sub), int(samples_per_sub), int(chunk)
+        dev = torch.device(device)
+        self.T = torch.from_numpy(T.view(np.float64).reshape(-1).copy()).to(dev)
+        self.r = torch.from_numpy(np.asarray(r, dtype=np.float64).copy()).to(dev)
+        self.ab = torch.empty(mp_ab_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
+        self.C = torch.empty(mp_c_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
+        self.n = torch.empty(self.chunk, dtype=torch.float64, device=dev)
+        self.ws_prop = torch.empty(mp_propagate_workspace(self.M, self.prec), dtype=torch.uint8,
+                                   device=dev)
+        self.X = torch.empty(mp_mode_occupations_bytes(self.M, self.chunk, self.prec),
+                             dtype=torch.uint8, device=dev)
+        nv = self.M * self.M
+        self.acc = torch.zeros(self.n_sub * nv * 2, dtype=torch.float64, device=dev)
+        self.mean = torch.empty(nv * 2, dtype=torch.float64, device=dev)
+        self.sigma = torch.empty(nv, dtype=torch.float64, device=dev)
+        self.packed = False
+
+    def run_chunk(self, g0: int, E: int, stream=None):
+        assert 1 <= E <= self.chunk
+        if not self.packed:
+            mp_pack_transmission(self.M, self.T, self.prec, self.ws_prop, stream)
+            self.packed = True
+        mp_sample(self.M, g0, E, self.r, self.seed, self.net, self.prec, self.ab, self.n, stream)
+        mp_propagate_packed(self.M, E, self.prec, self.ab, self.C, self.ws_prop, stream)
+        self.pairs_chunk(g0, E, stream)
+
+    def pairs_chunk(self, g0: int, E: int, stream=None):
+        mp_mode_occupations(self.M, E, self.C, self.prec, self.X, stream)
+        mp_pair_correlations_accumulate(self.M, E, self.X, self.prec, self.n_sub, self.ns, g0,
+                                        self.acc, stream)
+
+    def finalize(self, stream=None):
+        mp_subensemble_stats(self.n_sub, self.ns, self.M * self.M, 2, 1.0, self.acc, self.mean,
+                             self.sigma, stream)
+
+    def run(self, E_total: int | None = None, g_start: int = 0, stream=None):
+        E_total = self.n_sub * self.ns if E_total is None else E_total
+        done = 0
+        while done < E_total:
+            c = min(self.chunk, E_total - done)
+            self.run_chunk(g_start + done, c, stream)
+            done += c
+        self.finalize(stream)
+
+    def result(self):
+        """(G2, sigma): complex (M, M) means and sigma_T of their real parts
+        (synchronises)."""
+        m = self.mean.cpu().numpy().view(np.complex128).reshape(self.M, self.M)
+        return m, self.sigma.cpu().numpy().reshape(self.M, self.M)
+
+    def subensemble_sums(self):
+        """Per sub-ensemble sums, complex (n_sub, M, M) (synchronises)."""
+        return self.acc.cpu().numpy().view(np.complex128).reshape(self.n_sub, self.M, self.M)
 
 
 _HIP = None

@@ -71,6 +71,11 @@ mp_status subensemble_stats_launch(int32_t n_sub, int64_t ns, int64_t n_vals, in
                                    hipStream_t stream);
 
 int64_t mlp_param_count(const mp_mlp_shape* s);
+size_t mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec);
+mp_status mode_occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, void* X,
+                                  hipStream_t stream);
+mp_status pair_corr_launch(int32_t M, int64_t E, const void* X, mp_precision prec, int64_t ns,
+                           int64_t e0, double* acc, hipStream_t stream);
 size_t mlp_workspace(const mp_mlp_shape* s, int32_t batch);
 mp_status mlp_forward(const mp_mlp_shape* s, const uint16_t* w16, const float* params,
                       const float* X, int32_t batch, float* Y, void* ws, hipStream_t st);
@@ -396,6 +401,42 @@ mp_status mp_subensemble_stats(int32_t n_sub, int64_t samples_per_sub, int64_t n
                "mp_subensemble_stats: null pointer or non-finite scale");
   return subensemble_stats_launch(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean, sigma,
                                   (hipStream_t)stream);
+}
+
+size_t mp_mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec) {
+  return (M >= 1 && E >= 1 && valid_prec(prec)) ? mode_occupations_bytes(M, E, prec) : 0;
+}
+
+mp_status mp_mode_occupations(int32_t M, int64_t E, const void* C, mp_precision prec, void* X,
+                              void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1 && E >= 1, MP_ERR_ARG, "mp_mode_occupations: M and E must be >= 1");
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG, "mp_mode_occupations: unknown precision %d",
+               (int)prec);
+  MP_CHECK_ARG(C && X, MP_ERR_ARG, "mp_mode_occupations: null pointer argument");
+  MP_CHECK_ARG(aligned(C, 32) && aligned(X, 32), MP_ERR_ARG,
+               "mp_mode_occupations: C and X must be 32-byte aligned");
+  return mode_occupations_launch(M, E, C, prec, X, (hipStream_t)stream);
+}
+
+mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, mp_precision prec,
+                                          int32_t n_sub, int64_t samples_per_sub, int64_t e0,
+                                          double* acc, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1 && E >= 1, MP_ERR_ARG,
+               "mp_pair_correlations_accumulate: M and E must be >= 1");
+  MP_CHECK_ARG(valid_prec(prec), MP_ERR_ARG,
+               "mp_pair_correlations_accumulate: unknown precision %d", (int)prec);
+  MP_CHECK_ARG(X && acc, MP_ERR_ARG, "mp_pair_correlations_accumulate: null pointer argument");
+  MP_CHECK_ARG(aligned(X, 32) && aligned(acc, 16), MP_ERR_ARG,
+               "mp_pair_correlations_accumulate: X must be 32-byte and acc 16-byte aligned");
+  MP_CHECK_ARG(n_sub >= 1 && samples_per_sub >= 1 && e0 >= 0 &&
+                   (e0 + E - 1) / samples_per_sub < n_sub,
+               MP_ERR_ARG,
+               "mp_pair_correlations_accumulate: samples [%lld, %lld) do not fit n_sub = %d "
+               "sub-ensembles of %lld",
+               (long long)e0, (long long)(e0 + E), n_sub, (long long)samples_per_sub);
+  return pair_corr_launch(M, E, X, prec, samples_per_sub, e0, acc, (hipStream_t)stream);
 }
 
 int64_t mp_mlp_param_count(const mp_mlp_shape* shape) {

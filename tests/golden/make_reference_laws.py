@@ -7,6 +7,9 @@ Calls only oracle/ (and synth/ for the seeded networks):
   m1000_count_moments.json closed-form mean and variance (E4: W = T^T P_S T*)
                            of the two half-bins and the total of the M = 1000,
                            t = 0.9, r = 1 Haar workload
+  m1000_pair_moments.json  Isserlis closed form of <:n_i n_j:> for the same
+                           workload at every diagonal element and 2048
+                           seeded off-diagonal pairs (i < j)
 
 Run from the repository root:  python tests/golden/make_reference_laws.py
 """
@@ -39,6 +42,18 @@ def main():
         mean, var = exact.count_moments(w.T, w.r, counted)
         out["dists"].append({"name": name, "mean": mean, "var": var})
     json.dump(out, open(os.path.join(HERE, "m1000_count_moments.json"), "w"), indent=1)
+    G = exact.pair_moments(w.T, w.r)
+    rng = np.random.default_rng(2503)
+    i = rng.integers(0, w.M, 4 * 2048)
+    j = rng.integers(0, w.M, 4 * 2048)
+    keep = np.unique(np.stack([np.minimum(i, j), np.maximum(i, j)], 1)[i != j], axis=0)[:2048]
+    pairs = np.concatenate([np.stack([np.arange(w.M)] * 2, 1), keep])
+    json.dump({"source": "<:n_i n_j:> = N_ii N_jj + |N_ij|^2 + |S_ij|^2, N = T diag(sinh^2 r) T^+, "
+                         "S = T diag(sinh r cosh r) T^T (Isserlis), M = 1000, t = 0.9, r = 1 Haar "
+                         "workload (synth.workload_m1000)",
+               "i": pairs[:, 0].tolist(), "j": pairs[:, 1].tolist(),
+               "value": [float(G[a, b]) for a, b in pairs]},
+              open(os.path.join(HERE, "m1000_pair_moments.json"), "w"))
 
 
 if __name__ == "__main__":

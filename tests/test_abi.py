@@ -132,3 +132,25 @@ def test_observable_calls_validate_on_the_host():
     assert lib.mp_subensemble_stats(1, 1, 4, 3, 1.0, vp(16), vp(16), vp(16), None) == -1
     assert lib.mp_subensemble_stats(0, 1, 4, 1, 1.0, vp(16), vp(16), vp(16), None) == -1
     assert lib.mp_subensemble_stats(1, 1, 4, 1, float("nan"), vp(16), vp(16), vp(16), None) == -1
+
+
+def test_pair_calls_validate_on_the_host():
+    lib = _lib()
+    vp = ctypes.c_void_p
+    assert lib.mp_mode_occupations_bytes(333, 1000, 1) == 2 * 1000 * 384 * 4
+    assert lib.mp_mode_occupations_bytes(333, 1000, 0) == 2 * 1000 * 384 * 8
+    assert lib.mp_mode_occupations_bytes(0, 1000, 1) == 0
+    assert lib.mp_mode_occupations_bytes(8, 10, 9) == 0
+    # occupations: null and misaligned buffers, unknown precision
+    assert lib.mp_mode_occupations(8, 10, vp(0), 1, vp(64), None) == -1
+    assert lib.mp_mode_occupations(8, 10, vp(64), 1, vp(48), None) == -1
+    assert b"aligned" in lib.mp_last_error()
+    assert lib.mp_mode_occupations(8, 10, vp(64), 7, vp(64), None) == -1
+    # pair sums: samples beyond the sub-ensembles, bad counts, null accumulator
+    acc = lambda *a: lib.mp_pair_correlations_accumulate(*a)
+    assert acc(8, 10, vp(64), 1, 2, 4, 0, vp(64), None) == -1
+    assert b"do not fit" in lib.mp_last_error()
+    assert acc(8, 10, vp(64), 1, 0, 10, 0, vp(64), None) == -1
+    assert acc(8, 10, vp(64), 1, 1, 10, 0, vp(0), None) == -1
+    assert acc(8, 10, vp(64), 1, 1, 10, -1, vp(64), None) == -1
+    assert acc(0, 10, vp(64), 1, 1, 10, 0, vp(64), None) == -1
