@@ -21,6 +21,7 @@
 
 #include <vector>
 
+#include "chi.h"
 #include "common.h"
 
 namespace mp {
@@ -29,12 +30,6 @@ constexpr int kSBlk = 64;       // samples per workgroup of the fused kernel
 constexpr int kCountThreads = 256;
 constexpr int kEpt = 4;         // accumulator entries per thread per pass
 constexpr int kMaxDist = MP_MAX_BINS + 1;
-// Terms of a sample's characteristic function with log-magnitude below kLogEps
-// (e^-46 ~ 1e-20) are not evaluated.  The magnitude test is exact, so each
-// sub-ensemble mean of chi changes by less than 1e-20 per grid point and P(m)
-// (an average of those means) by less than 1e-20 absolute.
-constexpr double kLogEps = -46.0;
-
 struct CountsParams {
   int M;
   int64_t ldm;
@@ -87,38 +82,6 @@ __device__ inline void block_samples(const CountsParams& p, int b, int64_t& s, i
   hi = lo + kSBlk < z ? lo + kSBlk : z;
 }
 
-// One sample's partial n'_j sums over a mode range, wave-reduced.
-template <typename CT>
-__device__ inline void run_sum(const CT* __restrict__ ca, const CT* __restrict__ cb, int64_t ldm,
-                               int lo, int hi, int lane, double& re, double& im) {
-  double sr = 0.0, si = 0.0;
-  int j = lo + lane;
-  for (; j + 192 < hi; j += 256) {
-    double a[4], b[4], c[4], e[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = (double)ca[j + 64 * u];
-      b[u] = (double)ca[ldm + j + 64 * u];
-      c[u] = (double)cb[j + 64 * u];
-      e[u] = (double)cb[ldm + j + 64 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      // alpha' = a + i b, beta' = c - i e  ->  n' = (a c + b e) + i (b c - a e)
-      sr += a[u] * c[u] + b[u] * e[u];
-      si += b[u] * c[u] - a[u] * e[u];
-    }
-  }
-  for (; j < hi; j += 64) {
-    const double a = (double)ca[j], b = (double)ca[ldm + j];
-    const double c = (double)cb[j], e = (double)cb[ldm + j];
-    sr += a * c + b * e;
-    si += b * c - a * e;
-  }
-  re = wave_sum(sr);
-  im = wave_sum(si);
-}
-
 // Occupations of one sample: nb[b] = sum of n'_j over the modes of bin b
 // (every lane holds the wave-reduced sums).
 template <typename CT>
@@ -160,29 +123,6 @@ __device__ inline void dist_occupation(const CountsParams& p, const double (&nb)
       vr = nb[b][0];
       vi = nb[b][1];
     }
-}
-
-__device__ inline double reduce_2pi(double ph) {
-  constexpr double kTwoPi = 6.283185307179586476925286766559;
-  constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
-  return ph - kTwoPi * rint(ph * kInvTwoPi);
-}
-
-template <bool F64>
-__device__ inline void cis_exp(double ex, double ph, double& re, double& im) {
-  if constexpr (F64) {
-    const double mag = exp(ex);
-    double s, c;
-    sincos(ph, &s, &c);
-    re = mag * c;
-    im = mag * s;
-  } else {
-    const float mag = expf((float)ex);
-    float s, c;
-    sincosf((float)reduce_2pi(ph), &s, &c);
-    re = (double)(mag * c);
-    im = (double)(mag * s);
-  }
 }
 
 // Sources of a sample's bin sums for counts_fused: the propagated amplitudes C
@@ -382,37 +322,6 @@ struct Joint2Params {
   int64_t s_first, s_last;
 };
 
-__device__ inline double fmax_exponent(double R, double I) {
-  // max over theta of -(1 - cos t) R + |sin t| |I|
-  if (R <= 0.0) return 2.0 * fabs(R) + fabs(I);
-  const double t = atan2(fabs(I), R);
-  return -(1.0 - cos(t)) * R + sin(t) * fabs(I);
-}
-
-// Smallest h such that f(theta_k) + offset < kLogEps for every grid point at
-// circular distance > h from theta = 0; -1 when no point reaches the threshold.
-__device__ inline int band_halfwidth(double R, double I, double offset, int K) {
-  const double fmax = fmax_exponent(R, I);
-  if (fmax + offset < kLogEps) return -1;
-  const int half = K / 2;
-  if (R <= 0.0) return half;
-  constexpr double kTwoPi = 6.283185307179586476925286766559;
-  auto f = [&](int k) {
-    const double t = kTwoPi * k / K;
-    return -(1.0 - cos(t)) * R + fabs(sin(t)) * fabs(I) + offset;
-  };
-  if (f(half) >= kLogEps) return half;
-  // f decreases on [theta*, pi]: search the last k >= k* with f(k) >= eps
-  int lo = (int)floor(atan2(fabs(I), R) / kTwoPi * K);  // f(lo) may be >= eps
-  int hi = half;                                      // f(hi) < eps
-  if (f(lo) < kLogEps) return lo > 0 ? lo : 0;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (f(mid) >= kLogEps) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 // Per-sample record: n1, n2 (complex), c1, c2; and the chunk bands
 // band[0..3] = u1, u2, v1, v2 half-widths (atomic max, -1 = empty).
 template <typename CT>
@@ -471,13 +380,6 @@ __global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const 
 
 __global__ void joint2_band_init(int* band) {
   if (threadIdx.x < 4) band[threadIdx.x] = -1;
-}
-
-// circular distance of k from the centre c on a grid of K points
-__device__ inline int circ_dist(int k, int c, int K) {
-  int d = k - c;
-  d = ((d % K) + K) % K;
-  return d <= K / 2 ? d : K - d;
 }
 
 template <bool F64>
