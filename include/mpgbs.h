@@ -55,7 +55,7 @@ typedef enum {
 } mp_precision;
 
 typedef enum {
-  MP_JOINT = 0,              /* joint distribution of the d bin counts (d <= 2) */
+  MP_JOINT = 0,              /* joint distribution of the d bin counts (d <= 4) */
   MP_MARGINALS = 1,          /* d one-bin distributions (S = S_b alone) */
   MP_MARGINALS_AND_TOTAL = 2 /* the d marginals plus the total over all bins */
 } mp_bin_mode;
@@ -176,12 +176,13 @@ size_t mp_binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_
  * into acc (two-pass, deterministic: no floating-point atomics).
  *
  *   C, n        as written by mp_propagate / mp_sample for this chunk
- *   d           bins, 1..MP_MAX_BINS (MP_JOINT: d <= 2)
+ *   d           bins, 1..MP_MAX_BINS (MP_JOINT: d <= 4)
  *   bin_of_mode host int32[M], values in [-1, d); -1 = not counted.  Each bin
  *               must be a union of contiguous mode runs, at most MP_MAX_RUNS
  *               runs in total.
  *   m_lo, K     host int32 per distribution (d of them, d+1 with the total
- *               last); m_lo >= 0, 1 <= K <= 65536
+ *               last); m_lo >= 0, 1 <= K <= 65536 (MP_JOINT with d >= 3:
+ *               K <= 1024 and prod K_b < 2^31)
  *   n_sub, samples_per_sub  sub-ensembles N_R and their size N_S; global
  *               sample g belongs to sub-ensemble g / N_S < n_sub
  *   e0          global index of the chunk's first sample
@@ -189,6 +190,18 @@ size_t mp_binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_
  *               out [sub-ensemble][distribution][k]; zeroed by the caller
  *               before the first chunk.
  *   workspace   device, >= mp_binned_workspace(...) bytes, 256-aligned.
+ *
+ * Joint distributions of d = 3 or 4 bins (main text, higher-dimensional
+ * binning): per sample chi is the sum of two rank-1 tensors over the bins,
+ * e^{c1} prod_b e^{X_b} + e^{c2} prod_b e^{-X_b}.  Each is evaluated only in
+ * the box of grid points around theta = 0 (first) or theta = pi (second)
+ * outside which every sample of the chunk stays below e^-46 (~1e-20; the
+ * bound is exact per sample), as a contraction over samples: products of the
+ * first d - 1 bins' per-sample factors against the last bin's, on the FP32
+ * matrix cores (FP32 and split paths: factors rounded to FP32, FP32 sums
+ * over a chunk's samples of one sub-ensemble, FP64 across chunks) or with
+ * FP64 FMAs (FP64 path).  acc is the full grid [s][k_1]..[k_d]; entries
+ * outside the boxes stay zero.
  */
 mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
                            mp_precision prec, mp_estimator est, int32_t d,
@@ -241,6 +254,8 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
  *           NULL when that size is 0).  The joint two-bin transform runs
  *           separably over the rows and columns of acc that hold nonzero
  *           values (the frequency bands the chunks touched); K[0] <= 4096.
+ *           Joint d = 3, 4: one axis at a time per sub-ensemble over the
+ *           nonzero entries of each line; layout [k_1]..[k_d].
  */
 size_t mp_finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
 

@@ -225,8 +225,8 @@ class CountsPipeline:
         # most one partial tile of 64 samples
         blocks = -(-self.chunk // 64) + self.chunk // self.ns + 2
         wbytes = blocks * self.entries * 16 + 256
-        if self.mode == 0 and self.d == 2:
-            wbytes = mp_binned_workspace(2, 0, self.K, self.chunk, self.n_sub, self.ns, 0)
+        if self.mode == 0 and self.d >= 2:
+            wbytes = mp_binned_workspace(self.d, 0, self.K, self.chunk, self.n_sub, self.ns, 0)
         if self.fused:
             # the GEMM's partials plus the counts blocks of the worst chunk alignment
             wbytes += mp_propagate_counts_workspace(self.M, self.chunk, self.d, self.bins, self.mode,

@@ -185,10 +185,11 @@ mp_status mp_propagate_packed(int32_t M, int64_t E, mp_precision prec, const voi
 
 int64_t mp_acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K) {
   if (!K || d < 1 || d > MP_MAX_BINS || mode < MP_JOINT || mode > MP_MARGINALS_AND_TOTAL) return -1;
-  if (mode == MP_JOINT && d > 2) return -1;
+  if (mode == MP_JOINT && d > 4) return -1;
   const int nd = n_dist_of(d, mode);
+  const int kmax = (mode == MP_JOINT && d >= 3) ? 1024 : 65536;
   for (int q = 0; q < nd; ++q)
-    if (K[q] < 1 || K[q] > 65536) return -1;
+    if (K[q] < 1 || K[q] > kmax) return -1;
   return acc_entries(d, mode, K);
 }
 
@@ -225,8 +226,8 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
                  "mp_binned_counts: K[%d] = %d outside [1, 65536]", q, K[q]);
     MP_CHECK_ARG(m_lo[q] >= 0, MP_ERR_ARG, "mp_binned_counts: m_lo[%d] = %d < 0", q, m_lo[q]);
   }
-  MP_CHECK_ARG(mode != MP_JOINT || d <= 2, MP_ERR_UNSUPPORTED,
-               "mp_binned_counts: joint distributions need d <= 2");
+  MP_CHECK_ARG(mode != MP_JOINT || d <= 4, MP_ERR_UNSUPPORTED,
+               "mp_binned_counts: joint distributions need d <= 4");
   MP_CHECK_ARG(aligned(workspace, 256), MP_ERR_WORKSPACE,
                "mp_binned_counts: workspace must be 256-byte aligned");
   return binned_counts_launch(M, E, C, n, prec, est, d, bin_of_mode, mode, m_lo, K, n_sub,

@@ -709,7 +709,18 @@ __global__ void fill_int(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+size_t jointd_workspace(int32_t d, const int32_t* K, int64_t E);
+size_t jointd_finalize_workspace(int32_t d, const int32_t* K);
+mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp_precision prec,
+                        mp_estimator est, int32_t d, const int32_t* bin_of_mode,
+                        const int32_t* m_lo, const int32_t* K, int32_t n_sub, int64_t ns,
+                        int64_t e0, double* acc, void* ws, size_t ws_bytes, hipStream_t stream);
+mp_status jointd_finalize(int32_t d, const int32_t* K, int32_t n_sub, int64_t ns,
+                          const double* acc, double* P_re, double* P_im, double* sigma, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
 size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub) {
+  if (mode == MP_JOINT && d >= 3) return jointd_finalize_workspace(d, K);
   if (!(mode == MP_JOINT && d == 2)) return 0;
   return 256 + ((size_t)K[0] + K[1]) * 4 + (size_t)n_sub * K[0] * K[1] * 16 + 256;
 }
@@ -769,6 +780,7 @@ size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E
                         int64_t ns, int64_t e0) {
   if (!K || d < 1 || d > MP_MAX_BINS || E < 1 || ns < 1 || e0 < 0) return 0;
   if (mode == MP_JOINT && d == 2) return 256 + (size_t)E * 48;
+  if (mode == MP_JOINT && d >= 3) return jointd_workspace(d, K, E);
   CountsParams p{};
   p.E = E;
   p.e0 = e0;
@@ -824,8 +836,11 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
   if (mode == MP_JOINT && d == 2)
     return joint2_launch(M, E, C, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
                          ws_bytes, stream);
+  if (mode == MP_JOINT && d >= 3)
+    return jointd_launch(M, E, C, n, prec, est, d, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
+                         ws_bytes, stream);
   MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
-               "mp_binned_counts: joint distributions need d <= 2 (d = %d)", d);
+               "mp_binned_counts: joint distributions need d <= 4 (d = %d)", d);
   CountsParams p{};
   int64_t blocks = 0;
   const mp_status st = setup_counts(p, "mp_binned_counts", M, E, d, bin_of_mode, mode, m_lo, K,
@@ -923,6 +938,8 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
                                  double* sigma, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (mode == MP_JOINT && d >= 3)
+    return jointd_finalize(d, K, n_sub, ns, acc, P_re, P_im, sigma, ws, ws_bytes, stream);
   if (mode == MP_JOINT && d == 2) {
     const size_t need = finalize_workspace(d, mode, K, n_sub);
     MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,

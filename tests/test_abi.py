@@ -44,7 +44,8 @@ def test_sizes():
     assert mp.mp_acc_entries(1, "joint", [128]) == 128
     assert mp.mp_acc_entries(2, "joint", [16, 8]) == 128
     assert mp.mp_acc_entries(3, "marginals_and_total", [4, 5, 6, 7]) == 22
-    assert mp.mp_acc_entries(3, "joint", [4, 4, 4]) == -1
+    assert mp.mp_acc_entries(3, "joint", [4, 4, 4]) == 64
+    assert mp.mp_acc_entries(5, "joint", [4] * 5) == -1
     assert mp.mp_acc_entries(1, "joint", [0]) == -1
     # E = 1000 samples from e0 = 500 with N_S = 300: sub-ensembles 1..5
     ws = mp.mp_binned_workspace(1, "joint", [64], 1000, 10, 300, 500)
@@ -132,6 +133,26 @@ def test_observable_calls_validate_on_the_host():
     assert lib.mp_subensemble_stats(1, 1, 4, 3, 1.0, vp(16), vp(16), vp(16), None) == -1
     assert lib.mp_subensemble_stats(0, 1, 4, 1, 1.0, vp(16), vp(16), vp(16), None) == -1
     assert lib.mp_subensemble_stats(1, 1, 4, 1, float("nan"), vp(16), vp(16), vp(16), None) == -1
+
+
+def test_joint_limits_on_the_host():
+    """Joint distributions of up to four bins; d >= 3 windows are limited to
+    K <= 1024 and to grids below 2^31 cells."""
+    lib = _lib()
+    i32 = lambda xs: (ctypes.c_int32 * len(xs))(*xs)
+    assert lib.mp_acc_entries(3, 0, i32([8, 9, 10])) == 720
+    assert lib.mp_acc_entries(4, 0, i32([4, 4, 4, 4])) == 256
+    assert lib.mp_acc_entries(5, 0, i32([4] * 5)) == -1
+    assert lib.mp_acc_entries(3, 0, i32([1025, 4, 4])) == -1
+    assert lib.mp_binned_workspace(3, 0, i32([8, 9, 10]), 100, 1, 100, 0) > 100 * 8 * 8
+    assert lib.mp_finalize_workspace(3, 0, i32([8, 9, 10]), 2) >= 2 * 720 * 16
+    vp = ctypes.c_void_p
+    st = lib.mp_binned_counts(4, 8, vp(256), vp(256), 0, 0, 5, i32([0, 1, 2, 3]), 0, i32([0] * 5),
+                              i32([4] * 5), 1, 8, 0, vp(256), vp(256), 1 << 20, None)
+    assert st == -4 and b"d <= 4" in lib.mp_last_error()
+    st = lib.mp_binned_counts(4, 8, vp(256), vp(256), 0, 0, 4, i32([0, 1, 2, 3]), 0, i32([0] * 4),
+                              i32([1024] * 4), 1, 8, 0, vp(256), vp(256), 1 << 40, None)
+    assert st == -4 and b"2^31" in lib.mp_last_error()
 
 
 def test_pair_calls_validate_on_the_host():

@@ -1,0 +1,145 @@
+"""Joint distributions of three and four bins (mp_binned_counts with
+MP_JOINT, d = 3, 4) against the FP64 oracle's direct count-space estimator
+on identical noise.
+
+Tolerances
+  FP64 path: the binned-probability bound used throughout (1e-10 relative,
+  with floors 1e-4 max P and 1e-14 max P absolute).  The windows hold every
+  sample's law to far below that (|n_b| of a few units, K = 32 or 20), so the
+  aliasing of the grid route does not enter.
+  FP32 / split paths: per-sample factors rounded to FP32 and FP32 sums over a
+  sub-ensemble's samples; the estimates must stay far inside sigma_T
+  (2 % of sigma_T plus 1e-6 of the peak).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator as oest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_12749_amd  # noqa: F401
+    yield
+
+
+def _case(d):
+    """Bins of 4 (d = 3) or 3 (d = 4) modes in runs, one uncounted mode,
+    lossy non-normal network, small squeezing."""
+    if d == 3:
+        M = 12
+        bins = np.array([0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, -1])
+        r = np.linspace(0.3, 0.6, M)
+        K = 32
+    else:
+        M = 13
+        bins = np.array([0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, -1, 3])
+        r = np.linspace(0.2, 0.4, M)
+        K = 20
+    T = synth.haar_unitary(M, 40 + d) * np.linspace(0.75, 0.95, M)[None, :]
+    return M, T, r, bins, K
+
+
+def _run(d, prec, est="matrix_p", E=600, n_sub=3, chunk=256, seed=23, T=None, r=None, bins=None,
+         K=None, windows=None):
+    import paper_2503_12749_amd as mp
+    M0, T0, r0, b0, K0 = _case(d)
+    T = T0 if T is None else T
+    r = r0 if r is None else r
+    bins = b0 if bins is None else bins
+    K = K0 if K is None else K
+    windows = [(0, K)] * d if windows is None else windows
+    p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=d, mode="joint",
+                          windows=windows, n_sub=n_sub, samples_per_sub=E // n_sub, chunk=chunk,
+                          est=est, device=DEV)
+    p.run()
+    P, Pi, s = p.result()
+    shape = tuple(w[1] for w in windows)
+    return P.reshape(shape), s.reshape(shape), (T, r, bins, windows)
+
+
+def _bound(ref, rel=1e-10):
+    scale = np.abs(ref).max()
+    return rel * np.maximum(np.abs(ref), 1e-4 * scale) + 1e-14 * scale
+
+
+@pytest.mark.parametrize("d", [3, 4])
+@pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
+def test_joint_fp64_matches_oracle(d, est):
+    E, n_sub = (600, 3) if d == 3 else (300, 3)
+    P, s, (T, r, bins, wins) = _run(d, "fp64", est=est, E=E, n_sub=n_sub,
+                                    chunk=256 if d == 3 else 128)
+    ref = oest.estimate(T, r, 23, E, n_sub, bins, d, wins, mode="joint",
+                        chunk=100 if d == 3 else 30, plus_p=(est == "plus_p"))
+    bad = np.abs(P - ref["P"]) > _bound(ref["P"])
+    assert not bad.any(), (np.abs(P - ref["P"]).max(), np.abs(ref["P"]).max())
+    np.testing.assert_allclose(s, ref["sigma"], rtol=1e-6, atol=1e-12 * np.abs(ref["P"]).max())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_joint3_reduced_precision_within_sigma(prec):
+    P64, s64, (T, r, bins, wins) = _run(3, "fp64", E=1200, n_sub=6, chunk=512)
+    P, s, _ = _run(3, prec, E=1200, n_sub=6, chunk=512)
+    err = np.abs(P - P64)
+    tol = 0.02 * s64 + 1e-6 * np.abs(P64).max()
+    bulk = np.abs(P64) > 1e-3 * np.abs(P64).max()
+    print(f"{prec}: max |dP| = {err.max():.3e} (peak P {np.abs(P64).max():.3e}), bulk max "
+          f"|dP| / sigma_T = {(err[bulk] / s64[bulk]).max():.3e}")
+    assert np.all(err <= tol)
+
+
+def test_joint3_lossless_parity_and_two_bin_marginal():
+    """Lossless network, all modes counted: P vanishes when m_1 + m_2 + m_3 is
+    odd; the sum over m_3 equals the two-bin joint of the same noise with the
+    third bin's modes uncounted (the d = 2 path)."""
+    import paper_2503_12749_amd as mp
+    M = 9
+    T = synth.haar_unitary(M, 77)
+    r = np.full(M, 0.4)
+    bins = np.repeat([0, 1, 2], 3)
+    K = 32
+    P, s, _ = _run(3, "fp64", E=900, n_sub=3, chunk=300, T=T, r=r, bins=bins, K=K)
+    m = np.arange(K)
+    odd = (m[:, None, None] + m[None, :, None] + m[None, None, :]) % 2 == 1
+    assert np.abs(P[odd]).max() <= 1e-14 * np.abs(P).max()
+    p2 = mp.CountsPipeline(T, r, prec="fp64", seed=23, bin_of_mode=np.where(bins == 2, -1, bins),
+                           d=2, mode="joint", windows=[(0, K), (0, K)], n_sub=3,
+                           samples_per_sub=300, chunk=300, device=DEV)
+    p2.run()
+    P2 = p2.result()[0].reshape(K, K)
+    assert np.all(np.abs(P.sum(axis=2) - P2) <= _bound(P2))
+
+
+def _fold(ref, wins):
+    """The grid route's view of a law computed on [0, m_lo + K) per axis: the
+    counts below m_lo alias to m + K (the window holds every count above)."""
+    out = ref
+    for ax, (lo, K) in enumerate(wins):
+        top = np.take(out, np.arange(lo, lo + K), axis=ax)
+        low = np.take(out, np.arange(0, lo), axis=ax)
+        idx = [slice(None)] * out.ndim
+        idx[ax] = slice(K - lo, K)
+        top[tuple(idx)] += low
+        out = top
+    return out
+
+
+def test_joint3_offset_windows_and_ragged_chunks():
+    """Windows that start above zero (the window shift z^-m_lo, with the
+    counts below m_lo aliased mod K), unequal K, chunks of 100 samples over
+    sub-ensembles of 150."""
+    M, T, r, bins, _ = _case(3)
+    wins = [(3, 32), (2, 30), (1, 33)]
+    P, s, _ = _run(3, "fp64", E=450, n_sub=3, chunk=100, windows=wins)
+    wide = [(0, lo + K) for lo, K in wins]
+    ref = oest.estimate(T, r, 23, 450, 3, bins, 3, wide, mode="joint", chunk=50)
+    Pr = _fold(ref["P"], wins)
+    assert not (np.abs(P - Pr) > _bound(Pr)).any(), np.abs(P - Pr).max()
