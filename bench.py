@@ -670,6 +670,88 @@ def run_pairs_m1000(args, mp, torch, synth):
                            "frac_within_3_sigma": float((np.abs(z) < 3).mean())})
 
 
+def run_joint3_m300(args, mp, torch, synth):
+    """Joint distribution of three bins (main text, higher-dimensional
+    binning): lossless Haar network, M = 300, r = 0.5 on every mode, bins of
+    100 contiguous modes, window [0, 128) per bin (2.1e6 cells), E = 1.2e6 in
+    chunks of 1e5 (120 sub-ensembles of 1e4), FP32.  Each chunk: sample,
+    propagate, then mp_binned_counts (occupations, factor tables, the two
+    box contractions), timed with HIP events; the finalize (inverse DFT of
+    120 sub-ensemble grids) timed apart; the whole job timed after one
+    untimed run.  Checks: P vanishes for odd m_1 + m_2 + m_3 (lossless), and
+    the distribution of the total m_1 + m_2 + m_3 < 128 against the exact
+    lossless law (sd bound: the sum of the cells' sigma_T)."""
+    M, K = 300, 128
+    seed = synth.SEED_BASE + 40
+    T = synth.haar_unitary(M, seed)
+    r = np.full(M, 0.5)
+    bins = synth.contiguous_bins(M, 3)
+    E, ns, chunk = 1_200_000, 10_000, 100_000
+    p = mp.CountsPipeline(T, r, prec="fp32", seed=seed, bin_of_mode=bins, d=3, mode="joint",
+                          windows=[(0, K)] * 3, n_sub=E // ns, samples_per_sub=ns, chunk=chunk)
+    stream = torch.cuda.current_stream()
+    n_chunks = E // chunk
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n_chunks)]
+    fin = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def job():
+        p.reset()
+        p.packed = False
+        for c in range(n_chunks):
+            g = c * chunk
+            if not p.packed:
+                mp.mp_pack_transmission(p.M, p.T, p.prec, p.ws_prop)
+                p.packed = True
+            mp.mp_sample(p.M, g, chunk, p.r, p.seed, p.net, p.prec, p.ab, p.n)
+            mp.mp_propagate_packed(p.M, chunk, p.prec, p.ab, p.C, p.ws_prop)
+            ev[c][0].record(stream)
+            p.counts_chunk(g, chunk)
+            ev[c][1].record(stream)
+        fin[0].record(stream)
+        p.finalize()
+        fin[1].record(stream)
+    job()
+    secs = _timed(torch, job)
+    counts_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    fin_ms = fin[0].elapsed_time(fin[1])
+    P = p.result()[0].reshape(K, K, K)
+    sig = p.result()[2].reshape(K, K, K)
+    # box half-widths of the last chunk: the first 8 ints of the counting
+    # workspace (term 0 around theta = 0, term 1 around theta = pi)
+    band = p.ws_counts[:32].view(torch.int32).cpu().numpy()
+    widths = [[int(min(2 * h + 1, K)) if h >= 0 else 0 for h in band[4 * t: 4 * t + 3]]
+              for t in range(2)]
+    box_cells = sum(int(np.prod(w)) for w in widths)
+    flops = 8.0 * box_cells * chunk
+    achieved = flops / (counts_ms * 1e-3) / 1e12
+    m = np.arange(K)
+    tot_idx = m[:, None, None] + m[None, :, None] + m[None, None, :]
+    odd = tot_idx % 2 == 1
+    Ptot = np.bincount(tot_idx.ravel(), weights=P.ravel(), minlength=3 * K)[:K]
+    Stot = np.bincount(tot_idx.ravel(), weights=sig.ravel(), minlength=3 * K)[:K]
+    gold = np.array(_golden("lossless_m300_r0.5.json")["P"])
+    bulk = gold > 1e-4 * gold.max()
+    zt = np.abs(Ptot - gold)[bulk] / Stot[bulk]
+    log(f"[bench] joint3 m300: job {secs:.3f} s, counts {counts_ms:.2f} ms per chunk "
+        f"({achieved:.1f} TFLOP/s over the boxes {widths}), finalize {fin_ms:.1f} ms, "
+        f"max odd |P| / max P {np.abs(P[odd]).max() / P.max():.2e}, total-law max z {zt.max():.2f}")
+    return _envelope(
+        "joint distribution of three bins, M=300 lossless, r=0.5: ensemble samples per second",
+        E / secs, "samples/s", 1e3 * secs,
+        f"M300_lossless_r0.5: 3 bins of 100 modes, windows [0,{K}) each ({K ** 3} cells), "
+        f"E={E} in chunks of {chunk}, {E // ns} sub-ensembles", "fp32 (fp64 sums across chunks)",
+        job_s=secs, counts_ms_per_chunk=counts_ms, finalize_ms=fin_ms, box_widths=widths,
+        roofline={"bound": "mfma", "kernel": "jointd_sum_f32 (both terms; the timed call also "
+                  "holds the occupation and factor-table kernels)", "achieved": round(achieved, 2),
+                  "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s",
+                  "frac": round(achieved / PEAKS_TFLOPS["fp32"], 4),
+                  "algorithmic_flops_per_launch": flops, "traffic": None},
+        checks={"max_abs_P_odd_over_max_P": float(np.abs(P[odd]).max() / P.max()),
+                "total_law_max_abs_err_over_sigma_bound": float(zt.max()),
+                "total_law_max_abs_err": float(np.abs(Ptot - gold)[bulk].max()),
+                "sum_P_window": float(P.sum())})
+
+
 def run_scaling_appb(args, mp, torch, synth):
     """Appendix B scaling workloads.  Run time: lossless Haar networks,
     r = 0.89, M = 128 .. 8192, E = 1.2e6 (120 sub-ensembles of 1e4, chunks of
@@ -765,7 +847,8 @@ def main():
                     help="m8000: write C and count from it instead of the occupation-fused GEMM")
     ap.add_argument("--workload", default="m8000",
                     choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate",
-                             "plusp_m20", "moments_m1000", "pairs_m1000", "scaling_appb", "copy"],
+                             "plusp_m20", "moments_m1000", "pairs_m1000", "joint3_m300",
+                             "scaling_appb", "copy"],
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
@@ -784,6 +867,7 @@ def main():
                "precision_m4000": run_precision_m4000, "batched": run_batched,
                "surrogate": run_surrogate, "plusp_m20": run_plusp_m20,
                "moments_m1000": run_moments_m1000, "pairs_m1000": run_pairs_m1000,
+               "joint3_m300": run_joint3_m300,
                "scaling_appb": run_scaling_appb,
                "copy": run_copy}
     out = runners[args.workload](args, mp, torch, synth)

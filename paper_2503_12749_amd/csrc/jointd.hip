@@ -82,39 +82,54 @@ __global__ __launch_bounds__(256) void jointd_occupations(JointDParams p, const 
         ni[b] += im;
       }
   }
-  if (lane != 0) return;
+  // every lane holds the wave-reduced sums; lane 0 writes the record and
+  // lanes 0 .. 2 d - 1 each bound one (term, axis) box
   const double n = nglob[k];
   const bool with_v = p.est != MP_PLUS_P;
   const double L = log1p(exp(-2.0 * fabs(n)));
   const double c1 = with_v ? (n >= 0.0 ? 0.0 : 2.0 * n) - L : 0.0;
   const double c2 = (n >= 0.0 ? -2.0 * n : 0.0) - L;
-  double* r = rec + k * p.rec;
   double fm[kJD], fsum = 0.0, rsum = 0.0;
 #pragma unroll
   for (int b = 0; b < kJD; ++b) {
     fm[b] = 0.0;
     if (b < p.d) {
-      r[2 * b] = nr[b];
-      r[2 * b + 1] = ni[b];
       fm[b] = fmax_exponent(nr[b], ni[b]);
       fsum += fm[b];
       rsum += nr[b];
     }
   }
-  r[2 * p.d] = c1;
-  r[2 * p.d + 1] = with_v ? c2 : -INFINITY;
+  if (lane == 0) {
+    double* r = rec + k * p.rec;
+#pragma unroll
+    for (int b = 0; b < kJD; ++b)
+      if (b < p.d) {
+        r[2 * b] = nr[b];
+        r[2 * b + 1] = ni[b];
+      }
+    r[2 * p.d] = c1;
+    r[2 * p.d + 1] = with_v ? c2 : -INFINITY;
+  }
+  if (lane >= 2 * p.d) return;
+  const int tau = lane / p.d, ax = lane % p.d;
+  if (tau == 1 && !with_v) return;
+  double R = 0.0, I = 0.0, f = 0.0;
 #pragma unroll
   for (int b = 0; b < kJD; ++b)
-    if (b < p.d) {
-      atomicMax(&band[b], band_halfwidth(nr[b], ni[b], c1 + fsum - fm[b], p.K[b]));
-      if (with_v) {
-        // about theta = pi the exponent is 2 Re n_b + f_b(phi) with Im n_b
-        // negated; +1 because for odd K the grid is not symmetric about pi
-        int h = band_halfwidth(nr[b], ni[b], c2 + 2.0 * rsum + fsum - fm[b], p.K[b]);
-        h = h < 0 ? h : min(h + 1, p.K[b] / 2);
-        atomicMax(&band[kJD + b], h);
-      }
+    if (b == ax) {
+      R = nr[b];
+      I = ni[b];
+      f = fm[b];
     }
+  if (tau == 0) {
+    atomicMax(&band[ax], band_halfwidth(R, I, c1 + fsum - f, p.K[ax]));
+  } else {
+    // about theta = pi the exponent is 2 Re n_b + f_b(phi) with Im n_b
+    // negated; +1 because for odd K the grid is not symmetric about pi
+    int h = band_halfwidth(R, I, c2 + 2.0 * rsum + fsum - f, p.K[ax]);
+    h = h < 0 ? h : min(h + 1, p.K[ax] / 2);
+    atomicMax(&band[kJD + ax], h);
+  }
 }
 
 // Box of a term: half-widths h_b and widths w_b = min(2 h_b + 1, K_b); false

@@ -7,6 +7,9 @@ Calls only oracle/ (and synth/ for the seeded networks):
   m1000_count_moments.json closed-form mean and variance (E4: W = T^T P_S T*)
                            of the two half-bins and the total of the M = 1000,
                            t = 0.9, r = 1 Haar workload
+  lossless_m300_r0.5.json  exact total-count law of a lossless 300-mode network
+                           with r = 0.5 on every mode, m = 0..127 (the total
+                           of the three-bin joint workload)
   m1000_pair_moments.json  Isserlis closed form of <:n_i n_j:> for the same
                            workload at every diagonal element and 2048
                            seeded off-diagonal pairs (i < j)
@@ -32,6 +35,11 @@ def main():
     json.dump({"source": "eq. Exact_multi_mode_squeezed_state (lossless, identical r), M = 20, r = 0.5",
                "M": 20, "r": 0.5, "m": m.tolist(), "P": P.tolist()},
               open(os.path.join(HERE, "lossless_m20_r0.5.json"), "w"), indent=1)
+    m = np.arange(128)
+    P = exact.lossless_uniform_total(300, 0.5, m)
+    json.dump({"source": "eq. Exact_multi_mode_squeezed_state (lossless, identical r), M = 300, r = 0.5",
+               "M": 300, "r": 0.5, "m": m.tolist(), "P": P.tolist()},
+              open(os.path.join(HERE, "lossless_m300_r0.5.json"), "w"), indent=1)
     w = synth.workload_m1000()
     bins = synth.contiguous_bins(w.M, 2)
     out = {"source": "closed-form count moments (mean sum_j W_jj N_j, variance with the N N |W|^2 "
