@@ -44,7 +44,8 @@ typedef enum {
   MP_ERR_SHAPE = -2,       /* sizes inconsistent with each other */
   MP_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
   MP_ERR_UNSUPPORTED = -4, /* valid request outside what this build handles */
-  MP_ERR_WORKSPACE = -5    /* workspace missing or smaller than required */
+  MP_ERR_WORKSPACE = -5,   /* workspace missing or smaller than required */
+  MP_ERR_NONFINITE = -6    /* a result holds NaN or infinite values (mp_check_finite) */
 } mp_status;
 
 typedef enum {
@@ -181,8 +182,8 @@ size_t mp_binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_
  *               must be a union of contiguous mode runs, at most MP_MAX_RUNS
  *               runs in total.
  *   m_lo, K     host int32 per distribution (d of them, d+1 with the total
- *               last); m_lo >= 0, 1 <= K <= 65536 (MP_JOINT with d >= 3:
- *               K <= 1024 and prod K_b < 2^31)
+ *               last); m_lo >= 0, 1 <= K <= 65536 (MP_JOINT: K <= 4096 for
+ *               d = 2; K <= 1024 and prod K_b < 2^31 for d >= 3)
  *   n_sub, samples_per_sub  sub-ensembles N_R and their size N_S; global
  *               sample g belongs to sub-ensemble g / N_S < n_sub
  *   e0          global index of the chunk's first sample
@@ -251,11 +252,10 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
  *   P_re, P_im, sigma  device FP64[mp_acc_entries]; P_im may be NULL.
  *           Joint layout [k1][k2]; marginal layout concatenated per distribution.
  *   workspace  device, >= mp_finalize_workspace(...) bytes, 256-aligned (may be
- *           NULL when that size is 0).  The joint two-bin transform runs
- *           separably over the rows and columns of acc that hold nonzero
- *           values (the frequency bands the chunks touched); K[0] <= 4096.
- *           Joint d = 3, 4: one axis at a time per sub-ensemble over the
- *           nonzero entries of each line; layout [k_1]..[k_d].
+ *           NULL when that size is 0).  Joint grids (d = 2, 3, 4) are
+ *           transformed one axis at a time per sub-ensemble over the nonzero
+ *           entries of each line (acc is zero outside the frequency bands the
+ *           chunks touched); layout [k_1]..[k_d]; K <= 4096 for d = 2.
  */
 size_t mp_finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
 
@@ -370,6 +370,18 @@ mp_status mp_mode_occupations(int32_t M, int64_t E, const void* C, mp_precision 
 mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, mp_precision prec,
                                           int32_t n_sub, int64_t samples_per_sub, int64_t e0,
                                           double* acc, void* stream);
+
+/*
+ * Synchronous finiteness check of a device FP64 array, for estimates and
+ * accumulators that must always be finite (every path evaluates its
+ * exponentials in shifted, overflow-free forms; an overflow in a reduced-
+ * precision path would show here).  Counts the NaN and infinite entries of
+ * x[0, n) on `stream` into `scratch` (device, 8 bytes, caller-owned,
+ * overwritten), waits for the stream, stores the count in *n_bad when n_bad
+ * is not NULL, and returns MP_ERR_NONFINITE if it is nonzero.
+ */
+mp_status mp_check_finite(const double* x, int64_t n, int64_t* scratch, int64_t* n_bad,
+                          void* stream);
 
 /* ---------------------------------------------------------------- batching */
 

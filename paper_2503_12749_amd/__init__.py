@@ -22,7 +22,7 @@ __all__ = [
     "mp_binned_workspace", "mp_binned_counts", "mp_counts_finalize", "mp_finalize_workspace",
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
     "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_version", "CountsPipeline",
-    "PairPipeline", "Plan", "MPError",
+    "PairPipeline", "Plan", "MPError", "mp_check_finite",
 ]
 
 
@@ -138,6 +138,16 @@ def mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean
     _lib.check(_lib.load().mp_subensemble_stats(n_sub, samples_per_sub, n_vals, ncomp,
                                                 float(scale), _ptr(acc), _ptr(mean), _ptr(sigma),
                                                 _stream(stream)))
+
+
+def mp_check_finite(x, scratch, stream=None) -> int:
+    """Synchronous: raises MPError (MP_ERR_NONFINITE) if the device float64
+    tensor x holds NaN or infinite values; scratch is a device tensor of at
+    least 8 bytes.  Returns the count of such values (0)."""
+    bad = ctypes.c_int64(0)
+    _lib.check(_lib.load().mp_check_finite(_ptr(x), x.numel(), _ptr(scratch), ctypes.byref(bad),
+                                           _stream(stream)))
+    return bad.value
 
 
 def mp_mode_occupations_bytes(M: int, E: int, prec) -> int:
@@ -274,7 +284,11 @@ class CountsPipeline:
         self.finalize(stream)
 
     def result(self):
-        """(P_re, P_im, sigma) as numpy arrays (synchronises)."""
+        """(P_re, P_im, sigma) as numpy arrays (synchronises); raises MPError
+        (MP_ERR_NONFINITE) if the estimate holds NaN or infinite values."""
+        scratch = self.torch.empty(1, dtype=self.torch.int64, device=self.P_re.device)
+        mp_check_finite(self.P_re, scratch)
+        mp_check_finite(self.P_im, scratch)
         return (self.P_re.cpu().numpy(), self.P_im.cpu().numpy(), self.sigma.cpu().numpy())
 
     def alpha_beta(self, E: int):

@@ -71,6 +71,8 @@ mp_status subensemble_stats_launch(int32_t n_sub, int64_t ns, int64_t n_vals, in
                                    hipStream_t stream);
 
 int64_t mlp_param_count(const mp_mlp_shape* s);
+mp_status check_finite_launch(const double* x, int64_t n, int64_t* scratch, int64_t* n_bad,
+                              hipStream_t stream);
 size_t mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec);
 mp_status mode_occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, void* X,
                                   hipStream_t stream);
@@ -187,7 +189,7 @@ int64_t mp_acc_entries(int32_t d, mp_bin_mode mode, const int32_t* K) {
   if (!K || d < 1 || d > MP_MAX_BINS || mode < MP_JOINT || mode > MP_MARGINALS_AND_TOTAL) return -1;
   if (mode == MP_JOINT && d > 4) return -1;
   const int nd = n_dist_of(d, mode);
-  const int kmax = (mode == MP_JOINT && d >= 3) ? 1024 : 65536;
+  const int kmax = mode != MP_JOINT || d == 1 ? 65536 : (d == 2 ? 4096 : 1024);
   for (int q = 0; q < nd; ++q)
     if (K[q] < 1 || K[q] > kmax) return -1;
   return acc_entries(d, mode, K);
@@ -402,6 +404,16 @@ mp_status mp_subensemble_stats(int32_t n_sub, int64_t samples_per_sub, int64_t n
                "mp_subensemble_stats: null pointer or non-finite scale");
   return subensemble_stats_launch(n_sub, samples_per_sub, n_vals, ncomp, scale, acc, mean, sigma,
                                   (hipStream_t)stream);
+}
+
+mp_status mp_check_finite(const double* x, int64_t n, int64_t* scratch, int64_t* n_bad,
+                          void* stream) {
+  clear_error();
+  MP_CHECK_ARG(x && scratch && n >= 1, MP_ERR_ARG,
+               "mp_check_finite: x and scratch must be non-null and n >= 1");
+  MP_CHECK_ARG(aligned(x, 8) && aligned(scratch, 8), MP_ERR_ARG,
+               "mp_check_finite: x and scratch must be 8-byte aligned");
+  return check_finite_launch(x, n, scratch, n_bad, (hipStream_t)stream);
 }
 
 size_t mp_mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec) {

@@ -15,6 +15,10 @@ namespace mp {
 // (an average of those means) by less than 1e-20 absolute.
 constexpr double kLogEps = -46.0;
 
+// Samples per wave of the per-sample occupation kernels (one wave per sample
+// at a time, lanes over modes).
+constexpr int kOccPerWave = 16;
+
 // One sample's partial n'_j sums over a mode range, wave-reduced.
 template <typename CT>
 __device__ inline void run_sum(const CT* __restrict__ ca, const CT* __restrict__ cb, int64_t ldm,
@@ -78,7 +82,8 @@ __device__ inline double fmax_exponent(double R, double I) {
 }
 
 // Smallest h such that f(theta_k) + offset < kLogEps for every grid point at
-// circular distance > h from theta = 0; -1 when no point reaches the threshold.
+// circular distance > h from theta = 0 (the last grid point at or below pi
+// where it reaches the threshold); -1 when no point reaches it.
 __device__ inline int band_halfwidth(double R, double I, double offset, int K) {
   const double fmax = fmax_exponent(R, I);
   if (fmax + offset < kLogEps) return -1;
@@ -89,16 +94,43 @@ __device__ inline int band_halfwidth(double R, double I, double offset, int K) {
     const double t = kTwoPi * k / K;
     return -(1.0 - cos(t)) * R + fabs(sin(t)) * fabs(I) + offset;
   };
-  if (f(half) >= kLogEps) return half;
-  // f decreases on [theta*, pi]: search the last k >= k* with f(k) >= eps
-  int lo = (int)floor(atan2(fabs(I), R) / kTwoPi * K);  // f(lo) may be >= eps
-  int hi = half;                                      // f(hi) < eps
-  if (f(lo) < kLogEps) return lo > 0 ? lo : 0;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (f(mid) >= kLogEps) lo = mid; else hi = mid;
+  // On [0, pi], f(theta) = rho cos(theta - phi) - R + offset with
+  // rho = |n|, phi = atan2(|Im n|, Re n): it rises to its maximum at phi and
+  // falls after, so the grid points with f >= eps form one run.  Its last
+  // point from the closed form phi + acos((R + eps - offset) / rho), then
+  // corrected on the grid (the closed form lands at or after the point
+  // below phi, and rounding moves it by a point or two); -1 when no grid
+  // point reaches eps.
+  const double rho = hypot(R, I), phi = atan2(fabs(I), R);
+  const double c = (R + kLogEps - offset) / rho;
+  int k = c <= -1.0 ? half : (int)floor((phi + acos(fmin(c, 1.0))) / kTwoPi * K);
+  k = k < 0 ? 0 : (k > half ? half : k);
+  while (k < half && f(k + 1) >= kLogEps) ++k;
+  while (k >= 0 && f(k) < kLogEps) --k;
+  return k;
+}
+
+// Box half-width on axis b of term tau (0: about theta = 0, 1: about pi) for
+// one sample record r = (Re n_0, Im n_0, .., Re n_{d-1}, Im n_{d-1}, c1, c2):
+// band_halfwidth of the axis with every other axis at its maximum.  About
+// theta = pi the exponent is 2 Re n_b + f_b(phi) with Im n_b negated (the same
+// bound) and the offset holds c2 + 2 sum_b Re n_b; +1 there because for odd K
+// the grid is not symmetric about pi.  c2 = -inf (the +P estimator) removes
+// the second term.
+__device__ inline int record_band(const double* __restrict__ r, int d, int tau, int b, int K) {
+  double fsum = 0.0, rsum = 0.0, fb = 0.0;
+  for (int q = 0; q < d; ++q) {
+    const double f = fmax_exponent(r[2 * q], r[2 * q + 1]);
+    fsum += f;
+    rsum += r[2 * q];
+    if (q == b) fb = f;
   }
-  return lo;
+  const double R = r[2 * b], I = r[2 * b + 1];
+  if (tau == 0) return band_halfwidth(R, I, r[2 * d] + fsum - fb, K);
+  const double c2 = r[2 * d + 1];
+  if (c2 == -INFINITY) return -1;
+  const int h = band_halfwidth(R, I, c2 + 2.0 * rsum + fsum - fb, K);
+  return h < 0 ? h : min(h + 1, K / 2);
 }
 
 // circular distance of k from the centre c on a grid of K points

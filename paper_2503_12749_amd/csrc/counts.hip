@@ -322,16 +322,13 @@ struct Joint2Params {
   int64_t s_first, s_last;
 };
 
-// Per-sample record: n1, n2 (complex), c1, c2; and the chunk bands
+// Per-sample record (one wave per sample, lane 0 writes): n1, n2 (complex),
+// c1, c2 (c2 = -inf for +P).  record_bands then sets the chunk's bands
 // band[0..3] = u1, u2, v1, v2 half-widths (atomic max, -1 = empty).
 template <typename CT>
-__global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const CT* __restrict__ C,
-                                                          const double* __restrict__ nglob,
-                                                          double* __restrict__ rec,
-                                                          int* __restrict__ band) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
-  if (k >= p.E) return;
+__device__ inline void joint2_sample(const Joint2Params& p, const CT* __restrict__ C,
+                                     const double* __restrict__ nglob, double* __restrict__ rec,
+                                     int64_t k, int lane) {
   const int64_t ldc = 2 * p.ldm;
   const CT* ca = C + k * ldc;
   const CT* cb = C + (p.E + k) * ldc;
@@ -347,9 +344,8 @@ __global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const 
   }
   if (lane != 0) return;
   const double n = nglob[k];
-  double c1 = 0.0, c2 = 0.0;
-  bool with_v = p.est != MP_PLUS_P;
-  if (with_v) {
+  double c1 = 0.0, c2 = -INFINITY;
+  if (p.est != MP_PLUS_P) {
     const double L = log1p(exp(-2.0 * fabs(n)));
     c1 = (n >= 0.0 ? 0.0 : 2.0 * n) - L;
     c2 = (n >= 0.0 ? -2.0 * n : 0.0) - L;
@@ -360,26 +356,48 @@ __global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const 
   r[2] = R2;
   r[3] = I2;
   r[4] = c1;
-  r[5] = with_v ? c2 : -INFINITY;
-  const int hu1 = band_halfwidth(R1, I1, c1 + fmax_exponent(R2, I2), p.K[0]);
-  const int hu2 = band_halfwidth(R2, I2, c1 + fmax_exponent(R1, I1), p.K[1]);
-  atomicMax(&band[0], hu1);
-  atomicMax(&band[1], hu2);
-  if (with_v) {
-    // about theta = pi: exponent 2 R_b + f_b(phi) with Im n_b -> -Im n_b
-    const double off = c2 + 2.0 * R1 + 2.0 * R2;
-    // +1: for odd K the grid is not symmetric about theta = pi
-    int hv1 = band_halfwidth(R1, I1, off + fmax_exponent(R2, I2), p.K[0]);
-    int hv2 = band_halfwidth(R2, I2, off + fmax_exponent(R1, I1), p.K[1]);
-    hv1 = hv1 < 0 ? hv1 : min(hv1 + 1, p.K[0] / 2);
-    hv2 = hv2 < 0 ? hv2 : min(hv2 + 1, p.K[1] / 2);
-    atomicMax(&band[2], hv1);
-    atomicMax(&band[3], hv2);
+  r[5] = c2;
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const CT* __restrict__ C,
+                                                          const double* __restrict__ nglob,
+                                                          double* __restrict__ rec) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * (4 * kOccPerWave) + wave;
+  for (int j = 0; j < kOccPerWave; ++j) {
+    const int64_t k = base + 4 * j;
+    if (k >= p.E) return;
+    joint2_sample<CT>(p, C, nglob, rec, k, lane);
   }
 }
 
 __global__ void joint2_band_init(int* band) {
   if (threadIdx.x < 4) band[threadIdx.x] = -1;
+}
+
+// Box half-widths from the per-sample records (layout of record_band): block
+// row blockIdx.y = tau d + b, one sample per thread, a wave maximum, then one
+// atomic maximum per wave into band[tau * band_stride + b].
+__global__ __launch_bounds__(256) void record_bands(const double* __restrict__ rec, int64_t E,
+                                                    int d, int K0, int K1, int K2, int K3,
+                                                    int band_stride, int* __restrict__ band) {
+  const int tau = blockIdx.y / d, b = blockIdx.y % d;
+  const int K = b == 0 ? K0 : (b == 1 ? K1 : (b == 2 ? K2 : K3));
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int h = k < E ? record_band(rec + k * (2 * d + 2), d, tau, b, K) : -1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) h = max(h, __shfl_xor(h, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(&band[tau * band_stride + b], h);
+}
+
+mp_status record_bands_launch(const double* rec, int64_t E, int d, const int32_t* K,
+                              int band_stride, int* band, hipStream_t stream) {
+  hipLaunchKernelGGL(record_bands, dim3((unsigned)((E + 255) / 256), (unsigned)(2 * d)), dim3(256),
+                     0, stream, rec, E, d, K[0], d > 1 ? K[1] : 1, d > 2 ? K[2] : 1,
+                     d > 3 ? K[3] : 1, band_stride, band);
+  MP_HIP_LAUNCH_CHECK("mp_binned_counts box bounds launch");
+  return MP_OK;
 }
 
 template <bool F64>
@@ -513,14 +531,16 @@ mp_status joint2_launch(int32_t M, int64_t E, const void* C, const double* n, mp
   int* band = (int*)ws;
   double* rec = (double*)((char*)ws + 256);
   hipLaunchKernelGGL(joint2_band_init, dim3(1), dim3(64), 0, stream, band);
-  const unsigned blocks = (unsigned)((E + 3) / 4);
+  const unsigned blocks = (unsigned)((E + 4 * kOccPerWave - 1) / (4 * kOccPerWave));
   if (prec == MP_FP64)
     hipLaunchKernelGGL(joint2_occupations<double>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const double*)C, n, rec, band);
+                       (const double*)C, n, rec);
   else
     hipLaunchKernelGGL(joint2_occupations<float>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const float*)C, n, rec, band);
+                       (const float*)C, n, rec);
   MP_HIP_LAUNCH_CHECK("mp_binned_counts joint occupations launch");
+  const mp_status sb = record_bands_launch(rec, E, 2, K, 2, band, stream);
+  if (sb != MP_OK) return sb;
   const unsigned tiles = (unsigned)(((K[0] + kJT - 1) / kJT) * ((K[1] + kJT - 1) / kJT));
   const unsigned nst = (unsigned)(p.s_last - p.s_first + 1);
   if (prec == MP_FP64)
@@ -542,7 +562,6 @@ struct FinalParams {
   int entries;
   int n_sub;
   double inv_ns;
-  int joint2;  // 1: one 2-D distribution K[0] x K[1]
 };
 
 // One workgroup per output point; threads split the frequency sum, and the
@@ -553,33 +572,15 @@ __global__ __launch_bounds__(256) void counts_finalize(FinalParams p, const doub
                                                        double* __restrict__ sigma) {
   __shared__ double red_r[256], red_i[256];
   const int e = blockIdx.x;
-  int q = 0, l1 = 0, l2 = 0, K1 = 1, K2 = 1, nterms;
-  if (p.joint2) {
-    K1 = p.K[0];
-    K2 = p.K[1];
-    l1 = e / K2;
-    l2 = e % K2;
-    nterms = K1 * K2;
-  } else {
-    while (q + 1 < p.n_dist && e >= p.off[q + 1]) ++q;
-    K1 = p.K[q];
-    l1 = e - p.off[q];
-    nterms = K1;
-  }
+  int q = 0;
+  while (q + 1 < p.n_dist && e >= p.off[q + 1]) ++q;
+  const int K1 = p.K[q], l1 = e - p.off[q], nterms = K1;
   double mean_r = 0.0, mean_i = 0.0, m2 = 0.0;
   for (int s = 0; s < p.n_sub; ++s) {
-    const double* a = acc + ((int64_t)s * p.entries + (p.joint2 ? 0 : p.off[q])) * 2;
+    const double* a = acc + ((int64_t)s * p.entries + p.off[q]) * 2;
     double sr = 0.0, si = 0.0;
     for (int t = threadIdx.x; t < nterms; t += 256) {
-      int k1 = t, k2 = 0;
-      double frac;
-      if (p.joint2) {
-        k1 = t / K2;
-        k2 = t % K2;
-        frac = (double)(((int64_t)k1 * l1) % K1) / K1 + (double)(((int64_t)k2 * l2) % K2) / K2;
-      } else {
-        frac = (double)(((int64_t)k1 * l1) % K1) / K1;
-      }
+      const double frac = (double)(((int64_t)t * l1) % K1) / K1;
       double sw, cw;
       sincospi(-2.0 * frac, &sw, &cw);
       const double xr = a[2 * t], xi = a[2 * t + 1];
@@ -612,103 +613,6 @@ __global__ __launch_bounds__(256) void counts_finalize(FinalParams p, const doub
   }
 }
 
-// Joint (d = 2) inverse transform.  The accumulators are exactly zero
-// outside the frequency bands that any chunk touched, so the 2-D inverse DFT
-// is done separably over the nonzero rows and columns only:
-//   flags:   row k1 / column k2 nonzero in any sub-ensemble
-//   rows:    T_s[k1][l2] = sum_{k2 nonzero} chi_s[k1][k2] e^{-2 pi i k2 l2 / K2}
-//   columns: P_s[l1][l2] = sum_{k1 nonzero} T_s[k1][l2] e^{-2 pi i k1 l1 / K1}
-//            / (K1 K2 N_S), folded over s with Welford's update.
-__global__ void joint2_flags(const double* __restrict__ acc, int n_sub, int K1, int K2,
-                             int* __restrict__ rowf, int* __restrict__ colf) {
-  const int64_t total = (int64_t)n_sub * K1 * K2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    if (acc[2 * e] != 0.0 || acc[2 * e + 1] != 0.0) {
-      const int64_t kk = e % ((int64_t)K1 * K2);
-      atomicOr(&rowf[kk / K2], 1);
-      atomicOr(&colf[kk % K2], 1);
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void joint2_rows(const double* __restrict__ acc, int K1, int K2,
-                                                   const int* __restrict__ rowf,
-                                                   const int* __restrict__ colf,
-                                                   double* __restrict__ T) {
-  const int k1 = blockIdx.x;
-  const int64_t s = blockIdx.y;
-  if (!rowf[k1]) return;
-  const double* a = acc + (s * K1 * K2 + (int64_t)k1 * K2) * 2;
-  double* t = T + (s * K1 * K2 + (int64_t)k1 * K2) * 2;
-  for (int l2 = threadIdx.x; l2 < K2; l2 += blockDim.x) {
-    double sr = 0.0, si = 0.0;
-    for (int k2 = 0; k2 < K2; ++k2) {
-      if (!colf[k2]) continue;
-      const double xr = a[2 * k2], xi = a[2 * k2 + 1];
-      double sw, cw;
-      sincospi(-2.0 * (double)(((int64_t)k2 * l2) % K2) / K2, &sw, &cw);
-      sr += xr * cw - xi * sw;
-      si += xr * sw + xi * cw;
-    }
-    t[2 * l2] = sr;
-    t[2 * l2 + 1] = si;
-  }
-}
-
-__global__ __launch_bounds__(256) void joint2_columns(const double* __restrict__ T, int n_sub,
-                                                      int K1, int K2, double scale,
-                                                      const int* __restrict__ rowf,
-                                                      double* __restrict__ P_re,
-                                                      double* __restrict__ P_im,
-                                                      double* __restrict__ sigma) {
-  __shared__ int rows[4096];
-  __shared__ double tw[4096][2];
-  __shared__ int nrows;
-  const int l1 = blockIdx.x;
-  if (threadIdx.x == 0) {
-    int c = 0;
-    for (int k1 = 0; k1 < K1; ++k1)
-      if (rowf[k1]) rows[c++] = k1;
-    nrows = c;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nrows; q += blockDim.x) {
-    double sw, cw;
-    sincospi(-2.0 * (double)(((int64_t)rows[q] * l1) % K1) / K1, &sw, &cw);
-    tw[q][0] = cw;
-    tw[q][1] = sw;
-  }
-  __syncthreads();
-  for (int l2 = blockIdx.y * blockDim.x + threadIdx.x; l2 < K2; l2 += gridDim.y * blockDim.x) {
-    double mean_r = 0.0, mean_i = 0.0, m2 = 0.0;
-    for (int s = 0; s < n_sub; ++s) {
-      const double* t = T + ((int64_t)s * K1 * K2 + l2) * 2;
-      double sr = 0.0, si = 0.0;
-      for (int q = 0; q < nrows; ++q) {
-        const double xr = t[(int64_t)rows[q] * K2 * 2], xi = t[(int64_t)rows[q] * K2 * 2 + 1];
-        sr += xr * tw[q][0] - xi * tw[q][1];
-        si += xr * tw[q][1] + xi * tw[q][0];
-      }
-      sr *= scale;
-      si *= scale;
-      const double dr = sr - mean_r;
-      mean_r += dr / (s + 1);
-      mean_i += (si - mean_i) / (s + 1);
-      m2 += dr * (sr - mean_r);
-    }
-    const int64_t e = (int64_t)l1 * K2 + l2;
-    P_re[e] = mean_r;
-    if (P_im) P_im[e] = mean_i;
-    sigma[e] = n_sub > 1 ? sqrt(m2 / (n_sub - 1) / n_sub) : __builtin_nan("");
-  }
-}
-
-__global__ void fill_int(int* p, int n, int v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 size_t jointd_workspace(int32_t d, const int32_t* K, int64_t E);
 size_t jointd_finalize_workspace(int32_t d, const int32_t* K);
 mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp_precision prec,
@@ -720,9 +624,8 @@ mp_status jointd_finalize(int32_t d, const int32_t* K, int32_t n_sub, int64_t ns
                           size_t ws_bytes, hipStream_t stream);
 
 size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub) {
-  if (mode == MP_JOINT && d >= 3) return jointd_finalize_workspace(d, K);
-  if (!(mode == MP_JOINT && d == 2)) return 0;
-  return 256 + ((size_t)K[0] + K[1]) * 4 + (size_t)n_sub * K[0] * K[1] * 16 + 256;
+  if (mode == MP_JOINT && d >= 2) return jointd_finalize_workspace(d, K);
+  return 0;
 }
 
 // ---------------------------------------------------------------- host side
@@ -938,33 +841,10 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
                                  double* sigma, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (mode == MP_JOINT && d >= 3)
+  if (mode == MP_JOINT && d >= 2)
     return jointd_finalize(d, K, n_sub, ns, acc, P_re, P_im, sigma, ws, ws_bytes, stream);
-  if (mode == MP_JOINT && d == 2) {
-    const size_t need = finalize_workspace(d, mode, K, n_sub);
-    MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,
-                 "mp_counts_finalize: workspace of %zu bytes needed, %zu given", need, ws_bytes);
-    MP_CHECK_ARG(K[0] <= 4096, MP_ERR_UNSUPPORTED,
-                 "mp_counts_finalize: joint windows need K[0] <= 4096");
-    const int K1 = K[0], K2 = K[1];
-    int* rowf = (int*)((char*)ws + 256);
-    int* colf = rowf + K1;
-    size_t toff = (256 + ((size_t)K1 + K2) * 4 + 255) / 256 * 256;
-    double* T = (double*)((char*)ws + toff);
-    hipLaunchKernelGGL(fill_int, dim3((K1 + K2 + 255) / 256), dim3(256), 0, stream, rowf, K1 + K2, 0);
-    hipLaunchKernelGGL(joint2_flags, dim3(2048), dim3(256), 0, stream, acc, n_sub, K1, K2, rowf,
-                       colf);
-    hipLaunchKernelGGL(joint2_rows, dim3(K1, n_sub), dim3(256), 0, stream, acc, K1, K2, rowf, colf,
-                       T);
-    const double scale = 1.0 / ((double)K1 * (double)K2 * (double)ns);
-    hipLaunchKernelGGL(joint2_columns, dim3(K1, (K2 + 255) / 256), dim3(256), 0, stream, T, n_sub,
-                       K1, K2, scale, rowf, P_re, P_im, sigma);
-    MP_HIP_LAUNCH_CHECK("mp_counts_finalize joint launch");
-    return MP_OK;
-  }
   FinalParams p{};
-  p.joint2 = (mode == MP_JOINT && d == 2) ? 1 : 0;
-  p.n_dist = mode == MP_JOINT ? (p.joint2 ? 2 : 1) : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
+  p.n_dist = mode == MP_JOINT ? 1 : d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
   p.off[0] = 0;
   for (int q = 0; q < p.n_dist; ++q) {
     p.K[q] = K[q];
@@ -980,16 +860,52 @@ mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, 
 }
 
 
+// ---------------------------------------------------------------- finiteness
+
+__global__ void zero_i64(int64_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+// Grid-stride count of non-finite entries, one atomic add per wave.
+__global__ __launch_bounds__(256) void count_nonfinite(const double* __restrict__ x, int64_t n,
+                                                       int64_t* __restrict__ count) {
+  int64_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    c += isfinite(x[i]) ? 0 : 1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c != 0) atomicAdd((unsigned long long*)count, (unsigned long long)c);
+}
+
+mp_status check_finite_launch(const double* x, int64_t n, int64_t* scratch, int64_t* n_bad,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(zero_i64, dim3(1), dim3(64), 0, stream, scratch);
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(count_nonfinite, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, scratch);
+  MP_HIP_LAUNCH_CHECK("mp_check_finite launch");
+  int64_t c = 0;
+  hipError_t e = hipMemcpyAsync(&c, scratch, sizeof(c), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    set_error("mp_check_finite: %s", hipGetErrorString(e));
+    return MP_ERR_HIP;
+  }
+  if (n_bad) *n_bad = c;
+  if (c != 0) {
+    set_error("mp_check_finite: %lld of %lld values are NaN or infinite", (long long)c,
+              (long long)n);
+    return MP_ERR_NONFINITE;
+  }
+  return MP_OK;
+}
+
 // ---------------------------------------------------------------- per-sample observables
 
 // Occupation of every distribution for every sample of the chunk (wave per
 // sample): nq[(k n_dist + q) 2 + {0, 1}] = (Re, Im) n_q of chunk sample k.
 template <typename CT>
-__global__ __launch_bounds__(256) void occupations_kernel(CountsParams p, const CT* __restrict__ C,
-                                                          double* __restrict__ nq) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
-  if (k >= p.E) return;
+__device__ inline void occupation_sample(const CountsParams& p, const CT* __restrict__ C,
+                                         double* __restrict__ nq, int64_t k, int lane) {
   const int64_t ldc = 2 * p.ldm;
   double nb[MP_MAX_BINS][2];
   sample_bin_sums<CT>(p, C + k * ldc, C + (p.E + k) * ldc, lane, nb);
@@ -1000,6 +916,19 @@ __global__ __launch_bounds__(256) void occupations_kernel(CountsParams p, const 
       nq[(k * p.n_dist + q) * 2] = vr;
       nq[(k * p.n_dist + q) * 2 + 1] = vi;
     }
+
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void occupations_kernel(CountsParams p, const CT* __restrict__ C,
+                                                          double* __restrict__ nq) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * (4 * kOccPerWave) + wave;
+  for (int j = 0; j < kOccPerWave; ++j) {
+    const int64_t k = base + 4 * j;
+    if (k >= p.E) return;
+    occupation_sample<CT>(p, C, nq, k, lane);
+  }
 }
 
 struct SampleStatParams {
@@ -1152,7 +1081,7 @@ mp_status occupations_launch(int32_t M, int64_t E, const void* C, mp_precision p
   }
   p.n_dist = d + (mode == MP_MARGINALS_AND_TOTAL ? 1 : 0);
   for (int q = 0; q < p.n_dist; ++q) p.dist_src[q] = q < d ? q : -1;
-  const int64_t blocks = (E + 3) / 4;
+  const int64_t blocks = (E + 4 * kOccPerWave - 1) / (4 * kOccPerWave);
   if (prec == MP_FP64)
     hipLaunchKernelGGL(occupations_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, p,
                        (const double*)C, nq);

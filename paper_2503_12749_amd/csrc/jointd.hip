@@ -1,5 +1,6 @@
 // Joint distribution of d = 3 or 4 bin counts (main text, higher-dimensional
-// binning; eq. General_GCP with the projector of eq. projection_op).
+// binning; eq. General_GCP with the projector of eq. projection_op), and the
+// inverse DFT of every joint grid (d = 2 included).
 //
 // Per sample the generating function on the grid theta_b = 2 pi k_b / K_b is
 //   chi(theta) = cosh(n + sum_b X_b) / cosh(n),   X_b = n_b (e^{i theta_b} - 1)
@@ -19,8 +20,8 @@
 // within the FP32 range.  The contraction runs on the FP32 matrix cores for
 // the FP32 and split paths and with FP64 FMAs for the FP64 path.
 //
-// Kernels per chunk: jointd_occupations (n_b, c1, c2 and the box
-// half-widths), jointd_factors (the tables of both terms inside their boxes),
+// Kernels per chunk: jointd_occupations (n_b, c1, c2 per sample),
+// record_bands (the box half-widths), jointd_factors (the tables of both terms inside their boxes),
 // jointd_sum_f32 / jointd_sum_f64 (acc[s][k_1]..[k_d] += S, one launch per
 // term, so each accumulator element has one writer per launch).  Finalize:
 // the d-dimensional inverse DFT one axis at a time over the nonzero entries
@@ -36,6 +37,7 @@ namespace mp {
 namespace {
 
 constexpr int kJD = 4;  // largest d of this path
+constexpr int kAxisMaxK = 4096;  // longest line of the inverse DFT (two-bin windows)
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
@@ -58,16 +60,13 @@ __global__ void band_init(int* band) {
   if (threadIdx.x < 2 * kJD) band[threadIdx.x] = -1;
 }
 
-// Per sample (one wave): record (Re n_b, Im n_b for b < d, c1, c2) and the
-// box half-widths band[term * 4 + b] (atomic max; -1 = term absent).
+// Per sample (one wave, lane 0 writes): the record (Re n_b, Im n_b for b < d,
+// c1, c2; c2 = -inf for +P).  record_bands then sets the box half-widths
+// band[term * 4 + b] (atomic max; -1 = term absent).
 template <typename CT>
-__global__ __launch_bounds__(256) void jointd_occupations(JointDParams p, const CT* __restrict__ C,
-                                                          const double* __restrict__ nglob,
-                                                          double* __restrict__ rec,
-                                                          int* __restrict__ band) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
-  if (k >= p.E) return;
+__device__ inline void jointd_sample(const JointDParams& p, const CT* __restrict__ C,
+                                     const double* __restrict__ nglob, double* __restrict__ rec,
+                                     int64_t k, int lane) {
   const int64_t ldc = 2 * p.ldm;
   const CT* ca = C + k * ldc;
   const CT* cb = C + (p.E + k) * ldc;
@@ -82,53 +81,31 @@ __global__ __launch_bounds__(256) void jointd_occupations(JointDParams p, const 
         ni[b] += im;
       }
   }
-  // every lane holds the wave-reduced sums; lane 0 writes the record and
-  // lanes 0 .. 2 d - 1 each bound one (term, axis) box
+  if (lane != 0) return;
   const double n = nglob[k];
   const bool with_v = p.est != MP_PLUS_P;
   const double L = log1p(exp(-2.0 * fabs(n)));
-  const double c1 = with_v ? (n >= 0.0 ? 0.0 : 2.0 * n) - L : 0.0;
-  const double c2 = (n >= 0.0 ? -2.0 * n : 0.0) - L;
-  double fm[kJD], fsum = 0.0, rsum = 0.0;
-#pragma unroll
-  for (int b = 0; b < kJD; ++b) {
-    fm[b] = 0.0;
-    if (b < p.d) {
-      fm[b] = fmax_exponent(nr[b], ni[b]);
-      fsum += fm[b];
-      rsum += nr[b];
-    }
-  }
-  if (lane == 0) {
-    double* r = rec + k * p.rec;
-#pragma unroll
-    for (int b = 0; b < kJD; ++b)
-      if (b < p.d) {
-        r[2 * b] = nr[b];
-        r[2 * b + 1] = ni[b];
-      }
-    r[2 * p.d] = c1;
-    r[2 * p.d + 1] = with_v ? c2 : -INFINITY;
-  }
-  if (lane >= 2 * p.d) return;
-  const int tau = lane / p.d, ax = lane % p.d;
-  if (tau == 1 && !with_v) return;
-  double R = 0.0, I = 0.0, f = 0.0;
+  double* r = rec + k * p.rec;
 #pragma unroll
   for (int b = 0; b < kJD; ++b)
-    if (b == ax) {
-      R = nr[b];
-      I = ni[b];
-      f = fm[b];
+    if (b < p.d) {
+      r[2 * b] = nr[b];
+      r[2 * b + 1] = ni[b];
     }
-  if (tau == 0) {
-    atomicMax(&band[ax], band_halfwidth(R, I, c1 + fsum - f, p.K[ax]));
-  } else {
-    // about theta = pi the exponent is 2 Re n_b + f_b(phi) with Im n_b
-    // negated; +1 because for odd K the grid is not symmetric about pi
-    int h = band_halfwidth(R, I, c2 + 2.0 * rsum + fsum - f, p.K[ax]);
-    h = h < 0 ? h : min(h + 1, p.K[ax] / 2);
-    atomicMax(&band[kJD + ax], h);
+  r[2 * p.d] = with_v ? (n >= 0.0 ? 0.0 : 2.0 * n) - L : 0.0;
+  r[2 * p.d + 1] = with_v ? (n >= 0.0 ? -2.0 * n : 0.0) - L : -INFINITY;
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void jointd_occupations(JointDParams p, const CT* __restrict__ C,
+                                                          const double* __restrict__ nglob,
+                                                          double* __restrict__ rec) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * (4 * kOccPerWave) + wave;
+  for (int j = 0; j < kOccPerWave; ++j) {
+    const int64_t k = base + 4 * j;
+    if (k >= p.E) return;
+    jointd_sample<CT>(p, C, nglob, rec, k, lane);
   }
 }
 
@@ -624,6 +601,9 @@ bool fill_params(JointDParams& p, int32_t M, int64_t E, int32_t d, const int32_t
 
 }  // namespace
 
+mp_status record_bands_launch(const double* rec, int64_t E, int d, const int32_t* K,
+                              int band_stride, int* band, hipStream_t stream);
+
 size_t jointd_workspace(int32_t d, const int32_t* K, int64_t E) {
   JointDParams p{};
   fill_params(p, 1, E, d, nullptr, nullptr, K, 1, 0);
@@ -669,13 +649,15 @@ mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp
   double* rec = (double*)((char*)ws + 256);
   void* tables = (char*)ws + 256 + round_up(E * p.rec * 8, 256);
   hipLaunchKernelGGL(band_init, dim3(1), dim3(64), 0, stream, band);
-  const unsigned blocks = (unsigned)((E + 3) / 4);
+  const unsigned blocks = (unsigned)((E + 4 * kOccPerWave - 1) / (4 * kOccPerWave));
   int kp_max = 0;
   for (int b = 0; b < d; ++b) kp_max = p.Kp[b] > kp_max ? p.Kp[b] : kp_max;
   const dim3 fgrid((unsigned)((E * kp_max + 255) / 256), (unsigned)(2 * d));
   if (prec == MP_FP64) {
     hipLaunchKernelGGL(jointd_occupations<double>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const double*)C, n, rec, band);
+                       (const double*)C, n, rec);
+    const mp_status sb = record_bands_launch(rec, E, d, K, kJD, band, stream);
+    if (sb != MP_OK) return sb;
     hipLaunchKernelGGL(jointd_factors<double>, fgrid, dim3(256), 0, stream, p, rec, band,
                        (double*)tables);
     for (int tau = 0; tau < 2; ++tau)
@@ -683,7 +665,9 @@ mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp
                          (const double*)tables, band, acc);
   } else {
     hipLaunchKernelGGL(jointd_occupations<float>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const float*)C, n, rec, band);
+                       (const float*)C, n, rec);
+    const mp_status sb = record_bands_launch(rec, E, d, K, kJD, band, stream);
+    if (sb != MP_OK) return sb;
     hipLaunchKernelGGL(jointd_factors<float>, fgrid, dim3(256), 0, stream, p, rec, band,
                        (float*)tables);
     for (int tau = 0; tau < 2; ++tau)
@@ -700,9 +684,20 @@ mp_status jointd_finalize(int32_t d, const int32_t* K, int32_t n_sub, int64_t ns
   const size_t need = jointd_finalize_workspace(d, K);
   MP_CHECK_ARG(ws && ws_bytes >= need, MP_ERR_WORKSPACE,
                "mp_counts_finalize: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  const int kmax = d == 2 ? kAxisMaxK : 1024;
   for (int b = 0; b < d; ++b)
-    MP_CHECK_ARG(K[b] >= 1 && K[b] <= 1024, MP_ERR_UNSUPPORTED,
-                 "mp_counts_finalize: joint windows of d >= 3 need 1 <= K <= 1024 (K[%d] = %d)", b, K[b]);
+    MP_CHECK_ARG(K[b] >= 1 && K[b] <= kmax, MP_ERR_UNSUPPORTED,
+                 "mp_counts_finalize: joint windows of %d bins need 1 <= K <= %d (K[%d] = %d)", d,
+                 kmax, b, K[b]);
+  static bool lds_set = false;
+  if (!lds_set) {
+    // a line of the largest grid with its twiddles and index list: 36 B per point
+    const hipError_t e = hipFuncSetAttribute((const void*)jointd_axis,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             36 * kAxisMaxK);
+    MP_CHECK_ARG(e == hipSuccess, MP_ERR_HIP, "mp_counts_finalize: %s", hipGetErrorString(e));
+    lds_set = true;
+  }
   int64_t cells = 1;
   for (int b = 0; b < d; ++b) cells *= K[b];
   MP_CHECK_ARG(cells < 0x7fffffff, MP_ERR_UNSUPPORTED,

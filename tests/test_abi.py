@@ -100,7 +100,7 @@ def test_host_validation_rejects_bad_arguments():
     st = lib.mp_counts_finalize(1, 0, i32([8]), 0, 8, vp(16), vp(16), vp(16), vp(16), vp(0), 0, None)
     assert st == -1
     # joint two-bin finalize needs a workspace
-    assert lib.mp_finalize_workspace(2, 0, i32([16, 8]), 3) >= 3 * 16 * 8 * 16
+    assert lib.mp_finalize_workspace(2, 0, i32([16, 8]), 3) >= 2 * 16 * 8 * 16
     st = lib.mp_counts_finalize(2, 0, i32([16, 8]), 3, 8, vp(256), vp(256), vp(256), vp(256), vp(0),
                                 0, None)
     assert st == -5
@@ -153,6 +153,16 @@ def test_joint_limits_on_the_host():
     st = lib.mp_binned_counts(4, 8, vp(256), vp(256), 0, 0, 4, i32([0, 1, 2, 3]), 0, i32([0] * 4),
                               i32([1024] * 4), 1, 8, 0, vp(256), vp(256), 1 << 40, None)
     assert st == -4 and b"2^31" in lib.mp_last_error()
+
+
+def test_check_finite_validates_on_the_host():
+    lib = _lib()
+    vp = ctypes.c_void_p
+    bad = ctypes.c_int64(-1)
+    assert lib.mp_check_finite(vp(0), 4, vp(64), ctypes.byref(bad), None) == -1
+    assert lib.mp_check_finite(vp(64), 0, vp(64), ctypes.byref(bad), None) == -1
+    assert lib.mp_check_finite(vp(64), 4, vp(0), ctypes.byref(bad), None) == -1
+    assert lib.mp_check_finite(vp(60), 4, vp(64), None, None) == -1
 
 
 def test_pair_calls_validate_on_the_host():

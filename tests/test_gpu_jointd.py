@@ -143,3 +143,30 @@ def test_joint3_offset_windows_and_ragged_chunks():
     ref = oest.estimate(T, r, 23, 450, 3, bins, 3, wide, mode="joint", chunk=50)
     Pr = _fold(ref["P"], wins)
     assert not (np.abs(P - Pr) > _bound(Pr)).any(), np.abs(P - Pr).max()
+
+
+def test_joint2_long_windows_sum_to_marginals():
+    """Two-bin joint on windows of 2048 x 1500 counts (inverse-DFT lines
+    longer than 64 KiB of LDS): summed over m_2 it equals the marginal of bin
+    1, and over m_1 that of bin 2, computed from the same noise by the
+    one-distribution path (identical aliasing; per sample the sum over a full
+    period of one axis is the other bin's generating function)."""
+    import paper_2503_12749_amd as mp
+    M = 64
+    T = 0.9 * synth.haar_unitary(M, 5)
+    r = np.full(M, 1.0)
+    bins = synth.contiguous_bins(M, 2)
+    wins = [(0, 2048), (0, 1500)]
+    kw = dict(prec="fp64", seed=31, bin_of_mode=bins, d=2, windows=wins, n_sub=4,
+              samples_per_sub=500, chunk=1000, device=DEV)
+    pj = mp.CountsPipeline(T, r, mode="joint", **kw)
+    pj.run()
+    Pj = pj.result()[0].reshape(2048, 1500)
+    del pj
+    pm = mp.CountsPipeline(T, r, mode="marginals", **kw)
+    pm.run()
+    Pm = pm.result()[0]
+    for got, ref in ((Pj.sum(axis=1), Pm[:2048]), (Pj.sum(axis=0), Pm[2048:])):
+        scale = np.abs(ref).max()
+        tol = 1e-10 * np.maximum(np.abs(ref), 1e-4 * scale) + 1e-13 * scale
+        assert np.all(np.abs(got - ref) <= tol), np.abs(got - ref).max()

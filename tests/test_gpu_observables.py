@@ -163,3 +163,16 @@ def test_stats_single_subensemble_sigma_is_nan_and_bad_arguments_fail():
         mp.mp_observable_histogram(4, n, nq, 1, 0, 2, "matrix_p", 0.0, 0.1, 3, 1, 2, 0, hist)
     with pytest.raises(mp.MPError):  # kmax too large
         mp.mp_moments_accumulate(4, n, nq, 1, 9, "matrix_p", 2, 2, 0, hist)
+
+
+def test_check_finite_counts_nan_and_inf():
+    import paper_2503_12749_amd as mp
+    x = torch.linspace(-1, 1, 100003, dtype=torch.float64, device="cuda:0")
+    scratch = torch.empty(1, dtype=torch.int64, device="cuda:0")
+    assert mp.mp_check_finite(x, scratch) == 0
+    x[7] = float("nan")
+    x[100002] = float("inf")
+    x[5000] = float("-inf")
+    with pytest.raises(mp.MPError) as e:
+        mp.mp_check_finite(x, scratch)
+    assert e.value.status == -6 and "3 of 100003" in str(e.value)
