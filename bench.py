@@ -632,7 +632,8 @@ def run_pairs_m1000(args, mp, torch, synth):
             ev[c][0].record(stream)
             mp.mp_mode_occupations(p.M, E, p.C, p.prec, p.X)
             ev[c][1].record(stream)
-            mp.mp_pair_correlations_accumulate(p.M, E, p.X, p.prec, p.n_sub, p.ns, g, p.acc)
+            mp.mp_pair_correlations_accumulate(p.M, E, p.X, p.prec, p.n_sub, p.ns, g, p.acc,
+                                               p.workspace(g, E))
             ev[c][2].record(stream)
         p.finalize()
     job()

@@ -358,18 +358,27 @@ mp_status mp_subensemble_stats(int32_t n_sub, int64_t samples_per_sub, int64_t n
  *   n_sub, samples_per_sub, e0  as for mp_binned_counts
  *   acc            device FP64, n_sub * M * M * 2 (re, im), layout [s][i][j],
  *                  caller-zeroed, added into (16-byte aligned)
+ *   workspace      device, >= mp_pair_correlations_workspace(M, E, prec,
+ *                  samples_per_sub, e0) bytes, 256-aligned; may be NULL when
+ *                  that size is 0
  * FP64 runs FP64 FMAs; FP32 and the split precisions multiply FP32 values on
  * the FP32 matrix cores, summing in FP32 over the chunk's samples of one
- * sub-ensemble and in FP64 across chunks.  One workgroup owns each (tile,
- * sub-ensemble), so the sums do not depend on scheduling.
+ * sub-ensemble and in FP64 across chunks.  When a chunk has few (128 x 128
+ * tile, sub-ensemble) items for the GPU, each is split into up to 8 pieces of
+ * samples summed in FP32 into partial tiles in the workspace, and the pieces
+ * are then added in order in FP64.  Either way each accumulator element has
+ * one writer per call and the sums do not depend on scheduling.
  * Means and sigma_T: mp_subensemble_stats(n_vals = M * M, ncomp = 2, scale = 1).
  */
 size_t mp_mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec);
 mp_status mp_mode_occupations(int32_t M, int64_t E, const void* C, mp_precision prec, void* X,
                               void* stream);
+size_t mp_pair_correlations_workspace(int32_t M, int64_t E, mp_precision prec,
+                                      int64_t samples_per_sub, int64_t e0);
 mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, mp_precision prec,
                                           int32_t n_sub, int64_t samples_per_sub, int64_t e0,
-                                          double* acc, void* stream);
+                                          double* acc, void* workspace, size_t ws_bytes,
+                                          void* stream);
 
 /*
  * Synchronous finiteness check of a device FP64 array, for estimates and

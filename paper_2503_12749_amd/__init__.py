@@ -21,7 +21,7 @@ __all__ = [
     "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries",
     "mp_binned_workspace", "mp_binned_counts", "mp_counts_finalize", "mp_finalize_workspace",
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
-    "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_version", "CountsPipeline",
+    "mp_pair_correlations_workspace", "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_version", "CountsPipeline",
     "PairPipeline", "Plan", "MPError", "mp_check_finite",
 ]
 
@@ -159,9 +159,16 @@ def mp_mode_occupations(M, E, C, prec, X, stream=None):
                                                _stream(stream)))
 
 
-def mp_pair_correlations_accumulate(M, E, X, prec, n_sub, samples_per_sub, e0, acc, stream=None):
+def mp_pair_correlations_workspace(M, E, prec, samples_per_sub, e0) -> int:
+    return int(_lib.load().mp_pair_correlations_workspace(M, E, _prec(prec), samples_per_sub, e0))
+
+
+def mp_pair_correlations_accumulate(M, E, X, prec, n_sub, samples_per_sub, e0, acc,
+                                    workspace=None, stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _lib.check(_lib.load().mp_pair_correlations_accumulate(M, E, _ptr(X), _prec(prec), n_sub,
                                                            samples_per_sub, e0, _ptr(acc),
+                                                           _ptr(workspace), nbytes,
                                                            _stream(stream)))
 
 
@@ -320,6 +327,7 @@ class PairPipeline:
     def __init__(self, T: np.ndarray, r: np.ndarray, *, prec="fp32", seed: int, net: int = 0,
                  n_sub: int, samples_per_sub: int, chunk: int, device="cuda:0"):
         import torch
+        self.torch = torch
         T = np.ascontiguousarray(T, dtype=np.complex128)
         self.M = int(T.shape[0])
         assert T.shape == (self.M, self.M)
@@ -338,6 +346,7 @@ class PairPipeline:
                              dtype=torch.uint8, device=dev)
         nv = self.M * self.M
         self.acc = torch.zeros(self.n_sub * nv * 2, dtype=torch.float64, device=dev)
+        self.ws = torch.empty(256, dtype=torch.uint8, device=dev)
         self.mean = torch.empty(nv * 2, dtype=torch.float64, device=dev)
         self.sigma = torch.empty(nv, dtype=torch.float64, device=dev)
         self.packed = False
@@ -351,10 +360,19 @@ class PairPipeline:
         mp_propagate_packed(self.M, E, self.prec, self.ab, self.C, self.ws_prop, stream)
         self.pairs_chunk(g0, E, stream)
 
+    def workspace(self, g0: int, E: int):
+        """The pair-sum workspace for samples [g0, g0 + E), grown when a
+        chunk's alignment or size needs more (a short chunk can need partial
+        tiles where a full one does not)."""
+        need = mp_pair_correlations_workspace(self.M, E, self.prec, self.ns, g0)
+        if need > self.ws.numel():
+            self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.ws.device)
+        return self.ws
+
     def pairs_chunk(self, g0: int, E: int, stream=None):
         mp_mode_occupations(self.M, E, self.C, self.prec, self.X, stream)
         mp_pair_correlations_accumulate(self.M, E, self.X, self.prec, self.n_sub, self.ns, g0,
-                                        self.acc, stream)
+                                        self.acc, self.workspace(g0, E), stream)
 
     def finalize(self, stream=None):
         mp_subensemble_stats(self.n_sub, self.ns, self.M * self.M, 2, 1.0, self.acc, self.mean,

@@ -23,7 +23,7 @@ EXPORTS = [
     "mp_propagate", "mp_pack_transmission", "mp_propagate_packed", "mp_occupations",
     "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries",
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
-    "mp_check_finite",
+    "mp_check_finite", "mp_pair_correlations_workspace",
     "mp_binned_workspace", "mp_binned_counts", "mp_propagate_counts_workspace",
     "mp_propagate_counts", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
     "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_destroy",
@@ -91,8 +91,9 @@ def load() -> ctypes.CDLL:
         "mp_check_finite": (ctypes.c_int, [vp, c_i64, vp, ctypes.POINTER(c_i64), vp]),
         "mp_mode_occupations_bytes": (sz, [c_i32, c_i64, ctypes.c_int]),
         "mp_mode_occupations": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, vp, vp]),
+        "mp_pair_correlations_workspace": (sz, [c_i32, c_i64, ctypes.c_int, c_i64, c_i64]),
         "mp_pair_correlations_accumulate": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, c_i32,
-                                                           c_i64, c_i64, vp, vp]),
+                                                           c_i64, c_i64, vp, vp, sz, vp]),
         "mp_binned_workspace": (sz, [c_i32, ctypes.c_int, i32p, c_i64, c_i32, c_i64, c_i64]),
         "mp_binned_counts": (ctypes.c_int, [c_i32, c_i64, vp, vp, ctypes.c_int, ctypes.c_int, c_i32,
                                             i32p, ctypes.c_int, i32p, i32p, c_i32, c_i64, c_i64,

@@ -76,8 +76,10 @@ mp_status check_finite_launch(const double* x, int64_t n, int64_t* scratch, int6
 size_t mode_occupations_bytes(int32_t M, int64_t E, mp_precision prec);
 mp_status mode_occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, void* X,
                                   hipStream_t stream);
+size_t pair_corr_workspace(int32_t M, int64_t E, mp_precision prec, int64_t ns, int64_t e0);
 mp_status pair_corr_launch(int32_t M, int64_t E, const void* X, mp_precision prec, int64_t ns,
-                           int64_t e0, double* acc, hipStream_t stream);
+                           int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
 size_t mlp_workspace(const mp_mlp_shape* s, int32_t batch);
 mp_status mlp_forward(const mp_mlp_shape* s, const uint16_t* w16, const float* params,
                       const float* X, int32_t batch, float* Y, void* ws, hipStream_t st);
@@ -432,9 +434,16 @@ mp_status mp_mode_occupations(int32_t M, int64_t E, const void* C, mp_precision 
   return mode_occupations_launch(M, E, C, prec, X, (hipStream_t)stream);
 }
 
+size_t mp_pair_correlations_workspace(int32_t M, int64_t E, mp_precision prec,
+                                      int64_t samples_per_sub, int64_t e0) {
+  if (M < 1 || E < 1 || !valid_prec(prec) || samples_per_sub < 1 || e0 < 0) return 0;
+  return pair_corr_workspace(M, E, prec, samples_per_sub, e0);
+}
+
 mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, mp_precision prec,
                                           int32_t n_sub, int64_t samples_per_sub, int64_t e0,
-                                          double* acc, void* stream) {
+                                          double* acc, void* workspace, size_t ws_bytes,
+                                          void* stream) {
   clear_error();
   MP_CHECK_ARG(M >= 1 && E >= 1, MP_ERR_ARG,
                "mp_pair_correlations_accumulate: M and E must be >= 1");
@@ -449,7 +458,10 @@ mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, m
                "mp_pair_correlations_accumulate: samples [%lld, %lld) do not fit n_sub = %d "
                "sub-ensembles of %lld",
                (long long)e0, (long long)(e0 + E), n_sub, (long long)samples_per_sub);
-  return pair_corr_launch(M, E, X, prec, samples_per_sub, e0, acc, (hipStream_t)stream);
+  MP_CHECK_ARG(workspace == nullptr || aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_pair_correlations_accumulate: workspace must be 256-byte aligned");
+  return pair_corr_launch(M, E, X, prec, samples_per_sub, e0, acc, workspace, ws_bytes,
+                          (hipStream_t)stream);
 }
 
 int64_t mp_mlp_param_count(const mp_mlp_shape* shape) {

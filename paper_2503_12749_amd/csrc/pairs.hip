@@ -10,13 +10,18 @@
 //                            imaginary parts in column E + k, ldm modes each)
 //   pair_corr_f32            FP32 MFMA, 128 x 128 complex tiles of the upper
 //                            block triangle, FP32 sums over the chunk's
-//                            samples of one sub-ensemble, added into FP64
+//                            samples of one sub-ensemble (or of one piece of
+//                            them), added into FP64
+//   pair_reduce              when a launch has few (tile, sub-ensemble) items,
+//                            each is split into pieces of samples that write
+//                            FP32 partial tiles; this adds the pieces in
+//                            order into the FP64 accumulator
 //   pair_corr_f64            FP64 FMA twin (64 x 64 tiles) for the FP64 path
 //
 // The accumulator is the full matrix, [s][i][j] (re, im): a tile off the
 // diagonal adds its block and the transposed block.  Every (sub-ensemble,
-// tile) pair is one workgroup, so each accumulator element has one writer
-// per launch and the result does not depend on scheduling.
+// tile) pair has one writer per launch (its workgroup, or pair_reduce over
+// its pieces in a fixed order), so the result does not depend on scheduling.
 #include "common.h"
 
 namespace mp {
@@ -54,8 +59,11 @@ __global__ __launch_bounds__(256) void mode_occupations_kernel(int64_t ldm, int6
 
 struct PairParams {
   int64_t M, ldm, E, e0, ns, s_first;
-  int nb;       // mode blocks per side (ldm / tile)
-  int n_pairs;  // nb (nb + 1) / 2
+  int nb;           // mode blocks per side (ldm / tile)
+  int n_pairs;      // nb (nb + 1) / 2
+  int pieces;       // sample pieces per (tile, sub-ensemble) item
+  int64_t piece;    // samples per piece (a multiple of the slab)
+  float* part;      // pieces > 1: partial tiles [item][piece][128 x 128][re, im]
 };
 
 // Row-major enumeration of the upper block triangle: (0,0), (0,1), ...
@@ -69,16 +77,26 @@ __device__ inline void pair_of_index(int q, int nb, int& I, int& J) {
   J = i + q;
 }
 
-// Workgroup -> (tile pair, sub-ensemble) and the chunk-local sample range
-// [k0, k1) of that sub-ensemble.
-__device__ inline void pair_item(const PairParams& p, int& I, int& J, int64_t& s, int64_t& k0,
-                                 int64_t& k1) {
+// Workgroup -> (sub-ensemble, piece, tile pair) and the chunk-local sample
+// range [k0, k1) of that piece of the sub-ensemble (empty for pieces past a
+// short sub-ensemble's end).
+__device__ inline void pair_item(const PairParams& p, int& I, int& J, int64_t& s, int& pc,
+                                 int64_t& k0, int64_t& k1) {
   const int q = (int)(blockIdx.x % (unsigned)p.n_pairs);
-  s = p.s_first + blockIdx.x / (unsigned)p.n_pairs;
+  const int64_t rest = blockIdx.x / (unsigned)p.n_pairs;
+  pc = (int)(rest % p.pieces);
+  s = p.s_first + rest / p.pieces;
   pair_of_index(q, p.nb, I, J);
   const int64_t lo = s * p.ns - p.e0, hi = (s + 1) * p.ns - p.e0;
-  k0 = lo > 0 ? lo : 0;
-  k1 = hi < p.E ? hi : p.E;
+  const int64_t a = (lo > 0 ? lo : 0) + pc * p.piece;
+  const int64_t b = hi < p.E ? hi : p.E;
+  k0 = a;
+  k1 = a + p.piece < b ? a + p.piece : b;
+}
+
+// Partial tile of (sub-ensemble s, tile pair q, piece pc).
+__device__ inline float* part_tile(const PairParams& p, int64_t s, int q, int pc) {
+  return p.part + (((s - p.s_first) * p.n_pairs + q) * p.pieces + pc) * (int64_t)(2 * 128 * 128);
 }
 
 // Adds one complex value into element (i, j) of sub-ensemble s, and into
@@ -113,9 +131,9 @@ constexpr int PK = 32;   // samples per slab
 __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const float* __restrict__ X,
                                                        double* __restrict__ acc) {
   __shared__ __attribute__((aligned(16))) float lds[4][PK][PT];  // Re I, Im I, Re J, Im J
-  int I, J;
+  int I, J, pc;
   int64_t s, k0, k1;
-  pair_item(p, I, J, s, k0, k1);
+  pair_item(p, I, J, s, pc, k0, k1);
   const bool diag = I == J;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wi = wave >> 1, wj = wave & 1, lr = lane & 31, lh = lane >> 5;
@@ -187,6 +205,22 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
     }
   }
 
+  if (p.pieces > 1) {
+    // partial tile, element (row, col) at 2 (128 row + col)
+    float* t = part_tile(p, s, (int)(blockIdx.x % (unsigned)p.n_pairs), pc);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 64 * wi + 32 * a + 8 * (r >> 2) + 4 * lh + (r & 3);
+          const int col = 64 * wj + 32 * b + lr;
+          typedef __attribute__((ext_vector_type(2))) float f32x2;
+          *(f32x2*)(t + 2 * (row * PT + col)) = f32x2{accR[a][b][r], accI[a][b][r]};
+        }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -197,6 +231,24 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
         const int64_t gj = (int64_t)J * PT + 64 * wj + 32 * b + lr;
         pair_add(p, acc, s, gi, gj, !diag, accR[a][b][r], accI[a][b][r]);
       }
+}
+
+// Sum of the pieces of each (sub-ensemble, tile pair) item in piece order
+// (FP64), added into the accumulator like pair_corr_f32's direct epilogue.
+// One thread per tile element; grid (items, 128 x 128 / 256).
+__global__ __launch_bounds__(256) void pair_reduce(PairParams p, double* __restrict__ acc) {
+  const int q = (int)(blockIdx.x % (unsigned)p.n_pairs);
+  const int64_t s = p.s_first + blockIdx.x / (unsigned)p.n_pairs;
+  const int e = blockIdx.y * 256 + threadIdx.x;  // row * 128 + col
+  int I, J;
+  pair_of_index(q, p.nb, I, J);
+  double re = 0.0, im = 0.0;
+  for (int pc = 0; pc < p.pieces; ++pc) {
+    const float* t = part_tile(p, s, q, pc);
+    re += (double)t[2 * e];
+    im += (double)t[2 * e + 1];
+  }
+  pair_add(p, acc, s, (int64_t)I * PT + e / PT, (int64_t)J * PT + e % PT, I != J, re, im);
 }
 
 // ---------------------------------------------------------------- FP64
@@ -211,9 +263,9 @@ constexpr int QK = 16;  // samples per slab
 __global__ __launch_bounds__(256) void pair_corr_f64(PairParams p, const double* __restrict__ X,
                                                     double* __restrict__ acc) {
   __shared__ __attribute__((aligned(32))) double lds[4][QK][QT];
-  int I, J;
+  int I, J, pc;
   int64_t s, k0, k1;
-  pair_item(p, I, J, s, k0, k1);
+  pair_item(p, I, J, s, pc, k0, k1);
   const bool diag = I == J;
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int lc = (tid & 15) * 4, lrow = tid >> 4;
@@ -286,8 +338,9 @@ mp_status mode_occupations_launch(int32_t M, int64_t E, const void* C, mp_precis
   return MP_OK;
 }
 
-mp_status pair_corr_launch(int32_t M, int64_t E, const void* X, mp_precision prec, int64_t ns,
-                           int64_t e0, double* acc, hipStream_t stream) {
+// Launch shape: (tile, sub-ensemble) items, split into sample pieces when
+// there are too few of them to keep every CU busy to the end (FP32 only).
+static PairParams pair_plan(int32_t M, int64_t E, mp_precision prec, int64_t ns, int64_t e0) {
   PairParams p{};
   p.M = M;
   p.ldm = ld_modes(M);
@@ -298,18 +351,59 @@ mp_status pair_corr_launch(int32_t M, int64_t E, const void* X, mp_precision pre
   p.nb = (int)(p.ldm / (prec == MP_FP64 ? QT : PT));
   p.n_pairs = p.nb * (p.nb + 1) / 2;
   const int64_t n_touched = (e0 + E - 1) / ns - p.s_first + 1;
-  const int64_t blocks = n_touched * p.n_pairs;
+  const int64_t items = n_touched * p.n_pairs;
+  const int64_t seg = ns < E ? ns : E;  // longest piece of a sub-ensemble in this chunk
+  p.pieces = 1;
+  p.piece = seg;
+  constexpr int64_t kTargetItems = 2048, kMaxPieces = 8, kMinPiece = 2 * PK;
+  if (prec != MP_FP64 && items < kTargetItems) {
+    int64_t pcs = (kTargetItems + items - 1) / items;
+    pcs = pcs < kMaxPieces ? pcs : kMaxPieces;
+    const int64_t by_len = seg / kMinPiece;
+    pcs = pcs < by_len ? pcs : by_len;
+    if (pcs > 1) {
+      p.pieces = (int)pcs;
+      p.piece = ((seg + pcs - 1) / pcs + PK - 1) / PK * PK;
+    }
+  }
+  return p;
+}
+
+size_t pair_corr_workspace(int32_t M, int64_t E, mp_precision prec, int64_t ns, int64_t e0) {
+  const PairParams p = pair_plan(M, E, prec, ns, e0);
+  if (p.pieces == 1) return 0;
+  const int64_t n_touched = (e0 + E - 1) / ns - p.s_first + 1;
+  return (size_t)(n_touched * p.n_pairs * p.pieces) * (2 * PT * PT) * sizeof(float);
+}
+
+mp_status pair_corr_launch(int32_t M, int64_t E, const void* X, mp_precision prec, int64_t ns,
+                           int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  PairParams p = pair_plan(M, E, prec, ns, e0);
+  const size_t need = pair_corr_workspace(M, E, prec, ns, e0);
+  if (need > 0 && (!ws || ws_bytes < need)) {
+    set_error("mp_pair_correlations_accumulate: workspace of %zu bytes needed, %zu given", need,
+              ws_bytes);
+    return MP_ERR_WORKSPACE;
+  }
+  p.part = (float*)ws;
+  const int64_t n_touched = (e0 + E - 1) / ns - p.s_first + 1;
+  const int64_t blocks = n_touched * p.n_pairs * p.pieces;
   if (blocks > 0x7fffffff) {
     set_error("mp_pair_correlations_accumulate: %lld workgroups exceed the grid limit",
               (long long)blocks);
     return MP_ERR_UNSUPPORTED;
   }
-  if (prec == MP_FP64)
+  if (prec == MP_FP64) {
     hipLaunchKernelGGL(pair_corr_f64, dim3((unsigned)blocks), dim3(256), 0, stream, p,
                        (const double*)X, acc);
-  else
+  } else {
     hipLaunchKernelGGL(pair_corr_f32, dim3((unsigned)blocks), dim3(256), 0, stream, p,
                        (const float*)X, acc);
+    if (p.pieces > 1)
+      hipLaunchKernelGGL(pair_reduce, dim3((unsigned)(n_touched * p.n_pairs), PT * PT / 256),
+                         dim3(256), 0, stream, p, acc);
+  }
   MP_HIP_LAUNCH_CHECK("mp_pair_correlations_accumulate launch");
   return MP_OK;
 }

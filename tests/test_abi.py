@@ -178,10 +178,18 @@ def test_pair_calls_validate_on_the_host():
     assert b"aligned" in lib.mp_last_error()
     assert lib.mp_mode_occupations(8, 10, vp(64), 7, vp(64), None) == -1
     # pair sums: samples beyond the sub-ensembles, bad counts, null accumulator
-    acc = lambda *a: lib.mp_pair_correlations_accumulate(*a)
-    assert acc(8, 10, vp(64), 1, 2, 4, 0, vp(64), None) == -1
+    acc = lambda *a: lib.mp_pair_correlations_accumulate(*a, vp(0), 0, None)
+    assert acc(8, 10, vp(64), 1, 2, 4, 0, vp(64)) == -1
     assert b"do not fit" in lib.mp_last_error()
-    assert acc(8, 10, vp(64), 1, 0, 10, 0, vp(64), None) == -1
-    assert acc(8, 10, vp(64), 1, 1, 10, 0, vp(0), None) == -1
-    assert acc(8, 10, vp(64), 1, 1, 10, -1, vp(64), None) == -1
-    assert acc(0, 10, vp(64), 1, 1, 10, 0, vp(64), None) == -1
+    assert acc(8, 10, vp(64), 1, 0, 10, 0, vp(64)) == -1
+    assert acc(8, 10, vp(64), 1, 1, 10, 0, vp(0)) == -1
+    assert acc(8, 10, vp(64), 1, 1, 10, -1, vp(64)) == -1
+    assert acc(0, 10, vp(64), 1, 1, 10, 0, vp(64)) == -1
+    # piece split: few items -> FP32 needs partial tiles, FP64 never does
+    ws32 = lib.mp_pair_correlations_workspace(1000, 100000, 1, 10000, 0)
+    assert ws32 == 10 * 36 * 6 * 128 * 128 * 8
+    assert lib.mp_pair_correlations_workspace(1000, 100000, 0, 10000, 0) == 0
+    assert lib.mp_pair_correlations_workspace(8000, 65536, 1, 8192, 0) == 0
+    st = lib.mp_pair_correlations_accumulate(1000, 100000, vp(256), 1, 10, 10000, 0, vp(256),
+                                             vp(256), 1024, None)
+    assert st == -5 and b"workspace" in lib.mp_last_error()

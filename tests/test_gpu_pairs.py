@@ -146,3 +146,30 @@ def test_pair_moments_vs_closed_form_m64():
     print(f"max |z| = {np.abs(z).max():.2f}, rms z = {np.sqrt((z ** 2).mean()):.3f}")
     assert np.abs(z).max() < 5.5
     assert 0.8 < np.sqrt((z ** 2).mean()) < 1.2
+
+
+def test_pair_unsplit_launch_m2000():
+    """M = 2000 (136 tile pairs) with 16 sub-ensembles of 128 in one chunk:
+    2176 items, so the FP32 launch sums each item in one workgroup (no sample
+    pieces, no workspace); 40 sampled modes (first and last included) against
+    the oracle."""
+    import paper_2503_12749_amd as mp
+    M, E, n_sub, seed = 2000, 2048, 16, 88
+    ns = E // n_sub
+    assert mp.mp_pair_correlations_workspace(M, E, "fp32", ns, 0) == 0
+    T = _network(M, 12, t_lo=0.85)
+    r = np.linspace(0.6, 1.1, M)
+    p = mp.PairPipeline(T, r, prec="fp32", seed=seed, n_sub=n_sub, samples_per_sub=ns, chunk=E,
+                        device=DEV)
+    p.run()
+    got = p.subensemble_sums()
+    rng = np.random.default_rng(6)
+    S = np.unique(np.concatenate([[0, M - 1], rng.choice(M, 38, replace=False)]))
+    a, b, _ = osamp.sample(r, 0, E, seed)
+    ap, bp = oest.propagate(T[S], a, b)
+    ref = oest.pair_correlations(T[S], r, seed, E, n_sub, chunk=E)
+    for s in range(n_sub):
+        sl = slice(s * ns, (s + 1) * ns)
+        tol = _tolerance("fp32", a[sl], b[sl], ap[sl], bp[sl], rel_scale=3.0)
+        err = np.abs(got[s][np.ix_(S, S)] - ref["Ps"][s] * ns)
+        assert np.all(err <= tol), (s, (err / tol).max())
