@@ -209,6 +209,24 @@ __device__ inline int64_t cell_of(const JointDParams& p, int tau, const int (&h)
   return flat * p.K[p.d - 1] + box_index(p, tau, p.d - 1, h[p.d - 1], c);
 }
 
+// acc[s] cell of box point indices j (row axes) and box column c of term tau.
+__device__ inline int64_t cell_from(const JointDParams& p, int tau, const int (&h)[kJD],
+                                    const int (&j)[kJD], int c) {
+  int64_t flat = 0;
+#pragma unroll
+  for (int b = 0; b < kJD; ++b)
+    if (b < p.d - 1) flat = flat * p.K[b] + box_index(p, tau, b, h[b], j[b]);
+  return flat * p.K[p.d - 1] + box_index(p, tau, p.d - 1, h[p.d - 1], c);
+}
+
+// Row widths of the FP32 box contraction: the last row axis (d - 2) padded
+// to a multiple of 4, so that the four consecutive rows a thread stages
+// share their other axes and take four aligned consecutive table entries.
+__device__ inline void padded_widths(const JointDParams& p, const int (&w)[kJD], int (&wp)[kJD]) {
+#pragma unroll
+  for (int b = 0; b < kJD; ++b) wp[b] = b == p.d - 2 ? (w[b] + 3) & ~3 : w[b];
+}
+
 // Product over the row axes of one sample's factors (complex).
 template <typename CT>
 __device__ inline void row_factor(const JointDParams& p, int tau, const CT* __restrict__ tables,
@@ -244,18 +262,21 @@ constexpr int PK = 32;   // samples per slab
 // (lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; output register
 // r of lane l is element (8 (r / 4) + 4 (l / 32) + r % 4, l % 32)); wave
 // (wi, wj) owns a 64 x 64 block of the 128 x 128 complex tile.  The row
-// factors are multiplied in FP64 while a slab is staged.
+// operand (the product of the row axes' factors) is formed in FP32 while a
+// slab is staged, from 16-byte loads of the last row axis and the column
+// axis and scalar loads of the others.
 __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau,
                                                         const float* __restrict__ tables,
                                                         const int* __restrict__ band,
                                                         double* __restrict__ acc) {
   __shared__ __attribute__((aligned(16))) float lds[4][PK][PT];  // A re, A im, B re, B im
-  int h[kJD], w[kJD];
+  int h[kJD], w[kJD], wp[kJD];
   if (!term_box(p, band, tau, h, w)) return;
-  int64_t nrows = 1;
+  padded_widths(p, w, wp);
+  int64_t nrows = 1;  // a multiple of 4
 #pragma unroll
   for (int b = 0; b < kJD - 1; ++b)
-    if (b < p.d - 1) nrows *= w[b];
+    if (b < p.d - 1) nrows *= wp[b];
   const int ncols = w[p.d - 1];
   int64_t s, rt;
   int ct;
@@ -267,18 +288,20 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
   const int wi = wave >> 1, wj = wave & 1, lr = lane & 31, lh = lane >> 5;
   const int lc = (tid & 31) * 4, lrow = tid >> 5;
 
-  int jr[4][kJD];
-  bool rv[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t r = rt * PT + lc + e;
-    rv[e] = r < nrows;
-    row_point(p, w, rv[e] ? r : 0, jr[e]);
-  }
-  const int bl = p.d - 1;
+  // the thread's rows r0 .. r0 + 3 share axes 0 .. d-3 and take entries
+  // jl .. jl + 3 (jl a multiple of 4) of the last row axis
+  const int64_t r0 = rt * PT + lc;
+  const bool rvalid = r0 < nrows;
+  int jr[kJD];
+  row_point(p, wp, rvalid ? r0 : 0, jr);
+  const int al = p.d - 2, bl = p.d - 1;
+  const int jl = jr[al], wl = w[al];
+  const float* tl = tables + p.tab[tau][al];
+  const int64_t tl_im = p.E * p.Kp[al];
   const float* tb = tables + p.tab[tau][bl];
   const int64_t tb_im = p.E * p.Kp[bl];
   const int c0 = ct * PT + lc;
+  const bool cvalid = c0 < ncols;  // then c0 + 3 < Kp (both multiples of 4)
 
   float st[4][4][4];  // [plane][u][e]
   auto load = [&](int64_t kb) {
@@ -286,15 +309,30 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
     for (int u = 0; u < 4; ++u) {
       const int64_t k = kb + lrow + 8 * u;
       const bool kv = k < k1;
+      float pr = 1.f, pi = 0.f;  // factors of axes 0 .. d-3
+#pragma unroll
+      for (int b = 0; b < kJD - 2; ++b)
+        if (b < al && kv && rvalid) {
+          const float* t = tables + p.tab[tau][b] + k * p.Kp[b] + jr[b];
+          const float fr = t[0], fi = t[p.E * p.Kp[b]];
+          const float nr = pr * fr - pi * fi;
+          pi = pr * fi + pi * fr;
+          pr = nr;
+        }
+      const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+      const f32x4 lre = kv && rvalid ? *(const f32x4*)(tl + k * p.Kp[al] + jl) : zero;
+      const f32x4 lim = kv && rvalid ? *(const f32x4*)(tl + tl_im + k * p.Kp[al] + jl) : zero;
+      const f32x4 bre = kv && cvalid ? *(const f32x4*)(tb + k * p.Kp[bl] + c0) : zero;
+      const f32x4 bim = kv && cvalid ? *(const f32x4*)(tb + tb_im + k * p.Kp[bl] + c0) : zero;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        double ar = 0.0, ai = 0.0;
-        if (kv && rv[e]) row_factor<float>(p, tau, tables, k, jr[e], ar, ai);
-        st[0][u][e] = (float)ar;
-        st[1][u][e] = (float)ai;
-        const bool cv = kv && c0 + e < ncols;
-        st[2][u][e] = cv ? tb[k * p.Kp[bl] + c0 + e] : 0.f;
-        st[3][u][e] = cv ? tb[tb_im + k * p.Kp[bl] + c0 + e] : 0.f;
+        // table entries past the box width are never written: select, not multiply
+        const bool av = jl + e < wl;
+        st[0][u][e] = av ? pr * lre[e] - pi * lim[e] : 0.f;
+        st[1][u][e] = av ? pr * lim[e] + pi * lre[e] : 0.f;
+        const bool bv = c0 + e < ncols;
+        st[2][u][e] = bv ? bre[e] : 0.f;
+        st[3][u][e] = bv ? bim[e] : 0.f;
       }
     }
   };
@@ -357,9 +395,13 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
         const int64_t gr = rt * PT + 64 * wi + 32 * a + 8 * (q >> 2) + 4 * lh + (q & 3);
         const int gc = ct * PT + 64 * wj + 32 * b + lr;
         if (gr < nrows && gc < ncols) {
-          double* o = as + 2 * cell_of(p, tau, h, w, gr, gc);
-          o[0] += accR[a][b][q];
-          o[1] += accI[a][b][q];
+          int j[kJD];
+          row_point(p, wp, gr, j);
+          if (j[al] < wl) {
+            double* o = as + 2 * cell_from(p, tau, h, j, gc);
+            o[0] += accR[a][b][q];
+            o[1] += accI[a][b][q];
+          }
         }
       }
 }
@@ -578,7 +620,8 @@ bool fill_params(JointDParams& p, int32_t M, int64_t E, int32_t d, const int32_t
     p.K[b] = K[b];
     p.Kp[b] = (int)round_up(K[b], 4);
     p.cells *= K[b];
-    if (b < d - 1) p.rows_max *= K[b];
+    // the FP32 contraction pads the last row axis to a multiple of 4
+    if (b < d - 1) p.rows_max *= b == d - 2 ? round_up(K[b], 4) : K[b];
   }
   p.s_first = e0 / ns;
   p.n_runs = 0;
