@@ -550,11 +550,17 @@ __global__ __launch_bounds__(256) void jointd_axis(const double* __restrict__ in
     __syncthreads();
   }
   const int nnz = total;
+  // k l < 2^24 (Ka <= 4096) is exact in FP32: the quotient estimate is off by
+  // at most one, which the correction removes
+  const float inv_k = 1.0f / (float)Ka;
   for (int l = tid; l < Ka; l += 256) {
     double sr = 0.0, si = 0.0;
     for (int q = 0; q < nnz; ++q) {
       const int k = list[q];
-      const int t = (int)(((int64_t)k * l) % Ka);
+      const int kl = k * l;
+      int t = kl - (int)((float)kl * inv_k) * Ka;
+      t += t < 0 ? Ka : 0;
+      t -= t >= Ka ? Ka : 0;
       const double xr = line[2 * k], xi = line[2 * k + 1];
       const double cr = tw[2 * t], ci = tw[2 * t + 1];
       sr += xr * cr - xi * ci;
