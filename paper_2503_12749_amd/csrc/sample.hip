@@ -25,14 +25,28 @@
 
 namespace mp {
 
+// Full 128-bit product of two 64-bit words from four 32 x 32 -> 64
+// multiply-adds (each partial sum fits in 64 bits): a b = p00 +
+// (a0 b1 + a1 b0) 2^32 + a1 b1 2^64 with the carries taken through t1, t2.
+__device__ inline void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t1 = (uint64_t)a0 * b1 + (p00 >> 32);
+  const uint64_t t2 = (uint64_t)a1 * b0 + (uint32_t)t1;
+  hi = (uint64_t)a1 * b1 + (t1 >> 32) + (t2 >> 32);
+  lo = (t2 << 32) | (uint32_t)p00;
+}
+
 __device__ inline void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3,
                                      uint64_t k0, uint64_t k1) {
   constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull, kMul1 = 0xCA5A826395121157ull;
   constexpr uint64_t kWeyl0 = 0x9E3779B97F4A7C15ull, kWeyl1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint64_t hi0 = __umul64hi(kMul0, c0), lo0 = kMul0 * c0;
-    const uint64_t hi1 = __umul64hi(kMul1, c2), lo1 = kMul1 * c2;
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(kMul0, c0, hi0, lo0);
+    mulhilo64(kMul1, c2, hi1, lo1);
     const uint64_t n0 = hi1 ^ c1 ^ k0;
     const uint64_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
