@@ -502,58 +502,70 @@ __global__ __launch_bounds__(256) void jointd_sum_f64(JointDParams p, int tau,
 
 // ---------------------------------------------------------------- finalize
 
-// One line along axis a (all other indices fixed) per workgroup:
+// Lines along axis a (all other indices fixed), G per workgroup (G = 4 for
+// K_a <= 64, 2 for K_a <= 128, else 1; each line owns 256 / G threads, whole
+// waves):
 //   out[.., l_a, ..] = sum_{k_a with in != 0} in[.., k_a, ..] e^{-2 pi i k_a l_a / K_a},
-// with the nonzero k_a listed in ascending order (ballot prefix sums) and the
-// twiddles taken from a table of e^{-2 pi i q / K_a} by (k_a l_a mod K_a).
-// On the last axis the value times `scale` is sub-ensemble s's estimate of
-// P, folded into the running mean (P_re, P_im) and sum of squared deviations
-// (m2) with Welford's update.
+// with a line's nonzero k_a listed in ascending order (ballot prefix sums
+// over its waves) and the twiddles taken from a shared table of
+// e^{-2 pi i q / K_a} by (k_a l_a mod K_a).  On the last axis the value times
+// `scale` is sub-ensemble s's estimate of P, folded into the running mean
+// (P_re, P_im) and sum of squared deviations (m2) with Welford's update.
 __global__ __launch_bounds__(256) void jointd_axis(const double* __restrict__ in,
-                                                   double* __restrict__ out, int Ka,
-                                                   int64_t stride, int last, double scale,
-                                                   int s, double* __restrict__ P_re,
+                                                   double* __restrict__ out, int Ka, int G,
+                                                   int64_t n_lines, int64_t stride, int last,
+                                                   double scale, int s,
+                                                   double* __restrict__ P_re,
                                                    double* __restrict__ P_im,
                                                    double* __restrict__ m2) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  double* line = (double*)smem;      // 2 Ka
-  double* tw = line + 2 * Ka;        // 2 Ka
-  int* list = (int*)(tw + 2 * Ka);   // Ka
+  double* tw = (double*)smem;             // 2 Ka, shared
+  double* lines = tw + 2 * Ka;            // G x 2 Ka
+  int* lists = (int*)(lines + 2 * G * Ka);  // G x Ka
   __shared__ int wcnt[4];
-  __shared__ int total;
+  __shared__ int total[4];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t L = blockIdx.x;
+  const int gsz = 256 / G, g = tid / gsz, gt = tid - g * gsz;
+  const int wpg = gsz / 64, wig = gt >> 6;  // waves per line, wave within the line
+  const int64_t L = (int64_t)blockIdx.x * G + g;
+  const bool active = L < n_lines;
   const int64_t outer = L / stride, inner = L - outer * stride;
   const int64_t base = outer * (int64_t)Ka * stride + inner;
+  double* line = lines + 2 * g * Ka;
+  int* list = lists + g * Ka;
   for (int k = tid; k < Ka; k += 256) {
-    line[2 * k] = in[2 * (base + k * stride)];
-    line[2 * k + 1] = in[2 * (base + k * stride) + 1];
     double sw, cw;
     sincospi(-2.0 * (double)k / (double)Ka, &sw, &cw);
     tw[2 * k] = cw;
     tw[2 * k + 1] = sw;
   }
-  if (tid == 0) total = 0;
+  for (int k = gt; k < Ka; k += gsz) {
+    line[2 * k] = active ? in[2 * (base + k * stride)] : 0.0;
+    line[2 * k + 1] = active ? in[2 * (base + k * stride) + 1] : 0.0;
+  }
+  if (gt == 0) total[g] = 0;
   __syncthreads();
-  for (int k0 = 0; k0 < Ka; k0 += 256) {
-    const int k = k0 + tid;
+  for (int k0 = 0; k0 < Ka; k0 += gsz) {  // same trip count in every line
+    const int k = k0 + gt;
     const bool nz = k < Ka && (line[2 * k] != 0.0 || line[2 * k + 1] != 0.0);
     const unsigned long long mask = __ballot(nz);
     const int pre = __popcll(mask & ((1ull << lane) - 1ull));
     if (lane == 0) wcnt[wave] = __popcll(mask);
     __syncthreads();
-    int off = total;
-    for (int q = 0; q < wave; ++q) off += wcnt[q];
+    int off = total[g];
+    for (int q = 0; q < wig; ++q) off += wcnt[g * wpg + q];
     if (nz) list[off + pre] = k;
     __syncthreads();
-    if (tid == 0) total += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (gt == 0)
+      for (int q = 0; q < wpg; ++q) total[g] += wcnt[g * wpg + q];
     __syncthreads();
   }
-  const int nnz = total;
+  if (!active) return;
+  const int nnz = total[g];
   // k l < 2^24 (Ka <= 4096) is exact in FP32: the quotient estimate is off by
   // at most one, which the correction removes
   const float inv_k = 1.0f / (float)Ka;
-  for (int l = tid; l < Ka; l += 256) {
+  for (int l = gt; l < Ka; l += gsz) {
     double sr = 0.0, si = 0.0;
     for (int q = 0; q < nnz; ++q) {
       const int k = list[q];
@@ -761,9 +773,12 @@ mp_status jointd_finalize(int32_t d, const int32_t* K, int32_t n_sub, int64_t ns
       for (int b = a + 1; b < d; ++b) stride *= K[b];
       const int last = a == d - 1;
       double* dst = buf[a & 1];
-      const size_t lds = (size_t)K[a] * 36;
-      hipLaunchKernelGGL(jointd_axis, dim3((unsigned)(cells / K[a])), dim3(256), lds, stream, src,
-                         dst, K[a], stride, last, scale, s, P_re, P_im, sigma);
+      const int G = K[a] <= 64 ? 4 : (K[a] <= 128 ? 2 : 1);
+      const int64_t n_lines = cells / K[a];
+      const size_t lds = (size_t)K[a] * (16 + 20 * G);
+      hipLaunchKernelGGL(jointd_axis, dim3((unsigned)((n_lines + G - 1) / G)), dim3(256), lds,
+                         stream, src, dst, K[a], G, n_lines, stride, last, scale, s, P_re, P_im,
+                         sigma);
       src = dst;
     }
   }
