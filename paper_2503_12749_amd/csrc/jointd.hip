@@ -136,7 +136,7 @@ __device__ inline int box_index(const JointDParams& p, int tau, int b, int h, in
 
 // Factor f_{s,b}(j) of term tau for chunk sample k and box point j < w_b:
 // e^{+-X_b(theta) + share (- 2 Re n_b for the second term)} e^{-i theta m_lo},
-// FP64 arithmetic, stored in the path's precision (re plane, then im plane).
+// stored in the path's precision (re plane, then im plane).
 template <typename CT>
 __global__ __launch_bounds__(256) void jointd_factors(JointDParams p, const double* __restrict__ rec,
                                                       const int* __restrict__ band,
@@ -167,10 +167,13 @@ __global__ __launch_bounds__(256) void jointd_factors(JointDParams p, const doub
     const double xr = cm1 * R - sn * I, xi = cm1 * I + sn * R;
     const int64_t red = (((int64_t)kg * (int64_t)p.m_lo[b]) % K + K) % K;
     const double thl = kTwoPi * (double)red / (double)K;
+    // FP64 tables take FP64 exp / sincos, FP32 tables FP32 ones (phase
+    // reduced in FP64 first)
+    constexpr bool kF64 = sizeof(CT) == 8;
     if (tau == 0)
-      cis_exp<true>(xr + share, xi - thl, fr, fi);
+      cis_exp<kF64>(xr + share, xi - thl, fr, fi);
     else
-      cis_exp<true>(-xr - 2.0 * R + share, -xi - thl, fr, fi);
+      cis_exp<kF64>(-xr - 2.0 * R + share, -xi - thl, fr, fi);
   }
   CT* t = tables + p.tab[tau][b];
   t[k * Kp + j] = (CT)fr;
