@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "chi.h"
+#include "cmfma.h"
 #include "common.h"
 
 namespace mp {
@@ -40,7 +41,7 @@ constexpr int kJD = 4;  // largest d of this path
 constexpr int kAxisMaxK = 4096;  // longest line of the inverse DFT (two-bin windows)
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
-typedef __attribute__((ext_vector_type(16))) float f32x16;
+using cmfma::f32x16;
 
 struct JointDParams {
   int M;
@@ -260,6 +261,7 @@ __device__ inline void sum_item(const JointDParams& p, int tile, int64_t& s, int
 
 constexpr int PT = 128;  // box rows / columns per FP32 tile
 constexpr int PK = 32;   // samples per slab
+static_assert(PT == cmfma::kTile && PK == cmfma::kSlab, "tile shape of the shared MFMA core");
 
 // FP32 matrix cores, the 4-product complex scheme of v_mfma_f32_32x32x2f32
 // (lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; output register
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
   int64_t k0, k1;
   segment(p, s, k0, k1);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, wj = wave & 1, lr = lane & 31, lh = lane >> 5;
+  const int wi = wave >> 1, wj = wave & 1;
   const int lc = (tid & 31) * 4, lrow = tid >> 5;
 
   // the thread's rows r0 .. r0 + 3 share axes 0 .. d-3 and take entries
@@ -341,15 +343,7 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
   };
 
   f32x16 accR[2][2], accI[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        accR[a][b][q] = 0.f;
-        accI[a][b][q] = 0.f;
-      }
+  cmfma::zero(accR, accI);
 
   load(k0);
   for (int64_t kb = k0; kb < k1; kb += PK) {
@@ -362,30 +356,8 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
             f32x4{st[pl][u][0], st[pl][u][1], st[pl][u][2], st[pl][u][3]};
     __syncthreads();
     if (kb + PK < k1) load(kb + PK);
-#pragma unroll 4
-    for (int t = 0; t < PK / 2; ++t) {
-      const int kk = 2 * t + lh;
-      float ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        ar[a] = lds[0][kk][64 * wi + 32 * a + lr];
-        ai[a] = lds[1][kk][64 * wi + 32 * a + lr];
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        br[b] = lds[2][kk][64 * wj + 32 * b + lr];
-        bi[b] = lds[3][kk][64 * wj + 32 * b + lr];
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a], br[b], accR[a][b], 0, 0, 0);
-          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[a], bi[b], accR[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a], bi[b], accI[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a], br[b], accI[a][b], 0, 0, 0);
-        }
-    }
+    cmfma::slab(&lds[0][0][0], &lds[1][0][0], &lds[2][0][0], &lds[3][0][0], wi, wj, lane,
+                accR, accI);
   }
 
   double* as = acc + 2 * s * p.cells;
@@ -395,8 +367,8 @@ __global__ __launch_bounds__(256, 2) void jointd_sum_f32(JointDParams p, int tau
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int64_t gr = rt * PT + 64 * wi + 32 * a + 8 * (q >> 2) + 4 * lh + (q & 3);
-        const int gc = ct * PT + 64 * wj + 32 * b + lr;
+        const int64_t gr = rt * PT + cmfma::out_row(wi, a, q, lane);
+        const int gc = ct * PT + cmfma::out_col(wj, b, lane);
         if (gr < nrows && gc < ncols) {
           int j[kJD];
           row_point(p, wp, gr, j);

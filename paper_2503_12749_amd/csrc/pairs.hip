@@ -22,6 +22,7 @@
 // diagonal adds its block and the transposed block.  Every (sub-ensemble,
 // tile) pair has one writer per launch (its workgroup, or pair_reduce over
 // its pieces in a fixed order), so the result does not depend on scheduling.
+#include "cmfma.h"
 #include "common.h"
 
 namespace mp {
@@ -29,7 +30,7 @@ namespace mp {
 namespace {
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
-typedef __attribute__((ext_vector_type(16))) float f32x16;
+using cmfma::f32x16;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
 template <typename CT> struct Vec4;
@@ -118,6 +119,7 @@ __device__ inline void pair_add(const PairParams& p, double* __restrict__ acc, i
 
 constexpr int PT = 128;  // modes per tile side
 constexpr int PK = 32;   // samples per slab
+static_assert(PT == cmfma::kTile && PK == cmfma::kSlab, "tile shape of the shared MFMA core");
 
 // v_mfma_f32_32x32x2f32 with A[i][k] = X[I block row i][sample k] and
 // B[k][j] = X[J block row j][sample k]: lane l supplies A[l % 32][l / 32] and
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
   pair_item(p, I, J, s, pc, k0, k1);
   const bool diag = I == J;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, wj = wave & 1, lr = lane & 31, lh = lane >> 5;
+  const int wi = wave >> 1, wj = wave & 1;
 
   // loader: four consecutive modes of rows lrow + 8 u (u < 4) of each plane
   const int lc = (tid & 31) * 4, lrow = tid >> 5;
@@ -159,15 +161,7 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
   const float* bim = diag ? &lds[1][0][0] : &lds[3][0][0];
 
   f32x16 accR[2][2], accI[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        accR[a][b][r] = 0.f;
-        accI[a][b][r] = 0.f;
-      }
+  cmfma::zero(accR, accI);
 
   load(k0);
   for (int64_t kb = k0; kb < k1; kb += PK) {
@@ -179,30 +173,7 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
         for (int u = 0; u < 4; ++u) *(f32x4*)&lds[pl][lrow + 8 * u][lc] = st[pl][u];
     __syncthreads();
     if (kb + PK < k1) load(kb + PK);
-#pragma unroll 4
-    for (int t = 0; t < PK / 2; ++t) {
-      const int kk = 2 * t + lh;
-      float ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        ar[a] = lds[0][kk][64 * wi + 32 * a + lr];
-        ai[a] = lds[1][kk][64 * wi + 32 * a + lr];
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        br[b] = bre[kk * PT + 64 * wj + 32 * b + lr];
-        bi[b] = bim[kk * PT + 64 * wj + 32 * b + lr];
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a], br[b], accR[a][b], 0, 0, 0);
-          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[a], bi[b], accR[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a], bi[b], accI[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a], br[b], accI[a][b], 0, 0, 0);
-        }
-    }
+    cmfma::slab(&lds[0][0][0], &lds[1][0][0], bre, bim, wi, wj, lane, accR, accI);
   }
 
   if (p.pieces > 1) {
@@ -214,8 +185,8 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = 64 * wi + 32 * a + 8 * (r >> 2) + 4 * lh + (r & 3);
-          const int col = 64 * wj + 32 * b + lr;
+          const int row = cmfma::out_row(wi, a, r, lane);
+          const int col = cmfma::out_col(wj, b, lane);
           typedef __attribute__((ext_vector_type(2))) float f32x2;
           *(f32x2*)(t + 2 * (row * PT + col)) = f32x2{accR[a][b][r], accI[a][b][r]};
         }
@@ -227,8 +198,8 @@ __global__ __launch_bounds__(256, 2) void pair_corr_f32(PairParams p, const floa
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t gi = (int64_t)I * PT + 64 * wi + 32 * a + 8 * (r >> 2) + 4 * lh + (r & 3);
-        const int64_t gj = (int64_t)J * PT + 64 * wj + 32 * b + lr;
+        const int64_t gi = (int64_t)I * PT + cmfma::out_row(wi, a, r, lane);
+        const int64_t gj = (int64_t)J * PT + cmfma::out_col(wj, b, lane);
         pair_add(p, acc, s, gi, gj, !diag, accR[a][b][r], accI[a][b][r]);
       }
 }
