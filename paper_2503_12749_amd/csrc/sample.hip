@@ -16,9 +16,9 @@
 // One wavefront per group of samples: lanes stride over mode pairs, so each
 // sample's column (contiguous over modes) is written with coalesced stores,
 // and n = alpha . beta is reduced across the wave with shuffles.  The FP64
-// path evaluates Box-Muller in FP64; the FP32 and split paths evaluate the
-// angle in FP32 (error ~1e-7 of the radius, at the level of their storage
-// rounding).
+// path evaluates Box-Muller in FP64; the FP32 and split paths evaluate it in
+// FP32 from the exact 53-bit uniforms (radius within a few FP32 ulps, angle
+// error ~1e-7 rad: the level of their storage rounding).
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -69,22 +69,51 @@ __device__ inline void box_muller(uint64_t xe, uint64_t xo, double& w1, double& 
 }
 
 // The same transform for the paths that store FP32 or split 16-bit
-// amplitudes.  The radius takes its logarithm in FP64 (u keeps all 53 bits;
-// in FP32 the rounding of u near 1 would swamp -ln u).  The angle
-// 2 pi v = pi x 2^-52 (x = xo >> 11) is reduced on the integer: its top two
-// bits give the quarter turn q, the other 51 bits the fraction f in [0, 1/2)
-// with angle = q pi/2 + pi f, so the FP32 sincospi sees f to 2^-25 absolute
-// (angle error ~1e-7 rad).
+// amplitudes.  The radius: u = (x + 1) 2^-53 is exact in FP64; with uf = u
+// rounded to FP32 and the residual e = u - uf (|e / uf| <= 2^-24),
+// ln u = ln uf + ln(1 + e / uf) = ln uf + e / uf to FP32 rounding, so -ln u
+// keeps FP32 relative accuracy also near u = 1, where uf alone would round
+// the small logarithm away.  The angle 2 pi v = pi x 2^-52 (x = xo >> 11) is
+// reduced on the integer: its top two bits give the quarter turn q, the other
+// 51 bits the fraction f in [0, 1/2) with angle = q pi/2 + pi f, and f >= 1/4
+// is reflected to g = 1/2 - f (sine and cosine swap), so the polynomials see
+// pi g in [0, pi/4] with g exact to 2^-33 (angle error ~1e-7 rad).
+__device__ inline void sincos_eighth(float t, float& s, float& c) {
+  // Taylor series of sin and cos to t^9 and t^8: on [0, pi/4] the first
+  // omitted terms are below 3e-9 and 4e-10.
+  const float t2 = t * t;
+  float ps = 1.0f / 362880.0f;
+  ps = fmaf(ps, t2, -1.0f / 5040.0f);
+  ps = fmaf(ps, t2, 1.0f / 120.0f);
+  ps = fmaf(ps, t2, -1.0f / 6.0f);
+  ps = fmaf(ps, t2, 1.0f);
+  float pc = 1.0f / 40320.0f;
+  pc = fmaf(pc, t2, -1.0f / 720.0f);
+  pc = fmaf(pc, t2, 1.0f / 24.0f);
+  pc = fmaf(pc, t2, -0.5f);
+  pc = fmaf(pc, t2, 1.0f);
+  s = t * ps;
+  c = pc;
+}
+
 __device__ inline void box_muller_f32(uint64_t xe, uint64_t xo, float& w1, float& w2) {
   const double u = (double)((xe >> 11) + 1ull) * 0x1p-53;
-  const float rho = sqrtf((float)(-2.0 * log(u)));
+  const float uf = (float)u;
+  const float e = (float)(u - (double)uf);
+  const float ln_u = logf(uf) + e * __builtin_amdgcn_rcpf(uf);
+  const float rho = sqrtf(fmaxf(-2.0f * ln_u, 0.0f));
   const uint64_t x = xo >> 11;
   const uint32_t q = (uint32_t)(x >> 51);
-  const float f = (float)(x & ((1ull << 51) - 1ull)) * 0x1p-52f;
+  const uint64_t fx = x & ((1ull << 51) - 1ull);  // f = fx 2^-52
+  const bool upper = (fx >> 50) != 0;              // f >= 1/4
+  const uint64_t gx = upper ? (1ull << 51) - fx : fx;  // g 2^52, at most 2^50
+  constexpr float kPi = 3.14159265358979323846f;
   float s, c;
-  sincospif(f, &s, &c);
-  const float cq = (q & 1u) ? -s : c;  // cos(q pi/2 + pi f) for q = 0, 1
-  const float sq = (q & 1u) ? c : s;
+  sincos_eighth((float)(uint32_t)(gx >> 19) * (0x1p-33f * kPi), s, c);
+  const float sf = upper ? c : s;  // sin(pi f), cos(pi f)
+  const float cf = upper ? s : c;
+  const float cq = (q & 1u) ? -sf : cf;  // cos(q pi/2 + pi f) for q = 0, 1
+  const float sq = (q & 1u) ? cf : sf;
   const float sign = (q & 2u) ? -1.0f : 1.0f;  // q = 2, 3: half a turn more
   w1 = rho * (sign * cq);
   w2 = rho * (sign * sq);

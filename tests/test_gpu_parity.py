@@ -232,11 +232,12 @@ def test_pack_once_then_propagate_matches_propagate(prec):
 
 
 def test_sampler_fp32_matches_oracle():
-    """The FP32 path draws the same noise and evaluates the Box-Muller angle in
-    FP32: each amplitude within 5e-7 of the scale of its terms (FP32 rounding
-    of the coefficients, the radius and the products, plus an angle error of
-    ~1e-7 rad times the radius), and n equal to the sum over the stored
-    values.  E = 261 leaves a ragged group of samples."""
+    """The FP32 path draws the same noise and evaluates the Box-Muller radius
+    and angle in FP32: each amplitude within 5e-7 of the scale of its terms
+    (FP32 rounding of the coefficients and the products, a radius within a few
+    FP32 ulps, an angle error of ~1e-7 rad times the radius), and n equal to
+    the sum over the stored values.  E = 261 leaves a ragged group of
+    samples."""
     import paper_2503_12749_amd as mp
     r = np.concatenate([np.linspace(0.2, 1.5, 139), [0.0]])
     M = r.size
