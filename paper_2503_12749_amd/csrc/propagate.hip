@@ -384,6 +384,15 @@ __device__ inline int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
 
 constexpr int S_BM = 256, S_BN = 256, S_BK = 32;
 constexpr int S_PLANE = S_BM * S_BK;  // elements of one LDS plane
+// LDS of a split tile: two stages of four planes, then a 256-byte sink for the
+// L2 prefetch loads (nothing reads it).  The sink sits in the same array as the
+// stages so that the compiler's wait analysis for direct-to-LDS loads keeps the
+// fragment reads free of extra vmcnt waits.
+constexpr int kSplitLdsElems = 2 * 4 * S_PLANE + 128;
+// The split kernels touch the lines of slab kt + 2 + kPrefetchSlabs while
+// loading slab kt + 2 (measured at M = 8000 on one box: distance 1 takes 3.3 %
+// off the occupation-fused GEMM, 2 takes 2.8 %, 3 or more less).
+constexpr int kPrefetchSlabs = 1;
 
 // Operands reach LDS through gfx950's direct global-to-LDS loads
 // (global_load_lds_dwordx4): lane l of a wave writes the 16 bytes at LDS slot
@@ -486,6 +495,7 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
 // The barrier sits between two MFMA groups, and the LDS reads after it
 // overlap the second group, so neither the barrier nor the LDS latency
 // leaves the matrix pipe idle for a whole fragment round trip.
+// lds points at kSplitLdsElems elements: the two stages and the prefetch sink.
 // FUSED: the tile's rows are the Re rows of modes [m0, m0 + 128) followed by
 // their Im rows, its columns the alpha columns of samples [n0, n0 + 128)
 // followed by their beta columns, and the epilogue is fused_epilogue instead
@@ -533,6 +543,27 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
     }
   };
+  // L2 prefetch of slab k0: one 4-byte direct-to-LDS load per 128-byte line
+  // (one row of the interleaved operand) into the sink after the stages.  The
+  // two waves of an operand split its 256 rows; the rows are clamped as in
+  // issue().  A line that misses the caches then costs its latency here, with
+  // two loads in flight per wave, and the sixteen loads that fill the stage
+  // later hit L2.
+  const uint16_t* pf_src = wave < 2 ? A + m0 * 2 * ldm : B + n0 * 2 * ldm;
+  auto prefetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      int64_t row = 128 * (wave & 1) + 64 * q + lane;
+      if constexpr (FUSED) {
+        const int64_t r = row & 127;
+        row = (r < row_limit ? r : row_limit - 1) + (row >= 128 ? hi_off : 0);
+      } else {
+        row = row < row_limit ? row : row_limit - 1;
+      }
+      const uint16_t* g = pf_src + row * 2 * ldm + 2 * k0;
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)&lds[2][0][0], 4, 0, 0);
+    }
+  };
   int oa[2][4], ob[2][4];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -571,10 +602,14 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
   const int KT = (int)(ldm / S_BK);  // >= 4
+  // Loads return in issue order, so every slab's stage loads are followed by
+  // exactly two prefetch loads and the loop waits for all but those two.
+  for (int p = 2; p <= kPrefetchSlabs; ++p) prefetch((int64_t)min(p, KT - 1) * S_BK);
   issue(0, 0);
   wait_vm<0>();
   barrier_no_fence();
   issue(1, S_BK);
+  prefetch((int64_t)min(1 + kPrefetchSlabs, KT - 1) * S_BK);
   read0(0);
   // scheduling-group masks: MFMA, LDS read, global (direct-to-LDS) load
   constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
@@ -601,8 +636,9 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     }
     __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 0);
     __builtin_amdgcn_sched_barrier(0);
-    // own loads of slab kt + 1 landed, own reads of stage cur complete
-    __builtin_amdgcn_s_waitcnt(0);
+    // own loads of slab kt + 1 landed (only the two prefetch loads issued
+    // after them may be in flight), own reads of stage cur complete
+    __builtin_amdgcn_s_waitcnt(2 | (7 << 4));  // vmcnt(2), lgkmcnt(0)
     barrier_no_fence();
     __builtin_amdgcn_sched_barrier(0);
     // phase B: MFMAs on F1 with the next loads and the reads of F0 threaded in.
@@ -610,6 +646,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     // just freed and the reads fetch unused fragments: both stay in bounds
     // and keep the loop free of branches around the MFMA stream.
     issue(cur, (int64_t)min(kt + 2, KT - 1) * S_BK);
+    prefetch((int64_t)min(kt + 2 + kPrefetchSlabs, KT - 1) * S_BK);
     read0(cur ^ 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -624,7 +661,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bh1[j], acc[i][j]);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 18; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
       __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
     }
@@ -633,10 +670,12 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
       __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
     }
-    __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 1);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 14, 1);
     __builtin_amdgcn_sched_barrier(0);
   }
-  __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
+  // the repeated tail loads and the prefetches land before the epilogue
+  // reuses the stages and before the wave ends
+  __builtin_amdgcn_s_waitcnt(0);
   if constexpr (FUSED) {
     fused_epilogue(acc, (float*)&lds[0][0][0], *fo, m0, n0, wm, wn, lane, out_scale);
     return;
@@ -664,7 +703,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
                                                                  float* __restrict__ C,
                                                                  int64_t ldm, int64_t ncols,
                                                                  float out_scale, int order) {
-  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  __shared__ __attribute__((aligned(1024))) uint16_t lds_raw[kSplitLdsElems];
+  uint16_t (*lds)[4][S_PLANE] = (uint16_t (*)[4][S_PLANE])lds_raw;
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
   if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
@@ -680,7 +720,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __
                                                               int64_t ldm, int64_t ncols,
                                                               float out_scale, int order,
                                                               FusedOut fo) {
-  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  __shared__ __attribute__((aligned(1024))) uint16_t lds_raw[kSplitLdsElems];
+  uint16_t (*lds)[4][S_PLANE] = (uint16_t (*)[4][S_PLANE])lds_raw;
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
   if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
@@ -874,7 +915,8 @@ template <typename H>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet* __restrict__ nets,
                                                                   const int4* __restrict__ items,
                                                                   int n_items) {
-  __shared__ __attribute__((aligned(1024))) uint16_t lds[2][4][S_PLANE];
+  __shared__ __attribute__((aligned(1024))) uint16_t lds_raw[kSplitLdsElems];
+  uint16_t (*lds)[4][S_PLANE] = (uint16_t (*)[4][S_PLANE])lds_raw;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 w = items[it];  // (net, tile_m, tile_n, unused); net < 0: idle slot
     if (w.x < 0) continue;
