@@ -32,7 +32,8 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
                              const void* ab, void* C, hipStream_t stream);
 mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
-                         mp_precision prec, hipStream_t stream);
+                         mp_precision prec, bool prefetch, hipStream_t stream);
+bool split_prefetch(int64_t ldm);
 size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
                         int64_t ns, int64_t e0);
 mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double* n,
@@ -246,8 +247,10 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
       }
     }
     if (split(p->prec)) {
+      bool prefetch = true;  // the L2 prefetch unless some network's stride aliases
+      for (const PlanNet& n : p->nets) prefetch = prefetch && split_prefetch(n.ldm);
       if ((st = grouped_launch(p->d_nets[pass], p->d_items[pass], p->n_items[pass], p->grid,
-                               p->prec, p->stream)) != MP_OK)
+                               p->prec, prefetch, p->stream)) != MP_OK)
         return st;
     } else {
       for (PlanNet& n : p->nets) {

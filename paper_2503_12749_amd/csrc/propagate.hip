@@ -391,8 +391,16 @@ constexpr int S_PLANE = S_BM * S_BK;  // elements of one LDS plane
 constexpr int kSplitLdsElems = 2 * 4 * S_PLANE + 128;
 // The split kernels touch the lines of slab kt + 2 + kPrefetchSlabs while
 // loading slab kt + 2 (measured at M = 8000 on one box: distance 1 takes 3.3 %
-// off the occupation-fused GEMM, 2 takes 2.8 %, 3 or more less).
+// off the occupation-fused GEMM, 2 takes 2.8 %, 3 or more less).  When the
+// operand rows are a multiple of 32 KB apart (ldm a multiple of 8192) the
+// prefetch slowed the GEMM instead (M = 8192: +4.7 %, 16384: +3.9 %; 12288 and
+// every other size measured from 2048 to 10240 gained 1-5 %; a prefetch reduced
+// to one line already in flight still cost 2 %), so those sizes run the loop
+// without it (the PF = false instances).
 constexpr int kPrefetchSlabs = 1;
+constexpr int64_t kPrefetchAliasModes = 8192;
+
+__host__ __device__ inline bool split_prefetch_for(int64_t ldm) { return ldm % kPrefetchAliasModes != 0; }
 
 // Operands reach LDS through gfx950's direct global-to-LDS loads
 // (global_load_lds_dwordx4): lane l of a wave writes the 16 bytes at LDS slot
@@ -496,11 +504,13 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
 // overlap the second group, so neither the barrier nor the LDS latency
 // leaves the matrix pipe idle for a whole fragment round trip.
 // lds points at kSplitLdsElems elements: the two stages and the prefetch sink.
+// PF: touch the lines of the slab after the one being loaded (see
+// kPrefetchSlabs); without it the loop waits for all its loads at each slab.
 // FUSED: the tile's rows are the Re rows of modes [m0, m0 + 128) followed by
 // their Im rows, its columns the alpha columns of samples [n0, n0 + 128)
 // followed by their beta columns, and the epilogue is fused_epilogue instead
 // of the store of C.
-template <typename H, bool FUSED>
+template <typename H, bool FUSED, bool PF>
 __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
                                      const uint16_t* __restrict__ B, float* __restrict__ C,
                                      int64_t ldm, int64_t ncols, int64_t m0, int64_t n0,
@@ -551,6 +561,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
   // later hit L2.
   const uint16_t* pf_src = wave < 2 ? A + m0 * 2 * ldm : B + n0 * 2 * ldm;
   auto prefetch = [&](int64_t k0) {
+    if constexpr (!PF) return;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       int64_t row = 128 * (wave & 1) + 64 * q + lane;
@@ -602,8 +613,9 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
   const int KT = (int)(ldm / S_BK);  // >= 4
-  // Loads return in issue order, so every slab's stage loads are followed by
-  // exactly two prefetch loads and the loop waits for all but those two.
+  // Loads return in issue order, so with PF every slab's stage loads are
+  // followed by exactly two prefetch loads and the loop waits for all but
+  // those two.
   for (int p = 2; p <= kPrefetchSlabs; ++p) prefetch((int64_t)min(p, KT - 1) * S_BK);
   issue(0, 0);
   wait_vm<0>();
@@ -636,9 +648,12 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     }
     __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 0);
     __builtin_amdgcn_sched_barrier(0);
-    // own loads of slab kt + 1 landed (only the two prefetch loads issued
-    // after them may be in flight), own reads of stage cur complete
-    __builtin_amdgcn_s_waitcnt(2 | (7 << 4));  // vmcnt(2), lgkmcnt(0)
+    // own loads of slab kt + 1 landed (with PF only the two prefetch loads
+    // issued after them may be in flight), own reads of stage cur complete
+    if constexpr (PF)
+      __builtin_amdgcn_s_waitcnt(2 | (7 << 4));  // vmcnt(2), lgkmcnt(0)
+    else
+      __builtin_amdgcn_s_waitcnt(0);
     barrier_no_fence();
     __builtin_amdgcn_sched_barrier(0);
     // phase B: MFMAs on F1 with the next loads and the reads of F0 threaded in.
@@ -660,8 +675,9 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bh1[j], acc[i][j]);
+    constexpr int kVmem = PF ? 18 : 16;
 #pragma unroll
-    for (int q = 0; q < 18; ++q) {
+    for (int q = 0; q < kVmem; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
       __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
     }
@@ -670,7 +686,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
       __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
     }
-    __builtin_amdgcn_sched_group_barrier(kSgMfma, 14, 1);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 48 - 16 - kVmem, 1);
     __builtin_amdgcn_sched_barrier(0);
   }
   // the repeated tail loads and the prefetches land before the epilogue
@@ -697,7 +713,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
   }
 }
 
-template <typename H>
+template <typename H, bool PF>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t* __restrict__ A,
                                                                  const uint16_t* __restrict__ B,
                                                                  float* __restrict__ C,
@@ -708,13 +724,13 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
   if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  split_pp_tile<H, false>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN,
-                          out_scale, nullptr);
+  split_pp_tile<H, false, PF>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN,
+                              out_scale, nullptr);
 }
 
 // Occupation-fused twin of gemm_split_256_pp: tile (tm, tn) covers modes
 // [128 tm, 128 tm + 128) and samples [128 tn, 128 tn + 128); no C is written.
-template <typename H>
+template <typename H, bool PF>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __restrict__ A,
                                                               const uint16_t* __restrict__ B,
                                                               int64_t ldm, int64_t ncols,
@@ -725,8 +741,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
   if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  split_pp_tile<H, true>(lds, A, B, nullptr, ldm, ncols, (int64_t)tm * 128, (int64_t)tn * 128,
-                         out_scale, &fo);
+  split_pp_tile<H, true, PF>(lds, A, B, nullptr, ldm, ncols, (int64_t)tm * 128, (int64_t)tn * 128,
+                             out_scale, &fo);
 }
 
 // ---------------------------------------------------------------- FP32, 256 x 256
@@ -911,7 +927,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
 // ordered so that the items an XCD processes at the same time are
 // neighbouring tiles of one network.
 
-template <typename H>
+template <typename H, bool PF>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet* __restrict__ nets,
                                                                   const int4* __restrict__ items,
                                                                   int n_items) {
@@ -921,7 +937,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet
     const int4 w = items[it];  // (net, tile_m, tile_n, unused); net < 0: idle slot
     if (w.x < 0) continue;
     const GroupNet g = nets[w.x];
-    split_pp_tile<H, false>(lds, g.A, g.B, g.C, g.ldm, g.ncols, (int64_t)w.y * S_BM,
+    split_pp_tile<H, false, PF>(lds, g.A, g.B, g.C, g.ldm, g.ncols, (int64_t)w.y * S_BM,
                             (int64_t)w.z * S_BN, g.out_scale, nullptr);
     __syncthreads();  // the next item reuses the LDS stages
   }
@@ -1001,10 +1017,12 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
 template <typename H>
 static void split_gemm(int grid, hipStream_t stream, const void* packed, const void* ab, void* C,
                        int64_t ldm, int64_t ncols, float scale) {
-  hipLaunchKernelGGL(gemm_split_256_pp<H>, dim3(grid), dim3(kThreads), 0, stream,
-                     (const uint16_t*)packed, (const uint16_t*)ab, (float*)C, ldm, ncols, scale,
-                     tile_order());
+  auto kernel = split_prefetch_for(ldm) ? gemm_split_256_pp<H, true> : gemm_split_256_pp<H, false>;
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
+                     (const uint16_t*)ab, (float*)C, ldm, ncols, scale, tile_order());
 }
+
+bool split_prefetch(int64_t ldm) { return split_prefetch_for(ldm); }
 
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
                              const void* ab, void* C, hipStream_t stream) {
@@ -1038,14 +1056,14 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
 }
 
 mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
-                         mp_precision prec, hipStream_t stream) {
-  if (prec == MP_SPLIT_BF16)
-    hipLaunchKernelGGL(gemm_split_grouped<__bf16>, dim3(grid), dim3(kThreads), 0, stream, d_nets,
-                       d_items, n_items);
-  else if (prec == MP_SPLIT_FP16)
-    hipLaunchKernelGGL(gemm_split_grouped<_Float16>, dim3(grid), dim3(kThreads), 0, stream, d_nets,
-                       d_items, n_items);
-  else {
+                         mp_precision prec, bool prefetch, hipStream_t stream) {
+  if (prec == MP_SPLIT_BF16) {
+    auto kernel = prefetch ? gemm_split_grouped<__bf16, true> : gemm_split_grouped<__bf16, false>;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
+  } else if (prec == MP_SPLIT_FP16) {
+    auto kernel = prefetch ? gemm_split_grouped<_Float16, true> : gemm_split_grouped<_Float16, false>;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
+  } else {
     set_error("grouped GEMM: split precisions only");
     return MP_ERR_UNSUPPORTED;
   }
@@ -1064,16 +1082,20 @@ mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precisi
                          (const float*)packed, (const float*)ab, (float*)nullptr, ldm, ncols,
                          tile_order(), fo);
       break;
-    case MP_SPLIT_BF16:
-      hipLaunchKernelGGL(gemm_split_occ<__bf16>, dim3(grid), dim3(kThreads), 0, stream,
-                         (const uint16_t*)packed, (const uint16_t*)ab, ldm, ncols, 1.0f,
+    case MP_SPLIT_BF16: {
+      auto kernel = split_prefetch_for(ldm) ? gemm_split_occ<__bf16, true> : gemm_split_occ<__bf16, false>;
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
+                         (const uint16_t*)ab, ldm, ncols, 1.0f, tile_order(), fo);
+      break;
+    }
+    case MP_SPLIT_FP16: {
+      auto kernel =
+          split_prefetch_for(ldm) ? gemm_split_occ<_Float16, true> : gemm_split_occ<_Float16, false>;
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
+                         (const uint16_t*)ab, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)),
                          tile_order(), fo);
       break;
-    case MP_SPLIT_FP16:
-      hipLaunchKernelGGL(gemm_split_occ<_Float16>, dim3(grid), dim3(kThreads), 0, stream,
-                         (const uint16_t*)packed, (const uint16_t*)ab, ldm, ncols,
-                         ldexpf(1.0f, -fp16_scale_exp(M)), tile_order(), fo);
-      break;
+    }
     default:
       set_error("mp_propagate_counts: the fused path supports FP32 and the split precisions");
       return MP_ERR_UNSUPPORTED;

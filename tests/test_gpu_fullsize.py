@@ -206,3 +206,44 @@ def test_m1000_full_run_total_joint_consistency():
     err0 = np.abs(P0 - ref["P"])
     print(f"m1000 sub-ensemble 0: max |dP| = {err0.max():.2e}, sd of one sub-ensemble {s_ref.max():.2e}")
     assert np.all(err0 <= 0.02 * s_ref + 1e-7 * ref["P"].max())
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_m8192_row_stride_without_prefetch(prec):
+    """M = 8192: the operand rows lie a multiple of 32 KB apart, where the
+    split kernels run their loop without the L2 prefetch.  T = t F D with F
+    the unitary DFT matrix and D random phases (dense and unitary, cheap to
+    build); one ragged chunk of E = 600 samples.  Sampled columns against the
+    oracle, then the occupation-fused run against the unfused one on the same
+    noise."""
+    import types
+    import paper_2503_12749_amd as mp
+    M, t, E, n_sub = 8192, 0.9, 600, 2
+    assert mp.mp_ld_modes(M) % 8192 == 0
+    rng = np.random.default_rng(8192)
+    j = np.arange(M)
+    T = (t / np.sqrt(M)) * np.exp(-2j * np.pi * (np.outer(j, j) % M) / M)
+    T *= np.exp(2j * np.pi * rng.random(M))[None, :]
+    r = np.full(M, 0.5)
+    mean, sd = synth.uniform_loss_moments(r, t)
+    win = synth.count_window(mean, sd)
+    w = types.SimpleNamespace(M=M, t=t, T=T, r=r, seed=31)
+    p = mp.CountsPipeline(T, r, prec=prec, seed=w.seed, windows=[win], n_sub=n_sub,
+                          samples_per_sub=E // n_sub, chunk=E, device="cuda:0")
+    mp.mp_sample(M, 0, E, p.r, w.seed, 0, prec, p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, prec, p.ab, p.C, p.ws_prop)
+    cols = [0, 1, 255, 256, 299, 300, 511, E - 1]
+    worst = _sampled_columns(p, w, 0, E, cols)
+    print(f"{prec} M=8192: worst sampled column error {worst:.2e}")
+    assert worst < REL[prec]
+    _release(p)
+    out = []
+    for fused in (True, False):
+        q = mp.CountsPipeline(T, r, prec=prec, seed=w.seed, windows=[win], n_sub=n_sub,
+                              samples_per_sub=E // n_sub, chunk=E, device="cuda:0", fused=fused)
+        q.run()
+        out.append(q.result())
+        _release(q)
+    (Pf, _, sf), (Pu, _, su) = out
+    assert abs(Pf.sum() - 1) < 1e-8
+    assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-7 * Pu.max()), np.abs(Pf - Pu).max()
