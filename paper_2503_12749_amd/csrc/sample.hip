@@ -16,9 +16,10 @@
 // One wavefront per group of samples: lanes stride over mode pairs, so each
 // sample's column (contiguous over modes) is written with coalesced stores,
 // and n = alpha . beta is reduced across the wave with shuffles.  The FP64
-// path evaluates Box-Muller in FP64; the FP32 and split paths evaluate it in
-// FP32 from the exact 53-bit uniforms (radius within a few FP32 ulps, angle
-// error ~1e-7 rad: the level of their storage rounding).
+// path evaluates Box-Muller with the library's FP64 log and sincos; the FP32
+// and split paths evaluate it by short FP64 series and round the radius and
+// the angle's sine and cosine to FP32 once (no systematic error beyond that
+// rounding).
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -69,49 +70,77 @@ __device__ inline void box_muller(uint64_t xe, uint64_t xo, double& w1, double& 
 }
 
 // The same transform for the paths that store FP32 or split 16-bit
-// amplitudes.  The radius: u = (x + 1) 2^-53 is exact in FP64; with uf = u
-// rounded to FP32 and the residual e = u - uf (|e / uf| <= 2^-24),
-// ln u = ln uf + ln(1 + e / uf) = ln uf + e / uf to FP32 rounding, so -ln u
-// keeps FP32 relative accuracy also near u = 1, where uf alone would round
-// the small logarithm away.  The angle 2 pi v = pi x 2^-52 (x = xo >> 11) is
-// reduced on the integer: its top two bits give the quarter turn q, the other
-// 51 bits the fraction f in [0, 1/2) with angle = q pi/2 + pi f, and f >= 1/4
-// is reflected to g = 1/2 - f (sine and cosine swap), so the polynomials see
-// pi g in [0, pi/4] with g exact to 2^-33 (angle error ~1e-7 rad).
-__device__ inline void sincos_eighth(float t, float& s, float& c) {
-  // Taylor series of sin and cos to t^9 and t^8: on [0, pi/4] the first
-  // omitted terms are below 3e-9 and 4e-10.
-  const float t2 = t * t;
-  float ps = 1.0f / 362880.0f;
-  ps = fmaf(ps, t2, -1.0f / 5040.0f);
-  ps = fmaf(ps, t2, 1.0f / 120.0f);
-  ps = fmaf(ps, t2, -1.0f / 6.0f);
-  ps = fmaf(ps, t2, 1.0f);
-  float pc = 1.0f / 40320.0f;
-  pc = fmaf(pc, t2, -1.0f / 720.0f);
-  pc = fmaf(pc, t2, 1.0f / 24.0f);
-  pc = fmaf(pc, t2, -0.5f);
-  pc = fmaf(pc, t2, 1.0f);
+// amplitudes.  Both parts are evaluated in FP64 by short series and rounded to
+// FP32 once, so the amplitudes carry only that rounding: a library FP32
+// logarithm was measured to bias -ln u by about +4e-8 on average, which biases
+// every photon number the same way (the radius) and does not average out.
+//   radius: u = m 2^k with m in [sqrt(1/2), sqrt(2)), s = (m - 1) / (m + 1)
+//     (|s| <= 0.172), ln m = 2 atanh s = 2 s (1 + s^2/3 + ... + s^12/13),
+//     the first omitted term below 1.3e-12 relative;
+//   angle: 2 pi v = pi x 2^-52 (x = xo >> 11); the top two bits of x give the
+//     quarter turn q, the other 51 the fraction f in [0, 1/2) with
+//     angle = q pi/2 + pi f, and f >= 1/4 is reflected to g = 1/2 - f (sine
+//     and cosine swap), exactly on the integer; sin and cos of pi g in
+//     [0, pi/4] from their Taylor series to t^13 and t^12 (first omitted terms
+//     below 3e-14 and 4e-13).
+__device__ inline double neg_log_unit(double u) {
+  int k;
+  double m = frexp(u, &k);  // u = m 2^k, m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    k -= 1;
+  }
+  // s = (m - 1) / (m + 1): hardware reciprocal refined by two Newton steps
+  const double d = m + 1.0;
+  double rd = __builtin_amdgcn_rcp(d);
+  rd = fma(rd, fma(-d, rd, 1.0), rd);
+  rd = fma(rd, fma(-d, rd, 1.0), rd);
+  const double s = (m - 1.0) * rd;
+  const double s2 = s * s;
+  double p = 1.0 / 13.0;
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, 1.0);
+  constexpr double kLn2 = 0.69314718055994530942;
+  return -fma((double)k, kLn2, 2.0 * s * p);
+}
+
+__device__ inline void sincos_eighth(double t, double& s, double& c) {
+  const double t2 = t * t;
+  double ps = 1.0 / 6227020800.0;  // 1/13!
+  ps = fma(ps, t2, -1.0 / 39916800.0);
+  ps = fma(ps, t2, 1.0 / 362880.0);
+  ps = fma(ps, t2, -1.0 / 5040.0);
+  ps = fma(ps, t2, 1.0 / 120.0);
+  ps = fma(ps, t2, -1.0 / 6.0);
+  ps = fma(ps, t2, 1.0);
+  double pc = 1.0 / 479001600.0;  // 1/12!
+  pc = fma(pc, t2, -1.0 / 3628800.0);
+  pc = fma(pc, t2, 1.0 / 40320.0);
+  pc = fma(pc, t2, -1.0 / 720.0);
+  pc = fma(pc, t2, 1.0 / 24.0);
+  pc = fma(pc, t2, -0.5);
+  pc = fma(pc, t2, 1.0);
   s = t * ps;
   c = pc;
 }
 
 __device__ inline void box_muller_f32(uint64_t xe, uint64_t xo, float& w1, float& w2) {
   const double u = (double)((xe >> 11) + 1ull) * 0x1p-53;
-  const float uf = (float)u;
-  const float e = (float)(u - (double)uf);
-  const float ln_u = logf(uf) + e * __builtin_amdgcn_rcpf(uf);
-  const float rho = sqrtf(fmaxf(-2.0f * ln_u, 0.0f));
+  const float rho = sqrtf((float)(2.0 * neg_log_unit(u)));  // two unbiased roundings
   const uint64_t x = xo >> 11;
   const uint32_t q = (uint32_t)(x >> 51);
   const uint64_t fx = x & ((1ull << 51) - 1ull);  // f = fx 2^-52
   const bool upper = (fx >> 50) != 0;              // f >= 1/4
-  const uint64_t gx = upper ? (1ull << 51) - fx : fx;  // g 2^52, at most 2^50
-  constexpr float kPi = 3.14159265358979323846f;
-  float s, c;
-  sincos_eighth((float)(uint32_t)(gx >> 19) * (0x1p-33f * kPi), s, c);
-  const float sf = upper ? c : s;  // sin(pi f), cos(pi f)
-  const float cf = upper ? s : c;
+  const uint64_t gx = upper ? (1ull << 51) - fx : fx;  // g 2^52, at most 2^50: exact in FP64
+  constexpr double kPi = 3.14159265358979323846;
+  double s, c;
+  sincos_eighth((double)gx * (0x1p-52 * kPi), s, c);
+  const float sf = (float)(upper ? c : s);  // sin(pi f), cos(pi f)
+  const float cf = (float)(upper ? s : c);
   const float cq = (q & 1u) ? -sf : cf;  // cos(q pi/2 + pi f) for q = 0, 1
   const float sq = (q & 1u) ? cf : sf;
   const float sign = (q & 2u) ? -1.0f : 1.0f;  // q = 2, 3: half a turn more
