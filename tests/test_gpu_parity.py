@@ -258,6 +258,40 @@ def test_sampler_fp32_matches_oracle():
     np.testing.assert_allclose(n_gpu, (a_gpu * b_gpu).sum(1), rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_sampler_rounding_unbiased(prec):
+    """The FP32 and split samplers round the FP64 Box-Muller values once, so
+    on the same noise their mean of alpha^2, beta^2 and n = alpha beta over
+    M = 4000 modes x 16384 samples equals the FP64 sampler's (itself equal to
+    the oracle's to 1e-14) to 1e-8 relative.  Rounding errors average to
+    ~1e-11 here; what remains is the FP32 rounding of the per-mode
+    coefficients (~1e-9).  A biased FP32 logarithm in the radius moved these
+    means by 3.7e-8."""
+    import paper_2503_12749_amd as mp
+    M, E, seed = 4000, 16384, 1234
+    r = np.random.default_rng(5).uniform(0.5, 1.5, M)
+    ldm = mp.mp_ld_modes(M)
+    rd = torch.tensor(r, dtype=torch.float64, device="cuda:0")
+    sums = {}
+    for pr in ("fp64", prec):
+        ab = torch.empty(mp.mp_ab_bytes(M, E, pr), dtype=torch.uint8, device="cuda:0")
+        n = torch.empty(E, dtype=torch.float64, device="cuda:0")
+        mp.mp_sample(M, 0, E, rd, seed, 0, pr, ab, n)
+        if pr == "split_bf16":
+            v = ab.view(torch.int16)[: 2 * ldm * 2 * E].reshape(2 * E, ldm // 32, 2, 32)
+            hi = (v[:, :, 0, :].to(torch.int32) << 16).view(torch.float32).double()
+            lo = (v[:, :, 1, :].to(torch.int32) << 16).view(torch.float32).double()
+            v = (hi + lo).reshape(2 * E, ldm)[:, :M]
+        else:
+            dt = torch.float64 if pr == "fp64" else torch.float32
+            v = ab.view(dt)[: ldm * 2 * E].reshape(2 * E, ldm)[:, :M].double()
+        a, b = v[:E], v[E:]
+        sums[pr] = ((a * a).sum().item(), (b * b).sum().item(), n.sum().item())
+        del ab, n, v, a, b
+    for got, ref in zip(sums[prec], sums["fp64"]):
+        assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref, (got - ref) / ref)
+
+
 @pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6), ("split_fp16", 1e-6)])
 def test_reduced_precision_counts_within_sigma(prec, floor):
     """M = 300, t = 0.9, r = 1: the reduced-precision estimate differs from the
