@@ -372,9 +372,9 @@ def run_precision_m4000(args, mp, torch, synth):
 def run_batched(args, mp, torch, synth):
     """16 networks (4 each of M = 500, 1000, 2000, 4000), t ~ U[0.85, 0.99],
     r = 1, E = 2e5 each (20 sub-ensembles of 1e4), split-FP16: one plan (a
-    captured hipGraph with one persistent grouped GEMM launch per pass over
-    chunks of 1e5) against the same networks run one after another through
-    CountsPipeline."""
+    captured hipGraph with one persistent grouped GEMM launch with the
+    occupation-fused epilogue per pass over chunks of 1e5) against the same
+    networks run one after another through the fused CountsPipeline."""
     rng = np.random.default_rng(synth.SEED_BASE + 7)
     Ms = [500] * 4 + [1000] * 4 + [2000] * 4 + [4000] * 4
     E, n_sub, chunk = 200_000, 20, 100_000
@@ -397,7 +397,7 @@ def run_batched(args, mp, torch, synth):
     for i, n in enumerate(nets):
         p = mp.CountsPipeline(n["T"], n["r"], prec="split_fp16", seed=n["seed"], net=n["net"],
                               windows=[n["window"]], n_sub=n_sub, samples_per_sub=E // n_sub,
-                              chunk=chunk)
+                              chunk=chunk, fused=True)
         p.run()
 
         def job():

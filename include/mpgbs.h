@@ -415,10 +415,15 @@ typedef struct {
  * grouped-GEMM work-list order with a timing autotuner (cached in the JSON
  * file `tune_cache` when it is not NULL), and captures the whole pass in a
  * hipGraph: accumulators cleared by fill kernels, sampling, ONE persistent
- * grouped split-precision GEMM launch over all networks' tiles per pass (FP64
- * and FP32 plans launch one GEMM per network instead), counts and inverse
- * DFT per network.  E must be <= chunk or a multiple of it; each pass covers
- * `chunk` samples of every network.  Synchronous; not thread-safe per plan.
+ * grouped split-precision GEMM launch over all networks' tiles per pass with
+ * the occupation-fused epilogue of mp_propagate_counts (FP32 plans run
+ * mp_propagate_counts per network, FP64 plans one GEMM writing C and the
+ * counts from it per network), counts from the per-block occupation partials
+ * and inverse DFT per network; only FP64 plans hold a propagated-amplitude
+ * buffer C.  Results equal those of mp_propagate_counts (FP32, split) or
+ * mp_propagate + mp_binned_counts (FP64) on the same noise, bit for bit.
+ * E must be <= chunk or a multiple of it; each pass covers `chunk` samples of
+ * every network.  Synchronous; not thread-safe per plan.
  */
 mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets,
                          mp_precision prec, mp_estimator est, int64_t chunk,

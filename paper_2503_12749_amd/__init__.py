@@ -412,8 +412,8 @@ def _hip_runtime():
 
 class Plan:
     """Batched plan over many networks (mp_plan_create / mp_plan_launch):
-    one captured hipGraph per plan, one persistent grouped GEMM launch per
-    pass.  `nets` is a list of dicts with keys T (complex numpy M x M), r,
+    one captured hipGraph per plan, one persistent grouped GEMM launch with
+    the occupation-fused epilogue per pass (split precisions).  `nets` is a list of dicts with keys T (complex numpy M x M), r,
     seed, net, E, n_sub, window=(m_lo, K)."""
 
     def __init__(self, nets, *, prec="split_fp16", est="matrix_p", chunk=None, tune_cache=None,

@@ -35,15 +35,6 @@ void clear_error();
 
 constexpr int kLdAlign = 128;  // mode padding (GEMM tile multiple)
 
-// One network of a grouped split-precision GEMM launch.
-struct GroupNet {
-  const uint16_t* A;  // packed [Re T; Im T], hi and lo interleaved in 32-blocks
-  const uint16_t* B;  // sampled amplitudes, hi and lo interleaved in 32-blocks
-  float* C;
-  int64_t ldm, ncols;
-  float out_scale;
-};
-
 // Output of the occupation-fused GEMM: per (slot, sample) the partial sums of
 // alpha'_j beta'_j over the modes of one bin run inside one 128-mode block.
 // Run q owns the slots slot_off[q] + (block - run_lo[q] / 128) for the blocks
@@ -55,6 +46,16 @@ struct FusedOut {
   int64_t E;
   int n_runs;
   int run_lo[MP_MAX_RUNS], run_hi[MP_MAX_RUNS], slot_off[MP_MAX_RUNS];
+};
+
+// One network of a grouped split-precision GEMM launch.
+struct GroupNet {
+  const uint16_t* A;  // packed [Re T; Im T], hi and lo interleaved in 32-blocks
+  const uint16_t* B;  // sampled amplitudes, hi and lo interleaved in 32-blocks
+  float* C;
+  int64_t ldm, ncols;
+  float out_scale;
+  FusedOut fo;  // the occupation-fused epilogue's output (C unused then)
 };
 
 // Slots of the fused partials for a set of runs; fills slot_off and returns

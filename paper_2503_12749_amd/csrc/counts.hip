@@ -796,12 +796,13 @@ size_t propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t
   return total;
 }
 
-mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
-                                  const void* ab, const double* n, const void* packed, int32_t d,
-                                  const int32_t* bin_of_mode, mp_bin_mode mode,
-                                  const int32_t* m_lo, const int32_t* K, int32_t n_sub,
-                                  int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
-                                  hipStream_t stream) {
+// The occupation-fused GEMM's output description for a chunk of E samples:
+// the runs of the bin partition, their slots, and the partials at the start of
+// ws (the counts kernel's per-block partials follow them).
+mp_status fused_out_setup(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                          mp_bin_mode mode, const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                          int64_t ns, int64_t e0, mp_estimator est, void* ws, size_t ws_bytes,
+                          FusedOut& fo) {
   MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
                "mp_propagate_counts: joint distributions of several bins are not fused (d = %d)",
                d);
@@ -814,7 +815,7 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
   propagate_counts_sizes(p, blocks, part_bytes, total);
   MP_CHECK_ARG(ws && ws_bytes >= total, MP_ERR_WORKSPACE,
                "mp_propagate_counts: workspace of %zu bytes needed, %zu given", total, ws_bytes);
-  FusedOut fo{};
+  fo = FusedOut{};
   fo.part = (float*)ws;
   fo.E = E;
   fo.n_runs = p.n_runs;
@@ -823,19 +824,50 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
     fo.run_hi[q] = p.run_hi[q];
   }
   fused_slots(p.n_runs, fo.run_lo, fo.run_hi, fo.slot_off);
+  return MP_OK;
+}
+
+// Counts from the partials an occupation-fused GEMM left at the start of ws
+// (laid out by fused_out_setup with the same arguments).
+mp_status counts_from_partials_launch(int32_t M, int64_t E, const double* n, mp_estimator est,
+                                      int32_t d, const int32_t* bin_of_mode, mp_bin_mode mode,
+                                      const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                      int64_t ns, int64_t e0, double* acc, void* ws,
+                                      size_t ws_bytes, hipStream_t stream) {
+  CountsParams p{};
+  int64_t blocks = 0;
+  const mp_status st = setup_counts(p, "mp_propagate_counts", M, E, d, bin_of_mode, mode, m_lo, K,
+                                    n_sub, ns, e0, est, blocks);
+  if (st != MP_OK) return st;
+  size_t part_bytes, total;
+  propagate_counts_sizes(p, blocks, part_bytes, total);
+  MP_CHECK_ARG(ws && ws_bytes >= total, MP_ERR_WORKSPACE,
+               "mp_propagate_counts: workspace of %zu bytes needed, %zu given", total, ws_bytes);
   double* blk = (double*)((char*)ws + part_bytes);
-  if (p.n_runs > 0) {
-    const mp_status sg = gemm_fused_launch(M, E, packed, prec, ab, fo, stream);
-    if (sg != MP_OK) return sg;
-  }
   hipLaunchKernelGGL((counts_fused<FromPartials, false>), dim3((unsigned)blocks),
-                     dim3(kCountThreads), 0, stream, p, FromPartials{fo.part}, n, blk);
+                     dim3(kCountThreads), 0, stream, p, FromPartials{(const float*)ws}, n, blk);
   MP_HIP_LAUNCH_CHECK("mp_propagate_counts counts launch");
   const int ns_touched = (int)(p.s_last - p.s_first + 1);
   hipLaunchKernelGGL(counts_reduce, dim3((p.entries + 255) / 256, ns_touched), dim3(256), 0, stream,
                      p, (const double*)blk, acc);
   MP_HIP_LAUNCH_CHECK("mp_propagate_counts reduce launch");
   return MP_OK;
+}
+
+mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                                  const void* ab, const double* n, const void* packed, int32_t d,
+                                  const int32_t* bin_of_mode, mp_bin_mode mode,
+                                  const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                  int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  FusedOut fo;
+  mp_status st = fused_out_setup(M, E, d, bin_of_mode, mode, m_lo, K, n_sub, ns, e0, est, ws,
+                                 ws_bytes, fo);
+  if (st != MP_OK) return st;
+  if (fo.n_runs > 0 && (st = gemm_fused_launch(M, E, packed, prec, ab, fo, stream)) != MP_OK)
+    return st;
+  return counts_from_partials_launch(M, E, n, est, d, bin_of_mode, mode, m_lo, K, n_sub, ns, e0,
+                                     acc, ws, ws_bytes, stream);
 }
 
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,

@@ -32,7 +32,25 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
                              const void* ab, void* C, hipStream_t stream);
 mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
-                         mp_precision prec, bool prefetch, hipStream_t stream);
+                         mp_precision prec, bool prefetch, bool fused, hipStream_t stream);
+size_t propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                                  mp_bin_mode mode, const int32_t* K, int32_t n_sub, int64_t ns,
+                                  int64_t e0);
+mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                                  const void* ab, const double* n, const void* packed, int32_t d,
+                                  const int32_t* bin_of_mode, mp_bin_mode mode,
+                                  const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                  int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+mp_status fused_out_setup(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
+                          mp_bin_mode mode, const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                          int64_t ns, int64_t e0, mp_estimator est, void* ws, size_t ws_bytes,
+                          FusedOut& fo);
+mp_status counts_from_partials_launch(int32_t M, int64_t E, const double* n, mp_estimator est,
+                                      int32_t d, const int32_t* bin_of_mode, mp_bin_mode mode,
+                                      const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                      int64_t ns, int64_t e0, double* acc, void* ws,
+                                      size_t ws_bytes, hipStream_t stream);
 bool split_prefetch(int64_t ldm);
 size_t binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_t E, int32_t n_sub,
                         int64_t ns, int64_t e0);
@@ -64,9 +82,9 @@ struct PlanNet {
   double* P_im = nullptr;
   double* sigma = nullptr;
   void* ab = nullptr;
-  void* C = nullptr;
+  void* C = nullptr;  // FP64 plans only; the others never materialise C
   void* packed = nullptr;
-  void* ws_counts = nullptr;
+  void* ws_counts = nullptr;  // FP64: counts partials; else fused partials + counts partials
   size_t ws_counts_bytes = 0;
   std::vector<int32_t> bins;
 };
@@ -226,6 +244,8 @@ static mp_status upload_items(Plan* p, int order) {
 }
 
 static bool split(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16; }
+// Every precision but FP64 runs the occupation-fused GEMM epilogue.
+static bool fused(mp_precision p) { return p != MP_FP64; }
 
 // Enqueues one full pass of every network on the plan stream.
 static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
@@ -247,24 +267,40 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
       }
     }
     if (split(p->prec)) {
+      // one grouped launch with the occupation epilogue, then counts from
+      // each network's partials
       bool prefetch = true;  // the L2 prefetch unless some network's stride aliases
       for (const PlanNet& n : p->nets) prefetch = prefetch && split_prefetch(n.ldm);
       if ((st = grouped_launch(p->d_nets[pass], p->d_items[pass], p->n_items[pass], p->grid,
-                               p->prec, prefetch, p->stream)) != MP_OK)
+                               p->prec, prefetch, true, p->stream)) != MP_OK)
         return st;
-    } else {
+      if (gemm_only) continue;
       for (PlanNet& n : p->nets) {
         const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
         if (e <= 0) continue;
-        if ((st = gemm_packed_launch(n.d.M, e, n.packed, p->prec, n.ab, n.C, p->stream)) != MP_OK)
+        const int32_t m_lo = n.d.m_lo, K = n.d.K;
+        if ((st = counts_from_partials_launch(n.d.M, e, n.n, p->est, 1, n.bins.data(), MP_JOINT,
+                                              &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
+                                              n.ws_counts, n.ws_counts_bytes, p->stream)) != MP_OK)
           return st;
       }
+      continue;
     }
-    if (gemm_only) continue;
     for (PlanNet& n : p->nets) {
       const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
       if (e <= 0) continue;
       const int32_t m_lo = n.d.m_lo, K = n.d.K;
+      if (fused(p->prec)) {  // FP32: the fused GEMM and its counts, one network at a time
+        if ((st = propagate_counts_launch(n.d.M, e, p->prec, p->est, n.ab, n.n, n.packed, 1,
+                                          n.bins.data(), MP_JOINT, &m_lo, &K, n.d.n_sub,
+                                          n.d.E / n.d.n_sub, g0, n.acc, n.ws_counts,
+                                          n.ws_counts_bytes, p->stream)) != MP_OK)
+          return st;
+        continue;
+      }
+      if ((st = gemm_packed_launch(n.d.M, e, n.packed, p->prec, n.ab, n.C, p->stream)) != MP_OK)
+        return st;
+      if (gemm_only) continue;
       if ((st = binned_counts_launch(n.d.M, e, n.C, n.n, p->prec, p->est, 1, n.bins.data(),
                                      MP_JOINT, &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
                                      n.ws_counts, n.ws_counts_bytes, p->stream)) != MP_OK)
@@ -337,18 +373,21 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     n.P_im = (double*)plan_alloc(p, (size_t)n.d.K * 8);
     n.sigma = (double*)plan_alloc(p, (size_t)n.d.K * 8);
     n.ab = plan_alloc(p, (size_t)n.ldm * 2 * n.chunk * (prec == MP_FP64 ? 8 : 4));
-    n.C = plan_alloc(p, (size_t)2 * n.ldm * 2 * n.chunk * eb);
+    if (!fused(prec)) n.C = plan_alloc(p, (size_t)2 * n.ldm * 2 * n.chunk * eb);
     n.packed = plan_alloc(p, propagate_workspace(n.d.M, prec));
     const int32_t K = n.d.K;
     const int64_t ns = n.d.E / n.d.n_sub;
     size_t wsb = 0;
-    for (int64_t g0 = 0; g0 < n.d.E; g0 += n.chunk)
-      wsb = std::max(wsb, binned_workspace(1, MP_JOINT, &K, std::min<int64_t>(n.chunk, n.d.E - g0),
-                                           n.d.n_sub, ns, g0));
+    for (int64_t g0 = 0; g0 < n.d.E; g0 += n.chunk) {
+      const int64_t e = std::min<int64_t>(n.chunk, n.d.E - g0);
+      wsb = std::max(wsb, fused(prec) ? propagate_counts_workspace(n.d.M, e, 1, n.bins.data(),
+                                                                   MP_JOINT, &K, n.d.n_sub, ns, g0)
+                                      : binned_workspace(1, MP_JOINT, &K, e, n.d.n_sub, ns, g0));
+    }
     n.ws_counts_bytes = wsb;
     n.ws_counts = plan_alloc(p, wsb);
-    if (!n.r || !n.n || !n.acc || !n.P_re || !n.P_im || !n.sigma || !n.ab || !n.C || !n.packed ||
-        !n.ws_counts) {
+    if (!n.r || !n.n || !n.acc || !n.P_re || !n.P_im || !n.sigma || !n.ab ||
+        (!fused(prec) && !n.C) || !n.packed || !n.ws_counts) {
       plan_free(p);
       set_error("mp_plan_create: device allocation failed (network %d)", i);
       return MP_ERR_HIP;
@@ -370,7 +409,18 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         PlanNet& n = p->nets[i];
         const int64_t e = std::max<int64_t>(0, std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk));
         const float sc = ldexpf(1.0f, -split_scale_exp(n.d.M, prec));
-        g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, (float*)n.C, n.ldm, 2 * e, sc};
+        g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, nullptr, n.ldm, 2 * e, sc,
+                        FusedOut{}};
+        if (e > 0) {
+          const int32_t m_lo = n.d.m_lo, K = n.d.K;
+          const mp_status st = fused_out_setup(n.d.M, e, 1, n.bins.data(), MP_JOINT, &m_lo, &K,
+                                               n.d.n_sub, n.d.E / n.d.n_sub, (int64_t)pass * n.chunk,
+                                               est, n.ws_counts, n.ws_counts_bytes, g[i].fo);
+          if (st != MP_OK) {
+            plan_free(p);
+            return st;
+          }
+        }
       }
       GroupNet* dn = (GroupNet*)plan_alloc(p, g.size() * sizeof(GroupNet));
       size_t max_items = 0;

@@ -514,9 +514,12 @@ template <typename H, bool FUSED, bool PF>
 __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
                                      const uint16_t* __restrict__ B, float* __restrict__ C,
                                      int64_t ldm, int64_t ncols, int64_t m0, int64_t n0,
-                                     float out_scale, const FusedOut* fo) {
+                                     float out_scale, const FusedOut* fo, int tid = -1) {
   typedef typename SplitMfma<H>::frag frag;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // tid < 0: the kernel's own thread index; else an index made opaque by the
+  // caller (the grouped kernel), whose wave number is made uniform here
+  const int wave = tid < 0 ? (int)(threadIdx.x >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid < 0 ? (int)(threadIdx.x & 63) : tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lh = lane >> 5;
 
@@ -925,9 +928,12 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
 // Persistent grouped launch over many networks: one workgroup per CU walks a
 // work list of (network, tile) items with stride gridDim.x; the list is
 // ordered so that the items an XCD processes at the same time are
-// neighbouring tiles of one network.
+// neighbouring tiles of one network.  FUSED: each item is a tile of
+// gemm_split_occ (modes [128 tm, 128 tm + 128), samples [128 tn, 128 tn + 128),
+// the same tile counts as the C tiles) and writes the network's occupation
+// partials (GroupNet::fo) instead of C.
 
-template <typename H, bool PF>
+template <typename H, bool PF, bool FUSED>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet* __restrict__ nets,
                                                                   const int4* __restrict__ items,
                                                                   int n_items) {
@@ -936,9 +942,18 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 w = items[it];  // (net, tile_m, tile_n, unused); net < 0: idle slot
     if (w.x < 0) continue;
-    const GroupNet g = nets[w.x];
-    split_pp_tile<H, false, PF>(lds, g.A, g.B, g.C, g.ldm, g.ncols, (int64_t)w.y * S_BM,
-                            (int64_t)w.z * S_BN, g.out_scale, nullptr);
+    const GroupNet* g = nets + w.x;
+    // the thread index, opaque to the compiler on every item, so that nothing
+    // derived from it is hoisted out of the item loop and held in registers
+    // across the epilogue
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if constexpr (FUSED)
+      split_pp_tile<H, true, PF>(lds, g->A, g->B, nullptr, g->ldm, g->ncols, (int64_t)w.y * 128,
+                                 (int64_t)w.z * 128, g->out_scale, &g->fo, tid);
+    else
+      split_pp_tile<H, false, PF>(lds, g->A, g->B, g->C, g->ldm, g->ncols, (int64_t)w.y * S_BM,
+                                  (int64_t)w.z * S_BN, g->out_scale, nullptr, tid);
     __syncthreads();  // the next item reuses the LDS stages
   }
 }
@@ -1055,14 +1070,20 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
   return MP_OK;
 }
 
+template <typename H>
+static auto grouped_kernel(bool prefetch, bool fused) {
+  return fused ? (prefetch ? gemm_split_grouped<H, true, true> : gemm_split_grouped<H, false, true>)
+               : (prefetch ? gemm_split_grouped<H, true, false> : gemm_split_grouped<H, false, false>);
+}
+
 mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
-                         mp_precision prec, bool prefetch, hipStream_t stream) {
+                         mp_precision prec, bool prefetch, bool fused, hipStream_t stream) {
   if (prec == MP_SPLIT_BF16) {
-    auto kernel = prefetch ? gemm_split_grouped<__bf16, true> : gemm_split_grouped<__bf16, false>;
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
+    hipLaunchKernelGGL(grouped_kernel<__bf16>(prefetch, fused), dim3(grid), dim3(kThreads), 0,
+                       stream, d_nets, d_items, n_items);
   } else if (prec == MP_SPLIT_FP16) {
-    auto kernel = prefetch ? gemm_split_grouped<_Float16, true> : gemm_split_grouped<_Float16, false>;
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
+    hipLaunchKernelGGL(grouped_kernel<_Float16>(prefetch, fused), dim3(grid), dim3(kThreads), 0,
+                       stream, d_nets, d_items, n_items);
   } else {
     set_error("grouped GEMM: split precisions only");
     return MP_ERR_UNSUPPORTED;

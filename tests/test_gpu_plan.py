@@ -1,8 +1,8 @@
 """Batched plans: one captured hipGraph, one persistent grouped GEMM launch
-over networks of uneven M.  A plan's result for each network must equal the
-single-network pipeline on the same noise (the grouped launch runs the same
-tile code), replays must be identical, and the autotuner's choice must be
-cached and reused."""
+with the occupation-fused epilogue over networks of uneven M.  A plan's
+result for each network must equal the single-network fused pipeline on the
+same noise bit for bit (the grouped launch runs the same tile code), replays
+must be identical, and the autotuner's choice must be cached and reused."""
 import json
 
 import numpy as np
@@ -36,10 +36,13 @@ def _nets(Ms, E, n_sub, seed0=900):
 
 
 def _single(n, prec):
+    """The single-network pipeline a plan reproduces: the occupation-fused
+    path for FP32 and the split precisions."""
     import paper_2503_12749_amd as mp
     p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
                           windows=[n["window"]], n_sub=n["n_sub"],
-                          samples_per_sub=n["E"] // n["n_sub"], chunk=n["E"])
+                          samples_per_sub=n["E"] // n["n_sub"], chunk=n["E"],
+                          fused=prec != "fp64")
     p.run()
     return p.result()
 
@@ -92,6 +95,27 @@ def test_plan_chunked_passes_and_fp64_oracle():
                             1, [n["window"]], net=n["net"], chunk=1000)
         tol = 1e-10 * np.maximum(np.abs(ref["P"]), 1e-4 * ref["P"].max()) + 1e-14 * ref["P"].max()
         assert np.all(np.abs(P - ref["P"]) <= tol), i
+    plan.close()
+
+
+def test_plan_fp32_fused_two_passes():
+    """FP32 plan (the occupation-fused GEMM and its counts per network inside
+    the graph) over two passes per network: bit-identical to the fused
+    single-network pipeline run in the same chunks."""
+    import paper_2503_12749_amd as mp
+    nets = _nets([50, 140, 260], E=2048, n_sub=4, seed0=311)
+    plan = mp.Plan(nets, prec="fp32", chunk=1024)
+    for rep in range(2):
+        plan.launch()
+        for i, n in enumerate(nets):
+            P, _, s = plan.result(i)
+            p = mp.CountsPipeline(n["T"], n["r"], prec="fp32", seed=n["seed"], net=n["net"],
+                                  windows=[n["window"]], n_sub=n["n_sub"],
+                                  samples_per_sub=n["E"] // n["n_sub"], chunk=1024, fused=True)
+            p.run()
+            Pr, _, sr = p.result()
+            assert np.array_equal(P, Pr) and np.array_equal(s, sr), (rep, i)
+            assert abs(P.sum() - 1) < 1e-8
     plan.close()
 
 
