@@ -175,8 +175,12 @@ mp_status mlp_forward(const mp_mlp_shape* s, const uint16_t* w16, const float* p
   mp_status r = mlp_fwd_impl(s, w16, params, X, batch, (float*)ws, st, Zs, As);
   if (r != MP_OK) return r;
   const int O = s->width[s->n_layers];
-  hipMemcpyAsync(Y, As[s->n_layers - 1], (size_t)batch * O * 4, hipMemcpyDeviceToDevice, st);
-  MP_HIP_LAUNCH_CHECK("mlp forward copy");
+  const hipError_t e =
+      hipMemcpyAsync(Y, As[s->n_layers - 1], (size_t)batch * O * 4, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) {
+    set_error("mlp forward copy: %s", hipGetErrorString(e));
+    return MP_ERR_HIP;
+  }
   return MP_OK;
 }
 

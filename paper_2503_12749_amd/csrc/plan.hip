@@ -119,11 +119,12 @@ static void* plan_alloc(Plan* p, size_t bytes) {
 }
 
 static void plan_free(Plan* p) {
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->stream) hipStreamSynchronize(p->stream);
-  for (void* a : p->allocs) hipFree(a);
-  if (p->stream) hipStreamDestroy(p->stream);
+  // teardown: errors here have nowhere to go (a failed creation already set one)
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (void* a : p->allocs) (void)hipFree(a);
+  if (p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
 
@@ -354,8 +355,12 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     return MP_ERR_HIP;
   }
   int dev = 0, cus = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    plan_free(p);
+    set_error("mp_plan_create: device query failed");
+    return MP_ERR_HIP;
+  }
   p->grid = std::max(kXcdsPlan, (cus / kXcdsPlan) * kXcdsPlan);
   const size_t eb = (prec == MP_FP64) ? 8 : 4;
   int64_t max_e = 0;
@@ -392,7 +397,12 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
       set_error("mp_plan_create: device allocation failed (network %d)", i);
       return MP_ERR_HIP;
     }
-    hipMemcpyAsync(n.r, n.d.r, (size_t)n.d.M * 8, hipMemcpyDeviceToDevice, p->stream);
+    if (hipMemcpyAsync(n.r, n.d.r, (size_t)n.d.M * 8, hipMemcpyDeviceToDevice, p->stream) !=
+        hipSuccess) {
+      plan_free(p);
+      set_error("mp_plan_create: copy of r failed (network %d)", i);
+      return MP_ERR_HIP;
+    }
     mp_status st = pack_launch(n.d.M, n.d.T, prec, n.packed, p->stream);
     if (st != MP_OK) {
       plan_free(p);
@@ -431,7 +441,11 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         set_error("mp_plan_create: device allocation failed (work lists)");
         return MP_ERR_HIP;
       }
-      hipMemcpy(dn, g.data(), g.size() * sizeof(GroupNet), hipMemcpyHostToDevice);
+      if (hipMemcpy(dn, g.data(), g.size() * sizeof(GroupNet), hipMemcpyHostToDevice) != hipSuccess) {
+        plan_free(p);
+        set_error("mp_plan_create: upload of the network table failed");
+        return MP_ERR_HIP;
+      }
       p->d_nets.push_back(dn);
       p->d_items.push_back(di);
       p->n_items.push_back((int)max_items);
@@ -448,26 +462,36 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         plan_free(p);
         return st;
       }
-      hipEvent_t a, b;
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        plan_free(p);
+        set_error("mp_plan_create: event creation failed");
+        return MP_ERR_HIP;
+      }
       double best = 1e30;
-      for (int o = 0; o < kOrders; ++o) {
+      for (int o = 0; o < kOrders && st == MP_OK; ++o) {
         if ((st = upload_items(p, o)) != MP_OK) break;
-        enqueue_pass(p, true);  // warm
-        hipEventRecord(a, p->stream);
-        for (int rep = 0; rep < 2; ++rep) enqueue_pass(p, true);
-        hipEventRecord(b, p->stream);
-        hipEventSynchronize(b);
+        if ((st = enqueue_pass(p, true)) != MP_OK) break;  // warm
         float t = 0.f;
-        hipEventElapsedTime(&t, a, b);
+        bool ok = hipEventRecord(a, p->stream) == hipSuccess;
+        for (int rep = 0; rep < 2 && ok && st == MP_OK; ++rep) st = enqueue_pass(p, true);
+        ok = ok && st == MP_OK && hipEventRecord(b, p->stream) == hipSuccess &&
+             hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess;
+        if (!ok) {
+          if (st == MP_OK) {
+            set_error("mp_plan_create: timing the work-list orders failed");
+            st = MP_ERR_HIP;
+          }
+          break;
+        }
         if (t / 2 < best) {
           best = t / 2;
           order = o;
         }
       }
-      hipEventDestroy(a);
-      hipEventDestroy(b);
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
       if (st != MP_OK) {
         plan_free(p);
         return st;
@@ -494,7 +518,7 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
   hipGraph_t graph = nullptr;
   const hipError_t ce = hipStreamEndCapture(p->stream, &graph);
   if (st != MP_OK || ce != hipSuccess || !graph) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     plan_free(p);
     if (st == MP_OK) set_error("mp_plan_create: stream capture failed: %s", hipGetErrorString(ce));
     return st == MP_OK ? MP_ERR_HIP : st;
@@ -520,12 +544,13 @@ mp_status mp_plan_launch(void* plan, void* stream) {
     return MP_ERR_HIP;
   }
   hipStream_t s = (hipStream_t)stream;
-  hipEventRecord(ev, s);
-  hipStreamWaitEvent(p->stream, ev, 0);
-  const hipError_t e = hipGraphLaunch(p->exec, p->stream);
-  hipEventRecord(ev, p->stream);
-  hipStreamWaitEvent(s, ev, 0);
-  hipEventDestroy(ev);
+  // each step runs only if the previous ones succeeded; the first error is reported
+  hipError_t e = hipEventRecord(ev, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, ev, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(p->exec, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev, p->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+  (void)hipEventDestroy(ev);
   if (e != hipSuccess) {
     set_error("mp_plan_launch: %s", hipGetErrorString(e));
     return MP_ERR_HIP;
