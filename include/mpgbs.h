@@ -437,8 +437,13 @@ mp_status mp_plan_launch(void* plan, void* stream);
 mp_status mp_plan_result(void* plan, int32_t i, const double** P_re, const double** P_im,
                          const double** sigma);
 
-/* Chosen work-list order, its tuned GEMM time (ms) and the plan's device bytes. */
-mp_status mp_plan_info(void* plan, int32_t* order, double* tuned_ms, size_t* device_bytes);
+/* The autotuner's choice: work-list order (0: groups of 8 row x 4 column tiles
+ * per XCD, 1: 4 x 8, 2: column-major without grouping) and whether the split
+ * GEMM prefetches the next slab's lines into L2 (1) or not (0), the tuned GEMM
+ * time of one pass (ms), and the plan's device bytes.  Any output pointer may
+ * be NULL. */
+mp_status mp_plan_info(void* plan, int32_t* order, int32_t* prefetch, double* tuned_ms,
+                       size_t* device_bytes);
 
 /* Waits for the plan's stream and frees everything the plan owns. */
 mp_status mp_plan_destroy(void* plan);

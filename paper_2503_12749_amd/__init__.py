@@ -463,10 +463,11 @@ class Plan:
         return tuple(out)
 
     def info(self):
-        o, ms, b = ctypes.c_int32(), ctypes.c_double(), ctypes.c_size_t()
-        _lib.check(_lib.load().mp_plan_info(self.handle, ctypes.byref(o), ctypes.byref(ms),
-                                            ctypes.byref(b)))
-        return {"order": o.value, "tuned_ms": ms.value, "device_bytes": b.value}
+        o, f, ms, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_size_t()
+        _lib.check(_lib.load().mp_plan_info(self.handle, ctypes.byref(o), ctypes.byref(f),
+                                            ctypes.byref(ms), ctypes.byref(b)))
+        return {"order": o.value, "prefetch": f.value, "tuned_ms": ms.value,
+                "device_bytes": b.value}
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

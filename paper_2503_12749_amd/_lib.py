@@ -107,8 +107,8 @@ def load() -> ctypes.CDLL:
         "mp_plan_launch": (ctypes.c_int, [vp, vp]),
         "mp_plan_result": (ctypes.c_int, [vp, c_i32, ctypes.POINTER(ctypes.c_void_p),
                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
-        "mp_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(c_i32), ctypes.POINTER(ctypes.c_double),
-                                        ctypes.POINTER(sz)]),
+        "mp_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(sz)]),
         "mp_plan_destroy": (ctypes.c_int, [vp]),
         "mp_mlp_param_count": (c_i64, [ctypes.POINTER(MlpShape)]),
         "mp_mlp_workspace": (sz, [ctypes.POINTER(MlpShape), c_i32]),

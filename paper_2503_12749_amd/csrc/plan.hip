@@ -105,6 +105,7 @@ struct Plan {
   std::vector<int> n_items;
   int grid = 0;
   int order = 0;
+  bool prefetch = true;  // the split GEMM's L2 prefetch (autotuned with the order)
   double tuned_ms = 0.0;
   size_t bytes = 0;
 };
@@ -183,8 +184,9 @@ static std::string tune_key(const Plan* p) {
   return k;
 }
 
-// The cache is a flat JSON object {"<key>": {"order": o, "ms": t}, ...}.
-static bool cache_lookup(const char* path, const std::string& key, int& order, double& ms) {
+// The cache is a flat JSON object {"<key>": {"order": o, "prefetch": f, "ms": t}, ...}.
+static bool cache_lookup(const char* path, const std::string& key, int& order, int& prefetch,
+                         double& ms) {
   if (!path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
@@ -193,13 +195,25 @@ static bool cache_lookup(const char* path, const std::string& key, int& order, d
   size_t got;
   while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
   fclose(f);
+  // the last entry of this key that parses (an older entry may lack a field)
   const std::string pat = "\"" + key + "\": {\"order\": ";
-  const size_t at = text.find(pat);
-  if (at == std::string::npos) return false;
-  return sscanf(text.c_str() + at + pat.size(), "%d, \"ms\": %lf", &order, &ms) == 2;
+  bool found = false;
+  for (size_t at = text.find(pat); at != std::string::npos; at = text.find(pat, at + 1)) {
+    int o = 0, f = 0;
+    double t = 0.0;
+    if (sscanf(text.c_str() + at + pat.size(), "%d, \"prefetch\": %d, \"ms\": %lf", &o, &f, &t) ==
+        3) {
+      order = o;
+      prefetch = f;
+      ms = t;
+      found = true;
+    }
+  }
+  return found;
 }
 
-static void cache_store(const char* path, const std::string& key, int order, double ms) {
+static void cache_store(const char* path, const std::string& key, int order, int prefetch,
+                        double ms) {
   if (!path) return;
   std::string text;
   if (FILE* f = fopen(path, "r")) {
@@ -212,7 +226,8 @@ static void cache_store(const char* path, const std::string& key, int order, dou
   std::string body = end == std::string::npos ? "" : text.substr(text.find('{') + 1, end - text.find('{') - 1);
   while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
   char entry[1024];
-  snprintf(entry, sizeof(entry), "\"%s\": {\"order\": %d, \"ms\": %.4f}", key.c_str(), order, ms);
+  snprintf(entry, sizeof(entry), "\"%s\": {\"order\": %d, \"prefetch\": %d, \"ms\": %.4f}",
+           key.c_str(), order, prefetch, ms);
   const std::string out = "{" + body + (body.empty() ? "\n  " : ",\n  ") + entry + "\n}\n";
   const std::string tmp = std::string(path) + ".tmp";
   if (FILE* f = fopen(tmp.c_str(), "w")) {
@@ -270,10 +285,8 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
     if (split(p->prec)) {
       // one grouped launch with the occupation epilogue, then counts from
       // each network's partials
-      bool prefetch = true;  // the L2 prefetch unless some network's stride aliases
-      for (const PlanNet& n : p->nets) prefetch = prefetch && split_prefetch(n.ldm);
       if ((st = grouped_launch(p->d_nets[pass], p->d_items[pass], p->n_items[pass], p->grid,
-                               p->prec, prefetch, true, p->stream)) != MP_OK)
+                               p->prec, p->prefetch, true, p->stream)) != MP_OK)
         return st;
       if (gemm_only) continue;
       for (PlanNet& n : p->nets) {
@@ -450,12 +463,17 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
       p->d_items.push_back(di);
       p->n_items.push_back((int)max_items);
     }
-    // autotune the work-list order on this plan's data
+    // autotune the work-list order and the L2 prefetch on this plan's data;
+    // the prefetch is a candidate only when no network's operand rows are a
+    // multiple of 32 KB apart (there it slowed the GEMM)
+    bool prefetch_allowed = true;
+    for (const PlanNet& n : p->nets) prefetch_allowed = prefetch_allowed && split_prefetch(n.ldm);
     const std::string key = tune_key(p);
-    int order = 0;
+    int order = 0, prefetch = prefetch_allowed ? 1 : 0;
     double ms = 0.0;
-    if (!cache_lookup(tune_cache, key, order, ms)) {
+    if (!cache_lookup(tune_cache, key, order, prefetch, ms) || (prefetch && !prefetch_allowed)) {
       // a valid work list must be on the device before the first grouped launch
+      p->prefetch = prefetch_allowed;
       mp_status st = upload_items(p, 0);
       if (st == MP_OK) st = enqueue_pass(p);  // real data in every buffer
       if (st != MP_OK) {
@@ -470,7 +488,10 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         return MP_ERR_HIP;
       }
       double best = 1e30;
-      for (int o = 0; o < kOrders && st == MP_OK; ++o) {
+      for (int c = 0; c < 2 * kOrders && st == MP_OK; ++c) {
+        const int o = c % kOrders, f = c < kOrders ? 1 : 0;
+        if (f && !prefetch_allowed) continue;
+        p->prefetch = f != 0;
         if ((st = upload_items(p, o)) != MP_OK) break;
         if ((st = enqueue_pass(p, true)) != MP_OK) break;  // warm
         float t = 0.f;
@@ -488,6 +509,7 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         if (t / 2 < best) {
           best = t / 2;
           order = o;
+          prefetch = f;
         }
       }
       (void)hipEventDestroy(a);
@@ -497,9 +519,10 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         return st;
       }
       ms = best;
-      cache_store(tune_cache, key, order, ms);
+      cache_store(tune_cache, key, order, prefetch, ms);
     }
     p->order = order;
+    p->prefetch = prefetch != 0;
     p->tuned_ms = ms;
     mp_status st = upload_items(p, order);
     if (st != MP_OK) {
@@ -570,11 +593,13 @@ mp_status mp_plan_result(void* plan, int32_t i, const double** P_re, const doubl
   return MP_OK;
 }
 
-mp_status mp_plan_info(void* plan, int32_t* order, double* tuned_ms, size_t* device_bytes) {
+mp_status mp_plan_info(void* plan, int32_t* order, int32_t* prefetch, double* tuned_ms,
+                       size_t* device_bytes) {
   clear_error();
   MP_CHECK_ARG(plan, MP_ERR_ARG, "mp_plan_info: null plan");
   Plan* p = (Plan*)plan;
   if (order) *order = p->order;
+  if (prefetch) *prefetch = p->prefetch ? 1 : 0;
   if (tuned_ms) *tuned_ms = p->tuned_ms;
   if (device_bytes) *device_bytes = p->bytes;
   return MP_OK;

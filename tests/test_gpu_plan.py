@@ -54,7 +54,7 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     cache = tmp_path / "tune.json"
     plan = mp.Plan(nets, prec=prec, tune_cache=cache)
     info = plan.info()
-    assert 0 <= info["order"] < 3 and info["tuned_ms"] > 0
+    assert 0 <= info["order"] < 3 and info["prefetch"] in (0, 1) and info["tuned_ms"] > 0
     first = []
     for rep in range(3):
         plan.launch()
@@ -77,6 +77,7 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     assert len(data) == 1
     plan2 = mp.Plan(nets, prec=prec, tune_cache=cache)
     assert plan2.info()["order"] == info["order"]
+    assert plan2.info()["prefetch"] == info["prefetch"]
     assert plan2.info()["tuned_ms"] == pytest.approx(info["tuned_ms"], rel=1e-3)
     plan.close()
     plan2.close()
