@@ -216,12 +216,15 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
  * (the occupation-fused GEMM): each 256 x 256 GEMM tile covers the Re and Im
  * rows of 128 modes and the alpha and beta columns of 128 samples, and its
  * epilogue reduces alpha'_j beta'_j over the modes of every bin run in the
- * tile to per-sample partials (16 bytes per run, block and sample, in
- * `workspace`); the counting kernel then reads those partials instead of C.
- * Same estimator, windows and accumulator layout as mp_binned_counts, with
- * the modes MP_MARGINALS, MP_MARGINALS_AND_TOTAL and MP_JOINT with d = 1.
- * The occupations are summed in FP32 within a tile and in FP64 across tiles,
- * so results agree with the unfused path to FP32 rounding.
+ * tile to per-sample partials (16 bytes per run, block and sample, at the
+ * start of `workspace`); the counting kernels then read those partials
+ * instead of C.  Same estimator, windows, limits and accumulator layout as
+ * mp_binned_counts, for every mode: MP_MARGINALS, MP_MARGINALS_AND_TOTAL and
+ * MP_JOINT with d = 1 .. 4 (joint distributions of d >= 2 bins take their
+ * per-sample bin sums from the partials; the rest of their path is the one
+ * mp_binned_counts runs).  The occupations are summed in FP32 within a tile
+ * and in FP64 across tiles, so results agree with the unfused path to FP32
+ * rounding.
  *
  *   prec       MP_FP32, MP_SPLIT_BF16 or MP_SPLIT_FP16 (others:
  *              MP_ERR_UNSUPPORTED)

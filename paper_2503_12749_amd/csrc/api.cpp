@@ -270,7 +270,8 @@ size_t mp_propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int3
                                      int64_t samples_per_sub, int64_t e0) {
   std::vector<int32_t> m_lo(MP_MAX_BINS + 1, 0);
   if (counts_args("mp_propagate_counts_workspace", M, E, MP_MATRIX_P, d, bin_of_mode, mode,
-                  m_lo.data(), K, n_sub, samples_per_sub, e0) != MP_OK)
+                  m_lo.data(), K, n_sub, samples_per_sub, e0) != MP_OK ||
+      (mode == MP_JOINT && d > 4))
     return 0;
   return propagate_counts_workspace(M, E, d, bin_of_mode, mode, K, n_sub, samples_per_sub, e0);
 }
@@ -289,6 +290,8 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
                MP_ERR_UNSUPPORTED,
                "mp_propagate_counts: precision %d is not fused (FP32 and split precisions are)",
                (int)prec);
+  MP_CHECK_ARG(mode != MP_JOINT || d <= 4, MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts: joint distributions need d <= 4");
   MP_CHECK_ARG(ab && n && packed && acc, MP_ERR_ARG, "mp_propagate_counts: null pointer argument");
   MP_CHECK_ARG(aligned(ab, 16), MP_ERR_ARG, "mp_propagate_counts: ab must be 16-byte aligned");
   const size_t need_packed = propagate_workspace(M, prec);

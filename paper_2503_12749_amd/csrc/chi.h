@@ -51,6 +51,25 @@ __device__ inline void run_sum(const CT* __restrict__ ca, const CT* __restrict__
   im = wave_sum(si);
 }
 
+// One sample's occupation sum over one bin run from the occupation-fused
+// GEMM's partials: the run's slots [slot0, slot0 + nblk) (one per 128-mode
+// block it touches), four floats per (slot, sample) at part[(slot E + k) 4]:
+// (re, im) from the Re-row half and from the Im-row half.  Wave-reduced.
+__device__ inline void run_sum_partials(const float* __restrict__ part, int64_t E, int slot0,
+                                        int nblk, int64_t k, int lane, double& re, double& im) {
+  double sr = 0.0, si = 0.0;
+  for (int t = lane; t < nblk; t += 64) {
+    const float4 v = *(const float4*)(part + ((int64_t)(slot0 + t) * E + k) * 4);
+    sr += (double)v.x + (double)v.z;
+    si += (double)v.y + (double)v.w;
+  }
+  re = wave_sum(sr);
+  im = wave_sum(si);
+}
+
+// Slots of a run [lo, hi) in the fused partials: the 128-mode blocks it touches.
+__host__ __device__ inline int run_blocks(int lo, int hi) { return ((hi - 1) >> 7) - (lo >> 7) + 1; }
+
 __device__ inline double reduce_2pi(double ph) {
   constexpr double kTwoPi = 6.283185307179586476925286766559;
   constexpr double kInvTwoPi = 0.15915494309189533576888376337251;

@@ -145,15 +145,9 @@ struct FromPartials {
     for (int b = 0; b < MP_MAX_BINS; ++b) nb[b][0] = nb[b][1] = 0.0;
     int slot0 = 0;
     for (int q = 0; q < p.n_runs; ++q) {
-      const int first = p.run_lo[q] >> 7, nblk = ((p.run_hi[q] - 1) >> 7) - first + 1;
-      double sr = 0.0, si = 0.0;
-      for (int t = lane; t < nblk; t += 64) {
-        const float4 v = *(const float4*)(part + ((int64_t)(slot0 + t) * p.E + k) * 4);
-        sr += (double)v.x + (double)v.z;
-        si += (double)v.y + (double)v.w;
-      }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
+      const int nblk = run_blocks(p.run_lo[q], p.run_hi[q]);
+      double sr, si;
+      run_sum_partials(part, p.E, slot0, nblk, k, lane, sr, si);
       const int bq = p.run_bin[q];
 #pragma unroll
       for (int b = 0; b < MP_MAX_BINS; ++b)
@@ -325,17 +319,27 @@ struct Joint2Params {
 // Per-sample record (one wave per sample, lane 0 writes): n1, n2 (complex),
 // c1, c2 (c2 = -inf for +P).  record_bands then sets the chunk's bands
 // band[0..3] = u1, u2, v1, v2 half-widths (atomic max, -1 = empty).
-template <typename CT>
+// PART: the bin sums come from the occupation-fused GEMM's partials (slots in
+// run order) instead of the propagated amplitudes C.
+template <typename CT, bool PART>
 __device__ inline void joint2_sample(const Joint2Params& p, const CT* __restrict__ C,
+                                     const float* __restrict__ part,
                                      const double* __restrict__ nglob, double* __restrict__ rec,
                                      int64_t k, int lane) {
   const int64_t ldc = 2 * p.ldm;
-  const CT* ca = C + k * ldc;
-  const CT* cb = C + (p.E + k) * ldc;
+  const CT* ca = PART ? nullptr : C + k * ldc;
+  const CT* cb = PART ? nullptr : C + (p.E + k) * ldc;
   double R1 = 0.0, I1 = 0.0, R2 = 0.0, I2 = 0.0;
+  int slot0 = 0;
   for (int q = 0; q < p.n_runs; ++q) {
     double re, im;
-    run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+    if constexpr (PART) {
+      const int nblk = run_blocks(p.run_lo[q], p.run_hi[q]);
+      run_sum_partials(part, p.E, slot0, nblk, k, lane, re, im);
+      slot0 += nblk;
+    } else {
+      run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+    }
     const bool first = p.run_bin[q] == 0;
     R1 += first ? re : 0.0;
     I1 += first ? im : 0.0;
@@ -359,8 +363,9 @@ __device__ inline void joint2_sample(const Joint2Params& p, const CT* __restrict
   r[5] = c2;
 }
 
-template <typename CT>
+template <typename CT, bool PART>
 __global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const CT* __restrict__ C,
+                                                          const float* __restrict__ part,
                                                           const double* __restrict__ nglob,
                                                           double* __restrict__ rec) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(256) void joint2_occupations(Joint2Params p, const 
   for (int j = 0; j < kOccPerWave; ++j) {
     const int64_t k = base + 4 * j;
     if (k >= p.E) return;
-    joint2_sample<CT>(p, C, nglob, rec, k, lane);
+    joint2_sample<CT, PART>(p, C, part, nglob, rec, k, lane);
   }
 }
 
@@ -490,10 +495,12 @@ __global__ __launch_bounds__(256) void joint2_accumulate(Joint2Params p, const d
   }
 }
 
+// part != nullptr: the bin sums come from the occupation-fused GEMM's partials
+// (runs in the order built here, as fused_runs builds them) and C is unused.
 mp_status joint2_launch(int32_t M, int64_t E, const void* C, const double* n, mp_precision prec,
                         mp_estimator est, const int32_t* bin_of_mode, const int32_t* m_lo,
                         const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0, double* acc,
-                        void* ws, size_t ws_bytes, hipStream_t stream) {
+                        void* ws, size_t ws_bytes, hipStream_t stream, const float* part) {
   Joint2Params p{};
   p.M = M;
   p.ldm = ld_modes(M);
@@ -532,12 +539,15 @@ mp_status joint2_launch(int32_t M, int64_t E, const void* C, const double* n, mp
   double* rec = (double*)((char*)ws + 256);
   hipLaunchKernelGGL(joint2_band_init, dim3(1), dim3(64), 0, stream, band);
   const unsigned blocks = (unsigned)((E + 4 * kOccPerWave - 1) / (4 * kOccPerWave));
-  if (prec == MP_FP64)
-    hipLaunchKernelGGL(joint2_occupations<double>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const double*)C, n, rec);
+  if (part)
+    hipLaunchKernelGGL((joint2_occupations<float, true>), dim3(blocks), dim3(256), 0, stream, p,
+                       (const float*)nullptr, part, n, rec);
+  else if (prec == MP_FP64)
+    hipLaunchKernelGGL((joint2_occupations<double, false>), dim3(blocks), dim3(256), 0, stream, p,
+                       (const double*)C, (const float*)nullptr, n, rec);
   else
-    hipLaunchKernelGGL(joint2_occupations<float>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const float*)C, n, rec);
+    hipLaunchKernelGGL((joint2_occupations<float, false>), dim3(blocks), dim3(256), 0, stream, p,
+                       (const float*)C, (const float*)nullptr, n, rec);
   MP_HIP_LAUNCH_CHECK("mp_binned_counts joint occupations launch");
   const mp_status sb = record_bands_launch(rec, E, 2, K, 2, band, stream);
   if (sb != MP_OK) return sb;
@@ -618,7 +628,8 @@ size_t jointd_finalize_workspace(int32_t d, const int32_t* K);
 mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp_precision prec,
                         mp_estimator est, int32_t d, const int32_t* bin_of_mode,
                         const int32_t* m_lo, const int32_t* K, int32_t n_sub, int64_t ns,
-                        int64_t e0, double* acc, void* ws, size_t ws_bytes, hipStream_t stream);
+                        int64_t e0, double* acc, void* ws, size_t ws_bytes, hipStream_t stream,
+                        const float* part);
 mp_status jointd_finalize(int32_t d, const int32_t* K, int32_t n_sub, int64_t ns,
                           const double* acc, double* P_re, double* P_im, double* sigma, void* ws,
                           size_t ws_bytes, hipStream_t stream);
@@ -738,10 +749,10 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
                                double* acc, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (mode == MP_JOINT && d == 2)
     return joint2_launch(M, E, C, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
-                         ws_bytes, stream);
+                         ws_bytes, stream, nullptr);
   if (mode == MP_JOINT && d >= 3)
     return jointd_launch(M, E, C, n, prec, est, d, bin_of_mode, m_lo, K, n_sub, ns, e0, acc, ws,
-                         ws_bytes, stream);
+                         ws_bytes, stream, nullptr);
   MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
                "mp_binned_counts: joint distributions need d <= 4 (d = %d)", d);
   CountsParams p{};
@@ -782,9 +793,43 @@ static void propagate_counts_sizes(const CountsParams& p, int64_t blocks, size_t
   total = part_bytes + (size_t)blocks * (size_t)p.entries * 16;
 }
 
+// Runs of a bin partition for the fused partials of a joint distribution of
+// d >= 2 bins: maximal ranges of modes with one bin >= 0, in mode order (the
+// order in which the joint paths walk them).
+static mp_status fused_runs(int32_t M, const int32_t* bin_of_mode, FusedOut& fo) {
+  fo.n_runs = 0;
+  for (int j = 0; j < M;) {
+    const int b = bin_of_mode[j];
+    int j2 = j + 1;
+    while (j2 < M && bin_of_mode[j2] == b) ++j2;
+    if (b >= 0) {
+      MP_CHECK_ARG(fo.n_runs < MP_MAX_RUNS, MP_ERR_UNSUPPORTED,
+                   "mp_propagate_counts: bins form more than %d contiguous mode runs", MP_MAX_RUNS);
+      fo.run_lo[fo.n_runs] = j;
+      fo.run_hi[fo.n_runs] = j2;
+      ++fo.n_runs;
+    }
+    j = j2;
+  }
+  fused_slots(fo.n_runs, fo.run_lo, fo.run_hi, fo.slot_off);
+  return MP_OK;
+}
+
+static size_t joint_part_bytes(const FusedOut& fo, int64_t E) {
+  const int64_t slots = fo.n_runs ? fo.slot_off[fo.n_runs - 1] +
+                                        run_blocks(fo.run_lo[fo.n_runs - 1], fo.run_hi[fo.n_runs - 1])
+                                  : 0;
+  return ((size_t)slots * (size_t)E * 16 + 255) / 256 * 256;
+}
+
 size_t propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
                                   mp_bin_mode mode, const int32_t* K, int32_t n_sub, int64_t ns,
                                   int64_t e0) {
+  if (mode == MP_JOINT && d >= 2) {  // the partials, then the joint path's workspace
+    FusedOut fo{};
+    if (fused_runs(M, bin_of_mode, fo) != MP_OK) return 0;
+    return joint_part_bytes(fo, E) + binned_workspace(d, mode, K, E, n_sub, ns, e0);
+  }
   CountsParams p{};
   std::vector<int32_t> m_lo(MP_MAX_BINS + 1, 0);
   int64_t blocks = 0;
@@ -803,9 +848,18 @@ mp_status fused_out_setup(int32_t M, int64_t E, int32_t d, const int32_t* bin_of
                           mp_bin_mode mode, const int32_t* m_lo, const int32_t* K, int32_t n_sub,
                           int64_t ns, int64_t e0, mp_estimator est, void* ws, size_t ws_bytes,
                           FusedOut& fo) {
-  MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
-               "mp_propagate_counts: joint distributions of several bins are not fused (d = %d)",
-               d);
+  if (mode == MP_JOINT && d >= 2) {
+    fo = FusedOut{};
+    const mp_status sr = fused_runs(M, bin_of_mode, fo);
+    if (sr != MP_OK) return sr;
+    const size_t total =
+        joint_part_bytes(fo, E) + binned_workspace(d, mode, K, E, n_sub, ns, e0);
+    MP_CHECK_ARG(ws && ws_bytes >= total, MP_ERR_WORKSPACE,
+                 "mp_propagate_counts: workspace of %zu bytes needed, %zu given", total, ws_bytes);
+    fo.part = (float*)ws;
+    fo.E = E;
+    return MP_OK;
+  }
   CountsParams p{};
   int64_t blocks = 0;
   const mp_status st = setup_counts(p, "mp_propagate_counts", M, E, d, bin_of_mode, mode, m_lo, K,
@@ -866,6 +920,16 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
   if (st != MP_OK) return st;
   if (fo.n_runs > 0 && (st = gemm_fused_launch(M, E, packed, prec, ab, fo, stream)) != MP_OK)
     return st;
+  if (mode == MP_JOINT && d >= 2) {
+    // the joint paths read the bin sums from the partials; their own workspace follows them
+    const size_t pb = joint_part_bytes(fo, E);
+    void* jws = (char*)ws + pb;
+    const size_t jbytes = ws_bytes - pb;
+    return d == 2 ? joint2_launch(M, E, nullptr, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0,
+                                  acc, jws, jbytes, stream, fo.part)
+                  : jointd_launch(M, E, nullptr, n, prec, est, d, bin_of_mode, m_lo, K, n_sub, ns,
+                                  e0, acc, jws, jbytes, stream, fo.part);
+  }
   return counts_from_partials_launch(M, E, n, est, d, bin_of_mode, mode, m_lo, K, n_sub, ns, e0,
                                      acc, ws, ws_bytes, stream);
 }

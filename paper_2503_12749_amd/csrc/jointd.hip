@@ -64,17 +64,27 @@ __global__ void band_init(int* band) {
 // Per sample (one wave, lane 0 writes): the record (Re n_b, Im n_b for b < d,
 // c1, c2; c2 = -inf for +P).  record_bands then sets the box half-widths
 // band[term * 4 + b] (atomic max; -1 = term absent).
-template <typename CT>
+// PART: the bin sums come from the occupation-fused GEMM's partials (slots in
+// run order) instead of the propagated amplitudes C.
+template <typename CT, bool PART>
 __device__ inline void jointd_sample(const JointDParams& p, const CT* __restrict__ C,
+                                     const float* __restrict__ part,
                                      const double* __restrict__ nglob, double* __restrict__ rec,
                                      int64_t k, int lane) {
   const int64_t ldc = 2 * p.ldm;
-  const CT* ca = C + k * ldc;
-  const CT* cb = C + (p.E + k) * ldc;
+  const CT* ca = PART ? nullptr : C + k * ldc;
+  const CT* cb = PART ? nullptr : C + (p.E + k) * ldc;
   double nr[kJD] = {0.0, 0.0, 0.0, 0.0}, ni[kJD] = {0.0, 0.0, 0.0, 0.0};
+  int slot0 = 0;
   for (int q = 0; q < p.n_runs; ++q) {
     double re, im;
-    run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+    if constexpr (PART) {
+      const int nblk = run_blocks(p.run_lo[q], p.run_hi[q]);
+      run_sum_partials(part, p.E, slot0, nblk, k, lane, re, im);
+      slot0 += nblk;
+    } else {
+      run_sum<CT>(ca, cb, p.ldm, p.run_lo[q], p.run_hi[q], lane, re, im);
+    }
 #pragma unroll
     for (int b = 0; b < kJD; ++b)
       if (b == p.run_bin[q]) {
@@ -97,8 +107,9 @@ __device__ inline void jointd_sample(const JointDParams& p, const CT* __restrict
   r[2 * p.d + 1] = with_v ? (n >= 0.0 ? -2.0 * n : 0.0) - L : -INFINITY;
 }
 
-template <typename CT>
+template <typename CT, bool PART>
 __global__ __launch_bounds__(256) void jointd_occupations(JointDParams p, const CT* __restrict__ C,
+                                                          const float* __restrict__ part,
                                                           const double* __restrict__ nglob,
                                                           double* __restrict__ rec) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -106,7 +117,7 @@ __global__ __launch_bounds__(256) void jointd_occupations(JointDParams p, const 
   for (int j = 0; j < kOccPerWave; ++j) {
     const int64_t k = base + 4 * j;
     if (k >= p.E) return;
-    jointd_sample<CT>(p, C, nglob, rec, k, lane);
+    jointd_sample<CT, PART>(p, C, part, nglob, rec, k, lane);
   }
 }
 
@@ -652,10 +663,13 @@ size_t jointd_finalize_workspace(int32_t d, const int32_t* K) {
   return (size_t)(256 + 2 * round_up(cells * 16, 256));
 }
 
+// part != nullptr: the bin sums come from the occupation-fused GEMM's partials
+// (runs in the order fill_params builds them) and C is unused.
 mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp_precision prec,
                         mp_estimator est, int32_t d, const int32_t* bin_of_mode,
                         const int32_t* m_lo, const int32_t* K, int32_t n_sub, int64_t ns,
-                        int64_t e0, double* acc, void* ws, size_t ws_bytes, hipStream_t stream) {
+                        int64_t e0, double* acc, void* ws, size_t ws_bytes, hipStream_t stream,
+                        const float* part) {
   MP_CHECK_ARG(d >= 3 && d <= kJD, MP_ERR_UNSUPPORTED,
                "mp_binned_counts: joint distributions need d <= %d (d = %d)", kJD, d);
   for (int b = 0; b < d; ++b)
@@ -690,8 +704,12 @@ mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp
   for (int b = 0; b < d; ++b) kp_max = p.Kp[b] > kp_max ? p.Kp[b] : kp_max;
   const dim3 fgrid((unsigned)((E * kp_max + 255) / 256), (unsigned)(2 * d));
   if (prec == MP_FP64) {
-    hipLaunchKernelGGL(jointd_occupations<double>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const double*)C, n, rec);
+    if (part)
+      hipLaunchKernelGGL((jointd_occupations<float, true>), dim3(blocks), dim3(256), 0, stream, p,
+                         (const float*)nullptr, part, n, rec);
+    else
+      hipLaunchKernelGGL((jointd_occupations<double, false>), dim3(blocks), dim3(256), 0, stream,
+                         p, (const double*)C, (const float*)nullptr, n, rec);
     const mp_status sb = record_bands_launch(rec, E, d, K, kJD, band, stream);
     if (sb != MP_OK) return sb;
     hipLaunchKernelGGL(jointd_factors<double>, fgrid, dim3(256), 0, stream, p, rec, band,
@@ -700,8 +718,12 @@ mp_status jointd_launch(int32_t M, int64_t E, const void* C, const double* n, mp
       hipLaunchKernelGGL(jointd_sum_f64, dim3((unsigned)items), dim3(256), 0, stream, p, tau,
                          (const double*)tables, band, acc);
   } else {
-    hipLaunchKernelGGL(jointd_occupations<float>, dim3(blocks), dim3(256), 0, stream, p,
-                       (const float*)C, n, rec);
+    if (part)
+      hipLaunchKernelGGL((jointd_occupations<float, true>), dim3(blocks), dim3(256), 0, stream, p,
+                         (const float*)nullptr, part, n, rec);
+    else
+      hipLaunchKernelGGL((jointd_occupations<float, false>), dim3(blocks), dim3(256), 0, stream,
+                         p, (const float*)C, (const float*)nullptr, n, rec);
     const mp_status sb = record_bands_launch(rec, E, d, K, kJD, band, stream);
     if (sb != MP_OK) return sb;
     hipLaunchKernelGGL(jointd_factors<float>, fgrid, dim3(256), 0, stream, p, rec, band,

@@ -66,6 +66,44 @@ def test_fused_equals_unfused(prec, est):
     np.testing.assert_allclose(sf, su, rtol=1e-3, atol=1e-6 * scale)
 
 
+def _run_joint(fused, prec, est, d, M=333, E=1000, n_sub=5, chunk=384, seed=73, t=0.9):
+    """Joint distribution of the first d bins of _bins (d = 2: bin 2 uncounted)."""
+    import paper_2503_12749_amd as mp
+    T = t * synth.haar_unitary(M, seed)
+    r = np.linspace(0.4, 1.2, M)
+    bins = _bins(M)
+    bins[bins >= d] = -1
+    N = np.sinh(r) ** 2
+    wins = []
+    for b in range(d):
+        mb = t * t * N[bins == b].sum()
+        sb = np.sqrt(mb + (t * t) ** 2 * (N[bins == b] * (2 * N[bins == b] + 1)).sum())
+        m_lo, K = synth.count_window(mb, 1.5 * sb)
+        wins.append((m_lo, min(K, 256)))
+    p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=d, mode="joint",
+                          windows=wins, n_sub=n_sub, samples_per_sub=E // n_sub, chunk=chunk,
+                          est=est, device=DEV, fused=fused)
+    p.run()
+    P, Pi, s = p.result()
+    return P, s
+
+
+@pytest.mark.parametrize("prec,est,d", [("fp32", "matrix_p", 2), ("split_bf16", "matrix_p", 2),
+                                        ("fp32", "plus_p", 2), ("fp32", "matrix_p", 3),
+                                        ("split_bf16", "matrix_p", 3)])
+def test_fused_joint_equals_unfused(prec, est, d):
+    """Joint distributions of two and three bins through mp_propagate_counts:
+    the bin sums come from the GEMM's partials instead of C, the rest of the
+    joint path is shared, so the two agree to FP32 rounding (three chunks, one
+    of them ragged)."""
+    Pf, sf = _run_joint(True, prec, est, d)
+    Pu, su = _run_joint(False, prec, est, d)
+    scale = np.abs(Pu).max()
+    assert abs(Pf.sum() - 1) < 1e-6
+    assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-6 * scale), np.abs(Pf - Pu).max()
+    np.testing.assert_allclose(sf, su, rtol=1e-3, atol=1e-6 * scale)
+
+
 def test_fused_matches_oracle():
     """Split-BF16 fused run against the FP64 oracle on the same noise, per
     distribution (three bin marginals and the total): far inside sigma_T."""
@@ -112,8 +150,9 @@ def test_fused_rejects_unsupported_cases():
         mp.CountsPipeline(np.eye(8, dtype=complex), np.ones(8), prec="fp64", seed=1,
                           windows=[(0, 64)], n_sub=1, samples_per_sub=64, chunk=64, device=DEV,
                           fused=True).run()
-    bins = np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.int32)
+    # joint distributions of more than four bins exist on no path
+    bins = np.array([0, 0, 1, 1, 2, 2, 3, 4], dtype=np.int32)
     with pytest.raises(mp.MPError):
         mp.CountsPipeline(np.eye(8, dtype=complex), np.ones(8), prec="fp32", seed=1, bin_of_mode=bins,
-                          d=2, mode="joint", windows=[(0, 32), (0, 32)], n_sub=1,
+                          d=5, mode="joint", windows=[(0, 8)] * 5, n_sub=1,
                           samples_per_sub=64, chunk=64, device=DEV, fused=True).run()
