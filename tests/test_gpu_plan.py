@@ -120,6 +120,29 @@ def test_plan_fp32_fused_two_passes():
     plan.close()
 
 
+def test_plan_split_uneven_passes():
+    """Split-BF16 plan over chunks of 2048 with networks of one and two passes:
+    in the second pass the finished networks have no work items and no
+    partials; every network equals the fused single-network pipeline run in
+    the same chunks, bit for bit."""
+    import paper_2503_12749_amd as mp
+    nets = _nets([90, 200, 330], E=4096, n_sub=4, seed0=515)
+    nets[1]["E"] = 2048
+    nets[1]["n_sub"] = 2
+    plan = mp.Plan(nets, prec="split_bf16", chunk=2048)
+    plan.launch()
+    for i, n in enumerate(nets):
+        P, _, s = plan.result(i)
+        p = mp.CountsPipeline(n["T"], n["r"], prec="split_bf16", seed=n["seed"], net=n["net"],
+                              windows=[n["window"]], n_sub=n["n_sub"],
+                              samples_per_sub=n["E"] // n["n_sub"], chunk=2048, fused=True)
+        p.run()
+        Pr, _, sr = p.result()
+        assert np.array_equal(P, Pr) and np.array_equal(s, sr), i
+        assert abs(P.sum() - 1) < 1e-8
+    plan.close()
+
+
 def test_plan_rejects_bad_networks():
     import paper_2503_12749_amd as mp
     nets = _nets([32], E=1000, n_sub=3)
