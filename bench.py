@@ -656,7 +656,8 @@ def run_pairs_m1000(args, mp, torch, synth):
     M, E_c = w.M, w.chunk
     flops = 4.0 * M * (M + 1) * E_c  # 8 flops per complex product-sum, i <= j
     nb = -(-M // 128)
-    executed = 8.0 * nb * (nb + 1) / 2 * 128 * 128 * E_c
+    # three real MFMA products (6 flops) per tile element and sample, full tiles
+    executed = 6.0 * nb * (nb + 1) / 2 * 128 * 128 * E_c
     achieved = flops / (pair_ms * 1e-3) / 1e12
     occ_bytes = M * E_c * (16 + 8)  # C read (4 FP32 per mode), X written (2 FP32)
     log(f"[bench] pairs m1000: job {secs:.3f} s, mode occupations {occ_ms:.3f} ms, pair sums "

@@ -68,6 +68,40 @@ __device__ __attribute__((always_inline)) inline void slab(const float* are, con
   }
 }
 
+// Three-product form of one slab: P1 += Ar Br^T, P2 += Ai Bi^T,
+// P3 += (Ar + Ai)(Br + Bi)^T, so that Re = P1 - P2 and Im = P3 - P1 - P2.
+__device__ __attribute__((always_inline)) inline void slab3(const float* are, const float* aim,
+                                                             const float* bre, const float* bim,
+                                                             int wi, int wj, int lane,
+                                                             f32x16 (&p1)[2][2], f32x16 (&p2)[2][2],
+                                                             f32x16 (&p3)[2][2]) {
+  const int lr = lane & 31, lh = lane >> 5;
+#pragma unroll 4
+  for (int t = 0; t < kSlab / 2; ++t) {
+    const int kk = 2 * t + lh;
+    float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      ar[a] = are[kk * kTile + 64 * wi + 32 * a + lr];
+      ai[a] = aim[kk * kTile + 64 * wi + 32 * a + lr];
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      br[b] = bre[kk * kTile + 64 * wj + 32 * b + lr];
+      bi[b] = bim[kk * kTile + 64 * wj + 32 * b + lr];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        p1[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a], br[b], p1[a][b], 0, 0, 0);
+        p2[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a], bi[b], p2[a][b], 0, 0, 0);
+        p3[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a] + ai[a], br[b] + bi[b], p3[a][b], 0,
+                                                        0, 0);
+      }
+  }
+}
+
 // Tile row and column of output register q of 32 x 32 block (a, b).
 __device__ __attribute__((always_inline)) inline int out_row(int wi, int a, int q, int lane) {
   return 64 * wi + 32 * a + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
