@@ -185,87 +185,6 @@ struct Slab {
   }
 };
 
-// ---------------------------------------------------------------- FP64
-
-// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16]; output
-// register r is row (l/16) + 4 r, column l%16.  Within one BK = 16 slab lane
-// group h = l/16 supplies k = 4h + s at MFMA step s (the same permutation of
-// k on both operands), so each lane reads 4 consecutive doubles per row.
-__global__ __launch_bounds__(kThreads) void gemm_f64(const double* __restrict__ A,
-                                                     const double* __restrict__ B,
-                                                     double* __restrict__ C, int64_t ldm,
-                                                     int64_t ncols, int order) {
-  constexpr int BK = 16, LDK = BK + 2;
-  __shared__ __attribute__((aligned(16))) double sA[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) double sB[2][BN * LDK];
-  const int tiles_m = (int)(2 * ldm / BM), tiles_n = (int)((ncols + BN - 1) / BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 15, lh = lane >> 4;
-
-  f64x4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
-
-  Slab<double, BK> la, lb;
-  const int KT = (int)(ldm / BK);
-  la.load(A, ldm, m0, 0, 2 * ldm);
-  lb.load(B, ldm, n0, 0, ncols);
-  la.store<LDK>(sA[0]);
-  lb.store<LDK>(sB[0]);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) {
-      la.load(A, ldm, m0, (int64_t)(kt + 1) * BK, 2 * ldm);
-      lb.load(B, ldm, n0, (int64_t)(kt + 1) * BK, ncols);
-    }
-    double a[4][4], b[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double* pa = sA[cur] + (wm * 64 + i * 16 + lr) * LDK + 4 * lh;
-      const double* pb = sB[cur] + (wn * 64 + i * 16 + lr) * LDK + 4 * lh;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        a[i][s] = pa[s];
-        b[i][s] = pb[s];
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-    if (kt + 1 < KT) {
-      la.store<LDK>(sA[cur ^ 1]);
-      lb.store<LDK>(sB[cur ^ 1]);
-    }
-    __syncthreads();
-  }
-  const int64_t ldc = 2 * ldm;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int64_t col = n0 + wn * 64 + j * 16 + lr;
-    if (col >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      // the f64 16x16 output interleaves rows: register r holds row lh + 4 r
-      double* p = C + col * ldc + m0 + wm * 64 + i * 16 + lh;
-      p[0] = acc[i][j][0];
-      p[4] = acc[i][j][1];
-      p[8] = acc[i][j][2];
-      p[12] = acc[i][j][3];
-    }
-  }
-}
-
 // ---------------------------------------------------------------- FP32
 
 // v_mfma_f32_32x32x2f32: lane l holds A[l%32][l/32], B[l/32][l%32]; output
@@ -422,6 +341,159 @@ template <int N>
 __device__ inline void wait_vm() {
   // s_waitcnt vmcnt(N), expcnt and lgkmcnt unconstrained (gfx9 encoding)
   __builtin_amdgcn_s_waitcnt(((N & 15) | ((N >> 4) << 14)) | (7 << 4) | (15 << 8));
+}
+
+// s_waitcnt lgkmcnt(0), vmcnt and expcnt unconstrained
+__device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4)); }
+
+// ---------------------------------------------------------------- FP64, 128 x 256
+
+// FP64 tile of 128 rows x 256 columns: four waves of 64 x 128 (4 x 8 blocks
+// of v_mfma_f64_16x16x4f64, 128 accumulators per lane, one wave per SIMD),
+// 16-deep slabs loaded direct-to-LDS into two stages of 384 rows (A rows, then
+// B rows) of 16 doubles.  16-byte chunk c of stage row r sits at slot
+// c ^ (r & 7), so the 16-byte fragment reads of eight consecutive rows touch
+// every bank once.  The MFMA takes A[l % 16][l / 16] and B[l / 16][l % 16]
+// from lane l; within a slab lane group h = l / 16 supplies k = 4 h + s at
+// MFMA step s (s = 0..3, the same permutation on both operands): the doubles
+// 4 h .. 4 h + 3 of its row, two 16-byte reads per block.  Output register r
+// of lane l is row l / 16 + 4 r, column l % 16 of a block.
+constexpr int D_BM = 128, D_BN = 256, D_BK = 16;
+constexpr int D_ROWS = D_BM + D_BN;  // stage rows
+// stages of 48 KB; three (loads issued two slabs ahead) measured 1.6 % slower
+constexpr int D_NST = 2;
+
+typedef __attribute__((ext_vector_type(2))) double f64x2;
+
+__global__ __launch_bounds__(kThreads, 1) void gemm_f64_pp(const double* __restrict__ A,
+                                                           const double* __restrict__ B,
+                                                           double* __restrict__ C, int64_t ldm,
+                                                           int64_t ncols, int order) {
+  __shared__ __attribute__((aligned(1024))) double lds[D_NST][D_ROWS * D_BK];
+  const int tiles_m = (int)(2 * ldm / D_BM), tiles_n = (int)((ncols + D_BN - 1) / D_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  const int64_t m0 = (int64_t)tm * D_BM, n0 = (int64_t)tn * D_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lh = lane >> 4;
+
+  // loader: instruction q of wave w fills stage rows 96 w + 8 q .. + 7 (1 KB):
+  // lane l writes slot l % 8 of row 96 w + 8 q + l / 8, i.e. its global chunk
+  // (l % 8) ^ (row & 7); B columns past the chunk repeat the last one
+  const double* src[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int r = 96 * wave + 8 * q + (lane >> 3);
+    const int c = (lane & 7) ^ (r & 7);
+    if (r < D_BM) {
+      src[q] = A + (m0 + r) * ldm + 2 * c;
+    } else {
+      int64_t col = n0 + (r - D_BM);
+      col = col < ncols ? col : ncols - 1;
+      src[q] = B + col * ldm + 2 * c;
+    }
+  }
+  auto issue = [&](int st, int64_t k0) {
+    char* dst = (char*)&lds[st][0] + 96 * wave * D_BK * 8;
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src[q] + k0), (lds_void*)(dst + q * 1024), 16,
+                                       0, 0);
+  };
+  // fragment offsets (doubles) of chunk 2 lh + half for the wave's row blocks
+  int oa[2][4], ob[2][8];
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 64 + i * 16 + lr;
+      oa[hf][i] = r * D_BK + 2 * ((2 * lh + hf) ^ (r & 7));
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int r = D_BM + wn * 128 + j * 16 + lr;
+      ob[hf][j] = r * D_BK + 2 * ((2 * lh + hf) ^ (r & 7));
+    }
+  }
+
+  f64x4 acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+
+  // fragments of one half slab: k steps 2 hf, 2 hf + 1 of every row block
+  auto frag = [&](int st, int hf, f64x2(&a)[4], f64x2(&b)[8]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const f64x2*)&lds[st][oa[hf][i]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = *(const f64x2*)&lds[st][ob[hf][j]];
+  };
+  auto mma = [&](const f64x2(&a)[4], const f64x2(&b)[8]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+  };
+
+  // Pipeline: slab kt + 2 is loaded while slab kt is multiplied; the second
+  // half of slab kt is read while its first half is multiplied, and the first
+  // half of slab kt + 1 while its second half is.  The one barrier per slab
+  // sits between the halves: past it every wave has read all of stage
+  // kt & 1 (so it may be refilled) and every wave's loads of slab kt + 1 have
+  // landed (so it may be read).
+  const int KT = (int)(ldm / D_BK);
+  f64x2 a0[4], b0[8], a1[4], b1[8];
+  // prologue: slabs 0 .. D_NST - 1 in flight (KT >= 8 since ldm is a multiple
+  // of 128), then wait for slab 0: loads complete in order, so the 12 loads
+  // of each younger slab may stay outstanding
+#pragma unroll
+  for (int st = 0; st < D_NST; ++st) issue(st, (int64_t)st * D_BK);
+  wait_vm<12 * (D_NST - 1)>();
+  barrier_no_fence();
+  frag(0, 0, a0, b0);
+  // One basic block per slab, the same for every slab: a branch in the body
+  // or a peeled last slab made the compiler keep the accumulators in
+  // different registers in the two halves and copy them every slab.  Past
+  // the end the loads re-fetch the last slab into the stage just freed and
+  // the last first-half read fetches a stage whose loads have been waited
+  // for; neither result is used.
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt % D_NST, nxt = (kt + 1) % D_NST;
+    frag(cur, 1, a1, b1);
+    mma(a0, b0);
+    // keep the products on their side of the barrier (the scheduler would
+    // otherwise sink them below it and expose the read latency)
+    __builtin_amdgcn_sched_barrier(0);
+    wait_lgkm0();  // this wave's reads of stage cur are done
+    // this wave's loads of slab kt + 1 have landed; every iteration issues
+    // 12 loads, so those of the D_NST - 2 younger ones may stay in flight
+    wait_vm<12 * (D_NST - 2)>();
+    barrier_no_fence();
+    issue(cur, (int64_t)min(kt + D_NST, KT - 1) * D_BK);
+    frag(nxt, 0, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
+  }
+  wait_vm<0>();  // no direct-to-LDS write may outlive the workgroup
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 16 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double* p = C + col * ldc + m0 + wm * 64 + i * 16 + lh;
+      p[0] = acc[i][j][0];
+      p[4] = acc[i][j][1];
+      p[8] = acc[i][j][2];
+      p[12] = acc[i][j][3];
+    }
+  }
 }
 
 // Occupation-fused epilogue (see FusedOut).  The tile covers modes
@@ -1044,8 +1116,9 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
   const int64_t ldm = ld_modes(M), ncols = 2 * E;
   switch (prec) {
     case MP_FP64:
-      hipLaunchKernelGGL(gemm_f64, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0, stream,
-                         (const double*)packed, (const double*)ab, (double*)C, ldm, ncols, tile_order());
+      hipLaunchKernelGGL(gemm_f64_pp, dim3(grid_tiles(ldm, ncols, D_BM, D_BN)), dim3(kThreads), 0,
+                         stream, (const double*)packed, (const double*)ab, (double*)C, ldm, ncols,
+                         tile_order());
       break;
     case MP_FP32:
       if (f32_variant() == 1)
