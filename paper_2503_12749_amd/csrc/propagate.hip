@@ -462,10 +462,18 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f64_pp(const double* __restr
   // the end the loads re-fetch the last slab into the stage just freed and
   // the last first-half read fetches a stage whose loads have been waited
   // for; neither result is used.
+  // scheduling-group masks: MFMA, LDS read, global (direct-to-LDS) load
+  constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt % D_NST, nxt = (kt + 1) % D_NST;
     frag(cur, 1, a1, b1);
     mma(a0, b0);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 52, 0);
     // keep the products on their side of the barrier (the scheduler would
     // otherwise sink them below it and expose the read latency)
     __builtin_amdgcn_sched_barrier(0);
@@ -474,10 +482,24 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f64_pp(const double* __restr
     // 12 loads, so those of the D_NST - 2 younger ones may stay in flight
     wait_vm<12 * (D_NST - 2)>();
     barrier_no_fence();
+    __builtin_amdgcn_sched_barrier(0);
+    // the second half's products start right after the barrier, with the
+    // loads and the next slab's first-half reads threaded between them
     issue(cur, (int64_t)min(kt + D_NST, KT - 1) * D_BK);
     frag(nxt, 0, a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
     mma(a1, b1);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 40, 1);
+    __builtin_amdgcn_sched_barrier(0);
   }
   wait_vm<0>();  // no direct-to-LDS write may outlive the workgroup
   const int64_t ldc = 2 * ldm;
