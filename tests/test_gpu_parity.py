@@ -66,8 +66,13 @@ def test_sampler_matches_oracle_fp64():
     assert torch.all(raw[:, M:] == 0)
 
 
-@pytest.mark.parametrize("M,E", [(16, 1000), (200, 333), (1, 7), (257, 130)])
+@pytest.mark.parametrize("M,E", [(16, 1000), (200, 333), (1, 7), (257, 130), (1000, 3000),
+                                 (2049, 1100)])
 def test_propagate_fp64_matches_oracle(M, E):
+    """FP64 GEMM against the oracle element by element.  The FP64 tile is 128
+    rows x 256 columns over 16-deep slabs: the cases span two to 34 row tiles
+    (the last of the larger ones a partial group of eight in the tile order),
+    8 to 136 slabs, and ragged last column tiles (2E = 14 ... 6000)."""
     T = 0.8 * synth.haar_unitary(M, 100 + M)
     r = synth.squeezing_random_uniform(M, 0.3, 1.2, M)
     p = _pipe(T, r, prec="fp64", seed=9, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
