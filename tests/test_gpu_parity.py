@@ -197,9 +197,12 @@ def test_lossless_odd_counts_vanish():
     assert np.all(np.abs(P - ref)[bulk] < 5 * s[bulk])
 
 
+@pytest.mark.parametrize("M,E", [(300, 200), (2049, 1100)])
 @pytest.mark.parametrize("prec,rel", [("fp32", 2e-6), ("split_bf16", 2e-5), ("split_fp16", 4e-6)])
-def test_reduced_precision_propagation(prec, rel):
-    M, E = 300, 200
+def test_reduced_precision_propagation(prec, rel, M, E):
+    """Every element against the oracle, relative to the largest per-sample
+    norm of the propagated amplitudes.  M = 2049 (ldm 2176, with the split
+    kernels' L2 prefetch) spans 17 row tiles of 256 and 68 slabs of 32."""
     T = 0.95 * synth.haar_unitary(M, 12)
     r = np.full(M, 1.0)
     p = _pipe(T, r, prec=prec, seed=5, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
