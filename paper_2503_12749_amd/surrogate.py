@@ -24,6 +24,7 @@ import argparse
 import ctypes
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -177,8 +178,9 @@ def generate(runner, sweeps, E, net0=0, log_every=0):
     for i, s in enumerate(sweeps):
         Y[i], _ = runner.run(*s, E=E, net=net0 + i)
         if log_every and (i + 1) % log_every == 0:
+            # progress goes to stderr: stdout carries the caller's result line
             print(f"[surrogate] {i + 1}/{len(sweeps)} sweeps, {time.perf_counter() - t0:.1f} s",
-                  flush=True)
+                  file=sys.stderr, flush=True)
     return X, Y
 
 
