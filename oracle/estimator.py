@@ -126,6 +126,8 @@ def estimate(T, r, seed, E, n_sub, bin_of_mode, d, windows, mode="joint",
     [(m_lo, K)] * d (d = 1 gives the total counts of the counted modes).
     mode "marginals": d separate one-bin distributions (S = S_b alone), each
     on its own window.
+    mode "marginals_and_total": those d distributions plus the total count of
+    all d bins (S = the union of the bins), d + 1 windows, the total last.
     Returns dict(P=real estimate, sigma=sigma_T, P_complex, Ps=sub-ensemble
     means, counts=list of count arrays)."""
     assert E % n_sub == 0
@@ -136,8 +138,9 @@ def estimate(T, r, seed, E, n_sub, bin_of_mode, d, windows, mode="joint",
         shape = tuple(len(c) for c in counts)
         nterm = 1
     else:
-        shape = (d, max(len(c) for c in counts))
-        nterm = d
+        nterm = d + 1 if mode == "marginals_and_total" else d
+        assert len(counts) == nterm
+        shape = (nterm, max(len(c) for c in counts))
     sums = np.zeros((n_sub,) + shape, dtype=np.complex128)
     done = 0
     while done < E:
@@ -149,6 +152,8 @@ def estimate(T, r, seed, E, n_sub, bin_of_mode, d, windows, mode="joint",
         if mode == "joint":
             G = pattern_probability(n, nb, counts, plus_p)
         else:
+            if nterm > d:  # the total of the counted modes, S = S_1 + .. + S_d
+                nb = np.concatenate([nb, nb.sum(axis=1, keepdims=True)], axis=1)
             G = np.zeros((c,) + shape, dtype=np.complex128)
             for b in range(nterm):
                 Gb = pattern_probability(n, nb[:, b:b + 1], [counts[b]], plus_p)

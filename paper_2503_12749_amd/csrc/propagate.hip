@@ -9,11 +9,11 @@
 // modes) and C column-major.  Both operands are K-contiguous, so every lane of
 // a wavefront feeds its MFMA fragment from one 16-byte LDS read.
 //
-// Kernels: FP64 (v_mfma_f64_16x16x4, 128 x 128 tiles), FP32
+// Kernels: FP64 (v_mfma_f64_16x16x4, 128 x 256 tiles), FP32
 // (v_mfma_f32_32x32x2, 256 x 256 tiles) and split BF16/FP16 (three
 // v_mfma_f32_32x32x16 products hi*hi + hi*lo + lo*hi with FP32 accumulation,
 // 256 x 256 tiles).  The 256 x 256 kernels feed LDS with direct global-to-LDS
-// loads in a two-stage ping-pong schedule, and every tile order keeps the
+// loads in a two-stage ping-pong schedule, and the tile order keeps the
 // workgroups of one XCD on neighbouring tiles that share rows of A and
 // columns of B in its L2.
 //
@@ -21,8 +21,6 @@
 // B) alternates a block of 32 hi values with the block of the 32 matching lo
 // values, so one 32-deep k-slab of a row is one full 128-byte line.
 #include <hip/hip_runtime.h>
-
-#include <cstdlib>
 
 #include "common.h"
 
@@ -35,11 +33,8 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
 typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 
-constexpr int BM = 128;  // tile rows (output rows of C)
-constexpr int BN = 128;  // tile columns (samples, alpha and beta columns)
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;     // MI355X: 8 XCDs, workgroups dispatched round-robin
-constexpr int kGroupM = 8;   // row tiles per group in the grouped tile order
 
 // ---------------------------------------------------------------- packing
 
@@ -90,26 +85,15 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
 
 // Tile order.  Blocks are dispatched to the XCDs round-robin, so block b
 // runs on XCD b % 8 and, with one workgroup per CU, the 32 blocks
-// b / 8 = 32 s .. 32 s + 31 of every XCD run together in "step" s.
-//
-// Order 1 (default): in each step all eight XCDs work on the same group of 8
-// row tiles, each XCD on its own 4 column tiles, and consecutive steps move
-// along the columns.  The A rows of a group are then shared by every XCD
-// through the infinity cache (MALL) and fetched from HBM about once per
-// group, instead of once per XCD and column block.
-// Order 0: each XCD takes one contiguous range of a sequence grouped by 8
-// row tiles (XCD-local L2 reuse only).
+// b / 8 = 32 s .. 32 s + 31 of every XCD run together in "step" s.  In each
+// step all eight XCDs work on the same group of 8 row tiles, each XCD on its
+// own 4 column tiles, and consecutive steps move along the columns.  The A
+// rows of a group are then shared by every XCD through the infinity cache
+// (MALL) and fetched from HBM about once per group, instead of once per XCD
+// and column block (measured faster than XCD-local groups of 8 row tiles).
 constexpr int kStepRows = 8, kStepColsPerXcd = 4;
 
-static int tile_order() {
-  static int v = [] {
-    const char* e = getenv("MPGBS_TILE_ORDER");
-    return e ? atoi(e) : 1;
-  }();
-  return v;
-}
-
-__device__ inline bool tile_of_block_mall(int tiles_m, int tiles_n, int& tm, int& tn) {
+__device__ inline bool tile_of_block(int tiles_m, int tiles_n, int& tm, int& tn) {
   const int b = blockIdx.x, x = b % kXcds, q = b / kXcds;
   const int per_xcd = kStepRows * kStepColsPerXcd;   // 32 blocks of one XCD per step
   const int s = q / per_xcd, j = q % per_xcd;
@@ -125,143 +109,6 @@ __host__ __device__ inline int mall_grid_blocks(int tiles_m, int tiles_n) {
   const int n_cg = (tiles_n + kXcds * kStepColsPerXcd - 1) / (kXcds * kStepColsPerXcd);
   const int n_rg = (tiles_m + kStepRows - 1) / kStepRows;
   return n_rg * n_cg * kXcds * kStepRows * kStepColsPerXcd;
-}
-
-__device__ inline bool tile_of_block_grouped(int tiles_m, int tiles_n, int& tm, int& tn) {
-  int total = tiles_m * tiles_n;
-  int per_xcd = (total + kXcds - 1) / kXcds;
-  int b = blockIdx.x;
-  int t = (b % kXcds) * per_xcd + b / kXcds;
-  if (t >= total) return false;
-  int group = kGroupM * tiles_n;
-  int gid = t / group;
-  int first_m = gid * kGroupM;
-  int gsize = min(kGroupM, tiles_m - first_m);
-  int r = t % group;
-  tm = first_m + r % gsize;
-  tn = r / gsize;
-  return true;
-}
-
-__device__ inline bool tile_of_block(int tiles_m, int tiles_n, int order, int& tm, int& tn) {
-  return order == 1 ? tile_of_block_mall(tiles_m, tiles_n, tm, tn)
-                    : tile_of_block_grouped(tiles_m, tiles_n, tm, tn);
-}
-
-// ---------------------------------------------------------------- loaders
-
-// Global -> register staging of one K-slab of a 128-row (or 128-column)
-// operand tile: 128 rows of BK contiguous elements, as 16-byte vectors.
-template <typename E, int BK>
-struct Slab {
-  static constexpr int kVec = 16 / sizeof(E);
-  static constexpr int kVecsPerRow = BK / kVec;
-  static constexpr int kPerThread = 128 * kVecsPerRow / kThreads;
-  u32x4 v[kPerThread];
-
-  // rows are valid when row < nrows (columns of B beyond 2E read as zero)
-  __device__ inline void load(const E* __restrict__ base, int64_t ld, int64_t row0, int64_t k0,
-                              int64_t nrows) {
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      int vi = threadIdx.x + i * kThreads;
-      int row = vi / kVecsPerRow, kv = vi % kVecsPerRow;
-      int64_t grow = row0 + row;
-      if (grow < nrows) {
-        v[i] = *(const u32x4*)(base + grow * ld + k0 + kv * kVec);
-      } else {
-        v[i] = u32x4{0, 0, 0, 0};
-      }
-    }
-  }
-  template <int LDK>
-  __device__ inline void store(E* lds) const {
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      int vi = threadIdx.x + i * kThreads;
-      int row = vi / kVecsPerRow, kv = vi % kVecsPerRow;
-      *(u32x4*)(lds + row * LDK + kv * kVec) = v[i];
-    }
-  }
-};
-
-// ---------------------------------------------------------------- FP32
-
-// v_mfma_f32_32x32x2f32: lane l holds A[l%32][l/32], B[l/32][l%32]; output
-// register r is row 8 (r/4) + 4 (l/32) + r%4, column l%32.  Within one
-// BK = 32 slab lane half h supplies k = 16h + s at step s.
-__global__ __launch_bounds__(kThreads) void gemm_f32(const float* __restrict__ A,
-                                                     const float* __restrict__ B,
-                                                     float* __restrict__ C, int64_t ldm,
-                                                     int64_t ncols, int order) {
-  constexpr int BK = 32, LDK = BK + 4;
-  __shared__ __attribute__((aligned(16))) float sA[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) float sB[2][BN * LDK];
-  const int tiles_m = (int)(2 * ldm / BM), tiles_n = (int)((ncols + BN - 1) / BN);
-  int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 31, lh = lane >> 5;
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  Slab<float, BK> la, lb;
-  const int KT = (int)(ldm / BK);
-  la.load(A, ldm, m0, 0, 2 * ldm);
-  lb.load(B, ldm, n0, 0, ncols);
-  la.store<LDK>(sA[0]);
-  lb.store<LDK>(sB[0]);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) {
-      la.load(A, ldm, m0, (int64_t)(kt + 1) * BK, 2 * ldm);
-      lb.load(B, ldm, n0, (int64_t)(kt + 1) * BK, ncols);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {  // 4 groups of 4 consecutive k per lane
-      f32x4 a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = *(const f32x4*)(sA[cur] + (wm * 64 + i * 32 + lr) * LDK + 16 * lh + 4 * q);
-        b[i] = *(const f32x4*)(sB[cur] + (wn * 64 + i * 32 + lr) * LDK + 16 * lh + 4 * q);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < KT) {
-      la.store<LDK>(sA[cur ^ 1]);
-      lb.store<LDK>(sB[cur ^ 1]);
-    }
-    __syncthreads();
-  }
-  const int64_t ldc = 2 * ldm;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    int64_t col = n0 + wn * 64 + j * 32 + lr;
-    if (col >= ncols) continue;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        int64_t row = m0 + wm * 64 + i * 32 + 8 * g + 4 * lh;
-        *(f32x4*)(C + col * ldc + row) =
-            f32x4{acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]};
-      }
-  }
 }
 
 // ---------------------------------------------------------------- split, 256 x 256
@@ -368,11 +215,11 @@ typedef __attribute__((ext_vector_type(2))) double f64x2;
 __global__ __launch_bounds__(kThreads, 1) void gemm_f64_pp(const double* __restrict__ A,
                                                            const double* __restrict__ B,
                                                            double* __restrict__ C, int64_t ldm,
-                                                           int64_t ncols, int order) {
+                                                           int64_t ncols) {
   __shared__ __attribute__((aligned(1024))) double lds[D_NST][D_ROWS * D_BK];
   const int tiles_m = (int)(2 * ldm / D_BM), tiles_n = (int)((ncols + D_BN - 1) / D_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * D_BM, n0 = (int64_t)tn * D_BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -815,12 +662,12 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_256_pp(const uint16_t*
                                                                  const uint16_t* __restrict__ B,
                                                                  float* __restrict__ C,
                                                                  int64_t ldm, int64_t ncols,
-                                                                 float out_scale, int order) {
+                                                                 float out_scale) {
   __shared__ __attribute__((aligned(1024))) uint16_t lds_raw[kSplitLdsElems];
   uint16_t (*lds)[4][S_PLANE] = (uint16_t (*)[4][S_PLANE])lds_raw;
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
   split_pp_tile<H, false, PF>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN,
                               out_scale, nullptr);
 }
@@ -831,13 +678,12 @@ template <typename H, bool PF>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __restrict__ A,
                                                               const uint16_t* __restrict__ B,
                                                               int64_t ldm, int64_t ncols,
-                                                              float out_scale, int order,
-                                                              FusedOut fo) {
+                                                              float out_scale, FusedOut fo) {
   __shared__ __attribute__((aligned(1024))) uint16_t lds_raw[kSplitLdsElems];
   uint16_t (*lds)[4][S_PLANE] = (uint16_t (*)[4][S_PLANE])lds_raw;
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
   split_pp_tile<H, true, PF>(lds, A, B, nullptr, ldm, ncols, (int64_t)tm * 128, (int64_t)tn * 128,
                              out_scale, &fo);
 }
@@ -866,11 +712,11 @@ template <bool FUSED>
 __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restrict__ A,
                                                            const float* __restrict__ B,
                                                            float* __restrict__ C, int64_t ldm,
-                                                           int64_t ncols, int order, FusedOut fo) {
+                                                           int64_t ncols, FusedOut fo) {
   __shared__ __attribute__((aligned(1024))) float lds[2][2][F_PLANE];
   const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
   int tm, tn;
-  if (!tile_of_block(tiles_m, tiles_n, order, tm, tn)) return;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
   const int64_t m0 = (int64_t)tm * (FUSED ? 128 : S_BM), n0 = (int64_t)tn * (FUSED ? 128 : S_BN);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -1064,22 +910,8 @@ size_t propagate_workspace(int32_t M, mp_precision prec) {
   }
 }
 
-// FP32 GEMM variant: 1 = 256 x 256 direct-to-LDS ping-pong (default),
-// 0 = 128 x 128 register staging.
-static int f32_variant() {
-  static int v = [] {
-    const char* e = getenv("MPGBS_F32_VARIANT");
-    return e ? atoi(e) : 1;
-  }();
-  return v;
-}
-
 static int grid_tiles(int64_t ldm, int64_t ncols, int bm, int bn) {
-  const int tiles_m = (int)(2 * ldm / bm), tiles_n = (int)((ncols + bn - 1) / bn);
-  if (tile_order() == 1) return mall_grid_blocks(tiles_m, tiles_n);
-  const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  const int64_t per = (tiles + kXcds - 1) / kXcds;
-  return (int)(per * kXcds);
+  return mall_grid_blocks((int)(2 * ldm / bm), (int)((ncols + bn - 1) / bn));
 }
 
 // Power-of-two prescale of T for the FP16 split operand: |T_ij| ~ M^-1/2 for
@@ -1128,7 +960,7 @@ static void split_gemm(int grid, hipStream_t stream, const void* packed, const v
                        int64_t ldm, int64_t ncols, float scale) {
   auto kernel = split_prefetch_for(ldm) ? gemm_split_256_pp<H, true> : gemm_split_256_pp<H, false>;
   hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
-                     (const uint16_t*)ab, (float*)C, ldm, ncols, scale, tile_order());
+                     (const uint16_t*)ab, (float*)C, ldm, ncols, scale);
 }
 
 bool split_prefetch(int64_t ldm) { return split_prefetch_for(ldm); }
@@ -1139,18 +971,12 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
   switch (prec) {
     case MP_FP64:
       hipLaunchKernelGGL(gemm_f64_pp, dim3(grid_tiles(ldm, ncols, D_BM, D_BN)), dim3(kThreads), 0,
-                         stream, (const double*)packed, (const double*)ab, (double*)C, ldm, ncols,
-                         tile_order());
+                         stream, (const double*)packed, (const double*)ab, (double*)C, ldm, ncols);
       break;
     case MP_FP32:
-      if (f32_variant() == 1)
-        hipLaunchKernelGGL(gemm_f32_pp<false>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
-                           dim3(kThreads), 0, stream, (const float*)packed, (const float*)ab,
-                           (float*)C, ldm, ncols, tile_order(), FusedOut{});
-      else
-        hipLaunchKernelGGL(gemm_f32, dim3(grid_tiles(ldm, ncols, BM, BN)), dim3(kThreads), 0,
-                           stream, (const float*)packed, (const float*)ab, (float*)C, ldm, ncols,
-                           tile_order());
+      hipLaunchKernelGGL(gemm_f32_pp<false>, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)),
+                         dim3(kThreads), 0, stream, (const float*)packed, (const float*)ab,
+                         (float*)C, ldm, ncols, FusedOut{});
       break;
     case MP_SPLIT_BF16:
       split_gemm<__bf16>(grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab, C, ldm, ncols,
@@ -1195,21 +1021,19 @@ mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precisi
   switch (prec) {
     case MP_FP32:
       hipLaunchKernelGGL(gemm_f32_pp<true>, dim3(grid), dim3(kThreads), 0, stream,
-                         (const float*)packed, (const float*)ab, (float*)nullptr, ldm, ncols,
-                         tile_order(), fo);
+                         (const float*)packed, (const float*)ab, (float*)nullptr, ldm, ncols, fo);
       break;
     case MP_SPLIT_BF16: {
       auto kernel = split_prefetch_for(ldm) ? gemm_split_occ<__bf16, true> : gemm_split_occ<__bf16, false>;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
-                         (const uint16_t*)ab, ldm, ncols, 1.0f, tile_order(), fo);
+                         (const uint16_t*)ab, ldm, ncols, 1.0f, fo);
       break;
     }
     case MP_SPLIT_FP16: {
       auto kernel =
           split_prefetch_for(ldm) ? gemm_split_occ<_Float16, true> : gemm_split_occ<_Float16, false>;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
-                         (const uint16_t*)ab, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)),
-                         tile_order(), fo);
+                         (const uint16_t*)ab, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)), fo);
       break;
     }
     default:
