@@ -314,21 +314,10 @@ def run_precision_m4000(args, mp, torch, synth):
     of 8192): every precision on the same noise, each result compared with
     the FP64 GPU path (itself pinned to the oracle) bin by bin, in units of
     the FP64 run's sigma_T."""
-    M, t = 4000, 0.95
-    seed = synth.SEED_BASE + 2
-    r = synth.squeezing_random_uniform(M, 0.5, 1.5, seed)
-    T = synth.transmission(M, t, seed)
-    bins = synth.contiguous_bins(M, 4)
-    N = np.sinh(r) ** 2
-    wins = []
-    for b in range(4):
-        mb = t * t * N[bins == b].sum()
-        sb = np.sqrt(mb + (t * t) ** 2 * (N[bins == b] * (2 * N[bins == b] + 1)).sum())
-        wins.append(synth.count_window(mb, sb * 1.3))
-    mt, stt = synth.uniform_loss_moments(r, t)
-    wins.append(synth.count_window(mt, stt))
     chunk, ns = 65536, 8192
-    E = 15 * chunk
+    w = synth.workload_m4000(E=15 * chunk, chunk=chunk, ns=ns)
+    M, T, r, seed, bins, wins = w.M, w.T, w.r, w.seed, w.bins, w.windows
+    E = w.E
     res = {}
     for prec in ("fp64", "fp32", "split_bf16", "split_fp16"):
         p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=4,
@@ -375,17 +364,9 @@ def run_batched(args, mp, torch, synth):
     captured hipGraph with one persistent grouped GEMM launch with the
     occupation-fused epilogue per pass over chunks of 1e5) against the same
     networks run one after another through the fused CountsPipeline."""
-    rng = np.random.default_rng(synth.SEED_BASE + 7)
-    Ms = [500] * 4 + [1000] * 4 + [2000] * 4 + [4000] * 4
     E, n_sub, chunk = 200_000, 20, 100_000
-    nets = []
-    for i, M in enumerate(Ms):
-        t = float(rng.uniform(0.85, 0.99))
-        r = np.ones(M)
-        mean, sd = synth.uniform_loss_moments(r, t)
-        nets.append(dict(T=synth.transmission(M, t, synth.SEED_BASE + 100 + i), r=r,
-                         seed=synth.SEED_BASE + 7, net=i, E=E, n_sub=n_sub,
-                         window=synth.count_window(mean, sd)))
+    Ms = synth.BATCHED_SIZES
+    nets = synth.batched_networks(E=E, n_sub=n_sub)
     log("[bench] batched: networks ready, creating the plan (autotunes the work-list order)")
     t0 = time.perf_counter()
     plan = mp.Plan(nets, prec="split_fp16", chunk=chunk)

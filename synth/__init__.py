@@ -149,3 +149,46 @@ def workload_m8000(E: int = 589_824, chunk: int = 65_536, with_T: bool = True) -
     n_sub = max(1, E // 8192)
     return Workload("M8000_t0.95_r1", M, t, r, T, E, n_sub, seed, all_modes_bin(M), 1,
                     [count_window(mean, sd)], chunk)
+
+
+def workload_m4000(E: int = 983_040, chunk: int = 65_536, ns: int = 8192,
+                   with_T: bool = True) -> Workload:
+    """M = 4000, Haar x t = 0.95, r_j ~ U[0.5, 1.5], four equal mode blocks:
+    their four marginal distributions and the total (windows in that order;
+    the block windows take 1.3x the independent-mode sd as margin for the
+    network correlations inside a block)."""
+    M, t = 4000, 0.95
+    seed = SEED_BASE + 2
+    r = squeezing_random_uniform(M, 0.5, 1.5, seed)
+    T = transmission(M, t, seed) if with_T else None
+    bins = contiguous_bins(M, 4)
+    N = np.sinh(r) ** 2
+    wins = []
+    for b in range(4):
+        Nb = N[bins == b]
+        mb = t * t * Nb.sum()
+        sb = math.sqrt(mb + (t * t) ** 2 * (Nb * (2 * Nb + 1)).sum())
+        wins.append(count_window(mb, sb * 1.3))
+    wins.append(count_window(*uniform_loss_moments(r, t)))
+    return Workload("M4000_t0.95_rU[0.5,1.5]", M, t, r, T, E, E // ns, seed, bins, 4, wins, chunk)
+
+
+BATCHED_SIZES = [500] * 4 + [1000] * 4 + [2000] * 4 + [4000] * 4
+
+
+def batched_networks(E: int = 200_000, n_sub: int = 20, indices=None) -> list[dict]:
+    """The sixteen networks of the batched workload (4 each of M = 500, 1000,
+    2000, 4000; t ~ U[0.85, 0.99]; r = 1; total counts), as dicts with keys
+    T, r, seed, net, E, n_sub, window, t.  `indices` selects networks (their
+    parameters do not depend on the selection)."""
+    rng = np.random.default_rng(SEED_BASE + 7)
+    ts = [float(rng.uniform(0.85, 0.99)) for _ in BATCHED_SIZES]
+    out = []
+    for i, M in enumerate(BATCHED_SIZES):
+        if indices is not None and i not in indices:
+            continue
+        t = ts[i]
+        r = np.ones(M)
+        out.append(dict(T=transmission(M, t, SEED_BASE + 100 + i), r=r, seed=SEED_BASE + 7, net=i,
+                        E=E, n_sub=n_sub, window=count_window(*uniform_loss_moments(r, t)), t=t))
+    return out

@@ -70,9 +70,12 @@ def _name(code):
 
 @pytest.mark.parametrize("prec", ["split_bf16", "fp32", "split_fp16"])
 def test_m8000_bench_launch(m8000, prec):
-    """M = 8000, t = 0.95, r = 1, one 65536-sample chunk as bench.py launches
-    it: sampled columns against the oracle, then the whole chunk's total-count
-    distribution against the closed-form moments."""
+    """M = 8000, t = 0.95, r = 1, one 65536-sample chunk through the unfused
+    path (mp_propagate writing C, then the counting kernels reading C; the
+    occupation-fused launch the benchmark times is compared with the oracle
+    bin by bin in test_gpu_oracle_fullsize): sampled columns against the
+    oracle, then the whole chunk's total-count distribution against the
+    closed-form moments."""
     import paper_2503_12749_amd as mp
     w = m8000
     E = 65536
@@ -114,7 +117,8 @@ def test_m4000_precision_study_per_bin():
     """M = 4000, t = 0.95, r_j ~ U[0.5, 1.5], four equal mode blocks
     (marginals + total): the split-BF16 and split-FP16 estimates differ from
     the FP64 GPU path on the same noise by a small fraction of sigma_T in
-    every bin, and the FP64 path's sampled columns match the oracle."""
+    every bin, and the FP64 path's sampled columns match the oracle (the
+    comparison with the oracle bin by bin is in test_gpu_oracle_fullsize)."""
     import paper_2503_12749_amd as mp
     M, t = 4000, 0.95
     seed = synth.SEED_BASE + 2
