@@ -246,6 +246,35 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
                               void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * mp_propagate_counts without a workspace, for callers that cannot allocate
+ * device memory: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It allocates nothing and calls no allocating
+ * routine; the GEMM's partials and the counting kernel's partials live in a
+ * scratch array of MP_NOALLOC_SCRATCH_BYTES that each GPU the library runs on
+ * holds until the process ends (its address is looked up on the first call on
+ * a device, with that device current; `stream` must belong to the current
+ * device).  Same arguments, kernels, results and accumulator layout as
+ * mp_propagate_counts, for MP_MARGINALS, MP_MARGINALS_AND_TOTAL and MP_JOINT
+ * with d = 1 (joint distributions of d >= 2 bins: MP_ERR_UNSUPPORTED).
+ *
+ *   Returns MP_ERR_WORKSPACE, enqueuing nothing, when the chunk needs more than
+ *   MP_NOALLOC_SCRATCH_BYTES (mp_propagate_counts_workspace(...) gives the
+ *   need; e.g. total counts at M = 8000 on a 3840-count window take about
+ *   2 KB per sample, so chunks up to about 32000 samples fit).
+ *   Every call on one GPU uses that GPU's single array, which keeps the last
+ *   call's contents (each call writes every scratch byte before it reads it,
+ *   so nothing needs clearing): calls that overlap on one GPU (other streams,
+ *   other threads) race and must be serialised by the caller.
+ */
+#define MP_NOALLOC_SCRATCH_BYTES (64u << 20)
+mp_status mp_propagate_counts_noalloc(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                                      const void* ab, const double* n, const void* packed,
+                                      size_t packed_bytes, int32_t d, const int32_t* bin_of_mode,
+                                      mp_bin_mode mode, const int32_t* m_lo, const int32_t* K,
+                                      int32_t n_sub, int64_t samples_per_sub, int64_t e0,
+                                      double* acc, void* stream);
+
+/*
  * Inverse DFT of each sub-ensemble's mean characteristic function,
  *   P_s(m_lo + l) = (1/K) sum_k chi_s(k) exp(-2 pi i k l / K),
  * then P = mean_s P_s and sigma_T = sd_s(Re P_s) / sqrt(n_sub) (Appendix A;

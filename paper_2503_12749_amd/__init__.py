@@ -21,7 +21,8 @@ __all__ = [
     "mp_moments_accumulate", "mp_observable_histogram", "mp_subensemble_stats", "mp_acc_entries",
     "mp_binned_workspace", "mp_binned_counts", "mp_counts_finalize", "mp_finalize_workspace",
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
-    "mp_pair_correlations_workspace", "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_version", "CountsPipeline",
+    "mp_pair_correlations_workspace", "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_propagate_counts_noalloc",
+    "mp_version", "CountsPipeline",
     "PairPipeline", "Plan", "MPError", "mp_check_finite",
 ]
 
@@ -185,6 +186,16 @@ def mp_propagate_counts(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_
         packed.numel() * packed.element_size(), d, i32_array(bin_of_mode), _mode(mode),
         i32_array(m_lo), i32_array(K), n_sub, samples_per_sub, e0, _ptr(acc), _ptr(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def mp_propagate_counts_noalloc(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K,
+                                n_sub, samples_per_sub, e0, acc, stream=None):
+    """mp_propagate_counts on the library's own device scratch (no workspace
+    argument, nothing allocated); bin_of_mode, m_lo, K: host sequences."""
+    _lib.check(_lib.load().mp_propagate_counts_noalloc(
+        M, E, _prec(prec), _est(est), _ptr(ab), _ptr(n), _ptr(packed),
+        packed.numel() * packed.element_size(), d, i32_array(bin_of_mode), _mode(mode),
+        i32_array(m_lo), i32_array(K), n_sub, samples_per_sub, e0, _ptr(acc), _stream(stream)))
 
 
 def mp_finalize_workspace(d: int, mode, K, n_sub: int) -> int:

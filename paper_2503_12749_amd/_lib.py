@@ -17,6 +17,7 @@ ESTIMATORS = {"matrix_p": 0, "plus_p": 1}
 MP_MAX_BINS = 8
 MP_MAX_RUNS = 16
 MP_MAX_MOMENTS = 8
+MP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = [
     "mp_ld_modes", "mp_ab_bytes", "mp_c_bytes", "mp_sample", "mp_propagate_workspace",
@@ -25,7 +26,7 @@ EXPORTS = [
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
     "mp_check_finite", "mp_pair_correlations_workspace",
     "mp_binned_workspace", "mp_binned_counts", "mp_propagate_counts_workspace",
-    "mp_propagate_counts", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
+    "mp_propagate_counts", "mp_propagate_counts_noalloc", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
     "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_destroy",
     "mp_mlp_param_count", "mp_mlp_workspace", "mp_mlp_round", "mp_mlp_forward", "mp_mlp_loss_grad",
     "mp_mlp_adam",
@@ -78,6 +79,9 @@ def load() -> ctypes.CDLL:
         "mp_propagate_counts": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                                sz, c_i32, vp, ctypes.c_int, vp, vp, c_i32, c_i64,
                                                c_i64, vp, vp, sz, vp]),
+        "mp_propagate_counts_noalloc": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, ctypes.c_int, vp,
+                                                       vp, vp, sz, c_i32, vp, ctypes.c_int, vp, vp,
+                                                       c_i32, c_i64, c_i64, vp, vp]),
         "mp_occupations": (ctypes.c_int, [c_i32, c_i64, vp, ctypes.c_int, c_i32, vp, ctypes.c_int,
                                           vp, vp]),
         "mp_moments_accumulate": (ctypes.c_int, [c_i64, vp, vp, c_i32, c_i32, ctypes.c_int, c_i32,

@@ -56,6 +56,13 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
                                   const int32_t* m_lo, const int32_t* K, int32_t n_sub,
                                   int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
+mp_status propagate_counts_noalloc_launch(int32_t M, int64_t E, mp_precision prec,
+                                          mp_estimator est, const void* ab, const double* n,
+                                          const void* packed, int32_t d,
+                                          const int32_t* bin_of_mode, mp_bin_mode mode,
+                                          const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                          int64_t ns, int64_t e0, double* acc,
+                                          hipStream_t stream);
 mp_status occupations_launch(int32_t M, int64_t E, const void* C, mp_precision prec, int32_t d,
                              const int32_t* bin_of_mode, mp_bin_mode mode, double* nq,
                              hipStream_t stream);
@@ -303,6 +310,32 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
   return propagate_counts_launch(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K,
                                  n_sub, samples_per_sub, e0, acc, workspace, ws_bytes,
                                  (hipStream_t)stream);
+}
+
+mp_status mp_propagate_counts_noalloc(int32_t M, int64_t E, mp_precision prec, mp_estimator est,
+                                      const void* ab, const double* n, const void* packed,
+                                      size_t packed_bytes, int32_t d, const int32_t* bin_of_mode,
+                                      mp_bin_mode mode, const int32_t* m_lo, const int32_t* K,
+                                      int32_t n_sub, int64_t samples_per_sub, int64_t e0,
+                                      double* acc, void* stream) {
+  clear_error();
+  const mp_status st = counts_args("mp_propagate_counts_noalloc", M, E, est, d, bin_of_mode, mode,
+                                   m_lo, K, n_sub, samples_per_sub, e0);
+  if (st != MP_OK) return st;
+  MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16,
+               MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts_noalloc: precision %d is not fused (FP32 and split "
+               "precisions are)", (int)prec);
+  MP_CHECK_ARG(ab && n && packed && acc, MP_ERR_ARG,
+               "mp_propagate_counts_noalloc: null pointer argument");
+  MP_CHECK_ARG(aligned(ab, 16), MP_ERR_ARG, "mp_propagate_counts_noalloc: ab must be 16-byte aligned");
+  const size_t need_packed = propagate_workspace(M, prec);
+  MP_CHECK_ARG(packed_bytes >= need_packed && aligned(packed, 256), MP_ERR_WORKSPACE,
+               "mp_propagate_counts_noalloc: packed operand of %zu bytes (256-aligned) needed, "
+               "%zu given", need_packed, packed_bytes);
+  return propagate_counts_noalloc_launch(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode,
+                                         m_lo, K, n_sub, samples_per_sub, e0, acc,
+                                         (hipStream_t)stream);
 }
 
 size_t mp_finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub) {

@@ -19,6 +19,7 @@
 // their standard deviation over sqrt(N_R).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <vector>
 
 #include "chi.h"
@@ -932,6 +933,79 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
   }
   return counts_from_partials_launch(M, E, n, est, d, bin_of_mode, mode, m_lo, K, n_sub, ns, e0,
                                      acc, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+
+// Scratch of mp_propagate_counts_noalloc: the occupation-fused GEMM's
+// per-block partials followed by the counting kernel's per-tile partials, in
+// a device array that every GPU the library runs on holds from module load to
+// process exit.  In host code the array's name is only a stand-in for the
+// symbol, never a device address: the address is looked up once per device
+// (with that device current) and kept, and only that address reaches kernels.
+// Each call writes every scratch byte it later reads (the GEMM epilogue every
+// (slot, sample) partial of the chunk, the counting kernel every entry of its
+// tile), so nothing has to start at zero and the previous call's contents are
+// never read.  Calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) unsigned char scratch[MP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxScratchDevices];
+
+static mp_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error("mp_propagate_counts_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    return MP_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    set_error("mp_propagate_counts_noalloc: device %d beyond the %d supported", dev,
+              kMaxScratchDevices);
+    return MP_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("mp_propagate_counts_noalloc: hipGetSymbolAddress of the scratch array: %s",
+                hipGetErrorString(e));
+      return MP_ERR_HIP;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return MP_OK;
+}
+
+// mp_propagate_counts with the library's scratch as its workspace; arguments
+// validated by the caller as for mp_propagate_counts.  Sizes are checked before
+// any HIP call.
+mp_status propagate_counts_noalloc_launch(int32_t M, int64_t E, mp_precision prec,
+                                          mp_estimator est, const void* ab, const double* n,
+                                          const void* packed, int32_t d,
+                                          const int32_t* bin_of_mode, mp_bin_mode mode,
+                                          const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                          int64_t ns, int64_t e0, double* acc,
+                                          hipStream_t stream) {
+  MP_CHECK_ARG(mode != MP_JOINT || d == 1, MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts_noalloc: joint distributions of %d bins are not supported "
+               "(use mp_propagate_counts)", d);
+  const size_t need = propagate_counts_workspace(M, E, d, bin_of_mode, mode, K, n_sub, ns, e0);
+  MP_CHECK_ARG(need > 0, MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts_noalloc: bins form more than %d contiguous mode runs",
+               MP_MAX_RUNS);
+  MP_CHECK_ARG(need <= (size_t)MP_NOALLOC_SCRATCH_BYTES, MP_ERR_WORKSPACE,
+               "mp_propagate_counts_noalloc: this chunk needs %zu bytes of scratch, more than "
+               "the library's %zu (split the chunk, or pass a workspace to "
+               "mp_propagate_counts)", need, (size_t)MP_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  const mp_status st = scratch_of_current_device(&ws);
+  if (st != MP_OK) return st;
+  return propagate_counts_launch(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K,
+                                 n_sub, ns, e0, acc, ws, (size_t)MP_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,

@@ -193,3 +193,31 @@ def test_pair_calls_validate_on_the_host():
     st = lib.mp_pair_correlations_accumulate(1000, 100000, vp(256), 1, 10, 10000, 0, vp(256),
                                              vp(256), 1024, None)
     assert st == -5 and b"workspace" in lib.mp_last_error()
+
+
+def test_noalloc_rejects_chunks_beyond_its_scratch():
+    """The no-allocation entry point refuses a chunk whose partials exceed its
+    scratch (here M = 8000, 65536 samples, a 3840-count window: about 129 MB)
+    and joint distributions of two bins, on the host, before any HIP call."""
+    lib = _lib()
+    from paper_2503_12749_amd import _lib as binding
+    vp = ctypes.c_void_p
+    i32 = lambda xs: (ctypes.c_int32 * len(xs))(*xs)
+    M, E = 8000, 65536
+    bins = i32([0] * M)
+    need = lib.mp_propagate_counts_workspace(M, E, 1, bins, 0, i32([3840]), 8, 8192, 0)
+    assert need > binding.MP_NOALLOC_SCRATCH_BYTES
+    packed_bytes = lib.mp_propagate_workspace(M, 2)
+    st = lib.mp_propagate_counts_noalloc(M, E, 2, 0, vp(4096), vp(4096), vp(4096), packed_bytes, 1,
+                                         bins, 0, i32([8083]), i32([3840]), 8, 8192, 0, vp(4096),
+                                         None)
+    assert st == -5
+    assert b"scratch" in lib.mp_last_error()
+    st = lib.mp_propagate_counts_noalloc(M, 4096, 2, 0, vp(4096), vp(4096), vp(4096), packed_bytes,
+                                         2, i32([0] * 4000 + [1] * 4000), 0, i32([0, 0]),
+                                         i32([64, 64]), 1, 4096, 0, vp(4096), None)
+    assert st == -4
+    st = lib.mp_propagate_counts_noalloc(M, 4096, 0, 0, vp(4096), vp(4096), vp(4096), packed_bytes,
+                                         1, bins, 0, i32([8083]), i32([3840]), 1, 4096, 0, vp(4096),
+                                         None)
+    assert st == -4
