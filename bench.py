@@ -30,7 +30,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "samples·M²/s and seconds to binned P(m) at 1σ≤1e-3, M=8000, mixed vs FP32"
-PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0}
+PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0,
+                "split1_fp16": 2500.0}
+# MFMA products per real multiply-add of the split forms (hi*hi + hi*lo + lo*hi;
+# one-sided: A*hi + A*lo)
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "split1_fp16": 2}
+DTYPES = {"split_bf16": "split-bf16 (fp32 acc)", "split_fp16": "split-fp16 (fp32 acc)",
+          "split1_fp16": "fp16 x split-fp16 (fp32 acc)", "fp32": "fp32", "fp64": "f64"}
 HBM_PEAK_GBS = 8000.0
 
 # FETCH_SIZE / WRITE_SIZE of the GEMM kernel at this workload (rocprofv3 --pmc,
@@ -102,28 +108,94 @@ def timed_run(mp, torch, pipe, steps, warmup, g_start=0):
     return secs, gemm_ms, g, pk[0].elapsed_time(pk[1])
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle on a bounded sample of the same workload."""
-    from oracle import estimator
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        return max([d.get("num_threads", 1) for d in threadpool_info()
+                    if d.get("user_api") == "blas"] or [1])
     except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, budget_s, synth):
+    """The FP64 oracle on the host cores (never tuned): the M = 8000 workload
+    on a bounded sample (whole pipeline: sampling, complex128 propagation,
+    count-space G(m)), its propagation alone, both again on one core, and the
+    M = 16 and M = 1000 configurations end to end."""
+    from threadpoolctl import threadpool_limits
+    from oracle import estimator, sampler
+
+    def whole(wl, E, chunk):
+        t = time.perf_counter()
+        estimator.estimate(wl.T, wl.r, wl.seed, E, 1, wl.bins, 1, wl.windows, chunk=chunk)
+        dt = time.perf_counter() - t
+        return E * wl.M ** 2 / dt, dt
+
+    def propagation(wl, E):
+        a, b, _ = sampler.sample(wl.r, 0, E, wl.seed)
+        t = time.perf_counter()
+        estimator.propagate(wl.T, a, b)
+        dt = time.perf_counter() - t
+        return E * wl.M ** 2 / dt, dt
+
+    threads = _blas_threads()
     E0 = 32
-    t = time.perf_counter()
-    estimator.estimate(w.T, w.r, w.seed, E0, 1, w.bins, 1, w.windows, chunk=E0)
-    dt = time.perf_counter() - t
+    _, dt = whole(w, E0, E0)
     E = int(max(E0, min(16384, E0 * budget_s / max(dt, 1e-3))))
     E = max(E0, (E // E0) * E0)
-    t = time.perf_counter()
-    estimator.estimate(w.T, w.r, w.seed, E, 1, w.bins, 1, w.windows, chunk=min(E, 512))
-    dt = time.perf_counter() - t
-    return {"value": E * w.M ** 2 / dt, "unit": "samples·M²/s", "cores": int(threads),
-            "kind": "oracle",
+    rate, dt = whole(w, E, min(E, 512))
+    prop_rate, prop_dt = propagation(w, 1024)
+    with threadpool_limits(1):
+        rate1, dt1 = whole(w, 64, 64)
+        prop1, pdt1 = propagation(w, 128)
+    c1 = synth.workload_small()
+    c1_rate, c1_dt = whole(c1, c1.E, 2000)
+    m1 = synth.workload_m1000(E=2000)
+    m1_rate, m1_dt = whole(m1, 2000, 500)
+    m1_prop, _ = propagation(m1, 2000)
+    return {"value": rate, "unit": "samples·M²/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{E} samples of the M=8000 workload through the FP64 oracle "
                       f"(sampling, complex128 propagation, direct count-space G(m) on the "
-                      f"{w.windows[0][1]}-count window), {dt:.1f} s"}
+                      f"{w.windows[0][1]}-count window), {dt:.1f} s",
+            "os_cpu_count": os.cpu_count(), "blas_threads": int(threads),
+            "legs": {
+                "m8000_whole_pipeline": {"samples_M2_per_s": rate, "samples": E, "s": dt,
+                                         "threads": int(threads)},
+                "m8000_propagation_only": {"samples_M2_per_s": prop_rate, "samples": 1024,
+                                           "s": prop_dt, "threads": int(threads)},
+                "m8000_whole_pipeline_1_core": {"samples_M2_per_s": rate1, "samples": 64,
+                                                "s": dt1, "threads": 1},
+                "m8000_propagation_only_1_core": {"samples_M2_per_s": prop1, "samples": 128,
+                                                  "s": pdt1, "threads": 1},
+                "m16_whole_pipeline": {"samples_M2_per_s": c1_rate, "samples": c1.E,
+                                       "s": c1_dt, "threads": int(threads),
+                                       "workload": "M=16, Haar x t=0.5, r=1, E=1e4, K=128"},
+                "m1000_whole_pipeline": {"samples_M2_per_s": m1_rate, "samples": 2000,
+                                         "s": m1_dt, "threads": int(threads),
+                                         "workload": "M=1000, Haar x t=0.9, r=1, window "
+                                                     f"{m1.windows[0]}"},
+                "m1000_propagation_only": {"samples_M2_per_s": m1_prop, "samples": 2000,
+                                           "threads": int(threads)},
+            }}
+
+
+def criterion_job(mp, torch, w, prec, E_need, chunk, ns, fused):
+    """The seconds-to-criterion job, timed end to end: pack T, run
+    ceil(E_need / chunk) chunks (sample + fused GEMM + counts), finalize the
+    inverse DFT; returns (seconds, samples, achieved max sigma_T / max P)."""
+    n_chunks = max(1, math.ceil(E_need / chunk))
+    E = n_chunks * chunk
+    pipe = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
+                             n_sub=E // ns, samples_per_sub=ns, chunk=chunk, fused=fused)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipe.run(E)  # packs T on the first chunk, finalizes after the last
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    P, _, sig = pipe.result()
+    del pipe
+    torch.cuda.empty_cache()
+    return secs, E, float(sig.max() / P.max())
 
 
 def run_m8000(args, mp, torch, synth):
@@ -143,12 +215,16 @@ def run_m8000(args, mp, torch, synth):
     n_sub = E_total // ns
 
     results = {}
-    for prec, steps in ((args.prec, args.steps), (args.compare, args.compare_steps)):
+    legs = [(args.prec, args.steps), (args.compare, args.compare_steps)]
+    if args.also and args.also != args.prec:
+        legs.append((args.also, args.compare_steps))
+    for prec, steps in legs:
         if not prec:
             continue
+        fused = not args.unfused and prec != "fp64"
         pipe = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
                                  n_sub=n_sub, samples_per_sub=ns, chunk=args.chunk,
-                                 fused=not args.unfused and prec != "fp64")
+                                 fused=fused)
         secs, gemm_ms, g, pack_ms = timed_run(mp, torch, pipe, steps,
                                               args.warmup if prec == args.prec else 1)
         t0 = time.perf_counter()
@@ -170,21 +246,28 @@ def run_m8000(args, mp, torch, synth):
         # handful of samples; sigma_T needs two sub-ensembles, so the run is at least 2 N_S
         E_abs = E_run * (sig.max() / 1e-3) ** 2
         secs_abs = max(E_abs, 2 * ns) * per_sample + fin_s + 1e-3 * pack_ms
+        del pipe
+        torch.cuda.empty_cache()
+        job_s, job_E, job_ratio = criterion_job(mp, torch, w, prec, E_need, args.chunk, ns, fused)
         results[prec] = dict(
             secs=secs, steps=steps, ms_per_step=1e3 * secs / steps,
             value=steps * args.chunk * w.M ** 2 / secs,
             gemm_ms=float(np.mean(gemm_ms)), gemm_ms_all=[round(x, 3) for x in gemm_ms],
             sigma_max=float(sig.max()), P_max=float(P.max()), sumP=float(P.sum()),
             E_run=E_run, E_needed=float(E_need),
-            seconds_to_criterion=float(E_need * per_sample + fin_s + 1e-3 * pack_ms),
+            seconds_to_criterion=job_s,
+            criterion_job={"samples": job_E, "seconds": job_s,
+                           "achieved_sigma_max_over_P_max": job_ratio,
+                           "what": "pack T, ceil(E_needed / chunk) chunks of sample + GEMM + "
+                                   "counts, inverse DFT; timed end to end"},
+            seconds_to_criterion_extrapolated=float(E_need * per_sample + fin_s + 1e-3 * pack_ms),
             E_needed_absolute=float(E_abs), seconds_to_criterion_absolute=float(secs_abs),
             finalize_s=fin_s, pack_ms=pack_ms,
             mean=float((np.arange(w.windows[0][0], w.windows[0][0] + w.windows[0][1]) * P).sum()))
         log(f"[bench] {prec}: {results[prec]['ms_per_step']:.1f} ms/step, GEMM {results[prec]['gemm_ms']:.1f} ms, "
             f"{results[prec]['value']:.3e} samples*M^2/s, sigma_max {sig.max():.2e} (P_max {P.max():.2e}), "
-            f"E needed {E_need:.3g}")
-        del pipe
-        torch.cuda.empty_cache()
+            f"E needed {E_need:.3g}; criterion job {job_E} samples in {job_s:.3f} s, "
+            f"sigma/P_max {job_ratio:.3e}")
 
     main_r = results[args.prec]
     flops = 8.0 * w.M ** 2 * args.chunk
@@ -199,8 +282,9 @@ def run_m8000(args, mp, torch, synth):
                        f"timed call includes the counting kernels)" if not args.unfused
                        else f"gemm_{args.prec} (mp_propagate_packed)"),
             "algorithmic_flops_per_launch": flops}
-    if args.prec.startswith("split"):
-        roof["executed_mfma_frac"] = round(3 * achieved / peak, 4)
+    if args.prec in PRODUCTS:
+        roof["executed_mfma_frac"] = round(PRODUCTS[args.prec] * achieved / peak, 4)
+        roof["mfma_products"] = PRODUCTS[args.prec]
     out = {
         "metric": METRIC,
         "value": main_r["value"],
@@ -212,7 +296,7 @@ def run_m8000(args, mp, torch, synth):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"split_bf16": "split-bf16 (fp32 acc)", "fp32": "fp32", "fp64": "f64"}.get(args.prec, args.prec),
+        "dtype": DTYPES.get(args.prec, args.prec),
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: M={w.M}, Haar x t={w.t}, r=1, total counts on window "
@@ -220,6 +304,8 @@ def run_m8000(args, mp, torch, synth):
                         f"{args.chunk} samples per step, sub-ensembles of {ns}",
             "precision": args.prec,
             "seconds_to_criterion": main_r["seconds_to_criterion"],
+            "criterion_job": main_r["criterion_job"],
+            "seconds_to_criterion_extrapolated": main_r["seconds_to_criterion_extrapolated"],
             "criterion_absolute": {"criterion": "max_m sigma_T(m) <= 1e-3 (absolute)",
                                    "E_needed": main_r["E_needed_absolute"],
                                    "seconds": main_r["seconds_to_criterion_absolute"]},
@@ -230,17 +316,25 @@ def run_m8000(args, mp, torch, synth):
         },
         "roofline": roof,
     }
-    if args.compare and args.compare in results:
-        c = results[args.compare]
-        out["config"]["compare"] = {
-            "precision": args.compare, "value": c["value"], "ms_per_step": c["ms_per_step"],
-            "gemm_ms": c["gemm_ms"], "seconds_to_criterion": c["seconds_to_criterion"],
-            "speedup_mixed_vs_compare": main_r["value"] / c["value"],
-            "gemm_tflops": 8.0 * w.M ** 2 * args.chunk / (c["gemm_ms"] * 1e-3) / 1e12,
-        }
+    for key, prec in (("compare", args.compare), ("also", args.also)):
+        if prec and prec in results and prec != args.prec:
+            c = results[prec]
+            out["config"][key] = {
+                "precision": prec, "value": c["value"], "steps": c["steps"],
+                "ms_per_step": c["ms_per_step"], "gemm_ms": c["gemm_ms"],
+                "gemm_ms_all": c["gemm_ms_all"],
+                "seconds_to_criterion": c["seconds_to_criterion"],
+                "criterion_job": c["criterion_job"],
+                "speedup_mixed_vs_this": main_r["value"] / c["value"],
+                "criterion_speedup_mixed_vs_this": c["seconds_to_criterion"] / main_r["seconds_to_criterion"],
+                "gemm_tflops": 8.0 * w.M ** 2 * args.chunk / (c["gemm_ms"] * 1e-3) / 1e12,
+            }
+    if args.compare in results:
+        out["config"]["compare"]["speedup_mixed_vs_compare"] = \
+            main_r["value"] / results[args.compare]["value"]
     if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        log("[bench] timing the FP64 CPU oracle on bounded samples ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, synth)
     return out
 
 
@@ -829,7 +923,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="split_bf16")
     ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
-    ap.add_argument("--compare-steps", type=int, default=2)
+    ap.add_argument("--compare-steps", type=int, default=5)
+    ap.add_argument("--also", default="split_bf16",
+                    help="m8000: a further mixed precision timed beside the main one ('' to skip)")
     ap.add_argument("--chunk", type=int, default=65536)
     ap.add_argument("--M", type=int, default=8000)
     ap.add_argument("--cpu-budget", type=float, default=45.0)

@@ -52,7 +52,9 @@ typedef enum {
   MP_FP64 = 0,       /* FP64 samples, FP64 MFMA GEMM, FP64 characteristic function */
   MP_FP32 = 1,       /* FP32 samples, FP32 MFMA GEMM, FP32 characteristic function */
   MP_SPLIT_BF16 = 2, /* hi/lo BF16 operands, 3 BF16 MFMA products, FP32 accumulate */
-  MP_SPLIT_FP16 = 3  /* hi/lo FP16 operands, 3 FP16 MFMA products, FP32 accumulate */
+  MP_SPLIT_FP16 = 3, /* hi/lo FP16 operands, 3 FP16 MFMA products, FP32 accumulate */
+  MP_SPLIT1_FP16 = 4 /* T as one FP16 value, samples hi/lo FP16 (MP_SPLIT_FP16's sample
+                        layout), 2 FP16 MFMA products, FP32 accumulate */
 } mp_precision;
 
 typedef enum {
@@ -103,7 +105,7 @@ size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
  *   ab     device, mp_ab_bytes(M, E, prec) bytes, column-major: column k < E
  *          holds alpha of sample g0+k, column E+k its beta (column stride ldm
  *          for FP64 and FP32).
- *          FP64 -> double, FP32 -> float.  SPLIT_* -> 16-bit values with
+ *          FP64 -> double, FP32 -> float.  SPLIT_* and SPLIT1_FP16 -> 16-bit values with
  *          x = hi + lo (hi = x rounded, lo = the rounded remainder), column
  *          stride 2 ldm: mode j of a column has hi at 64 (j / 32) + j % 32 and
  *          lo 32 values further (blocks of 32 hi values, each followed by

@@ -293,7 +293,8 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
   const mp_status st = counts_args("mp_propagate_counts", M, E, est, d, bin_of_mode, mode, m_lo, K,
                                    n_sub, samples_per_sub, e0);
   if (st != MP_OK) return st;
-  MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16,
+  MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16 ||
+                   prec == MP_SPLIT1_FP16,
                MP_ERR_UNSUPPORTED,
                "mp_propagate_counts: precision %d is not fused (FP32 and split precisions are)",
                (int)prec);
@@ -322,7 +323,8 @@ mp_status mp_propagate_counts_noalloc(int32_t M, int64_t E, mp_precision prec, m
   const mp_status st = counts_args("mp_propagate_counts_noalloc", M, E, est, d, bin_of_mode, mode,
                                    m_lo, K, n_sub, samples_per_sub, e0);
   if (st != MP_OK) return st;
-  MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16,
+  MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16 ||
+                   prec == MP_SPLIT1_FP16,
                MP_ERR_UNSUPPORTED,
                "mp_propagate_counts_noalloc: precision %d is not fused (FP32 and split "
                "precisions are)", (int)prec);

@@ -81,7 +81,7 @@ inline size_t elem_bytes_ab(mp_precision p) {
 
 inline size_t elem_bytes_c(mp_precision p) { return p == MP_FP64 ? 8 : 4; }
 
-inline bool valid_prec(int p) { return p >= MP_FP64 && p <= MP_SPLIT_FP16; }
+inline bool valid_prec(int p) { return p >= MP_FP64 && p <= MP_SPLIT1_FP16; }
 
 // Wave-wide sums (64 lanes) via cross-lane shuffles.
 __device__ inline double wave_sum(double v) {

@@ -70,6 +70,9 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
     const int64_t at = row * 2 * ldm + split_offset(j);
     ((uint16_t*)A)[at] = hi;
     ((uint16_t*)A)[at + 32] = lo;
+  } else if constexpr (PREC == MP_SPLIT1_FP16) {
+    // one FP16 value per entry, prescaled like MP_SPLIT_FP16, row-major
+    ((_Float16*)A)[idx] = (_Float16)ldexp(v, scale_exp);
   } else {
     // FP16: A is packed as T * 2^scale_exp so that both halves stay normal
     const double x = ldexp(v, scale_exp);
@@ -688,6 +691,245 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __
                              out_scale, &fo);
 }
 
+// ---------------------------------------------------------------- one-sided split, 256 x 256
+
+// MP_SPLIT1_FP16: the packed transmission operand holds one FP16 value per
+// entry (prescaled by 2^e as for MP_SPLIT_FP16) and only the sampled
+// amplitudes are split, x = hi + lo, so each product is A B_hi + A B_lo: two
+// v_mfma_f32_32x32x16_f16 products per fragment pair instead of three.  The
+// FP16 rounding of T (at most 2^-11 relative per entry, unbiased) perturbs
+// the network once for all samples; the propagated amplitudes are those of
+// the rounded network to the split's 2^-22.
+//
+// Same 256 x 256 tile, four waves of 128 x 128 and ping-pong schedule as
+// split_pp_tile.  A stage holds three 256 x 32 planes (A, B hi, B lo) with the
+// split kernel's swizzle: 48 KB per stage, two stages.  The 48 one-KB
+// direct-to-LDS loads of a slab are spread over the waves, 12 each: load
+// g = 12 w + q fills rows 16 (g & 15) .. 16 (g & 15) + 15 of plane g >> 4.  A
+// row's 32-deep slab of A is half a 128-byte line (slabs kt and kt + 1 share
+// it); a column's slab of B is one whole line (hi and lo interleaved).
+constexpr int S1_NPL = 3;                                  // planes per stage
+constexpr int kSplit1StageElems = 2 * S1_NPL * S_PLANE;    // two stages
+// the fused epilogue reuses 2 x 16384 floats of the array
+constexpr int kSplit1LdsElems = (kSplit1StageElems > 65536 ? kSplit1StageElems : 65536) + 128;
+
+template <bool FUSED, bool PF>
+__device__ __attribute__((always_inline)) inline void split1_pp_tile(
+    uint16_t* __restrict__ lds, const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+    float* __restrict__ C, int64_t ldm, int64_t ncols, int64_t m0, int64_t n0, float out_scale,
+    const FusedOut* fo, int tid = -1) {
+  typedef f16x8 frag;
+  const int wave = tid < 0 ? (int)(threadIdx.x >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid < 0 ? (int)(threadIdx.x & 63) : tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  // Rows of the tile: A row r (FUSED: r < 128 the Re row of mode m0 + r, else
+  // its Im row), B column r (FUSED: r < 128 the alpha column of sample n0 + r,
+  // else its beta column; columns past the chunk repeat its last one).
+  const int64_t bcols = FUSED ? ncols / 2 - n0 : ncols - n0;
+  auto a_row = [&](int r) -> int64_t {
+    if constexpr (FUSED) return r < 128 ? m0 + r : ldm + m0 + (r - 128);
+    return m0 + r;
+  };
+  auto b_col = [&](int r) -> int64_t {
+    if constexpr (FUSED) {
+      const int64_t c = r & 127;
+      return (c < bcols ? c : bcols - 1) + n0 + (r >= 128 ? ncols / 2 : 0);
+    }
+    return n0 + (r < bcols ? r : bcols - 1);
+  };
+  const int lrow = lane >> 2;
+  const char* src[12];
+  int sh[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int g = 12 * wave + q, plane = g >> 4;
+    const int r = 16 * (g & 15) + lrow;
+    const int chunk = (lane & 3) ^ swz(r);
+    if (plane == 0) {
+      src[q] = (const char*)(A + a_row(r) * ldm + chunk * 8);
+      sh[q] = 1;  // slab k0 starts k0 FP16 values into the row
+    } else {
+      src[q] = (const char*)(B + b_col(r) * 2 * ldm + (plane == 2 ? 32 : 0) + chunk * 8);
+      sh[q] = 2;  // 2 k0 values (hi and lo blocks) into the column
+    }
+  }
+  auto issue = [&](int st, int64_t k0) {
+    char* base = (char*)(lds + st * S1_NPL * S_PLANE);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      const int g = 12 * wave + q;
+      char* dst = base + (g >> 4) * (S_PLANE * 2) + (g & 15) * 1024;
+      __builtin_amdgcn_global_load_lds((const void*)(src[q] + (k0 << sh[q])), (lds_void*)dst, 16,
+                                       0, 0);
+    }
+  };
+  // L2 prefetch of slab k0: one 4-byte load per row of A (waves 0, 1) or per
+  // column of B (waves 2, 3) into the sink after the stages (see split_pp_tile)
+  const char* pf_src[2];
+  int pf_sh = wave < 2 ? 1 : 2;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = 128 * (wave & 1) + 64 * q + lane;
+    pf_src[q] = wave < 2 ? (const char*)(A + a_row(r) * ldm) : (const char*)(B + b_col(r) * 2 * ldm);
+  }
+  auto prefetch = [&](int64_t k0) {
+    if constexpr (!PF) return;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(pf_src[q] + (k0 << pf_sh)),
+                                       (lds_void*)(lds + kSplit1StageElems), 4, 0, 0);
+  };
+  int oa[2][4], ob[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+      oa[s][i] = ra * S_BK + (((2 * lh + s) ^ swz(ra)) << 3);
+      ob[s][i] = rb * S_BK + (((2 * lh + s) ^ swz(rb)) << 3);
+    }
+  frag a0[4], bh0[4], bl0[4], a1[4], bh1[4], bl1[4];
+  auto plane = [&](int st, int p) { return lds + (st * S1_NPL + p) * S_PLANE; };
+  auto read0 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bl0[i] = *(const frag*)(plane(st, 2) + ob[0][i]);
+      a0[i] = *(const frag*)(plane(st, 0) + oa[0][i]);
+      bh0[i] = *(const frag*)(plane(st, 1) + ob[0][i]);
+    }
+  };
+  auto read1 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bl1[i] = *(const frag*)(plane(st, 2) + ob[1][i]);
+      a1[i] = *(const frag*)(plane(st, 0) + oa[1][i]);
+      bh1[i] = *(const frag*)(plane(st, 1) + ob[1][i]);
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = (int)(ldm / S_BK);  // >= 4
+  for (int p = 2; p <= kPrefetchSlabs; ++p) prefetch((int64_t)min(p, KT - 1) * S_BK);
+  issue(0, 0);
+  wait_vm<0>();
+  barrier_no_fence();
+  issue(1, S_BK);
+  prefetch((int64_t)min(1 + kPrefetchSlabs, KT - 1) * S_BK);
+  read0(0);
+  constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    // phase A: MFMAs on F0 (lo products first) with the reads of F1 between them
+    read1(cur);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0[i], bl0[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0[i], bh0[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 8, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (PF)
+      __builtin_amdgcn_s_waitcnt(2 | (7 << 4));  // vmcnt(2), lgkmcnt(0)
+    else
+      __builtin_amdgcn_s_waitcnt(0);
+    barrier_no_fence();
+    __builtin_amdgcn_sched_barrier(0);
+    // phase B: MFMAs on F1 with the next slab's loads and the reads of F0
+    // threaded in (the last two slabs reload the final slab, in bounds)
+    issue(cur, (int64_t)min(kt + 2, KT - 1) * S_BK);
+    prefetch((int64_t)min(kt + 2 + kPrefetchSlabs, KT - 1) * S_BK);
+    read0(cur ^ 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[i], bl1[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[i], bh1[j], acc[i][j], 0, 0, 0);
+    constexpr int kVmem = PF ? 14 : 12;
+#pragma unroll
+    for (int q = 0; q < kVmem; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 32 - 12 - kVmem, 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if constexpr (FUSED) {
+    fused_epilogue(acc, (float*)lds, *fo, m0, n0, wm, wn, lane, out_scale);
+    return;
+  }
+  const int64_t ldc = 2 * ldm;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1_pp(const uint16_t* __restrict__ A,
+                                                              const uint16_t* __restrict__ B,
+                                                              float* __restrict__ C, int64_t ldm,
+                                                              int64_t ncols, float out_scale) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[kSplit1LdsElems];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  split1_pp_tile<false, PF>(lds, A, B, C, ldm, ncols, (int64_t)tm * S_BM, (int64_t)tn * S_BN,
+                            out_scale, nullptr);
+}
+
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1_occ(const uint16_t* __restrict__ A,
+                                                               const uint16_t* __restrict__ B,
+                                                               int64_t ldm, int64_t ncols,
+                                                               float out_scale, FusedOut fo) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[kSplit1LdsElems];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+  split1_pp_tile<true, PF>(lds, A, B, nullptr, ldm, ncols, (int64_t)tm * 128, (int64_t)tn * 128,
+                           out_scale, &fo);
+}
+
 // ---------------------------------------------------------------- FP32, 256 x 256
 
 // FP32 twin of the split ping-pong kernel: the same 256 x 256 tile, four
@@ -906,7 +1148,8 @@ size_t propagate_workspace(int32_t M, mp_precision prec) {
   switch (prec) {
     case MP_FP64: return elems * 8;
     case MP_FP32: return elems * 4;
-    default: return elems * 4;  // two 16-bit planes
+    case MP_SPLIT1_FP16: return elems * 2;  // one FP16 value per entry
+    default: return elems * 4;  // hi and lo 16-bit values
   }
 }
 
@@ -925,7 +1168,7 @@ static int fp16_scale_exp(int32_t M) {
 // ---- used by plans (plan.hip)
 
 int split_scale_exp(int32_t M, mp_precision prec) {
-  return prec == MP_SPLIT_FP16 ? fp16_scale_exp(M) : 0;
+  return (prec == MP_SPLIT_FP16 || prec == MP_SPLIT1_FP16) ? fp16_scale_exp(M) : 0;
 }
 
 mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
@@ -947,6 +1190,10 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
       break;
     case MP_SPLIT_FP16:
       hipLaunchKernelGGL(pack_transmission<MP_SPLIT_FP16>, dim3(blocks), dim3(256), 0, stream, T,
+                         M, ldm, packed, fp16_scale_exp(M));
+      break;
+    case MP_SPLIT1_FP16:
+      hipLaunchKernelGGL(pack_transmission<MP_SPLIT1_FP16>, dim3(blocks), dim3(256), 0, stream, T,
                          M, ldm, packed, fp16_scale_exp(M));
       break;
   }
@@ -986,6 +1233,13 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
       split_gemm<_Float16>(grid_tiles(ldm, ncols, S_BM, S_BN), stream, packed, ab, C, ldm, ncols,
                            ldexpf(1.0f, -fp16_scale_exp(M)));
       break;
+    case MP_SPLIT1_FP16: {
+      auto kernel = split_prefetch_for(ldm) ? gemm_split1_pp<true> : gemm_split1_pp<false>;
+      hipLaunchKernelGGL(kernel, dim3(grid_tiles(ldm, ncols, S_BM, S_BN)), dim3(kThreads), 0,
+                         stream, (const uint16_t*)packed, (const uint16_t*)ab, (float*)C, ldm,
+                         ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
+      break;
+    }
   }
   MP_HIP_LAUNCH_CHECK("mp_propagate gemm launch");
   return MP_OK;
@@ -1032,6 +1286,12 @@ mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precisi
     case MP_SPLIT_FP16: {
       auto kernel =
           split_prefetch_for(ldm) ? gemm_split_occ<_Float16, true> : gemm_split_occ<_Float16, false>;
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
+                         (const uint16_t*)ab, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)), fo);
+      break;
+    }
+    case MP_SPLIT1_FP16: {
+      auto kernel = split_prefetch_for(ldm) ? gemm_split1_occ<true> : gemm_split1_occ<false>;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
                          (const uint16_t*)ab, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)), fo);
       break;

@@ -295,6 +295,7 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
                          M, ldm, g0, E, r, seed, net, ab, n_out);
       break;
     case MP_SPLIT_FP16:
+    case MP_SPLIT1_FP16:  // the same split sample layout
       hipLaunchKernelGGL(sample_kernel<MP_SPLIT_FP16>, dim3((unsigned)blocks), dim3(256), 0, stream,
                          M, ldm, g0, E, r, seed, net, ab, n_out);
       break;

@@ -56,7 +56,7 @@ def _run(fused, prec, est, M=333, E=1000, n_sub=5, chunk=384, seed=71, t=0.9):
     return P, s, T, r, bins, wins
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "split1_fp16"])
 @pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
 def test_fused_equals_unfused(prec, est):
     Pf, sf, *_ = _run(True, prec, est)

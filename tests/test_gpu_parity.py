@@ -219,7 +219,47 @@ def test_reduced_precision_propagation(prec, rel, M, E):
     assert np.abs(nS - 0.9025 * n).max() < 50 * rel * np.abs(n).max()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16"])
+def _fp16_network(T, M):
+    """T with each real and imaginary part rounded to FP16 after the power-of-two
+    prescale 2^floor(log2(M) / 2) (the packed operand of the one-sided split)."""
+    e = 0
+    while 4 ** (e + 1) <= M:
+        e += 1
+    sc = 2.0 ** e
+    q = lambda x: np.float16(x * sc).astype(np.float64) / sc
+    return q(T.real) + 1j * q(T.imag)
+
+
+@pytest.mark.parametrize("M,E", [(300, 200), (2049, 1100)])
+def test_split1_propagation(M, E):
+    """The one-sided split (T as one FP16 value, samples hi/lo FP16, two
+    products): every element against the oracle propagating with the
+    FP16-rounded network, relative to the largest per-sample norm (4e-6, the
+    split-FP16 bound: what remains is the samples' 2^-22 split and FP32
+    accumulation); the distance to the unrounded network is the T rounding
+    itself, below 2e-4 of the norm."""
+    import paper_2503_12749_amd as mp
+    prec = "split1_fp16"
+    T = 0.95 * synth.haar_unitary(M, 12)
+    r = np.full(M, 1.0)
+    p = _pipe(T, r, prec=prec, seed=5, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, prec, p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, prec, p.ab, p.C, p.ws_prop)
+    ag, bg = p.propagated(E)
+    a, b, n = osamp.sample(r, 0, E, 5)
+    ao, bo = oest.propagate(_fp16_network(T, M), a, b)
+    norm = np.linalg.norm(ao, axis=1, keepdims=True).max()
+    err = max(np.abs(ag - ao).max(), np.abs(bg - bo).max()) / norm
+    at, bt = oest.propagate(T, a, b)
+    dist = max(np.abs(ag - at).max(), np.abs(bg - bt).max()) / norm
+    print(f"split1 M={M}: vs rounded network {err:.2e}, vs exact network {dist:.2e}")
+    assert err < 4e-6
+    assert dist < 2e-4
+    nS = (ag * bg).sum(1)
+    assert np.abs(nS - (ao * bo).sum(1)).max() < 200 * 4e-6 * np.abs(n).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16"])
 def test_pack_once_then_propagate_matches_propagate(prec):
     """mp_pack_transmission + mp_propagate_packed give the same bits as
     mp_propagate, over several tiles with ragged edges."""

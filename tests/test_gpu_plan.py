@@ -99,18 +99,19 @@ def test_plan_chunked_passes_and_fp64_oracle():
     plan.close()
 
 
-def test_plan_fp32_fused_two_passes():
-    """FP32 plan (the occupation-fused GEMM and its counts per network inside
-    the graph) over two passes per network: bit-identical to the fused
-    single-network pipeline run in the same chunks."""
+@pytest.mark.parametrize("prec", ["fp32", "split1_fp16"])
+def test_plan_fused_per_network_two_passes(prec):
+    """FP32 and one-sided split plans (the occupation-fused GEMM and its counts
+    per network inside the graph) over two passes per network: bit-identical
+    to the fused single-network pipeline run in the same chunks."""
     import paper_2503_12749_amd as mp
     nets = _nets([50, 140, 260], E=2048, n_sub=4, seed0=311)
-    plan = mp.Plan(nets, prec="fp32", chunk=1024)
+    plan = mp.Plan(nets, prec=prec, chunk=1024)
     for rep in range(2):
         plan.launch()
         for i, n in enumerate(nets):
             P, _, s = plan.result(i)
-            p = mp.CountsPipeline(n["T"], n["r"], prec="fp32", seed=n["seed"], net=n["net"],
+            p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
                                   windows=[n["window"]], n_sub=n["n_sub"],
                                   samples_per_sub=n["E"] // n["n_sub"], chunk=1024, fused=True)
             p.run()
