@@ -3,14 +3,14 @@
 Workload: M = 8000 modes, Haar network x t = 0.95, r = 1 on every mode,
 total-count distribution on the window [8083, 8083 + 3840) (mean 9972,
 sd 209), sub-ensembles of 8192 samples.  One step = one chunk of 65536
-samples through the whole path: mp_sample -> mp_propagate_counts (split-BF16
+samples through the whole path: mp_sample -> mp_propagate_counts (the mixed
 MFMA GEMM whose epilogue forms the per-sample occupations, then the counting
-kernels; --unfused writes C and counts from it).  T is packed once per network
-(mp_pack_transmission, timed separately) and the inverse DFT
-(mp_counts_finalize) runs once after the timed steps; both enter the
-seconds-to-criterion figure.  The FP32 path is timed on the same workload for
-the mixed-vs-FP32 comparison; both paths consume the same noise, so the
-ensemble size the criterion needs is the same for both.
+kernels; --unfused writes C and counts from it).  The default mixed path is
+the one-sided split (T as one FP16 value, samples hi/lo FP16, two products);
+the three-product split-BF16 path and the FP32 path are timed on the same
+workload.  All consume the same noise, so the ensemble size the criterion
+needs is the same for all; the criterion job (pack T, the chunks that size
+needs, inverse DFT) is timed end to end for each.
 
 Prints one JSON line (last line of stdout).  Progress goes to stderr.
 """
@@ -413,7 +413,7 @@ def run_precision_m4000(args, mp, torch, synth):
     M, T, r, seed, bins, wins = w.M, w.T, w.r, w.seed, w.bins, w.windows
     E = w.E
     res = {}
-    for prec in ("fp64", "fp32", "split_bf16", "split_fp16"):
+    for prec in ("fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16"):
         p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=4,
                               mode="marginals_and_total", windows=wins, n_sub=E // ns,
                               samples_per_sub=ns, chunk=chunk)
@@ -431,7 +431,7 @@ def run_precision_m4000(args, mp, torch, synth):
     off = np.cumsum([0] + [k for _, k in wins])
     s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
     per = {}
-    for prec in ("fp32", "split_bf16", "split_fp16"):
+    for prec in ("fp32", "split_bf16", "split_fp16", "split1_fp16"):
         secs, P = res[prec][0], res[prec][1]
         rows = []
         for b in range(5):
@@ -921,7 +921,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="split_bf16")
+    ap.add_argument("--prec", default="split1_fp16")
     ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
     ap.add_argument("--compare-steps", type=int, default=5)
     ap.add_argument("--also", default="split_bf16",

@@ -117,34 +117,28 @@ def subensemble_stats(sums: np.ndarray, counts: np.ndarray):
     return Ps, P, sig
 
 
-def estimate(T, r, seed, E, n_sub, bin_of_mode, d, windows, mode="joint",
-             g0=0, net=0, chunk=2000, plus_p=False):
-    """Full oracle pipeline over samples g0 .. g0+E-1 split into n_sub equal
-    sub-ensembles (E must be a multiple of n_sub).
-
-    mode "joint": the d-dimensional joint distribution on the windows
-    [(m_lo, K)] * d (d = 1 gives the total counts of the counted modes).
-    mode "marginals": d separate one-bin distributions (S = S_b alone), each
-    on its own window.
-    mode "marginals_and_total": those d distributions plus the total count of
-    all d bins (S = the union of the bins), d + 1 windows, the total last.
-    Returns dict(P=real estimate, sigma=sigma_T, P_complex, Ps=sub-ensemble
-    means, counts=list of count arrays)."""
-    assert E % n_sub == 0
-    ns = E // n_sub
-    r = np.asarray(r, dtype=np.float64)
+def _distributions(windows, mode, d):
+    """Count arrays of each distribution and the shape of the per-sample G."""
     counts = [np.arange(lo, lo + K) for lo, K in windows]
     if mode == "joint":
-        shape = tuple(len(c) for c in counts)
-        nterm = 1
-    else:
-        nterm = d + 1 if mode == "marginals_and_total" else d
-        assert len(counts) == nterm
-        shape = (nterm, max(len(c) for c in counts))
-    sums = np.zeros((n_sub,) + shape, dtype=np.complex128)
-    done = 0
-    while done < E:
-        c = min(chunk, E - done)
+        return counts, tuple(len(c) for c in counts), 1
+    nterm = d + 1 if mode == "marginals_and_total" else d
+    assert len(counts) == nterm
+    return counts, (nterm, max(len(c) for c in counts)), nterm
+
+
+def accumulate(sums, T, r, seed, ns, bin_of_mode, d, windows, g_begin, g_end, mode="joint",
+               g0=0, net=0, chunk=2000, plus_p=False):
+    """Adds G of samples g0 + g_begin .. g0 + g_end - 1 into the per-sub-ensemble
+    sums (sample g0 + i belongs to sub-ensemble i // ns), in chunks of `chunk`
+    counted from g_begin.  A run can stop after any chunk and continue from
+    the saved sums and the next sample index."""
+    r = np.asarray(r, dtype=np.float64)
+    counts, shape, nterm = _distributions(windows, mode, d)
+    assert sums.shape[1:] == shape
+    done = g_begin
+    while done < g_end:
+        c = min(chunk, g_end - done)
         alpha, beta, n = sampler.sample(r, g0 + done, c, seed, net)
         ap, bp = propagate(T, alpha, beta)
         nb = bin_occupations(ap, bp, bin_of_mode, d)
@@ -160,6 +154,28 @@ def estimate(T, r, seed, E, n_sub, bin_of_mode, d, windows, mode="joint",
                 G[:, b, :len(counts[b])] = Gb
         np.add.at(sums, sub, G)
         done += c
+    return sums
+
+
+def estimate(T, r, seed, E, n_sub, bin_of_mode, d, windows, mode="joint",
+             g0=0, net=0, chunk=2000, plus_p=False):
+    """Full oracle pipeline over samples g0 .. g0+E-1 split into n_sub equal
+    sub-ensembles (E must be a multiple of n_sub).
+
+    mode "joint": the d-dimensional joint distribution on the windows
+    [(m_lo, K)] * d (d = 1 gives the total counts of the counted modes).
+    mode "marginals": d separate one-bin distributions (S = S_b alone), each
+    on its own window.
+    mode "marginals_and_total": those d distributions plus the total count of
+    all d bins (S = the union of the bins), d + 1 windows, the total last.
+    Returns dict(P=real estimate, sigma=sigma_T, P_complex, Ps=sub-ensemble
+    means, counts=list of count arrays)."""
+    assert E % n_sub == 0
+    ns = E // n_sub
+    counts, shape, _ = _distributions(windows, mode, d)
+    sums = np.zeros((n_sub,) + shape, dtype=np.complex128)
+    accumulate(sums, T, r, seed, ns, bin_of_mode, d, windows, 0, E, mode=mode, g0=g0, net=net,
+               chunk=chunk, plus_p=plus_p)
     Ps, P, sig = subensemble_stats(sums, np.full(n_sub, ns, dtype=np.float64))
     return dict(P=P.real, P_complex=P, sigma=sig, Ps=Ps, counts=counts)
 

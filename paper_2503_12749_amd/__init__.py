@@ -301,6 +301,24 @@ class CountsPipeline:
             done += c
         self.finalize(stream)
 
+    def checkpoint(self, next_g: int) -> dict:
+        """What a run needs to continue after its last chunk: a host copy of the
+        per-sub-ensemble FP64 accumulators and the next global sample index
+        (synchronises).  The noise is counter-based, so a run restored from it
+        and continued with the same chunk boundaries equals the uninterrupted
+        run bit for bit."""
+        return {"acc": self.acc.cpu().numpy().copy(), "next_g": int(next_g)}
+
+    def restore(self, state: dict) -> int:
+        """Loads accumulators saved by checkpoint(); returns the next sample
+        index, from which run(E_total - next_g, g_start=next_g) continues."""
+        a = np.ascontiguousarray(state["acc"], dtype=np.float64).reshape(-1)
+        if a.size != self.acc.numel():
+            raise ValueError(f"checkpoint holds {a.size} accumulator values, this pipeline "
+                             f"{self.acc.numel()}")
+        self.acc.copy_(self.torch.from_numpy(a).to(self.acc.device))
+        return int(state["next_g"])
+
     def result(self):
         """(P_re, P_im, sigma) as numpy arrays (synchronises); raises MPError
         (MP_ERR_NONFINITE) if the estimate holds NaN or infinite values."""

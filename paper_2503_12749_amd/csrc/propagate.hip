@@ -50,6 +50,15 @@ __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint3
 // values at 64 b .. 64 b + 31 and the 32 lo values right after them.
 __host__ __device__ inline int64_t split_offset(int64_t j) { return 64 * (j >> 5) + (j & 31); }
 
+// MP_SPLIT1_FP16 packs the single FP16 A in row pairs: for rows 2p, 2p + 1
+// and k-block b = j / 32, the 32 values of row 2p and then the 32 of row
+// 2p + 1 (one 128-byte line per pair and block), so a 32-deep slab of two
+// rows is one whole line.  Otherwise row-major.
+constexpr bool kSplit1ALines = true;
+__host__ __device__ inline int64_t split1_a_offset(int64_t row, int64_t j, int64_t ldm) {
+  return kSplit1ALines ? (row >> 1) * 2 * ldm + split_offset(j) + (row & 1) * 32 : row * ldm + j;
+}
+
 template <int PREC>
 __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t ldm,
                                   void* __restrict__ A, int scale_exp) {
@@ -71,8 +80,8 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
     ((uint16_t*)A)[at] = hi;
     ((uint16_t*)A)[at + 32] = lo;
   } else if constexpr (PREC == MP_SPLIT1_FP16) {
-    // one FP16 value per entry, prescaled like MP_SPLIT_FP16, row-major
-    ((_Float16*)A)[idx] = (_Float16)ldexp(v, scale_exp);
+    // one FP16 value per entry, prescaled like MP_SPLIT_FP16
+    ((_Float16*)A)[split1_a_offset(row, j, ldm)] = (_Float16)ldexp(v, scale_exp);
   } else {
     // FP16: A is packed as T * 2^scale_exp so that both halves stay normal
     const double x = ldexp(v, scale_exp);
@@ -150,6 +159,10 @@ struct SplitMfma<_Float16> {
 };
 
 __device__ inline int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+// 128-byte LDS rows (8 chunks of 16 bytes): chunk c of row r at c ^ swz8(r);
+// the 16 consecutive rows one 16-byte read touches per LDS cycle land in
+// distinct banks (even and odd rows in different bank halves).
+__device__ inline int swz8(int r) { return (r >> 1) & 7; }
 
 constexpr int S_BM = 256, S_BN = 256, S_BK = 32;
 constexpr int S_PLANE = S_BM * S_BK;  // elements of one LDS plane
@@ -702,23 +715,34 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_occ(const uint16_t* __
 // the rounded network to the split's 2^-22.
 //
 // Same 256 x 256 tile, four waves of 128 x 128 and ping-pong schedule as
-// split_pp_tile.  A stage holds three 256 x 32 planes (A, B hi, B lo) with the
-// split kernel's swizzle: 48 KB per stage, two stages.  The 48 one-KB
-// direct-to-LDS loads of a slab are spread over the waves, 12 each: load
-// g = 12 w + q fills rows 16 (g & 15) .. 16 (g & 15) + 15 of plane g >> 4.  A
-// row's 32-deep slab of A is half a 128-byte line (slabs kt and kt + 1 share
-// it); a column's slab of B is one whole line (hi and lo interleaved).
-constexpr int S1_NPL = 3;                                  // planes per stage
-constexpr int kSplit1StageElems = 2 * S1_NPL * S_PLANE;    // two stages
+// split_pp_tile.  A stage is 48 KB: A as 128 row pairs of 128 bytes (the
+// packed A holds each row pair's 32-deep block as one line, see
+// split1_a_offset) and B as 256 columns of 128 bytes (hi block, lo block),
+// 16-byte chunk c of row r at c ^ swz8(r); two stages.  The 48 one-KB
+// direct-to-LDS loads of a slab (each 8 whole lines) are spread over the
+// waves, 12 each: load g = 12 w + q fills A row pairs 8 g .. 8 g + 7 (g < 16)
+// or B rows 8 (g - 16) .. 8 (g - 16) + 7.  Fetching whole lines per load
+// matters here: with 64-byte rows each line was requested by two loads of
+// different waves, the second waiting on the first's miss.
+constexpr int S1_NPL = 3;       // stage size in 256 x 32 planes
+constexpr int kSplit1Stages = 2;  // LDS stages (loads run kSplit1Stages - 1 slabs ahead)
+// B stage as 256 rows of 128 bytes (a column's hi and lo blocks side by side),
+// so that each load instruction fetches 8 whole lines instead of 16 halves
+// (M = 8000: 57.4 -> 54.7 ms per fused GEMM, same bits; with the A row pairs
+// below 53.6 ms; three stages measured no faster).
+constexpr bool kSplit1Lines = true;
+constexpr int kSplit1StageElems = kSplit1Stages * S1_NPL * S_PLANE;
 // the fused epilogue reuses 2 x 16384 floats of the array
 constexpr int kSplit1LdsElems = (kSplit1StageElems > 65536 ? kSplit1StageElems : 65536) + 128;
 
-template <bool FUSED, bool PF>
+template <bool FUSED, bool PF, int NST = kSplit1Stages, bool BL = kSplit1Lines,
+          bool AL = kSplit1ALines>
 __device__ __attribute__((always_inline)) inline void split1_pp_tile(
     uint16_t* __restrict__ lds, const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
     float* __restrict__ C, int64_t ldm, int64_t ncols, int64_t m0, int64_t n0, float out_scale,
     const FusedOut* fo, int tid = -1) {
   typedef f16x8 frag;
+  static_assert(NST >= 2 && NST <= kSplit1Stages, "the LDS array holds kSplit1Stages stages");
   const int wave = tid < 0 ? (int)(threadIdx.x >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid < 0 ? (int)(threadIdx.x & 63) : tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -747,7 +771,18 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
     const int g = 12 * wave + q, plane = g >> 4;
     const int r = 16 * (g & 15) + lrow;
     const int chunk = (lane & 3) ^ swz(r);
-    if (plane == 0) {
+    if (BL && plane > 0) {
+      // B rows 8 (g - 16) .. + 7, 128 bytes each: lane l fills slot l % 8 of
+      // row l / 8 with global chunk (l % 8) ^ swz8(row) (hi: 0-3, lo: 4-7)
+      const int rb = 8 * (g - 16) + (lane >> 3);
+      src[q] = (const char*)(B + b_col(rb) * 2 * ldm + (((lane & 7) ^ swz8(rb)) * 8));
+      sh[q] = 2;
+    } else if (AL && plane == 0) {
+      // A row pairs 8 g .. 8 g + 7 (rows 16 g .. 16 g + 15), 128 bytes each
+      const int pr = 8 * g + (lane >> 3);
+      src[q] = (const char*)(A + a_row(2 * pr) * ldm + (((lane & 7) ^ swz8(pr)) * 8));
+      sh[q] = 2;
+    } else if (plane == 0) {
       src[q] = (const char*)(A + a_row(r) * ldm + chunk * 8);
       sh[q] = 1;  // slab k0 starts k0 FP16 values into the row
     } else {
@@ -768,10 +803,11 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
   // L2 prefetch of slab k0: one 4-byte load per row of A (waves 0, 1) or per
   // column of B (waves 2, 3) into the sink after the stages (see split_pp_tile)
   const char* pf_src[2];
-  int pf_sh = wave < 2 ? 1 : 2;
+  int pf_sh = (wave < 2 && !AL) ? 1 : 2;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int r = 128 * (wave & 1) + 64 * q + lane;
+    // AL: 128 row-pair lines, each wave of A touches its 64 twice
+    const int r = AL && wave < 2 ? 2 * (64 * (wave & 1) + lane) : 128 * (wave & 1) + 64 * q + lane;
     pf_src[q] = wave < 2 ? (const char*)(A + a_row(r) * ldm) : (const char*)(B + b_col(r) * 2 * ldm);
   }
   auto prefetch = [&](int64_t k0) {
@@ -779,33 +815,47 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
 #pragma unroll
     for (int q = 0; q < 2; ++q)
       __builtin_amdgcn_global_load_lds((const void*)(pf_src[q] + (k0 << pf_sh)),
-                                       (lds_void*)(lds + kSplit1StageElems), 4, 0, 0);
+                                       (lds_void*)(lds + NST * S1_NPL * S_PLANE), 4, 0, 0);
   };
-  int oa[2][4], ob[2][4];
+  // fragment offsets (elements from the stage's plane 0 / plane 1): A in
+  // 64-byte rows; B hi and lo in planes 1 and 2 of 64-byte rows, or (BL) in
+  // one plane of 128-byte rows, hi chunks 0-3 and lo chunks 4-7
+  int oa[2][4], obh[2][4], obl[2][4];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
-      oa[s][i] = ra * S_BK + (((2 * lh + s) ^ swz(ra)) << 3);
-      ob[s][i] = rb * S_BK + (((2 * lh + s) ^ swz(rb)) << 3);
+      if constexpr (AL) {
+        const int pr = ra >> 1;
+        oa[s][i] = pr * 2 * S_BK + ((((ra & 1) * 4 + 2 * lh + s) ^ swz8(pr)) << 3);
+      } else {
+        oa[s][i] = ra * S_BK + (((2 * lh + s) ^ swz(ra)) << 3);
+      }
+      if constexpr (BL) {
+        obh[s][i] = rb * 2 * S_BK + (((2 * lh + s) ^ swz8(rb)) << 3);
+        obl[s][i] = rb * 2 * S_BK + (((4 + 2 * lh + s) ^ swz8(rb)) << 3);
+      } else {
+        obh[s][i] = rb * S_BK + (((2 * lh + s) ^ swz(rb)) << 3);
+        obl[s][i] = S_PLANE + obh[s][i];
+      }
     }
   frag a0[4], bh0[4], bl0[4], a1[4], bh1[4], bl1[4];
   auto plane = [&](int st, int p) { return lds + (st * S1_NPL + p) * S_PLANE; };
   auto read0 = [&](int st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      bl0[i] = *(const frag*)(plane(st, 2) + ob[0][i]);
+      bl0[i] = *(const frag*)(plane(st, 1) + obl[0][i]);
       a0[i] = *(const frag*)(plane(st, 0) + oa[0][i]);
-      bh0[i] = *(const frag*)(plane(st, 1) + ob[0][i]);
+      bh0[i] = *(const frag*)(plane(st, 1) + obh[0][i]);
     }
   };
   auto read1 = [&](int st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      bl1[i] = *(const frag*)(plane(st, 2) + ob[1][i]);
+      bl1[i] = *(const frag*)(plane(st, 1) + obl[1][i]);
       a1[i] = *(const frag*)(plane(st, 0) + oa[1][i]);
-      bh1[i] = *(const frag*)(plane(st, 1) + ob[1][i]);
+      bh1[i] = *(const frag*)(plane(st, 1) + obh[1][i]);
     }
   };
 
@@ -817,17 +867,30 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
+  // Slab kt lives in stage kt % NST; the loads of slab kt + NST go into its
+  // stage once every wave has passed the barrier of slab kt.  Each slab's
+  // group of loads is 12 stage loads (+ 2 prefetch loads with PF), and loads
+  // complete in issue order, so "slab kt + 1 landed" is vmcnt(the groups of
+  // the NST - 2 later slabs + its own prefetch).
+  constexpr int kGroup = PF ? 14 : 12;
+  constexpr int kWaitN = kGroup * (NST - 2) + (PF ? 2 : 0);
+  static_assert(kWaitN < 64, "vmcnt field");
   const int KT = (int)(ldm / S_BK);  // >= 4
-  for (int p = 2; p <= kPrefetchSlabs; ++p) prefetch((int64_t)min(p, KT - 1) * S_BK);
   issue(0, 0);
-  wait_vm<0>();
+#pragma unroll
+  for (int s = 1; s + 1 < NST; ++s) {
+    issue(s, (int64_t)s * S_BK);
+    prefetch((int64_t)min(s + kPrefetchSlabs, KT - 1) * S_BK);
+  }
+  wait_vm<kGroup * (NST - 2)>();  // slab 0 landed
   barrier_no_fence();
-  issue(1, S_BK);
-  prefetch((int64_t)min(1 + kPrefetchSlabs, KT - 1) * S_BK);
+  issue(NST - 1, (int64_t)min(NST - 1, KT - 1) * S_BK);
+  prefetch((int64_t)min(NST - 1 + kPrefetchSlabs, KT - 1) * S_BK);
   read0(0);
   constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
+  int cur = 0;
   for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
+    const int nxt = cur + 1 == NST ? 0 : cur + 1;
     // phase A: MFMAs on F0 (lo products first) with the reads of F1 between them
     read1(cur);
 #pragma unroll
@@ -847,17 +910,15 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
     }
     __builtin_amdgcn_sched_group_barrier(kSgMfma, 8, 0);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (PF)
-      __builtin_amdgcn_s_waitcnt(2 | (7 << 4));  // vmcnt(2), lgkmcnt(0)
-    else
-      __builtin_amdgcn_s_waitcnt(0);
+    // own loads of slab kt + 1 landed, own reads of stage cur complete
+    __builtin_amdgcn_s_waitcnt((kWaitN & 15) | ((kWaitN >> 4) << 14) | (7 << 4));
     barrier_no_fence();
     __builtin_amdgcn_sched_barrier(0);
-    // phase B: MFMAs on F1 with the next slab's loads and the reads of F0
-    // threaded in (the last two slabs reload the final slab, in bounds)
-    issue(cur, (int64_t)min(kt + 2, KT - 1) * S_BK);
-    prefetch((int64_t)min(kt + 2 + kPrefetchSlabs, KT - 1) * S_BK);
-    read0(cur ^ 1);
+    // phase B: MFMAs on F1 with slab kt + NST's loads and the reads of F0
+    // threaded in (the last slabs reload the final slab, in bounds)
+    issue(cur, (int64_t)min(kt + NST, KT - 1) * S_BK);
+    prefetch((int64_t)min(kt + NST + kPrefetchSlabs, KT - 1) * S_BK);
+    read0(nxt);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -881,6 +942,7 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
     }
     __builtin_amdgcn_sched_group_barrier(kSgMfma, 32 - 12 - kVmem, 1);
     __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
   }
   __builtin_amdgcn_s_waitcnt(0);
   if constexpr (FUSED) {
@@ -945,7 +1007,6 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1_occ(const uint16_t* _
 constexpr int F_BK = 32;
 constexpr int F_PLANE = S_BM * F_BK;  // floats of one LDS operand plane
 
-__device__ inline int swz8(int r) { return (r >> 1) & 7; }
 
 // FUSED: tile (tm, tn) covers modes [128 tm, 128 tm + 128) and samples
 // [128 tn, 128 tn + 128) as in gemm_split_occ, and the epilogue is
