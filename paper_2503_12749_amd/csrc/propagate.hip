@@ -181,6 +181,7 @@ constexpr int kSplitLdsElems = 2 * 4 * S_PLANE + 128;
 // without it (the PF = false instances).
 constexpr int kPrefetchSlabs = 1;
 constexpr int64_t kPrefetchAliasModes = 8192;
+constexpr int kSplitPf = 2;  // prefetch loads per wave and slab: 2 = A and B lines, 1 = B only
 
 __host__ __device__ inline bool split_prefetch_for(int64_t ldm) { return ldm % kPrefetchAliasModes != 0; }
 
@@ -413,10 +414,8 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
   const float* cre = lds_f;          // Re beta'
   const float* cim = lds_f + 16384;  // -Im beta'
   const int blk = (int)m0;
-  for (int q = 0; q < fo.n_runs; ++q) {
-    const int lo = (fo.run_lo[q] > blk ? fo.run_lo[q] : blk) - blk;
-    const int hi = (fo.run_hi[q] < blk + 128 ? fo.run_hi[q] : blk + 128) - blk;
-    if (lo >= hi) continue;
+  // sums over the block's modes [lo, hi) of one run into its slot
+  auto emit = [&](int q, int lo, int hi, bool whole) {
     const int64_t slot = fo.slot_off[q] + (blk >> 7) - (fo.run_lo[q] >> 7);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -431,7 +430,8 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
             const int mode = i * 32 + 8 * g + 4 * lh + rr;
-            const float x = (mode >= lo && mode < hi) ? acc[i][j][4 * g + rr] * out_scale : 0.0f;
+            const float x = (whole || (mode >= lo && mode < hi)) ? acc[i][j][4 * g + rr] * out_scale
+                                                                 : 0.0f;
             if (wm == 0) {
               pr = fmaf(x, c[rr], pr);
               pi = fmaf(-x, e[rr], pi);
@@ -449,6 +449,22 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
         *(f32x2*)(fo.part + (slot * fo.E + smp) * 4 + 2 * wm) = f32x2{pr, pi};
       }
     }
+  };
+  // A block inside one run (every block of a one-bin partition but the
+  // padded last) needs no mode masks; with them the compiler copied all 256
+  // accumulators out of the AGPRs at once for the run loop and spilled some.
+  int whole = -1;
+  for (int q = 0; q < fo.n_runs; ++q)
+    if (fo.run_lo[q] <= blk && fo.run_hi[q] >= blk + 128) whole = q;
+  if (whole >= 0) {
+    emit(whole, 0, 128, true);
+    return;
+  }
+  for (int q = 0; q < fo.n_runs; ++q) {
+    const int lo = (fo.run_lo[q] > blk ? fo.run_lo[q] : blk) - blk;
+    const int hi = (fo.run_hi[q] < blk + 128 ? fo.run_hi[q] : blk + 128) - blk;
+    if (lo >= hi) continue;
+    emit(q, lo, hi, false);
   }
 }
 
@@ -519,17 +535,21 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
   // issue().  A line that misses the caches then costs its latency here, with
   // two loads in flight per wave, and the sixteen loads that fill the stage
   // later hit L2.
-  const uint16_t* pf_src = wave < 2 ? A + m0 * 2 * ldm : B + n0 * 2 * ldm;
+  // kSplitPf = 1: only the lines of B, 64 columns per wave
+  constexpr int NPF = kSplitPf;
+  const uint16_t* pf_src = (wave < 2 && NPF == 2) ? A + m0 * 2 * ldm : B + n0 * 2 * ldm;
+  const int64_t pf_limit = NPF == 2 ? row_limit : (FUSED ? ncols / 2 - n0 : ncols - n0);
+  const int64_t pf_hi = NPF == 2 ? hi_off : ncols / 2;
   auto prefetch = [&](int64_t k0) {
     if constexpr (!PF) return;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      int64_t row = 128 * (wave & 1) + 64 * q + lane;
+    for (int q = 0; q < NPF; ++q) {
+      int64_t row = NPF == 2 ? 128 * (wave & 1) + 64 * q + lane : 64 * wave + lane;
       if constexpr (FUSED) {
         const int64_t r = row & 127;
-        row = (r < row_limit ? r : row_limit - 1) + (row >= 128 ? hi_off : 0);
+        row = (r < pf_limit ? r : pf_limit - 1) + (row >= 128 ? pf_hi : 0);
       } else {
-        row = row < row_limit ? row : row_limit - 1;
+        row = row < pf_limit ? row : pf_limit - 1;
       }
       const uint16_t* g = pf_src + row * 2 * ldm + 2 * k0;
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)&lds[2][0][0], 4, 0, 0);
@@ -611,7 +631,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     // own loads of slab kt + 1 landed (with PF only the two prefetch loads
     // issued after them may be in flight), own reads of stage cur complete
     if constexpr (PF)
-      __builtin_amdgcn_s_waitcnt(2 | (7 << 4));  // vmcnt(2), lgkmcnt(0)
+      __builtin_amdgcn_s_waitcnt(NPF | (7 << 4));  // vmcnt(NPF), lgkmcnt(0)
     else
       __builtin_amdgcn_s_waitcnt(0);
     barrier_no_fence();
@@ -635,7 +655,7 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bh1[j], acc[i][j]);
-    constexpr int kVmem = PF ? 18 : 16;
+    constexpr int kVmem = PF ? 16 + NPF : 16;
 #pragma unroll
     for (int q = 0; q < kVmem; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
@@ -731,6 +751,7 @@ constexpr int kSplit1Stages = 2;  // LDS stages (loads run kSplit1Stages - 1 sla
 // (M = 8000: 57.4 -> 54.7 ms per fused GEMM, same bits; with the A row pairs
 // below 53.6 ms; three stages measured no faster).
 constexpr bool kSplit1Lines = true;
+constexpr int kSplit1Pf = 1;  // L2 prefetch loads per wave and slab (see split1_pp_tile)
 constexpr int kSplit1StageElems = kSplit1Stages * S1_NPL * S_PLANE;
 // the fused epilogue reuses 2 x 16384 floats of the array
 constexpr int kSplit1LdsElems = (kSplit1StageElems > 65536 ? kSplit1StageElems : 65536) + 128;
@@ -800,20 +821,26 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
                                        0, 0);
     }
   };
-  // L2 prefetch of slab k0: one 4-byte load per row of A (waves 0, 1) or per
-  // column of B (waves 2, 3) into the sink after the stages (see split_pp_tile)
-  const char* pf_src[2];
-  int pf_sh = (wave < 2 && !AL) ? 1 : 2;
+  // L2 prefetch of slab k0 into the sink after the stages (see split_pp_tile).
+  // kSplit1Pf = 2: one 4-byte load per row (pair) of A (waves 0, 1) and per
+  // column of B (waves 2, 3); 1: B columns only, 64 per wave.
+  constexpr int NPF = kSplit1Pf;
+  const char* pf_src[NPF];
+  const int pf_sh = (NPF == 2 && wave < 2 && !AL) ? 1 : 2;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    // AL: 128 row-pair lines, each wave of A touches its 64 twice
-    const int r = AL && wave < 2 ? 2 * (64 * (wave & 1) + lane) : 128 * (wave & 1) + 64 * q + lane;
-    pf_src[q] = wave < 2 ? (const char*)(A + a_row(r) * ldm) : (const char*)(B + b_col(r) * 2 * ldm);
+  for (int q = 0; q < NPF; ++q) {
+    if constexpr (NPF == 1) {
+      pf_src[q] = (const char*)(B + b_col(64 * wave + lane) * 2 * ldm);
+    } else {
+      // AL: 128 row-pair lines, each wave of A touches its 64 twice
+      const int r = AL && wave < 2 ? 2 * (64 * (wave & 1) + lane) : 128 * (wave & 1) + 64 * q + lane;
+      pf_src[q] = wave < 2 ? (const char*)(A + a_row(r) * ldm) : (const char*)(B + b_col(r) * 2 * ldm);
+    }
   }
   auto prefetch = [&](int64_t k0) {
     if constexpr (!PF) return;
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < NPF; ++q)
       __builtin_amdgcn_global_load_lds((const void*)(pf_src[q] + (k0 << pf_sh)),
                                        (lds_void*)(lds + NST * S1_NPL * S_PLANE), 4, 0, 0);
   };
@@ -872,8 +899,8 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
   // group of loads is 12 stage loads (+ 2 prefetch loads with PF), and loads
   // complete in issue order, so "slab kt + 1 landed" is vmcnt(the groups of
   // the NST - 2 later slabs + its own prefetch).
-  constexpr int kGroup = PF ? 14 : 12;
-  constexpr int kWaitN = kGroup * (NST - 2) + (PF ? 2 : 0);
+  constexpr int kGroup = PF ? 12 + NPF : 12;
+  constexpr int kWaitN = kGroup * (NST - 2) + (PF ? NPF : 0);
   static_assert(kWaitN < 64, "vmcnt field");
   const int KT = (int)(ldm / S_BK);  // >= 4
   issue(0, 0);
@@ -929,7 +956,7 @@ __device__ __attribute__((always_inline)) inline void split1_pp_tile(
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[i], bh1[j], acc[i][j], 0, 0, 0);
-    constexpr int kVmem = PF ? 14 : 12;
+    constexpr int kVmem = PF ? 12 + NPF : 12;
 #pragma unroll
     for (int q = 0; q < kVmem; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
@@ -1147,7 +1174,12 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
   }
   __builtin_amdgcn_s_waitcnt(0);  // the repeated tail loads land before the wave ends
   if constexpr (FUSED) {
-    fused_epilogue(acc, &lds[0][0][0], fo, m0, n0, wm, wn, lane, 1.0f);
+    // a unit scale the compiler cannot fold: with the constant 1 it kept the
+    // accumulators for the stores of the beta waves in their registers and
+    // spilled 41 of them around the epilogue
+    float one = 1.0f;
+    asm volatile("" : "+s"(one));
+    fused_epilogue(acc, &lds[0][0][0], fo, m0, n0, wm, wn, lane, one);
     return;
   }
   const int64_t ldc = 2 * ldm;
