@@ -53,19 +53,29 @@ typedef enum {
   MP_FP32 = 1,       /* FP32 samples, FP32 MFMA GEMM, FP32 characteristic function */
   MP_SPLIT_BF16 = 2, /* hi/lo BF16 operands, 3 BF16 MFMA products, FP32 accumulate */
   MP_SPLIT_FP16 = 3, /* hi/lo FP16 operands, 3 FP16 MFMA products, FP32 accumulate */
-  MP_SPLIT1_FP16 = 4 /* T as one FP16 value, samples hi/lo FP16 (MP_SPLIT_FP16's sample
-                        layout), 2 FP16 MFMA products, FP32 accumulate */
+  MP_SPLIT1_FP16 = 4, /* T as one FP16 value, samples hi/lo FP16 (MP_SPLIT_FP16's sample
+                         layout), 2 FP16 MFMA products, FP32 accumulate */
+  /* Range markers, not values: with them every int is a representable
+   * mp_precision, so an out-of-range argument reaches the library's check
+   * (MP_ERR_ARG) instead of being undefined on the C++ side.  The same holds
+   * for the other enumerations below. */
+  MP_PRECISION_RANGE_MIN_ = -0x7fffffff - 1,
+  MP_PRECISION_RANGE_MAX_ = 0x7fffffff
 } mp_precision;
 
 typedef enum {
   MP_JOINT = 0,              /* joint distribution of the d bin counts (d <= 4) */
   MP_MARGINALS = 1,          /* d one-bin distributions (S = S_b alone) */
-  MP_MARGINALS_AND_TOTAL = 2 /* the d marginals plus the total over all bins */
+  MP_MARGINALS_AND_TOTAL = 2, /* the d marginals plus the total over all bins */
+  MP_BIN_MODE_RANGE_MIN_ = -0x7fffffff - 1,
+  MP_BIN_MODE_RANGE_MAX_ = 0x7fffffff
 } mp_bin_mode;
 
 typedef enum {
   MP_MATRIX_P = 0, /* parity-projected weight g0 (main text, eq. c-number-variable) */
-  MP_PLUS_P = 1    /* positive-P observable, g0 = 1 (Appendix A) */
+  MP_PLUS_P = 1,   /* positive-P observable, g0 = 1 (Appendix A) */
+  MP_ESTIMATOR_RANGE_MIN_ = -0x7fffffff - 1,
+  MP_ESTIMATOR_RANGE_MAX_ = 0x7fffffff
 } mp_estimator;
 
 #define MP_MAX_BINS 8  /* bins per call */

@@ -1289,6 +1289,9 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
       hipLaunchKernelGGL(pack_transmission<MP_SPLIT1_FP16>, dim3(blocks), dim3(256), 0, stream, T,
                          M, ldm, packed, fp16_scale_exp(M));
       break;
+    default:
+      set_error("transmission pack: unknown precision %d", (int)prec);
+      return MP_ERR_ARG;
   }
   MP_HIP_LAUNCH_CHECK("transmission pack launch");
   return MP_OK;
@@ -1333,6 +1336,9 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
                          ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
       break;
     }
+    default:
+      set_error("mp_propagate: unknown precision %d", (int)prec);
+      return MP_ERR_ARG;
   }
   MP_HIP_LAUNCH_CHECK("mp_propagate gemm launch");
   return MP_OK;

@@ -299,6 +299,9 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
       hipLaunchKernelGGL(sample_kernel<MP_SPLIT_FP16>, dim3((unsigned)blocks), dim3(256), 0, stream,
                          M, ldm, g0, E, r, seed, net, ab, n_out);
       break;
+    default:
+      set_error("mp_sample: unknown precision %d", (int)prec);
+      return MP_ERR_ARG;
   }
   MP_HIP_LAUNCH_CHECK("mp_sample launch");
   return MP_OK;
