@@ -21,6 +21,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -452,50 +453,79 @@ def run_precision_m4000(args, mp, torch, synth):
         fp64_run_s=s64, fp64_samples_M2_per_s=E * M ** 2 / s64, precisions=per)
 
 
+def _batched_leg(mp, torch, nets, chunk, label):
+    """One plan over `nets` (tuned, tuning cache in a temporary file), the same
+    plan with every network forced to the 128-sample tile, and the networks
+    run one after another through the fused CountsPipeline; seconds per job
+    (best of three) and whether all three agree bit for bit."""
+    tmp = tempfile.TemporaryDirectory(prefix="mpgbs_tune_")
+    cache = os.path.join(tmp.name, "tune.json")
+    t0 = time.perf_counter()
+    plan = mp.Plan(nets, prec="split_fp16", chunk=chunk, tune_cache=cache)
+    create_s = time.perf_counter() - t0
+    plan.launch()
+    plan_s = min(_timed(torch, plan.launch) for _ in range(3))
+    info = plan.info()
+    res = [plan.result(i)[0] for i in range(len(nets))]
+    plan.close()
+    log(f"[bench] {label}: tuned plan {plan_s:.4f} s, {info}")
+    # the same order and prefetch with every network on the 128-sample tile
+    with open(cache) as f:
+        (key, entry), = json.load(f).items()
+    entry["nj"] = ",".join(["4"] * len(nets))
+    with open(cache, "w") as f:
+        json.dump({key: entry}, f)
+    wide = mp.Plan(nets, prec="split_fp16", chunk=chunk, tune_cache=cache)
+    wide.launch()
+    wide_s = min(_timed(torch, wide.launch) for _ in range(3))
+    same = all(np.array_equal(wide.result(i)[0], res[i]) for i in range(len(nets)))
+    wide.close()
+    tmp.cleanup()
+    seq_s = 0.0
+    for i, n in enumerate(nets):
+        p = mp.CountsPipeline(n["T"], n["r"], prec="split_fp16", seed=n["seed"], net=n["net"],
+                              windows=[n["window"]], n_sub=n["n_sub"],
+                              samples_per_sub=n["E"] // n["n_sub"], chunk=chunk, fused=True)
+        p.run()
+
+        def job():  # T stays packed, as in the plan
+            p.reset()
+            p.run()
+        seq_s += min(_timed(torch, job) for _ in range(3))
+        same = same and np.array_equal(p.result()[0], res[i])
+        del p
+        torch.cuda.empty_cache()
+    log(f"[bench] {label}: all 128-sample tiles {wide_s:.4f} s, sequential {seq_s:.4f} s, "
+        f"same bits {same}")
+    return dict(plan_s=plan_s, plan_all_128_sample_tiles_s=wide_s, sequential_s=seq_s,
+                speedup_vs_sequential=seq_s / plan_s, tile_choice_speedup=wide_s / plan_s,
+                plan_create_s=create_s, plan_info=info, same_bits_plan_wide_sequential=same)
+
+
 def run_batched(args, mp, torch, synth):
     """16 networks (4 each of M = 500, 1000, 2000, 4000), t ~ U[0.85, 0.99],
     r = 1, E = 2e5 each (20 sub-ensembles of 1e4), split-FP16: one plan (a
     captured hipGraph with one persistent grouped GEMM launch with the
     occupation-fused epilogue per pass over chunks of 1e5) against the same
-    networks run one after another through the fused CountsPipeline."""
+    networks run one after another through the fused CountsPipeline.  A
+    second leg runs the same networks at E = 4096 (4 sub-ensembles of 1024),
+    where a single network offers the 256 compute units few GEMM tiles."""
     E, n_sub, chunk = 200_000, 20, 100_000
     Ms = synth.BATCHED_SIZES
-    nets = synth.batched_networks(E=E, n_sub=n_sub)
-    log("[bench] batched: networks ready, creating the plan (autotunes the work-list order)")
-    t0 = time.perf_counter()
-    plan = mp.Plan(nets, prec="split_fp16", chunk=chunk)
-    create_s = time.perf_counter() - t0
-    plan.launch()
-    plan_s = min(_timed(torch, plan.launch) for _ in range(3))
-    info = plan.info()
-    seq_s, max_diff = 0.0, 0.0
-    for i, n in enumerate(nets):
-        p = mp.CountsPipeline(n["T"], n["r"], prec="split_fp16", seed=n["seed"], net=n["net"],
-                              windows=[n["window"]], n_sub=n_sub, samples_per_sub=E // n_sub,
-                              chunk=chunk, fused=True)
-        p.run()
-
-        def job():
-            p.reset()
-            p.packed = False
-            p.run()
-        seq_s += _timed(torch, job)
-        P = p.result()[0]
-        max_diff = max(max_diff, float(np.abs(P - plan.result(i)[0]).max()))
-        del p
-        torch.cuda.empty_cache()
-    plan.close()
+    log("[bench] batched: creating the plans (autotuned order, prefetch, tiles)")
+    full = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk, "batched")
+    small = _batched_leg(mp, torch, synth.batched_networks(E=4096, n_sub=4), 4096,
+                         "batched E=4096")
+    plan_s = full["plan_s"]
     work = sum(E * M ** 2 for M in Ms)
     flops = 8.0 * work
-    log(f"[bench] batched: plan {plan_s:.3f} s, sequential {seq_s:.3f} s")
+    small["samples_M2_per_s"] = sum(4096 * M ** 2 for M in Ms) / small["plan_s"]
     return _envelope(
         "samples·M²/s over 16 uneven networks in one plan, split-FP16", work / plan_s,
         "samples·M²/s", 1e3 * plan_s,
         "16 networks: 4 x M in {500, 1000, 2000, 4000}, t ~ U[0.85, 0.99], r = 1, E = 2e5 "
         "each in chunks of 1e5, total counts", "split-fp16 (fp32 acc)",
-        plan_s=plan_s, sequential_s=seq_s, speedup_vs_sequential=seq_s / plan_s,
-        plan_create_s=create_s, plan_info=info, max_abs_diff_plan_vs_sequential=max_diff,
-        algorithmic_tflops_whole_job=flops / plan_s / 1e12)
+        **full, algorithmic_tflops_whole_job=flops / plan_s / 1e12, small_ensemble_e4096=small)
 
 
 def run_surrogate(args, mp, torch, synth):

@@ -456,13 +456,15 @@ typedef struct {
  * Plan for many independent networks of uneven size (the batched form of the
  * matrix-P pass).  Creation copies r, packs every T (T and r may be freed
  * afterwards), allocates all buffers (the plan owns them), chooses the
- * grouped-GEMM work-list order with a timing autotuner (cached in the JSON
- * file `tune_cache` when it is not NULL), and captures the whole pass in a
- * hipGraph: accumulators cleared by fill kernels, sampling, ONE persistent
- * grouped split-precision GEMM launch over all networks' tiles per pass with
- * the occupation-fused epilogue of mp_propagate_counts (FP32 plans run
- * mp_propagate_counts per network, FP64 plans one GEMM writing C and the
- * counts from it per network), counts from the per-block occupation partials
+ * grouped-GEMM work-list order, L2 prefetch and per-network tile width with a
+ * timing autotuner (cached in the JSON file `tune_cache` when it is not NULL),
+ * and captures the whole pass in a hipGraph: accumulators cleared by fill
+ * kernels, sampling, ONE persistent grouped GEMM launch over all networks'
+ * tiles per pass for the three-product split precisions (MP_SPLIT_BF16,
+ * MP_SPLIT_FP16) with the occupation-fused epilogue of mp_propagate_counts
+ * (FP32 and MP_SPLIT1_FP16 plans run mp_propagate_counts per network, FP64
+ * plans one GEMM writing C and the counts from it per network), counts from
+ * the per-block occupation partials
  * and inverse DFT per network; only FP64 plans hold a propagated-amplitude
  * buffer C.  Results equal those of mp_propagate_counts (FP32, split) or
  * mp_propagate + mp_binned_counts (FP64) on the same noise, bit for bit.
@@ -488,6 +490,12 @@ mp_status mp_plan_result(void* plan, int32_t i, const double** P_re, const doubl
  * be NULL. */
 mp_status mp_plan_info(void* plan, int32_t* order, int32_t* prefetch, double* tuned_ms,
                        size_t* device_bytes);
+
+/* Tile of network i in the grouped GEMM: 128 modes by 128 or 64 samples (the
+ * autotuner's per size class choice; both give the same bits).  0 x 0 for
+ * plans without a grouped launch (FP64, FP32, MP_SPLIT1_FP16).  i outside
+ * [0, n_net): MP_ERR_ARG.  Either output pointer may be NULL. */
+mp_status mp_plan_tile(void* plan, int32_t i, int32_t* modes, int32_t* samples);
 
 /* Waits for the plan's stream and frees everything the plan owns. */
 mp_status mp_plan_destroy(void* plan);

@@ -495,8 +495,13 @@ class Plan:
         o, f, ms, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_size_t()
         _lib.check(_lib.load().mp_plan_info(self.handle, ctypes.byref(o), ctypes.byref(f),
                                             ctypes.byref(ms), ctypes.byref(b)))
+        tiles = []
+        for i in range(len(self.K)):
+            m, e = ctypes.c_int32(), ctypes.c_int32()
+            _lib.check(_lib.load().mp_plan_tile(self.handle, i, ctypes.byref(m), ctypes.byref(e)))
+            tiles.append((m.value, e.value))
         return {"order": o.value, "prefetch": f.value, "tuned_ms": ms.value,
-                "device_bytes": b.value}
+                "device_bytes": b.value, "tiles": tiles}
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

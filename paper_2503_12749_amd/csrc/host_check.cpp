@@ -173,6 +173,7 @@ static void validation() {
   EXPECT(mp_plan_create(&plan, 0, &nd, MP_SPLIT_FP16, MP_MATRIX_P, 1000, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_launch(nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_info(nullptr, nullptr, nullptr, nullptr, nullptr) == MP_ERR_ARG);
+  EXPECT(mp_plan_tile(nullptr, 0, nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_destroy(nullptr) == MP_OK);
   // the surrogate's calls
   mp_mlp_shape sh{};

@@ -6,14 +6,19 @@
 // A plan owns all of its device memory (allocated in mp_plan_create).
 //
 // Autotuning: the grouped launch's work-list order decides which tiles share
-// an XCD's L2 at the same time.  Candidate orders are timed on the plan's own
-// data at creation and the fastest is kept; results are cached in a small
-// JSON file keyed by precision and the networks' (M, samples per chunk).
+// an XCD's L2 at the same time, and each network's tile shape (128 modes by
+// 128 or by 64 samples) trades operand reuse against the number of tiles a
+// small network offers the 256 compute units.  Candidate orders (with and
+// without the L2 prefetch) are timed on the plan's own data at creation, then
+// the narrower shape per size class of networks (equal M), largest first,
+// kept where it is faster; results are cached in a small JSON file keyed by
+// precision and the networks' (M, samples per chunk).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -32,7 +37,7 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
                              const void* ab, void* C, hipStream_t stream);
 mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
-                         mp_precision prec, bool prefetch, bool fused, hipStream_t stream);
+                         mp_precision prec, bool prefetch, hipStream_t stream);
 size_t propagate_counts_workspace(int32_t M, int64_t E, int32_t d, const int32_t* bin_of_mode,
                                   mp_bin_mode mode, const int32_t* K, int32_t n_sub, int64_t ns,
                                   int64_t e0);
@@ -70,7 +75,7 @@ __global__ void fill_zero_f64(double* p, int64_t n) {
 
 constexpr int kOrders = 3;  // autotuner candidates
 constexpr int kXcdsPlan = 8;
-constexpr int kTileRows = 256, kTileCols = 256;
+constexpr int kTileModes = 128;  // per grouped work item; samples: 32 x (4 or 2)
 
 struct PlanNet {
   mp_net_desc d;
@@ -87,7 +92,15 @@ struct PlanNet {
   void* ws_counts = nullptr;  // FP64: counts partials; else fused partials + counts partials
   size_t ws_counts_bytes = 0;
   std::vector<int32_t> bins;
+  int nj = 4;  // grouped tile: 128 modes x 32 nj samples (nj 4 or 2)
 };
+
+// Side streams of a plan: the per-network kernels (sampling, counts, inverse
+// DFT) of different networks are independent, so the captured graph holds
+// them as parallel branches, network i on branch i % kBranches, joined
+// before and after each grouped GEMM.  With small ensembles these kernels
+// fill a fraction of the chip each, and the branches let them overlap.
+constexpr int kBranches = 4;
 
 struct Plan {
   std::vector<PlanNet> nets;
@@ -96,6 +109,8 @@ struct Plan {
   int64_t chunk = 0;
   int passes = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side[kBranches] = {};
+  std::vector<hipEvent_t> events;  // fork and join points (created as needed)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<void*> allocs;
@@ -124,7 +139,12 @@ static void plan_free(Plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (hipStream_t s : p->side)
+    if (s) (void)hipStreamSynchronize(s);
   for (void* a : p->allocs) (void)hipFree(a);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  for (hipStream_t s : p->side)
+    if (s) (void)hipStreamDestroy(s);
   if (p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -132,7 +152,7 @@ static void plan_free(Plan* p) {
 // Work list of one pass in the given order.  Slot it * grid + w is processed
 // by workgroup w (on XCD w % 8) in its it-th round.
 static std::vector<int4> build_items(const Plan* p, int pass, int order, int grid) {
-  struct T4 { int net, tm, tn; };
+  struct T4 { int net, tm, tn, nj; };
   std::vector<T4> seq;
   std::vector<int> idx(p->nets.size());
   for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
@@ -143,23 +163,23 @@ static std::vector<int4> build_items(const Plan* p, int pass, int order, int gri
     const PlanNet& n = p->nets[i];
     const int64_t e_this = std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk);
     if (e_this <= 0) continue;
-    const int tiles_m = (int)(2 * n.ldm / kTileRows);
-    const int tiles_n = (int)((2 * e_this + kTileCols - 1) / kTileCols);
+    const int tiles_m = (int)(n.ldm / kTileModes);
+    const int tiles_n = (int)((e_this + 32 * n.nj - 1) / (32 * n.nj));
     if (order == 2) {
       for (int tn = 0; tn < tiles_n; ++tn)
-        for (int tm = 0; tm < tiles_m; ++tm) seq.push_back({i, tm, tn});
+        for (int tm = 0; tm < tiles_m; ++tm) seq.push_back({i, tm, tn, n.nj});
     } else {
       for (int bm = 0; bm < tiles_m; bm += gm)
         for (int bn = 0; bn < tiles_n; bn += gn)
           for (int tn = bn; tn < std::min(bn + gn, tiles_n); ++tn)
-            for (int tm = bm; tm < std::min(bm + gm, tiles_m); ++tm) seq.push_back({i, tm, tn});
+            for (int tm = bm; tm < std::min(bm + gm, tiles_m); ++tm) seq.push_back({i, tm, tn, n.nj});
     }
   }
   const int n = (int)seq.size();
   const int rounds = (n + grid - 1) / grid;
   std::vector<int4> items((size_t)rounds * grid, int4{-1, 0, 0, 0});
   if (order == 2) {
-    for (int q = 0; q < n; ++q) items[q] = int4{seq[q].net, seq[q].tm, seq[q].tn, 0};
+    for (int q = 0; q < n; ++q) items[q] = int4{seq[q].net, seq[q].tm, seq[q].tn, seq[q].nj};
     return items;
   }
   // groups of consecutive sequence entries go to the workgroups of one XCD:
@@ -169,7 +189,7 @@ static std::vector<int4> build_items(const Plan* p, int pass, int order, int gri
     const int g = q / per, j = q % per;
     const int it = g / kXcdsPlan, x = g % kXcdsPlan;
     const int slot = it * grid + x + kXcdsPlan * j;
-    items[slot] = int4{seq[q].net, seq[q].tm, seq[q].tn, 0};
+    items[slot] = int4{seq[q].net, seq[q].tm, seq[q].tn, seq[q].nj};
   }
   return items;
 }
@@ -184,9 +204,11 @@ static std::string tune_key(const Plan* p) {
   return k;
 }
 
-// The cache is a flat JSON object {"<key>": {"order": o, "prefetch": f, "ms": t}, ...}.
+// The cache is a flat JSON object
+//   {"<key>": {"order": o, "prefetch": f, "ms": t, "nj": "4,2,..."}, ...}
+// with one tile width per network ("nj" absent: 4 for every network).
 static bool cache_lookup(const char* path, const std::string& key, int& order, int& prefetch,
-                         double& ms) {
+                         double& ms, std::vector<int>& nj) {
   if (!path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
@@ -201,19 +223,36 @@ static bool cache_lookup(const char* path, const std::string& key, int& order, i
   for (size_t at = text.find(pat); at != std::string::npos; at = text.find(pat, at + 1)) {
     int o = 0, f = 0;
     double t = 0.0;
-    if (sscanf(text.c_str() + at + pat.size(), "%d, \"prefetch\": %d, \"ms\": %lf", &o, &f, &t) ==
-        3) {
-      order = o;
-      prefetch = f;
-      ms = t;
-      found = true;
+    if (sscanf(text.c_str() + at + pat.size(), "%d, \"prefetch\": %d, \"ms\": %lf", &o, &f, &t) !=
+        3)
+      continue;
+    if (o < 0 || o >= kOrders || (f != 0 && f != 1)) continue;
+    // tile widths: inside this entry, one per network, each 4 or 2
+    std::vector<int> w(nj.size(), 4);
+    const size_t close = text.find('}', at + pat.size());
+    const size_t q = text.find("\"nj\": \"", at + pat.size());
+    if (q != std::string::npos && q < close) {
+      const char* c = text.c_str() + q + 7;
+      size_t k = 0;
+      bool ok = true;
+      while (ok && k < w.size()) {
+        if (*c != '4' && *c != '2') ok = false;
+        else w[k++] = *c++ - '0';
+        if (ok && k < w.size()) ok = *c++ == ',';
+      }
+      if (!ok || *c != '"') continue;
     }
+    order = o;
+    prefetch = f;
+    ms = t;
+    nj = w;
+    found = true;
   }
   return found;
 }
 
 static void cache_store(const char* path, const std::string& key, int order, int prefetch,
-                        double ms) {
+                        double ms, const std::vector<int>& nj) {
   if (!path) return;
   std::string text;
   if (FILE* f = fopen(path, "r")) {
@@ -225,9 +264,12 @@ static void cache_store(const char* path, const std::string& key, int order, int
   size_t end = text.rfind('}');
   std::string body = end == std::string::npos ? "" : text.substr(text.find('{') + 1, end - text.find('{') - 1);
   while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
-  char entry[1024];
-  snprintf(entry, sizeof(entry), "\"%s\": {\"order\": %d, \"prefetch\": %d, \"ms\": %.4f}",
-           key.c_str(), order, prefetch, ms);
+  char head[128];
+  snprintf(head, sizeof(head), "{\"order\": %d, \"prefetch\": %d, \"ms\": %.4f, \"nj\": \"", order,
+           prefetch, ms);
+  std::string entry = "\"" + key + "\": " + head;
+  for (size_t i = 0; i < nj.size(); ++i) entry += (i ? "," : "") + std::to_string(nj[i]);
+  entry += "\"}";
   const std::string out = "{" + body + (body.empty() ? "\n  " : ",\n  ") + entry + "\n}\n";
   const std::string tmp = std::string(path) + ".tmp";
   if (FILE* f = fopen(tmp.c_str(), "w")) {
@@ -263,72 +305,124 @@ static bool split(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_F
 // Every precision but FP64 runs the occupation-fused GEMM epilogue.
 static bool fused(mp_precision p) { return p != MP_FP64; }
 
-// Enqueues one full pass of every network on the plan stream.
+static mp_status plan_event(Plan* p, hipEvent_t& e) {
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    set_error("mp_plan: event creation failed");
+    return MP_ERR_HIP;
+  }
+  p->events.push_back(e);
+  return MP_OK;
+}
+
+// The side streams continue from the work queued on the plan stream so far.
+static mp_status branch_fork(Plan* p) {
+  hipEvent_t e;
+  mp_status st = plan_event(p, e);
+  if (st != MP_OK) return st;
+  hipError_t h = hipEventRecord(e, p->stream);
+  for (int b = 0; b < kBranches && h == hipSuccess; ++b) h = hipStreamWaitEvent(p->side[b], e, 0);
+  if (h != hipSuccess) {
+    set_error("mp_plan: fork: %s", hipGetErrorString(h));
+    return MP_ERR_HIP;
+  }
+  return MP_OK;
+}
+
+// The plan stream waits for everything queued on the side streams.
+static mp_status branch_join(Plan* p) {
+  for (int b = 0; b < kBranches; ++b) {
+    hipEvent_t e;
+    mp_status st = plan_event(p, e);
+    if (st != MP_OK) return st;
+    hipError_t h = hipEventRecord(e, p->side[b]);
+    if (h == hipSuccess) h = hipStreamWaitEvent(p->stream, e, 0);
+    if (h != hipSuccess) {
+      set_error("mp_plan: join: %s", hipGetErrorString(h));
+      return MP_ERR_HIP;
+    }
+  }
+  return MP_OK;
+}
+
+// Enqueues one full pass of every network: per-network kernels on the side
+// streams (network i on side[i % kBranches]) between fork and join points,
+// the grouped GEMM on the plan stream.  gemm_only: the GEMMs alone (timing).
 static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
   mp_status st;
+  const bool grouped = split(p->prec);
+  if (!gemm_only && (st = branch_fork(p)) != MP_OK) return st;
   for (int pass = 0; pass < p->passes; ++pass) {
     if (!gemm_only) {
-      if (pass == 0)
-        for (PlanNet& n : p->nets) {
+      for (size_t i = 0; i < p->nets.size(); ++i) {
+        PlanNet& n = p->nets[i];
+        hipStream_t s = p->side[i % kBranches];
+        if (pass == 0) {
           const int64_t cnt = (int64_t)n.d.n_sub * n.d.K * 2;
-          hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
-                             p->stream, n.acc, cnt);
+          hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                             n.acc, cnt);
         }
-      for (PlanNet& n : p->nets) {
         const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
         if (e <= 0) continue;
-        if ((st = sample_launch(n.d.M, g0, e, n.r, n.d.seed, n.d.net, p->prec, n.ab, n.n,
-                                p->stream)) != MP_OK)
+        if ((st = sample_launch(n.d.M, g0, e, n.r, n.d.seed, n.d.net, p->prec, n.ab, n.n, s)) !=
+            MP_OK)
           return st;
       }
     }
-    if (split(p->prec)) {
+    if (grouped) {
       // one grouped launch with the occupation epilogue, then counts from
       // each network's partials
+      if (!gemm_only && (st = branch_join(p)) != MP_OK) return st;
       if ((st = grouped_launch(p->d_nets[pass], p->d_items[pass], p->n_items[pass], p->grid,
-                               p->prec, p->prefetch, true, p->stream)) != MP_OK)
+                               p->prec, p->prefetch, p->stream)) != MP_OK)
         return st;
       if (gemm_only) continue;
-      for (PlanNet& n : p->nets) {
+      if ((st = branch_fork(p)) != MP_OK) return st;
+      for (size_t i = 0; i < p->nets.size(); ++i) {
+        PlanNet& n = p->nets[i];
         const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
         if (e <= 0) continue;
         const int32_t m_lo = n.d.m_lo, K = n.d.K;
         if ((st = counts_from_partials_launch(n.d.M, e, n.n, p->est, 1, n.bins.data(), MP_JOINT,
                                               &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
-                                              n.ws_counts, n.ws_counts_bytes, p->stream)) != MP_OK)
+                                              n.ws_counts, n.ws_counts_bytes,
+                                              p->side[i % kBranches])) != MP_OK)
           return st;
       }
       continue;
     }
-    for (PlanNet& n : p->nets) {
+    // one GEMM per network, each on its network's branch (gemm_only: all on
+    // the plan stream)
+    for (size_t i = 0; i < p->nets.size(); ++i) {
+      PlanNet& n = p->nets[i];
+      hipStream_t s = gemm_only ? p->stream : p->side[i % kBranches];
       const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
       if (e <= 0) continue;
       const int32_t m_lo = n.d.m_lo, K = n.d.K;
-      if (fused(p->prec)) {  // FP32: the fused GEMM and its counts, one network at a time
+      if (fused(p->prec)) {  // FP32, one-sided split: the fused GEMM and its counts
         if ((st = propagate_counts_launch(n.d.M, e, p->prec, p->est, n.ab, n.n, n.packed, 1,
                                           n.bins.data(), MP_JOINT, &m_lo, &K, n.d.n_sub,
                                           n.d.E / n.d.n_sub, g0, n.acc, n.ws_counts,
-                                          n.ws_counts_bytes, p->stream)) != MP_OK)
+                                          n.ws_counts_bytes, s)) != MP_OK)
           return st;
         continue;
       }
-      if ((st = gemm_packed_launch(n.d.M, e, n.packed, p->prec, n.ab, n.C, p->stream)) != MP_OK)
-        return st;
+      if ((st = gemm_packed_launch(n.d.M, e, n.packed, p->prec, n.ab, n.C, s)) != MP_OK) return st;
       if (gemm_only) continue;
       if ((st = binned_counts_launch(n.d.M, e, n.C, n.n, p->prec, p->est, 1, n.bins.data(),
                                      MP_JOINT, &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
-                                     n.ws_counts, n.ws_counts_bytes, p->stream)) != MP_OK)
+                                     n.ws_counts, n.ws_counts_bytes, s)) != MP_OK)
         return st;
     }
   }
-  if (!gemm_only)
-    for (PlanNet& n : p->nets) {
-      const int32_t K = n.d.K;
-      if ((st = counts_finalize_launch(1, MP_JOINT, &K, n.d.n_sub, n.d.E / n.d.n_sub, n.acc,
-                                       n.P_re, n.P_im, n.sigma, nullptr, 0, p->stream)) != MP_OK)
-        return st;
-    }
-  return MP_OK;
+  if (gemm_only) return MP_OK;
+  for (size_t i = 0; i < p->nets.size(); ++i) {
+    PlanNet& n = p->nets[i];
+    const int32_t K = n.d.K;
+    if ((st = counts_finalize_launch(1, MP_JOINT, &K, n.d.n_sub, n.d.E / n.d.n_sub, n.acc, n.P_re,
+                                     n.P_im, n.sigma, nullptr, 0, p->side[i % kBranches])) != MP_OK)
+      return st;
+  }
+  return branch_join(p);
 }
 
 }  // namespace mp
@@ -367,6 +461,13 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     set_error("mp_plan_create: hipStreamCreate failed");
     return MP_ERR_HIP;
   }
+  for (hipStream_t& s : p->side)
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      s = nullptr;
+      plan_free(p);
+      set_error("mp_plan_create: hipStreamCreate failed");
+      return MP_ERR_HIP;
+    }
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
@@ -446,8 +547,12 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         }
       }
       GroupNet* dn = (GroupNet*)plan_alloc(p, g.size() * sizeof(GroupNet));
+      // room for the longest work list over orders and tile widths (the
+      // narrower tile has at least as many items per network)
       size_t max_items = 0;
+      for (PlanNet& n : p->nets) n.nj = 2;
       for (int o = 0; o < kOrders; ++o) max_items = std::max(max_items, build_items(p, pass, o, p->grid).size());
+      for (PlanNet& n : p->nets) n.nj = 4;
       int4* di = (int4*)plan_alloc(p, max_items * sizeof(int4));
       if (!dn || !di) {
         plan_free(p);
@@ -471,7 +576,8 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     const std::string key = tune_key(p);
     int order = 0, prefetch = prefetch_allowed ? 1 : 0;
     double ms = 0.0;
-    if (!cache_lookup(tune_cache, key, order, prefetch, ms) || (prefetch && !prefetch_allowed)) {
+    std::vector<int> nj(p->nets.size(), 4);
+    if (!cache_lookup(tune_cache, key, order, prefetch, ms, nj) || (prefetch && !prefetch_allowed)) {
       // a valid work list must be on the device before the first grouped launch
       p->prefetch = prefetch_allowed;
       mp_status st = upload_items(p, 0);
@@ -487,29 +593,53 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         set_error("mp_plan_create: event creation failed");
         return MP_ERR_HIP;
       }
+      // mean time of the grouped launches of one pass under the current
+      // order, prefetch and tile widths (a warm pass, then two timed)
+      auto time_pass = [&](int o, float& ms_out) -> mp_status {
+        mp_status s2 = upload_items(p, o);
+        if (s2 == MP_OK) s2 = enqueue_pass(p, true);
+        float t = 0.f;
+        bool ok = s2 == MP_OK && hipEventRecord(a, p->stream) == hipSuccess;
+        for (int rep = 0; rep < 2 && ok && s2 == MP_OK; ++rep) s2 = enqueue_pass(p, true);
+        ok = ok && s2 == MP_OK && hipEventRecord(b, p->stream) == hipSuccess &&
+             hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess;
+        if (!ok && s2 == MP_OK) {
+          set_error("mp_plan_create: timing the grouped launch failed");
+          s2 = MP_ERR_HIP;
+        }
+        ms_out = t / 2;
+        return s2;
+      };
       double best = 1e30;
       for (int c = 0; c < 2 * kOrders && st == MP_OK; ++c) {
         const int o = c % kOrders, f = c < kOrders ? 1 : 0;
         if (f && !prefetch_allowed) continue;
         p->prefetch = f != 0;
-        if ((st = upload_items(p, o)) != MP_OK) break;
-        if ((st = enqueue_pass(p, true)) != MP_OK) break;  // warm
         float t = 0.f;
-        bool ok = hipEventRecord(a, p->stream) == hipSuccess;
-        for (int rep = 0; rep < 2 && ok && st == MP_OK; ++rep) st = enqueue_pass(p, true);
-        ok = ok && st == MP_OK && hipEventRecord(b, p->stream) == hipSuccess &&
-             hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess;
-        if (!ok) {
-          if (st == MP_OK) {
-            set_error("mp_plan_create: timing the work-list orders failed");
-            st = MP_ERR_HIP;
-          }
-          break;
-        }
-        if (t / 2 < best) {
-          best = t / 2;
+        if ((st = time_pass(o, t)) != MP_OK) break;
+        if (t < best) {
+          best = t;
           order = o;
           prefetch = f;
+        }
+      }
+      // tile width per size class, largest networks first, under the chosen
+      // order and prefetch
+      p->prefetch = prefetch != 0;
+      std::vector<int32_t> sizes;
+      for (const PlanNet& n : p->nets) sizes.push_back(n.d.M);
+      std::sort(sizes.begin(), sizes.end(), std::greater<int32_t>());
+      sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+      for (size_t c = 0; c < sizes.size() && st == MP_OK; ++c) {
+        for (PlanNet& n : p->nets)
+          if (n.d.M == sizes[c]) n.nj = 2;
+        float t = 0.f;
+        if ((st = time_pass(order, t)) != MP_OK) break;
+        if (t < best) {
+          best = t;
+        } else {
+          for (PlanNet& n : p->nets)
+            if (n.d.M == sizes[c]) n.nj = 4;
         }
       }
       (void)hipEventDestroy(a);
@@ -519,8 +649,10 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         return st;
       }
       ms = best;
-      cache_store(tune_cache, key, order, prefetch, ms);
+      for (size_t i = 0; i < p->nets.size(); ++i) nj[i] = p->nets[i].nj;
+      cache_store(tune_cache, key, order, prefetch, ms, nj);
     }
+    for (size_t i = 0; i < p->nets.size(); ++i) p->nets[i].nj = nj[i];
     p->order = order;
     p->prefetch = prefetch != 0;
     p->tuned_ms = ms;
@@ -602,6 +734,17 @@ mp_status mp_plan_info(void* plan, int32_t* order, int32_t* prefetch, double* tu
   if (prefetch) *prefetch = p->prefetch ? 1 : 0;
   if (tuned_ms) *tuned_ms = p->tuned_ms;
   if (device_bytes) *device_bytes = p->bytes;
+  return MP_OK;
+}
+
+mp_status mp_plan_tile(void* plan, int32_t i, int32_t* modes, int32_t* samples) {
+  clear_error();
+  MP_CHECK_ARG(plan, MP_ERR_ARG, "mp_plan_tile: null plan");
+  Plan* p = (Plan*)plan;
+  MP_CHECK_ARG(i >= 0 && i < (int)p->nets.size(), MP_ERR_ARG, "mp_plan_tile: network %d", i);
+  const bool grouped = split(p->prec);
+  if (modes) *modes = grouped ? kTileModes : 0;
+  if (samples) *samples = grouped ? 32 * p->nets[i].nj : 0;
   return MP_OK;
 }
 

@@ -22,6 +22,8 @@
 // values, so one 32-deep k-slab of a row is one full 128-byte line.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace mp {
@@ -392,8 +394,9 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f64_pp(const double* __restr
 // interleaved rows and are combined by a shuffle) and store per-sample
 // partials.  LDS layout: [wm][(i 4 + j) 4 + g][lane][4] floats, conflict-free
 // 16-byte accesses.
+template <int NJ = 4>
 __device__ __attribute__((always_inline)) inline void fused_epilogue(
-    f32x16 (&acc)[4][4], float* __restrict__ lds_f, const FusedOut& fo, int64_t m0, int64_t n0,
+    f32x16 (&acc)[4][NJ], float* __restrict__ lds_f, const FusedOut& fo, int64_t m0, int64_t n0,
     int wm, int wn, int lane, float out_scale) {
   const int lr = lane & 31, lh = lane >> 5;
   __syncthreads();  // every wave is done reading the operand stages
@@ -402,10 +405,10 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int g = 0; g < 4; ++g)
-          *(f32x4*)(dst + ((((i * 4 + j) * 4 + g) * 64) + lane) * 4) =
+          *(f32x4*)(dst + ((((i * NJ + j) * 4 + g) * 64) + lane) * 4) =
               f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
                     acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
   }
@@ -418,13 +421,13 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
   auto emit = [&](int q, int lo, int hi, bool whole) {
     const int64_t slot = fo.slot_off[q] + (blk >> 7) - (fo.run_lo[q] >> 7);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       float pr = 0.0f, pi = 0.0f;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-          const int off = ((((i * 4 + j) * 4 + g) * 64) + lane) * 4;
+          const int off = ((((i * NJ + j) * 4 + g) * 64) + lane) * 4;
           const f32x4 c = *(const f32x4*)(cre + off);
           const f32x4 e = *(const f32x4*)(cim + off);
 #pragma unroll
@@ -483,7 +486,12 @@ __device__ __attribute__((always_inline)) inline void fused_epilogue(
 // their Im rows, its columns the alpha columns of samples [n0, n0 + 128)
 // followed by their beta columns, and the epilogue is fused_epilogue instead
 // of the store of C.
-template <typename H, bool FUSED, bool PF>
+// NJ: 32-column blocks per wave.  4: the 256 x 256 tile; 2: a 256 x 128 tile
+// (fused: 128 modes x 64 samples) whose B planes use their first 128 rows,
+// for batched plans (a tile-shape candidate of the plan's autotuner).  Every
+// output element goes through the same MFMA sequence in either shape, so the
+// results are the same bits.
+template <typename H, bool FUSED, bool PF, int NJ = 4>
 __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*lds)[4][S_PLANE], const uint16_t* __restrict__ A,
                                      const uint16_t* __restrict__ B, float* __restrict__ C,
                                      int64_t ldm, int64_t ncols, int64_t m0, int64_t n0,
@@ -513,14 +521,18 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
   }
   const int lrow = lane >> 2;
   const int lchunk = (lane & 3) ^ swz(lrow);
-  auto issue = [&](int st, int64_t k0) {
+  // NQ loads of 16 rows fill a plane: 16 (256 rows) for A and for the full
+  // tile's B, 4 NJ for the B of a narrower tile (its second half the beta
+  // columns when fused)
+  auto issue_rows = [&](auto NQc, int st, int64_t k0) {
+    constexpr int NQ = decltype(NQc)::value;
     char* dst = (char*)&lds[st][wave][0];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       int64_t row;
       if constexpr (FUSED) {
-        row = 16 * (q & 7) + lrow;
-        row = (row < row_limit ? row : row_limit - 1) + (q >= 8 ? hi_off : 0);
+        row = 16 * (q % (NQ / 2)) + lrow;
+        row = (row < row_limit ? row : row_limit - 1) + (q >= NQ / 2 ? hi_off : 0);
       } else {
         row = 16 * q + lrow;
         row = row < row_limit ? row : row_limit - 1;
@@ -528,6 +540,12 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       const uint16_t* g = plane_src + row * 2 * ldm + 2 * k0 + lchunk * 8;
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(dst + q * 1024), 16, 0, 0);
     }
+  };
+  auto issue = [&](int st, int64_t k0) {
+    if (NJ == 4 || wave < 2)
+      issue_rows(std::integral_constant<int, 16>{}, st, k0);
+    else
+      issue_rows(std::integral_constant<int, 4 * NJ>{}, st, k0);
   };
   // L2 prefetch of slab k0: one 4-byte direct-to-LDS load per 128-byte line
   // (one row of the interleaved operand) into the sink after the stages.  The
@@ -540,14 +558,20 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
   const uint16_t* pf_src = (wave < 2 && NPF == 2) ? A + m0 * 2 * ldm : B + n0 * 2 * ldm;
   const int64_t pf_limit = NPF == 2 ? row_limit : (FUSED ? ncols / 2 - n0 : ncols - n0);
   const int64_t pf_hi = NPF == 2 ? hi_off : ncols / 2;
+  static_assert(NJ == 4 || NPF == 2, "narrower tiles prefetch both operands");
+  // rows of the prefetched operand: the B of a narrower tile has 64 NJ rows,
+  // 32 NJ per wave (NJ = 2: one per lane, touched twice)
+  const bool pf_full = NJ == 4 || wave < 2;
+  const int pf_half = pf_full ? 128 : 32 * NJ;
   auto prefetch = [&](int64_t k0) {
     if constexpr (!PF) return;
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
-      int64_t row = NPF == 2 ? 128 * (wave & 1) + 64 * q + lane : 64 * wave + lane;
+      int64_t row = NPF == 2 ? (pf_full ? 128 * (wave & 1) + 64 * q + lane : 32 * NJ * (wave & 1) + lane)
+                             : 64 * wave + lane;
       if constexpr (FUSED) {
-        const int64_t r = row & 127;
-        row = (r < pf_limit ? r : pf_limit - 1) + (row >= 128 ? pf_hi : 0);
+        const int64_t r = row & (pf_half - 1);
+        row = (r < pf_limit ? r : pf_limit - 1) + (row >= pf_half ? pf_hi : 0);
       } else {
         row = row < pf_limit ? row : pf_limit - 1;
       }
@@ -555,40 +579,45 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
       __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)&lds[2][0][0], 4, 0, 0);
     }
   };
-  int oa[2][4], ob[2][4];
+  int oa[2][4], ob[2][NJ];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < 2; ++s) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+      const int ra = wm * 128 + i * 32 + lr;
       oa[s][i] = ra * S_BK + (((2 * lh + s) ^ swz(ra)) << 3);
-      ob[s][i] = rb * S_BK + (((2 * lh + s) ^ swz(rb)) << 3);
     }
-  frag ah0[4], al0[4], bh0[4], bl0[4], ah1[4], al1[4], bh1[4], bl1[4];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int rb = wn * 32 * NJ + j * 32 + lr;
+      ob[s][j] = rb * S_BK + (((2 * lh + s) ^ swz(rb)) << 3);
+    }
+  }
+  frag ah0[4], al0[4], bh0[NJ], bl0[NJ], ah1[4], al1[4], bh1[NJ], bl1[NJ];
   auto read0 = [&](int st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       al0[i] = *(const frag*)(&lds[st][1][oa[0][i]]);
-      bh0[i] = *(const frag*)(&lds[st][2][ob[0][i]]);
+      if (i < NJ) bh0[i] = *(const frag*)(&lds[st][2][ob[0][i]]);
       ah0[i] = *(const frag*)(&lds[st][0][oa[0][i]]);
-      bl0[i] = *(const frag*)(&lds[st][3][ob[0][i]]);
+      if (i < NJ) bl0[i] = *(const frag*)(&lds[st][3][ob[0][i]]);
     }
   };
   auto read1 = [&](int st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       al1[i] = *(const frag*)(&lds[st][1][oa[1][i]]);
-      bh1[i] = *(const frag*)(&lds[st][2][ob[1][i]]);
+      if (i < NJ) bh1[i] = *(const frag*)(&lds[st][2][ob[1][i]]);
       ah1[i] = *(const frag*)(&lds[st][0][oa[1][i]]);
-      bl1[i] = *(const frag*)(&lds[st][3][ob[1][i]]);
+      if (i < NJ) bl1[i] = *(const frag*)(&lds[st][3][ob[1][i]]);
     }
   };
 
-  f32x16 acc[4][4];
+  f32x16 acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
@@ -612,21 +641,23 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al0[i], bh0[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = SplitMfma<H>::mma(al0[i], bh0[j], acc[i][j]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah0[i], bl0[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = SplitMfma<H>::mma(ah0[i], bl0[j], acc[i][j]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah0[i], bh0[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = SplitMfma<H>::mma(ah0[i], bh0[j], acc[i][j]);
+    // per phase: 12 NJ MFMAs, 8 + 2 NJ fragment reads
+    constexpr int kReads = 8 + 2 * NJ, kMfma = 12 * NJ, kMpr = NJ == 4 ? 2 : 1;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+    for (int q = 0; q < kReads; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, kMpr, 0);
       __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(kSgMfma, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, kMfma - kMpr * kReads, 0);
     __builtin_amdgcn_sched_barrier(0);
     // own loads of slab kt + 1 landed (with PF only the two prefetch loads
     // issued after them may be in flight), own reads of stage cur complete
@@ -646,40 +677,41 @@ __device__ __attribute__((always_inline)) inline void split_pp_tile(uint16_t (*l
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(al1[i], bh1[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = SplitMfma<H>::mma(al1[i], bh1[j], acc[i][j]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bl1[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bl1[j], acc[i][j]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bh1[j], acc[i][j]);
-    constexpr int kVmem = PF ? 16 + NPF : 16;
+      for (int j = 0; j < NJ; ++j) acc[i][j] = SplitMfma<H>::mma(ah1[i], bh1[j], acc[i][j]);
+    // loads of the A waves (the B waves of a narrower tile issue fewer)
+    constexpr int kVmem = NJ == 4 ? (PF ? 16 + NPF : 16) : 8;
 #pragma unroll
     for (int q = 0; q < kVmem; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
       __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < kReads; ++q) {
       __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
       __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
     }
-    __builtin_amdgcn_sched_group_barrier(kSgMfma, 48 - 16 - kVmem, 1);
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, kMfma - kReads - kVmem, 1);
     __builtin_amdgcn_sched_barrier(0);
   }
   // the repeated tail loads and the prefetches land before the epilogue
   // reuses the stages and before the wave ends
   __builtin_amdgcn_s_waitcnt(0);
   if constexpr (FUSED) {
-    fused_epilogue(acc, (float*)&lds[0][0][0], *fo, m0, n0, wm, wn, lane, out_scale);
+    fused_epilogue<NJ>(acc, (float*)&lds[0][0][0], *fo, m0, n0, wm, wn, lane, out_scale);
     return;
   }
   const int64_t ldc = 2 * ldm;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t col = n0 + wn * 128 + j * 32 + lr;
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t col = n0 + wn * 32 * NJ + j * 32 + lr;
     if (col >= ncols) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1208,14 +1240,15 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_pp(const float* __restri
 // the same tile counts as the C tiles) and writes the network's occupation
 // partials (GroupNet::fo) instead of C.
 
-template <typename H, bool PF, bool FUSED>
+template <typename H, bool PF>
 __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet* __restrict__ nets,
                                                                   const int4* __restrict__ items,
                                                                   int n_items) {
   __shared__ __attribute__((aligned(1024))) uint16_t lds_raw[kSplitLdsElems];
   uint16_t (*lds)[4][S_PLANE] = (uint16_t (*)[4][S_PLANE])lds_raw;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const int4 w = items[it];  // (net, tile_m, tile_n, unused); net < 0: idle slot
+    // (net, tile_m, tile_n, columns blocks per wave: 4 or 2); net < 0: idle slot
+    const int4 w = items[it];
     if (w.x < 0) continue;
     const GroupNet* g = nets + w.x;
     // the thread index, opaque to the compiler on every item, so that nothing
@@ -1223,12 +1256,14 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet
     // across the epilogue
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    if constexpr (FUSED)
-      split_pp_tile<H, true, PF>(lds, g->A, g->B, nullptr, g->ldm, g->ncols, (int64_t)w.y * 128,
-                                 (int64_t)w.z * 128, g->out_scale, &g->fo, tid);
+    if (w.w == 2)  // 256 x 128 tile: 128 modes x 64 samples
+      split_pp_tile<H, true, PF, 2>(lds, g->A, g->B, nullptr, g->ldm, g->ncols,
+                                    (int64_t)w.y * 128, (int64_t)w.z * 64, g->out_scale, &g->fo,
+                                    tid);
     else
-      split_pp_tile<H, false, PF>(lds, g->A, g->B, g->C, g->ldm, g->ncols, (int64_t)w.y * S_BM,
-                                  (int64_t)w.z * S_BN, g->out_scale, nullptr, tid);
+      split_pp_tile<H, true, PF, 4>(lds, g->A, g->B, nullptr, g->ldm, g->ncols,
+                                    (int64_t)w.y * 128, (int64_t)w.z * 128, g->out_scale, &g->fo,
+                                    tid);
     __syncthreads();  // the next item reuses the LDS stages
   }
 }
@@ -1345,21 +1380,20 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
 }
 
 template <typename H>
-static auto grouped_kernel(bool prefetch, bool fused) {
-  return fused ? (prefetch ? gemm_split_grouped<H, true, true> : gemm_split_grouped<H, false, true>)
-               : (prefetch ? gemm_split_grouped<H, true, false> : gemm_split_grouped<H, false, false>);
+static auto grouped_kernel(bool prefetch) {
+  return prefetch ? gemm_split_grouped<H, true> : gemm_split_grouped<H, false>;
 }
 
 mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_items, int grid,
-                         mp_precision prec, bool prefetch, bool fused, hipStream_t stream) {
+                         mp_precision prec, bool prefetch, hipStream_t stream) {
   if (prec == MP_SPLIT_BF16) {
-    hipLaunchKernelGGL(grouped_kernel<__bf16>(prefetch, fused), dim3(grid), dim3(kThreads), 0,
-                       stream, d_nets, d_items, n_items);
+    hipLaunchKernelGGL(grouped_kernel<__bf16>(prefetch), dim3(grid), dim3(kThreads), 0, stream,
+                       d_nets, d_items, n_items);
   } else if (prec == MP_SPLIT_FP16) {
-    hipLaunchKernelGGL(grouped_kernel<_Float16>(prefetch, fused), dim3(grid), dim3(kThreads), 0,
-                       stream, d_nets, d_items, n_items);
+    hipLaunchKernelGGL(grouped_kernel<_Float16>(prefetch), dim3(grid), dim3(kThreads), 0, stream,
+                       d_nets, d_items, n_items);
   } else {
-    set_error("grouped GEMM: split precisions only");
+    set_error("grouped GEMM: the three-product split precisions only");
     return MP_ERR_UNSUPPORTED;
   }
   MP_HIP_LAUNCH_CHECK("plan grouped gemm launch");

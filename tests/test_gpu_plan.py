@@ -55,6 +55,7 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     plan = mp.Plan(nets, prec=prec, tune_cache=cache)
     info = plan.info()
     assert 0 <= info["order"] < 3 and info["prefetch"] in (0, 1) and info["tuned_ms"] > 0
+    assert len(info["tiles"]) == len(nets)
     first = []
     for rep in range(3):
         plan.launch()
@@ -79,8 +80,47 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     assert plan2.info()["order"] == info["order"]
     assert plan2.info()["prefetch"] == info["prefetch"]
     assert plan2.info()["tuned_ms"] == pytest.approx(info["tuned_ms"], rel=1e-3)
+    assert plan2.info()["tiles"] == info["tiles"]
     plan.close()
     plan2.close()
+
+
+def test_plan_tile_widths_from_cache(tmp_path):
+    """Tile widths per network (128 modes by 128 or 64 samples) read from the
+    tuning cache: a plan forced to mixed widths, with ragged sample tails in
+    both, gives the same bits as the tuned plan and the single-network runs;
+    an entry with a malformed width list is ignored (the plan retunes)."""
+    import paper_2503_12749_amd as mp
+    nets = _nets([70, 200, 330, 600], E=4000, n_sub=4, seed0=123)
+    cache = tmp_path / "tune.json"
+    plan = mp.Plan(nets, prec="split_fp16", tune_cache=cache)
+    info = plan.info()
+    assert all(t[0] == 128 and t[1] in (64, 128) for t in info["tiles"])
+    plan.launch()
+    ref = [plan.result(i) for i in range(len(nets))]
+    plan.close()
+    data = json.loads(cache.read_text())
+    (key, entry), = data.items()
+    for widths in ("2,4,2,4", "2,2,2,2", "4,4,4,4"):
+        entry["nj"] = widths
+        cache.write_text(json.dumps({key: entry}))
+        p2 = mp.Plan(nets, prec="split_fp16", tune_cache=cache)
+        assert [t[1] for t in p2.info()["tiles"]] == [32 * int(w) for w in widths.split(",")]
+        assert p2.info()["order"] == entry["order"]
+        p2.launch()
+        for i in range(len(nets)):
+            P, Pi, s = p2.result(i)
+            assert np.array_equal(P, ref[i][0]) and np.array_equal(s, ref[i][2]), (widths, i)
+        p2.close()
+    for i, n in enumerate(nets):
+        P, _, s = _single(n, "split_fp16")
+        assert np.array_equal(ref[i][0], P) and np.array_equal(ref[i][2], s), i
+    entry["nj"] = "2,3,2,4"
+    cache.write_text(json.dumps({key: entry}))
+    p3 = mp.Plan(nets, prec="split_fp16", tune_cache=cache)
+    assert len(json.loads(cache.read_text())) == 1  # retuned and stored under the same key
+    assert "3" not in json.loads(cache.read_text())[key]["nj"]
+    p3.close()
 
 
 def test_plan_chunked_passes_and_fp64_oracle():
@@ -107,6 +147,7 @@ def test_plan_fused_per_network_two_passes(prec):
     import paper_2503_12749_amd as mp
     nets = _nets([50, 140, 260], E=2048, n_sub=4, seed0=311)
     plan = mp.Plan(nets, prec=prec, chunk=1024)
+    assert plan.info()["tiles"] == [(0, 0)] * len(nets)  # no grouped launch
     for rep in range(2):
         plan.launch()
         for i, n in enumerate(nets):
