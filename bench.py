@@ -45,10 +45,12 @@ HBM_PEAK_GBS = 8000.0
 # (fetch x2, write x1); valid only for the GEMM source they were taken from.
 # Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
 TRAFFIC = {
-    ("split_bf16", True): {"source_sha256_16": "fc9fafc5dd2d948c",
-                           "fetch_bytes": 4.981e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("fp32", True): {"source_sha256_16": "fc9fafc5dd2d948c",
-                     "fetch_bytes": 6.736e7 * 1024 * 2, "write_bytes": 1.387e6 * 1024},
+    ("split1_fp16", True): {"source_sha256_16": "660652ba02ffac8c",
+                            "fetch_bytes": 3.277e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("split_bf16", True): {"source_sha256_16": "660652ba02ffac8c",
+                           "fetch_bytes": 5.033e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("fp32", True): {"source_sha256_16": "660652ba02ffac8c",
+                     "fetch_bytes": 4.904e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
 }
 
 
