@@ -45,12 +45,12 @@ HBM_PEAK_GBS = 8000.0
 # (fetch x2, write x1); valid only for the GEMM source they were taken from.
 # Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
 TRAFFIC = {
-    ("split1_fp16", True): {"source_sha256_16": "660652ba02ffac8c",
+    ("split1_fp16", True): {"source_sha256_16": "0bae512632f1e4c5",
                             "fetch_bytes": 3.277e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("split_bf16", True): {"source_sha256_16": "660652ba02ffac8c",
-                           "fetch_bytes": 5.033e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("fp32", True): {"source_sha256_16": "660652ba02ffac8c",
-                     "fetch_bytes": 4.904e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("split_bf16", True): {"source_sha256_16": "0bae512632f1e4c5",
+                           "fetch_bytes": 4.98e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("fp32", True): {"source_sha256_16": "0bae512632f1e4c5",
+                     "fetch_bytes": 4.903e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
 }
 
 
@@ -455,15 +455,16 @@ def run_precision_m4000(args, mp, torch, synth):
         fp64_run_s=s64, fp64_samples_M2_per_s=E * M ** 2 / s64, precisions=per)
 
 
-def _batched_leg(mp, torch, nets, chunk, label):
+def _batched_leg(mp, torch, nets, chunk, label, prec="split_fp16"):
     """One plan over `nets` (tuned, tuning cache in a temporary file), the same
-    plan with every network forced to the 128-sample tile, and the networks
-    run one after another through the fused CountsPipeline; seconds per job
-    (best of three) and whether all three agree bit for bit."""
+    plan with every network forced to the 128-sample tile (three-product
+    splits, which have two tile widths), and the networks run one after
+    another through the fused CountsPipeline; seconds per job (best of three)
+    and whether they agree bit for bit."""
     tmp = tempfile.TemporaryDirectory(prefix="mpgbs_tune_")
     cache = os.path.join(tmp.name, "tune.json")
     t0 = time.perf_counter()
-    plan = mp.Plan(nets, prec="split_fp16", chunk=chunk, tune_cache=cache)
+    plan = mp.Plan(nets, prec=prec, chunk=chunk, tune_cache=cache)
     create_s = time.perf_counter() - t0
     plan.launch()
     plan_s = min(_timed(torch, plan.launch) for _ in range(3))
@@ -471,21 +472,23 @@ def _batched_leg(mp, torch, nets, chunk, label):
     res = [plan.result(i)[0] for i in range(len(nets))]
     plan.close()
     log(f"[bench] {label}: tuned plan {plan_s:.4f} s, {info}")
-    # the same order and prefetch with every network on the 128-sample tile
-    with open(cache) as f:
-        (key, entry), = json.load(f).items()
-    entry["nj"] = ",".join(["4"] * len(nets))
-    with open(cache, "w") as f:
-        json.dump({key: entry}, f)
-    wide = mp.Plan(nets, prec="split_fp16", chunk=chunk, tune_cache=cache)
-    wide.launch()
-    wide_s = min(_timed(torch, wide.launch) for _ in range(3))
-    same = all(np.array_equal(wide.result(i)[0], res[i]) for i in range(len(nets)))
-    wide.close()
+    wide_s, same = None, True
+    if prec != "split1_fp16":
+        # the same order and prefetch with every network on the 128-sample tile
+        with open(cache) as f:
+            (key, entry), = json.load(f).items()
+        entry["nj"] = ",".join(["4"] * len(nets))
+        with open(cache, "w") as f:
+            json.dump({key: entry}, f)
+        wide = mp.Plan(nets, prec=prec, chunk=chunk, tune_cache=cache)
+        wide.launch()
+        wide_s = min(_timed(torch, wide.launch) for _ in range(3))
+        same = all(np.array_equal(wide.result(i)[0], res[i]) for i in range(len(nets)))
+        wide.close()
     tmp.cleanup()
     seq_s = 0.0
     for i, n in enumerate(nets):
-        p = mp.CountsPipeline(n["T"], n["r"], prec="split_fp16", seed=n["seed"], net=n["net"],
+        p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
                               windows=[n["window"]], n_sub=n["n_sub"],
                               samples_per_sub=n["E"] // n["n_sub"], chunk=chunk, fused=True)
         p.run()
@@ -497,10 +500,11 @@ def _batched_leg(mp, torch, nets, chunk, label):
         same = same and np.array_equal(p.result()[0], res[i])
         del p
         torch.cuda.empty_cache()
-    log(f"[bench] {label}: all 128-sample tiles {wide_s:.4f} s, sequential {seq_s:.4f} s, "
+    log(f"[bench] {label}: all 128-sample tiles {wide_s} s, sequential {seq_s:.4f} s, "
         f"same bits {same}")
-    return dict(plan_s=plan_s, plan_all_128_sample_tiles_s=wide_s, sequential_s=seq_s,
-                speedup_vs_sequential=seq_s / plan_s, tile_choice_speedup=wide_s / plan_s,
+    return dict(precision=prec, plan_s=plan_s, plan_all_128_sample_tiles_s=wide_s,
+                sequential_s=seq_s, speedup_vs_sequential=seq_s / plan_s,
+                tile_choice_speedup=None if wide_s is None else wide_s / plan_s,
                 plan_create_s=create_s, plan_info=info, same_bits_plan_wide_sequential=same)
 
 
@@ -511,13 +515,18 @@ def run_batched(args, mp, torch, synth):
     occupation-fused epilogue per pass over chunks of 1e5) against the same
     networks run one after another through the fused CountsPipeline.  A
     second leg runs the same networks at E = 4096 (4 sub-ensembles of 1024),
-    where a single network offers the 256 compute units few GEMM tiles."""
+    where a single network offers the 256 compute units few GEMM tiles; a
+    third runs the E = 2e5 job in the one-sided split FP16 precision (T as one
+    FP16 value, two products)."""
     E, n_sub, chunk = 200_000, 20, 100_000
     Ms = synth.BATCHED_SIZES
     log("[bench] batched: creating the plans (autotuned order, prefetch, tiles)")
     full = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk, "batched")
     small = _batched_leg(mp, torch, synth.batched_networks(E=4096, n_sub=4), 4096,
                          "batched E=4096")
+    one_sided = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
+                             "batched one-sided split", prec="split1_fp16")
+    one_sided["samples_M2_per_s"] = sum(E * M ** 2 for M in Ms) / one_sided["plan_s"]
     plan_s = full["plan_s"]
     work = sum(E * M ** 2 for M in Ms)
     flops = 8.0 * work
@@ -527,7 +536,8 @@ def run_batched(args, mp, torch, synth):
         "samples·M²/s", 1e3 * plan_s,
         "16 networks: 4 x M in {500, 1000, 2000, 4000}, t ~ U[0.85, 0.99], r = 1, E = 2e5 "
         "each in chunks of 1e5, total counts", "split-fp16 (fp32 acc)",
-        **full, algorithmic_tflops_whole_job=flops / plan_s / 1e12, small_ensemble_e4096=small)
+        **full, algorithmic_tflops_whole_job=flops / plan_s / 1e12, small_ensemble_e4096=small,
+        one_sided_split_fp16=one_sided)
 
 
 def run_surrogate(args, mp, torch, synth):

@@ -460,11 +460,11 @@ typedef struct {
  * timing autotuner (cached in the JSON file `tune_cache` when it is not NULL),
  * and captures the whole pass in a hipGraph: accumulators cleared by fill
  * kernels, sampling, ONE persistent grouped GEMM launch over all networks'
- * tiles per pass for the three-product split precisions (MP_SPLIT_BF16,
- * MP_SPLIT_FP16) with the occupation-fused epilogue of mp_propagate_counts
- * (FP32 and MP_SPLIT1_FP16 plans run mp_propagate_counts per network, FP64
- * plans one GEMM writing C and the counts from it per network), counts from
- * the per-block occupation partials
+ * tiles per pass for the split precisions (MP_SPLIT_BF16, MP_SPLIT_FP16,
+ * MP_SPLIT1_FP16) with the occupation-fused epilogue of mp_propagate_counts
+ * (FP32 plans run mp_propagate_counts per network, FP64 plans one GEMM writing
+ * C and the counts from it per network), counts from the per-block occupation
+ * partials
  * and inverse DFT per network; only FP64 plans hold a propagated-amplitude
  * buffer C.  Results equal those of mp_propagate_counts (FP32, split) or
  * mp_propagate + mp_binned_counts (FP64) on the same noise, bit for bit.
@@ -492,9 +492,10 @@ mp_status mp_plan_info(void* plan, int32_t* order, int32_t* prefetch, double* tu
                        size_t* device_bytes);
 
 /* Tile of network i in the grouped GEMM: 128 modes by 128 or 64 samples (the
- * autotuner's per size class choice; both give the same bits).  0 x 0 for
- * plans without a grouped launch (FP64, FP32, MP_SPLIT1_FP16).  i outside
- * [0, n_net): MP_ERR_ARG.  Either output pointer may be NULL. */
+ * autotuner's per size class choice for MP_SPLIT_BF16 and MP_SPLIT_FP16; both
+ * give the same bits), 128 x 128 for MP_SPLIT1_FP16, 0 x 0 for plans without
+ * a grouped launch (FP64, FP32).  i outside [0, n_net): MP_ERR_ARG.  Either
+ * output pointer may be NULL. */
 mp_status mp_plan_tile(void* plan, int32_t i, int32_t* modes, int32_t* samples);
 
 /* Waits for the plan's stream and frees everything the plan owns. */

@@ -2,12 +2,14 @@
 // captured once in a hipGraph and replayed.  The pass is
 //   zero accumulators (fill kernels; no memset nodes) -> sample every network
 //   -> one persistent grouped split-precision GEMM launch over all networks'
-//   tiles -> occupations/characteristic function per network -> inverse DFT.
+//   tiles -> occupations/characteristic function per network -> inverse DFT
+// (FP32 plans: the occupation-fused GEMM per network; FP64: GEMM writing C,
+// then the counts from C, per network).
 // A plan owns all of its device memory (allocated in mp_plan_create).
 //
 // Autotuning: the grouped launch's work-list order decides which tiles share
 // an XCD's L2 at the same time, and each network's tile shape (128 modes by
-// 128 or by 64 samples) trades operand reuse against the number of tiles a
+// 128 or by 64 samples; three-product split precisions) trades operand reuse against the number of tiles a
 // small network offers the 256 compute units.  Candidate orders (with and
 // without the L2 prefetch) are timed on the plan's own data at creation, then
 // the narrower shape per size class of networks (equal M), largest first,
@@ -149,6 +151,13 @@ static void plan_free(Plan* p) {
   delete p;
 }
 
+// The split precisions run one grouped GEMM per pass; the three-product ones
+// offer two tile widths (the one-sided split kernel has the 128-sample tile only).
+static bool split(mp_precision p) {
+  return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16 || p == MP_SPLIT1_FP16;
+}
+static bool two_widths(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16; }
+
 // Work list of one pass in the given order.  Slot it * grid + w is processed
 // by workgroup w (on XCD w % 8) in its it-th round.
 static std::vector<int4> build_items(const Plan* p, int pass, int order, int grid) {
@@ -164,15 +173,16 @@ static std::vector<int4> build_items(const Plan* p, int pass, int order, int gri
     const int64_t e_this = std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk);
     if (e_this <= 0) continue;
     const int tiles_m = (int)(n.ldm / kTileModes);
-    const int tiles_n = (int)((e_this + 32 * n.nj - 1) / (32 * n.nj));
+    const int nj = two_widths(p->prec) ? n.nj : 4;
+    const int tiles_n = (int)((e_this + 32 * nj - 1) / (32 * nj));
     if (order == 2) {
       for (int tn = 0; tn < tiles_n; ++tn)
-        for (int tm = 0; tm < tiles_m; ++tm) seq.push_back({i, tm, tn, n.nj});
+        for (int tm = 0; tm < tiles_m; ++tm) seq.push_back({i, tm, tn, nj});
     } else {
       for (int bm = 0; bm < tiles_m; bm += gm)
         for (int bn = 0; bn < tiles_n; bn += gn)
           for (int tn = bn; tn < std::min(bn + gn, tiles_n); ++tn)
-            for (int tm = bm; tm < std::min(bm + gm, tiles_m); ++tm) seq.push_back({i, tm, tn, n.nj});
+            for (int tm = bm; tm < std::min(bm + gm, tiles_m); ++tm) seq.push_back({i, tm, tn, nj});
     }
   }
   const int n = (int)seq.size();
@@ -301,7 +311,6 @@ static mp_status upload_items(Plan* p, int order) {
   return MP_OK;
 }
 
-static bool split(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16; }
 // Every precision but FP64 runs the occupation-fused GEMM epilogue.
 static bool fused(mp_precision p) { return p != MP_FP64; }
 
@@ -398,7 +407,7 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
       const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
       if (e <= 0) continue;
       const int32_t m_lo = n.d.m_lo, K = n.d.K;
-      if (fused(p->prec)) {  // FP32, one-sided split: the fused GEMM and its counts
+      if (fused(p->prec)) {  // FP32: the fused GEMM and its counts
         if ((st = propagate_counts_launch(n.d.M, e, p->prec, p->est, n.ab, n.n, n.packed, 1,
                                           n.bins.data(), MP_JOINT, &m_lo, &K, n.d.n_sub,
                                           n.d.E / n.d.n_sub, g0, n.acc, n.ws_counts,
@@ -630,7 +639,7 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
       for (const PlanNet& n : p->nets) sizes.push_back(n.d.M);
       std::sort(sizes.begin(), sizes.end(), std::greater<int32_t>());
       sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
-      for (size_t c = 0; c < sizes.size() && st == MP_OK; ++c) {
+      for (size_t c = 0; c < sizes.size() && st == MP_OK && two_widths(prec); ++c) {
         for (PlanNet& n : p->nets)
           if (n.d.M == sizes[c]) n.nj = 2;
         float t = 0.f;
@@ -652,7 +661,7 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
       for (size_t i = 0; i < p->nets.size(); ++i) nj[i] = p->nets[i].nj;
       cache_store(tune_cache, key, order, prefetch, ms, nj);
     }
-    for (size_t i = 0; i < p->nets.size(); ++i) p->nets[i].nj = nj[i];
+    for (size_t i = 0; i < p->nets.size(); ++i) p->nets[i].nj = two_widths(prec) ? nj[i] : 4;
     p->order = order;
     p->prefetch = prefetch != 0;
     p->tuned_ms = ms;
@@ -744,7 +753,7 @@ mp_status mp_plan_tile(void* plan, int32_t i, int32_t* modes, int32_t* samples) 
   MP_CHECK_ARG(i >= 0 && i < (int)p->nets.size(), MP_ERR_ARG, "mp_plan_tile: network %d", i);
   const bool grouped = split(p->prec);
   if (modes) *modes = grouped ? kTileModes : 0;
-  if (samples) *samples = grouped ? 32 * p->nets[i].nj : 0;
+  if (samples) *samples = grouped ? 32 * (two_widths(p->prec) ? p->nets[i].nj : 4) : 0;
   return MP_OK;
 }
 

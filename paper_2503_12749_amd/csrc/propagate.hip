@@ -1268,6 +1268,26 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split_grouped(const GroupNet
   }
 }
 
+// One-sided split FP16 form of the grouped launch: the same work list, every
+// item a 256 x 256 tile (128 modes x 128 samples) of split1_pp_tile with the
+// occupation epilogue.
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1_grouped(const GroupNet* __restrict__ nets,
+                                                                   const int4* __restrict__ items,
+                                                                   int n_items) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[kSplit1LdsElems];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];  // (net, tile_m, tile_n, 4)
+    if (w.x < 0) continue;
+    const GroupNet* g = nets + w.x;
+    int tid = threadIdx.x;  // opaque per item, as in gemm_split_grouped
+    asm volatile("" : "+v"(tid));
+    split1_pp_tile<true, PF>(lds, g->A, g->B, nullptr, g->ldm, g->ncols, (int64_t)w.y * 128,
+                             (int64_t)w.z * 128, g->out_scale, &g->fo, tid);
+    __syncthreads();  // the next item reuses the LDS stages
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 size_t propagate_workspace(int32_t M, mp_precision prec) {
@@ -1392,8 +1412,11 @@ mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_item
   } else if (prec == MP_SPLIT_FP16) {
     hipLaunchKernelGGL(grouped_kernel<_Float16>(prefetch), dim3(grid), dim3(kThreads), 0, stream,
                        d_nets, d_items, n_items);
+  } else if (prec == MP_SPLIT1_FP16) {
+    hipLaunchKernelGGL(prefetch ? gemm_split1_grouped<true> : gemm_split1_grouped<false>,
+                       dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
   } else {
-    set_error("grouped GEMM: the three-product split precisions only");
+    set_error("grouped GEMM: the split precisions only");
     return MP_ERR_UNSUPPORTED;
   }
   MP_HIP_LAUNCH_CHECK("plan grouped gemm launch");

@@ -160,25 +160,36 @@ def test_m4000_precision_study_vs_oracle(m4000, prec, fused):
 # ---------------------------------------------------------------- batched plan
 
 
-def test_batched_plan_vs_oracle():
-    """The batched form: one split-FP16 plan (hipGraph, persistent grouped
-    GEMM with the occupation epilogue) over one network of each size class of
-    the 16-network workload (M = 500, 1000, 2000, 4000 with their own t),
-    8192 samples each in 4 sub-ensembles; every network's P(m) against the
-    oracle on the same noise (network id in the Philox counter)."""
-    import paper_2503_12749_amd as mp
+@pytest.fixture(scope="module")
+def batched_refs():
     E, n_sub = 8192, 4
     nets = synth.batched_networks(E=E, n_sub=n_sub, indices=[0, 4, 8, 12])
-    plan = mp.Plan(nets, prec="split_fp16", chunk=E)
+    refs = []
+    for n in nets:
+        M = n["T"].shape[0]
+        t0 = time.perf_counter()
+        refs.append(oest.estimate(n["T"], n["r"], n["seed"], E, n_sub, synth.all_modes_bin(M), 1,
+                                  [n["window"]], net=n["net"], chunk=2048))
+        print(f"[oracle] M={M} net {n['net']}: {time.perf_counter() - t0:.1f} s", flush=True)
+    return nets, refs, E
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split1_fp16"])
+def test_batched_plan_vs_oracle(batched_refs, prec):
+    """The batched form: one split plan (hipGraph, persistent grouped GEMM
+    with the occupation epilogue; three-product split FP16 and the one-sided
+    split) over one network of each size class of the 16-network workload
+    (M = 500, 1000, 2000, 4000 with their own t), 8192 samples each in 4
+    sub-ensembles; every network's P(m) against the oracle on the same noise
+    (network id in the Philox counter)."""
+    import paper_2503_12749_amd as mp
+    nets, refs, E = batched_refs
+    plan = mp.Plan(nets, prec=prec, chunk=E)
     plan.launch()
     res = [plan.result(i) for i in range(len(nets))]
     print(f"plan info: {plan.info()}", flush=True)
     plan.close()
-    for n, (P, P_im, _) in zip(nets, res):
+    for n, (P, P_im, _), ref in zip(nets, res, refs):
         M = n["T"].shape[0]
-        t0 = time.perf_counter()
-        ref = oest.estimate(n["T"], n["r"], n["seed"], E, n_sub, synth.all_modes_bin(M), 1,
-                            [n["window"]], net=n["net"], chunk=2048)
-        print(f"[oracle] M={M} net {n['net']}: {time.perf_counter() - t0:.1f} s", flush=True)
         assert abs(P.sum() - 1.0) < 1e-8
-        _compare(f"plan M={M} t={n['t']:.3f}", P, P_im, ref["P"], ref["sigma"], False)
+        _compare(f"plan {prec} M={M} t={n['t']:.3f}", P, P_im, ref["P"], ref["sigma"], False)

@@ -47,7 +47,7 @@ def _single(n, prec):
     return p.result()
 
 
-@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "split1_fp16"])
 def test_plan_equals_single_network_runs(prec, tmp_path):
     import paper_2503_12749_amd as mp
     nets = _nets([60, 130, 300, 520], E=4096, n_sub=4)
@@ -56,6 +56,8 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     info = plan.info()
     assert 0 <= info["order"] < 3 and info["prefetch"] in (0, 1) and info["tuned_ms"] > 0
     assert len(info["tiles"]) == len(nets)
+    if prec == "split1_fp16":  # one tile width
+        assert info["tiles"] == [(128, 128)] * len(nets)
     first = []
     for rep in range(3):
         plan.launch()
@@ -141,13 +143,15 @@ def test_plan_chunked_passes_and_fp64_oracle():
 
 @pytest.mark.parametrize("prec", ["fp32", "split1_fp16"])
 def test_plan_fused_per_network_two_passes(prec):
-    """FP32 and one-sided split plans (the occupation-fused GEMM and its counts
-    per network inside the graph) over two passes per network: bit-identical
-    to the fused single-network pipeline run in the same chunks."""
+    """FP32 plans (the occupation-fused GEMM and its counts per network inside
+    the graph) and one-sided split plans (one grouped launch per pass) over
+    two passes per network: bit-identical to the fused single-network
+    pipeline run in the same chunks."""
     import paper_2503_12749_amd as mp
     nets = _nets([50, 140, 260], E=2048, n_sub=4, seed0=311)
     plan = mp.Plan(nets, prec=prec, chunk=1024)
-    assert plan.info()["tiles"] == [(0, 0)] * len(nets)  # no grouped launch
+    grouped = prec != "fp32"
+    assert plan.info()["tiles"] == [(128, 128) if grouped else (0, 0)] * len(nets)
     for rep in range(2):
         plan.launch()
         for i, n in enumerate(nets):
@@ -162,8 +166,9 @@ def test_plan_fused_per_network_two_passes(prec):
     plan.close()
 
 
-def test_plan_split_uneven_passes():
-    """Split-BF16 plan over chunks of 2048 with networks of one and two passes:
+@pytest.mark.parametrize("prec", ["split_bf16", "split1_fp16"])
+def test_plan_split_uneven_passes(prec):
+    """Split plans over chunks of 2048 with networks of one and two passes:
     in the second pass the finished networks have no work items and no
     partials; every network equals the fused single-network pipeline run in
     the same chunks, bit for bit."""
@@ -171,11 +176,11 @@ def test_plan_split_uneven_passes():
     nets = _nets([90, 200, 330], E=4096, n_sub=4, seed0=515)
     nets[1]["E"] = 2048
     nets[1]["n_sub"] = 2
-    plan = mp.Plan(nets, prec="split_bf16", chunk=2048)
+    plan = mp.Plan(nets, prec=prec, chunk=2048)
     plan.launch()
     for i, n in enumerate(nets):
         P, _, s = plan.result(i)
-        p = mp.CountsPipeline(n["T"], n["r"], prec="split_bf16", seed=n["seed"], net=n["net"],
+        p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
                               windows=[n["window"]], n_sub=n["n_sub"],
                               samples_per_sub=n["E"] // n["n_sub"], chunk=2048, fused=True)
         p.run()
