@@ -32,12 +32,13 @@ if ROOT not in sys.path:
 
 METRIC = "samples·M²/s and seconds to binned P(m) at 1σ≤1e-3, M=8000, mixed vs FP32"
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0,
-                "split1_fp16": 2500.0}
+                "split1_fp16": 2500.0, "split1t_fp16": 2500.0}
 # MFMA products per real multiply-add of the split forms (hi*hi + hi*lo + lo*hi;
-# one-sided: A*hi + A*lo)
-PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "split1_fp16": 2}
+# one-sided: A*hi + A*lo or hi*B + lo*B)
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "split1_fp16": 2, "split1t_fp16": 2}
 DTYPES = {"split_bf16": "split-bf16 (fp32 acc)", "split_fp16": "split-fp16 (fp32 acc)",
-          "split1_fp16": "fp16 x split-fp16 (fp32 acc)", "fp32": "fp32", "fp64": "f64"}
+          "split1_fp16": "fp16 x split-fp16 (fp32 acc)",
+          "split1t_fp16": "split-fp16 x fp16 (fp32 acc)", "fp32": "fp32", "fp64": "f64"}
 HBM_PEAK_GBS = 8000.0
 
 # FETCH_SIZE / WRITE_SIZE of the GEMM kernel at this workload (rocprofv3 --pmc,
@@ -45,11 +46,11 @@ HBM_PEAK_GBS = 8000.0
 # (fetch x2, write x1); valid only for the GEMM source they were taken from.
 # Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
 TRAFFIC = {
-    ("split1_fp16", True): {"source_sha256_16": "0bae512632f1e4c5",
-                            "fetch_bytes": 3.277e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("split_bf16", True): {"source_sha256_16": "0bae512632f1e4c5",
-                           "fetch_bytes": 4.98e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("fp32", True): {"source_sha256_16": "0bae512632f1e4c5",
+    ("split1t_fp16", True): {"source_sha256_16": "9f7e172132c8e725",
+                             "fetch_bytes": 4.079e7 * 1024 * 2, "write_bytes": 1.29e5 * 1024},
+    ("split_bf16", True): {"source_sha256_16": "9f7e172132c8e725",
+                           "fetch_bytes": 5.009e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("fp32", True): {"source_sha256_16": "9f7e172132c8e725",
                      "fetch_bytes": 4.903e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
 }
 
@@ -416,7 +417,7 @@ def run_precision_m4000(args, mp, torch, synth):
     M, T, r, seed, bins, wins = w.M, w.T, w.r, w.seed, w.bins, w.windows
     E = w.E
     res = {}
-    for prec in ("fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16"):
+    for prec in ("fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16"):
         p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=4,
                               mode="marginals_and_total", windows=wins, n_sub=E // ns,
                               samples_per_sub=ns, chunk=chunk)
@@ -434,7 +435,7 @@ def run_precision_m4000(args, mp, torch, synth):
     off = np.cumsum([0] + [k for _, k in wins])
     s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
     per = {}
-    for prec in ("fp32", "split_bf16", "split_fp16", "split1_fp16"):
+    for prec in ("fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16"):
         secs, P = res[prec][0], res[prec][1]
         rows = []
         for b in range(5):
@@ -453,6 +454,47 @@ def run_precision_m4000(args, mp, torch, synth):
         f"M4000_t0.95_rU[0.5,1.5]: 4 equal bins + total, E={E} in chunks of {chunk}, "
         f"{E // ns} sub-ensembles", "split-bf16 (fp32 acc)",
         fp64_run_s=s64, fp64_samples_M2_per_s=E * M ** 2 / s64, precisions=per)
+
+
+def run_precision_m8000(args, mp, torch, synth):
+    """The headline workload at the criterion's sample count: M = 8000, Haar x
+    0.95, r = 1, total counts, E = 11 chunks of 65536 (88 sub-ensembles of
+    8192, max sigma_T / max P about 1e-3), every precision through the
+    benchmark's launch (the occupation-fused GEMM; FP64 through C) on the same
+    noise, each compared with the FP64 GPU path bin by bin in units of its
+    sigma_T."""
+    chunk, ns = 65536, 8192
+    E = 11 * chunk
+    w = synth.workload_m8000(E=E, chunk=chunk)
+    res = {}
+    for prec in ("fp64", "split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
+        p = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
+                              n_sub=E // ns, samples_per_sub=ns, chunk=chunk,
+                              fused=prec != "fp64")
+        secs = _timed(torch, p.run)
+        res[prec] = (secs,) + p.result()
+        log(f"[bench] precision_m8000 {prec}: {secs:.3f} s")
+        del p
+        torch.cuda.empty_cache()
+    s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
+    bulk = P64 > 1e-3 * P64.max()
+    per = {}
+    for prec in ("split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
+        secs, P = res[prec][0], res[prec][1]
+        err = np.abs(P - P64)
+        per[prec] = {"run_s": secs, "max_abs_err": float(err.max()),
+                     "max_err_over_sigma": float((err / sig64)[bulk].max()),
+                     "mean_err_over_sigma": float((err / sig64)[bulk].mean())}
+        log(f"[bench] precision_m8000 {prec}: max |P - P64| / sigma_T = "
+            f"{per[prec]['max_err_over_sigma']:.3e}")
+    main = res["split1t_fp16"][0]
+    return _envelope(
+        "samples·M²/s, M=8000 run to max sigma_T <= 1e-3 max P, T-split FP16 "
+        "(error vs FP64 per bin in config)",
+        E * w.M ** 2 / main, "samples·M²/s", 1e3 * main / (E / chunk),
+        f"M8000_t0.95_r1: total counts, E={E} in chunks of {chunk}, {E // ns} sub-ensembles",
+        "split-fp16 x fp16 (fp32 acc)", fp64_run_s=s64,
+        sigma_max_over_P_max=float(sig64.max() / P64.max()), precisions=per)
 
 
 def _batched_leg(mp, torch, nets, chunk, label, prec="split_fp16"):
@@ -963,7 +1005,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="split1_fp16")
+    ap.add_argument("--prec", default="split1t_fp16")
     ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
     ap.add_argument("--compare-steps", type=int, default=5)
     ap.add_argument("--also", default="split_bf16",
@@ -975,7 +1017,8 @@ def main():
     ap.add_argument("--unfused", action="store_true",
                     help="m8000: write C and count from it instead of the occupation-fused GEMM")
     ap.add_argument("--workload", default="m8000",
-                    choices=["m8000", "joint_m1000", "precision_m4000", "batched", "surrogate",
+                    choices=["m8000", "joint_m1000", "precision_m4000", "precision_m8000", "batched",
+                             "surrogate",
                              "plusp_m20", "moments_m1000", "pairs_m1000", "joint3_m300",
                              "scaling_appb", "copy"],
                     help="m8000 (default) is the headline metric; the others measure the other "
@@ -993,7 +1036,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     runners = {"m8000": run_m8000, "joint_m1000": run_joint_m1000,
-               "precision_m4000": run_precision_m4000, "batched": run_batched,
+               "precision_m4000": run_precision_m4000, "precision_m8000": run_precision_m8000,
+               "batched": run_batched,
                "surrogate": run_surrogate, "plusp_m20": run_plusp_m20,
                "moments_m1000": run_moments_m1000, "pairs_m1000": run_pairs_m1000,
                "joint3_m300": run_joint3_m300,

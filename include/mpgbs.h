@@ -55,6 +55,10 @@ typedef enum {
   MP_SPLIT_FP16 = 3, /* hi/lo FP16 operands, 3 FP16 MFMA products, FP32 accumulate */
   MP_SPLIT1_FP16 = 4, /* T as one FP16 value, samples hi/lo FP16 (MP_SPLIT_FP16's sample
                          layout), 2 FP16 MFMA products, FP32 accumulate */
+  MP_SPLIT1T_FP16 = 5, /* T hi/lo FP16 (MP_SPLIT_FP16's packing), samples as one FP16
+                          value (column pairs, below), 2 FP16 MFMA products, FP32
+                          accumulate: the rounding error is per sample and averages
+                          like the sampling noise */
   /* Range markers, not values: with them every int is a representable
    * mp_precision, so an out-of-range argument reaches the library's check
    * (MP_ERR_ARG) instead of being undefined on the C++ side.  The same holds
@@ -120,6 +124,13 @@ size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
  *          stride 2 ldm: mode j of a column has hi at 64 (j / 32) + j % 32 and
  *          lo 32 values further (blocks of 32 hi values, each followed by
  *          its 32 lo values).
+ *          SPLIT1T_FP16 -> one FP16 value per entry, in storage columns: alpha
+ *          of sample k in column k, beta in column E2 + k with E2 = E rounded
+ *          up to even; columns 2q and 2q + 1 are stored as a pair, mode j of
+ *          column c at (c / 2) 2 ldm + 64 (j / 32) + j % 32 + 32 (c % 2) (for
+ *          each 32-mode block, the pair's two 32-value runs side by side).
+ *          With E odd the storage columns E and E2 + E are padding, written
+ *          as zeros.
  *   n_out  device FP64[E]: n = sum_j alpha_j beta_j of the values as stored
  *          (after rounding to `prec`).
  */
@@ -461,7 +472,7 @@ typedef struct {
  * and captures the whole pass in a hipGraph: accumulators cleared by fill
  * kernels, sampling, ONE persistent grouped GEMM launch over all networks'
  * tiles per pass for the split precisions (MP_SPLIT_BF16, MP_SPLIT_FP16,
- * MP_SPLIT1_FP16) with the occupation-fused epilogue of mp_propagate_counts
+ * MP_SPLIT1_FP16, MP_SPLIT1T_FP16) with the occupation-fused epilogue of mp_propagate_counts
  * (FP32 plans run mp_propagate_counts per network, FP64 plans one GEMM writing
  * C and the counts from it per network), counts from the per-block occupation
  * partials
@@ -493,7 +504,7 @@ mp_status mp_plan_info(void* plan, int32_t* order, int32_t* prefetch, double* tu
 
 /* Tile of network i in the grouped GEMM: 128 modes by 128 or 64 samples (the
  * autotuner's per size class choice for MP_SPLIT_BF16 and MP_SPLIT_FP16; both
- * give the same bits), 128 x 128 for MP_SPLIT1_FP16, 0 x 0 for plans without
+ * give the same bits), 128 x 128 for the one-sided splits, 0 x 0 for plans without
  * a grouped launch (FP64, FP32).  i outside [0, n_net): MP_ERR_ARG.  Either
  * output pointer may be NULL. */
 mp_status mp_plan_tile(void* plan, int32_t i, int32_t* modes, int32_t* samples);

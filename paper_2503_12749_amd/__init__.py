@@ -329,9 +329,17 @@ class CountsPipeline:
 
     def alpha_beta(self, E: int):
         """Views of the last chunk's stored amplitudes as numpy (E, M) arrays
-        (FP64 and FP32 storage only; synchronises)."""
+        (FP64, FP32 and the T-split form's single FP16 storage; synchronises)."""
         t = self.torch
         ldm = mp_ld_modes(self.M)
+        if self.prec == _lib.PRECISIONS["split1t_fp16"]:
+            h = self.ab.view(t.float16).double().cpu().numpy()
+            e2 = E + (E & 1)
+            j = np.arange(self.M)
+            def cols(c):
+                c = np.asarray(c)[:, None]
+                return h[(c >> 1) * 2 * ldm + 64 * (j >> 5) + (j & 31) + (c & 1) * 32]
+            return cols(np.arange(E)), cols(e2 + np.arange(E))
         dt = {0: t.float64, 1: t.float32}[self.prec]
         v = self.ab.view(dt)[: ldm * 2 * E].reshape(2 * E, ldm)[:, : self.M].double().cpu().numpy()
         return v[:E], v[E:]

@@ -75,13 +75,18 @@ inline size_t elem_bytes_ab(mp_precision p) {
   switch (p) {
     case MP_FP64: return 8;
     case MP_FP32: return 4;
+    case MP_SPLIT1T_FP16: return 2;  // one FP16 value (storage columns: split1t_half)
     default: return 4;  // hi + lo values of 2 bytes each
   }
 }
 
 inline size_t elem_bytes_c(mp_precision p) { return p == MP_FP64 ? 8 : 4; }
 
-inline bool valid_prec(int p) { return p >= MP_FP64 && p <= MP_SPLIT1_FP16; }
+inline bool valid_prec(int p) { return p >= MP_FP64 && p <= MP_SPLIT1T_FP16; }
+
+// Storage columns per half of the MP_SPLIT1T_FP16 sample operand: E rounded
+// up to even, so that the beta columns start a column pair.
+__host__ __device__ inline int64_t split1t_half(int64_t E) { return E + (E & 1); }
 
 // Wave-wide sums (64 lanes) via cross-lane shuffles.
 __device__ inline double wave_sum(double v) {

@@ -154,7 +154,7 @@ static void plan_free(Plan* p) {
 // The split precisions run one grouped GEMM per pass; the three-product ones
 // offer two tile widths (the one-sided split kernel has the 128-sample tile only).
 static bool split(mp_precision p) {
-  return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16 || p == MP_SPLIT1_FP16;
+  return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16 || p == MP_SPLIT1_FP16 || p == MP_SPLIT1T_FP16;
 }
 static bool two_widths(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16; }
 
@@ -542,7 +542,9 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         PlanNet& n = p->nets[i];
         const int64_t e = std::max<int64_t>(0, std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk));
         const float sc = ldexpf(1.0f, -split_scale_exp(n.d.M, prec));
-        g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, nullptr, n.ldm, 2 * e, sc,
+        // the T-split sample operand's storage columns: beta from E2 on
+        const int64_t cols = prec == MP_SPLIT1T_FP16 ? 2 * split1t_half(e) : 2 * e;
+        g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, nullptr, n.ldm, cols, sc,
                         FusedOut{}};
         if (e > 0) {
           const int32_t m_lo = n.d.m_lo, K = n.d.K;

@@ -107,22 +107,25 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
 // and column block (measured faster than XCD-local groups of 8 row tiles).
 constexpr int kStepRows = 8, kStepColsPerXcd = 4;
 
+// SR row tiles by SC column tiles per XCD and step (SR SC = 32 workgroups).
+template <int SR = kStepRows, int SC = kStepColsPerXcd>
 __device__ inline bool tile_of_block(int tiles_m, int tiles_n, int& tm, int& tn) {
   const int b = blockIdx.x, x = b % kXcds, q = b / kXcds;
-  const int per_xcd = kStepRows * kStepColsPerXcd;   // 32 blocks of one XCD per step
+  const int per_xcd = SR * SC;   // 32 blocks of one XCD per step
   const int s = q / per_xcd, j = q % per_xcd;
-  const int cols_per_step = kXcds * kStepColsPerXcd;  // 32 column tiles per step
+  const int cols_per_step = kXcds * SC;  // column tiles per step
   const int n_cg = (tiles_n + cols_per_step - 1) / cols_per_step;
   const int rg = s / n_cg, cg = s % n_cg;
-  tm = rg * kStepRows + j % kStepRows;
-  tn = cg * cols_per_step + x * kStepColsPerXcd + j / kStepRows;
+  tm = rg * SR + j % SR;
+  tn = cg * cols_per_step + x * SC + j / SR;
   return tm < tiles_m && tn < tiles_n;
 }
 
+template <int SR = kStepRows, int SC = kStepColsPerXcd>
 __host__ __device__ inline int mall_grid_blocks(int tiles_m, int tiles_n) {
-  const int n_cg = (tiles_n + kXcds * kStepColsPerXcd - 1) / (kXcds * kStepColsPerXcd);
-  const int n_rg = (tiles_m + kStepRows - 1) / kStepRows;
-  return n_rg * n_cg * kXcds * kStepRows * kStepColsPerXcd;
+  const int n_cg = (tiles_n + kXcds * SC - 1) / (kXcds * SC);
+  const int n_rg = (tiles_m + SR - 1) / SR;
+  return n_rg * n_cg * kXcds * SR * SC;
 }
 
 // ---------------------------------------------------------------- split, 256 x 256
@@ -1051,6 +1054,264 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1_occ(const uint16_t* _
                            out_scale, &fo);
 }
 
+// ---------------------------------------------------------------- one-sided split of T, 256 x 256
+
+// MP_SPLIT1T_FP16: the transmission operand is split, T = T_hi + T_lo (the
+// MP_SPLIT_FP16 packing, prescaled by 2^e), and the sampled amplitudes are one
+// FP16 value each, so each product is A_hi B + A_lo B: two
+// v_mfma_f32_32x32x16_f16 per fragment pair.  The propagation is the one of
+// the FP16-rounded samples through T to the split's 2^-22; the rounding error
+// is a different draw for every sample, so it averages over the ensemble like
+// the sampling noise (no bias of the network itself).
+//
+// The mirror of split1_pp_tile: a 48 KB stage holds B as 128 column pairs of
+// 128 bytes (plane 0: one pair's two 32-value runs side by side, as the
+// sampler stores them) and A as 256 rows of 128 bytes (planes 1-2: a row's hi
+// and lo blocks of one slab); 16-byte chunk c of LDS row r at c ^ swz8(r).
+// Load g = 12 w + q of a slab fills B pairs 8 g .. 8 g + 7 (g < 16) or A rows
+// 8 (g - 16) .. 8 (g - 16) + 7, eight whole lines per load.
+//
+// Columns are storage columns of the sample operand (split1t_half): FUSED
+// tiles take the alpha pairs of samples [n0, n0 + 128) and the beta pairs
+// (E2 = ncols / 2 further); pairs past the chunk repeat its last pair.  The
+// C-writing form maps storage column c to C column c (alpha, c < E) or
+// E + c - E2 (beta) and skips the padding columns of an odd E (`e_real`).
+// PFA: the L2 prefetch touches the lines of A's rows (else of B's pairs).
+template <bool FUSED, bool PF, bool PFA>
+__device__ __attribute__((always_inline)) inline void split1t_pp_tile(
+    uint16_t* __restrict__ lds, const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+    float* __restrict__ C, int64_t ldm, int64_t ncols, int64_t e_real, int64_t m0, int64_t n0,
+    float out_scale, const FusedOut* fo, int tid = -1) {
+  typedef f16x8 frag;
+  constexpr int NST = kSplit1Stages;
+  const int wave = tid < 0 ? (int)(threadIdx.x >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid < 0 ? (int)(threadIdx.x & 63) : tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  auto a_row = [&](int r) -> int64_t {
+    if constexpr (FUSED) return r < 128 ? m0 + r : ldm + m0 + (r - 128);
+    return m0 + r;
+  };
+  // first storage column of tile column pair pr (tile columns 2 pr, 2 pr + 1)
+  const int64_t half = FUSED ? ncols / 2 : ncols;  // storage columns per block
+  auto b_pair = [&](int pr) -> int64_t {
+    if constexpr (FUSED) {
+      const int64_t c = n0 + 2 * (pr & 63);
+      return (c <= half - 2 ? c : half - 2) + (pr >= 64 ? half : 0);
+    }
+    const int64_t c = n0 + 2 * pr;
+    return c <= half - 2 ? c : half - 2;
+  };
+  const char* src[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int g = 12 * wave + q;
+    if (g < 16) {
+      // B pairs 8 g .. 8 g + 7: lane l fills slot l % 8 of pair l / 8 with
+      // global chunk (l % 8) ^ swz8(pair) (chunks 0-3 the even column, 4-7 the odd)
+      const int pr = 8 * g + (lane >> 3);
+      src[q] = (const char*)(B + b_pair(pr) * ldm + (((lane & 7) ^ swz8(pr)) * 8));
+    } else {
+      // A rows 8 (g - 16) .. + 7, hi chunks 0-3 and lo chunks 4-7
+      const int ra = 8 * (g - 16) + (lane >> 3);
+      src[q] = (const char*)(A + a_row(ra) * 2 * ldm + (((lane & 7) ^ swz8(ra)) * 8));
+    }
+  }
+  // both operands advance 2 k0 values per slab (hi and lo blocks, or the
+  // pair's two runs)
+  auto issue = [&](int st, int64_t k0) {
+    char* base = (char*)(lds + st * S1_NPL * S_PLANE);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      const int g = 12 * wave + q;
+      char* dst = base + (g >> 4) * (S_PLANE * 2) + (g & 15) * 1024;
+      __builtin_amdgcn_global_load_lds((const void*)(src[q] + (k0 << 2)), (lds_void*)dst, 16, 0,
+                                       0);
+    }
+  };
+  // L2 prefetch of slab k0 into the sink after the stages: one 4-byte load
+  // per wave and slab, 64 A rows per wave (PFA) or 32 B pairs per wave (each
+  // touched by two lanes)
+  const char* pf_src = PFA ? (const char*)(A + a_row(64 * wave + lane) * 2 * ldm)
+                           : (const char*)(B + b_pair(32 * wave + (lane & 31)) * ldm);
+  auto prefetch = [&](int64_t k0) {
+    if constexpr (!PF) return;
+    __builtin_amdgcn_global_load_lds((const void*)(pf_src + (k0 << 2)),
+                                     (lds_void*)(lds + NST * S1_NPL * S_PLANE), 4, 0, 0);
+  };
+  constexpr int NPF = 1;
+  // fragment offsets: A hi and lo in planes 1-2 (128-byte rows), B in plane 0
+  // (128-byte pair rows)
+  int oah[2][4], oal[2][4], ob[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+      oah[s][i] = ra * 2 * S_BK + (((2 * lh + s) ^ swz8(ra)) << 3);
+      oal[s][i] = ra * 2 * S_BK + (((4 + 2 * lh + s) ^ swz8(ra)) << 3);
+      const int pr = rb >> 1;
+      ob[s][i] = pr * 2 * S_BK + ((((rb & 1) * 4 + 2 * lh + s) ^ swz8(pr)) << 3);
+    }
+  frag b0[4], ah0[4], al0[4], b1[4], ah1[4], al1[4];
+  auto plane = [&](int st, int p) { return lds + (st * S1_NPL + p) * S_PLANE; };
+  auto read0 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      al0[i] = *(const frag*)(plane(st, 1) + oal[0][i]);
+      b0[i] = *(const frag*)(plane(st, 0) + ob[0][i]);
+      ah0[i] = *(const frag*)(plane(st, 1) + oah[0][i]);
+    }
+  };
+  auto read1 = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      al1[i] = *(const frag*)(plane(st, 1) + oal[1][i]);
+      b1[i] = *(const frag*)(plane(st, 0) + ob[1][i]);
+      ah1[i] = *(const frag*)(plane(st, 1) + oah[1][i]);
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // the schedule and waits of split1_pp_tile (two stages)
+  constexpr int kGroup = PF ? 12 + NPF : 12;
+  constexpr int kWaitN = PF ? NPF : 0;
+  const int KT = (int)(ldm / S_BK);  // >= 4
+  issue(0, 0);
+  wait_vm<0>();  // slab 0 landed
+  barrier_no_fence();
+  issue(1, (int64_t)min(1, KT - 1) * S_BK);
+  prefetch((int64_t)min(1 + kPrefetchSlabs, KT - 1) * S_BK);
+  read0(0);
+  constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
+  int cur = 0;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int nxt = cur ^ 1;
+    // phase A: MFMAs on F0 (lo products first) with the reads of F1 between them
+    read1(cur);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al0[i], b0[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah0[i], b0[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 8, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    // own loads of slab kt + 1 landed (with PF only the prefetch load issued
+    // after them may be in flight), own reads of stage cur complete
+    __builtin_amdgcn_s_waitcnt((kWaitN & 15) | ((kWaitN >> 4) << 14) | (7 << 4));
+    barrier_no_fence();
+    __builtin_amdgcn_sched_barrier(0);
+    // phase B: MFMAs on F1 with slab kt + 2's loads and the reads of F0
+    // threaded in (the last slabs reload the final slab, in bounds)
+    issue(cur, (int64_t)min(kt + NST, KT - 1) * S_BK);
+    prefetch((int64_t)min(kt + NST + kPrefetchSlabs, KT - 1) * S_BK);
+    read0(nxt);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al1[i], b1[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah1[i], b1[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 32 - 12 - kGroup, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if constexpr (FUSED) {
+    fused_epilogue(acc, (float*)lds, *fo, m0, n0, wm, wn, lane, out_scale);
+    return;
+  }
+  const int64_t ldc = 2 * ldm, e2 = split1t_half(e_real);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t sc = n0 + wn * 128 + j * 32 + lr;  // storage column
+    if (sc >= ncols) continue;
+    int64_t col;
+    if (sc < e2) {
+      if (sc >= e_real) continue;  // padding of an odd E
+      col = sc;
+    } else {
+      if (sc - e2 >= e_real) continue;
+      col = e_real + (sc - e2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
+// The L2 prefetch of the T-split kernels touches the sample operand's pairs
+// (M = 8000, fused call: 51.3 ms against 55.7 ms touching A's rows; with 4 x 8
+// tiles per XCD step 52.0 and 56.2 ms).
+constexpr bool kSplit1tPfA = false;
+// Tile order of the T-split kernels: row tiles by column tiles per XCD and step.
+constexpr int kS1tStepRows = 8, kS1tStepCols = 4;
+
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t_pp(const uint16_t* __restrict__ A,
+                                                               const uint16_t* __restrict__ B,
+                                                               float* __restrict__ C, int64_t ldm,
+                                                               int64_t ncols, int64_t e_real,
+                                                               float out_scale) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[kSplit1LdsElems];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
+  split1t_pp_tile<false, PF, kSplit1tPfA>(lds, A, B, C, ldm, ncols, e_real, (int64_t)tm * S_BM,
+                                          (int64_t)tn * S_BN, out_scale, nullptr);
+}
+
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t_occ(const uint16_t* __restrict__ A,
+                                                                const uint16_t* __restrict__ B,
+                                                                int64_t ldm, int64_t ncols,
+                                                                float out_scale, FusedOut fo) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[kSplit1LdsElems];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
+  split1t_pp_tile<true, PF, kSplit1tPfA>(lds, A, B, nullptr, ldm, ncols, 0, (int64_t)tm * 128,
+                                         (int64_t)tn * 128, out_scale, &fo);
+}
+
 // ---------------------------------------------------------------- FP32, 256 x 256
 
 // FP32 twin of the split ping-pong kernel: the same 256 x 256 tile, four
@@ -1288,6 +1549,26 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1_grouped(const GroupNe
   }
 }
 
+// T-split form of the grouped launch (256 x 256 tiles; GroupNet::ncols holds
+// the storage columns 2 E2 of the network's chunk).
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t_grouped(const GroupNet* __restrict__ nets,
+                                                                    const int4* __restrict__ items,
+                                                                    int n_items) {
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[kSplit1LdsElems];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];  // (net, tile_m, tile_n, 4)
+    if (w.x < 0) continue;
+    const GroupNet* g = nets + w.x;
+    int tid = threadIdx.x;  // opaque per item, as in gemm_split_grouped
+    asm volatile("" : "+v"(tid));
+    split1t_pp_tile<true, PF, kSplit1tPfA>(lds, g->A, g->B, nullptr, g->ldm, g->ncols, 0,
+                                           (int64_t)w.y * 128, (int64_t)w.z * 128, g->out_scale,
+                                           &g->fo, tid);
+    __syncthreads();  // the next item reuses the LDS stages
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 size_t propagate_workspace(int32_t M, mp_precision prec) {
@@ -1304,6 +1585,10 @@ size_t propagate_workspace(int32_t M, mp_precision prec) {
 static int grid_tiles(int64_t ldm, int64_t ncols, int bm, int bn) {
   return mall_grid_blocks((int)(2 * ldm / bm), (int)((ncols + bn - 1) / bn));
 }
+static int grid_tiles_s1t(int64_t ldm, int64_t ncols) {
+  return mall_grid_blocks<kS1tStepRows, kS1tStepCols>((int)(2 * ldm / S_BM),
+                                                       (int)((ncols + S_BN - 1) / S_BN));
+}
 
 // Power-of-two prescale of T for the FP16 split operand: |T_ij| ~ M^-1/2 for
 // a spread-out network, so 2^floor(log2(M)/2) brings typical entries near 1.
@@ -1316,7 +1601,9 @@ static int fp16_scale_exp(int32_t M) {
 // ---- used by plans (plan.hip)
 
 int split_scale_exp(int32_t M, mp_precision prec) {
-  return (prec == MP_SPLIT_FP16 || prec == MP_SPLIT1_FP16) ? fp16_scale_exp(M) : 0;
+  return (prec == MP_SPLIT_FP16 || prec == MP_SPLIT1_FP16 || prec == MP_SPLIT1T_FP16)
+             ? fp16_scale_exp(M)
+             : 0;
 }
 
 mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
@@ -1337,6 +1624,7 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
                          M, ldm, packed, 0);
       break;
     case MP_SPLIT_FP16:
+    case MP_SPLIT1T_FP16:  // the same hi/lo packing
       hipLaunchKernelGGL(pack_transmission<MP_SPLIT_FP16>, dim3(blocks), dim3(256), 0, stream, T,
                          M, ldm, packed, fp16_scale_exp(M));
       break;
@@ -1391,6 +1679,15 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
                          ncols, ldexpf(1.0f, -fp16_scale_exp(M)));
       break;
     }
+    case MP_SPLIT1T_FP16: {
+      // tiles over the storage columns (2 E2), stored to C columns
+      const int64_t scols = 2 * split1t_half(E);
+      auto kernel = split_prefetch_for(ldm) ? gemm_split1t_pp<true> : gemm_split1t_pp<false>;
+      hipLaunchKernelGGL(kernel, dim3(grid_tiles_s1t(ldm, scols)), dim3(kThreads), 0, stream,
+                         (const uint16_t*)packed, (const uint16_t*)ab, (float*)C, ldm, scols, E,
+                         ldexpf(1.0f, -fp16_scale_exp(M)));
+      break;
+    }
     default:
       set_error("mp_propagate: unknown precision %d", (int)prec);
       return MP_ERR_ARG;
@@ -1414,6 +1711,9 @@ mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_item
                        d_nets, d_items, n_items);
   } else if (prec == MP_SPLIT1_FP16) {
     hipLaunchKernelGGL(prefetch ? gemm_split1_grouped<true> : gemm_split1_grouped<false>,
+                       dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
+  } else if (prec == MP_SPLIT1T_FP16) {
+    hipLaunchKernelGGL(prefetch ? gemm_split1t_grouped<true> : gemm_split1t_grouped<false>,
                        dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
   } else {
     set_error("grouped GEMM: the split precisions only");
@@ -1450,6 +1750,14 @@ mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precisi
       auto kernel = split_prefetch_for(ldm) ? gemm_split1_occ<true> : gemm_split1_occ<false>;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, stream, (const uint16_t*)packed,
                          (const uint16_t*)ab, ldm, ncols, ldexpf(1.0f, -fp16_scale_exp(M)), fo);
+      break;
+    }
+    case MP_SPLIT1T_FP16: {
+      const int64_t scols = 2 * split1t_half(E);  // storage columns, beta from E2 on
+      auto kernel = split_prefetch_for(ldm) ? gemm_split1t_occ<true> : gemm_split1t_occ<false>;
+      hipLaunchKernelGGL(kernel, dim3(grid_tiles_s1t(ldm, scols)), dim3(kThreads), 0, stream,
+                         (const uint16_t*)packed, (const uint16_t*)ab, ldm, scols,
+                         ldexpf(1.0f, -fp16_scale_exp(M)), fo);
       break;
     }
     default:

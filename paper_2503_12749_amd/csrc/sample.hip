@@ -182,6 +182,13 @@ __device__ inline void store_pair_f32(void* ab, int64_t off, float x0, float x1,
     *(uint32_t*)(q + off + 32) = (uint32_t)l0 | ((uint32_t)l1 << 16);
     y0 = (double)bf16_val(h0) + (double)bf16_val(l0);
     y1 = (double)bf16_val(h1) + (double)bf16_val(l1);
+  } else if constexpr (PREC == MP_SPLIT1T_FP16) {
+    // one FP16 value per entry (off from split1t_offset)
+    const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
+    typedef __attribute__((ext_vector_type(2))) _Float16 h2;
+    *(h2*)((_Float16*)ab + off) = h2{h0, h1};
+    y0 = (double)(float)h0;
+    y1 = (double)(float)h1;
   } else {
     const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
     const _Float16 l0 = (_Float16)(x0 - (float)h0), l1 = (_Float16)(x1 - (float)h1);
@@ -192,6 +199,12 @@ __device__ inline void store_pair_f32(void* ab, int64_t off, float x0, float x1,
     y0 = (double)(float)h0 + (double)(float)l0;
     y1 = (double)(float)h1 + (double)(float)l1;
   }
+}
+
+// MP_SPLIT1T_FP16 storage: mode j of storage column c (column pairs, each
+// 32-mode block holding the pair's two runs of 32 values side by side).
+__device__ inline int64_t split1t_offset(int64_t c, int64_t j, int64_t ldm) {
+  return (c >> 1) * 2 * ldm + 64 * (j >> 5) + (j & 31) + (c & 1) * 32;
 }
 
 // Each wavefront owns kWaveSamples consecutive samples; its lanes stride over
@@ -230,12 +243,19 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
     for (int s = 0; s < kWaveSamples; ++s) {
       if (s >= nk) break;
       const int64_t k = k0 + s;
-      // column stride ldm (FP64, FP32) or 2 ldm (split, hi and lo interleaved)
-      const int64_t col_a = (PREC == MP_FP64 || PREC == MP_FP32) ? k * ldm + j0
-                                                                 : k * 2 * ldm + 64 * (j0 >> 5) + (j0 & 31);
-      const int64_t col_b = (PREC == MP_FP64 || PREC == MP_FP32)
-                                ? (E + k) * ldm + j0
-                                : (E + k) * 2 * ldm + 64 * (j0 >> 5) + (j0 & 31);
+      // column stride ldm (FP64, FP32) or 2 ldm (split, hi and lo
+      // interleaved); the T-split form stores column pairs, beta from E2 on
+      int64_t col_a, col_b;
+      if constexpr (PREC == MP_FP64 || PREC == MP_FP32) {
+        col_a = k * ldm + j0;
+        col_b = (E + k) * ldm + j0;
+      } else if constexpr (PREC == MP_SPLIT1T_FP16) {
+        col_a = split1t_offset(k, j0, ldm);
+        col_b = split1t_offset(split1t_half(E) + k, j0, ldm);
+      } else {
+        col_a = k * 2 * ldm + 64 * (j0 >> 5) + (j0 & 31);
+        col_b = (E + k) * 2 * ldm + 64 * (j0 >> 5) + (j0 & 31);
+      }
       uint64_t c0 = (uint64_t)(g0 + k), c1 = (uint64_t)p, c2 = net, c3 = 0;
       if (j0 < M) philox4x64_10(c0, c1, c2, c3, seed, 0);
       if constexpr (PREC == MP_FP64) {
@@ -262,6 +282,15 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
         store_pair_f32<PREC>(ab, col_a, a0, a1, ya0, ya1);
         store_pair_f32<PREC>(ab, col_b, b0, b1, yb0, yb1);
         nsum[s] += ya0 * yb0 + ya1 * yb1;
+        if constexpr (PREC == MP_SPLIT1T_FP16) {
+          // odd E: the last sample (even k) shares its pairs with the padding
+          // columns E and E2 + E, which the GEMM reads; they hold zeros
+          if ((E & 1) && k == E - 1) {
+            double z0, z1;
+            store_pair_f32<PREC>(ab, col_a + 32, 0.0f, 0.0f, z0, z1);
+            store_pair_f32<PREC>(ab, col_b + 32, 0.0f, 0.0f, z0, z1);
+          }
+        }
       }
     }
   }
@@ -298,6 +327,10 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
     case MP_SPLIT1_FP16:  // the same split sample layout
       hipLaunchKernelGGL(sample_kernel<MP_SPLIT_FP16>, dim3((unsigned)blocks), dim3(256), 0, stream,
                          M, ldm, g0, E, r, seed, net, ab, n_out);
+      break;
+    case MP_SPLIT1T_FP16:
+      hipLaunchKernelGGL(sample_kernel<MP_SPLIT1T_FP16>, dim3((unsigned)blocks), dim3(256), 0,
+                         stream, M, ldm, g0, E, r, seed, net, ab, n_out);
       break;
     default:
       set_error("mp_sample: unknown precision %d", (int)prec);

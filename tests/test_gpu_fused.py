@@ -56,7 +56,7 @@ def _run(fused, prec, est, M=333, E=1000, n_sub=5, chunk=384, seed=71, t=0.9):
     return P, s, T, r, bins, wins
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "split1_fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16"])
 @pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
 def test_fused_equals_unfused(prec, est):
     Pf, sf, *_ = _run(True, prec, est)
@@ -102,6 +102,47 @@ def test_fused_joint_equals_unfused(prec, est, d):
     assert abs(Pf.sum() - 1) < 1e-6
     assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-6 * scale), np.abs(Pf - Pu).max()
     np.testing.assert_allclose(sf, su, rtol=1e-3, atol=1e-6 * scale)
+
+
+def test_split1t_odd_chunks_fused_equals_unfused():
+    """The T-split form in chunks of odd length (333, 333, 333 and 2 samples:
+    padded column pairs in every chunk), marginals of three bins and the
+    total: fused and unfused agree, and both stay far inside sigma_T of the
+    FP64 oracle."""
+    import paper_2503_12749_amd as mp
+    M, E, n_sub = 300, 1001, 7
+    T = 0.9 * synth.haar_unitary(M, 91)
+    r = np.linspace(0.4, 1.2, M)
+    bins = _bins(M)
+    N = np.sinh(r) ** 2
+    wins = []
+    for b in range(3):
+        mb = 0.81 * N[bins == b].sum()
+        sb = np.sqrt(mb + 0.6561 * (N[bins == b] * (2 * N[bins == b] + 1)).sum())
+        wins.append(synth.count_window(mb, 1.5 * sb))
+    mt = 0.81 * N[bins >= 0].sum()
+    st = np.sqrt(mt + 0.6561 * (N[bins >= 0] * (2 * N[bins >= 0] + 1)).sum())
+    wins.append(synth.count_window(mt, 1.5 * st))
+    out = []
+    for fused in (True, False):
+        p = mp.CountsPipeline(T, r, prec="split1t_fp16", seed=29, bin_of_mode=bins, d=3,
+                              mode="marginals_and_total", windows=wins, n_sub=n_sub,
+                              samples_per_sub=E // n_sub, chunk=333, device=DEV, fused=fused)
+        p.run()
+        out.append(p.result())
+    (Pf, _, sf), (Pu, _, su) = out
+    scale = np.abs(Pu).max()
+    assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-6 * scale), np.abs(Pf - Pu).max()
+    mar = oest.estimate(T, r, 29, E, n_sub, bins, 3, wins[:3], mode="marginals", chunk=500)
+    tot = oest.estimate(T, r, 29, E, n_sub, np.where(bins >= 0, 0, -1), 1, wins[3:], mode="joint",
+                        chunk=500)
+    off = 0
+    for q in range(4):
+        K = wins[q][1]
+        Pr, sr = (mar["P"][q, :K], mar["sigma"][q, :K]) if q < 3 else (tot["P"], tot["sigma"])
+        for P in (Pf, Pu):
+            assert np.all(np.abs(P[off: off + K] - Pr) <= 0.05 * sr + 1e-6 * np.abs(Pr).max()), q
+        off += K
 
 
 def test_fused_matches_oracle():

@@ -259,7 +259,49 @@ def test_split1_propagation(M, E):
     assert np.abs(nS - (ao * bo).sum(1)).max() < 200 * 4e-6 * np.abs(n).max()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16"])
+@pytest.mark.parametrize("M,E", [(300, 201), (2049, 1100)])
+def test_split1t_sampler_and_propagation(M, E):
+    """The T-split one-sided form (T hi/lo FP16, samples as one FP16 value,
+    two products).  Sampler: every stored amplitude is the oracle's rounded
+    to FP16 (within half an FP16 ulp plus the FP32 evaluation's 5e-7 of the
+    term scale), n is the sum over the stored values, and the padding columns
+    of an odd E hold zeros.  GEMM: every element against the oracle
+    propagating the stored (rounded) samples through the exact network, at
+    the split's 2^-22 and FP32 accumulation (4e-6 of the largest per-sample
+    norm); E = 201 leaves a ragged tile and a padded column pair."""
+    import paper_2503_12749_amd as mp
+    prec = "split1t_fp16"
+    T = 0.95 * synth.haar_unitary(M, 12)
+    r = np.linspace(0.5, 1.5, M)
+    p = _pipe(T, r, prec=prec, seed=5, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, prec, p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, prec, p.ab, p.C, p.ws_prop)
+    a_s, b_s = p.alpha_beta(E)
+    a, b, n = osamp.sample(r, 0, E, 5)
+    scale = np.abs(a).max()
+    assert np.all(np.abs(a_s - a) <= 2.0 ** -11 * np.abs(a) + 5e-7 * scale + 1e-7)
+    assert np.all(np.abs(b_s - b) <= 2.0 ** -11 * np.abs(b) + 5e-7 * scale + 1e-7)
+    ng = p.n.cpu().numpy()
+    assert np.abs(ng - (a_s * b_s).sum(1)).max() <= 1e-12 * np.abs(a_s * b_s).sum(1).max()
+    if E % 2:
+        h = p.ab.view(torch.float16).cpu().numpy()
+        ldm = mp.mp_ld_modes(M)
+        j = np.arange(ldm)
+        for c in (E, E + 1 + E):  # the padding columns E and E2 + E
+            assert not h[(c >> 1) * 2 * ldm + 64 * (j >> 5) + (j & 31) + 32].any()
+    ag, bg = p.propagated(E)
+    ao, bo = oest.propagate(T, a_s, b_s)
+    norm = np.linalg.norm(ao, axis=1, keepdims=True).max()
+    err = max(np.abs(ag - ao).max(), np.abs(bg - bo).max()) / norm
+    at, bt = oest.propagate(T, a, b)
+    dist = max(np.abs(ag - at).max(), np.abs(bg - bt).max()) / norm
+    print(f"split1t M={M} E={E}: vs rounded samples {err:.2e}, vs unrounded samples {dist:.2e}")
+    assert err < 4e-6
+    assert dist < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16",
+                                  "split1t_fp16"])
 def test_pack_once_then_propagate_matches_propagate(prec):
     """mp_pack_transmission + mp_propagate_packed give the same bits as
     mp_propagate, over several tiles with ragged edges."""
@@ -340,7 +382,8 @@ def test_sampler_rounding_unbiased(prec):
         assert abs(got - ref) <= 1e-8 * abs(ref), (got, ref, (got - ref) / ref)
 
 
-@pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6), ("split_fp16", 1e-6)])
+@pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6), ("split_fp16", 1e-6),
+                                        ("split1_fp16", 1e-6), ("split1t_fp16", 1e-6)])
 def test_reduced_precision_counts_within_sigma(prec, floor):
     """M = 300, t = 0.9, r = 1: the reduced-precision estimate differs from the
     FP64 oracle on the same noise by far less than sigma_T.  Besides the

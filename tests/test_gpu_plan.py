@@ -47,7 +47,7 @@ def _single(n, prec):
     return p.result()
 
 
-@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "split1_fp16"])
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "split1_fp16", "split1t_fp16"])
 def test_plan_equals_single_network_runs(prec, tmp_path):
     import paper_2503_12749_amd as mp
     nets = _nets([60, 130, 300, 520], E=4096, n_sub=4)
@@ -56,7 +56,7 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     info = plan.info()
     assert 0 <= info["order"] < 3 and info["prefetch"] in (0, 1) and info["tuned_ms"] > 0
     assert len(info["tiles"]) == len(nets)
-    if prec == "split1_fp16":  # one tile width
+    if prec.startswith("split1"):  # one tile width
         assert info["tiles"] == [(128, 128)] * len(nets)
     first = []
     for rep in range(3):
@@ -166,7 +166,7 @@ def test_plan_fused_per_network_two_passes(prec):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "split1_fp16"])
+@pytest.mark.parametrize("prec", ["split_bf16", "split1_fp16", "split1t_fp16"])
 def test_plan_split_uneven_passes(prec):
     """Split plans over chunks of 2048 with networks of one and two passes:
     in the second pass the finished networks have no work items and no
