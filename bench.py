@@ -585,7 +585,7 @@ def run_batched(args, mp, torch, synth):
 def run_surrogate(args, mp, torch, synth):
     """The learned surrogate end to end: method-generated training sweeps
     (M in [100, 2000], t in [0.8, 0.99], rbar in [0.5, 1.5], s_r in [0, 0.3],
-    d in {1, 2, 4}; E = 4096 each), GPU training, then screening of 256
+    d in {1, 2, 4}; E = 1e4 each), GPU training, then screening of 256
     candidate profiles at M = 8000, t = 0.95, d = 4 with the method
     (E = 2^20 per judged candidate) as judge."""
     from paper_2503_12749_amd import surrogate as sg
@@ -593,7 +593,7 @@ def run_surrogate(args, mp, torch, synth):
     runner = sg.MethodRunner()
     sweeps = sg.sample_sweeps(args.sweeps, rng)
     t0 = time.perf_counter()
-    X, Y = sg.generate(runner, sweeps, E=4096, log_every=max(1, args.sweeps // 10))
+    X, Y = sg.generate(runner, sweeps, E=args.sweep_E, log_every=max(1, args.sweeps // 10))
     gen_s = time.perf_counter() - t0
     net = sg.Mlp(seed=3)
     t0 = time.perf_counter()
@@ -609,7 +609,7 @@ def run_surrogate(args, mp, torch, synth):
     return _envelope(
         "candidates screened per second by the surrogate, M=8000 (method time per candidate in config)",
         len(cands) / res["t_predict_s"], "candidates/s", 1e3 * res["t_predict_s"],
-        f"surrogate: {args.sweeps} training sweeps at E=4096, screening 256 profiles at M=8000, "
+        f"surrogate: {args.sweeps} training sweeps at E={args.sweep_E}, screening 256 profiles at M=8000, "
         f"t=0.95, d=4, judge E=2^20", "bf16 weights, fp32 accumulate",
         generate_s=gen_s, train_s=train_s, loss_first_last=[hist[0][1], hist[-1][1]],
         predict_s_256=res["t_predict_s"], method_s_per_candidate=per_method,
@@ -1024,6 +1024,7 @@ def main():
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
+    ap.add_argument("--sweep-E", type=int, default=10000, help="surrogate: samples per sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sample-sharded "

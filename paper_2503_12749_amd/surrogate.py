@@ -16,7 +16,7 @@ on the selected candidates, judges the predictions and replaces any that
 miss.
 
 Run as a module to generate data, train and screen:
-    python -m paper_2503_12749_amd.surrogate --sweeps 4000 --E 4096
+    python -m paper_2503_12749_amd.surrogate --sweeps 4000 --E 10000
 """
 from __future__ import annotations
 
@@ -329,7 +329,7 @@ def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_mean=0.01, tol_va
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sweeps", type=int, default=4000)
-    ap.add_argument("--E", type=int, default=4096)
+    ap.add_argument("--E", type=int, default=10000)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--screen-M", type=int, default=8000)
     ap.add_argument("--screen-E", type=int, default=1_048_576)
