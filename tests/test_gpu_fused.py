@@ -145,6 +145,32 @@ def test_split1t_odd_chunks_fused_equals_unfused():
         off += K
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split1_fp16", "split1t_fp16"])
+@pytest.mark.parametrize("M,E", [(1, 1), (1, 3), (5, 1), (5, 3)])
+def test_tiny_chunks_fused_and_unfused(prec, M, E):
+    """One mode or five, one sample or three (a single ragged tile, the
+    T-split form's padded column pair, n often negative): fused and unfused
+    agree to FP32 rounding, and both give the oracle's per-sample G(m) to the
+    precision's rounding (the operands' 2^-11 to 2^-22 relative, times counts
+    up to 31 in the exponent: within 2 % of max |P|)."""
+    import paper_2503_12749_amd as mp
+    rng = np.random.default_rng(M * 10 + E)
+    T = 0.8 * synth.haar_unitary(M, 7) if M > 1 else np.array([[0.7 * np.exp(0.4j)]])
+    r = rng.uniform(0.4, 1.2, M)
+    out = []
+    for fused in (True, False):
+        p = mp.CountsPipeline(T, r, prec=prec, seed=13, windows=[(0, 32)], n_sub=1,
+                              samples_per_sub=E, chunk=E, device=DEV, fused=fused)
+        p.run()
+        out.append(p.result()[0])
+    ref = oest.estimate(T, r, 13, E, 1, np.zeros(M, int), 1, [(0, 32)], chunk=E)["P"]
+    scale = np.abs(ref).max()
+    assert np.all(np.abs(out[0] - out[1]) <= 1e-4 * scale), np.abs(out[0] - out[1]).max()
+    for P in out:
+        assert np.all(np.isfinite(P))
+        assert np.abs(P - ref).max() <= 2e-2 * scale, np.abs(P - ref).max() / scale
+
+
 def test_fused_matches_oracle():
     """Split-BF16 fused run against the FP64 oracle on the same noise, per
     distribution (three bin marginals and the total): far inside sigma_T."""

@@ -190,6 +190,30 @@ def test_plan_split_uneven_passes(prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["split1t_fp16", "split_fp16"])
+def test_plan_odd_ensembles(prec):
+    """Odd sample counts per pass (999 and 333: the T-split form's padded
+    column pairs inside a grouped launch, ragged 64- and 128-sample tiles):
+    every network equals the fused single-network pipeline, bit for bit."""
+    import paper_2503_12749_amd as mp
+    nets = _nets([77, 150, 260], E=999, n_sub=3, seed0=808)
+    nets[1]["E"] = 333
+    nets[1]["n_sub"] = 1
+    plan = mp.Plan(nets, prec=prec, chunk=999)
+    plan.launch()
+    for i, n in enumerate(nets):
+        P, _, s = plan.result(i)
+        p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
+                              windows=[n["window"]], n_sub=n["n_sub"],
+                              samples_per_sub=n["E"] // n["n_sub"], chunk=999, fused=True)
+        p.run()
+        Pr, _, sr = p.result()
+        assert np.array_equal(P, Pr), i
+        assert np.array_equal(s, sr) or (n["n_sub"] == 1 and np.isnan(s).all() and np.isnan(sr).all()), i
+        assert abs(P.sum() - 1) < 1e-8
+    plan.close()
+
+
 def test_plan_rejects_bad_networks():
     import paper_2503_12749_amd as mp
     nets = _nets([32], E=1000, n_sub=3)
