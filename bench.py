@@ -989,6 +989,35 @@ def run_scaling_appb(args, mp, torch, synth):
                        "timing": timing, "errors": errors}}
 
 
+def run_mfma_peak(args, mp, torch, synth):
+    """The matrix cores' sustained rate with no memory traffic (the library's
+    probe: one workgroup of four waves per CU, 16 independent MFMA chains per
+    wave on register-resident operands), per instruction the GEMMs use, timed
+    with events; against the published dense peaks."""
+    sink = torch.empty(512 * 256, dtype=torch.float64, device="cuda:0")
+    out = {}
+    for kind, name, peak, iters in ((0, "fp16 32x32x16", 2500.0, 2000),
+                                    (1, "fp32 32x32x2", 157.3, 2000),
+                                    (2, "fp64 16x16x4", 78.6, 2000)):
+        mp.mp_mfma_sustained(kind, 100, sink)  # first launch
+        best = None
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            flops = mp.mp_mfma_sustained(kind, iters, sink)
+            b.record()
+            torch.cuda.synchronize()
+            s = a.elapsed_time(b) * 1e-3
+            best = s if best is None else min(best, s)
+        tf = flops / best / 1e12
+        out[name] = {"tflops": tf, "published_peak": peak, "fraction": tf / peak, "ms": 1e3 * best}
+        log(f"[bench] mfma_peak {name}: {tf:.1f} TFLOP/s = {100 * tf / peak:.1f} % of {peak}")
+    f16 = out["fp16 32x32x16"]
+    return _envelope("TFLOP/s of back-to-back FP16 MFMA (no memory traffic)", f16["tflops"],
+                     "TFLOP/s", f16["ms"], "matrix-core probe: 4 waves per CU, 16 chains per wave",
+                     "f16 (fp32 acc)", kinds=out)
+
+
 def run_copy(args, mp, torch, synth):
     """A plain 1 GiB device-to-device copy, three times: the reference for
     scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
@@ -1020,7 +1049,7 @@ def main():
                     choices=["m8000", "joint_m1000", "precision_m4000", "precision_m8000", "batched",
                              "surrogate",
                              "plusp_m20", "moments_m1000", "pairs_m1000", "joint3_m300",
-                             "scaling_appb", "copy"],
+                             "scaling_appb", "copy", "mfma_peak"],
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
@@ -1043,7 +1072,7 @@ def main():
                "moments_m1000": run_moments_m1000, "pairs_m1000": run_pairs_m1000,
                "joint3_m300": run_joint3_m300,
                "scaling_appb": run_scaling_appb,
-               "copy": run_copy}
+               "copy": run_copy, "mfma_peak": run_mfma_peak}
     out = runners[args.workload](args, mp, torch, synth)
     print(json.dumps(out), flush=True)
 

@@ -447,6 +447,25 @@ mp_status mp_pair_correlations_accumulate(int32_t M, int64_t E, const void* X, m
 mp_status mp_check_finite(const double* x, int64_t n, int64_t* scratch, int64_t* n_bad,
                           void* stream);
 
+/*
+ * Diagnostics: the matrix cores' sustained rate on the current device.  One
+ * workgroup of four waves (one per SIMD, the occupancy of the GEMM kernels)
+ * per compute unit; every wave issues `iters` rounds of 16 independent MFMAs
+ * on register-resident operands, with no memory traffic inside the loop.
+ *   kind   0: v_mfma_f32_32x32x16_f16, 1: v_mfma_f32_32x32x2f32,
+ *          2: v_mfma_f64_16x16x4f64; other values MP_ERR_ARG
+ *   iters  >= 1
+ *   sink   device FP64, one value per thread (256 per compute unit), caller-
+ *          owned and overwritten (keeps the products live); smaller:
+ *          MP_ERR_WORKSPACE
+ *   flops  host, may be NULL: the launch's MFMA flop count
+ * Asynchronous on `stream`; time it with events on that stream.  Not part of
+ * the estimator: it measures the ceiling the GEMMs run against (the clock the
+ * part holds under a pure matrix load).
+ */
+mp_status mp_mfma_sustained(int32_t kind, int64_t iters, double* sink, size_t sink_bytes,
+                            double* flops, void* stream);
+
 /* ---------------------------------------------------------------- batching */
 
 /* One network of a batched plan: total counts of all M outputs on the window

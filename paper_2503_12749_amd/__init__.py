@@ -23,7 +23,7 @@ __all__ = [
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
     "mp_pair_correlations_workspace", "mp_propagate_counts_workspace", "mp_propagate_counts", "mp_propagate_counts_noalloc",
     "mp_version", "CountsPipeline",
-    "PairPipeline", "Plan", "MPError", "mp_check_finite",
+    "PairPipeline", "Plan", "MPError", "mp_check_finite", "mp_mfma_sustained",
 ]
 
 
@@ -149,6 +149,16 @@ def mp_check_finite(x, scratch, stream=None) -> int:
     _lib.check(_lib.load().mp_check_finite(_ptr(x), x.numel(), _ptr(scratch), ctypes.byref(bad),
                                            _stream(stream)))
     return bad.value
+
+
+def mp_mfma_sustained(kind: int, iters: int, sink, stream=None) -> float:
+    """Launches the matrix-core rate probe (kind 0: FP16 32x32x16, 1: FP32
+    32x32x2, 2: FP64 16x16x4) on `stream`; sink is a device float64 tensor of
+    at least 256 entries per compute unit.  Returns the launch's flop count."""
+    flops = ctypes.c_double(0.0)
+    _lib.check(_lib.load().mp_mfma_sustained(kind, iters, _ptr(sink), sink.numel() * 8,
+                                             ctypes.byref(flops), _stream(stream)))
+    return flops.value
 
 
 def mp_mode_occupations_bytes(M: int, E: int, prec) -> int:

@@ -28,7 +28,7 @@ EXPORTS = [
     "mp_check_finite", "mp_pair_correlations_workspace",
     "mp_binned_workspace", "mp_binned_counts", "mp_propagate_counts_workspace",
     "mp_propagate_counts", "mp_propagate_counts_noalloc", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
-    "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_tile",
+    "mp_mfma_sustained", "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_tile",
     "mp_plan_destroy",
     "mp_mlp_param_count", "mp_mlp_workspace", "mp_mlp_round", "mp_mlp_forward", "mp_mlp_loss_grad",
     "mp_mlp_adam",
@@ -116,6 +116,7 @@ def load() -> ctypes.CDLL:
         "mp_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(sz)]),
         "mp_plan_tile": (ctypes.c_int, [vp, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+        "mp_mfma_sustained": (ctypes.c_int, [c_i32, c_i64, vp, sz, ctypes.POINTER(ctypes.c_double), vp]),
         "mp_plan_destroy": (ctypes.c_int, [vp]),
         "mp_mlp_param_count": (c_i64, [ctypes.POINTER(MlpShape)]),
         "mp_mlp_workspace": (sz, [ctypes.POINTER(MlpShape), c_i32]),

@@ -11,7 +11,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpgbs.so")
-SOURCES = ["api.cpp", "sample.hip", "propagate.hip", "counts.hip", "jointd.hip", "pairs.hip", "plan.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "sample.hip", "propagate.hip", "counts.hip", "jointd.hip", "pairs.hip", "plan.hip",
+           "mlp.hip", "diag.hip"]
 ARCH = os.environ.get("MPGBS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

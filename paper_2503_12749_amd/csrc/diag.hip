@@ -1,0 +1,123 @@
+// Diagnostics: the matrix cores' sustained rate on this device.  Every wave
+// issues rounds of 16 independent MFMAs on register-resident operands, with
+// no memory traffic inside the loop, so the launch runs at whatever clock the
+// part holds under a pure matrix load.  That rate, not the nominal peak, is
+// the ceiling a GEMM of the same instruction can approach.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace mp {
+
+typedef __attribute__((ext_vector_type(16))) float burn_f32x16;
+typedef __attribute__((ext_vector_type(4))) double burn_f64x4;
+typedef __attribute__((ext_vector_type(8))) _Float16 burn_f16x8;
+
+constexpr int kBurnChains = 16;  // independent accumulators per wave (256 AGPRs for the FP16/FP32 forms)
+
+// Flops of one MFMA of each kind.
+static double burn_flops(int kind) {
+  switch (kind) {
+    case 0: return 2.0 * 32 * 32 * 16;  // v_mfma_f32_32x32x16_f16
+    case 1: return 2.0 * 32 * 32 * 2;   // v_mfma_f32_32x32x2f32
+    default: return 2.0 * 16 * 16 * 4;  // v_mfma_f64_16x16x4f64
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256, 1) void mfma_burn(int64_t iters, double* __restrict__ sink) {
+  const int t = threadIdx.x;
+  // operands that differ across lanes and are not known to the compiler
+  const float x = 1.0f + (float)(t & 63) * (1.0f / 64.0f);
+  const float y = 0.5f + (float)((t * 7) & 63) * (1.0f / 128.0f);
+  double out = 0.0;
+  if constexpr (KIND == 0) {
+    burn_f16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = (_Float16)(x + 0.125f * e);
+      b[e] = (_Float16)(y - 0.0625f * e);
+    }
+    burn_f32x16 acc[kBurnChains];
+#pragma unroll
+    for (int c = 0; c < kBurnChains; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kBurnChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < kBurnChains; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out += acc[c][r];
+  } else if constexpr (KIND == 1) {
+    burn_f32x16 acc[kBurnChains];
+#pragma unroll
+    for (int c = 0; c < kBurnChains; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kBurnChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < kBurnChains; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out += acc[c][r];
+  } else {
+    burn_f64x4 acc[kBurnChains];
+#pragma unroll
+    for (int c = 0; c < kBurnChains; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[c][r] = 0.0;
+    const double xd = x, yd = y;
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kBurnChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xd, yd, acc[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < kBurnChains; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out += acc[c][r];
+  }
+  sink[(int64_t)blockIdx.x * blockDim.x + t] = out;
+}
+
+}  // namespace mp
+
+using namespace mp;
+
+extern "C" {
+
+mp_status mp_mfma_sustained(int32_t kind, int64_t iters, double* sink, size_t sink_bytes,
+                            double* flops, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(kind >= 0 && kind <= 2, MP_ERR_ARG, "mp_mfma_sustained: kind %d not in [0, 2]",
+               kind);
+  MP_CHECK_ARG(iters >= 1, MP_ERR_ARG, "mp_mfma_sustained: iters must be >= 1");
+  MP_CHECK_ARG(sink, MP_ERR_ARG, "mp_mfma_sustained: null sink");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    set_error("mp_mfma_sustained: device query failed");
+    return MP_ERR_HIP;
+  }
+  MP_CHECK_ARG(sink_bytes >= (size_t)cus * 256 * sizeof(double), MP_ERR_WORKSPACE,
+               "mp_mfma_sustained: sink of %zu bytes needed (256 doubles per compute unit)",
+               (size_t)cus * 256 * sizeof(double));
+  hipStream_t s = (hipStream_t)stream;
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(mfma_burn<0>, dim3(cus), dim3(256), 0, s, iters, sink); break;
+    case 1: hipLaunchKernelGGL(mfma_burn<1>, dim3(cus), dim3(256), 0, s, iters, sink); break;
+    default: hipLaunchKernelGGL(mfma_burn<2>, dim3(cus), dim3(256), 0, s, iters, sink); break;
+  }
+  MP_HIP_LAUNCH_CHECK("mp_mfma_sustained launch");
+  if (flops) *flops = (double)cus * 4 * kBurnChains * (double)iters * burn_flops(kind);
+  return MP_OK;
+}
+
+}  // extern "C"
