@@ -991,14 +991,17 @@ def run_scaling_appb(args, mp, torch, synth):
 
 def run_mfma_peak(args, mp, torch, synth):
     """The matrix cores' sustained rate with no memory traffic (the library's
-    probe: one workgroup of four waves per CU, 16 independent MFMA chains per
-    wave on register-resident operands), per instruction the GEMMs use, timed
+    probe: one workgroup of four waves per CU, 256 accumulator registers of
+    independent MFMA chains per wave on register-resident operands), per
+    instruction the GEMMs use, timed
     with events; against the published dense peaks."""
     sink = torch.empty(512 * 256, dtype=torch.float64, device="cuda:0")
     out = {}
-    for kind, name, peak, iters in ((0, "fp16 32x32x16", 2500.0, 2000),
-                                    (1, "fp32 32x32x2", 157.3, 2000),
-                                    (2, "fp64 16x16x4", 78.6, 2000)):
+    # about 50 ms per launch, the length of one GEMM of the benchmark (the
+    # clock settles under load within milliseconds)
+    for kind, name, peak, iters in ((0, "fp16 32x32x16", 2500.0, 200000),
+                                    (1, "fp32 32x32x2", 157.3, 100000),
+                                    (2, "fp64 16x16x4", 78.6, 50000)):
         mp.mp_mfma_sustained(kind, 100, sink)  # first launch
         best = None
         for _ in range(3):
@@ -1014,7 +1017,7 @@ def run_mfma_peak(args, mp, torch, synth):
         log(f"[bench] mfma_peak {name}: {tf:.1f} TFLOP/s = {100 * tf / peak:.1f} % of {peak}")
     f16 = out["fp16 32x32x16"]
     return _envelope("TFLOP/s of back-to-back FP16 MFMA (no memory traffic)", f16["tflops"],
-                     "TFLOP/s", f16["ms"], "matrix-core probe: 4 waves per CU, 16 chains per wave",
+                     "TFLOP/s", f16["ms"], "matrix-core probe: 4 waves per CU, 256 accumulator registers per wave",
                      "f16 (fp32 acc)", kinds=out)
 
 

@@ -450,8 +450,9 @@ mp_status mp_check_finite(const double* x, int64_t n, int64_t* scratch, int64_t*
 /*
  * Diagnostics: the matrix cores' sustained rate on the current device.  One
  * workgroup of four waves (one per SIMD, the occupancy of the GEMM kernels)
- * per compute unit; every wave issues `iters` rounds of 16 independent MFMAs
- * on register-resident operands, with no memory traffic inside the loop.
+ * per compute unit; every wave issues `iters` rounds of independent MFMAs (16
+ * chains for FP16 and FP32, 32 for FP64: 256 accumulator registers, as in the
+ * GEMMs) on register-resident operands, with no memory traffic in the loop.
  *   kind   0: v_mfma_f32_32x32x16_f16, 1: v_mfma_f32_32x32x2f32,
  *          2: v_mfma_f64_16x16x4f64; other values MP_ERR_ARG
  *   iters  >= 1

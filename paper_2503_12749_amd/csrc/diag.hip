@@ -1,5 +1,5 @@
 // Diagnostics: the matrix cores' sustained rate on this device.  Every wave
-// issues rounds of 16 independent MFMAs on register-resident operands, with
+// issues rounds of independent MFMAs on register-resident operands, with
 // no memory traffic inside the loop, so the launch runs at whatever clock the
 // part holds under a pure matrix load.  That rate, not the nominal peak, is
 // the ceiling a GEMM of the same instruction can approach.
@@ -13,7 +13,10 @@ typedef __attribute__((ext_vector_type(16))) float burn_f32x16;
 typedef __attribute__((ext_vector_type(4))) double burn_f64x4;
 typedef __attribute__((ext_vector_type(8))) _Float16 burn_f16x8;
 
-constexpr int kBurnChains = 16;  // independent accumulators per wave (256 AGPRs for the FP16/FP32 forms)
+// Independent accumulators per wave: 16 of 16 registers (FP16, FP32) or 32 of
+// 8 (FP64), 256 accumulator registers either way, as in the GEMMs.
+template <int KIND>
+constexpr int burn_chains() { return KIND == 2 ? 32 : 16; }
 
 // Flops of one MFMA of each kind.
 static double burn_flops(int kind) {
@@ -38,49 +41,53 @@ __global__ __launch_bounds__(256, 1) void mfma_burn(int64_t iters, double* __res
       a[e] = (_Float16)(x + 0.125f * e);
       b[e] = (_Float16)(y - 0.0625f * e);
     }
-    burn_f32x16 acc[kBurnChains];
+    burn_f32x16 acc[burn_chains<KIND>()];
 #pragma unroll
-    for (int c = 0; c < kBurnChains; ++c)
+    for (int c = 0; c < burn_chains<KIND>(); ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
     for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
-      for (int c = 0; c < kBurnChains; ++c)
+      for (int c = 0; c < burn_chains<KIND>(); ++c)
         acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[c], 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < kBurnChains; ++c)
+    for (int c = 0; c < burn_chains<KIND>(); ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) out += acc[c][r];
   } else if constexpr (KIND == 1) {
-    burn_f32x16 acc[kBurnChains];
+    burn_f32x16 acc[burn_chains<KIND>()];
 #pragma unroll
-    for (int c = 0; c < kBurnChains; ++c)
+    for (int c = 0; c < burn_chains<KIND>(); ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
     for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
-      for (int c = 0; c < kBurnChains; ++c)
+      for (int c = 0; c < burn_chains<KIND>(); ++c)
         acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc[c], 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < kBurnChains; ++c)
+    for (int c = 0; c < burn_chains<KIND>(); ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) out += acc[c][r];
   } else {
-    burn_f64x4 acc[kBurnChains];
-#pragma unroll
-    for (int c = 0; c < kBurnChains; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[c][r] = 0.0;
+    constexpr int NC = burn_chains<KIND>();
     const double xd = x, yd = y;
-    for (int64_t it = 0; it < iters; ++it) {
+    const burn_f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+    // the first round from a zero accumulator, so that every value the loop
+    // carries comes out of an MFMA (with zero-initialised accumulators the
+    // compiler carried them in VGPRs and copied them to AGPRs and back in
+    // every round)
+    burn_f64x4 acc[NC];
 #pragma unroll
-      for (int c = 0; c < kBurnChains; ++c)
+    for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xd, yd, zero, 0, 0, 0);
+    for (int64_t it = 1; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xd, yd, acc[c], 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < kBurnChains; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) out += acc[c][r];
   }
@@ -116,7 +123,8 @@ mp_status mp_mfma_sustained(int32_t kind, int64_t iters, double* sink, size_t si
     default: hipLaunchKernelGGL(mfma_burn<2>, dim3(cus), dim3(256), 0, s, iters, sink); break;
   }
   MP_HIP_LAUNCH_CHECK("mp_mfma_sustained launch");
-  if (flops) *flops = (double)cus * 4 * kBurnChains * (double)iters * burn_flops(kind);
+  const int chains = kind == 2 ? burn_chains<2>() : burn_chains<0>();
+  if (flops) *flops = (double)cus * 4 * chains * (double)iters * burn_flops(kind);
   return MP_OK;
 }
 

@@ -1,7 +1,7 @@
 """The matrix-core rate probe (mp_mfma_sustained): it runs for every kind,
 reports the launch's flop count (4 waves per compute unit, 16 MFMA chains
-per wave, iters rounds), leaves finite values in its sink, and rejects
-invalid arguments."""
+per wave for FP16 and FP32, 32 for FP64, iters rounds), leaves finite values
+in its sink, and rejects invalid arguments."""
 import numpy as np
 import pytest
 
@@ -17,15 +17,16 @@ def _gpu():
     yield
 
 
-@pytest.mark.parametrize("kind,flops_per_mfma", [(0, 2 * 32 * 32 * 16), (1, 2 * 32 * 32 * 2),
-                                                 (2, 2 * 16 * 16 * 4)])
-def test_probe_runs_and_counts_flops(kind, flops_per_mfma):
+@pytest.mark.parametrize("kind,flops_per_round", [(0, 16 * 2 * 32 * 32 * 16),
+                                                   (1, 16 * 2 * 32 * 32 * 2),
+                                                   (2, 32 * 2 * 16 * 16 * 4)])
+def test_probe_runs_and_counts_flops(kind, flops_per_round):
     import paper_2503_12749_amd as mp
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     sink = torch.full((cus * 256,), float("nan"), dtype=torch.float64, device="cuda:0")
     flops = mp.mp_mfma_sustained(kind, 7, sink)
     torch.cuda.synchronize()
-    assert flops == cus * 4 * 16 * 7 * flops_per_mfma
+    assert flops == cus * 4 * 7 * flops_per_round  # 4 waves per CU, 7 rounds
     v = sink.cpu().numpy()
     assert np.all(np.isfinite(v)) and np.all(v > 0)
 
