@@ -202,6 +202,19 @@ def criterion_job(mp, torch, w, prec, E_need, chunk, ns, fused):
     return secs, E, float(sig.max() / P.max())
 
 
+def sustained_fp16_tflops(mp, torch):
+    """TFLOP/s of the library's FP16 matrix-core probe (back-to-back
+    v_mfma_f32_32x32x16_f16, no memory traffic) over about 50 ms."""
+    sink = torch.empty(512 * 256, dtype=torch.float64, device="cuda:0")
+    mp.mp_mfma_sustained(0, 1000, sink)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    flops = mp.mp_mfma_sustained(0, 200000, sink)
+    b.record()
+    torch.cuda.synchronize()
+    return flops / (a.elapsed_time(b) * 1e-3) / 1e12
+
+
 def run_m8000(args, mp, torch, synth):
     """The headline workload (see the module docstring)."""
     t = time.perf_counter()
@@ -289,6 +302,12 @@ def run_m8000(args, mp, torch, synth):
     if args.prec in PRODUCTS:
         roof["executed_mfma_frac"] = round(PRODUCTS[args.prec] * achieved / peak, 4)
         roof["mfma_products"] = PRODUCTS[args.prec]
+        if args.prec != "split_bf16":
+            # the FP16 matrix cores' sustained rate on this machine with no memory
+            # traffic (about one GEMM's duration), as context for the fraction
+            sust = sustained_fp16_tflops(mp, torch)
+            roof["sustained_fp16_mfma_tflops_measured"] = round(sust, 1)
+            roof["executed_frac_of_sustained"] = round(PRODUCTS[args.prec] * achieved / sust, 4)
     out = {
         "metric": METRIC,
         "value": main_r["value"],
