@@ -534,7 +534,7 @@ def _batched_leg(mp, torch, nets, chunk, label, prec="split_fp16"):
     plan.close()
     log(f"[bench] {label}: tuned plan {plan_s:.4f} s, {info}")
     wide_s, same = None, True
-    if prec != "split1_fp16":
+    if not prec.startswith("split1"):  # the one-sided forms have one tile width
         # the same order and prefetch with every network on the 128-sample tile
         with open(cache) as f:
             (key, entry), = json.load(f).items()
@@ -577,8 +577,8 @@ def run_batched(args, mp, torch, synth):
     networks run one after another through the fused CountsPipeline.  A
     second leg runs the same networks at E = 4096 (4 sub-ensembles of 1024),
     where a single network offers the 256 compute units few GEMM tiles; a
-    third runs the E = 2e5 job in the one-sided split FP16 precision (T as one
-    FP16 value, two products)."""
+    third runs the E = 2e5 job in the default mixed precision, the T-split
+    one-sided FP16 (T hi/lo, samples one FP16 value, two products)."""
     E, n_sub, chunk = 200_000, 20, 100_000
     Ms = synth.BATCHED_SIZES
     log("[bench] batched: creating the plans (autotuned order, prefetch, tiles)")
@@ -586,7 +586,7 @@ def run_batched(args, mp, torch, synth):
     small = _batched_leg(mp, torch, synth.batched_networks(E=4096, n_sub=4), 4096,
                          "batched E=4096")
     one_sided = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
-                             "batched one-sided split", prec="split1_fp16")
+                             "batched one-sided split", prec="split1t_fp16")
     one_sided["samples_M2_per_s"] = sum(E * M ** 2 for M in Ms) / one_sided["plan_s"]
     plan_s = full["plan_s"]
     work = sum(E * M ** 2 for M in Ms)
