@@ -571,34 +571,35 @@ def _batched_leg(mp, torch, nets, chunk, label, prec="split_fp16"):
 
 def run_batched(args, mp, torch, synth):
     """16 networks (4 each of M = 500, 1000, 2000, 4000), t ~ U[0.85, 0.99],
-    r = 1, E = 2e5 each (20 sub-ensembles of 1e4), split-FP16: one plan (a
-    captured hipGraph with one persistent grouped GEMM launch with the
+    r = 1, E = 2e5 each (20 sub-ensembles of 1e4): one plan (a captured
+    hipGraph with one persistent grouped GEMM launch with the
     occupation-fused epilogue per pass over chunks of 1e5) against the same
-    networks run one after another through the fused CountsPipeline.  A
-    second leg runs the same networks at E = 4096 (4 sub-ensembles of 1024),
-    where a single network offers the 256 compute units few GEMM tiles; a
-    third runs the E = 2e5 job in the default mixed precision, the T-split
-    one-sided FP16 (T hi/lo, samples one FP16 value, two products)."""
+    networks run one after another through the fused CountsPipeline.  The
+    line of record runs the default mixed precision (T-split FP16: T hi/lo,
+    samples one FP16 value, two products); a second leg runs the
+    three-product split FP16, whose plans also choose a tile width per size
+    class, and a third the same at E = 4096 (4 sub-ensembles of 1024), where
+    a single network offers the 256 compute units few GEMM tiles."""
     E, n_sub, chunk = 200_000, 20, 100_000
     Ms = synth.BATCHED_SIZES
-    log("[bench] batched: creating the plans (autotuned order, prefetch, tiles)")
-    full = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk, "batched")
-    small = _batched_leg(mp, torch, synth.batched_networks(E=4096, n_sub=4), 4096,
-                         "batched E=4096")
-    one_sided = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
-                             "batched one-sided split", prec="split1t_fp16")
-    one_sided["samples_M2_per_s"] = sum(E * M ** 2 for M in Ms) / one_sided["plan_s"]
-    plan_s = full["plan_s"]
     work = sum(E * M ** 2 for M in Ms)
-    flops = 8.0 * work
+    log("[bench] batched: creating the plans (autotuned order, prefetch, tiles)")
+    main = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
+                        "batched T-split", prec="split1t_fp16")
+    three = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
+                         "batched three-product split")
+    three["samples_M2_per_s"] = work / three["plan_s"]
+    small = _batched_leg(mp, torch, synth.batched_networks(E=4096, n_sub=4), 4096,
+                         "batched three-product E=4096")
     small["samples_M2_per_s"] = sum(4096 * M ** 2 for M in Ms) / small["plan_s"]
+    plan_s = main["plan_s"]
     return _envelope(
         "samples·M²/s over 16 uneven networks in one plan, split-FP16", work / plan_s,
         "samples·M²/s", 1e3 * plan_s,
         "16 networks: 4 x M in {500, 1000, 2000, 4000}, t ~ U[0.85, 0.99], r = 1, E = 2e5 "
-        "each in chunks of 1e5, total counts", "split-fp16 (fp32 acc)",
-        **full, algorithmic_tflops_whole_job=flops / plan_s / 1e12, small_ensemble_e4096=small,
-        one_sided_split_fp16=one_sided)
+        "each in chunks of 1e5, total counts", "split-fp16 x fp16 (fp32 acc)",
+        **main, algorithmic_tflops_whole_job=8.0 * work / plan_s / 1e12,
+        three_product_split_fp16=three, three_product_split_fp16_e4096=small)
 
 
 def run_surrogate(args, mp, torch, synth):
