@@ -1079,8 +1079,9 @@ def main():
     ap.add_argument("--sweep-E", type=int, default=10000, help="surrogate: samples per sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sample-sharded "
-              f"multi-GPU path is a design, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library "
+              f"computes on one device; sharding the samples over GPUs is not implemented.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
