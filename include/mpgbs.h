@@ -469,8 +469,13 @@ mp_status mp_mfma_sustained(int32_t kind, int64_t iters, double* sink, size_t si
 
 /* ---------------------------------------------------------------- batching */
 
-/* One network of a batched plan: total counts of all M outputs on the window
- * [m_lo, m_lo + K), E samples in n_sub sub-ensembles, noise stream `net`. */
+/* One network of a batched plan: E samples in n_sub sub-ensembles, noise
+ * stream `net`, and the distributions to estimate.  d = 0: the total count
+ * of all M outputs on the window [m_lo, m_lo + K).  d >= 1: the outputs
+ * grouped by bin_of_mode with `mode`, one window per distribution in m_lo_b
+ * and K_b (d entries, d + 1 for MP_MARGINALS_AND_TOTAL), exactly as for
+ * mp_propagate_counts (joint grids of up to 4 bins); m_lo and K unused.  The
+ * host arrays are read during mp_plan_create only. */
 typedef struct {
   int32_t M;
   const double* T; /* device, complex M x M row-major interleaved (as mp_propagate) */
@@ -481,6 +486,11 @@ typedef struct {
   int32_t n_sub;
   int32_t m_lo;
   int32_t K;
+  int32_t d;                  /* 0: total counts on (m_lo, K); else bins, as above */
+  mp_bin_mode mode;
+  const int32_t* bin_of_mode; /* host int32[M], -1 = uncounted (d >= 1) */
+  const int32_t* m_lo_b;      /* host int32, one per distribution (d >= 1) */
+  const int32_t* K_b;         /* host int32, one per distribution (d >= 1) */
 } mp_net_desc;
 
 /*
@@ -510,7 +520,9 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets,
  * stream waits for the replay.  Results are overwritten by each replay. */
 mp_status mp_plan_launch(void* plan, void* stream);
 
-/* Device pointers (owned by the plan) to network i's P_re, P_im, sigma[K]. */
+/* Device pointers (owned by the plan) to network i's P_re, P_im and sigma:
+ * K entries for d = 0, mp_acc_entries(d, mode, K_b) otherwise (the layout of
+ * mp_counts_finalize). */
 mp_status mp_plan_result(void* plan, int32_t i, const double** P_re, const double** P_im,
                          const double** sigma);
 

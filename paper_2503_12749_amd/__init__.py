@@ -460,8 +460,11 @@ def _hip_runtime():
 class Plan:
     """Batched plan over many networks (mp_plan_create / mp_plan_launch):
     one captured hipGraph per plan, one persistent grouped GEMM launch with
-    the occupation-fused epilogue per pass (split precisions).  `nets` is a list of dicts with keys T (complex numpy M x M), r,
-    seed, net, E, n_sub, window=(m_lo, K)."""
+    the occupation-fused epilogue per pass (split precisions).  `nets` is a
+    list of dicts with keys T (complex numpy M x M), r, seed, net, E, n_sub
+    and either window=(m_lo, K) (the total count of all modes) or
+    bin_of_mode, d, mode and windows=[(m_lo, K), ...] (one per distribution,
+    as for CountsPipeline)."""
 
     def __init__(self, nets, *, prec="split_fp16", est="matrix_p", chunk=None, tune_cache=None,
                  device="cuda:0"):
@@ -469,6 +472,7 @@ class Plan:
         self.torch = torch
         dev = torch.device(device)
         keep = []
+        self.K = []  # result entries per network
         descs = (_lib.NetDesc * len(nets))()
         for i, n in enumerate(nets):
             T = np.ascontiguousarray(n["T"], dtype=np.complex128)
@@ -476,9 +480,26 @@ class Plan:
             Td = torch.from_numpy(T.view(np.float64).reshape(-1).copy()).to(dev)
             rd = torch.from_numpy(np.asarray(n["r"], dtype=np.float64).copy()).to(dev)
             keep += [Td, rd]
-            m_lo, K = n["window"]
-            descs[i] = _lib.NetDesc(M, Td.data_ptr(), rd.data_ptr(), int(n["seed"]), int(n["net"]),
-                                    int(n["E"]), int(n["n_sub"]), int(m_lo), int(K))
+            if "windows" in n:  # binned distributions
+                d = int(n["d"])
+                bins = i32_array(n["bin_of_mode"])
+                mlo = i32_array([w[0] for w in n["windows"]])
+                Kb = i32_array([w[1] for w in n["windows"]])
+                keep += [bins, mlo, Kb]
+                descs[i] = _lib.NetDesc(M, Td.data_ptr(), rd.data_ptr(), int(n["seed"]),
+                                        int(n["net"]), int(n["E"]), int(n["n_sub"]), 0, 0, d,
+                                        _mode(n.get("mode", "joint")),
+                                        ctypes.cast(bins, ctypes.c_void_p),
+                                        ctypes.cast(mlo, ctypes.c_void_p),
+                                        ctypes.cast(Kb, ctypes.c_void_p))
+                self.K.append(mp_acc_entries(d, n.get("mode", "joint"),
+                                             [w[1] for w in n["windows"]]))
+            else:
+                m_lo, K = n["window"]
+                descs[i] = _lib.NetDesc(M, Td.data_ptr(), rd.data_ptr(), int(n["seed"]),
+                                        int(n["net"]), int(n["E"]), int(n["n_sub"]), int(m_lo),
+                                        int(K), 0, 0, None, None, None)
+                self.K.append(int(K))
         chunk = max(int(n["E"]) for n in nets) if chunk is None else int(chunk)
         torch.cuda.synchronize()
         h = ctypes.c_void_p()
@@ -486,7 +507,6 @@ class Plan:
         _lib.check(_lib.load().mp_plan_create(ctypes.byref(h), len(nets), descs, _prec(prec),
                                               _est(est), chunk, path))
         self.handle = h
-        self.K = [int(n["window"][1]) for n in nets]
         del keep
 
     def launch(self, stream=None):

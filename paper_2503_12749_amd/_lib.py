@@ -44,7 +44,9 @@ class MlpShape(ctypes.Structure):
 class NetDesc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("T", ctypes.c_void_p), ("r", ctypes.c_void_p),
                 ("seed", ctypes.c_uint64), ("net", ctypes.c_uint32), ("E", ctypes.c_int64),
-                ("n_sub", ctypes.c_int32), ("m_lo", ctypes.c_int32), ("K", ctypes.c_int32)]
+                ("n_sub", ctypes.c_int32), ("m_lo", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("mode", ctypes.c_int), ("bin_of_mode", ctypes.c_void_p),
+                ("m_lo_b", ctypes.c_void_p), ("K_b", ctypes.c_void_p)]
 
 
 class MPError(RuntimeError):

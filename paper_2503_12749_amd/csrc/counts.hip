@@ -463,14 +463,20 @@ __global__ __launch_bounds__(256) void joint2_accumulate(Joint2Params p, const d
         if (i < nsmp) {
           const double* r = rec + (base + i - p.e0) * 6;
           const double cterm = term == 0 ? r[4] : r[5];
+          // the product's log-magnitude at the band centre (c, or c + 2 Re n_1
+          // + 2 Re n_2 for the second term) is shared evenly between the two
+          // factors, so neither overflows while the other underflows in FP32
+          const double share = 0.5 * (cterm + (term == 0 ? 0.0 : 2.0 * (r[0] + r[2])));
           if (which == 0) {
             const int kk = t1 * kJT + q;
             if (kk < K1 && cterm > -INFINITY)
-              factor<F64>(r[0], r[1], cterm, kk, K1, p.m_lo[0], sign, fr, fi);
+              factor<F64>(r[0], r[1], share - (term == 0 ? 0.0 : 2.0 * r[0]), kk, K1, p.m_lo[0],
+                          sign, fr, fi);
           } else {
             const int kk = t2 * kJT + q;
             if (kk < K2 && cterm > -INFINITY)
-              factor<F64>(r[2], r[3], 0.0, kk, K2, p.m_lo[1], sign, fr, fi);
+              factor<F64>(r[2], r[3], share - (term == 0 ? 0.0 : 2.0 * r[2]), kk, K2, p.m_lo[1],
+                          sign, fr, fi);
           }
         }
         double(*dst)[kJT][2] = which == 0 ? f1 : f2;
@@ -883,12 +889,30 @@ mp_status fused_out_setup(int32_t M, int64_t E, int32_t d, const int32_t* bin_of
 }
 
 // Counts from the partials an occupation-fused GEMM left at the start of ws
-// (laid out by fused_out_setup with the same arguments).
+// (laid out by fused_out_setup with the same arguments).  The fused GEMM runs
+// in FP32 or a split precision, so the joint paths take their FP32 factor
+// tables.
 mp_status counts_from_partials_launch(int32_t M, int64_t E, const double* n, mp_estimator est,
                                       int32_t d, const int32_t* bin_of_mode, mp_bin_mode mode,
                                       const int32_t* m_lo, const int32_t* K, int32_t n_sub,
                                       int64_t ns, int64_t e0, double* acc, void* ws,
                                       size_t ws_bytes, hipStream_t stream) {
+  if (mode == MP_JOINT && d >= 2) {
+    // the joint paths read the bin sums from the partials; their own
+    // workspace follows them
+    FusedOut fo{};
+    const mp_status sr = fused_runs(M, bin_of_mode, fo);
+    if (sr != MP_OK) return sr;
+    const size_t pb = joint_part_bytes(fo, E);
+    MP_CHECK_ARG(ws && ws_bytes >= pb, MP_ERR_WORKSPACE,
+                 "mp_propagate_counts: workspace of %zu bytes needed, %zu given", pb, ws_bytes);
+    void* jws = (char*)ws + pb;
+    const size_t jbytes = ws_bytes - pb;
+    return d == 2 ? joint2_launch(M, E, nullptr, n, MP_FP32, est, bin_of_mode, m_lo, K, n_sub, ns,
+                                  e0, acc, jws, jbytes, stream, (const float*)ws)
+                  : jointd_launch(M, E, nullptr, n, MP_FP32, est, d, bin_of_mode, m_lo, K, n_sub,
+                                  ns, e0, acc, jws, jbytes, stream, (const float*)ws);
+  }
   CountsParams p{};
   int64_t blocks = 0;
   const mp_status st = setup_counts(p, "mp_propagate_counts", M, E, d, bin_of_mode, mode, m_lo, K,
@@ -921,16 +945,6 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
   if (st != MP_OK) return st;
   if (fo.n_runs > 0 && (st = gemm_fused_launch(M, E, packed, prec, ab, fo, stream)) != MP_OK)
     return st;
-  if (mode == MP_JOINT && d >= 2) {
-    // the joint paths read the bin sums from the partials; their own workspace follows them
-    const size_t pb = joint_part_bytes(fo, E);
-    void* jws = (char*)ws + pb;
-    const size_t jbytes = ws_bytes - pb;
-    return d == 2 ? joint2_launch(M, E, nullptr, n, prec, est, bin_of_mode, m_lo, K, n_sub, ns, e0,
-                                  acc, jws, jbytes, stream, fo.part)
-                  : jointd_launch(M, E, nullptr, n, prec, est, d, bin_of_mode, m_lo, K, n_sub, ns,
-                                  e0, acc, jws, jbytes, stream, fo.part);
-  }
   return counts_from_partials_launch(M, E, n, est, d, bin_of_mode, mode, m_lo, K, n_sub, ns, e0,
                                      acc, ws, ws_bytes, stream);
 }

@@ -176,6 +176,27 @@ static void validation() {
   nd.K = 0;
   EXPECT(mp_plan_create(&plan, 1, &nd, MP_SPLIT_FP16, MP_MATRIX_P, 1000, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_create(&plan, 0, &nd, MP_SPLIT_FP16, MP_MATRIX_P, 1000, nullptr) == MP_ERR_ARG);
+  // binned networks: bins in range, windows per distribution, supported modes
+  std::vector<int32_t> bins64(64, 0);
+  bins64[10] = 1;
+  bins64[20] = 2;  // outside [-1, 2) for d = 2
+  const int32_t mlo3[3] = {0, 0, 0}, k3[3] = {64, 64, 128};
+  nd.K = 64;
+  nd.d = 2;
+  nd.mode = MP_MARGINALS_AND_TOTAL;
+  nd.bin_of_mode = bins64.data();
+  nd.m_lo_b = mlo3;
+  nd.K_b = k3;
+  EXPECT(mp_plan_create(&plan, 1, &nd, MP_SPLIT_FP16, MP_MATRIX_P, 1000, nullptr) == MP_ERR_ARG);
+  EXPECT(std::strstr(mp_last_error(), "bin_of_mode[20]") != nullptr);
+  bins64[20] = 1;
+  nd.bin_of_mode = nullptr;
+  EXPECT(mp_plan_create(&plan, 1, &nd, MP_SPLIT_FP16, MP_MATRIX_P, 1000, nullptr) == MP_ERR_ARG);
+  nd.bin_of_mode = bins64.data();
+  nd.d = 5;
+  nd.mode = MP_JOINT;  // joint grids of more than 4 bins are not supported
+  EXPECT(mp_plan_create(&plan, 1, &nd, MP_SPLIT_FP16, MP_MATRIX_P, 1000, nullptr) == MP_ERR_ARG);
+  nd.d = 0;
   EXPECT(mp_plan_launch(nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_info(nullptr, nullptr, nullptr, nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_tile(nullptr, 0, nullptr, nullptr) == MP_ERR_ARG);

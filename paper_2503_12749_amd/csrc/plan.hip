@@ -66,6 +66,7 @@ mp_status binned_counts_launch(int32_t M, int64_t E, const void* C, const double
                                const int32_t* bin_of_mode, mp_bin_mode mode, const int32_t* m_lo,
                                const int32_t* K, int32_t n_sub, int64_t ns, int64_t e0,
                                double* acc, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t finalize_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub);
 mp_status counts_finalize_launch(int32_t d, mp_bin_mode mode, const int32_t* K, int32_t n_sub,
                                  int64_t ns, const double* acc, double* P_re, double* P_im,
                                  double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -93,7 +94,16 @@ struct PlanNet {
   void* packed = nullptr;
   void* ws_counts = nullptr;  // FP64: counts partials; else fused partials + counts partials
   size_t ws_counts_bytes = 0;
+  // distributions: d bins by `bins` with `mode`, one window per
+  // distribution (the total count of all modes on one window when the
+  // descriptor's d is 0)
   std::vector<int32_t> bins;
+  int32_t nb = 1;
+  mp_bin_mode mode = MP_JOINT;
+  std::vector<int32_t> m_lo, K;
+  int64_t entries = 0;     // accumulator / result entries per sub-ensemble
+  void* ws_fin = nullptr;  // inverse DFT workspace (joint grids of d >= 2)
+  size_t ws_fin_bytes = 0;
   int nj = 4;  // grouped tile: 128 modes x 32 nj samples (nj 4 or 2)
 };
 
@@ -366,7 +376,7 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
         PlanNet& n = p->nets[i];
         hipStream_t s = p->side[i % kBranches];
         if (pass == 0) {
-          const int64_t cnt = (int64_t)n.d.n_sub * n.d.K * 2;
+          const int64_t cnt = (int64_t)n.d.n_sub * n.entries * 2;
           hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                              n.acc, cnt);
         }
@@ -390,9 +400,9 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
         PlanNet& n = p->nets[i];
         const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
         if (e <= 0) continue;
-        const int32_t m_lo = n.d.m_lo, K = n.d.K;
-        if ((st = counts_from_partials_launch(n.d.M, e, n.n, p->est, 1, n.bins.data(), MP_JOINT,
-                                              &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
+        if ((st = counts_from_partials_launch(n.d.M, e, n.n, p->est, n.nb, n.bins.data(), n.mode,
+                                              n.m_lo.data(), n.K.data(), n.d.n_sub,
+                                              n.d.E / n.d.n_sub, g0, n.acc,
                                               n.ws_counts, n.ws_counts_bytes,
                                               p->side[i % kBranches])) != MP_OK)
           return st;
@@ -406,10 +416,10 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
       hipStream_t s = gemm_only ? p->stream : p->side[i % kBranches];
       const int64_t g0 = (int64_t)pass * n.chunk, e = std::min<int64_t>(n.chunk, n.d.E - g0);
       if (e <= 0) continue;
-      const int32_t m_lo = n.d.m_lo, K = n.d.K;
       if (fused(p->prec)) {  // FP32: the fused GEMM and its counts
-        if ((st = propagate_counts_launch(n.d.M, e, p->prec, p->est, n.ab, n.n, n.packed, 1,
-                                          n.bins.data(), MP_JOINT, &m_lo, &K, n.d.n_sub,
+        if ((st = propagate_counts_launch(n.d.M, e, p->prec, p->est, n.ab, n.n, n.packed, n.nb,
+                                          n.bins.data(), n.mode, n.m_lo.data(), n.K.data(),
+                                          n.d.n_sub,
                                           n.d.E / n.d.n_sub, g0, n.acc, n.ws_counts,
                                           n.ws_counts_bytes, s)) != MP_OK)
           return st;
@@ -417,8 +427,9 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
       }
       if ((st = gemm_packed_launch(n.d.M, e, n.packed, p->prec, n.ab, n.C, s)) != MP_OK) return st;
       if (gemm_only) continue;
-      if ((st = binned_counts_launch(n.d.M, e, n.C, n.n, p->prec, p->est, 1, n.bins.data(),
-                                     MP_JOINT, &m_lo, &K, n.d.n_sub, n.d.E / n.d.n_sub, g0, n.acc,
+      if ((st = binned_counts_launch(n.d.M, e, n.C, n.n, p->prec, p->est, n.nb, n.bins.data(),
+                                     n.mode, n.m_lo.data(), n.K.data(), n.d.n_sub,
+                                     n.d.E / n.d.n_sub, g0, n.acc,
                                      n.ws_counts, n.ws_counts_bytes, s)) != MP_OK)
         return st;
     }
@@ -426,9 +437,9 @@ static mp_status enqueue_pass(Plan* p, bool gemm_only = false) {
   if (gemm_only) return MP_OK;
   for (size_t i = 0; i < p->nets.size(); ++i) {
     PlanNet& n = p->nets[i];
-    const int32_t K = n.d.K;
-    if ((st = counts_finalize_launch(1, MP_JOINT, &K, n.d.n_sub, n.d.E / n.d.n_sub, n.acc, n.P_re,
-                                     n.P_im, n.sigma, nullptr, 0, p->side[i % kBranches])) != MP_OK)
+    if ((st = counts_finalize_launch(n.nb, n.mode, n.K.data(), n.d.n_sub, n.d.E / n.d.n_sub, n.acc,
+                                     n.P_re, n.P_im, n.sigma, n.ws_fin, n.ws_fin_bytes,
+                                     p->side[i % kBranches])) != MP_OK)
       return st;
   }
   return branch_join(p);
@@ -458,8 +469,25 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     MP_CHECK_ARG(d.E <= chunk || d.E % chunk == 0, MP_ERR_SHAPE,
                  "mp_plan_create: network %d: E = %lld must be <= chunk or a multiple of it", i,
                  (long long)d.E);
-    MP_CHECK_ARG(d.K >= 1 && d.K <= 65536 && d.m_lo >= 0, MP_ERR_ARG,
-                 "mp_plan_create: network %d: window K in [1, 65536] and m_lo >= 0 required", i);
+    if (d.d == 0) {
+      MP_CHECK_ARG(d.K >= 1 && d.K <= 65536 && d.m_lo >= 0, MP_ERR_ARG,
+                   "mp_plan_create: network %d: window K in [1, 65536] and m_lo >= 0 required", i);
+    } else {
+      MP_CHECK_ARG(d.d >= 1 && d.d <= MP_MAX_BINS && d.bin_of_mode && d.m_lo_b && d.K_b,
+                   MP_ERR_ARG,
+                   "mp_plan_create: network %d: d in [1, %d] with bin_of_mode, m_lo_b, K_b", i,
+                   MP_MAX_BINS);
+      MP_CHECK_ARG(mp_acc_entries(d.d, d.mode, d.K_b) > 0, MP_ERR_ARG,
+                   "mp_plan_create: network %d: unsupported bin mode or window sizes", i);
+      for (int j = 0; j < d.M; ++j)
+        MP_CHECK_ARG(d.bin_of_mode[j] >= -1 && d.bin_of_mode[j] < d.d, MP_ERR_ARG,
+                     "mp_plan_create: network %d: bin_of_mode[%d] = %d outside [-1, %d)", i, j,
+                     d.bin_of_mode[j], d.d);
+      const int nd = d.mode == MP_JOINT ? d.d : (d.mode == MP_MARGINALS ? d.d : d.d + 1);
+      for (int q = 0; q < nd; ++q)
+        MP_CHECK_ARG(d.m_lo_b[q] >= 0, MP_ERR_ARG, "mp_plan_create: network %d: m_lo_b[%d] < 0",
+                     i, q);
+    }
   }
   Plan* p = new Plan();
   p->prec = prec;
@@ -492,30 +520,51 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     n.d = nets[i];
     n.ldm = ld_modes(n.d.M);
     n.chunk = std::min<int64_t>(chunk, n.d.E);
-    n.bins.assign(n.d.M, 0);
+    if (n.d.d == 0) {  // total count of all modes on one window
+      n.bins.assign(n.d.M, 0);
+      n.nb = 1;
+      n.mode = MP_JOINT;
+      n.m_lo.assign(1, n.d.m_lo);
+      n.K.assign(1, n.d.K);
+    } else {
+      n.bins.assign(n.d.bin_of_mode, n.d.bin_of_mode + n.d.M);
+      n.nb = n.d.d;
+      n.mode = n.d.mode;
+      const int nd = n.mode == MP_MARGINALS_AND_TOTAL ? n.nb + 1 : n.nb;
+      n.m_lo.assign(n.d.m_lo_b, n.d.m_lo_b + nd);
+      n.K.assign(n.d.K_b, n.d.K_b + nd);
+    }
+    n.entries = mp_acc_entries(n.nb, n.mode, n.K.data());
+    // the descriptor's pointers need not outlive creation
+    n.d.bin_of_mode = nullptr;
+    n.d.m_lo_b = nullptr;
+    n.d.K_b = nullptr;
     max_e = std::max<int64_t>(max_e, n.d.E);
     n.r = (double*)plan_alloc(p, (size_t)n.d.M * 8);
     n.n = (double*)plan_alloc(p, (size_t)n.chunk * 8);
-    n.acc = (double*)plan_alloc(p, (size_t)n.d.n_sub * n.d.K * 16);
-    n.P_re = (double*)plan_alloc(p, (size_t)n.d.K * 8);
-    n.P_im = (double*)plan_alloc(p, (size_t)n.d.K * 8);
-    n.sigma = (double*)plan_alloc(p, (size_t)n.d.K * 8);
+    n.acc = (double*)plan_alloc(p, (size_t)n.d.n_sub * n.entries * 16);
+    n.P_re = (double*)plan_alloc(p, (size_t)n.entries * 8);
+    n.P_im = (double*)plan_alloc(p, (size_t)n.entries * 8);
+    n.sigma = (double*)plan_alloc(p, (size_t)n.entries * 8);
+    n.ws_fin_bytes = finalize_workspace(n.nb, n.mode, n.K.data(), n.d.n_sub);
+    if (n.ws_fin_bytes) n.ws_fin = plan_alloc(p, n.ws_fin_bytes);
     n.ab = plan_alloc(p, (size_t)n.ldm * 2 * n.chunk * (prec == MP_FP64 ? 8 : 4));
     if (!fused(prec)) n.C = plan_alloc(p, (size_t)2 * n.ldm * 2 * n.chunk * eb);
     n.packed = plan_alloc(p, propagate_workspace(n.d.M, prec));
-    const int32_t K = n.d.K;
     const int64_t ns = n.d.E / n.d.n_sub;
     size_t wsb = 0;
     for (int64_t g0 = 0; g0 < n.d.E; g0 += n.chunk) {
       const int64_t e = std::min<int64_t>(n.chunk, n.d.E - g0);
-      wsb = std::max(wsb, fused(prec) ? propagate_counts_workspace(n.d.M, e, 1, n.bins.data(),
-                                                                   MP_JOINT, &K, n.d.n_sub, ns, g0)
-                                      : binned_workspace(1, MP_JOINT, &K, e, n.d.n_sub, ns, g0));
+      wsb = std::max(wsb, fused(prec) ? propagate_counts_workspace(n.d.M, e, n.nb, n.bins.data(),
+                                                                   n.mode, n.K.data(), n.d.n_sub,
+                                                                   ns, g0)
+                                      : binned_workspace(n.nb, n.mode, n.K.data(), e, n.d.n_sub,
+                                                         ns, g0));
     }
     n.ws_counts_bytes = wsb;
     n.ws_counts = plan_alloc(p, wsb);
     if (!n.r || !n.n || !n.acc || !n.P_re || !n.P_im || !n.sigma || !n.ab ||
-        (!fused(prec) && !n.C) || !n.packed || !n.ws_counts) {
+        (!fused(prec) && !n.C) || !n.packed || !n.ws_counts || (n.ws_fin_bytes && !n.ws_fin)) {
       plan_free(p);
       set_error("mp_plan_create: device allocation failed (network %d)", i);
       return MP_ERR_HIP;
@@ -547,8 +596,8 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, nullptr, n.ldm, cols, sc,
                         FusedOut{}};
         if (e > 0) {
-          const int32_t m_lo = n.d.m_lo, K = n.d.K;
-          const mp_status st = fused_out_setup(n.d.M, e, 1, n.bins.data(), MP_JOINT, &m_lo, &K,
+          const mp_status st = fused_out_setup(n.d.M, e, n.nb, n.bins.data(), n.mode,
+                                               n.m_lo.data(), n.K.data(),
                                                n.d.n_sub, n.d.E / n.d.n_sub, (int64_t)pass * n.chunk,
                                                est, n.ws_counts, n.ws_counts_bytes, g[i].fo);
           if (st != MP_OK) {

@@ -170,3 +170,41 @@ def test_joint2_long_windows_sum_to_marginals():
         scale = np.abs(ref).max()
         tol = 1e-10 * np.maximum(np.abs(ref), 1e-4 * scale) + 1e-13 * scale
         assert np.all(np.abs(got - ref) <= tol), np.abs(got - ref).max()
+
+
+@pytest.mark.parametrize("prec,fused", [("fp32", False), ("fp32", True), ("split_bf16", True),
+                                        ("split1t_fp16", True)])
+def test_joint2_large_bin_occupations_reduced_precision(prec, fused):
+    """Two-bin joint grid of a network whose bins hold about 50 photons each
+    (M = 90, r = 1, t = 0.93, one mode uncounted): at the centre of its band
+    the parity partner's factor of one bin reaches e^{2 Re n_b}, up to about
+    e^{195}, and that of the other bin e^{2 Re n_b + c2}, down to about
+    e^{-240}.  Their product is moderate, so it is representable only if its
+    magnitude is shared between the two factors; the FP32 and split paths
+    must then stay finite and far inside sigma_T of the FP64 path on the same
+    noise (2 % of sigma_T plus 1e-6 of the peak, as for the joints above).
+    Sixteen sub-ensembles, so that no cell's sigma_T estimate is near zero
+    by chance."""
+    import paper_2503_12749_amd as mp
+    M, t = 90, 0.928
+    T = synth.transmission(M, t, 717)
+    r = np.ones(M)
+    bins = np.minimum(np.arange(M) * 2 // M, 1).astype(np.int32)
+    bins[M // 3] = -1
+    wins = [(0, 192), (0, 192)]
+    kw = dict(seed=717, bin_of_mode=bins, d=2, mode="joint", windows=wins, n_sub=16,
+              samples_per_sub=64, chunk=1024, device=DEV)
+    p64 = mp.CountsPipeline(T, r, prec="fp64", **kw)
+    p64.run()
+    ref, _, s = p64.result()
+    del p64
+    p = mp.CountsPipeline(T, r, prec=prec, fused=fused, **kw)
+    p.run()
+    got, _, sg = p.result()
+    assert np.all(np.isfinite(got)) and np.all(np.isfinite(sg))
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    print(f"{prec} fused={fused}: max |P - P_fp64| = {err.max():.2e} "
+          f"(max over cells of (|dP| - 1e-6 peak) / sigma: "
+          f"{((err - 1e-6 * scale) / np.maximum(s, 1e-300)).max():.2e}), peak {scale:.2e}")
+    assert np.all(err <= 0.02 * s + 1e-6 * scale), err.max()

@@ -87,7 +87,8 @@ def test_plan_equals_single_network_runs(prec, tmp_path):
     plan2.close()
 
 
-def test_plan_tile_widths_from_cache(tmp_path):
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+def test_plan_tile_widths_from_cache(prec, tmp_path):
     """Tile widths per network (128 modes by 128 or 64 samples) read from the
     tuning cache: a plan forced to mixed widths, with ragged sample tails in
     both, gives the same bits as the tuned plan and the single-network runs;
@@ -95,7 +96,7 @@ def test_plan_tile_widths_from_cache(tmp_path):
     import paper_2503_12749_amd as mp
     nets = _nets([70, 200, 330, 600], E=4000, n_sub=4, seed0=123)
     cache = tmp_path / "tune.json"
-    plan = mp.Plan(nets, prec="split_fp16", tune_cache=cache)
+    plan = mp.Plan(nets, prec=prec, tune_cache=cache)
     info = plan.info()
     assert all(t[0] == 128 and t[1] in (64, 128) for t in info["tiles"])
     plan.launch()
@@ -106,7 +107,7 @@ def test_plan_tile_widths_from_cache(tmp_path):
     for widths in ("2,4,2,4", "2,2,2,2", "4,4,4,4"):
         entry["nj"] = widths
         cache.write_text(json.dumps({key: entry}))
-        p2 = mp.Plan(nets, prec="split_fp16", tune_cache=cache)
+        p2 = mp.Plan(nets, prec=prec, tune_cache=cache)
         assert [t[1] for t in p2.info()["tiles"]] == [32 * int(w) for w in widths.split(",")]
         assert p2.info()["order"] == entry["order"]
         p2.launch()
@@ -115,11 +116,11 @@ def test_plan_tile_widths_from_cache(tmp_path):
             assert np.array_equal(P, ref[i][0]) and np.array_equal(s, ref[i][2]), (widths, i)
         p2.close()
     for i, n in enumerate(nets):
-        P, _, s = _single(n, "split_fp16")
+        P, _, s = _single(n, prec)
         assert np.array_equal(ref[i][0], P) and np.array_equal(ref[i][2], s), i
     entry["nj"] = "2,3,2,4"
     cache.write_text(json.dumps({key: entry}))
-    p3 = mp.Plan(nets, prec="split_fp16", tune_cache=cache)
+    p3 = mp.Plan(nets, prec=prec, tune_cache=cache)
     assert len(json.loads(cache.read_text())) == 1  # retuned and stored under the same key
     assert "3" not in json.loads(cache.read_text())[key]["nj"]
     p3.close()
@@ -211,6 +212,63 @@ def test_plan_odd_ensembles(prec):
         assert np.array_equal(P, Pr), i
         assert np.array_equal(s, sr) or (n["n_sub"] == 1 and np.isnan(s).all() and np.isnan(sr).all()), i
         assert abs(P.sum() - 1) < 1e-8
+    plan.close()
+
+
+def _binned_nets(Ms, E, n_sub, seed0, mode, d):
+    """Networks whose outputs are split into d bins (the first d - 1 equal
+    blocks, the rest the last bin, one mode uncounted), with windows from the
+    per-bin uniform-loss moments."""
+    nets = _nets(Ms, E, n_sub, seed0)
+    for n in nets:
+        M = len(n["r"])
+        bins = np.minimum(np.arange(M) * d // M, d - 1).astype(np.int32)
+        bins[M // 3] = -1
+        wins = []
+        for b in range(d):
+            frac = (bins == b).sum() / M
+            mean, sd = synth.uniform_loss_moments(n["r"], n["t"], frac=frac)
+            wins.append(synth.count_window(mean, sd))
+        if mode == "marginals_and_total":
+            mean, sd = synth.uniform_loss_moments(n["r"], n["t"], frac=(bins >= 0).sum() / M)
+            wins.append(synth.count_window(mean, sd))
+        if mode == "joint":
+            cap = 192 if d == 2 else 32
+            wins = [(lo, min(K, cap)) for lo, K in wins]
+        n.update(bin_of_mode=bins, d=d, mode=mode, windows=wins)
+        del n["window"]
+    return nets
+
+
+@pytest.mark.parametrize("prec,mode,d", [("split1t_fp16", "marginals_and_total", 3),
+                                         ("split_fp16", "marginals_and_total", 2),
+                                         ("split_bf16", "joint", 2),
+                                         ("split_fp16", "joint", 3),
+                                         ("fp32", "marginals", 3),
+                                         ("fp64", "joint", 2)])
+def test_plan_binned_equals_single_network_runs(prec, mode, d):
+    """Plans over binned distributions (marginals of d bins with or without
+    the total, joint grids of two and three bins; an uncounted mode; two
+    passes for the larger networks): every network's accumulators finalise to
+    the same bits
+    as the single-network pipeline in the same chunks (the occupation-fused
+    path; FP64 through C)."""
+    import paper_2503_12749_amd as mp
+    nets = _binned_nets([90, 200, 330], E=2048, n_sub=4, seed0=717, mode=mode, d=d)
+    nets[0]["E"] = 1024
+    nets[0]["n_sub"] = 2
+    plan = mp.Plan(nets, prec=prec, chunk=1024)
+    plan.launch()
+    for i, n in enumerate(nets):
+        P, _, s = plan.result(i)
+        p = mp.CountsPipeline(n["T"], n["r"], prec=prec, seed=n["seed"], net=n["net"],
+                              bin_of_mode=n["bin_of_mode"], d=d, mode=mode, windows=n["windows"],
+                              n_sub=n["n_sub"], samples_per_sub=n["E"] // n["n_sub"], chunk=1024,
+                              fused=prec != "fp64")
+        p.run()
+        Pr, _, sr = p.result()
+        assert P.shape == Pr.shape, (i, P.shape, Pr.shape)
+        assert np.array_equal(P, Pr) and np.array_equal(s, sr), i
     plan.close()
 
 
