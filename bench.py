@@ -31,14 +31,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "samples·M²/s and seconds to binned P(m) at 1σ≤1e-3, M=8000, mixed vs FP32"
+# The split forms are priced against the dense FP16 (BF16) peak: the product
+# they deliver is an FP16-operand contraction (the T-split form's FP8 MFMA only
+# computes its correction term).
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0,
-                "split1_fp16": 2500.0, "split1t_fp16": 2500.0}
-# MFMA products per real multiply-add of the split forms (hi*hi + hi*lo + lo*hi;
-# one-sided: A*hi + A*lo or hi*B + lo*B)
-PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "split1_fp16": 2, "split1t_fp16": 2}
+                "split1_fp16": 2500.0, "split1t_fp16": 2500.0, "split1t_f8": 2500.0}
+# MFMA products per real multiply-add of the split forms, in FP16-product
+# equivalents (hi*hi + hi*lo + lo*hi; one-sided: A*hi + A*lo or hi*B + lo*B;
+# the FP8 correction form: one FP16 product and one FP8 product, which issues
+# at twice the FP16 rate)
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "split1_fp16": 2, "split1t_fp16": 2,
+            "split1t_f8": 1.5}
 DTYPES = {"split_bf16": "split-bf16 (fp32 acc)", "split_fp16": "split-fp16 (fp32 acc)",
           "split1_fp16": "fp16 x split-fp16 (fp32 acc)",
-          "split1t_fp16": "split-fp16 x fp16 (fp32 acc)", "fp32": "fp32", "fp64": "f64"}
+          "split1t_fp16": "split-fp16 x fp16 (fp32 acc)",
+          "split1t_f8": "fp16 x fp16 + e4m3 x e4m3 correction (fp32 acc)", "fp32": "fp32",
+          "fp64": "f64"}
 HBM_PEAK_GBS = 8000.0
 
 # FETCH_SIZE / WRITE_SIZE of the GEMM kernel at this workload (rocprofv3 --pmc,
@@ -436,7 +444,8 @@ def run_precision_m4000(args, mp, torch, synth):
     M, T, r, seed, bins, wins = w.M, w.T, w.r, w.seed, w.bins, w.windows
     E = w.E
     res = {}
-    for prec in ("fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16"):
+    for prec in ("fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16",
+                 "split1t_f8"):
         p = mp.CountsPipeline(T, r, prec=prec, seed=seed, bin_of_mode=bins, d=4,
                               mode="marginals_and_total", windows=wins, n_sub=E // ns,
                               samples_per_sub=ns, chunk=chunk)
@@ -454,7 +463,7 @@ def run_precision_m4000(args, mp, torch, synth):
     off = np.cumsum([0] + [k for _, k in wins])
     s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
     per = {}
-    for prec in ("fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16"):
+    for prec in ("fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16", "split1t_f8"):
         secs, P = res[prec][0], res[prec][1]
         rows = []
         for b in range(5):
@@ -486,7 +495,7 @@ def run_precision_m8000(args, mp, torch, synth):
     E = 11 * chunk
     w = synth.workload_m8000(E=E, chunk=chunk)
     res = {}
-    for prec in ("fp64", "split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
+    for prec in ("fp64", "split1t_f8", "split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
         p = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
                               n_sub=E // ns, samples_per_sub=ns, chunk=chunk,
                               fused=prec != "fp64")
@@ -498,7 +507,7 @@ def run_precision_m8000(args, mp, torch, synth):
     s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
     bulk = P64 > 1e-3 * P64.max()
     per = {}
-    for prec in ("split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
+    for prec in ("split1t_f8", "split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
         secs, P = res[prec][0], res[prec][1]
         err = np.abs(P - P64)
         per[prec] = {"run_s": secs, "max_abs_err": float(err.max()),
@@ -506,13 +515,13 @@ def run_precision_m8000(args, mp, torch, synth):
                      "mean_err_over_sigma": float((err / sig64)[bulk].mean())}
         log(f"[bench] precision_m8000 {prec}: max |P - P64| / sigma_T = "
             f"{per[prec]['max_err_over_sigma']:.3e}")
-    main = res["split1t_fp16"][0]
+    main = res["split1t_f8"][0]
     return _envelope(
-        "samples·M²/s, M=8000 run to max sigma_T <= 1e-3 max P, T-split FP16 "
-        "(error vs FP64 per bin in config)",
+        "samples·M²/s, M=8000 run to max sigma_T <= 1e-3 max P, T-split with the FP8 "
+        "correction (error vs FP64 per bin in config)",
         E * w.M ** 2 / main, "samples·M²/s", 1e3 * main / (E / chunk),
         f"M8000_t0.95_r1: total counts, E={E} in chunks of {chunk}, {E // ns} sub-ensembles",
-        "split-fp16 x fp16 (fp32 acc)", fp64_run_s=s64,
+        DTYPES["split1t_f8"], fp64_run_s=s64,
         sigma_max_over_P_max=float(sig64.max() / P64.max()), precisions=per)
 
 
@@ -575,17 +584,21 @@ def run_batched(args, mp, torch, synth):
     hipGraph with one persistent grouped GEMM launch with the
     occupation-fused epilogue per pass over chunks of 1e5) against the same
     networks run one after another through the fused CountsPipeline.  The
-    line of record runs the default mixed precision (T-split FP16: T hi/lo,
-    samples one FP16 value, two products); a second leg runs the
-    three-product split FP16, whose plans also choose a tile width per size
-    class, and a third the same at E = 4096 (4 sub-ensembles of 1024), where
-    a single network offers the 256 compute units few GEMM tiles."""
+    line of record runs the default mixed precision (the T-split form with
+    its correction product in FP8); further legs run the T-split FP16 form
+    (two FP16 products), the three-product split FP16, whose plans also
+    choose a tile width per size class, and the latter at E = 4096 (4
+    sub-ensembles of 1024), where a single network offers the 256 compute
+    units few GEMM tiles."""
     E, n_sub, chunk = 200_000, 20, 100_000
     Ms = synth.BATCHED_SIZES
     work = sum(E * M ** 2 for M in Ms)
     log("[bench] batched: creating the plans (autotuned order, prefetch, tiles)")
     main = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
-                        "batched T-split", prec="split1t_fp16")
+                        "batched T-split FP8 correction", prec="split1t_f8")
+    tsplit = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
+                          "batched T-split", prec="split1t_fp16")
+    tsplit["samples_M2_per_s"] = work / tsplit["plan_s"]
     three = _batched_leg(mp, torch, synth.batched_networks(E=E, n_sub=n_sub), chunk,
                          "batched three-product split")
     three["samples_M2_per_s"] = work / three["plan_s"]
@@ -597,9 +610,10 @@ def run_batched(args, mp, torch, synth):
         "samples·M²/s over 16 uneven networks in one plan, split-FP16", work / plan_s,
         "samples·M²/s", 1e3 * plan_s,
         "16 networks: 4 x M in {500, 1000, 2000, 4000}, t ~ U[0.85, 0.99], r = 1, E = 2e5 "
-        "each in chunks of 1e5, total counts", "split-fp16 x fp16 (fp32 acc)",
+        "each in chunks of 1e5, total counts", DTYPES["split1t_f8"],
         **main, algorithmic_tflops_whole_job=8.0 * work / plan_s / 1e12,
-        three_product_split_fp16=three, three_product_split_fp16_e4096=small)
+        t_split_fp16=tsplit, three_product_split_fp16=three,
+        three_product_split_fp16_e4096=small)
 
 
 def run_surrogate(args, mp, torch, synth):

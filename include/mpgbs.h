@@ -59,6 +59,11 @@ typedef enum {
                           value (column pairs, below), 2 FP16 MFMA products, FP32
                           accumulate: the rounding error is per sample and averages
                           like the sampling noise */
+  MP_SPLIT1T_F8 = 6,   /* MP_SPLIT1T_FP16 with the correction product in FP8: T as an
+                          FP16 value and its FP16 remainder scaled into OCP e4m3, the
+                          samples as one FP16 value plus an e4m3 copy (layouts below);
+                          C = T_hi S + T_lo8 S8 by one FP16 and one FP8 MFMA product
+                          per pair of 32-deep slabs, FP32 accumulate */
   /* Range markers, not values: with them every int is a representable
    * mp_precision, so an out-of-range argument reaches the library's check
    * (MP_ERR_ARG) instead of being undefined on the C++ side.  The same holds
@@ -131,6 +136,12 @@ size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
  *          each 32-mode block, the pair's two 32-value runs side by side).
  *          With E odd the storage columns E and E2 + E are padding, written
  *          as zeros.
+ *          SPLIT1T_F8 -> the SPLIT1T_FP16 operand (same storage columns and
+ *          layout, 2 ldm 2 E2 bytes), followed by the e4m3 copy of each value
+ *          (OCP FP8: 4 exponent bits, bias 7, 3 mantissa bits, round to
+ *          nearest even): mode j of storage column c at byte (c / 2) 2 ldm +
+ *          128 (j / 64) + 64 (c % 2) + j % 64 of that second part (for each
+ *          64-mode block, the pair's two 64-byte runs side by side).
  *   n_out  device FP64[E]: n = sum_j alpha_j beta_j of the values as stored
  *          (after rounding to `prec`).
  */

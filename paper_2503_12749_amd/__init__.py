@@ -339,10 +339,11 @@ class CountsPipeline:
 
     def alpha_beta(self, E: int):
         """Views of the last chunk's stored amplitudes as numpy (E, M) arrays
-        (FP64, FP32 and the T-split form's single FP16 storage; synchronises)."""
+        (FP64, FP32 and the single FP16 storage of the two T-split forms;
+        synchronises)."""
         t = self.torch
         ldm = mp_ld_modes(self.M)
-        if self.prec == _lib.PRECISIONS["split1t_fp16"]:
+        if self.prec in (_lib.PRECISIONS["split1t_fp16"], _lib.PRECISIONS["split1t_f8"]):
             h = self.ab.view(t.float16).double().cpu().numpy()
             e2 = E + (E & 1)
             j = np.arange(self.M)

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libmpgbs.so")
 
 MP_OK, MP_ERR_ARG, MP_ERR_SHAPE, MP_ERR_HIP, MP_ERR_UNSUPPORTED, MP_ERR_WORKSPACE = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3, "split1_fp16": 4,
-              "split1t_fp16": 5}
+              "split1t_fp16": 5, "split1t_f8": 6}
 BIN_MODES = {"joint": 0, "marginals": 1, "marginals_and_total": 2}
 ESTIMATORS = {"matrix_p": 0, "plus_p": 1}
 MP_MAX_BINS = 8

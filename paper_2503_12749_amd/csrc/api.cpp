@@ -122,8 +122,7 @@ int64_t mp_ld_modes(int32_t M) { return M < 1 ? -1 : ld_modes(M); }
 
 size_t mp_ab_bytes(int32_t M, int64_t E, mp_precision prec) {
   if (M < 1 || E < 1 || !valid_prec(prec)) return 0;
-  const int64_t cols = prec == MP_SPLIT1T_FP16 ? 2 * split1t_half(E) : 2 * E;
-  return (size_t)ld_modes(M) * (size_t)cols * elem_bytes_ab(prec);
+  return (size_t)ld_modes(M) * (size_t)ab_columns(E, prec) * elem_bytes_ab(prec);
 }
 
 size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec) {
@@ -295,7 +294,7 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
                                    n_sub, samples_per_sub, e0);
   if (st != MP_OK) return st;
   MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16 ||
-                   prec == MP_SPLIT1_FP16 || prec == MP_SPLIT1T_FP16,
+                   prec == MP_SPLIT1_FP16 || pair_columns(prec),
                MP_ERR_UNSUPPORTED,
                "mp_propagate_counts: precision %d is not fused (FP32 and split precisions are)",
                (int)prec);
@@ -325,7 +324,7 @@ mp_status mp_propagate_counts_noalloc(int32_t M, int64_t E, mp_precision prec, m
                                    m_lo, K, n_sub, samples_per_sub, e0);
   if (st != MP_OK) return st;
   MP_CHECK_ARG(prec == MP_FP32 || prec == MP_SPLIT_BF16 || prec == MP_SPLIT_FP16 ||
-                   prec == MP_SPLIT1_FP16 || prec == MP_SPLIT1T_FP16,
+                   prec == MP_SPLIT1_FP16 || pair_columns(prec),
                MP_ERR_UNSUPPORTED,
                "mp_propagate_counts_noalloc: precision %d is not fused (FP32 and split "
                "precisions are)", (int)prec);

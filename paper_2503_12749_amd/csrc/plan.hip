@@ -34,6 +34,7 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
                         hipStream_t stream);
 size_t propagate_workspace(int32_t M, mp_precision prec);
 int split_scale_exp(int32_t M, mp_precision prec);
+int f8_scale_a(int32_t M);
 mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
                       hipStream_t stream);
 mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
@@ -164,7 +165,8 @@ static void plan_free(Plan* p) {
 // The split precisions run one grouped GEMM per pass; the three-product ones
 // offer two tile widths (the one-sided split kernel has the 128-sample tile only).
 static bool split(mp_precision p) {
-  return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16 || p == MP_SPLIT1_FP16 || p == MP_SPLIT1T_FP16;
+  return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16 || p == MP_SPLIT1_FP16 || p == MP_SPLIT1T_FP16 ||
+         p == MP_SPLIT1T_F8;
 }
 static bool two_widths(mp_precision p) { return p == MP_SPLIT_BF16 || p == MP_SPLIT_FP16; }
 
@@ -548,7 +550,7 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
     n.sigma = (double*)plan_alloc(p, (size_t)n.entries * 8);
     n.ws_fin_bytes = finalize_workspace(n.nb, n.mode, n.K.data(), n.d.n_sub);
     if (n.ws_fin_bytes) n.ws_fin = plan_alloc(p, n.ws_fin_bytes);
-    n.ab = plan_alloc(p, (size_t)n.ldm * 2 * n.chunk * (prec == MP_FP64 ? 8 : 4));
+    n.ab = plan_alloc(p, (size_t)n.ldm * ab_columns(n.chunk, prec) * elem_bytes_ab(prec));
     if (!fused(prec)) n.C = plan_alloc(p, (size_t)2 * n.ldm * 2 * n.chunk * eb);
     n.packed = plan_alloc(p, propagate_workspace(n.d.M, prec));
     const int64_t ns = n.d.E / n.d.n_sub;
@@ -592,9 +594,9 @@ mp_status mp_plan_create(void** plan, int32_t n_net, const mp_net_desc* nets, mp
         const int64_t e = std::max<int64_t>(0, std::min<int64_t>(n.chunk, n.d.E - (int64_t)pass * n.chunk));
         const float sc = ldexpf(1.0f, -split_scale_exp(n.d.M, prec));
         // the T-split sample operand's storage columns: beta from E2 on
-        const int64_t cols = prec == MP_SPLIT1T_FP16 ? 2 * split1t_half(e) : 2 * e;
+        const int64_t cols = ab_columns(e, prec);
         g[i] = GroupNet{(const uint16_t*)n.packed, (const uint16_t*)n.ab, nullptr, n.ldm, cols, sc,
-                        FusedOut{}};
+                        prec == MP_SPLIT1T_F8 ? f8_scale_a(n.d.M) : 0, FusedOut{}};
         if (e > 0) {
           const mp_status st = fused_out_setup(n.d.M, e, n.nb, n.bins.data(), n.mode,
                                                n.m_lo.data(), n.K.data(),

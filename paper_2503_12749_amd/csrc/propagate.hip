@@ -84,6 +84,14 @@ __global__ void pack_transmission(const double* __restrict__ T, int M, int64_t l
   } else if constexpr (PREC == MP_SPLIT1_FP16) {
     // one FP16 value per entry, prescaled like MP_SPLIT_FP16
     ((_Float16*)A)[split1_a_offset(row, j, ldm)] = (_Float16)ldexp(v, scale_exp);
+  } else if constexpr (PREC == MP_SPLIT1T_F8) {
+    // the MP_SPLIT1_FP16 packing, then (from byte 4 ldm^2 on) the remainder
+    // x - hi in e4m3, scaled by 2^e4m3_lo_scale_exp, in row pairs
+    const double x = ldexp(v, scale_exp);
+    const _Float16 hi = (_Float16)x;
+    ((_Float16*)A)[split1_a_offset(row, j, ldm)] = hi;
+    const float lo = (float)ldexp(x - (double)hi, e4m3_lo_scale_exp(scale_exp));
+    ((uint8_t*)A)[4 * ldm * ldm + pair8_offset(row, j, ldm)] = e4m3_rne(lo);
   } else {
     // FP16: A is packed as T * 2^scale_exp so that both halves stay normal
     const double x = ldexp(v, scale_exp);
@@ -1312,6 +1320,311 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1t_occ(const uint16_t* 
                                          (int64_t)tn * 128, out_scale, &fo);
 }
 
+// ---------------------------------------------------------------- T-split with an FP8 correction, 256 x 256
+
+// MP_SPLIT1T_F8: the T-split product T_hi S + T_lo S with its correction term
+// in FP8.  T_hi is T (prescaled by 2^e) rounded to FP16; the remainder
+// T_lo = x - T_hi, at most 2^-10 of x, is scaled by 2^(18 - e) and rounded
+// to e4m3, so the network is kept to about 2^-15 of x; the samples are one
+// FP16 value S and its e4m3 copy S8.  The correction T_lo8 S8 needs only a
+// few significant bits (it is 2^-11 of the product), and one
+// v_mfma_scale_f32_32x32x64_f8f6f4 (its A block scale 2^(e - 18) undoes the
+// remainder's scale) replaces the second FP16 product of a 64-deep block at
+// half its issue cost: per pair of 32-deep slabs 4 FP16 MFMAs and 1 FP8 MFMA
+// per 32 x 32 block instead of 8 FP16 MFMAs.
+//
+// Operands in pair lines (128 bytes): T_hi in row pairs (MP_SPLIT1_FP16's
+// packing) and S in column pairs (MP_SPLIT1T_FP16's layout) per 32-deep
+// slab; T_lo8 and S8 in row / column pairs per 64-deep block.  LDS: two
+// FP16 stages of 32 KB ([S pairs][T_hi pairs], 16 KB each) and two FP8
+// buffers of 32 KB ([S8 pairs][T_lo8 pairs]), then the prefetch sink; 16-byte
+// chunk c of pair line p at c ^ swz8(p) in every plane.  A 32-byte FP8
+// fragment of row r is the chunks 2 lh, 2 lh + 1 of its 64-byte run (lane
+// half lh supplies k = 32 lh .. 32 lh + 31, the same on both operands).
+//
+// Slab kt uses FP16 stage kt & 1 and FP8 buffer (kt / 2) & 1: an even slab
+// reads T_lo8's fragments (all four row blocks, kept in registers for the
+// odd slab) and S8's for column blocks 0-1, an odd slab S8's for blocks 2-3;
+// each slab issues the FP8 MFMAs of its two column blocks.  The FP8 loads of
+// pair q are issued half in slab 2q - 3 (S8) and half in slab 2q - 2
+// (T_lo8), after the barriers that end the reads of pair q - 2 from the same
+// buffer, and land before the slab 2q - 1 barrier that precedes their reads;
+// past the last pair they reload it into the buffer no longer read.
+constexpr int F8_PLANE = 16384;              // bytes: 128 pair lines
+constexpr int F8_STAGE = 2 * F8_PLANE;       // [B pairs][A pairs]
+constexpr int F8_LDS = 4 * F8_STAGE + 1024;  // two FP16 stages, two FP8 buffers, sink
+
+__device__ inline int f8_chunk_off(int r, int c) {
+  return (r >> 1) * 128 + ((c ^ swz8(r >> 1)) << 4);
+}
+
+template <bool FUSED, bool PF>
+__device__ __attribute__((always_inline)) inline void split1t8_pp_tile(
+    char* __restrict__ lds, const uint16_t* __restrict__ A, const uint8_t* __restrict__ A8,
+    const uint16_t* __restrict__ B, const uint8_t* __restrict__ B8, float* __restrict__ C,
+    int64_t ldm, int64_t ncols, int64_t e_real, int64_t m0, int64_t n0, float out_scale,
+    int scale_a, const FusedOut* fo, int tid = -1) {
+  typedef __attribute__((ext_vector_type(8))) int i32x8;
+  typedef __attribute__((ext_vector_type(4))) int i32x4;
+  const int wave = tid < 0 ? (int)(threadIdx.x >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid < 0 ? (int)(threadIdx.x & 63) : tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  // first global row of tile row pair pa (tile rows 2 pa, 2 pa + 1)
+  auto a_row = [&](int pa) -> int64_t {
+    if constexpr (FUSED) return pa < 64 ? m0 + 2 * pa : ldm + m0 + 2 * (pa - 64);
+    return m0 + 2 * pa;
+  };
+  // first storage column of tile column pair pr
+  const int64_t half = FUSED ? ncols / 2 : ncols;
+  auto b_pair = [&](int pr) -> int64_t {
+    if constexpr (FUSED) {
+      const int64_t c = n0 + 2 * (pr & 63);
+      return (c <= half - 2 ? c : half - 2) + (pr >= 64 ? half : 0);
+    }
+    const int64_t c = n0 + 2 * pr;
+    return c <= half - 2 ? c : half - 2;
+  };
+  // FP16 stage: load g = 8 wave + q fills B pairs 8 g .. (g < 16) or A pairs
+  // 8 (g - 16) ..; lane l fills slot l % 8 of pair l / 8 with global chunk
+  // (l % 8) ^ swz8(pair)
+  const char* src16[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int g = 8 * wave + q, chunk = lane & 7;
+    if (g < 16) {
+      const int pr = 8 * g + (lane >> 3);
+      src16[q] = (const char*)(B + b_pair(pr) * ldm) + ((chunk ^ swz8(pr)) << 4);
+    } else {
+      const int pa = 8 * (g - 16) + (lane >> 3);
+      src16[q] = (const char*)(A + a_row(pa) * ldm) + ((chunk ^ swz8(pa)) << 4);
+    }
+  }
+  // FP8 buffer: half 0 = B8 pairs, half 1 = A8 pairs, load g = 4 wave + q
+  const char* src8[2][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g = 4 * wave + q, chunk = lane & 7, p = 8 * g + (lane >> 3);
+    src8[0][q] = (const char*)(B8 + b_pair(p) * ldm) + ((chunk ^ swz8(p)) << 4);
+    src8[1][q] = (const char*)(A8 + a_row(p) * ldm) + ((chunk ^ swz8(p)) << 4);
+  }
+  auto issue16 = [&](int st, int64_t k0) {
+    char* base = lds + st * F8_STAGE;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src16[q] + (k0 << 2)),
+                                       (lds_void*)(base + (8 * wave + q) * 1024), 16, 0, 0);
+  };
+  const int KT = (int)(ldm / S_BK);  // even (ldm is a multiple of 128), >= 4
+  const int NP = KT / 2;
+  // half `hf` of FP8 pair `pair` into buffer pair & 1 (data of pair min(pair, NP - 1))
+  auto issue8 = [&](int pair, int hf) {
+    char* base = lds + 2 * F8_STAGE + (pair & 1) * F8_STAGE + hf * F8_PLANE;
+    const int64_t k0 = (int64_t)min(pair, NP - 1) * 64;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src8[hf][q] + (k0 << 1)),
+                                       (lds_void*)(base + (4 * wave + q) * 1024), 16, 0, 0);
+  };
+  // L2 prefetch of the sample pairs' lines, one 4-byte load per wave and slab
+  const char* pf_src = (const char*)(B + b_pair(32 * wave + (lane & 31)) * ldm);
+  auto prefetch = [&](int64_t k0) {
+    if constexpr (!PF) return;
+    __builtin_amdgcn_global_load_lds((const void*)(pf_src + (k0 << 2)),
+                                     (lds_void*)(lds + 4 * F8_STAGE), 4, 0, 0);
+  };
+  int oa[2][4], ob[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = wm * 128 + i * 32 + lr, rb = wn * 128 + i * 32 + lr;
+      oa[s][i] = f8_chunk_off(ra, (ra & 1) * 4 + 2 * lh + s);
+      ob[s][i] = f8_chunk_off(rb, (rb & 1) * 4 + 2 * lh + s);
+    }
+  f16x8 a0[4], b0[4], a1[4], b1[4];
+  i32x8 a8[4], b8[4];
+  auto read16 = [&](int st, int s, f16x8* a, f16x8* b) {
+    const char* pb = lds + st * F8_STAGE;
+    const char* pa = pb + F8_PLANE;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = *(const f16x8*)(pa + oa[s][i]);
+      b[i] = *(const f16x8*)(pb + ob[s][i]);
+    }
+  };
+  auto rd8 = [&](const char* p, int o0, int o1) -> i32x8 {
+    const i32x4 x = *(const i32x4*)(p + o0), y = *(const i32x4*)(p + o1);
+    return i32x8{x[0], x[1], x[2], x[3], y[0], y[1], y[2], y[3]};
+  };
+  auto read8 = [&](int kt, auto par) {
+    constexpr int P = decltype(par)::value;
+    const char* pb = lds + 2 * F8_STAGE + ((kt >> 1) & 1) * F8_STAGE;
+    const char* pa = pb + F8_PLANE;
+    if constexpr (P == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a8[i] = rd8(pa, oa[0][i], oa[1][i]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b8[j] = rd8(pb, ob[0][j], ob[1][j]);
+    } else {
+#pragma unroll
+      for (int j = 2; j < 4; ++j) b8[j] = rd8(pb, ob[0][j], ob[1][j]);
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // prologue: slab 0 and FP8 pair 0 landed; slab 1 and pair 1's first half in flight
+  issue16(0, 0);
+  issue8(0, 0);
+  issue8(0, 1);
+  __builtin_amdgcn_s_waitcnt(0);
+  barrier_no_fence();
+  issue16(1, S_BK);
+  issue8(1, 0);
+  prefetch((int64_t)min(1 + kPrefetchSlabs, KT - 1) * S_BK);
+  read16(0, 0, a0, b0);
+  constexpr int kSgMfma = 0x008, kSgDsRead = 0x100, kSgVmem = 0x020;
+  constexpr int kWaitN = PF ? 1 : 0;
+  auto slab = [&](int kt, auto par) {
+    constexpr int P = decltype(par)::value;  // kt & 1: the FP16 stage
+    // phase A: FP16 MFMAs on step 0; reads of step 1 and of the slab's FP8 fragments
+    read16(P, 1, a1, b1);
+    read8(kt, par);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0[i], b0[j], acc[i][j], 0, 0, 0);
+    if constexpr (P == 0) {  // 8 + 12 reads
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSgDsRead, 2, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 6, 0);
+    } else {  // 8 + 4 reads
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
+        __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 4, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // own loads of the previous slab landed (with PF but the prefetch after
+    // them), own reads complete
+    __builtin_amdgcn_s_waitcnt((kWaitN & 15) | ((kWaitN >> 4) << 14) | (7 << 4));
+    barrier_no_fence();
+    __builtin_amdgcn_sched_barrier(0);
+    // phase B: FP16 MFMAs on step 1 and the FP8 MFMAs of column blocks 2P,
+    // 2P + 1; loads of slab kt + 2 and of half P ^ 1 of FP8 pair
+    // (kt + 1) / 2 + 1; reads of step 0 of slab kt + 1
+    issue16(P, (int64_t)min(kt + 2, KT - 1) * S_BK);
+    issue8((kt + 1) / 2 + 1, P ^ 1);
+    prefetch((int64_t)min(kt + 2 + kPrefetchSlabs, KT - 1) * S_BK);
+    read16(P ^ 1, 0, a0, b0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[i], b1[j], acc[i][j], 0, 0, 0);
+    constexpr int jb = 2 * P;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+        acc[i][jb + jj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+            a8[i], b8[jb + jj], acc[i][jb + jj], 0, 0, 0, scale_a, 0, 127);
+    constexpr int kVm = PF ? 13 : 12;
+#pragma unroll
+    for (int q = 0; q < kVm; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgVmem, 1, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      __builtin_amdgcn_sched_group_barrier(kSgMfma, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(kSgDsRead, 1, 1);
+    }
+    __builtin_amdgcn_sched_group_barrier(kSgMfma, 24 - kVm - 8, 1);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int kt = 0; kt < KT; kt += 2) {
+    slab(kt, std::integral_constant<int, 0>{});
+    slab(kt + 1, std::integral_constant<int, 1>{});
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if constexpr (FUSED) {
+    fused_epilogue(acc, (float*)lds, *fo, m0, n0, wm, wn, lane, out_scale);
+    return;
+  }
+  const int64_t ldc = 2 * ldm, e2 = split1t_half(e_real);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t sc = n0 + wn * 128 + j * 32 + lr;  // storage column
+    if (sc >= ncols) continue;
+    int64_t col;
+    if (sc < e2) {
+      if (sc >= e_real) continue;  // padding of an odd E
+      col = sc;
+    } else {
+      if (sc - e2 >= e_real) continue;
+      col = e_real + (sc - e2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t row = m0 + wm * 128 + i * 32 + 8 * g + 4 * lh;
+        *(f32x4*)(C + col * ldc + row) =
+            f32x4{acc[i][j][4 * g] * out_scale, acc[i][j][4 * g + 1] * out_scale,
+                  acc[i][j][4 * g + 2] * out_scale, acc[i][j][4 * g + 3] * out_scale};
+      }
+  }
+}
+
+// A8 and B8 follow the FP16 parts of the packed operand (4 ldm^2 bytes) and
+// of the sample operand (2 ncols ldm bytes).
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_pp(const uint16_t* __restrict__ A,
+                                                                const uint16_t* __restrict__ B,
+                                                                float* __restrict__ C, int64_t ldm,
+                                                                int64_t ncols, int64_t e_real,
+                                                                float out_scale, int scale_a) {
+  __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
+  const uint8_t* A8 = (const uint8_t*)A + 4 * ldm * ldm;
+  const uint8_t* B8 = (const uint8_t*)B + 2 * ncols * ldm;
+  split1t8_pp_tile<false, PF>(lds, A, A8, B, B8, C, ldm, ncols, e_real, (int64_t)tm * S_BM,
+                              (int64_t)tn * S_BN, out_scale, scale_a, nullptr);
+}
+
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_occ(const uint16_t* __restrict__ A,
+                                                                 const uint16_t* __restrict__ B,
+                                                                 int64_t ldm, int64_t ncols,
+                                                                 float out_scale, int scale_a,
+                                                                 FusedOut fo) {
+  __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
+  const uint8_t* A8 = (const uint8_t*)A + 4 * ldm * ldm;
+  const uint8_t* B8 = (const uint8_t*)B + 2 * ncols * ldm;
+  split1t8_pp_tile<true, PF>(lds, A, A8, B, B8, nullptr, ldm, ncols, 0, (int64_t)tm * 128,
+                             (int64_t)tn * 128, out_scale, scale_a, &fo);
+}
+
 // ---------------------------------------------------------------- FP32, 256 x 256
 
 // FP32 twin of the split ping-pong kernel: the same 256 x 256 tile, four
@@ -1569,6 +1882,28 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1t_grouped(const GroupN
   }
 }
 
+// Grouped form of the T-split kernel with the FP8 correction (the FP8 parts
+// follow the FP16 parts of each network's operands, as in gemm_split1t8_occ).
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_grouped(const GroupNet* __restrict__ nets,
+                                                                     const int4* __restrict__ items,
+                                                                     int n_items) {
+  __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];  // (net, tile_m, tile_n, 4)
+    if (w.x < 0) continue;
+    const GroupNet* g = nets + w.x;
+    int tid = threadIdx.x;  // opaque per item, as in gemm_split_grouped
+    asm volatile("" : "+v"(tid));
+    const uint8_t* A8 = (const uint8_t*)g->A + 4 * g->ldm * g->ldm;
+    const uint8_t* B8 = (const uint8_t*)g->B + 2 * g->ncols * g->ldm;
+    split1t8_pp_tile<true, PF>(lds, g->A, A8, g->B, B8, nullptr, g->ldm, g->ncols, 0,
+                               (int64_t)w.y * 128, (int64_t)w.z * 128, g->out_scale,
+                               g->f8_scale_a, &g->fo, tid);
+    __syncthreads();  // the next item reuses the LDS stages
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 size_t propagate_workspace(int32_t M, mp_precision prec) {
@@ -1578,6 +1913,7 @@ size_t propagate_workspace(int32_t M, mp_precision prec) {
     case MP_FP64: return elems * 8;
     case MP_FP32: return elems * 4;
     case MP_SPLIT1_FP16: return elems * 2;  // one FP16 value per entry
+    case MP_SPLIT1T_F8: return elems * 3;   // FP16 value, then the e4m3 remainder
     default: return elems * 4;  // hi and lo 16-bit values
   }
 }
@@ -1601,10 +1937,15 @@ static int fp16_scale_exp(int32_t M) {
 // ---- used by plans (plan.hip)
 
 int split_scale_exp(int32_t M, mp_precision prec) {
-  return (prec == MP_SPLIT_FP16 || prec == MP_SPLIT1_FP16 || prec == MP_SPLIT1T_FP16)
+  return (prec == MP_SPLIT_FP16 || prec == MP_SPLIT1_FP16 || prec == MP_SPLIT1T_FP16 ||
+          prec == MP_SPLIT1T_F8)
              ? fp16_scale_exp(M)
              : 0;
 }
+
+// Block scale (E8M0, 2^(s - 127)) of the FP8 product's A operand: undoes the
+// e4m3 remainder's scale 2^e4m3_lo_scale_exp.
+int f8_scale_a(int32_t M) { return 127 - e4m3_lo_scale_exp(fp16_scale_exp(M)); }
 
 mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packed,
                       hipStream_t stream) {
@@ -1630,6 +1971,10 @@ mp_status pack_launch(int32_t M, const double* T, mp_precision prec, void* packe
       break;
     case MP_SPLIT1_FP16:
       hipLaunchKernelGGL(pack_transmission<MP_SPLIT1_FP16>, dim3(blocks), dim3(256), 0, stream, T,
+                         M, ldm, packed, fp16_scale_exp(M));
+      break;
+    case MP_SPLIT1T_F8:
+      hipLaunchKernelGGL(pack_transmission<MP_SPLIT1T_F8>, dim3(blocks), dim3(256), 0, stream, T,
                          M, ldm, packed, fp16_scale_exp(M));
       break;
     default:
@@ -1688,6 +2033,14 @@ mp_status gemm_packed_launch(int32_t M, int64_t E, const void* packed, mp_precis
                          ldexpf(1.0f, -fp16_scale_exp(M)));
       break;
     }
+    case MP_SPLIT1T_F8: {
+      const int64_t scols = 2 * split1t_half(E);
+      auto kernel = split_prefetch_for(ldm) ? gemm_split1t8_pp<true> : gemm_split1t8_pp<false>;
+      hipLaunchKernelGGL(kernel, dim3(grid_tiles_s1t(ldm, scols)), dim3(kThreads), 0, stream,
+                         (const uint16_t*)packed, (const uint16_t*)ab, (float*)C, ldm, scols, E,
+                         ldexpf(1.0f, -fp16_scale_exp(M)), f8_scale_a(M));
+      break;
+    }
     default:
       set_error("mp_propagate: unknown precision %d", (int)prec);
       return MP_ERR_ARG;
@@ -1714,6 +2067,9 @@ mp_status grouped_launch(const GroupNet* d_nets, const int4* d_items, int n_item
                        dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
   } else if (prec == MP_SPLIT1T_FP16) {
     hipLaunchKernelGGL(prefetch ? gemm_split1t_grouped<true> : gemm_split1t_grouped<false>,
+                       dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
+  } else if (prec == MP_SPLIT1T_F8) {
+    hipLaunchKernelGGL(prefetch ? gemm_split1t8_grouped<true> : gemm_split1t8_grouped<false>,
                        dim3(grid), dim3(kThreads), 0, stream, d_nets, d_items, n_items);
   } else {
     set_error("grouped GEMM: the split precisions only");
@@ -1758,6 +2114,14 @@ mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precisi
       hipLaunchKernelGGL(kernel, dim3(grid_tiles_s1t(ldm, scols)), dim3(kThreads), 0, stream,
                          (const uint16_t*)packed, (const uint16_t*)ab, ldm, scols,
                          ldexpf(1.0f, -fp16_scale_exp(M)), fo);
+      break;
+    }
+    case MP_SPLIT1T_F8: {
+      const int64_t scols = 2 * split1t_half(E);
+      auto kernel = split_prefetch_for(ldm) ? gemm_split1t8_occ<true> : gemm_split1t8_occ<false>;
+      hipLaunchKernelGGL(kernel, dim3(grid_tiles_s1t(ldm, scols)), dim3(kThreads), 0, stream,
+                         (const uint16_t*)packed, (const uint16_t*)ab, ldm, scols,
+                         ldexpf(1.0f, -fp16_scale_exp(M)), f8_scale_a(M), fo);
       break;
     }
     default:

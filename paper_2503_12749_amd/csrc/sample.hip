@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
       if constexpr (PREC == MP_FP64 || PREC == MP_FP32) {
         col_a = k * ldm + j0;
         col_b = (E + k) * ldm + j0;
-      } else if constexpr (PREC == MP_SPLIT1T_FP16) {
+      } else if constexpr (PREC == MP_SPLIT1T_FP16 || PREC == MP_SPLIT1T_F8) {
         col_a = split1t_offset(k, j0, ldm);
         col_b = split1t_offset(split1t_half(E) + k, j0, ldm);
       } else {
@@ -278,17 +278,32 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
         const float fp0 = (float)cp0, fm0 = (float)cm0, fp1 = (float)cp1, fm1 = (float)cm1;
         const float a0 = fp0 * w1 + fm0 * w2, b0 = fp0 * w1 - fm0 * w2;
         const float a1 = fp1 * w3 + fm1 * w4, b1 = fp1 * w3 - fm1 * w4;
+        // the pair forms store the FP16 operand (and then its e4m3 copy)
+        constexpr int SP = PREC == MP_SPLIT1T_F8 ? MP_SPLIT1T_FP16 : PREC;
         double ya0, ya1, yb0, yb1;
-        store_pair_f32<PREC>(ab, col_a, a0, a1, ya0, ya1);
-        store_pair_f32<PREC>(ab, col_b, b0, b1, yb0, yb1);
+        store_pair_f32<SP>(ab, col_a, a0, a1, ya0, ya1);
+        store_pair_f32<SP>(ab, col_b, b0, b1, yb0, yb1);
         nsum[s] += ya0 * yb0 + ya1 * yb1;
-        if constexpr (PREC == MP_SPLIT1T_FP16) {
+        if constexpr (PREC == MP_SPLIT1T_F8) {
+          // e4m3 copies of the stored FP16 values, after the FP16 part
+          uint8_t* b8 = (uint8_t*)ab + 4 * split1t_half(E) * ldm;
+          const int64_t e2 = split1t_half(E);
+          *(uint16_t*)(b8 + pair8_offset(k, j0, ldm)) =
+              (uint16_t)(e4m3_rne((float)ya0) | ((uint32_t)e4m3_rne((float)ya1) << 8));
+          *(uint16_t*)(b8 + pair8_offset(e2 + k, j0, ldm)) =
+              (uint16_t)(e4m3_rne((float)yb0) | ((uint32_t)e4m3_rne((float)yb1) << 8));
+          if ((E & 1) && k == E - 1) {
+            *(uint16_t*)(b8 + pair8_offset(k, j0, ldm) + 64) = 0;
+            *(uint16_t*)(b8 + pair8_offset(e2 + k, j0, ldm) + 64) = 0;
+          }
+        }
+        if constexpr (PREC == MP_SPLIT1T_FP16 || PREC == MP_SPLIT1T_F8) {
           // odd E: the last sample (even k) shares its pairs with the padding
           // columns E and E2 + E, which the GEMM reads; they hold zeros
           if ((E & 1) && k == E - 1) {
             double z0, z1;
-            store_pair_f32<PREC>(ab, col_a + 32, 0.0f, 0.0f, z0, z1);
-            store_pair_f32<PREC>(ab, col_b + 32, 0.0f, 0.0f, z0, z1);
+            store_pair_f32<SP>(ab, col_a + 32, 0.0f, 0.0f, z0, z1);
+            store_pair_f32<SP>(ab, col_b + 32, 0.0f, 0.0f, z0, z1);
           }
         }
       }
@@ -330,6 +345,10 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
       break;
     case MP_SPLIT1T_FP16:
       hipLaunchKernelGGL(sample_kernel<MP_SPLIT1T_FP16>, dim3((unsigned)blocks), dim3(256), 0,
+                         stream, M, ldm, g0, E, r, seed, net, ab, n_out);
+      break;
+    case MP_SPLIT1T_F8:
+      hipLaunchKernelGGL(sample_kernel<MP_SPLIT1T_F8>, dim3((unsigned)blocks), dim3(256), 0,
                          stream, M, ldm, g0, E, r, seed, net, ab, n_out);
       break;
     default:

@@ -56,7 +56,8 @@ def _run(fused, prec, est, M=333, E=1000, n_sub=5, chunk=384, seed=71, t=0.9):
     return P, s, T, r, bins, wins
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "split1_fp16", "split1t_fp16",
+                                  "split1t_f8"])
 @pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
 def test_fused_equals_unfused(prec, est):
     Pf, sf, *_ = _run(True, prec, est)
@@ -145,7 +146,7 @@ def test_split1t_odd_chunks_fused_equals_unfused():
         off += K
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split1_fp16", "split1t_fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split1_fp16", "split1t_fp16", "split1t_f8"])
 @pytest.mark.parametrize("M,E", [(1, 1), (1, 3), (5, 1), (5, 3)])
 def test_tiny_chunks_fused_and_unfused(prec, M, E):
     """One mode or five, one sample or three (a single ragged tile, the

@@ -173,7 +173,7 @@ def test_joint2_long_windows_sum_to_marginals():
 
 
 @pytest.mark.parametrize("prec,fused", [("fp32", False), ("fp32", True), ("split_bf16", True),
-                                        ("split1t_fp16", True)])
+                                        ("split1t_fp16", True), ("split1t_f8", True)])
 def test_joint2_large_bin_occupations_reduced_precision(prec, fused):
     """Two-bin joint grid of a network whose bins hold about 50 photons each
     (M = 90, r = 1, t = 0.93, one mode uncounted): at the centre of its band

@@ -100,7 +100,7 @@ def m8000():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "split_bf16", "fp32", "split_fp16", "split1_fp16",
-                                  "split1t_fp16"])
+                                  "split1t_fp16", "split1t_f8"])
 def test_m8000_per_bin_vs_oracle(m8000, prec):
     """M = 8000, t = 0.95, r = 1, total counts on [8083, 11923): one
     65536-sample chunk through mp_sample and mp_propagate_counts (FP32 and
@@ -134,7 +134,8 @@ def m4000():
 @pytest.mark.parametrize("prec,fused", [("fp64", False), ("split_bf16", False),
                                         ("split_bf16", True), ("split_fp16", False),
                                         ("split_fp16", True), ("fp32", True),
-                                        ("split1_fp16", True), ("split1t_fp16", True)])
+                                        ("split1_fp16", True), ("split1t_fp16", True),
+                                        ("split1t_f8", True)])
 def test_m4000_precision_study_vs_oracle(m4000, prec, fused):
     """M = 4000, t = 0.95, r_j ~ U[0.5, 1.5], four equal mode blocks: the four
     marginals and the total of one 65536-sample chunk (the precision study's
@@ -175,7 +176,7 @@ def batched_refs():
     return nets, refs, E
 
 
-@pytest.mark.parametrize("prec", ["split_fp16", "split1_fp16", "split1t_fp16"])
+@pytest.mark.parametrize("prec", ["split_fp16", "split1_fp16", "split1t_fp16", "split1t_f8"])
 def test_batched_plan_vs_oracle(batched_refs, prec):
     """The batched form: one split plan (hipGraph, persistent grouped GEMM
     with the occupation epilogue; three-product split FP16 and the one-sided

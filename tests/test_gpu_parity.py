@@ -300,8 +300,116 @@ def test_split1t_sampler_and_propagation(M, E):
     assert dist < 1e-3
 
 
+def _e4m3_table():
+    """Values of the OCP e4m3 codes 0x00 .. 0x7E (4 exponent bits, bias 7,
+    3 mantissa bits, subnormals below 2^-6), increasing with the code."""
+    c = np.arange(127)
+    e, m = c >> 3, c & 7
+    return np.where(e > 0, np.ldexp(1.0 + m / 8.0, e - 7), np.ldexp(m / 8.0, -6))
+
+
+def _e4m3_decode(codes):
+    v = _e4m3_table()[np.asarray(codes) & 0x7F]
+    return np.where(np.asarray(codes) & 0x80, -v, v)
+
+
+def _e4m3_rne(x):
+    """Codes of x rounded to the nearest e4m3 value, ties to the even code,
+    saturating at 448: the rounding by the definition, over the code table."""
+    tab = _e4m3_table()
+    a = np.abs(np.asarray(x, dtype=np.float64))
+    hi = np.clip(np.searchsorted(tab, a), 1, 126)
+    lo = hi - 1
+    dlo, dhi = a - tab[lo], tab[hi] - a
+    code = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(lo % 2 == 0, lo, hi)))
+    code = np.where(a >= tab[126], 126, code)
+    return (code | np.where(np.signbit(x), 0x80, 0)).astype(np.uint8)
+
+
+def test_e4m3_reference_rounding():
+    """The test-side e4m3 rounding against hand-checked values."""
+    assert _e4m3_rne([1.0, 1.0625, 1.1875, 448.0, 1e6, -2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -10,
+                      0.0]).tolist() == [0x38, 0x38, 0x3A, 0x7E, 0x7E, 0x81, 0x00, 0x02, 0x00]
+    assert np.array_equal(_e4m3_decode(_e4m3_rne(_e4m3_table())), _e4m3_table())
+
+
+@pytest.mark.parametrize("M,E", [(300, 201), (2049, 1100)])
+def test_split1t_f8_sampler_packing_and_propagation(M, E):
+    """The T-split form with an FP8 correction product.  Sampler: the FP16
+    operand and n equal the T-split form's bit for bit, the e4m3 copy is the
+    nearest-even e4m3 of every stored FP16 value, and the padding pairs of
+    an odd E hold zeros.  Packing: T_hi is T 2^e within half an FP16 unit and
+    the e4m3 remainder is the nearest-even e4m3 of (x - T_hi) 2^(18 - e).
+    GEMM, every element against the oracle propagating the stored samples
+    through the exact network: the network is kept to 2^-15 |x| per entry
+    (remainder at most 2^-11 |x|, e4m3's relative rounding 2^-4) and the
+    correction product's sample copy to 2^-15 of the product, so by
+    Cauchy-Schwarz over a row of T (norm <= 1) |error| <= 2^-14 |beta| per
+    element, plus FP32 accumulation; the bound is 2^-14 of the largest
+    sample norm plus 4e-6 of the largest propagated norm."""
+    import paper_2503_12749_amd as mp
+    T = 0.95 * synth.haar_unitary(M, 12)
+    r = np.linspace(0.5, 1.5, M)
+    ldm = mp.mp_ld_modes(M)
+    e2 = E + (E & 1)
+    kw = dict(seed=5, windows=[(0, 64)], n_sub=1, samples_per_sub=E, chunk=E)
+    q = _pipe(T, r, prec="split1t_fp16", **kw)
+    mp.mp_sample(M, 0, E, q.r, q.seed, 0, "split1t_fp16", q.ab, q.n)
+    p = _pipe(T, r, prec="split1t_f8", **kw)
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, "split1t_f8", p.ab, p.n)
+    assert mp.mp_ab_bytes(M, E, "split1t_f8") == 3 * ldm * 2 * e2
+    raw = p.ab.view(torch.uint8).cpu().numpy()
+    h16 = 4 * e2 * ldm  # bytes of the FP16 part
+    assert np.array_equal(raw[:h16], q.ab.view(torch.uint8).cpu().numpy()[:h16])
+    assert np.array_equal(p.n.cpu().numpy(), q.n.cpu().numpy())
+    a_s, b_s = p.alpha_beta(E)
+    j = np.arange(M)
+    b8 = raw[h16:]
+
+    def codes(c):
+        c = np.asarray(c)[:, None]
+        return b8[(c >> 1) * 2 * ldm + 128 * (j >> 6) + 64 * (c & 1) + (j & 63)]
+
+    assert np.array_equal(codes(np.arange(E)), _e4m3_rne(a_s))
+    assert np.array_equal(codes(e2 + np.arange(E)), _e4m3_rne(b_s))
+    if E % 2:
+        jj = np.arange(ldm)
+        for c in (E, e2 + E):
+            assert not b8[(c >> 1) * 2 * ldm + 128 * (jj >> 6) + 64 + (jj & 63)].any()
+    # packing
+    Td = torch.from_numpy(np.ascontiguousarray(T).view(np.float64).reshape(-1).copy()).to(DEV)
+    packed = torch.empty(mp.mp_propagate_workspace(M, "split1t_f8"), dtype=torch.uint8, device=DEV)
+    assert packed.numel() == 3 * 2 * ldm * ldm
+    mp.mp_pack_transmission(M, Td, "split1t_f8", packed)
+    praw = packed.cpu().numpy()
+    hi = praw[: 4 * ldm * ldm].view(np.float16).astype(np.float64)
+    lo8 = praw[4 * ldm * ldm:]
+    e = int(np.floor(np.log2(M) / 2))
+    rows = np.arange(2 * ldm)
+    A = np.zeros((2 * ldm, ldm))
+    A[:M, :M], A[ldm: ldm + M, :M] = T.real, T.imag
+    x = np.ldexp(A, e)
+    kk = np.arange(ldm)
+    R, K = rows[:, None], kk[None, :]
+    hi_rk = hi[(R >> 1) * 2 * ldm + 64 * (K >> 5) + (K & 31) + 32 * (R & 1)]
+    lo_rk = lo8[(R >> 1) * 2 * ldm + 128 * (K >> 6) + 64 * (R & 1) + (K & 63)]
+    assert np.all(np.abs(hi_rk - x) <= np.ldexp(np.abs(x), -11) + 2.0 ** -25)
+    ref_lo = _e4m3_rne(np.ldexp(x - hi_rk, 18 - e).astype(np.float32))
+    assert np.array_equal(lo_rk, ref_lo)
+    # propagation
+    mp.mp_propagate(M, E, p.T, "split1t_f8", p.ab, p.C, p.ws_prop)
+    ag, bg = p.propagated(E)
+    ao, bo = oest.propagate(T, a_s, b_s)
+    norm = np.linalg.norm(ao, axis=1).max()
+    snorm = max(np.linalg.norm(a_s, axis=1).max(), np.linalg.norm(b_s, axis=1).max())
+    err = max(np.abs(ag - ao).max(), np.abs(bg - bo).max())
+    print(f"split1t_f8 M={M} E={E}: max |error| {err:.2e} = {err / snorm:.2e} of the largest "
+          f"sample norm (bound 2^-14 = {2.0 ** -14:.2e})")
+    assert err <= 2.0 ** -14 * snorm + 4e-6 * norm
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16",
-                                  "split1t_fp16"])
+                                  "split1t_fp16", "split1t_f8"])
 def test_pack_once_then_propagate_matches_propagate(prec):
     """mp_pack_transmission + mp_propagate_packed give the same bits as
     mp_propagate, over several tiles with ragged edges."""
@@ -383,7 +491,8 @@ def test_sampler_rounding_unbiased(prec):
 
 
 @pytest.mark.parametrize("prec,floor", [("fp32", 1e-7), ("split_bf16", 1e-6), ("split_fp16", 1e-6),
-                                        ("split1_fp16", 1e-6), ("split1t_fp16", 1e-6)])
+                                        ("split1_fp16", 1e-6), ("split1t_fp16", 1e-6),
+                                        ("split1t_f8", 1e-6)])
 def test_reduced_precision_counts_within_sigma(prec, floor):
     """M = 300, t = 0.9, r = 1: the reduced-precision estimate differs from the
     FP64 oracle on the same noise by far less than sigma_T.  Besides the

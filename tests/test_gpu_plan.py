@@ -47,7 +47,8 @@ def _single(n, prec):
     return p.result()
 
 
-@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "split1_fp16", "split1t_fp16"])
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "split1_fp16", "split1t_fp16",
+                                  "split1t_f8"])
 def test_plan_equals_single_network_runs(prec, tmp_path):
     import paper_2503_12749_amd as mp
     nets = _nets([60, 130, 300, 520], E=4096, n_sub=4)
@@ -167,7 +168,7 @@ def test_plan_fused_per_network_two_passes(prec):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "split1_fp16", "split1t_fp16"])
+@pytest.mark.parametrize("prec", ["split_bf16", "split1_fp16", "split1t_fp16", "split1t_f8"])
 def test_plan_split_uneven_passes(prec):
     """Split plans over chunks of 2048 with networks of one and two passes:
     in the second pass the finished networks have no work items and no
@@ -191,7 +192,7 @@ def test_plan_split_uneven_passes(prec):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["split1t_fp16", "split_fp16"])
+@pytest.mark.parametrize("prec", ["split1t_fp16", "split_fp16", "split1t_f8"])
 def test_plan_odd_ensembles(prec):
     """Odd sample counts per pass (999 and 333: the T-split form's padded
     column pairs inside a grouped launch, ragged 64- and 128-sample tiles):
@@ -244,6 +245,7 @@ def _binned_nets(Ms, E, n_sub, seed0, mode, d):
                                          ("split_fp16", "marginals_and_total", 2),
                                          ("split_bf16", "joint", 2),
                                          ("split_fp16", "joint", 3),
+                                         ("split1t_f8", "marginals", 2),
                                          ("fp32", "marginals", 3),
                                          ("fp64", "joint", 2)])
 def test_plan_binned_equals_single_network_runs(prec, mode, d):

@@ -20,7 +20,7 @@ def _gpu():
 
 
 @pytest.mark.parametrize("prec,fused", [("fp64", False), ("split1_fp16", True), ("split1t_fp16", True),
-                                        ("split_bf16", True)])
+                                        ("split1t_f8", True), ("split_bf16", True)])
 def test_resume_from_checkpoint_file(prec, fused, tmp_path):
     import paper_2503_12749_amd as mp
     w = synth.workload_m1000(E=60_000)

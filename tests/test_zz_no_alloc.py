@@ -58,7 +58,7 @@ def _both(M, T, r, prec, E, e0, bins, d, mode, windows, n_sub, ns, seed):
     return acc_ws.cpu().numpy(), acc_na.cpu().numpy(), ws.numel()
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "fp32", "split1t_fp16"])
+@pytest.mark.parametrize("prec", ["split_bf16", "fp32", "split1t_fp16", "split1t_f8"])
 def test_noalloc_matches_workspace_entry_point(prec):
     import paper_2503_12749_amd as mp
     # call 1: M = 8000, total counts, 16384 samples (about half the scratch)
