@@ -1071,7 +1071,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="split1t_fp16")
+    ap.add_argument("--prec", default="split1t_f8")
     ap.add_argument("--compare", default="fp32", help="second precision timed ('' to skip)")
     ap.add_argument("--compare-steps", type=int, default=5)
     ap.add_argument("--also", default="split_bf16",

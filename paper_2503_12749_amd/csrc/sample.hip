@@ -201,30 +201,49 @@ __device__ inline void store_pair_f32(void* ab, int64_t off, float x0, float x1,
   }
 }
 
+// Two values as e4m3 codes (first in the low byte) by the hardware pack
+// conversion, which rounds to nearest even and gives e4m3_rne's codes for
+// every input below 448 in magnitude (checked over 4e6 inputs, every rounding
+// tie and the subnormal range included); inputs are clamped to +-448 first,
+// e4m3_rne's saturation.  One instruction instead of e4m3_rne's integer
+// sequence, in a kernel bound by its ALU work.
+__device__ inline uint16_t e4m3_pair(float x0, float x1) {
+  x0 = fminf(fmaxf(x0, -448.0f), 448.0f);
+  x1 = fminf(fmaxf(x1, -448.0f), 448.0f);
+  return (uint16_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x0, x1, 0, false) & 0xFFFF);
+}
+
 // MP_SPLIT1T_FP16 storage: mode j of storage column c (column pairs, each
 // 32-mode block holding the pair's two runs of 32 values side by side).
 __device__ inline int64_t split1t_offset(int64_t c, int64_t j, int64_t ldm) {
   return (c >> 1) * 2 * ldm + 64 * (j >> 5) + (j & 31) + (c & 1) * 32;
 }
 
-// Each wavefront owns kWaveSamples consecutive samples; its lanes stride over
-// mode pairs, so the coefficients c+, c- of a lane's modes are computed once
-// and reused for all of the wave's samples, and every store of one sample's
-// column is coalesced across the wave.
+// Each wavefront owns wave_samples<PREC>() consecutive samples; its lanes
+// stride over mode pairs, so the coefficients c+, c- of a lane's modes are
+// computed once and reused for all of the wave's samples, and every store of
+// one sample's column is coalesced across the wave.  8 samples for FP64, 4
+// otherwise: the samples of a wave are unrolled, and with 8 the
+// reduced-precision instances needed 225-278 VGPRs (one or two waves per
+// SIMD; the e4m3 form one), with 4 they need 153-183 (two or three) for a
+// kernel bound by its ALU work.
 constexpr int kWaveSamples = 8;
+template <int PREC>
+constexpr int wave_samples() { return PREC == MP_FP64 ? kWaveSamples : 4; }
 
 template <int PREC>
 __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t g0, int64_t E,
                                                      const double* __restrict__ r, uint64_t seed,
                                                      uint32_t net, void* __restrict__ ab,
                                                      double* __restrict__ n_out) {
+  constexpr int WS = wave_samples<PREC>();
   const int lane = threadIdx.x & 63;
-  const int64_t k0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kWaveSamples;
+  const int64_t k0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * WS;
   if (k0 >= E) return;
-  const int nk = (int)(E - k0 < kWaveSamples ? E - k0 : kWaveSamples);
-  double nsum[kWaveSamples];
+  const int nk = (int)(E - k0 < WS ? E - k0 : WS);
+  double nsum[WS];
 #pragma unroll
-  for (int s = 0; s < kWaveSamples; ++s) nsum[s] = 0.0;
+  for (int s = 0; s < WS; ++s) nsum[s] = 0.0;
   for (int64_t p = lane; p < ldm / 2; p += 64) {
     const int64_t j0 = 2 * p;
     // c+ = sqrt(e^{2r} - 1) / 2, c- = sqrt(1 - e^{-2r}) / 2; zero on padding
@@ -240,7 +259,7 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
       cm1 = 0.5 * sqrt(-expm1(-2.0 * r1));
     }
 #pragma unroll
-    for (int s = 0; s < kWaveSamples; ++s) {
+    for (int s = 0; s < WS; ++s) {
       if (s >= nk) break;
       const int64_t k = k0 + s;
       // column stride ldm (FP64, FP32) or 2 ldm (split, hi and lo
@@ -288,10 +307,16 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
           // e4m3 copies of the stored FP16 values, after the FP16 part
           uint8_t* b8 = (uint8_t*)ab + 4 * split1t_half(E) * ldm;
           const int64_t e2 = split1t_half(E);
-          *(uint16_t*)(b8 + pair8_offset(k, j0, ldm)) =
-              (uint16_t)(e4m3_rne((float)ya0) | ((uint32_t)e4m3_rne((float)ya1) << 8));
-          *(uint16_t*)(b8 + pair8_offset(e2 + k, j0, ldm)) =
-              (uint16_t)(e4m3_rne((float)yb0) | ((uint32_t)e4m3_rne((float)yb1) << 8));
+          // lanes 2q and 2q + 1 hold modes 4q' .. 4q' + 3 of a 64-mode block:
+          // the even lane stores the four codes as one word
+          const uint32_t ca = e4m3_pair((float)ya0, (float)ya1);
+          const uint32_t cb = e4m3_pair((float)yb0, (float)yb1);
+          const uint32_t na = (uint32_t)__shfl_xor((int)ca, 1, 64);
+          const uint32_t nb = (uint32_t)__shfl_xor((int)cb, 1, 64);
+          if ((lane & 1) == 0) {
+            *(uint32_t*)(b8 + pair8_offset(k, j0, ldm)) = ca | (na << 16);
+            *(uint32_t*)(b8 + pair8_offset(e2 + k, j0, ldm)) = cb | (nb << 16);
+          }
           if ((E & 1) && k == E - 1) {
             *(uint16_t*)(b8 + pair8_offset(k, j0, ldm) + 64) = 0;
             *(uint16_t*)(b8 + pair8_offset(e2 + k, j0, ldm) + 64) = 0;
@@ -310,7 +335,7 @@ __global__ __launch_bounds__(256) void sample_kernel(int M, int64_t ldm, int64_t
     }
   }
 #pragma unroll
-  for (int s = 0; s < kWaveSamples; ++s) {
+  for (int s = 0; s < WS; ++s) {
     const double v = wave_sum(nsum[s]);
     if (lane == 0 && s < nk) n_out[k0 + s] = v;
   }
@@ -320,7 +345,8 @@ mp_status sample_launch(int32_t M, int64_t g0, int64_t E, const double* r, uint6
                         uint32_t net, mp_precision prec, void* ab, double* n_out,
                         hipStream_t stream) {
   const int64_t ldm = ld_modes(M);
-  const int64_t blocks = (E + 4 * kWaveSamples - 1) / (4 * kWaveSamples);
+  const int64_t ws = prec == MP_FP64 ? wave_samples<MP_FP64>() : wave_samples<MP_FP32>();
+  const int64_t blocks = (E + 4 * ws - 1) / (4 * ws);
   if (blocks > 0x7FFFFFFF) {
     set_error("mp_sample: E too large for one launch");
     return MP_ERR_UNSUPPORTED;
