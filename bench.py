@@ -54,11 +54,11 @@ HBM_PEAK_GBS = 8000.0
 # (fetch x2, write x1); valid only for the GEMM source they were taken from.
 # Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
 TRAFFIC = {
-    ("split1t_fp16", True): {"source_sha256_16": "9f7e172132c8e725",
-                             "fetch_bytes": 4.079e7 * 1024 * 2, "write_bytes": 1.29e5 * 1024},
-    ("split_bf16", True): {"source_sha256_16": "9f7e172132c8e725",
-                           "fetch_bytes": 5.009e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("fp32", True): {"source_sha256_16": "9f7e172132c8e725",
+    ("split1t_f8", True): {"source_sha256_16": "4d57559857de40bc",
+                           "fetch_bytes": 3.681e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("split_bf16", True): {"source_sha256_16": "4d57559857de40bc",
+                           "fetch_bytes": 4.931e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("fp32", True): {"source_sha256_16": "4d57559857de40bc",
                      "fetch_bytes": 4.903e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
 }
 
