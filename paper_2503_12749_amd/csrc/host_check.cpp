@@ -32,7 +32,7 @@ static void* P(uintptr_t v) { return (void*)v; }  // fake aligned device pointer
 static void sizes() {
   EXPECT(mp_ld_modes(1) == 128 && mp_ld_modes(8000) == 8064 && mp_ld_modes(0) == -1);
   const mp_precision precs[] = {MP_FP64, MP_FP32, MP_SPLIT_BF16, MP_SPLIT_FP16, MP_SPLIT1_FP16,
-                                MP_SPLIT1T_FP16};
+                                MP_SPLIT1T_FP16, MP_SPLIT1T_F8};
   for (mp_precision p : precs) {
     EXPECT(mp_ab_bytes(16, 10, p) > 0 && mp_c_bytes(16, 10, p) > 0);
     EXPECT(mp_propagate_workspace(8000, p) > 0);
@@ -44,6 +44,12 @@ static void sizes() {
   // T-split samples: one FP16 value, columns rounded up to even per half
   EXPECT(mp_ab_bytes(16, 10, MP_SPLIT1T_FP16) == 128u * 20 * 2);
   EXPECT(mp_ab_bytes(16, 11, MP_SPLIT1T_FP16) == 128u * 24 * 2);
+  // FP8-correction form: the T-split operand plus one e4m3 byte per entry; T as
+  // FP16 plus its e4m3 remainder
+  EXPECT(mp_ab_bytes(16, 10, MP_SPLIT1T_F8) == 128u * 20 * 3);
+  EXPECT(mp_ab_bytes(16, 11, MP_SPLIT1T_F8) == 128u * 24 * 3);
+  EXPECT(mp_propagate_workspace(8000, MP_SPLIT1T_F8) == 2u * 8064 * 8064 * 3);
+  EXPECT(mp_ab_bytes(16, 10, (mp_precision)(MP_SPLIT1T_F8 + 1)) == 0);
   const int32_t K1[] = {128}, K3[] = {8, 9, 10}, K4[] = {4, 5, 6, 7}, K5[] = {4, 4, 4, 4, 4};
   EXPECT(mp_acc_entries(1, MP_JOINT, K1) == 128);
   EXPECT(mp_acc_entries(3, MP_JOINT, K3) == 720);

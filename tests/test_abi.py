@@ -38,6 +38,10 @@ def test_sizes():
     assert mp.mp_ld_modes(0) == -1
     assert mp.mp_ab_bytes(16, 10, "fp64") == 128 * 20 * 8
     assert mp.mp_ab_bytes(16, 10, "split_bf16") == 128 * 20 * 4
+    # the pair-column forms: E rounded up to even per half; FP16 (+ e4m3 copy)
+    assert mp.mp_ab_bytes(16, 11, "split1t_fp16") == 128 * 24 * 2
+    assert mp.mp_ab_bytes(16, 11, "split1t_f8") == 128 * 24 * 3
+    assert mp.mp_propagate_workspace(16, "split1t_f8") == 256 * 128 * 3
     assert mp.mp_c_bytes(16, 10, "fp32") == 256 * 20 * 4
     assert mp.mp_c_bytes(16, 0, "fp32") == 0
     assert mp.mp_propagate_workspace(16, "fp64") == 256 * 128 * 8
