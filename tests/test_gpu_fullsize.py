@@ -251,3 +251,49 @@ def test_m8192_row_stride_without_prefetch(prec):
     (Pf, _, sf), (Pu, _, su) = out
     assert abs(Pf.sum() - 1) < 1e-8
     assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-7 * Pu.max()), np.abs(Pf - Pu).max()
+
+
+@pytest.mark.parametrize("prec", ["split1t_fp16", "split1t_f8"])
+def test_m8192_pair_forms_without_prefetch(prec):
+    """The two T-split forms at M = 8192, where they too run their loop
+    without the L2 prefetch (same network and ragged chunk as above).
+    Sampled columns of the C-writing GEMM against the oracle propagating the
+    stored (FP16-rounded) samples through the exact network: the T-split FP16
+    form within 4e-6 of the propagated norm (the split's 2^-22 and FP32
+    accumulation), the FP8-correction form within 2^-14 of the largest sample
+    norm plus that (the bound its parity test derives); then the
+    occupation-fused run against the unfused one on the same noise."""
+    import paper_2503_12749_amd as mp
+    M, t, E, n_sub = 8192, 0.9, 600, 2
+    assert mp.mp_ld_modes(M) % 8192 == 0
+    rng = np.random.default_rng(8192)
+    j = np.arange(M)
+    T = (t / np.sqrt(M)) * np.exp(-2j * np.pi * (np.outer(j, j) % M) / M)
+    T *= np.exp(2j * np.pi * rng.random(M))[None, :]
+    r = np.full(M, 0.5)
+    win = synth.count_window(*synth.uniform_loss_moments(r, t))
+    p = mp.CountsPipeline(T, r, prec=prec, seed=31, windows=[win], n_sub=n_sub,
+                          samples_per_sub=E // n_sub, chunk=E, device="cuda:0")
+    mp.mp_sample(M, 0, E, p.r, 31, 0, prec, p.ab, p.n)
+    mp.mp_propagate(M, E, p.T, prec, p.ab, p.C, p.ws_prop)
+    a_s, b_s = p.alpha_beta(E)
+    ag, bg = p.propagated(E)
+    cols = [0, 1, 255, 256, 299, 300, 511, E - 1]
+    ao, bo = oest.propagate(T, a_s[cols], b_s[cols])
+    norm = np.linalg.norm(ao, axis=1).max()
+    snorm = max(np.linalg.norm(a_s[cols], axis=1).max(), np.linalg.norm(b_s[cols], axis=1).max())
+    err = max(np.abs(ag[cols] - ao).max(), np.abs(bg[cols] - bo).max())
+    bound = 4e-6 * norm + (2.0 ** -14 * snorm if prec == "split1t_f8" else 0.0)
+    print(f"{prec} M=8192: worst sampled column error {err:.2e} (bound {bound:.2e})")
+    assert err <= bound
+    _release(p)
+    out = []
+    for fused in (True, False):
+        q = mp.CountsPipeline(T, r, prec=prec, seed=31, windows=[win], n_sub=n_sub,
+                              samples_per_sub=E // n_sub, chunk=E, device="cuda:0", fused=fused)
+        q.run()
+        out.append(q.result())
+        _release(q)
+    (Pf, _, sf), (Pu, _, su) = out
+    assert abs(Pf.sum() - 1) < 1e-8
+    assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-7 * Pu.max()), np.abs(Pf - Pu).max()
