@@ -210,14 +210,17 @@ def criterion_job(mp, torch, w, prec, E_need, chunk, ns, fused):
     return secs, E, float(sig.max() / P.max())
 
 
-def sustained_fp16_tflops(mp, torch):
-    """TFLOP/s of the library's FP16 matrix-core probe (back-to-back
-    v_mfma_f32_32x32x16_f16, no memory traffic) over about 50 ms."""
+def sustained_fp16_tflops(mp, torch, kind=0):
+    """Executed TFLOP/s of the library's matrix-core probe with no memory
+    traffic over about 50 ms: kind 0 back-to-back v_mfma_f32_32x32x16_f16,
+    kind 3 the FP8-correction GEMM's mix (four of those and one FP8 MFMA per
+    chain and round)."""
+    iters = 200000 if kind == 0 else 80000
     sink = torch.empty(512 * 256, dtype=torch.float64, device="cuda:0")
-    mp.mp_mfma_sustained(0, 1000, sink)
+    mp.mp_mfma_sustained(kind, 1000, sink)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    flops = mp.mp_mfma_sustained(0, 200000, sink)
+    flops = mp.mp_mfma_sustained(kind, iters, sink)
     b.record()
     torch.cuda.synchronize()
     return flops / (a.elapsed_time(b) * 1e-3) / 1e12
@@ -316,6 +319,12 @@ def run_m8000(args, mp, torch, synth):
             sust = sustained_fp16_tflops(mp, torch)
             roof["sustained_fp16_mfma_tflops_measured"] = round(sust, 1)
             roof["executed_frac_of_sustained"] = round(PRODUCTS[args.prec] * achieved / sust, 4)
+        if args.prec == "split1t_f8":
+            # the same probe running this kernel's own instruction mix: its
+            # product of depth 64 is half of the mix's executed flops
+            mix = sustained_fp16_tflops(mp, torch, kind=3)
+            roof["sustained_f16_f8_mix_tflops_measured"] = round(mix, 1)
+            roof["frac_of_sustained_mix"] = round(achieved / (0.5 * mix), 4)
     out = {
         "metric": METRIC,
         "value": main_r["value"],
@@ -1033,9 +1042,15 @@ def run_mfma_peak(args, mp, torch, synth):
     out = {}
     # about 50 ms per launch, the length of one GEMM of the benchmark (the
     # clock settles under load within milliseconds)
+    # kind 3: 4 FP16 MFMAs and one e4m3 32x32x64 MFMA per chain and round, the
+    # FP8-correction GEMM's mix; its peak when each instruction ran at its
+    # published rate: (4 x 32768 + 131072) flops in 4 x 32768 / 2500 +
+    # 131072 / 5000 TFLOP/s-time units
+    mix_peak = (4 * 32768 + 131072) / (4 * 32768 / 2500.0 + 131072 / 5000.0)
     for kind, name, peak, iters in ((0, "fp16 32x32x16", 2500.0, 200000),
                                     (1, "fp32 32x32x2", 157.3, 100000),
-                                    (2, "fp64 16x16x4", 78.6, 50000)):
+                                    (2, "fp64 16x16x4", 78.6, 50000),
+                                    (3, "fp16 x4 + fp8 32x32x64", mix_peak, 80000)):
         mp.mp_mfma_sustained(kind, 100, sink)  # first launch
         best = None
         for _ in range(3):

@@ -465,12 +465,16 @@ mp_status mp_check_finite(const double* x, int64_t n, int64_t* scratch, int64_t*
  * chains for FP16 and FP32, 32 for FP64: 256 accumulator registers, as in the
  * GEMMs) on register-resident operands, with no memory traffic in the loop.
  *   kind   0: v_mfma_f32_32x32x16_f16, 1: v_mfma_f32_32x32x2f32,
- *          2: v_mfma_f64_16x16x4f64; other values MP_ERR_ARG
+ *          2: v_mfma_f64_16x16x4f64, 3: per chain and round four
+ *          v_mfma_f32_32x32x16_f16 and one v_mfma_scale_f32_32x32x64_f8f6f4
+ *          on e4m3 operands (the MP_SPLIT1T_F8 GEMM's mix per 64-deep
+ *          block); other values MP_ERR_ARG
  *   iters  >= 1
  *   sink   device FP64, one value per thread (256 per compute unit), caller-
  *          owned and overwritten (keeps the products live); smaller:
  *          MP_ERR_WORKSPACE
- *   flops  host, may be NULL: the launch's MFMA flop count
+ *   flops  host, may be NULL: the launch's MFMA flop count (kind 3: the
+ *          flops of both instructions, 262144 per chain and round)
  * Asynchronous on `stream`; time it with events on that stream.  Not part of
  * the estimator: it measures the ceiling the GEMMs run against (the clock the
  * part holds under a pure matrix load).

@@ -12,18 +12,21 @@ namespace mp {
 typedef __attribute__((ext_vector_type(16))) float burn_f32x16;
 typedef __attribute__((ext_vector_type(4))) double burn_f64x4;
 typedef __attribute__((ext_vector_type(8))) _Float16 burn_f16x8;
+typedef __attribute__((ext_vector_type(8))) int burn_i32x8;
 
 // Independent accumulators per wave: 16 of 16 registers (FP16, FP32) or 32 of
 // 8 (FP64), 256 accumulator registers either way, as in the GEMMs.
 template <int KIND>
 constexpr int burn_chains() { return KIND == 2 ? 32 : 16; }
 
-// Flops of one MFMA of each kind.
+// Flops per chain and round of each kind (one MFMA; kind 3: four FP16 MFMAs
+// and one FP8 MFMA, the FP8-correction GEMM's mix per 64-deep block).
 static double burn_flops(int kind) {
   switch (kind) {
     case 0: return 2.0 * 32 * 32 * 16;  // v_mfma_f32_32x32x16_f16
     case 1: return 2.0 * 32 * 32 * 2;   // v_mfma_f32_32x32x2f32
-    default: return 2.0 * 16 * 16 * 4;  // v_mfma_f64_16x16x4f64
+    case 2: return 2.0 * 16 * 16 * 4;   // v_mfma_f64_16x16x4f64
+    default: return 4 * 2.0 * 32 * 32 * 16 + 2.0 * 32 * 32 * 64;
   }
 }
 
@@ -50,6 +53,36 @@ __global__ __launch_bounds__(256, 1) void mfma_burn(int64_t iters, double* __res
 #pragma unroll
       for (int c = 0; c < burn_chains<KIND>(); ++c)
         acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < burn_chains<KIND>(); ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out += acc[c][r];
+  } else if constexpr (KIND == 3) {
+    burn_f16x8 a, b;
+    burn_i32x8 a8, b8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = (_Float16)(x + 0.125f * e);
+      b[e] = (_Float16)(y - 0.0625f * e);
+      a8[e] = 0x38383838 + (t & 3);         // e4m3 codes near 1
+      b8[e] = 0x30303030 + ((t >> 2) & 3);  // near 1/2
+    }
+    burn_f32x16 acc[burn_chains<KIND>()];
+#pragma unroll
+    for (int c = 0; c < burn_chains<KIND>(); ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < burn_chains<KIND>(); ++c)
+          acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < burn_chains<KIND>(); ++c)
+        acc[c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[c], 0, 0, 0, 127, 0,
+                                                                 127);
     }
 #pragma unroll
     for (int c = 0; c < burn_chains<KIND>(); ++c)
@@ -103,7 +136,7 @@ extern "C" {
 mp_status mp_mfma_sustained(int32_t kind, int64_t iters, double* sink, size_t sink_bytes,
                             double* flops, void* stream) {
   clear_error();
-  MP_CHECK_ARG(kind >= 0 && kind <= 2, MP_ERR_ARG, "mp_mfma_sustained: kind %d not in [0, 2]",
+  MP_CHECK_ARG(kind >= 0 && kind <= 3, MP_ERR_ARG, "mp_mfma_sustained: kind %d not in [0, 3]",
                kind);
   MP_CHECK_ARG(iters >= 1, MP_ERR_ARG, "mp_mfma_sustained: iters must be >= 1");
   MP_CHECK_ARG(sink, MP_ERR_ARG, "mp_mfma_sustained: null sink");
@@ -120,7 +153,8 @@ mp_status mp_mfma_sustained(int32_t kind, int64_t iters, double* sink, size_t si
   switch (kind) {
     case 0: hipLaunchKernelGGL(mfma_burn<0>, dim3(cus), dim3(256), 0, s, iters, sink); break;
     case 1: hipLaunchKernelGGL(mfma_burn<1>, dim3(cus), dim3(256), 0, s, iters, sink); break;
-    default: hipLaunchKernelGGL(mfma_burn<2>, dim3(cus), dim3(256), 0, s, iters, sink); break;
+    case 2: hipLaunchKernelGGL(mfma_burn<2>, dim3(cus), dim3(256), 0, s, iters, sink); break;
+    default: hipLaunchKernelGGL(mfma_burn<3>, dim3(cus), dim3(256), 0, s, iters, sink); break;
   }
   MP_HIP_LAUNCH_CHECK("mp_mfma_sustained launch");
   const int chains = kind == 2 ? burn_chains<2>() : burn_chains<0>();

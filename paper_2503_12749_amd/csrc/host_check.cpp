@@ -206,7 +206,8 @@ static void validation() {
   EXPECT(mp_plan_launch(nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_info(nullptr, nullptr, nullptr, nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_tile(nullptr, 0, nullptr, nullptr) == MP_ERR_ARG);
-  EXPECT(mp_mfma_sustained(3, 10, (double*)P(256), 1 << 20, nullptr, nullptr) == MP_ERR_ARG);
+  EXPECT(mp_mfma_sustained(4, 10, (double*)P(256), 1 << 20, nullptr, nullptr) == MP_ERR_ARG);
+  EXPECT(mp_mfma_sustained(-1, 10, (double*)P(256), 1 << 20, nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_mfma_sustained(0, 0, (double*)P(256), 1 << 20, nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_mfma_sustained(1, 10, nullptr, 1 << 20, nullptr, nullptr) == MP_ERR_ARG);
   EXPECT(mp_plan_destroy(nullptr) == MP_OK);
