@@ -141,7 +141,12 @@ size_t mp_c_bytes(int32_t M, int64_t E, mp_precision prec);
  *          (OCP FP8: 4 exponent bits, bias 7, 3 mantissa bits, round to
  *          nearest even): mode j of storage column c at byte (c / 2) 2 ldm +
  *          128 (j / 64) + 64 (c % 2) + j % 64 of that second part (for each
- *          64-mode block, the pair's two 64-byte runs side by side).
+ *          64-mode block, the pair's two 64-byte runs side by side).  The
+ *          copies saturate at 448: an amplitude beyond it (possible only
+ *          for squeezing r above about 4.6, where the largest amplitude a
+ *          Box-Muller pair can give, 8.6 (c+ + c-) ~ 4.3 e^r, reaches 448)
+ *          keeps its FP16 value in the main product and enters the
+ *          correction term, 2^-11 of that product, as 448.
  *   n_out  device FP64[E]: n = sum_j alpha_j beta_j of the values as stored
  *          (after rounding to `prec`).
  */
