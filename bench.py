@@ -48,6 +48,14 @@ DTYPES = {"split_bf16": "split-bf16 (fp32 acc)", "split_fp16": "split-fp16 (fp32
           "split1t_f8": "fp16 x fp16 + e4m3 x e4m3 correction (fp32 acc)", "fp32": "fp32",
           "fp64": "f64"}
 HBM_PEAK_GBS = 8000.0
+# the GEMM kernel each precision runs: occupation-fused, C-writing
+GEMM_KERNELS = {"split1t_f8": ("gemm_split1t8_occ", "gemm_split1t8_pp"),
+                "split1t_fp16": ("gemm_split1t_occ", "gemm_split1t_pp"),
+                "split1_fp16": ("gemm_split1_occ", "gemm_split1_pp"),
+                "split_bf16": ("gemm_split_occ<bf16>", "gemm_split_256_pp<bf16>"),
+                "split_fp16": ("gemm_split_occ<f16>", "gemm_split_256_pp<f16>"),
+                "fp32": ("gemm_f32_pp<true>", "gemm_f32_pp<false>"),
+                "fp64": ("gemm_f64_pp", "gemm_f64_pp")}
 
 # FETCH_SIZE / WRITE_SIZE of the GEMM kernel at this workload (rocprofv3 --pmc,
 # one counter per run, per dispatch), scaled by the factors a 1 GiB copy gives
@@ -306,9 +314,10 @@ def run_m8000(args, mp, torch, synth):
             "traffic": (gemm_traffic_gb(args.prec, not args.unfused)
                         if w.M == 8000 and args.chunk == 65536 else None),
             "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, calibrated on a 1 GiB copy)",
-            "kernel": (f"gemm_{args.prec} with the occupation epilogue (mp_propagate_counts; the "
-                       f"timed call includes the counting kernels)" if not args.unfused
-                       else f"gemm_{args.prec} (mp_propagate_packed)"),
+            "kernel": (f"{GEMM_KERNELS[args.prec][0]} (mp_propagate_counts: the GEMM with the "
+                       f"occupation epilogue; the timed call includes the counting kernels)"
+                       if not args.unfused
+                       else f"{GEMM_KERNELS[args.prec][1]} (mp_propagate_packed)"),
             "algorithmic_flops_per_launch": flops}
     if args.prec in PRODUCTS:
         roof["executed_mfma_frac"] = round(PRODUCTS[args.prec] * achieved / peak, 4)
