@@ -91,7 +91,8 @@ def _run_joint(fused, prec, est, d, M=333, E=1000, n_sub=5, chunk=384, seed=73, 
 
 @pytest.mark.parametrize("prec,est,d", [("fp32", "matrix_p", 2), ("split_bf16", "matrix_p", 2),
                                         ("fp32", "plus_p", 2), ("fp32", "matrix_p", 3),
-                                        ("split_bf16", "matrix_p", 3)])
+                                        ("split_bf16", "matrix_p", 3), ("split1t_f8", "matrix_p", 2),
+                                        ("split1t_f8", "matrix_p", 3)])
 def test_fused_joint_equals_unfused(prec, est, d):
     """Joint distributions of two and three bins through mp_propagate_counts:
     the bin sums come from the GEMM's partials instead of C, the rest of the
