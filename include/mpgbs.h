@@ -242,6 +242,15 @@ size_t mp_binned_workspace(int32_t d, mp_bin_mode mode, const int32_t* K, int64_
  * over a chunk's samples of one sub-ensemble, FP64 across chunks) or with
  * FP64 FMAs (FP64 path).  acc is the full grid [s][k_1]..[k_d]; entries
  * outside the boxes stay zero.
+ *
+ * Non-finite samples: a sample whose n or bin sums are NaN or infinite (an
+ * amplitude beyond a reduced precision's range, e.g. FP16 samples at
+ * squeezing r above about 9.6) is not dropped by the e^-46 skip or the boxes:
+ * it turns the accumulators it reaches NaN (every grid point of its
+ * sub-ensemble's distributions), so mp_check_finite on P or acc reports
+ * MP_ERR_NONFINITE rather than a finite estimate without it.  The same holds
+ * for mp_propagate_counts, mp_moments_accumulate (NaN sums) and
+ * mp_observable_histogram (the top, not-finite bin).
  */
 mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
                            mp_precision prec, mp_estimator est, int32_t d,

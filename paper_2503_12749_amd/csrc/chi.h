@@ -19,6 +19,19 @@ constexpr double kLogEps = -46.0;
 // at a time, lanes over modes).
 constexpr int kOccPerWave = 16;
 
+// Log-weights of a sample's two parity terms (matrix-P estimator),
+// c1 = log(e^n / (2 cosh n)) and c2 = log(e^-n / (2 cosh n)), in forms that
+// cannot overflow.  `finite` is false when n or one of the sample's bin sums
+// is not finite (an amplitude beyond a reduced precision's range): both
+// weights are then NaN, so the sample reaches the FP64 accumulators, and
+// mp_check_finite, as NaN instead of reading as a sample of very large |n|.
+__device__ inline void parity_log_weights(double n, bool finite, double& c1, double& c2) {
+  const double L = log1p(exp(-2.0 * fabs(n)));
+  c1 = (n >= 0.0 ? 0.0 : 2.0 * n) - L;
+  c2 = (n >= 0.0 ? -2.0 * n : 0.0) - L;
+  if (!finite) c1 = c2 = __builtin_nan("");
+}
+
 // One sample's partial n'_j sums over a mode range, wave-reduced.
 template <typename CT>
 __device__ inline void run_sum(const CT* __restrict__ ca, const CT* __restrict__ cb, int64_t ldm,
@@ -105,8 +118,11 @@ __device__ inline double fmax_exponent(double R, double I) {
 // where it reaches the threshold); -1 when no point reaches it.
 __device__ inline int band_halfwidth(double R, double I, double offset, int K) {
   const double fmax = fmax_exponent(R, I);
-  if (fmax + offset < kLogEps) return -1;
   const int half = K / 2;
+  // a sample that is not finite takes the whole axis, so its NaN reaches every
+  // point of the sums (and no index is formed from it)
+  if (!isfinite(fmax + offset)) return half;
+  if (fmax + offset < kLogEps) return -1;
   if (R <= 0.0) return half;
   constexpr double kTwoPi = 6.283185307179586476925286766559;
   auto f = [&](int k) {

@@ -182,14 +182,15 @@ __global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, Sr
     if (lane == 0) {
       for (int q = 0; q < p.n_dist; ++q) dist_occupation(p, nb, q, s_nb[i][q][0], s_nb[i][q][1]);
       const double n = nglob[k];
+      bool finite = p.est == MP_PLUS_P || isfinite(n);
+      for (int q = 0; q < p.n_dist; ++q)
+        finite = finite && isfinite(s_nb[i][q][0]) && isfinite(s_nb[i][q][1]);
       if (p.est == MP_PLUS_P) {
-        s_c1[i] = 0.0;
+        s_c1[i] = finite ? 0.0 : __builtin_nan("");
         s_c2[i] = 0.0;
         s_skip2[i] = 1;
       } else {
-        const double L = log1p(exp(-2.0 * fabs(n)));
-        s_c1[i] = (n >= 0.0 ? 0.0 : 2.0 * n) - L;
-        s_c2[i] = (n >= 0.0 ? -2.0 * n : 0.0) - L;
+        parity_log_weights(n, finite, s_c1[i], s_c2[i]);
         // |e^{-X}| <= e^{2 |n_b|}: skip the parity partner when it underflows
         double mx = 0.0;
         for (int q = 0; q < p.n_dist; ++q) {
@@ -232,9 +233,9 @@ __global__ __launch_bounds__(kCountThreads) void counts_fused(CountsParams p, Sr
         if (dq[u] < 0) continue;
         const double nr = s_nb[i][dq[u]][0], ni = s_nb[i][dq[u]][1];
         // log-magnitudes of the two terms are xr + c1 and c2 - xr; a term
-        // below e^kLogEps is skipped
+        // below e^kLogEps is skipped (a NaN one is kept: it must reach the sums)
         const double xr = cm1[u] * nr - sn[u] * ni;
-        const bool t1 = xr + c1 > kLogEps, t2 = !skip2 && c2 - xr > kLogEps;
+        const bool t1 = !(xr + c1 <= kLogEps), t2 = !skip2 && !(c2 - xr <= kLogEps);
         if (!(t1 || t2)) continue;
         const double xi = cm1[u] * ni + sn[u] * nr;
         double tr, ti;
@@ -318,7 +319,8 @@ struct Joint2Params {
 };
 
 // Per-sample record (one wave per sample, lane 0 writes): n1, n2 (complex),
-// c1, c2 (c2 = -inf for +P).  record_bands then sets the chunk's bands
+// c1, c2 (c2 = -inf for +P; both NaN for a sample that is not finite).
+// record_bands then sets the chunk's bands
 // band[0..3] = u1, u2, v1, v2 half-widths (atomic max, -1 = empty).
 // PART: the bin sums come from the occupation-fused GEMM's partials (slots in
 // run order) instead of the propagated amplitudes C.
@@ -349,12 +351,12 @@ __device__ inline void joint2_sample(const Joint2Params& p, const CT* __restrict
   }
   if (lane != 0) return;
   const double n = nglob[k];
+  const bool sums_finite = isfinite(R1) && isfinite(I1) && isfinite(R2) && isfinite(I2);
   double c1 = 0.0, c2 = -INFINITY;
-  if (p.est != MP_PLUS_P) {
-    const double L = log1p(exp(-2.0 * fabs(n)));
-    c1 = (n >= 0.0 ? 0.0 : 2.0 * n) - L;
-    c2 = (n >= 0.0 ? -2.0 * n : 0.0) - L;
-  }
+  if (p.est != MP_PLUS_P)
+    parity_log_weights(n, sums_finite && isfinite(n), c1, c2);
+  else if (!sums_finite)
+    c1 = c2 = __builtin_nan("");
   double* r = rec + k * 6;
   r[0] = R1;
   r[1] = I1;
@@ -469,12 +471,12 @@ __global__ __launch_bounds__(256) void joint2_accumulate(Joint2Params p, const d
           const double share = 0.5 * (cterm + (term == 0 ? 0.0 : 2.0 * (r[0] + r[2])));
           if (which == 0) {
             const int kk = t1 * kJT + q;
-            if (kk < K1 && cterm > -INFINITY)
+            if (kk < K1 && cterm != -INFINITY)
               factor<F64>(r[0], r[1], share - (term == 0 ? 0.0 : 2.0 * r[0]), kk, K1, p.m_lo[0],
                           sign, fr, fi);
           } else {
             const int kk = t2 * kJT + q;
-            if (kk < K2 && cterm > -INFINITY)
+            if (kk < K2 && cterm != -INFINITY)
               factor<F64>(r[2], r[3], share - (term == 0 ? 0.0 : 2.0 * r[2]), kk, K2, p.m_lo[1],
                           sign, fr, fi);
           }
@@ -1145,7 +1147,11 @@ __global__ __launch_bounds__(256) void moments_kernel(SampleStatParams p, const 
   for (int64_t g = lo + threadIdx.x; g < hi; g += 256) {
     const int64_t k = g - p.e0;
     const double zr = nq[(k * p.n_dist + q) * 2], zi = nq[(k * p.n_dist + q) * 2 + 1];
-    const double w = p.est == MP_PLUS_P ? 1.0 : tanh(n[k]);
+    double w = 1.0;  // +P
+    if (p.est != MP_PLUS_P) {
+      const double nk = n[k];
+      w = isfinite(nk) ? tanh(nk) : __builtin_nan("");
+    }
     double pr = 1.0, pi = 0.0;
 #pragma unroll
     for (int o = 0; o < MP_MAX_MOMENTS; ++o) {
@@ -1215,6 +1221,8 @@ __global__ __launch_bounds__(256) void histogram_kernel(SampleStatParams p, cons
     const double par = (p.m & 1) ? -1.0 : 1.0;
     G = exp(lr - zr + c1) * cos(lp - zi) + par * exp(lr + zr + c2) * cos(lp + zi);
   }
+  if (!isfinite(zr) || !isfinite(zi) || (p.est != MP_PLUS_P && !isfinite(n[k])))
+    G = __builtin_nan("");
   int64_t b;
   if (!(G == G) || G - G != 0.0) {
     b = p.n_bins + 1;  // not finite

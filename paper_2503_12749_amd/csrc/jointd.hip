@@ -62,7 +62,8 @@ __global__ void band_init(int* band) {
 }
 
 // Per sample (one wave, lane 0 writes): the record (Re n_b, Im n_b for b < d,
-// c1, c2; c2 = -inf for +P).  record_bands then sets the box half-widths
+// c1, c2; c2 = -inf for +P, both NaN for a sample that is not finite).
+// record_bands then sets the box half-widths
 // band[term * 4 + b] (atomic max; -1 = term absent).
 // PART: the bin sums come from the occupation-fused GEMM's partials (slots in
 // run order) instead of the propagated amplitudes C.
@@ -94,17 +95,22 @@ __device__ inline void jointd_sample(const JointDParams& p, const CT* __restrict
   }
   if (lane != 0) return;
   const double n = nglob[k];
-  const bool with_v = p.est != MP_PLUS_P;
-  const double L = log1p(exp(-2.0 * fabs(n)));
   double* r = rec + k * p.rec;
+  bool sums_finite = true;
 #pragma unroll
   for (int b = 0; b < kJD; ++b)
     if (b < p.d) {
       r[2 * b] = nr[b];
       r[2 * b + 1] = ni[b];
+      sums_finite = sums_finite && isfinite(nr[b]) && isfinite(ni[b]);
     }
-  r[2 * p.d] = with_v ? (n >= 0.0 ? 0.0 : 2.0 * n) - L : 0.0;
-  r[2 * p.d + 1] = with_v ? (n >= 0.0 ? -2.0 * n : 0.0) - L : -INFINITY;
+  double c1 = 0.0, c2 = -INFINITY;
+  if (p.est != MP_PLUS_P)
+    parity_log_weights(n, sums_finite && isfinite(n), c1, c2);
+  else if (!sums_finite)
+    c1 = c2 = __builtin_nan("");
+  r[2 * p.d] = c1;
+  r[2 * p.d + 1] = c2;
 }
 
 template <typename CT, bool PART>
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(256) void jointd_factors(JointDParams p, const doub
   const double R = r[2 * b], I = r[2 * b + 1];
   double fr = 0.0, fi = 0.0;
   const double cterm = tau == 0 ? r[2 * p.d] : r[2 * p.d + 1];
-  if (cterm > -INFINITY) {
+  if (cterm != -INFINITY) {  // NaN weights are evaluated: they must reach the sums
     double share = cterm;
     if (tau == 1)
       for (int q = 0; q < p.d; ++q) share += 2.0 * r[2 * q];
