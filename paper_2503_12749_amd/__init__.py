@@ -437,7 +437,10 @@ class PairPipeline:
 
     def result(self):
         """(G2, sigma): complex (M, M) means and sigma_T of their real parts
-        (synchronises)."""
+        (synchronises); raises MPError (MP_ERR_NONFINITE) if the means hold
+        NaN or infinite values."""
+        scratch = self.torch.empty(1, dtype=self.torch.int64, device=self.mean.device)
+        mp_check_finite(self.mean, scratch)
         m = self.mean.cpu().numpy().view(np.complex128).reshape(self.M, self.M)
         return m, self.sigma.cpu().numpy().reshape(self.M, self.M)
 
@@ -508,19 +511,26 @@ class Plan:
         _lib.check(_lib.load().mp_plan_create(ctypes.byref(h), len(nets), descs, _prec(prec),
                                               _est(est), chunk, path))
         self.handle = h
+        self.device = dev
         del keep
 
     def launch(self, stream=None):
         _lib.check(_lib.load().mp_plan_launch(self.handle, _stream(stream)))
 
     def result(self, i):
-        """(P_re, P_im, sigma) of network i as numpy arrays (synchronises)."""
+        """(P_re, P_im, sigma) of network i as numpy arrays (synchronises);
+        raises MPError (MP_ERR_NONFINITE) if the estimate holds NaN or
+        infinite values."""
         t = self.torch
         pr, pi, sg = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
         _lib.check(_lib.load().mp_plan_result(self.handle, i, ctypes.byref(pr), ctypes.byref(pi),
                                               ctypes.byref(sg)))
         t.cuda.synchronize()
         K = self.K[i]
+        scratch = t.empty(1, dtype=t.int64, device=self.device)
+        for ptr in (pr, pi):
+            _lib.check(_lib.load().mp_check_finite(ctypes.c_void_p(ptr.value), K, _ptr(scratch),
+                                                   None, None))
         out = []
         hip = _hip_runtime()
         for ptr in (pr, pi, sg):

@@ -3,9 +3,10 @@ and infinite entries on the device.  Samples whose FP16 amplitudes overflow
 (squeezing far beyond FP16's range: r = 12 gives amplitudes near 8e4 against
 FP16's 65504) make the estimate NaN on every counting path: totals, marginals,
 joint d = 2 and d = 3, both estimators, unfused and occupation-fused.  result()
-therefore raises MP_ERR_NONFINITE instead of returning a finite but wrong P(m).
-Per-sample moments and histograms carry such samples as NaN, or in the
-histogram's non-finite bin."""
+therefore raises MP_ERR_NONFINITE instead of returning a finite but wrong P(m),
+and so do a batched plan's result for that network (only) and the pair
+moments.  Per-sample moments and histograms carry such samples as NaN, or in
+the histogram's non-finite bin."""
 import ctypes
 
 import numpy as np
@@ -138,3 +139,41 @@ def test_overflowing_samples_reach_moments_and_histogram(est):
     h = hist.cpu().numpy()
     assert h.sum() == E
     assert h[-1] >= bad.sum()
+
+
+def test_plan_reports_overflow_of_one_network_only():
+    """A batched plan: the network whose FP16 amplitudes overflow raises
+    MP_ERR_NONFINITE from result(); the other network's estimate is finite."""
+    import paper_2503_12749_amd as mp
+    nets = []
+    for i, (Mi, r_big) in enumerate(((60, 1.0), (130, 12.0))):
+        r = np.ones(Mi)
+        r[:4] = r_big
+        mean, sd = synth.uniform_loss_moments(np.ones(Mi), 0.9)
+        nets.append(dict(T=synth.transmission(Mi, 0.9, 77 + i), r=r, seed=77, net=i, E=1024,
+                         n_sub=4, window=synth.count_window(mean, sd)))
+    plan = mp.Plan(nets, prec="split1t_f8")
+    plan.launch()
+    P, _, s = plan.result(0)
+    assert np.isfinite(P).all() and np.isfinite(s).all() and abs(P.sum() - 1) < 1e-6
+    with pytest.raises(mp.MPError) as e:
+        plan.result(1)
+    assert e.value.status == NONFINITE
+
+
+@pytest.mark.parametrize("r_big,raises", [(12.0, True), (1.0, False)])
+def test_pair_moments_report_overflow(r_big, raises):
+    import paper_2503_12749_amd as mp
+    Mi = 70
+    r = np.full(Mi, 0.8)
+    r[:3] = r_big
+    p = mp.PairPipeline(0.9 * synth.haar_unitary(Mi, 5), r, prec="split_fp16", seed=9, n_sub=2,
+                        samples_per_sub=256, chunk=512, device=DEV)
+    p.run()
+    if raises:
+        with pytest.raises(mp.MPError) as e:
+            p.result()
+        assert e.value.status == NONFINITE
+    else:
+        G2, s = p.result()
+        assert np.isfinite(G2).all() and np.isfinite(s).all()
