@@ -297,3 +297,31 @@ def test_m8192_pair_forms_without_prefetch(prec):
     (Pf, _, sf), (Pu, _, su) = out
     assert abs(Pf.sum() - 1) < 1e-8
     assert np.all(np.abs(Pf - Pu) <= 1e-3 * su + 1e-7 * Pu.max()), np.abs(Pf - Pu).max()
+
+
+@pytest.mark.parametrize("prec", ["split1t_f8", "split_bf16", "fp32"])
+def test_m8000_chunk_beyond_4gib(m8000, prec):
+    """One chunk of 2^19 samples at M = 8000 through the occupation-fused path:
+    the sample operand (25 GB for the default form, 34 GB for split-BF16 and
+    FP32) puts byte offsets far past 2^32 in the sampler, the GEMM's operand
+    loads and the epilogue's partials.  The accumulators equal those of the
+    same samples in eight chunks of 2^16 bit for bit: each sample keeps its
+    place within its 256-column tile, and every sub-ensemble lies inside one
+    chunk either way."""
+    import paper_2503_12749_amd as mp
+    w = m8000
+    big, small = 1 << 19, 1 << 16
+    kw = dict(prec=prec, seed=w.seed, windows=w.windows, n_sub=big // 8192,
+              samples_per_sub=8192, device="cuda:0", fused=True)
+    p1 = mp.CountsPipeline(w.T, w.r, chunk=big, **kw)
+    p1.run()
+    acc1 = p1.acc.cpu().numpy()
+    P1 = p1.result()[0]
+    del p1
+    torch.cuda.empty_cache()
+    p2 = mp.CountsPipeline(w.T, w.r, chunk=small, **kw)
+    p2.run()
+    assert np.array_equal(p2.acc.cpu().numpy(), acc1)
+    assert abs(P1.sum() - 1) < 1e-8
+    del p2
+    torch.cuda.empty_cache()
