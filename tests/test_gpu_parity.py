@@ -408,6 +408,54 @@ def test_split1t_f8_sampler_packing_and_propagation(M, E):
     assert err <= 2.0 ** -14 * snorm + 4e-6 * norm
 
 
+def test_split1t_f8_saturated_sample_copies():
+    """Squeezing r = 7 on ten modes puts about 40 % of their amplitudes above
+    448, e4m3's largest value (and far below FP16's 65504).  Their e4m3 copies
+    saturate (the nearest-even rounding with saturation, as documented), the
+    FP16 operand is unaffected, and the product stays finite: the correction
+    term, at most 2^-11 of each entry's product, only loses the excess
+    (|S| - 448)+, so by Cauchy-Schwarz over a row of T the error bound of the
+    unsaturated case grows by at most 2^-11 of the norm of those excesses."""
+    import paper_2503_12749_amd as mp
+    M, E = 300, 201
+    T = 0.95 * synth.haar_unitary(M, 13)
+    r = np.full(M, 0.8)
+    r[:10] = 7.0
+    ldm = mp.mp_ld_modes(M)
+    e2 = E + (E & 1)
+    p = _pipe(T, r, prec="split1t_f8", seed=6, windows=[(0, 64)], n_sub=1, samples_per_sub=E,
+              chunk=E)
+    mp.mp_sample(M, 0, E, p.r, p.seed, 0, "split1t_f8", p.ab, p.n)
+    a_s, b_s = p.alpha_beta(E)
+    assert np.isfinite(a_s).all() and np.isfinite(b_s).all()
+    over = (np.abs(a_s) > 448).sum() + (np.abs(b_s) > 448).sum()
+    assert over > 200
+    raw = p.ab.view(torch.uint8).cpu().numpy()
+    b8 = raw[4 * e2 * ldm:]
+    j = np.arange(M)
+
+    def codes(c):
+        c = np.asarray(c)[:, None]
+        return b8[(c >> 1) * 2 * ldm + 128 * (j >> 6) + 64 * (c & 1) + (j & 63)]
+
+    ca, cb = codes(np.arange(E)), codes(e2 + np.arange(E))
+    assert np.array_equal(ca, _e4m3_rne(a_s)) and np.array_equal(cb, _e4m3_rne(b_s))
+    assert set(np.unique(ca[np.abs(a_s) > 448] & 0x7F)) == {0x7E}
+    mp.mp_propagate(M, E, p.T, "split1t_f8", p.ab, p.C, p.ws_prop)
+    ag, bg = p.propagated(E)
+    assert np.isfinite(ag).all() and np.isfinite(bg).all()
+    ao, bo = oest.propagate(T, a_s, b_s)
+    norm = np.linalg.norm(ao, axis=1).max()
+    snorm = max(np.linalg.norm(a_s, axis=1).max(), np.linalg.norm(b_s, axis=1).max())
+    excess = max(np.linalg.norm(np.maximum(np.abs(a_s) - 448, 0), axis=1).max(),
+                 np.linalg.norm(np.maximum(np.abs(b_s) - 448, 0), axis=1).max())
+    err = max(np.abs(ag - ao).max(), np.abs(bg - bo).max())
+    bound = 2.0 ** -14 * snorm + 2.0 ** -11 * excess + 4e-6 * norm
+    print(f"saturated e4m3 copies: max |error| {err:.3e}, bound {bound:.3e} "
+          f"(excess norm {excess:.1f}, sample norm {snorm:.1f})")
+    assert err <= bound
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split_bf16", "split_fp16", "split1_fp16",
                                   "split1t_fp16", "split1t_f8"])
 def test_pack_once_then_propagate_matches_propagate(prec):
