@@ -274,8 +274,9 @@ mp_status mp_binned_counts(int32_t M, int64_t E, const void* C, const double* n,
  * and in FP64 across tiles, so results agree with the unfused path to FP32
  * rounding.
  *
- *   prec       MP_FP32, MP_SPLIT_BF16 or MP_SPLIT_FP16 (others:
- *              MP_ERR_UNSUPPORTED)
+ *   prec       MP_FP32 or any split precision (MP_SPLIT_BF16, MP_SPLIT_FP16,
+ *              MP_SPLIT1_FP16, MP_SPLIT1T_FP16, MP_SPLIT1T_F8); MP_FP64:
+ *              MP_ERR_UNSUPPORTED
  *   ab, n      as written by mp_sample for this chunk
  *   packed     device, as written by mp_pack_transmission(M, T, prec, ...),
  *              packed_bytes >= mp_propagate_workspace(M, prec), 256-aligned
@@ -292,6 +293,58 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
                               mp_bin_mode mode, const int32_t* m_lo, const int32_t* K,
                               int32_t n_sub, int64_t samples_per_sub, int64_t e0, double* acc,
                               void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * One count distribution through a bilinear form (main text: the generating
+ * function of binned counts depends on the samples only through
+ * n_S = sum_{j in S} alpha'_j beta'_j, with alpha' = T alpha and beta' = T* beta
+ * for the linear network).  For real alpha, beta this is exactly
+ *     n_S = alpha^T W beta,   W = T^T P_S T*   (P_S: the projector on S),
+ * so one complex M x M operator applied to beta replaces T applied to both
+ * alpha and beta: 4 M^2 flops per sample instead of 8 M^2.  W is formed once per
+ * network (8 M^3 FP64 flops): its off-diagonal part packed as the precision
+ * packs T, its real diagonal D_a = sum_{j in S} |T_ja|^2 in FP32 after it.  D
+ * alone sets the mean of n_S (E[alpha_a beta_b] = 0 for a != b), so it is
+ * applied exactly, as sum_a D_a alpha_a beta_a in the GEMM's epilogue; the
+ * off-diagonal part's packing rounding then only adds noise.  Only one
+ * distribution per pass (S, d = 1); marginals and joint distributions need
+ * one W per bin and stay with mp_propagate_counts.
+ *
+ * mp_pack_bilinear forms W on the FP64 matrix cores and packs it.
+ *   T            device, complex M x M as for mp_propagate
+ *   bin_of_mode  host, len M: 0 for the modes of S, -1 for the others
+ *   prec         MP_SPLIT1T_F8 (others: MP_ERR_UNSUPPORTED)
+ *   packed       device, >= mp_bilinear_packed_bytes(M) bytes, 256-aligned;
+ *                overwritten with packed W
+ *   scratch      device, >= mp_bilinear_workspace(M) bytes (about 96 M^2
+ *                bytes: 6.2 GB at M = 8000), 256-aligned; overwritten
+ *
+ * mp_propagate_counts_bilinear is mp_propagate_counts for one distribution of
+ * the set W was packed for: the FP8-correction GEMM of W against the beta half
+ * of the sample operand, its epilogue reducing sum_a alpha_a (W beta)_a over
+ * each 128-mode block to the per-sample partials, then the counting kernels.
+ *   ab, n        as written by mp_sample(..., MP_SPLIT1T_F8, ...) for this
+ *                chunk
+ *   packed       as written by mp_pack_bilinear
+ *   m_lo, K      host, one window; n_sub ... acc as for mp_binned_counts
+ *                with d = 1
+ *   workspace    device, >= mp_propagate_counts_workspace(M, E, 1, b, MP_JOINT,
+ *                K, n_sub, samples_per_sub, e0) bytes with b all zero,
+ *                256-aligned; overwritten
+ * Rounding: the T-split form's, with W in place of T (W's packing keeps each
+ * entry to about 2^-15; the samples' FP16 rounding averages like the noise).
+ */
+size_t mp_bilinear_workspace(int32_t M);
+size_t mp_bilinear_packed_bytes(int32_t M);
+mp_status mp_pack_bilinear(int32_t M, const double* T, const int32_t* bin_of_mode,
+                           mp_precision prec, void* packed, size_t packed_bytes, void* scratch,
+                           size_t scratch_bytes, void* stream);
+mp_status mp_propagate_counts_bilinear(int32_t M, int64_t E, mp_precision prec,
+                                       mp_estimator est, const void* ab, const double* n,
+                                       const void* packed, size_t packed_bytes,
+                                       const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                       int64_t samples_per_sub, int64_t e0, double* acc,
+                                       void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * mp_propagate_counts without a workspace, for callers that cannot allocate

@@ -198,6 +198,34 @@ def mp_propagate_counts(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_
         workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
+def mp_bilinear_workspace(M) -> int:
+    return int(_lib.load().mp_bilinear_workspace(M))
+
+
+def mp_bilinear_packed_bytes(M) -> int:
+    return int(_lib.load().mp_bilinear_packed_bytes(M))
+
+
+def mp_pack_bilinear(M, T, bin_of_mode, prec, packed, scratch, stream=None):
+    """W = T^T P_S T* (S: modes with bin_of_mode == 0) packed as prec packs T;
+    T is the device complex128 operand (as a float64 tensor), bin_of_mode a
+    host sequence of 0 / -1."""
+    _lib.check(_lib.load().mp_pack_bilinear(
+        M, _ptr(T), i32_array(bin_of_mode), _prec(prec), _ptr(packed),
+        packed.numel() * packed.element_size(), _ptr(scratch),
+        scratch.numel() * scratch.element_size(), _stream(stream)))
+
+
+def mp_propagate_counts_bilinear(M, E, prec, est, ab, n, packed, m_lo, K, n_sub, samples_per_sub,
+                                 e0, acc, workspace, stream=None):
+    """One distribution through the bilinear form alpha^T W beta; m_lo, K: ints."""
+    _lib.check(_lib.load().mp_propagate_counts_bilinear(
+        M, E, _prec(prec), _est(est), _ptr(ab), _ptr(n), _ptr(packed),
+        packed.numel() * packed.element_size(), i32_array([m_lo]), i32_array([K]), n_sub,
+        samples_per_sub, e0, _ptr(acc), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def mp_propagate_counts_noalloc(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K,
                                 n_sub, samples_per_sub, e0, acc, stream=None):
     """mp_propagate_counts on the library's own device scratch (no workspace
@@ -229,7 +257,7 @@ class CountsPipeline:
     def __init__(self, T: np.ndarray, r: np.ndarray, *, prec="fp64", seed: int, net: int = 0,
                  bin_of_mode=None, d: int = 1, mode="joint", windows, n_sub: int,
                  samples_per_sub: int, chunk: int, est="matrix_p", device="cuda:0",
-                 fused: bool = False):
+                 fused: bool = False, bilinear: bool = False):
         import torch
         self.torch = torch
         T = np.ascontiguousarray(T, dtype=np.complex128)
@@ -248,13 +276,20 @@ class CountsPipeline:
         self.device = dev
         self.T = torch.from_numpy(T.view(np.float64).reshape(-1).copy()).to(dev)
         self.r = torch.from_numpy(np.asarray(r, dtype=np.float64).copy()).to(dev)
-        self.fused = bool(fused)
+        self.fused = bool(fused) or bool(bilinear)
+        # one distribution through alpha^T W beta, W = T^T P_S T* formed once
+        # (mp_pack_bilinear) in place of packing T
+        self.bilinear = bool(bilinear)
+        if self.bilinear and not (self.d == 1 and self.prec == _lib.PRECISIONS["split1t_f8"]):
+            raise MPError(-4, "the bilinear form takes one distribution (d = 1) in split1t_f8")
         self.ab = torch.empty(mp_ab_bytes(self.M, self.chunk, self.prec), dtype=torch.uint8, device=dev)
         # the occupation-fused path never materialises C
         self.C = None if self.fused else torch.empty(mp_c_bytes(self.M, self.chunk, self.prec),
                                                       dtype=torch.uint8, device=dev)
         self.n = torch.empty(self.chunk, dtype=torch.float64, device=dev)
-        self.ws_prop = torch.empty(mp_propagate_workspace(self.M, self.prec), dtype=torch.uint8, device=dev)
+        pbytes = (mp_bilinear_packed_bytes(self.M) if self.bilinear
+                  else mp_propagate_workspace(self.M, self.prec))
+        self.ws_prop = torch.empty(pbytes, dtype=torch.uint8, device=dev)
         self.packed = False
         self.entries = mp_acc_entries(self.d, self.mode, self.K)
         if self.entries < 0:
@@ -266,8 +301,10 @@ class CountsPipeline:
         if self.mode == 0 and self.d >= 2:
             wbytes = mp_binned_workspace(self.d, 0, self.K, self.chunk, self.n_sub, self.ns, 0)
         if self.fused:
-            # the GEMM's partials plus the counts blocks of the worst chunk alignment
-            wbytes += mp_propagate_counts_workspace(self.M, self.chunk, self.d, self.bins, self.mode,
+            # the GEMM's partials plus the counts blocks of the worst chunk alignment (the
+            # bilinear form's partials cover one run of all modes)
+            wbins = np.zeros(self.M, np.int32) if self.bilinear else self.bins
+            wbytes += mp_propagate_counts_workspace(self.M, self.chunk, self.d, wbins, self.mode,
                                                     self.K, self.n_sub, self.ns, 0)
         self.ws_counts = torch.empty(wbytes, dtype=torch.uint8, device=dev)
         self.acc = torch.zeros(self.n_sub * self.entries * 2, dtype=torch.float64, device=dev)
@@ -283,9 +320,21 @@ class CountsPipeline:
     def run_chunk(self, g0: int, E: int, stream=None):
         assert 1 <= E <= self.chunk
         if not self.packed:
-            mp_pack_transmission(self.M, self.T, self.prec, self.ws_prop, stream)
+            if self.bilinear:
+                scratch = self.torch.empty(mp_bilinear_workspace(self.M), dtype=self.torch.uint8,
+                                           device=self.device)
+                mp_pack_bilinear(self.M, self.T, self.bins, self.prec, self.ws_prop, scratch, stream)
+                self.torch.cuda.synchronize()  # once per run: the scratch is free to go
+                del scratch
+            else:
+                mp_pack_transmission(self.M, self.T, self.prec, self.ws_prop, stream)
             self.packed = True
         mp_sample(self.M, g0, E, self.r, self.seed, self.net, self.prec, self.ab, self.n, stream)
+        if self.bilinear:
+            mp_propagate_counts_bilinear(self.M, E, self.prec, self.est, self.ab, self.n,
+                                         self.ws_prop, self.m_lo[0], self.K[0], self.n_sub, self.ns,
+                                         g0, self.acc, self.ws_counts, stream)
+            return
         if self.fused:
             mp_propagate_counts(self.M, E, self.prec, self.est, self.ab, self.n, self.ws_prop, self.d,
                                 self.bins, self.mode, self.m_lo, self.K, self.n_sub, self.ns, g0,

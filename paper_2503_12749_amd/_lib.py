@@ -27,7 +27,9 @@ EXPORTS = [
     "mp_mode_occupations_bytes", "mp_mode_occupations", "mp_pair_correlations_accumulate",
     "mp_check_finite", "mp_pair_correlations_workspace",
     "mp_binned_workspace", "mp_binned_counts", "mp_propagate_counts_workspace",
-    "mp_propagate_counts", "mp_propagate_counts_noalloc", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
+    "mp_propagate_counts", "mp_propagate_counts_noalloc", "mp_bilinear_workspace",
+    "mp_bilinear_packed_bytes",
+    "mp_pack_bilinear", "mp_propagate_counts_bilinear", "mp_counts_finalize", "mp_finalize_workspace", "mp_last_error", "mp_version",
     "mp_mfma_sustained", "mp_plan_create", "mp_plan_launch", "mp_plan_result", "mp_plan_info", "mp_plan_tile",
     "mp_plan_destroy",
     "mp_mlp_param_count", "mp_mlp_workspace", "mp_mlp_round", "mp_mlp_forward", "mp_mlp_loss_grad",
@@ -83,6 +85,12 @@ def load() -> ctypes.CDLL:
         "mp_propagate_counts": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                                sz, c_i32, vp, ctypes.c_int, vp, vp, c_i32, c_i64,
                                                c_i64, vp, vp, sz, vp]),
+        "mp_bilinear_workspace": (sz, [c_i32]),
+        "mp_bilinear_packed_bytes": (sz, [c_i32]),
+        "mp_pack_bilinear": (ctypes.c_int, [c_i32, vp, vp, ctypes.c_int, vp, sz, vp, sz, vp]),
+        "mp_propagate_counts_bilinear": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, ctypes.c_int,
+                                                        vp, vp, vp, sz, vp, vp, c_i32, c_i64,
+                                                        c_i64, vp, vp, sz, vp]),
         "mp_propagate_counts_noalloc": (ctypes.c_int, [c_i32, c_i64, ctypes.c_int, ctypes.c_int, vp,
                                                        vp, vp, sz, c_i32, vp, ctypes.c_int, vp, vp,
                                                        c_i32, c_i64, c_i64, vp, vp]),

@@ -56,6 +56,16 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
                                   const int32_t* m_lo, const int32_t* K, int32_t n_sub,
                                   int64_t ns, int64_t e0, double* acc, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
+size_t bilinear_workspace(int32_t M);
+size_t bilinear_packed_bytes(int32_t M, mp_precision prec);
+mp_status bilinear_pack_launch(int32_t M, const double* T, const int32_t* in_s,
+                               mp_precision prec, void* packed, void* scratch, hipStream_t stream);
+mp_status propagate_counts_bilinear_launch(int32_t M, int64_t E, mp_precision prec,
+                                           mp_estimator est, const void* ab, const double* n,
+                                           const void* packed, const int32_t* m_lo,
+                                           const int32_t* K, int32_t n_sub, int64_t ns,
+                                           int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                                           hipStream_t stream);
 mp_status propagate_counts_noalloc_launch(int32_t M, int64_t E, mp_precision prec,
                                           mp_estimator est, const void* ab, const double* n,
                                           const void* packed, int32_t d,
@@ -311,6 +321,64 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
   return propagate_counts_launch(M, E, prec, est, ab, n, packed, d, bin_of_mode, mode, m_lo, K,
                                  n_sub, samples_per_sub, e0, acc, workspace, ws_bytes,
                                  (hipStream_t)stream);
+}
+
+size_t mp_bilinear_workspace(int32_t M) { return M >= 1 ? bilinear_workspace(M) : 0; }
+
+size_t mp_bilinear_packed_bytes(int32_t M) {
+  return M >= 1 ? bilinear_packed_bytes(M, MP_SPLIT1T_F8) : 0;
+}
+
+mp_status mp_pack_bilinear(int32_t M, const double* T, const int32_t* bin_of_mode,
+                           mp_precision prec, void* packed, size_t packed_bytes, void* scratch,
+                           size_t scratch_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1, MP_ERR_ARG, "mp_pack_bilinear: M must be >= 1");
+  MP_CHECK_ARG(prec == MP_SPLIT1T_F8, MP_ERR_UNSUPPORTED,
+               "mp_pack_bilinear: precision %d (MP_SPLIT1T_F8 only)", (int)prec);
+  MP_CHECK_ARG(T && bin_of_mode && packed && scratch, MP_ERR_ARG,
+               "mp_pack_bilinear: null pointer argument");
+  for (int j = 0; j < M; ++j)
+    MP_CHECK_ARG(bin_of_mode[j] == 0 || bin_of_mode[j] == -1, MP_ERR_ARG,
+                 "mp_pack_bilinear: bin_of_mode[%d] = %d (0: in the set, -1: not)", j,
+                 bin_of_mode[j]);
+  const size_t need_packed = bilinear_packed_bytes(M, prec);
+  MP_CHECK_ARG(packed_bytes >= need_packed && aligned(packed, 256), MP_ERR_WORKSPACE,
+               "mp_pack_bilinear: packed operand of %zu bytes (256-aligned) needed, %zu given",
+               need_packed, packed_bytes);
+  const size_t need_scratch = bilinear_workspace(M);
+  MP_CHECK_ARG(scratch_bytes >= need_scratch && aligned(scratch, 256), MP_ERR_WORKSPACE,
+               "mp_pack_bilinear: scratch of %zu bytes (256-aligned) needed, %zu given",
+               need_scratch, scratch_bytes);
+  return bilinear_pack_launch(M, T, bin_of_mode, prec, packed, scratch, (hipStream_t)stream);
+}
+
+mp_status mp_propagate_counts_bilinear(int32_t M, int64_t E, mp_precision prec,
+                                       mp_estimator est, const void* ab, const double* n,
+                                       const void* packed, size_t packed_bytes,
+                                       const int32_t* m_lo, const int32_t* K, int32_t n_sub,
+                                       int64_t samples_per_sub, int64_t e0, double* acc,
+                                       void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  MP_CHECK_ARG(M >= 1, MP_ERR_ARG, "mp_propagate_counts_bilinear: M must be >= 1");
+  const std::vector<int32_t> all(M, 0);
+  const mp_status st = counts_args("mp_propagate_counts_bilinear", M, E, est, 1, all.data(),
+                                   MP_JOINT, m_lo, K, n_sub, samples_per_sub, e0);
+  if (st != MP_OK) return st;
+  MP_CHECK_ARG(prec == MP_SPLIT1T_F8, MP_ERR_UNSUPPORTED,
+               "mp_propagate_counts_bilinear: precision %d (MP_SPLIT1T_F8 only)", (int)prec);
+  MP_CHECK_ARG(ab && n && packed && acc, MP_ERR_ARG,
+               "mp_propagate_counts_bilinear: null pointer argument");
+  MP_CHECK_ARG(aligned(ab, 16), MP_ERR_ARG, "mp_propagate_counts_bilinear: ab must be 16-byte aligned");
+  const size_t need_packed = bilinear_packed_bytes(M, prec);
+  MP_CHECK_ARG(packed_bytes >= need_packed && aligned(packed, 256), MP_ERR_WORKSPACE,
+               "mp_propagate_counts_bilinear: packed operand of %zu bytes (256-aligned) needed, "
+               "%zu given", need_packed, packed_bytes);
+  MP_CHECK_ARG(aligned(workspace, 256), MP_ERR_WORKSPACE,
+               "mp_propagate_counts_bilinear: workspace must be 256-byte aligned");
+  return propagate_counts_bilinear_launch(M, E, prec, est, ab, n, packed, m_lo, K, n_sub,
+                                          samples_per_sub, e0, acc, workspace, ws_bytes,
+                                          (hipStream_t)stream);
 }
 
 mp_status mp_propagate_counts_noalloc(int32_t M, int64_t E, mp_precision prec, mp_estimator est,

@@ -951,6 +951,28 @@ mp_status propagate_counts_launch(int32_t M, int64_t E, mp_precision prec, mp_es
                                      acc, ws, ws_bytes, stream);
 }
 
+// One distribution through the bilinear form alpha^T W beta (W packed by
+// bilinear_pack_launch; the mode set S is inside W): the GEMM's partials cover
+// one run of all M input modes, which the d = 1 counting kernels then read.
+mp_status gemm_bilinear_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                               const void* ab, const FusedOut& fo, hipStream_t stream);
+
+mp_status propagate_counts_bilinear_launch(int32_t M, int64_t E, mp_precision prec,
+                                           mp_estimator est, const void* ab, const double* n,
+                                           const void* packed, const int32_t* m_lo,
+                                           const int32_t* K, int32_t n_sub, int64_t ns,
+                                           int64_t e0, double* acc, void* ws, size_t ws_bytes,
+                                           hipStream_t stream) {
+  const std::vector<int32_t> all(M, 0);
+  FusedOut fo;
+  mp_status st = fused_out_setup(M, E, 1, all.data(), MP_JOINT, m_lo, K, n_sub, ns, e0, est, ws,
+                                 ws_bytes, fo);
+  if (st != MP_OK) return st;
+  if ((st = gemm_bilinear_launch(M, E, packed, prec, ab, fo, stream)) != MP_OK) return st;
+  return counts_from_partials_launch(M, E, n, est, 1, all.data(), MP_JOINT, m_lo, K, n_sub, ns,
+                                     e0, acc, ws, ws_bytes, stream);
+}
+
 // ---------------------------------------------------------------- no-allocation variant
 
 // Scratch of mp_propagate_counts_noalloc: the occupation-fused GEMM's

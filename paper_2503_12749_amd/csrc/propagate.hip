@@ -1320,6 +1320,68 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1t_occ(const uint16_t* 
                                          (int64_t)tn * 128, out_scale, &fo);
 }
 
+// ---------------------------------------------------------------- bilinear-form epilogue
+
+// One distribution S needs only n_S = sum_{j in S} alpha'_j beta'_j per sample,
+// and with alpha' = T alpha, beta' = T* beta (real alpha, beta) that is the
+// bilinear form alpha^T W beta, W = T^T P_S T* (P_S: the projector on S).  W's
+// diagonal D (real: D_a = sum_{j in S} |T_ja|^2) alone sets the mean of n_S,
+// since E[alpha_a beta_b] vanishes for a != b; it is applied in FP32 here, as
+// sum_a D_a alpha_a beta_a, and the GEMM applies the off-diagonal part, whose
+// packing rounding then only adds noise per sample (packed with D in it, the
+// rounding of equal diagonal entries would bias every sample alike).  The tile
+// holds the Re and Im rows of W_off beta for 128 input modes a (waves wm = 0
+// and 1) and 256 samples; each sample's partial is sum_a alpha_a (W beta)_a
+// over the tile's modes, written as (Re, 0) by wm = 0 and (0, Im) by wm = 1 in
+// the occupation partials' layout (slot = the 128-mode block, one run from mode
+// 0), which the counting kernels read unchanged.  alpha and beta are the FP16
+// sample operand's halves in column pairs (zeros on padding modes, as D); the
+// register of acc[i][j] at 4 g + rr is mode i 32 + 8 g + 4 lh + rr of the wave
+// and sample j 32 + lr.
+__device__ inline void bilinear_epilogue(f32x16 (&acc)[4][4], const uint16_t* __restrict__ alpha,
+                                         const uint16_t* __restrict__ beta,
+                                         const float* __restrict__ diag, const FusedOut& fo,
+                                         int64_t ldm, int64_t m0, int64_t n0, int wm, int wn,
+                                         int lane, float out_scale) {
+  typedef __attribute__((ext_vector_type(4))) _Float16 f16x4;
+  typedef __attribute__((ext_vector_type(2))) float f32x2;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int64_t slot = fo.slot_off[0] + (m0 >> 7);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t smp = n0 + wn * 128 + j * 32 + lr;
+    float sum = 0.f, dsum = 0.f;
+    if (smp < fo.E) {
+      const int64_t off = (smp >> 1) * 2 * ldm + 32 * (smp & 1);
+      const _Float16* col = (const _Float16*)alpha + off;
+      const _Float16* bcol = (const _Float16*)beta + off;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int64_t mode = m0 + i * 32 + 8 * g + 4 * lh;  // four consecutive modes
+          const int64_t at = 64 * (mode >> 5) + (mode & 31);
+          const f16x4 a4 = *(const f16x4*)(col + at);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) sum += (float)a4[rr] * acc[i][j][4 * g + rr];
+          if (wm == 0) {
+            const f16x4 b4 = *(const f16x4*)(bcol + at);
+            const f32x4 d4 = *(const f32x4*)(diag + mode);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) dsum += d4[rr] * ((float)a4[rr] * (float)b4[rr]);
+          }
+        }
+    }
+    sum = sum * out_scale + dsum;
+    sum += __shfl_xor(sum, 32, 64);  // the other lane half's modes
+    if (lh == 0 && smp < fo.E) {
+      const float v = sum;
+      *(f32x2*)(fo.part + (slot * fo.E + smp) * 4 + 2 * wm) =
+          wm == 0 ? f32x2{v, 0.f} : f32x2{0.f, v};
+    }
+  }
+}
+
 // ---------------------------------------------------------------- T-split with an FP8 correction, 256 x 256
 
 // MP_SPLIT1T_F8: the T-split product T_hi S + T_lo S with its correction term
@@ -1358,12 +1420,18 @@ __device__ inline int f8_chunk_off(int r, int c) {
   return (r >> 1) * 128 + ((c ^ swz8(r >> 1)) << 4);
 }
 
-template <bool FUSED, bool PF>
+// MODE 0 stores C; MODE 1 is the occupation-fused tile (128 alpha and 128 beta
+// columns of the same samples, Re and Im rows of 128 modes); MODE 2 is the
+// bilinear-form tile (Re and Im rows of 128 modes of W beta for 256 samples,
+// reduced against alpha by bilinear_epilogue).
+template <int MODE, bool PF>
 __device__ __attribute__((always_inline)) inline void split1t8_pp_tile(
     char* __restrict__ lds, const uint16_t* __restrict__ A, const uint8_t* __restrict__ A8,
     const uint16_t* __restrict__ B, const uint8_t* __restrict__ B8, float* __restrict__ C,
     int64_t ldm, int64_t ncols, int64_t e_real, int64_t m0, int64_t n0, float out_scale,
-    int scale_a, const FusedOut* fo, int tid = -1) {
+    int scale_a, const FusedOut* fo, int tid = -1, const uint16_t* __restrict__ alpha = nullptr,
+    const float* __restrict__ diag = nullptr) {
+  constexpr bool FUSED = MODE == 1, ROWS_RI = MODE != 0;
   typedef __attribute__((ext_vector_type(8))) int i32x8;
   typedef __attribute__((ext_vector_type(4))) int i32x4;
   const int wave = tid < 0 ? (int)(threadIdx.x >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1373,7 +1441,7 @@ __device__ __attribute__((always_inline)) inline void split1t8_pp_tile(
 
   // first global row of tile row pair pa (tile rows 2 pa, 2 pa + 1)
   auto a_row = [&](int pa) -> int64_t {
-    if constexpr (FUSED) return pa < 64 ? m0 + 2 * pa : ldm + m0 + 2 * (pa - 64);
+    if constexpr (ROWS_RI) return pa < 64 ? m0 + 2 * pa : ldm + m0 + 2 * (pa - 64);
     return m0 + 2 * pa;
   };
   // first storage column of tile column pair pr
@@ -1566,6 +1634,10 @@ __device__ __attribute__((always_inline)) inline void split1t8_pp_tile(
     fused_epilogue(acc, (float*)lds, *fo, m0, n0, wm, wn, lane, out_scale);
     return;
   }
+  if constexpr (MODE == 2) {
+    bilinear_epilogue(acc, alpha, B, diag, *fo, ldm, m0, n0, wm, wn, lane, out_scale);
+    return;
+  }
   const int64_t ldc = 2 * ldm, e2 = split1t_half(e_real);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -1605,7 +1677,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_pp(const uint16_t* 
   if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
   const uint8_t* A8 = (const uint8_t*)A + 4 * ldm * ldm;
   const uint8_t* B8 = (const uint8_t*)B + 2 * ncols * ldm;
-  split1t8_pp_tile<false, PF>(lds, A, A8, B, B8, C, ldm, ncols, e_real, (int64_t)tm * S_BM,
+  split1t8_pp_tile<0, PF>(lds, A, A8, B, B8, C, ldm, ncols, e_real, (int64_t)tm * S_BM,
                               (int64_t)tn * S_BN, out_scale, scale_a, nullptr);
 }
 
@@ -1621,8 +1693,74 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_occ(const uint16_t*
   if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
   const uint8_t* A8 = (const uint8_t*)A + 4 * ldm * ldm;
   const uint8_t* B8 = (const uint8_t*)B + 2 * ncols * ldm;
-  split1t8_pp_tile<true, PF>(lds, A, A8, B, B8, nullptr, ldm, ncols, 0, (int64_t)tm * 128,
+  split1t8_pp_tile<1, PF>(lds, A, A8, B, B8, nullptr, ldm, ncols, 0, (int64_t)tm * 128,
                              (int64_t)tn * 128, out_scale, scale_a, &fo);
+}
+
+// Bilinear form alpha^T W beta per sample (one distribution): A is W packed
+// as MP_SPLIT1T_F8 packs T, B and B8 the beta half of the sample operand
+// (storage columns E2 ..) and its e4m3 copies, alpha the FP16 alpha half.
+template <bool PF>
+__global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_bilin(
+    const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, const uint8_t* __restrict__ B8,
+    const uint16_t* __restrict__ alpha, const float* __restrict__ diag, int64_t ldm,
+    int64_t ncols, float out_scale, int scale_a, FusedOut fo) {
+  __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
+  const int tiles_m = (int)(2 * ldm / S_BM), tiles_n = (int)((ncols + S_BN - 1) / S_BN);
+  int tm, tn;
+  if (!tile_of_block<kS1tStepRows, kS1tStepCols>(tiles_m, tiles_n, tm, tn)) return;
+  const uint8_t* A8 = (const uint8_t*)A + 4 * ldm * ldm;
+  split1t8_pp_tile<2, PF>(lds, A, A8, B, B8, nullptr, ldm, ncols, 0, (int64_t)tm * 128,
+                          (int64_t)tn * S_BN, out_scale, scale_a, &fo, -1, alpha, diag);
+}
+
+// ---- W = T^T P_S T* for the bilinear form, from the FP64 GEMM
+
+// Tt = T^T (complex, the layout of T: entry (i, j) at 2 (i M + j)).
+__global__ void bilin_transpose(const double* __restrict__ T, int M, double* __restrict__ Tt) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)M * M) return;
+  const int64_t a = idx / M, b = idx % M;
+  Tt[2 * idx] = T[2 * (b * M + a)];
+  Tt[2 * idx + 1] = T[2 * (b * M + a) + 1];
+}
+
+// X in the FP64 sample layout with E = M: column k holds P_S Re T[:, k] and
+// column M + k holds P_S Im T[:, k] (modes j with in_s[j] < 0 and padding zero).
+__global__ void bilin_columns(const double* __restrict__ T, int M, int64_t ldm,
+                              const int32_t* __restrict__ in_s, double* __restrict__ X) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)M * ldm) return;
+  const int64_t k = idx / ldm, j = idx % ldm;
+  double re = 0.0, im = 0.0;
+  if (j < M && in_s[j] >= 0) {
+    re = T[2 * (j * M + k)];
+    im = T[2 * (j * M + k) + 1];
+  }
+  X[k * ldm + j] = re;
+  X[(M + k) * ldm + j] = im;
+}
+
+// With T = A + i B, C = [A^T; B^T] [P A | P B] holds A^T P A, B^T P A (columns
+// b < M) and A^T P B, B^T P B (columns M + b); W = T^T P T* has real part
+// A^T P A + B^T P B and imaginary part B^T P A - A^T P B.
+__global__ void bilin_combine(const double* __restrict__ C, int M, int64_t ldm,
+                              double* __restrict__ W) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)M * M) return;
+  const int64_t a = idx / M, b = idx % M, ldc = 2 * ldm;
+  const double* c1 = C + b * ldc;        // column b: [A^T P A; B^T P A] e_b
+  const double* c2 = C + (M + b) * ldc;  // column M + b: [A^T P B; B^T P B] e_b
+  W[2 * idx] = a == b ? 0.0 : c1[a] + c2[ldm + a];  // the diagonal goes to D
+  W[2 * idx + 1] = a == b ? 0.0 : c1[ldm + a] - c2[a];
+}
+
+// D_a = Re W_aa (W_aa = sum_{j in S} |T_ja|^2 is real) in FP32, zero on padding.
+__global__ void bilin_diag(const double* __restrict__ C, int M, int64_t ldm,
+                           float* __restrict__ D) {
+  const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (a >= ldm) return;
+  D[a] = a < M ? (float)(C[a * 2 * ldm + a] + C[(M + a) * 2 * ldm + ldm + a]) : 0.0f;
 }
 
 // ---------------------------------------------------------------- FP32, 256 x 256
@@ -1897,7 +2035,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_split1t8_grouped(const Group
     asm volatile("" : "+v"(tid));
     const uint8_t* A8 = (const uint8_t*)g->A + 4 * g->ldm * g->ldm;
     const uint8_t* B8 = (const uint8_t*)g->B + 2 * g->ncols * g->ldm;
-    split1t8_pp_tile<true, PF>(lds, g->A, A8, g->B, B8, nullptr, g->ldm, g->ncols, 0,
+    split1t8_pp_tile<1, PF>(lds, g->A, A8, g->B, B8, nullptr, g->ldm, g->ncols, 0,
                                (int64_t)w.y * 128, (int64_t)w.z * 128, g->out_scale,
                                g->f8_scale_a, &g->fo, tid);
     __syncthreads();  // the next item reuses the LDS stages
@@ -2129,6 +2267,82 @@ mp_status gemm_fused_launch(int32_t M, int64_t E, const void* packed, mp_precisi
       return MP_ERR_UNSUPPORTED;
   }
   MP_HIP_LAUNCH_CHECK("mp_propagate_counts fused gemm launch");
+  return MP_OK;
+}
+
+// Scratch of bilinear_pack_launch: T^T, the FP64 sample operand X (E = M),
+// T^T packed in FP64, C (2 ldm x 2 M), W, the device copy of the mode set.
+static int64_t round256(int64_t x) { return (x + 255) / 256 * 256; }
+size_t bilinear_workspace(int32_t M) {
+  const int64_t ldm = ld_modes(M), m2 = (int64_t)M * M;
+  return (size_t)(round256(16 * m2) + round256(8 * ldm * 2 * M) +
+                  round256((int64_t)propagate_workspace(M, MP_FP64)) +
+                  round256(8 * 2 * ldm * 2 * M) + round256(16 * m2) + round256(4 * (int64_t)M));
+}
+
+// Bytes of the packed bilinear operand: W's off-diagonal part packed as `prec`
+// packs T, then D (ldm FP32 values).
+size_t bilinear_packed_bytes(int32_t M, mp_precision prec) {
+  return propagate_workspace(M, prec) + (size_t)round256(4 * ld_modes(M));
+}
+
+// Packs W = T^T P_S T* (S: modes with in_s[j] >= 0; in_s on the host): its
+// off-diagonal part as `prec` packs T, its diagonal in FP32 after it.  W comes
+// from the FP64 GEMM, so the packed form carries only the packing's rounding.
+mp_status bilinear_pack_launch(int32_t M, const double* T, const int32_t* in_s,
+                               mp_precision prec, void* packed, void* scratch,
+                               hipStream_t stream) {
+  const int64_t ldm = ld_modes(M), m2 = (int64_t)M * M;
+  char* p = (char*)scratch;
+  double* Tt = (double*)p;
+  p += round256(16 * m2);
+  double* X = (double*)p;
+  p += round256(8 * ldm * 2 * M);
+  void* packed64 = p;
+  p += round256((int64_t)propagate_workspace(M, MP_FP64));
+  double* C = (double*)p;
+  p += round256(8 * 2 * ldm * 2 * M);
+  double* W = (double*)p;
+  p += round256(16 * m2);
+  int32_t* mask = (int32_t*)p;
+  hipError_t e = hipMemcpyAsync(mask, in_s, 4 * (size_t)M, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    set_error("mp_pack_bilinear: copy of the mode set: %s", hipGetErrorString(e));
+    return MP_ERR_HIP;
+  }
+  hipLaunchKernelGGL(bilin_transpose, dim3((unsigned)((m2 + 255) / 256)), dim3(256), 0, stream, T,
+                     M, Tt);
+  hipLaunchKernelGGL(bilin_columns, dim3((unsigned)((M * ldm + 255) / 256)), dim3(256), 0, stream,
+                     T, M, ldm, (const int32_t*)mask, X);
+  MP_HIP_LAUNCH_CHECK("mp_pack_bilinear setup launch");
+  mp_status st = pack_launch(M, Tt, MP_FP64, packed64, stream);
+  if (st != MP_OK) return st;
+  if ((st = gemm_packed_launch(M, M, packed64, MP_FP64, X, C, stream)) != MP_OK) return st;
+  hipLaunchKernelGGL(bilin_combine, dim3((unsigned)((m2 + 255) / 256)), dim3(256), 0, stream, C, M,
+                     ldm, W);
+  hipLaunchKernelGGL(bilin_diag, dim3((unsigned)((ldm + 255) / 256)), dim3(256), 0, stream, C, M,
+                     ldm, (float*)((char*)packed + propagate_workspace(M, prec)));
+  MP_HIP_LAUNCH_CHECK("mp_pack_bilinear combine launch");
+  return pack_launch(M, W, prec, packed, stream);
+}
+
+// The bilinear-form GEMM with its epilogue (one run of all modes in fo).
+mp_status gemm_bilinear_launch(int32_t M, int64_t E, const void* packed, mp_precision prec,
+                               const void* ab, const FusedOut& fo, hipStream_t stream) {
+  if (prec != MP_SPLIT1T_F8) {
+    set_error("mp_propagate_counts_bilinear: precision %d (MP_SPLIT1T_F8 only)", (int)prec);
+    return MP_ERR_UNSUPPORTED;
+  }
+  const int64_t ldm = ld_modes(M), e2 = split1t_half(E);
+  const uint16_t* alpha = (const uint16_t*)ab;
+  const uint16_t* B = alpha + e2 * ldm;                              // beta: storage columns E2 ..
+  const uint8_t* B8 = (const uint8_t*)ab + 4 * e2 * ldm + e2 * ldm;  // their e4m3 copies
+  auto kernel = split_prefetch_for(ldm) ? gemm_split1t8_bilin<true> : gemm_split1t8_bilin<false>;
+  const float* diag = (const float*)((const char*)packed + propagate_workspace(M, prec));
+  hipLaunchKernelGGL(kernel, dim3(grid_tiles_s1t(ldm, e2)), dim3(kThreads), 0, stream,
+                     (const uint16_t*)packed, B, B8, alpha, diag, ldm, e2,
+                     ldexpf(1.0f, -fp16_scale_exp(M)), f8_scale_a(M), fo);
+  MP_HIP_LAUNCH_CHECK("mp_propagate_counts_bilinear gemm launch");
   return MP_OK;
 }
 

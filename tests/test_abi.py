@@ -225,3 +225,36 @@ def test_noalloc_rejects_chunks_beyond_its_scratch():
                                          1, bins, 0, i32([8083]), i32([3840]), 1, 4096, 0, vp(4096),
                                          None)
     assert st == -4
+
+
+def test_bilinear_entries_validate_on_the_host():
+    """mp_pack_bilinear and mp_propagate_counts_bilinear reject what they do
+    not cover before any device work: precisions other than the FP8-correction
+    form, mode sets other than 0 / -1, short or unaligned buffers, nulls."""
+    lib = _lib()
+    vp = ctypes.c_void_p
+    M = 100
+    ok_bins = (ctypes.c_int32 * M)(*([0] * M))
+    bad_bins = (ctypes.c_int32 * M)(*([0] * (M - 1) + [1]))
+    need_p = lib.mp_bilinear_packed_bytes(M)
+    assert need_p == lib.mp_propagate_workspace(M, 6) + 4 * 128  # ldm = 128 FP32 diagonal values
+    need_s = lib.mp_bilinear_workspace(M)
+    assert need_s > 0 and lib.mp_bilinear_workspace(0) == 0
+    assert lib.mp_pack_bilinear(M, vp(256), ok_bins, 5, vp(256), need_p, vp(512), need_s, None) == -4
+    assert lib.mp_pack_bilinear(M, vp(256), bad_bins, 6, vp(256), need_p, vp(512), need_s, None) == -1
+    assert lib.mp_pack_bilinear(M, None, ok_bins, 6, vp(256), need_p, vp(512), need_s, None) == -1
+    assert lib.mp_pack_bilinear(M, vp(256), ok_bins, 6, vp(256), need_p - 1, vp(512), need_s,
+                                None) == -5
+    assert lib.mp_pack_bilinear(M, vp(256), ok_bins, 6, vp(256), need_p, vp(512), need_s - 1,
+                                None) == -5
+    assert lib.mp_pack_bilinear(M, vp(256), ok_bins, 6, vp(256), need_p, vp(520), need_s,
+                                None) == -5
+    m_lo, K = (ctypes.c_int32 * 1)(0), (ctypes.c_int32 * 1)(64)
+    args = lambda prec, packed_bytes: (M, 256, prec, 0, vp(256), vp(256), vp(256), packed_bytes,
+                                       m_lo, K, 2, 128, 0, vp(256), vp(256), 1 << 20, None)
+    assert lib.mp_propagate_counts_bilinear(*args(1, need_p)) == -4
+    assert lib.mp_propagate_counts_bilinear(*args(6, need_p - 1)) == -5
+    bad_k = (ctypes.c_int32 * 1)(0)
+    assert lib.mp_propagate_counts_bilinear(M, 256, 6, 0, vp(256), vp(256), vp(256), need_p, m_lo,
+                                            bad_k, 2, 128, 0, vp(256), vp(256), 1 << 20,
+                                            None) == -1

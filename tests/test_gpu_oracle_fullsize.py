@@ -122,6 +122,23 @@ def test_m8000_per_bin_vs_oracle(m8000, prec):
     _compare(f"M8000 {prec}", P, P_im, ref["P"], ref["sigma"], prec == "fp64")
 
 
+def test_m8000_bilinear_per_bin_vs_oracle(m8000):
+    """The same chunk through the bilinear form (n_S = alpha^T W beta with
+    W = T^T T*, formed once in FP64 and packed as the FP8-correction form
+    packs T; the GEMM applies W to beta only): P(m) against the oracle."""
+    import paper_2503_12749_amd as mp
+    w, ref = m8000
+    p = mp.CountsPipeline(w.T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
+                          n_sub=CHUNK // NS, samples_per_sub=NS, chunk=CHUNK, device="cuda:0",
+                          bilinear=True)
+    p.run_chunk(0, CHUNK)
+    P, P_im, _ = _finalize_first(p, NR_ORACLE)
+    del p
+    torch.cuda.empty_cache()
+    assert abs(P.sum() - 1.0) < 1e-8
+    _compare("M8000 split1t_f8 bilinear", P, P_im, ref["P"], ref["sigma"], False)
+
+
 # ---------------------------------------------------------------- M = 4000
 
 
@@ -157,6 +174,27 @@ def test_m4000_precision_study_vs_oracle(m4000, prec, fused):
         assert abs(P[sl].sum() - 1.0) < 1e-8
         _compare(f"M4000 {prec}{' fused' if fused else ''} {'total' if b == 4 else f'bin {b}'}",
                  P[sl], P_im[sl], ref["P"][b, :K], ref["sigma"][b, :K], prec == "fp64")
+
+
+@pytest.mark.parametrize("b", [0, 4])
+def test_m4000_bilinear_vs_oracle(m4000, b):
+    """One distribution at a time through the bilinear form: the first bin's
+    marginal (S = modes 0 .. 999, W = T^T P_S T*) and the total of the four
+    bins, against the oracle's marginal and total."""
+    import paper_2503_12749_amd as mp
+    w, ref = m4000
+    bins = np.where(w.bins == 0, 0, -1) if b < 4 else np.where(w.bins >= 0, 0, -1)
+    p = mp.CountsPipeline(w.T, w.r, prec="split1t_f8", seed=w.seed, bin_of_mode=bins.astype(np.int32),
+                          d=1, windows=[w.windows[b]], n_sub=CHUNK // NS, samples_per_sub=NS,
+                          chunk=CHUNK, device="cuda:0", bilinear=True)
+    p.run_chunk(0, CHUNK)
+    P, P_im, _ = _finalize_first(p, NR_ORACLE)
+    del p
+    torch.cuda.empty_cache()
+    K = w.windows[b][1]
+    assert abs(P.sum() - 1.0) < 1e-8
+    _compare(f"M4000 split1t_f8 bilinear {'total' if b == 4 else f'bin {b}'}", P, P_im,
+             ref["P"][b, :K], ref["sigma"][b, :K], False)
 
 
 # ---------------------------------------------------------------- batched plan
