@@ -62,11 +62,11 @@ GEMM_KERNELS = {"split1t_f8": ("gemm_split1t8_occ", "gemm_split1t8_pp"),
 # (fetch x2, write x1); valid only for the GEMM source they were taken from.
 # Commands and per-kernel figures: profiles/m8000_gemm_traffic.md.
 TRAFFIC = {
-    ("split1t_f8", True): {"source_sha256_16": "4d57559857de40bc",
-                           "fetch_bytes": 3.681e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("split_bf16", True): {"source_sha256_16": "4d57559857de40bc",
-                           "fetch_bytes": 4.931e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
-    ("fp32", True): {"source_sha256_16": "4d57559857de40bc",
+    ("split1t_f8", True): {"source_sha256_16": "7df0e3e2fad6d5c8",
+                           "fetch_bytes": 3.696e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("split_bf16", True): {"source_sha256_16": "7df0e3e2fad6d5c8",
+                           "fetch_bytes": 4.916e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    ("fp32", True): {"source_sha256_16": "7df0e3e2fad6d5c8",
                      "fetch_bytes": 4.903e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
 }
 
@@ -541,6 +541,93 @@ def run_precision_m8000(args, mp, torch, synth):
         f"M8000_t0.95_r1: total counts, E={E} in chunks of {chunk}, {E // ns} sub-ensembles",
         DTYPES["split1t_f8"], fp64_run_s=s64,
         sigma_max_over_P_max=float(sig64.max() / P64.max()), precisions=per)
+
+
+def run_bilinear_m8000(args, mp, torch, synth):
+    """One count distribution through the bilinear form n_S = alpha^T W beta
+    (W = T^T P_S T*, formed once; the GEMM applies W's off-diagonal part to
+    beta alone: 4 M^2 flops per sample instead of 8 M^2) against the T form,
+    both in the FP8-correction precision, at M = 8000 on two networks.  The
+    headline one (Haar x 0.95, total counts) has W = 0.9025 I, so the GEMM's
+    operand is zero and draws less power than a general one; the same Haar
+    unitary with mode-dependent output loss l_j ~ U[0.9, 1] (T = diag(l) U,
+    W dense) is the representative case and gives the line's value.  Per
+    network and form: ms per step (sample + GEMM + counts), the GEMM call
+    (HIP events), the first chunk with packing T or forming W, and the
+    criterion job end to end; per network the largest difference of the two
+    forms' P(m) on the same noise, in units of sigma_T."""
+    chunk, ns = args.chunk, 8192
+    steps = max(args.steps, 3)
+    w = synth.workload_m8000(E=chunk, chunk=chunk)
+    U = w.T / w.t
+    l = np.random.default_rng(synth.SEED_BASE + 77).uniform(0.9, 1.0, w.M)
+    nets = {"haar_x0.95": w.T, "output_loss_0.9_1": l[:, None] * U}
+    E_job = 10 * chunk
+    res = {}
+    for name, T in nets.items():
+        res[name] = {}
+        for form, kw in (("T_form", dict(fused=True)), ("bilinear", dict(bilinear=True))):
+            n_sub = (steps + 2) * chunk // ns
+            p = mp.CountsPipeline(T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
+                                  n_sub=n_sub, samples_per_sub=ns, chunk=chunk, **kw)
+            first = _timed(torch, lambda: p.run_chunk(0, chunk))
+            p.run_chunk(chunk, chunk)
+            stream = torch.cuda.current_stream()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                g = (2 + i) * chunk
+                mp.mp_sample(p.M, g, chunk, p.r, p.seed, p.net, p.prec, p.ab, p.n)
+                ev[i][0].record(stream)
+                if form == "bilinear":
+                    mp.mp_propagate_counts_bilinear(p.M, chunk, p.prec, p.est, p.ab, p.n, p.ws_prop,
+                                                    p.m_lo[0], p.K[0], p.n_sub, p.ns, g, p.acc,
+                                                    p.ws_counts)
+                else:
+                    mp.mp_propagate_counts(p.M, chunk, p.prec, p.est, p.ab, p.n, p.ws_prop, p.d,
+                                           p.bins, p.mode, p.m_lo, p.K, p.n_sub, p.ns, g, p.acc,
+                                           p.ws_counts)
+                ev[i][1].record(stream)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            gemm = float(np.median([a.elapsed_time(b) for a, b in ev]))
+            del p
+            torch.cuda.empty_cache()
+            job = mp.CountsPipeline(T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
+                                    n_sub=E_job // ns, samples_per_sub=ns, chunk=chunk, **kw)
+            job_s = _timed(torch, lambda: job.run(E_job))
+            P, _, sig = job.result()
+            del job
+            torch.cuda.empty_cache()
+            flops = (4 if form == "bilinear" else 8) * w.M ** 2 * chunk
+            res[name][form] = {"ms_per_step": ms, "gemm_call_ms": gemm,
+                               "first_chunk_ms_with_pack": 1e3 * first, "job_s": job_s,
+                               "job_samples": E_job,
+                               "sigma_max_over_P_max": float(sig.max() / P.max()),
+                               "gemm_algorithmic_tflops": flops / gemm / 1e9,
+                               "_P": P, "_sig": sig}
+            log(f"[bench] bilinear_m8000 {name} {form}: {ms:.2f} ms/step, GEMM call {gemm:.2f} ms, "
+                f"first chunk {1e3 * first:.1f} ms, job {job_s:.3f} s")
+        a, b = res[name]["T_form"], res[name]["bilinear"]
+        bulk = a["_P"] > 1e-3 * a["_P"].max()
+        d = np.abs(a["_P"] - b["_P"])
+        res[name]["max_diff_over_sigma"] = float((d / a["_sig"])[bulk].max())
+        res[name]["step_speedup"] = a["ms_per_step"] / b["ms_per_step"]
+        res[name]["job_speedup"] = a["job_s"] / b["job_s"]
+        for f in ("T_form", "bilinear"):
+            del res[name][f]["_P"], res[name][f]["_sig"]
+        log(f"[bench] bilinear_m8000 {name}: step {res[name]['step_speedup']:.2f}x, job "
+            f"{res[name]['job_speedup']:.2f}x, max |P_T - P_bilinear| / sigma_T "
+            f"{res[name]['max_diff_over_sigma']:.2e}")
+    rep_ = res["output_loss_0.9_1"]["bilinear"]
+    return _envelope(
+        "samples·M²/s, one count distribution at M=8000 through the bilinear form (general network)",
+        chunk * w.M ** 2 / (rep_["ms_per_step"] / 1e3), "samples·M²/s", rep_["ms_per_step"],
+        "M8000_r1: total counts on [8083, 11923), 65536 samples per step; networks Haar x 0.95 "
+        "(W = 0.9025 I) and diag(l) Haar with l ~ U[0.9, 1] (W dense)",
+        DTYPES["split1t_f8"], networks=res)
 
 
 def _batched_leg(mp, torch, nets, chunk, label, prec="split_fp16"):
@@ -1112,7 +1199,7 @@ def main():
                     choices=["m8000", "joint_m1000", "precision_m4000", "precision_m8000", "batched",
                              "surrogate",
                              "plusp_m20", "moments_m1000", "pairs_m1000", "joint3_m300",
-                             "scaling_appb", "copy", "mfma_peak"],
+                             "scaling_appb", "copy", "mfma_peak", "bilinear_m8000"],
                     help="m8000 (default) is the headline metric; the others measure the other "
                          "configurations of the hot path and print their own JSON line")
     ap.add_argument("--sweeps", type=int, default=20000, help="surrogate: training sweeps")
@@ -1136,7 +1223,8 @@ def main():
                "moments_m1000": run_moments_m1000, "pairs_m1000": run_pairs_m1000,
                "joint3_m300": run_joint3_m300,
                "scaling_appb": run_scaling_appb,
-               "copy": run_copy, "mfma_peak": run_mfma_peak}
+               "copy": run_copy, "mfma_peak": run_mfma_peak,
+               "bilinear_m8000": run_bilinear_m8000}
     out = runners[args.workload](args, mp, torch, synth)
     print(json.dumps(out), flush=True)
 
