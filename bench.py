@@ -381,6 +381,13 @@ def run_m8000(args, mp, torch, synth):
     if args.compare in results:
         out["config"]["compare"]["speedup_mixed_vs_compare"] = \
             main_r["value"] / results[args.compare]["value"]
+    if args.bilinear and args.M == 8000 and args.prec == "split1t_f8":
+        # the same distribution through the bilinear form, on a network whose W is
+        # dense (the headline network's W is a multiple of the identity)
+        out["config"]["one_distribution_bilinear_form"] = dict(
+            network="diag(l) x the same Haar unitary, l ~ U[0.9, 1] (W dense)",
+            **_bilinear_pair(mp, torch, w, _dense_w_network(w, synth), "dense_W", args.chunk,
+                             8192, 3))
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 CPU oracle on bounded samples ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, synth)
@@ -543,84 +550,90 @@ def run_precision_m8000(args, mp, torch, synth):
         sigma_max_over_P_max=float(sig64.max() / P64.max()), precisions=per)
 
 
+def _bilinear_pair(mp, torch, w, T, name, chunk, ns, steps):
+    """The T form and the bilinear form of one network (FP8-correction
+    precision, one total-count distribution): ms per step, the GEMM call (HIP
+    events), the first chunk with packing T or forming W, the criterion job
+    (10 chunks) end to end, and the largest difference of the two forms' P(m)
+    on the same noise in units of sigma_T."""
+    E_job = 10 * chunk
+    res = {}
+    for form, kw in (("T_form", dict(fused=True)), ("bilinear", dict(bilinear=True))):
+        n_sub = (steps + 2) * chunk // ns
+        p = mp.CountsPipeline(T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
+                              n_sub=n_sub, samples_per_sub=ns, chunk=chunk, **kw)
+        first = _timed(torch, lambda: p.run_chunk(0, chunk))
+        p.run_chunk(chunk, chunk)
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            g = (2 + i) * chunk
+            mp.mp_sample(p.M, g, chunk, p.r, p.seed, p.net, p.prec, p.ab, p.n)
+            ev[i][0].record(stream)
+            if form == "bilinear":
+                mp.mp_propagate_counts_bilinear(p.M, chunk, p.prec, p.est, p.ab, p.n, p.ws_prop,
+                                                p.m_lo[0], p.K[0], p.n_sub, p.ns, g, p.acc,
+                                                p.ws_counts)
+            else:
+                mp.mp_propagate_counts(p.M, chunk, p.prec, p.est, p.ab, p.n, p.ws_prop, p.d, p.bins,
+                                       p.mode, p.m_lo, p.K, p.n_sub, p.ns, g, p.acc, p.ws_counts)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        gemm = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        del p
+        torch.cuda.empty_cache()
+        job = mp.CountsPipeline(T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
+                                n_sub=E_job // ns, samples_per_sub=ns, chunk=chunk, **kw)
+        job_s = _timed(torch, lambda: job.run(E_job))
+        P, _, sig = job.result()
+        del job
+        torch.cuda.empty_cache()
+        flops = (4 if form == "bilinear" else 8) * w.M ** 2 * chunk
+        res[form] = {"ms_per_step": ms, "gemm_call_ms": gemm,
+                     "first_chunk_ms_with_pack": 1e3 * first, "job_s": job_s, "job_samples": E_job,
+                     "sigma_max_over_P_max": float(sig.max() / P.max()),
+                     "gemm_algorithmic_tflops": flops / gemm / 1e9, "_P": P, "_sig": sig}
+        log(f"[bench] bilinear {name} {form}: {ms:.2f} ms/step, GEMM call {gemm:.2f} ms, "
+            f"first chunk {1e3 * first:.1f} ms, job {job_s:.3f} s")
+    a, b = res["T_form"], res["bilinear"]
+    bulk = a["_P"] > 1e-3 * a["_P"].max()
+    res["max_diff_over_sigma"] = float((np.abs(a["_P"] - b["_P"]) / a["_sig"])[bulk].max())
+    res["step_speedup"] = a["ms_per_step"] / b["ms_per_step"]
+    res["job_speedup"] = a["job_s"] / b["job_s"]
+    for f in ("T_form", "bilinear"):
+        del res[f]["_P"], res[f]["_sig"]
+    log(f"[bench] bilinear {name}: step {res['step_speedup']:.2f}x, job {res['job_speedup']:.2f}x, "
+        f"max |P_T - P_bilinear| / sigma_T {res['max_diff_over_sigma']:.2e}")
+    return res
+
+
+def _dense_w_network(w, synth):
+    """The headline network's Haar unitary with mode-dependent output loss
+    l_j ~ U[0.9, 1]: T = diag(l) U, so W = T^T T* is dense (for the headline
+    network itself W = 0.9025 I and the bilinear GEMM's operand is zero)."""
+    l = np.random.default_rng(synth.SEED_BASE + 77).uniform(0.9, 1.0, w.M)
+    return l[:, None] * (w.T / w.t)
+
+
 def run_bilinear_m8000(args, mp, torch, synth):
     """One count distribution through the bilinear form n_S = alpha^T W beta
     (W = T^T P_S T*, formed once; the GEMM applies W's off-diagonal part to
     beta alone: 4 M^2 flops per sample instead of 8 M^2) against the T form,
-    both in the FP8-correction precision, at M = 8000 on two networks.  The
-    headline one (Haar x 0.95, total counts) has W = 0.9025 I, so the GEMM's
-    operand is zero and draws less power than a general one; the same Haar
-    unitary with mode-dependent output loss l_j ~ U[0.9, 1] (T = diag(l) U,
-    W dense) is the representative case and gives the line's value.  Per
-    network and form: ms per step (sample + GEMM + counts), the GEMM call
-    (HIP events), the first chunk with packing T or forming W, and the
-    criterion job end to end; per network the largest difference of the two
-    forms' P(m) on the same noise, in units of sigma_T."""
+    both in the FP8-correction precision, at M = 8000 on two networks: the
+    headline one (Haar x 0.95, total counts: W = 0.9025 I, so the GEMM's
+    operand is zero and draws less power than a general one) and the same Haar
+    unitary with output loss l_j ~ U[0.9, 1] (W dense), the representative
+    case, which gives the line's value."""
     chunk, ns = args.chunk, 8192
     steps = max(args.steps, 3)
     w = synth.workload_m8000(E=chunk, chunk=chunk)
-    U = w.T / w.t
-    l = np.random.default_rng(synth.SEED_BASE + 77).uniform(0.9, 1.0, w.M)
-    nets = {"haar_x0.95": w.T, "output_loss_0.9_1": l[:, None] * U}
-    E_job = 10 * chunk
-    res = {}
-    for name, T in nets.items():
-        res[name] = {}
-        for form, kw in (("T_form", dict(fused=True)), ("bilinear", dict(bilinear=True))):
-            n_sub = (steps + 2) * chunk // ns
-            p = mp.CountsPipeline(T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
-                                  n_sub=n_sub, samples_per_sub=ns, chunk=chunk, **kw)
-            first = _timed(torch, lambda: p.run_chunk(0, chunk))
-            p.run_chunk(chunk, chunk)
-            stream = torch.cuda.current_stream()
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(steps)]
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for i in range(steps):
-                g = (2 + i) * chunk
-                mp.mp_sample(p.M, g, chunk, p.r, p.seed, p.net, p.prec, p.ab, p.n)
-                ev[i][0].record(stream)
-                if form == "bilinear":
-                    mp.mp_propagate_counts_bilinear(p.M, chunk, p.prec, p.est, p.ab, p.n, p.ws_prop,
-                                                    p.m_lo[0], p.K[0], p.n_sub, p.ns, g, p.acc,
-                                                    p.ws_counts)
-                else:
-                    mp.mp_propagate_counts(p.M, chunk, p.prec, p.est, p.ab, p.n, p.ws_prop, p.d,
-                                           p.bins, p.mode, p.m_lo, p.K, p.n_sub, p.ns, g, p.acc,
-                                           p.ws_counts)
-                ev[i][1].record(stream)
-            torch.cuda.synchronize()
-            ms = 1e3 * (time.perf_counter() - t0) / steps
-            gemm = float(np.median([a.elapsed_time(b) for a, b in ev]))
-            del p
-            torch.cuda.empty_cache()
-            job = mp.CountsPipeline(T, w.r, prec="split1t_f8", seed=w.seed, windows=w.windows,
-                                    n_sub=E_job // ns, samples_per_sub=ns, chunk=chunk, **kw)
-            job_s = _timed(torch, lambda: job.run(E_job))
-            P, _, sig = job.result()
-            del job
-            torch.cuda.empty_cache()
-            flops = (4 if form == "bilinear" else 8) * w.M ** 2 * chunk
-            res[name][form] = {"ms_per_step": ms, "gemm_call_ms": gemm,
-                               "first_chunk_ms_with_pack": 1e3 * first, "job_s": job_s,
-                               "job_samples": E_job,
-                               "sigma_max_over_P_max": float(sig.max() / P.max()),
-                               "gemm_algorithmic_tflops": flops / gemm / 1e9,
-                               "_P": P, "_sig": sig}
-            log(f"[bench] bilinear_m8000 {name} {form}: {ms:.2f} ms/step, GEMM call {gemm:.2f} ms, "
-                f"first chunk {1e3 * first:.1f} ms, job {job_s:.3f} s")
-        a, b = res[name]["T_form"], res[name]["bilinear"]
-        bulk = a["_P"] > 1e-3 * a["_P"].max()
-        d = np.abs(a["_P"] - b["_P"])
-        res[name]["max_diff_over_sigma"] = float((d / a["_sig"])[bulk].max())
-        res[name]["step_speedup"] = a["ms_per_step"] / b["ms_per_step"]
-        res[name]["job_speedup"] = a["job_s"] / b["job_s"]
-        for f in ("T_form", "bilinear"):
-            del res[name][f]["_P"], res[name][f]["_sig"]
-        log(f"[bench] bilinear_m8000 {name}: step {res[name]['step_speedup']:.2f}x, job "
-            f"{res[name]['job_speedup']:.2f}x, max |P_T - P_bilinear| / sigma_T "
-            f"{res[name]['max_diff_over_sigma']:.2e}")
+    nets = {"haar_x0.95": w.T, "output_loss_0.9_1": _dense_w_network(w, synth)}
+    res = {name: _bilinear_pair(mp, torch, w, T, name, chunk, ns, steps)
+           for name, T in nets.items()}
     rep_ = res["output_loss_0.9_1"]["bilinear"]
     return _envelope(
         "samples·M²/s, one count distribution at M=8000 through the bilinear form (general network)",
@@ -1193,6 +1206,8 @@ def main():
     ap.add_argument("--M", type=int, default=8000)
     ap.add_argument("--cpu-budget", type=float, default=45.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bilinear", dest="bilinear", action="store_false",
+                    help="m8000: skip the one-distribution bilinear-form comparison leg")
     ap.add_argument("--unfused", action="store_true",
                     help="m8000: write C and count from it instead of the occupation-fused GEMM")
     ap.add_argument("--workload", default="m8000",
