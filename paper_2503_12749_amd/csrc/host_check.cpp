@@ -145,6 +145,37 @@ static void validation() {
                                      mp_propagate_workspace(8000, MP_SPLIT1_FP16), 1, all.data(),
                                      MP_JOINT, lot, Kt, 8, 8192, 0, (double*)P(256),
                                      nullptr) == MP_ERR_WORKSPACE);
+  // the bilinear form: sizes, precision, mode set, buffers, windows
+  EXPECT(mp_bilinear_workspace(0) == 0 && mp_bilinear_packed_bytes(0) == 0);
+  EXPECT(mp_bilinear_packed_bytes(8000) == mp_propagate_workspace(8000, MP_SPLIT1T_F8) + 4 * 8064);
+  EXPECT(mp_bilinear_workspace(8000) > (size_t)96 * 8000 * 8000 - (size_t)200000000);
+  {
+    const size_t pb = mp_bilinear_packed_bytes(8000), sb = mp_bilinear_workspace(8000);
+    std::vector<int32_t> bad(all);
+    bad[7999] = 1;
+    EXPECT(mp_pack_bilinear(8000, (const double*)P(256), all.data(), MP_SPLIT1T_FP16, P(256), pb,
+                            P(512), sb, nullptr) == MP_ERR_UNSUPPORTED);
+    EXPECT(mp_pack_bilinear(8000, (const double*)P(256), bad.data(), MP_SPLIT1T_F8, P(256), pb,
+                            P(512), sb, nullptr) == MP_ERR_ARG);
+    EXPECT(mp_pack_bilinear(8000, nullptr, all.data(), MP_SPLIT1T_F8, P(256), pb, P(512), sb,
+                            nullptr) == MP_ERR_ARG);
+    EXPECT(mp_pack_bilinear(8000, (const double*)P(256), all.data(), MP_SPLIT1T_F8, P(256), pb - 1,
+                            P(512), sb, nullptr) == MP_ERR_WORKSPACE);
+    EXPECT(mp_pack_bilinear(8000, (const double*)P(256), all.data(), MP_SPLIT1T_F8, P(256), pb,
+                            P(520), sb, nullptr) == MP_ERR_WORKSPACE);
+    EXPECT(mp_propagate_counts_bilinear(8000, 65536, MP_FP32, MP_MATRIX_P, P(256),
+                                        (const double*)P(256), P(256), pb, lot, Kt, 8, 8192, 0,
+                                        (double*)P(256), P(256), 1 << 30,
+                                        nullptr) == MP_ERR_UNSUPPORTED);
+    EXPECT(mp_propagate_counts_bilinear(8000, 65536, MP_SPLIT1T_F8, MP_MATRIX_P, P(256),
+                                        (const double*)P(256), P(256), pb - 1, lot, Kt, 8, 8192, 0,
+                                        (double*)P(256), P(256), 1 << 30,
+                                        nullptr) == MP_ERR_WORKSPACE);
+    EXPECT(mp_propagate_counts_bilinear(8000, 65536, MP_SPLIT1T_F8, MP_MATRIX_P, P(256),
+                                        (const double*)P(256), P(256), pb, lot, Kt, 4, 8192, 0,
+                                        (double*)P(256), P(256), 1 << 30,
+                                        nullptr) == MP_ERR_SHAPE);
+  }
   // finalize, observables, statistics, finiteness
   EXPECT(mp_counts_finalize(1, MP_JOINT, Kk, 0, 8, (const double*)P(256), (double*)P(256),
                             (double*)P(256), (double*)P(256), nullptr, 0, nullptr) == MP_ERR_ARG);
