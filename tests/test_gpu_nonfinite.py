@@ -103,6 +103,23 @@ def test_fp16_overflow_is_reported_plus_p(layout, fused):
     assert e.value.status == NONFINITE
 
 
+@pytest.mark.parametrize("est", ["matrix_p", "plus_p"])
+def test_fp16_overflow_is_reported_bilinear(est):
+    """The bilinear form (one distribution): overflowing amplitudes reach its
+    epilogue's sums as NaN, and result() raises."""
+    import paper_2503_12749_amd as mp
+    T = 0.9 * synth.haar_unitary(M, 7)
+    r = np.ones(M)
+    r[:4] = 12.0
+    p = mp.CountsPipeline(T, r, prec="split1t_f8", seed=4242, windows=[(0, 64)], n_sub=N_SUB,
+                          samples_per_sub=E_TOTAL // N_SUB, chunk=CHUNK, est=est, device=DEV,
+                          bilinear=True)
+    p.run()
+    with pytest.raises(mp.MPError) as e:
+        p.result()
+    assert e.value.status == NONFINITE
+
+
 @pytest.mark.parametrize("layout", ["total", "joint2", "joint3"])
 def test_in_range_squeezing_stays_finite(layout):
     """Control: the same networks at r = 1 give a finite estimate."""

@@ -20,13 +20,14 @@ def _gpu():
 
 
 @pytest.mark.parametrize("prec,fused", [("fp64", False), ("split1_fp16", True), ("split1t_fp16", True),
-                                        ("split1t_f8", True), ("split_bf16", True)])
+                                        ("split1t_f8", True), ("split_bf16", True),
+                                        ("split1t_f8", "bilinear")])
 def test_resume_from_checkpoint_file(prec, fused, tmp_path):
     import paper_2503_12749_amd as mp
     w = synth.workload_m1000(E=60_000)
     chunk, ns = 7_000, 6_000  # chunks straddle sub-ensemble boundaries
     kw = dict(prec=prec, seed=w.seed, windows=w.windows, n_sub=w.E // ns, samples_per_sub=ns,
-              chunk=chunk, device="cuda:0", fused=fused)
+              chunk=chunk, device="cuda:0", fused=fused is True, bilinear=fused == "bilinear")
     full = mp.CountsPipeline(w.T, w.r, **kw)
     full.run(w.E)
     P0, _, s0 = full.result()
