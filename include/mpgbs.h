@@ -310,7 +310,9 @@ mp_status mp_propagate_counts(int32_t M, int64_t E, mp_precision prec, mp_estima
  * distribution per pass (S, d = 1); marginals and joint distributions need
  * one W per bin and stay with mp_propagate_counts.
  *
- * mp_pack_bilinear forms W on the FP64 matrix cores and packs it.
+ * mp_pack_bilinear forms W on the FP64 matrix cores and packs it, then waits
+ * for `stream` (it reads bin_of_mode from host memory on the stream), so it
+ * returns once W is packed.
  *   T            device, complex M x M as for mp_propagate
  *   bin_of_mode  host, len M: 0 for the modes of S, -1 for the others
  *   prec         MP_SPLIT1T_F8 (others: MP_ERR_UNSUPPORTED)

@@ -350,7 +350,17 @@ mp_status mp_pack_bilinear(int32_t M, const double* T, const int32_t* bin_of_mod
   MP_CHECK_ARG(scratch_bytes >= need_scratch && aligned(scratch, 256), MP_ERR_WORKSPACE,
                "mp_pack_bilinear: scratch of %zu bytes (256-aligned) needed, %zu given",
                need_scratch, scratch_bytes);
-  return bilinear_pack_launch(M, T, bin_of_mode, prec, packed, scratch, (hipStream_t)stream);
+  const mp_status st =
+      bilinear_pack_launch(M, T, bin_of_mode, prec, packed, scratch, (hipStream_t)stream);
+  if (st != MP_OK) return st;
+  // the mode set is copied from host memory on the stream: return only once
+  // the stream has passed the packing, whatever memory the caller's array is
+  const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) {
+    set_error("mp_pack_bilinear: %s", hipGetErrorString(e));
+    return MP_ERR_HIP;
+  }
+  return MP_OK;
 }
 
 mp_status mp_propagate_counts_bilinear(int32_t M, int64_t E, mp_precision prec,
