@@ -68,6 +68,9 @@ TRAFFIC = {
                            "fetch_bytes": 4.916e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
     ("fp32", True): {"source_sha256_16": "7df0e3e2fad6d5c8",
                      "fetch_bytes": 4.903e7 * 1024 * 2, "write_bytes": 9.677e4 * 1024},
+    # gemm_split1t8_bilin on the dense-W network of the bilinear_m8000 workload
+    ("bilinear", True): {"source_sha256_16": "7df0e3e2fad6d5c8",
+                         "fetch_bytes": 1.955e7 * 1024 * 2, "write_bytes": 3.231e5 * 1024},
 }
 
 
@@ -635,12 +638,22 @@ def run_bilinear_m8000(args, mp, torch, synth):
     res = {name: _bilinear_pair(mp, torch, w, T, name, chunk, ns, steps)
            for name, T in nets.items()}
     rep_ = res["output_loss_0.9_1"]["bilinear"]
-    return _envelope(
+    out = _envelope(
         "samples·M²/s, one count distribution at M=8000 through the bilinear form (general network)",
         chunk * w.M ** 2 / (rep_["ms_per_step"] / 1e3), "samples·M²/s", rep_["ms_per_step"],
         "M8000_r1: total counts on [8083, 11923), 65536 samples per step; networks Haar x 0.95 "
         "(W = 0.9025 I) and diag(l) Haar with l ~ U[0.9, 1] (W dense)",
         DTYPES["split1t_f8"], networks=res)
+    achieved = rep_["gemm_algorithmic_tflops"]
+    out["roofline"] = {
+        "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAKS_TFLOPS["split1t_f8"],
+        "unit": "TFLOP/s", "frac": round(achieved / PEAKS_TFLOPS["split1t_f8"], 4),
+        "traffic": gemm_traffic_gb("bilinear", True),
+        "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, calibrated on a 1 GiB copy)",
+        "kernel": "gemm_split1t8_bilin (mp_propagate_counts_bilinear, dense-W network: the GEMM "
+                  "with the bilinear epilogue; the timed call includes the counting kernels)",
+        "algorithmic_flops_per_launch": 4.0 * w.M ** 2 * chunk}
+    return out
 
 
 def _batched_leg(mp, torch, nets, chunk, label, prec="split_fp16"):
