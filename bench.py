@@ -752,7 +752,7 @@ def run_surrogate(args, mp, torch, synth):
     (M in [100, 2000], t in [0.8, 0.99], rbar in [0.5, 1.5], s_r in [0, 0.3],
     d in {1, 2, 4}; E = 1e4 each), GPU training, then screening of 256
     candidate profiles at M = 8000, t = 0.95, d = 4 with the method
-    (E = 2^20 per judged candidate) as judge."""
+    (E = 2^20 per checked candidate) as the check."""
     from paper_2503_12749_amd import surrogate as sg
     rng = np.random.default_rng(2503)
     runner = sg.MethodRunner()
@@ -769,18 +769,18 @@ def run_surrogate(args, mp, torch, synth):
     log("[bench] surrogate: screening at M=8000")
     res = sg.screen(net, runner, 8000, 0.95, 4, cands, 1 << 20, 8)
     errs = [{k: j[k] for k in ("mean_rel_err", "var_rel_err", "baseline_mean_rel_err",
-                               "baseline_var_rel_err", "fallback")} for j in res["judged"]]
-    per_method = res["t_method_s"] / len(res["judged"])
+                               "baseline_var_rel_err", "fallback")} for j in res["checked"]]
+    per_method = res["t_method_s"] / len(res["checked"])
     return _envelope(
         "candidates screened per second by the surrogate, M=8000 (method time per candidate in config)",
         len(cands) / res["t_predict_s"], "candidates/s", 1e3 * res["t_predict_s"],
         f"surrogate: {args.sweeps} training sweeps at E={args.sweep_E}, screening 256 profiles at M=8000, "
-        f"t=0.95, d=4, judge E=2^20", "bf16 weights, fp32 accumulate",
+        f"t=0.95, d=4, check E=2^20", "bf16 weights, fp32 accumulate",
         generate_s=gen_s, train_s=train_s, loss_first_last=[hist[0][1], hist[-1][1]],
         predict_s_256=res["t_predict_s"], method_s_per_candidate=per_method,
         speedup_vs_method=per_method * len(cands) / res["t_predict_s"],
         fallback_rule="method replaces a prediction off by > 1 % (mean) or > 5 % (variance)",
-        judged=errs)
+        checked=errs)
 
 
 def _golden(name):

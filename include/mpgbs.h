@@ -43,7 +43,7 @@ typedef enum {
   MP_ERR_ARG = -1,         /* invalid scalar argument or null pointer */
   MP_ERR_SHAPE = -2,       /* sizes inconsistent with each other */
   MP_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
-  MP_ERR_UNSUPPORTED = -4, /* valid request outside what this build handles */
+  MP_ERR_UNSUPPORTED = -4, /* valid request outside what the library handles */
   MP_ERR_WORKSPACE = -5,   /* workspace missing or smaller than required */
   MP_ERR_NONFINITE = -6    /* a result holds NaN or infinite values (mp_check_finite) */
 } mp_status;
@@ -632,7 +632,7 @@ mp_status mp_plan_destroy(void* plan);
 
 /*
  * Small MLP trained on method outputs (sweep parameters -> moments of a bin's
- * count distribution) to screen parameter sweeps; the method judges and
+ * count distribution) to screen parameter sweeps; the method checks and
  * replaces its predictions.  Layer l maps width[l] -> width[l+1] as
  * y = x W_l + b_l with W_l row-major (width[l] x width[l+1]) followed by b_l,
  * layers concatenated in one FP32 vector `params`; SiLU on hidden layers,

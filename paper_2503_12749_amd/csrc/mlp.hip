@@ -1,8 +1,8 @@
 // Small MLP surrogate: forward, mean-squared-error backward and Adam, as
 // plain HIP kernels.  The network maps sweep parameters to moments of the
 // binned count distribution that the matrix-P method produces; it is trained
-// on method outputs and screens parameter sweeps, with the method itself as
-// the judge (see the Python driver).
+// on method outputs and screens parameter sweeps, with the method itself
+// checking its picks (see the Python driver).
 //
 // Layout: layer l maps width[l] -> width[l+1] with y = x W_l + b_l, W_l stored
 // row-major (width[l] rows, width[l+1] columns), then b_l; the layers are

@@ -12,7 +12,7 @@ whose dependence on M is weak.  Training data come from the method itself
 (CountsPipeline runs); training, inference and the Adam updates run in the
 library's HIP kernels (mp_mlp_*).  Screening: the network ranks candidate
 squeezing profiles at a size outside its training range, and the method, run
-on the selected candidates, judges the predictions and replaces any that
+on the selected candidates, checks the predictions and replaces any that
 miss.
 
 Run as a module to generate data, train and screen:
@@ -284,14 +284,14 @@ class Mlp:
 
 # ---------------------------------------------------------------- screening
 
-def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_mean=0.01, tol_var=0.05,
+def screen(mlp, runner, M, t, d, candidates, E_check, top, tol_mean=0.01, tol_var=0.05,
            net0=100000):
     """Predicts the bin-0 cumulants of every candidate (rbar, sr) profile,
     selects the `top` candidates whose Fano factor (variance / mean) is
     closest to the middle of the predicted range, and runs the method on
     them.  The method's values replace a prediction (fallback) when the
     predicted mean or variance misses the method's by more than tol_mean or
-    tol_var relative.  Each judged entry also carries the error of the
+    tol_var relative.  Each checked entry also carries the error of the
     independent-mode baseline alone, the part the network corrects."""
     profs = [runner.profile(M, rb, sr, net0 + q) for q, (rb, sr) in enumerate(candidates)]
     t0 = time.perf_counter()
@@ -302,19 +302,19 @@ def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_mean=0.01, tol_va
     fano = np.array([kb[1] / kb[0] for kb, _ in mom])
     target = 0.5 * (fano.min() + fano.max())
     order = np.argsort(np.abs(fano - target))[:top]
-    judged = []
+    checked = []
     t0 = time.perf_counter()
     for q in order:
         rb, sr = candidates[q]
-        yq, ((m, P, s), _) = runner.run(M, t, rb, sr, d, E=E_judge, net=net0 + int(q),
-                                        chunk=min(E_judge, 65536), n_sub=max(2, E_judge // 8192))
+        yq, ((m, P, s), _) = runner.run(M, t, rb, sr, d, E=E_check, net=net0 + int(q),
+                                        chunk=min(E_check, 65536), n_sub=max(2, E_check // 8192))
         kb, _ = moments_from_targets(M, t, profs[q], d, yq)
         pb, _ = mom[q]
         base, _ = moments_from_targets(M, t, profs[q], d, np.ones(2 * N_CUM))
         sig_mean = float(np.sqrt(((m - kb[0]) ** 2 * s ** 2).sum()))
         e_mean = abs(pb[0] - kb[0]) / kb[0]
         e_var = abs(pb[1] - kb[1]) / kb[1]
-        judged.append(dict(candidate=[rb, sr], predicted_mean=float(pb[0]),
+        checked.append(dict(candidate=[rb, sr], predicted_mean=float(pb[0]),
                            predicted_var=float(pb[1]), method_mean=float(kb[0]),
                            method_var=float(kb[1]), sigma_mean=sig_mean,
                            mean_rel_err=float(e_mean), var_rel_err=float(e_var),
@@ -323,7 +323,7 @@ def screen(mlp, runner, M, t, d, candidates, E_judge, top, tol_mean=0.01, tol_va
                            fallback=bool(e_mean > tol_mean or e_var > tol_var)))
     t_method = time.perf_counter() - t0
     return dict(t_predict_s=t_pred, t_method_s=t_method, n_candidates=len(candidates),
-                judged=judged)
+                checked=checked)
 
 
 def main():
