@@ -523,10 +523,12 @@ def run_precision_m8000(args, mp, torch, synth):
     E = 11 * chunk
     w = synth.workload_m8000(E=E, chunk=chunk)
     res = {}
-    for prec in ("fp64", "split1t_f8", "split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
-        p = mp.CountsPipeline(w.T, w.r, prec=prec, seed=w.seed, windows=w.windows,
-                              n_sub=E // ns, samples_per_sub=ns, chunk=chunk,
-                              fused=prec != "fp64")
+    for prec in ("fp64", "split1t_f8", "split1t_f8_bilinear", "split1t_fp16", "split1_fp16",
+                 "split_bf16", "fp32"):
+        bil = prec.endswith("_bilinear")
+        p = mp.CountsPipeline(w.T, w.r, prec=prec.replace("_bilinear", ""), seed=w.seed,
+                              windows=w.windows, n_sub=E // ns, samples_per_sub=ns, chunk=chunk,
+                              fused=prec != "fp64" and not bil, bilinear=bil)
         secs = _timed(torch, p.run)
         res[prec] = (secs,) + p.result()
         log(f"[bench] precision_m8000 {prec}: {secs:.3f} s")
@@ -535,7 +537,8 @@ def run_precision_m8000(args, mp, torch, synth):
     s64, P64, sig64 = res["fp64"][0], res["fp64"][1], res["fp64"][3]
     bulk = P64 > 1e-3 * P64.max()
     per = {}
-    for prec in ("split1t_f8", "split1t_fp16", "split1_fp16", "split_bf16", "fp32"):
+    for prec in ("split1t_f8", "split1t_f8_bilinear", "split1t_fp16", "split1_fp16", "split_bf16",
+                 "fp32"):
         secs, P = res[prec][0], res[prec][1]
         err = np.abs(P - P64)
         per[prec] = {"run_s": secs, "max_abs_err": float(err.max()),
